@@ -1,0 +1,159 @@
+"""CPU oracle -- TEST INFRASTRUCTURE ONLY.
+
+Plain, slow, obviously-correct CPU implementations of what the GPU library
+computes.  Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline
+leg of ``bench.py`` may import this package; the GPU library never calls it
+and shares no code with it.
+
+Parts (each function cites the passage it follows):
+  * ``knn_brute``  -- the k-NN definition written out (C, ``or_knn_brute``);
+  * ``KdTree``     -- the static kd-tree with object-median splits and its
+                      k-NN search (C, ``or_kd_build`` / ``or_kd_knn``);
+  * ``bdl_model``  -- the BDL-tree's logarithmic method on point sets
+                      (Algorithms 3 and 4), in Python;
+  * ``grad``       -- the closed-form FP64 gradient of summed k-NN squared
+                      distances and central finite differences, in NumPy.
+
+Readings of the paper adopted where it is silent (also listed in the design
+notes): ties in distance go to the smaller id; squared distances are exact
+int64 for int32 coordinates and FP64 for float32 coordinates; split
+dimension = level mod d; split rank floor((2j+1)n/2^(l+1)) under
+(coordinate, index); leaves at depth L = min{L : ceil(n/2^L) <= leaf}.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+DT_INT, DT_F32 = 0, 1
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            from . import build_oracle
+            build_oracle.build()
+        L = ctypes.CDLL(_SO)
+        vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
+        L.or_knn_brute.argtypes = [vp, vp, vp, i64, i32, i32, vp, i64, i32, vp, vp, i32]
+        L.or_knn_brute.restype = i32
+        L.or_kd_build.argtypes = [vp, i64, i32, i32, i32]
+        L.or_kd_build.restype = vp
+        L.or_kd_free.argtypes = [vp]
+        L.or_kd_free.restype = None
+        L.or_kd_levels.argtypes = [vp]
+        L.or_kd_levels.restype = i32
+        L.or_kd_export.argtypes = [vp, vp, vp]
+        L.or_kd_export.restype = None
+        L.or_kd_knn.argtypes = [vp, vp, vp, vp, i64, i32, vp, vp, vp]
+        L.or_kd_knn.restype = i32
+        _lib = L
+    return _lib
+
+
+def _dtype_code(a: np.ndarray) -> int:
+    if a.dtype == np.int32:
+        return DT_INT
+    if a.dtype == np.float32:
+        return DT_F32
+    raise TypeError(f"oracle takes int32 or float32 coordinates, got {a.dtype}")
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+def _outputs(m, k, dt):
+    ids = np.empty((m, k), dtype=np.int64)
+    dist = np.empty((m, k), dtype=np.int64 if dt == DT_INT else np.float64)
+    return ids, dist
+
+
+def knn_brute(points, queries, k, ids=None, alive=None, nthreads=1):
+    """The definition: for every query the k smallest (D, id) keys, ascending.
+    Returns (ids int64 [m][k], dist int64 or float64 [m][k]); missing slots
+    hold id -1 and distance INT64_MAX / +inf."""
+    points = np.ascontiguousarray(points)
+    queries = np.ascontiguousarray(queries, dtype=points.dtype)
+    dt = _dtype_code(points)
+    n, d = points.shape
+    m = queries.shape[0]
+    if ids is not None:
+        ids = np.ascontiguousarray(ids, dtype=np.int64)
+    if alive is not None:
+        alive = np.ascontiguousarray(alive, dtype=np.uint8)
+    out_id, out_d = _outputs(m, k, dt)
+    rc = lib().or_knn_brute(_ptr(points), _ptr(ids), _ptr(alive), n, d, dt,
+                            _ptr(queries), m, k, _ptr(out_id), _ptr(out_d), int(nthreads))
+    if rc != 0:
+        raise ValueError("or_knn_brute: bad arguments")
+    return out_id, out_d
+
+
+class KdTree:
+    """Static kd-tree by object-median splits (Appendix C, Algorithm 1 and the
+    proof of its work bound: one median partition per level), read as: split
+    dimension = level mod d, split position floor((2j+1)n/2^(l+1)) under the
+    key (coordinate, row index), all leaves at depth L."""
+
+    def __init__(self, points, leaf=16):
+        self.points = np.ascontiguousarray(points)
+        self.dt = _dtype_code(self.points)
+        self.n, self.d = self.points.shape
+        self.leaf = leaf
+        self._h = lib().or_kd_build(_ptr(self.points), self.n, self.d, self.dt, leaf)
+        if not self._h:
+            raise ValueError("or_kd_build: bad arguments")
+        self.levels = lib().or_kd_levels(self._h)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().or_kd_free(h)
+            self._h = None
+
+    def export(self):
+        """(split values of heap nodes 1..2^L-1 as float64, rows in leaf order)."""
+        ni = (1 << self.levels) - 1
+        splits = np.empty(ni, dtype=np.float64)
+        perm = np.empty(self.n, dtype=np.int64)
+        lib().or_kd_export(self._h, _ptr(splits), _ptr(perm))
+        return splits, perm
+
+    def leaf_ranges(self):
+        L = self.levels
+        j = np.arange((1 << L) + 1, dtype=object)
+        return np.array([(int(x) * self.n) >> L for x in j], dtype=np.int64)
+
+    def knn(self, queries, k, ids=None, alive=None):
+        """Appendix C single-query search for every query; returns
+        (ids, dist, counters) with counters = [internal nodes visited,
+        leaves added, points whose distance was computed] summed."""
+        queries = np.ascontiguousarray(queries, dtype=self.points.dtype)
+        m = queries.shape[0]
+        if ids is not None:
+            ids = np.ascontiguousarray(ids, dtype=np.int64)
+        if alive is not None:
+            alive = np.ascontiguousarray(alive, dtype=np.uint8)
+        out_id, out_d = _outputs(m, k, self.dt)
+        counters = np.zeros(3, dtype=np.int64)
+        rc = lib().or_kd_knn(self._h, _ptr(ids), _ptr(alive), _ptr(queries), m, k,
+                             _ptr(out_id), _ptr(out_d), _ptr(counters))
+        if rc != 0:
+            raise ValueError("or_kd_knn: bad arguments")
+        return out_id, out_d, counters
+
+
+def tree_depth(n: int, leaf: int) -> int:
+    """L = min{L : ceil(n / 2^L) <= leaf}."""
+    L = 0
+    while -(-n // (1 << L)) > leaf:
+        L += 1
+    return L

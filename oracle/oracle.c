@@ -1,0 +1,400 @@
+/*
+ * CPU ORACLE -- test infrastructure only.
+ *
+ * A plain, serial (the brute-force search may split its queries over
+ * threads, which changes no result), obviously-correct implementation of what
+ * the GPU path computes.  Only the tests, the smoke check and the benchmark's
+ * CPU-baseline leg may load it.  It shares no code, header or table with the
+ * GPU library.
+ *
+ * Coordinates come in one of two types:
+ *   dt = 0 : int32 coordinates; squared distances are exact in int64;
+ *   dt = 1 : float32 coordinates; squared distances in FP64, summed over
+ *            dimensions 0..d-1 in order.
+ *
+ * Definition of the k-NN result used throughout (the paper leaves the order of
+ * equal distances open; the reading adopted is the lexicographic order on
+ * (squared distance, id), smaller id first): for a query q over the point set
+ * {(p_j, id_j)}, the result is the k smallest keys (D(q,p_j), id_j) in
+ * ascending order; when fewer than k points exist, the remaining slots hold
+ * id -1 and distance INT64_MAX (int) or +inf (float).
+ *
+ * Parts:
+ *   or_knn_brute   -- the definition written out (all pairs).
+ *   or_kd_build    -- static kd-tree by object-median splits (Section 5;
+ *                     Appendix C "Parallel vEB Construction", Algorithm 1 and
+ *                     the proof of its work bound), with the readings: split
+ *                     dimension = level mod d, split rank floor((2j+1)n/2^(l+1))
+ *                     under the key (coordinate, index), all leaves at depth
+ *                     L = min{L : ceil(n/2^L) <= leaf}.
+ *   or_kd_knn      -- the single-query search of Appendix C "Data-Parallel
+ *                     k-NN" (descend to the leaf, fill from siblings while
+ *                     fewer than k candidates, then contained / disjoint /
+ *                     intersecting subtree boxes), run for every query, with
+ *                     the 2k candidate buffer the same passage describes.
+ *                     Counts visited internal nodes, leaves and points.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <math.h>
+#include <pthread.h>
+
+#define OR_DT_INT 0
+#define OR_DT_F32 1
+
+/* ------------------------------------------------------------------------ */
+/* Keys: (squared distance, id), compared lexicographically.                 */
+/* ------------------------------------------------------------------------ */
+typedef struct { int64_t di; double df; int64_t id; } or_key;
+
+static int key_less(const or_key* a, const or_key* b, int dt) {
+    if (dt == OR_DT_INT) {
+        if (a->di != b->di) return a->di < b->di;
+    } else {
+        if (a->df != b->df) return a->df < b->df;
+    }
+    return a->id < b->id;
+}
+
+static int key_cmp_int(const void* x, const void* y) {
+    const or_key* a = (const or_key*)x; const or_key* b = (const or_key*)y;
+    if (a->di != b->di) return a->di < b->di ? -1 : 1;
+    return (a->id > b->id) - (a->id < b->id);
+}
+static int key_cmp_f(const void* x, const void* y) {
+    const or_key* a = (const or_key*)x; const or_key* b = (const or_key*)y;
+    if (a->df != b->df) return a->df < b->df ? -1 : 1;
+    return (a->id > b->id) - (a->id < b->id);
+}
+
+/* Squared Euclidean distance between query row q and point row p. */
+static or_key dist_key(const void* pts, int64_t j, const void* qs, int64_t i,
+                       int d, int dt, int64_t id) {
+    or_key k; k.di = 0; k.df = 0.0; k.id = id;
+    if (dt == OR_DT_INT) {
+        const int32_t* P = (const int32_t*)pts; const int32_t* Q = (const int32_t*)qs;
+        for (int c = 0; c < d; c++) {
+            int64_t diff = (int64_t)Q[i * d + c] - (int64_t)P[j * d + c];
+            k.di += diff * diff;
+        }
+    } else {
+        const float* P = (const float*)pts; const float* Q = (const float*)qs;
+        for (int c = 0; c < d; c++) {
+            double diff = (double)Q[i * d + c] - (double)P[j * d + c];
+            k.df += diff * diff;
+        }
+    }
+    return k;
+}
+
+static void write_result(const or_key* best, int cnt, int k, int dt,
+                         int64_t* out_id, void* out_dist, int64_t row) {
+    for (int r = 0; r < k; r++) {
+        if (r < cnt) {
+            out_id[row * k + r] = best[r].id;
+            if (dt == OR_DT_INT) ((int64_t*)out_dist)[row * k + r] = best[r].di;
+            else ((double*)out_dist)[row * k + r] = best[r].df;
+        } else {
+            out_id[row * k + r] = -1;
+            if (dt == OR_DT_INT) ((int64_t*)out_dist)[row * k + r] = INT64_MAX;
+            else ((double*)out_dist)[row * k + r] = INFINITY;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* O1: brute force -- the definition.  For each query every point's key is  */
+/* offered to a sorted list of the k smallest keys seen so far.              */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    const void* pts; const int64_t* ids; const uint8_t* alive; int64_t n; int d, dt;
+    const void* qs; int64_t q0, q1; int k; int64_t* out_id; void* out_dist;
+} brute_job;
+
+static void* brute_worker(void* arg) {
+    brute_job* J = (brute_job*)arg;
+    or_key* best = (or_key*)malloc(sizeof(or_key) * (size_t)(J->k > 0 ? J->k : 1));
+    for (int64_t i = J->q0; i < J->q1; i++) {
+        int cnt = 0;
+        for (int64_t j = 0; j < J->n; j++) {
+            if (J->alive && !J->alive[j]) continue;
+            or_key key = dist_key(J->pts, j, J->qs, i, J->d, J->dt, J->ids ? J->ids[j] : j);
+            if (cnt == J->k && !key_less(&key, &best[J->k - 1], J->dt)) continue;
+            int pos = cnt < J->k ? cnt++ : J->k - 1;
+            while (pos > 0 && key_less(&key, &best[pos - 1], J->dt)) { best[pos] = best[pos - 1]; pos--; }
+            best[pos] = key;
+        }
+        write_result(best, cnt, J->k, J->dt, J->out_id, J->out_dist, i);
+    }
+    free(best);
+    return NULL;
+}
+
+/* pts [n][d], ids [n] (NULL: id = row index), alive [n] (NULL: all alive),
+ * qs [m][d]; out_id [m][k]; out_dist [m][k] int64 (dt 0) or double (dt 1). */
+int or_knn_brute(const void* pts, const int64_t* ids, const uint8_t* alive, int64_t n,
+                 int d, int dt, const void* qs, int64_t m, int k,
+                 int64_t* out_id, void* out_dist, int nthreads) {
+    if (d < 1 || k < 1 || n < 0 || m < 0) return 1;
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > 256) nthreads = 256;
+    if (m < nthreads) nthreads = m > 0 ? (int)m : 1;
+    brute_job jobs[256]; pthread_t th[256];
+    for (int t = 0; t < nthreads; t++) {
+        brute_job J = {pts, ids, alive, n, d, dt, qs, m * t / nthreads, m * (t + 1) / nthreads, k, out_id, out_dist};
+        jobs[t] = J;
+    }
+    if (nthreads == 1) { brute_worker(&jobs[0]); return 0; }
+    for (int t = 0; t < nthreads; t++) pthread_create(&th[t], NULL, brute_worker, &jobs[t]);
+    for (int t = 0; t < nthreads; t++) pthread_join(th[t], NULL);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* O2: static kd-tree, object-median splits.                                 */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int64_t n; int d, dt, L;
+    const void* pts;          /* caller's [n][d] array, kept by reference     */
+    int64_t* perm;            /* [n] point rows in leaf order                 */
+    double* split;            /* [2^L] heap 1-based, split value of node h    */
+    double* bmin; double* bmax; /* [2^(L+1)][d] tight box of node h's points  */
+} or_tree;
+
+static double coord(const or_tree* T, int64_t row, int c) {
+    if (T->dt == OR_DT_INT) return (double)((const int32_t*)T->pts)[row * T->d + c];
+    return (double)((const float*)T->pts)[row * T->d + c];
+}
+
+/* Node (level l, j) covers positions [floor(j n / 2^l), floor((j+1) n / 2^l)). */
+static int64_t node_lo(int64_t n, int l, int64_t j) { return (int64_t)(((__int128)j * n) >> l); }
+
+/* Key of a point for the split along dimension c: (coordinate, row index). */
+static int cut_less(const or_tree* T, int64_t a, int64_t b, int c) {
+    double x = coord(T, a, c), y = coord(T, b, c);
+    if (x != y) return x < y;
+    return a < b;
+}
+
+/* Quickselect: rearrange perm[lo,hi) so that position r holds the element of
+ * rank r - lo under cut_less, with smaller keys before and larger after.
+ * Keys are distinct (the row index breaks ties), so the split set is unique. */
+static void select_rank(const or_tree* T, int64_t* perm, int64_t lo, int64_t hi, int64_t r,
+                        int c, uint64_t* seed) {
+    while (hi - lo > 1) {
+        *seed = *seed * 6364136223846793005ULL + 1442695040888963407ULL;
+        int64_t piv = perm[lo + (int64_t)((*seed >> 33) % (uint64_t)(hi - lo))];
+        /* three-way partition around piv: [lo,a) less, [a,b) == piv, [b,hi) greater */
+        int64_t a = lo, b = lo, e = hi;
+        while (b < e) {
+            int64_t x = perm[b];
+            if (x == piv) { b++; }
+            else if (cut_less(T, x, piv, c)) { int64_t t = perm[a]; perm[a] = x; perm[b] = t; a++; b++; }
+            else { e--; int64_t t = perm[e]; perm[e] = x; perm[b] = t; }
+        }
+        if (r < a) hi = a;
+        else if (r >= b) lo = b;
+        else return;
+    }
+}
+
+static void build_rec(or_tree* T, int l, int64_t j, uint64_t* seed) {
+    if (l == T->L) return;
+    int64_t lo = node_lo(T->n, l, j), hi = node_lo(T->n, l, j + 1);
+    int64_t mid = node_lo(T->n, l + 1, 2 * j + 1);
+    int c = l % T->d;
+    /* The split value is the key of the first right element; when the right
+     * child is empty (only possible for leaf size 1) it is the largest left
+     * key.  Internal nodes are never empty. */
+    int64_t at = mid < hi ? mid : hi - 1;
+    select_rank(T, T->perm, lo, hi, at, c, seed);
+    int64_t h = ((int64_t)1 << l) + j;
+    T->split[h] = coord(T, T->perm[at], c);
+    build_rec(T, l + 1, 2 * j, seed);
+    build_rec(T, l + 1, 2 * j + 1, seed);
+}
+
+static int tree_depth(int64_t n, int leaf) {
+    int L = 0;
+    while (((n + ((int64_t)1 << L) - 1) >> L) > leaf) L++;
+    return L;
+}
+
+void or_kd_free(or_tree* T) {
+    if (!T) return;
+    free(T->perm); free(T->split); free(T->bmin); free(T->bmax); free(T);
+}
+
+or_tree* or_kd_build(const void* pts, int64_t n, int d, int dt, int leaf) {
+    if (d < 1 || leaf < 1 || n < 0) return NULL;
+    or_tree* T = (or_tree*)calloc(1, sizeof(or_tree));
+    T->n = n; T->d = d; T->dt = dt; T->pts = pts;
+    T->L = tree_depth(n, leaf);
+    int64_t nn = (int64_t)1 << (T->L + 1);
+    T->perm = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    T->split = (double*)calloc((size_t)(nn / 2 + 1), sizeof(double));
+    T->bmin = (double*)malloc(sizeof(double) * (size_t)(nn * d));
+    T->bmax = (double*)malloc(sizeof(double) * (size_t)(nn * d));
+    for (int64_t i = 0; i < n; i++) T->perm[i] = i;
+    uint64_t seed = 0x9E3779B97F4A7C15ULL;
+    build_rec(T, 0, 0, &seed);
+    /* Tight boxes: leaves from their points, internal nodes from children. */
+    int64_t first_leaf = (int64_t)1 << T->L;
+    for (int64_t h = first_leaf; h < nn; h++) {
+        int64_t j = h - first_leaf;
+        int64_t lo = node_lo(n, T->L, j), hi = node_lo(n, T->L, j + 1);
+        for (int c = 0; c < d; c++) { T->bmin[h * d + c] = INFINITY; T->bmax[h * d + c] = -INFINITY; }
+        for (int64_t i = lo; i < hi; i++)
+            for (int c = 0; c < d; c++) {
+                double v = coord(T, T->perm[i], c);
+                if (v < T->bmin[h * d + c]) T->bmin[h * d + c] = v;
+                if (v > T->bmax[h * d + c]) T->bmax[h * d + c] = v;
+            }
+    }
+    for (int64_t h = first_leaf - 1; h >= 1; h--)
+        for (int c = 0; c < d; c++) {
+            double a = T->bmin[2 * h * d + c], b = T->bmin[(2 * h + 1) * d + c];
+            T->bmin[h * d + c] = a < b ? a : b;
+            a = T->bmax[2 * h * d + c]; b = T->bmax[(2 * h + 1) * d + c];
+            T->bmax[h * d + c] = a > b ? a : b;
+        }
+    return T;
+}
+
+int or_kd_levels(const or_tree* T) { return T->L; }
+
+/* Copies the split values (heap index 1..2^L-1, as double) and the leaf-order
+ * point rows out of the tree. */
+void or_kd_export(const or_tree* T, double* split_out, int64_t* perm_out) {
+    int64_t ni = ((int64_t)1 << T->L);
+    for (int64_t h = 1; h < ni; h++) split_out[h - 1] = T->split[h];
+    for (int64_t i = 0; i < T->n; i++) perm_out[i] = T->perm[i];
+}
+
+/* ------------------------------------------------------------------------ */
+/* O3: kd-tree k-NN (Appendix C, "Data-Parallel k-NN").                      */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    or_key* buf; int cnt, k;  /* 2k candidate buffer */
+    int dt;
+} knn_buffer;
+
+static int cmp_dt_int(const void* a, const void* b) { return key_cmp_int(a, b); }
+static int cmp_dt_f(const void* a, const void* b) { return key_cmp_f(a, b); }
+
+/* Keep the k smallest candidates (selection by sorting the buffer). */
+static void buffer_trim(knn_buffer* B) {
+    qsort(B->buf, (size_t)B->cnt, sizeof(or_key), B->dt == OR_DT_INT ? cmp_dt_int : cmp_dt_f);
+    if (B->cnt > B->k) B->cnt = B->k;
+}
+
+static void buffer_add(knn_buffer* B, or_key key) {
+    B->buf[B->cnt++] = key;
+    if (B->cnt == 2 * B->k) buffer_trim(B);
+}
+
+/* The current k-th smallest key (only meaningful when cnt >= k). */
+static or_key buffer_kth(knn_buffer* B) {
+    buffer_trim(B);
+    return B->buf[B->k - 1];
+}
+
+typedef struct {
+    const or_tree* T; const void* qs; int64_t qi; const int64_t* ids; const uint8_t* alive;
+    knn_buffer* B;
+    int64_t n_internal, n_leaves, n_points;
+} knn_ctx;
+
+static double qcoord(const knn_ctx* C, int c) {
+    if (C->T->dt == OR_DT_INT) return (double)((const int32_t*)C->qs)[C->qi * C->T->d + c];
+    return (double)((const float*)C->qs)[C->qi * C->T->d + c];
+}
+
+static void add_point(knn_ctx* C, int64_t row) {
+    if (C->alive && !C->alive[row]) return;
+    C->n_points++;
+    buffer_add(C->B, dist_key(C->T->pts, row, C->qs, C->qi, C->T->d, C->T->dt,
+                              C->ids ? C->ids[row] : row));
+}
+
+static void add_subtree(knn_ctx* C, int l, int64_t j) {
+    /* every leaf under (l, j) */
+    int L = C->T->L;
+    int64_t j0 = j << (L - l), j1 = (j + 1) << (L - l);
+    int64_t lo = node_lo(C->T->n, L, j0), hi = node_lo(C->T->n, L, j1);
+    C->n_leaves += j1 - j0;
+    for (int64_t i = lo; i < hi; i++) add_point(C, C->T->perm[i]);
+}
+
+/* Smallest and largest squared distance from the query to the box of node h.
+ * Integer coordinates: exact in int64.  Float coordinates: the same FP64
+ * operations, in the same order, as dist_key, so that (rounding being
+ * monotone) lo <= D(q,p) <= hi holds for the computed distance of every
+ * point p in the box. */
+static void box_bounds(const knn_ctx* C, int64_t h, or_key* lo_key, or_key* hi_key) {
+    const or_tree* T = C->T; int d = T->d;
+    int64_t loi = 0, hii = 0; double lof = 0.0, hif = 0.0;
+    for (int c = 0; c < d; c++) {
+        double q = qcoord(C, c), a = T->bmin[h * d + c], b = T->bmax[h * d + c];
+        if (T->dt == OR_DT_INT) {
+            int64_t qi = (int64_t)q, ai = (int64_t)a, bi = (int64_t)b;
+            int64_t gap = qi < ai ? ai - qi : (qi > bi ? qi - bi : 0);
+            int64_t far = (qi - ai > bi - qi) ? qi - ai : bi - qi;
+            loi += gap * gap; hii += far * far;
+        } else {
+            double gap = q < a ? a - q : (q > b ? q - b : 0.0);
+            double fa = fabs(q - a), fb = fabs(q - b);
+            double far = fa > fb ? fa : fb;
+            lof += gap * gap; hif += far * far;
+        }
+    }
+    lo_key->di = loi; lo_key->df = lof; lo_key->id = INT64_MIN;
+    hi_key->di = hii; hi_key->df = hif; hi_key->id = INT64_MAX;
+}
+
+static void knn_rec(knn_ctx* C, int l, int64_t j) {
+    const or_tree* T = C->T;
+    if (l == T->L) { /* leaf: add all of its points */
+        C->n_leaves++;
+        int64_t lo = node_lo(T->n, l, j), hi = node_lo(T->n, l, j + 1);
+        for (int64_t i = lo; i < hi; i++) add_point(C, T->perm[i]);
+        return;
+    }
+    C->n_internal++;
+    int64_t h = ((int64_t)1 << l) + j;
+    int c = l % T->d;
+    int64_t near_j = qcoord(C, c) < T->split[h] ? 2 * j : 2 * j + 1;
+    int64_t far_j = near_j ^ 1;
+    knn_rec(C, l + 1, near_j);
+    /* unwinding: the sibling subtree (l+1, far_j) */
+    if (C->B->cnt < C->B->k) { add_subtree(C, l + 1, far_j); return; }
+    or_key kth = buffer_kth(C->B), lo, hi;
+    int64_t hf = ((int64_t)1 << (l + 1)) + far_j;
+    box_bounds(C, hf, &lo, &hi);
+    int contained = T->dt == OR_DT_INT ? hi.di <= kth.di : hi.df <= kth.df;
+    int disjoint = T->dt == OR_DT_INT ? lo.di > kth.di : lo.df > kth.df;
+    if (contained) add_subtree(C, l + 1, far_j);
+    else if (!disjoint) knn_rec(C, l + 1, far_j);
+}
+
+/* k-NN of every query row over the tree.  ids/alive as in or_knn_brute.
+ * counters (may be NULL): [0] internal nodes, [1] leaves, [2] points, summed. */
+int or_kd_knn(const or_tree* T, const int64_t* ids, const uint8_t* alive,
+              const void* qs, int64_t m, int k,
+              int64_t* out_id, void* out_dist, int64_t* counters) {
+    if (!T || k < 1 || m < 0) return 1;
+    knn_buffer B; B.k = k; B.dt = T->dt; B.buf = (or_key*)malloc(sizeof(or_key) * (size_t)(2 * k));
+    int64_t ci = 0, cl = 0, cp = 0;
+    for (int64_t i = 0; i < m; i++) {
+        B.cnt = 0;
+        knn_ctx C = {T, qs, i, ids, alive, &B, 0, 0, 0};
+        if (T->n > 0) knn_rec(&C, 0, 0);
+        buffer_trim(&B);
+        write_result(B.buf, B.cnt, k, T->dt, out_id, out_dist, i);
+        ci += C.n_internal; cl += C.n_leaves; cp += C.n_points;
+    }
+    free(B.buf);
+    if (counters) { counters[0] = ci; counters[1] = cl; counters[2] = cp; }
+    return 0;
+}

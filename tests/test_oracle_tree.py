@@ -1,0 +1,96 @@
+"""Pins for the oracle's static kd-tree (object-median splits, Appendix C /
+Algorithm 1 read as: dimension = level mod d, split rank
+floor((2j+1)n/2^(l+1)) under (coordinate, index), leaves at depth L)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2207_01834_amd import datagen
+
+
+def _node(n, l, j):
+    return (j * n) >> l
+
+
+def check_tree(points, leaf):
+    n, d = points.shape
+    t = oracle.KdTree(points, leaf=leaf)
+    L = t.levels
+    splits, perm = t.export()
+    # (I3) depth: ceil(n/2^L) <= leaf and (L == 0 or ceil(n/2^(L-1)) > leaf)
+    assert -(-n // (1 << L)) <= leaf
+    if L > 0:
+        assert -(-n // (1 << (L - 1))) > leaf
+    # (I2) every row appears exactly once
+    assert np.array_equal(np.sort(perm), np.arange(n))
+    # leaf sizes in {floor(n/2^L), ceil(n/2^L)}
+    sizes = np.diff([_node(n, L, j) for j in range((1 << L) + 1)])
+    assert set(sizes.tolist()) <= {n >> L, -(-n // (1 << L))}
+    for l in range(L):
+        c = l % d
+        for j in range(1 << l):
+            lo, hi = _node(n, l, j), _node(n, l, j + 1)
+            mid = _node(n, l + 1, 2 * j + 1)
+            left, right = perm[lo:mid], perm[mid:hi]
+            s = splits[(1 << l) + j - 1]
+            # (I1) the split separates: left coords <= s <= right coords
+            if len(left):
+                assert points[left, c].max() <= s
+            if len(right):
+                assert points[right, c].min() == s
+            # (I4) rank split under (coordinate, index): every left key is
+            # below every right key, so the left set is the mid-lo smallest
+            if len(left) and len(right):
+                lk = max(zip(points[left, c].tolist(), left.tolist()))
+                rk = min(zip(points[right, c].tolist(), right.tolist()))
+                assert lk < rk
+    return t
+
+
+@pytest.mark.parametrize("n,d,leaf", [(0, 2, 16), (1, 3, 16), (17, 2, 1), (100, 3, 4),
+                                      (1000, 2, 16), (2049, 5, 16), (777, 8, 3), (64, 1, 64)])
+def test_tree_invariants_uniform(n, d, leaf):
+    check_tree(datagen.uniform_int(n, d, seed=n + d), leaf)
+
+
+def test_tree_invariants_duplicates_and_floats():
+    g = np.random.default_rng(9)
+    check_tree(g.integers(0, 3, size=(500, 3)).astype(np.int32), 5)
+    check_tree(np.full((129, 2), 4, dtype=np.int32), 8)
+    check_tree((np.floor(g.random((600, 2)) * 4) / 4).astype(np.float32), 7)
+    check_tree(g.random((1000, 5)).astype(np.float32), 16)
+
+
+def test_tree_equals_sort_based_construction():
+    # The median-partition step reduces to a library sort: sort every node
+    # by (coordinate, index) and cut at the split position.
+    g = np.random.default_rng(4)
+    pts = g.integers(0, 20, size=(1500, 3)).astype(np.int32)
+    n, d, leaf = len(pts), 3, 6
+    t = oracle.KdTree(pts, leaf=leaf)
+    splits, perm = t.export()
+    L = t.levels
+    ref = np.arange(n)
+    ref_splits = np.zeros((1 << L) - 1)
+    for l in range(L):
+        c = l % d
+        for j in range(1 << l):
+            lo, hi = _node(n, l, j), _node(n, l, j + 1)
+            seg = ref[lo:hi]
+            order = np.lexsort((seg, pts[seg, c]))
+            ref[lo:hi] = seg[order]
+            mid = _node(n, l + 1, 2 * j + 1)
+            ref_splits[(1 << l) + j - 1] = pts[ref[mid], c]
+    assert np.array_equal(splits, ref_splits)
+    for j in range(1 << L):
+        lo, hi = _node(n, L, j), _node(n, L, j + 1)
+        assert set(perm[lo:hi].tolist()) == set(ref[lo:hi].tolist())
+
+
+def test_cfg1_depth_and_leaves():
+    # 2-D, n = 10,000, leaf 16: L = 10, 1,024 leaves of 9 or 10 points.
+    assert oracle.tree_depth(10_000, 16) == 10
+    assert oracle.tree_depth(10_000_000, 16) == 20
+    pts = datagen.uniform_int(10_000, 2, seed=1)
+    t = check_tree(pts, 16)
+    assert t.levels == 10
