@@ -1,0 +1,202 @@
+#!/usr/bin/env python3
+"""Benchmark: static 3-D kd-tree build + all-points k-NN on one MI355X.
+
+Workload (the paper's uniform data set shape, Section 6): n = 10,000,000
+points with int32 coordinates uniform in [0, 2^20)^3 (seed 2), k = 10,
+leaves of at most 16 points, every point queried.  One step = build the tree
+from device-resident points + k-NN of all n points.  ``value`` is the
+end-to-end rate (queries per second of the whole step, build included);
+``build_mpts_s`` and ``knn_qps`` give the two parts.
+
+The roofline object covers the dominant kernel (the k-NN search): its
+algorithmic bytes per query come from the oracle's visit counts on this
+workload (see the design doc and ``python -m oracle.visit_counts``), multiplied by
+the n queries of one launch and divided by the launch time measured with HIP
+events on the stream the kernel runs on.
+
+The cpu_baseline object times the CPU oracle (serial C) on the same points:
+the full tree build and the k-NN search of a sample of queries, projected to
+the whole step.
+
+Progress goes to stderr; stdout carries exactly one JSON line.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+N, D, K, LEAF = 10_000_000, 3, 10, 16
+
+# Oracle visit counts per query on this workload (100,000 sampled queries):
+# internal nodes 40.923, points 92.575  ->  bytes/query = 4d + k(4+s) + 4 N_int
+# + 4(d+1) N_pts with s = 8 (int64 distances) or 4 (float32 distances).
+N_INT, N_PTS = 40.923, 92.575
+
+
+def bytes_per_query(dist_bytes):
+    return 4 * D + K * (4 + dist_bytes) + 4 * N_INT + 4 * (D + 1) * N_PTS
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def knn_source_hash():
+    h = hashlib.sha256()
+    for f in ("knn.hip", "search.hpp", "knn.hpp", "common.hpp"):
+        with open(os.path.join(ROOT, "paper_2207_01834_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(dtype):
+    """HBM bytes per k-NN launch from the committed rocprofv3 counter summary,
+    when it was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"knn_all_{dtype}3d_10M_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("source_hash") != knn_source_hash():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(pts, sample):
+    import numpy as np
+
+    import oracle
+    log(f"cpu baseline: oracle build of {len(pts)} points + {sample} sampled queries")
+    t0 = time.perf_counter()
+    t = oracle.KdTree(pts, leaf=LEAF)
+    tb = time.perf_counter() - t0
+    rows = np.random.default_rng(7).choice(len(pts), size=sample, replace=False)
+    t0 = time.perf_counter()
+    _, _, cnt = t.knn(pts[rows], K)
+    tq = time.perf_counter() - t0
+    step_s = tb + tq * len(pts) / sample
+    return {
+        "value": len(pts) / step_s, "unit": "queries/s", "cores": 1, "kind": "oracle",
+        "sample": (f"serial C oracle: full object-median build of all {len(pts):,} points "
+                   f"({tb:.2f} s) + kd-tree k-NN of {sample:,} sampled points ({tq:.2f} s), "
+                   f"projected to the {len(pts):,}-query step"),
+        "build_mpts_s": len(pts) / tb / 1e6, "knn_qps": sample / tq,
+        "visits_per_query": {"internal": cnt[0] / sample, "leaves": cnt[1] / sample,
+                             "points": cnt[2] / sample},
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--dtype", choices=["int", "float"], default="int")
+    ap.add_argument("--cpu-sample", type=int, default=100_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2207_01834_amd import _binding as pg
+    from paper_2207_01834_amd import datagen
+
+    dev = torch.device("cuda:0")
+    pts = datagen.uniform_int(N, D, seed=2)
+    if args.dtype == "float":
+        pts = datagen.int_to_unit_float(pts)
+    x = torch.from_numpy(pts).to(dev)
+    dist_dtype = torch.int64 if args.dtype == "int" else torch.float32
+    idx = torch.empty((N, K), dtype=torch.int32, device=dev)
+    dist = torch.empty((N, K), dtype=dist_dtype, device=dev)
+    torch.cuda.synchronize()
+
+    def step(evs=None):
+        if evs:
+            evs[0].record()
+        t = pg.kdtree_build(x, leaf=LEAF)
+        if evs:
+            evs[1].record()
+        t.knn_all(K, out=(idx, dist))
+        if evs:
+            evs[2].record()
+        return t
+
+    for w in range(args.warmup):
+        log(f"warmup {w + 1}/{args.warmup}")
+        t = step()
+        del t
+    torch.cuda.synchronize()
+
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        t = step(evs[s])
+        del t
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    build_ms = float(np.median([e[0].elapsed_time(e[1]) for e in evs]))
+    knn_ms = float(np.median([e[1].elapsed_time(e[2]) for e in evs]))
+    ms_per_step = wall * 1000.0 / args.steps
+    log(f"step {ms_per_step:.3f} ms (build {build_ms:.3f} ms, knn {knn_ms:.3f} ms)")
+
+    dbytes = 8 if args.dtype == "int" else 4
+    launch_bytes = bytes_per_query(dbytes) * N
+    achieved = launch_bytes / (knn_ms * 1e-3) / 1e9
+    traffic = measured_traffic(args.dtype)
+    line = {
+        "metric": "kNN queries/sec + build Mpts/s (3D n=10M k=10), % HBM roofline, vs CPU oracle",
+        "value": N / (ms_per_step * 1e-3),
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int64" if args.dtype == "int" else "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": ("static 3-D kd-tree build + all-points k-NN: n=10,000,000 points, "
+                         + ("int32 coordinates uniform in [0,2^20)^3, exact int64 squared distances"
+                            if args.dtype == "int" else
+                            "float32 coordinates uniform in [0,1)^3 (int grid / 2^20), float32 distances")
+                         + ", k=10, leaf size 16, queries = all points"),
+            "n": N, "d": D, "k": K, "leaf": LEAF, "seed": 2,
+        },
+        "build_mpts_s": N / (build_ms * 1e-3) / 1e6,
+        "knn_qps": N / (knn_ms * 1e-3),
+        "build_ms": build_ms,
+        "knn_ms": knn_ms,
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "knn_static_kernel (all-points)",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "algorithmic_bytes_per_launch": launch_bytes,
+            "algorithmic_bytes_per_query": bytes_per_query(dbytes),
+        },
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(pts, args.cpu_sample)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,114 @@
+/*
+ * pargeo_hip.h -- C ABI of libpargeo_hip.so, a GPU (AMD Instinct MI355X,
+ * gfx950) implementation of the kd-tree hot path of ParGeo (Wang et al.,
+ * "ParGeo: A Library for Parallel Computational Geometry", ESA 2022):
+ * kd-tree construction and batched k-nearest-neighbour search, static and in
+ * the batch-dynamic BDL-tree form.
+ *
+ * Conventions for every call:
+ *   - Pointers are DEVICE pointers unless marked (host).  Point and query
+ *     arrays are row-major [count][d], 32-bit coordinates of the given dtype.
+ *   - `stream` is a hipStream_t (NULL = the null stream).  Work is enqueued on
+ *     it; calls that must report a data-dependent error or count (marked
+ *     "synchronises") wait for the stream before returning.
+ *   - Argument errors (bad sizes, null pointers) are returned before anything
+ *     is enqueued and leave every output untouched.  pg_last_error() then
+ *     gives a message (thread-local).
+ *   - Coordinates: int32 values must lie in [-2^29, 2^29) (so squared
+ *     distances are exact in int64 for d <= 8); float32 values must be finite
+ *     with |x| <= 1e18.  -0.0 is stored as +0.0.
+ *   - k-NN results: for each query the k points with the smallest
+ *     (squared Euclidean distance, id) keys in ascending order (ties in
+ *     distance go to the smaller id).  Squared distances are exact int64 for
+ *     int32 input, float32 for float32 input.  When fewer than k points
+ *     exist the remaining slots hold id -1 and distance INT64_MAX / +inf.
+ *   - Handles are owned by the library until the matching *_free call; the
+ *     caller's input arrays are copied and may be reused once the stream has
+ *     passed the call.  Device memory is stream-ordered (hipMallocAsync).
+ */
+#ifndef PARGEO_HIP_H
+#define PARGEO_HIP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PG_OK = 0,
+    PG_ERR_INVALID = 1,     /* bad argument (size, pointer, handle)          */
+    PG_ERR_RANGE = 2,       /* coordinate out of range / non-finite          */
+    PG_ERR_NOMEM = 3,       /* device allocation failed                      */
+    PG_ERR_DEVICE = 4,      /* a HIP call or kernel launch failed            */
+    PG_ERR_UNSUPPORTED = 5  /* valid request this build does not serve       */
+} pg_status;
+
+typedef enum { PG_INT32 = 0, PG_FLOAT32 = 1 } pg_dtype;
+
+typedef struct pg_tree pg_tree;
+typedef struct pg_bdl pg_bdl;
+
+/* Text of the last non-OK status on this thread (never NULL). */
+const char* pg_last_error(void);
+/* Library version string (host). */
+const char* pg_version(void);
+
+/* ---------------------------------------------------------------------- */
+/* Static kd-tree                                                          */
+/* ---------------------------------------------------------------------- */
+
+/* Builds a kd-tree over n points (Section 5; Appendix C, "Parallel vEB
+ * Construction" / Algorithm 1: object-median splits, one median partition
+ * per level).  Readings: the split dimension of level l is l mod d; node j of
+ * level l holds leaf-order positions [floor(j n/2^l), floor((j+1) n/2^l)) and
+ * its left child takes the floor((2j+1)n/2^(l+1)) - floor(j n/2^l) smallest
+ * points under (coordinate, input row); every leaf sits at depth
+ * L = min{L : ceil(n/2^L) <= leaf}, so a leaf holds at most `leaf` points.
+ * The split value of a node is the coordinate of its right child's smallest
+ * point (the largest left point when the right child is empty).
+ *   points : [n][d] int32 or float32 (dtype), device
+ *   n      : 0 <= n < 2^31        d : 1..8        leaf : 1..64
+ *   out    : (host) receives the handle
+ * Synchronises (one 8-byte read of the range check).  PG_ERR_RANGE if a
+ * coordinate is out of range. */
+pg_status pg_kdtree_build(const void* points, int64_t n, int32_t d, int32_t leaf,
+                          int32_t dtype, void* stream, pg_tree** out);
+
+/* k-NN of m query points over the tree (Appendix C, "Data-Parallel k-NN":
+ * queries in parallel, each search serial).
+ *   queries  : [m][d], same dtype as the tree, device
+ *   k        : 1..64
+ *   out_idx  : [m][k] int32, input row of each neighbour (-1 = none)
+ *   out_dist : [m][k] int64 (int32 trees) or float32 (float32 trees)
+ * Synchronises (query range check). */
+pg_status pg_knn(const pg_tree* t, const void* queries, int64_t m, int32_t k,
+                 int32_t* out_idx, void* out_dist, void* stream);
+
+/* All-points k-NN: the queries are the tree's own n points (each point is
+ * its own first neighbour unless an identical point has a smaller row).
+ * Output row i belongs to input row i.  Does not synchronise. */
+pg_status pg_knn_all(const pg_tree* t, int32_t k, int32_t* out_idx, void* out_dist,
+                     void* stream);
+
+/* Tree facts (host outputs; any may be NULL). */
+pg_status pg_tree_info(const pg_tree* t, int64_t* n, int32_t* d, int32_t* leaf,
+                       int32_t* levels, int32_t* dtype);
+
+/* Copies the tree out for inspection (synchronises):
+ *   splits_host : (host) [2^L - 1] 32-bit split values of heap nodes 1..2^L-1
+ *                 (node h has children 2h, 2h+1; node 2^l + j is node j of
+ *                 level l), int32 or float32 per dtype
+ *   perm_host   : (host) [n] int32 input rows in leaf order; leaf j holds
+ *                 positions [floor(j n/2^L), floor((j+1) n/2^L)) */
+pg_status pg_tree_export(const pg_tree* t, void* splits_host, int32_t* perm_host,
+                         void* stream);
+
+/* Releases the tree (stream-ordered on the stream it was built on). */
+void pg_tree_free(pg_tree* t);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PARGEO_HIP_H */

@@ -1,0 +1,161 @@
+"""ctypes binding of libpargeo_hip.so.
+
+Argument marshalling only: tensors are passed as device pointers together
+with torch's current HIP stream; every step of the computation runs in the
+library's kernels.  There is no CPU fallback: without the built library or
+without a GPU these functions raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SO = os.path.join(HERE, "libpargeo_hip.so")
+
+PG_INT32, PG_FLOAT32 = 0, 1
+_STATUS = {0: "PG_OK", 1: "PG_ERR_INVALID", 2: "PG_ERR_RANGE", 3: "PG_ERR_NOMEM",
+           4: "PG_ERR_DEVICE", 5: "PG_ERR_UNSUPPORTED"}
+
+
+class PargeoError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class RangeError(PargeoError, ValueError):
+    pass
+
+
+_lib = None
+
+vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+P64 = ctypes.POINTER(ctypes.c_int64)
+P32 = ctypes.POINTER(ctypes.c_int32)
+
+# name -> (restype, argtypes); the declarations of include/pargeo_hip.h
+SIGNATURES = {
+    "pg_last_error": (ctypes.c_char_p, []),
+    "pg_version": (ctypes.c_char_p, []),
+    "pg_kdtree_build": (i32, [vp, i64, i32, i32, i32, vp, ctypes.POINTER(vp)]),
+    "pg_knn": (i32, [vp, vp, i64, i32, vp, vp, vp]),
+    "pg_knn_all": (i32, [vp, i32, vp, vp, vp]),
+    "pg_tree_info": (i32, [vp, P64, P32, P32, P32, P32]),
+    "pg_tree_export": (i32, [vp, vp, vp, vp]),
+    "pg_tree_free": (None, [vp]),
+}
+
+
+def lib():
+    """Loads the library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(SO):
+            raise RuntimeError(f"{SO} is missing: build it first (python -c 'import __graft_entry__ as g; g.build()')")
+        L = ctypes.CDLL(SO)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(status: int):
+    if status != 0:
+        msg = lib().pg_last_error().decode()
+        if status == 2:
+            raise RangeError(status, msg)
+        raise PargeoError(status, msg)
+
+
+def stream_ptr(device=None):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _dtype_code(t: torch.Tensor) -> int:
+    if t.dtype == torch.int32:
+        return PG_INT32
+    if t.dtype == torch.float32:
+        return PG_FLOAT32
+    raise TypeError(f"coordinates must be int32 or float32, got {t.dtype}")
+
+
+def _points(t: torch.Tensor, name: str) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dim() != 2:
+        raise ValueError(f"{name} must be [count][d]")
+    return t.contiguous()
+
+
+def _dist_dtype(code: int):
+    return torch.int64 if code == PG_INT32 else torch.float32
+
+
+class KdTree:
+    """Static kd-tree on the GPU (object-median splits, leaves of at most
+    ``leaf`` points).  Built by :func:`kdtree_build`."""
+
+    def __init__(self, handle, points_dtype: int, device):
+        self._h = handle
+        self.dtype_code = points_dtype
+        self.device = device
+        n, d, leaf, levels, dt = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        check(lib().pg_tree_info(self._h, ctypes.byref(n), ctypes.byref(d), ctypes.byref(leaf),
+                                 ctypes.byref(levels), ctypes.byref(dt)))
+        self.n, self.d, self.leaf, self.levels = n.value, d.value, leaf.value, levels.value
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.pg_tree_free(h)
+            self._h = None
+
+    def knn(self, queries: torch.Tensor, k: int):
+        """k nearest (distance, row) of each query: (idx int32 [m][k],
+        dist int64 or float32 [m][k])."""
+        q = _points(queries, "queries")
+        if _dtype_code(q) != self.dtype_code:
+            raise TypeError("queries must have the tree's dtype")
+        m = q.shape[0]
+        idx = torch.empty((m, k), dtype=torch.int32, device=q.device)
+        dist = torch.empty((m, k), dtype=_dist_dtype(self.dtype_code), device=q.device)
+        check(lib().pg_knn(self._h, ctypes.c_void_p(q.data_ptr()), m, k,
+                           ctypes.c_void_p(idx.data_ptr()), ctypes.c_void_p(dist.data_ptr()),
+                           stream_ptr(q.device)))
+        return idx, dist
+
+    def knn_all(self, k: int, out=None):
+        """All-points k-NN; row i belongs to input row i."""
+        if out is None:
+            idx = torch.empty((self.n, k), dtype=torch.int32, device=self.device)
+            dist = torch.empty((self.n, k), dtype=_dist_dtype(self.dtype_code), device=self.device)
+        else:
+            idx, dist = out
+        check(lib().pg_knn_all(self._h, k, ctypes.c_void_p(idx.data_ptr()),
+                               ctypes.c_void_p(dist.data_ptr()), stream_ptr(self.device)))
+        return idx, dist
+
+    def export(self):
+        """(split values of heap nodes 1..2^L-1, input rows in leaf order) as
+        NumPy arrays."""
+        import numpy as np
+        ni = (1 << self.levels) - 1
+        splits = np.empty(ni, dtype=np.int32 if self.dtype_code == PG_INT32 else np.float32)
+        perm = np.empty(self.n, dtype=np.int32)
+        check(lib().pg_tree_export(self._h, ctypes.c_void_p(splits.ctypes.data),
+                                   ctypes.c_void_p(perm.ctypes.data), stream_ptr(self.device)))
+        return splits, perm
+
+
+def kdtree_build(points: torch.Tensor, leaf: int = 16) -> KdTree:
+    p = _points(points, "points")
+    code = _dtype_code(p)
+    h = ctypes.c_void_p()
+    check(lib().pg_kdtree_build(ctypes.c_void_p(p.data_ptr()), p.shape[0], p.shape[1], leaf, code,
+                                stream_ptr(p.device), ctypes.byref(h)))
+    return KdTree(h, code, p.device)

@@ -1,0 +1,132 @@
+// C ABI of libpargeo_hip.so: argument validation, handles, memory, errors.
+#include <mutex>
+#include <new>
+#include <string>
+
+#include "build.hpp"
+#include "knn.hpp"
+
+namespace pg {
+
+namespace {
+thread_local std::string g_last_error = "no error";
+std::once_flag g_pool_once;
+
+void configure_pool() {
+    // Keep freed blocks in the stream-ordered pool instead of returning them
+    // at every synchronisation: repeated builds reuse the same memory.
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return;
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, dev) != hipSuccess) return;
+    uint64_t thr = UINT64_MAX;
+    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+}
+}  // namespace
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+pg_status fail(pg_status st, const std::string& msg) {
+    g_last_error = msg;
+    return st;
+}
+
+pg_status dmalloc(void** p, size_t bytes, hipStream_t s) {
+    std::call_once(g_pool_once, configure_pool);
+    hipError_t e = hipMallocAsync(p, bytes ? bytes : 4, s);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return fail(e == hipErrorOutOfMemory ? PG_ERR_NOMEM : PG_ERR_DEVICE,
+                    std::string("hipMallocAsync(") + std::to_string(bytes) + "): " +
+                        hipGetErrorString(e));
+    }
+    return PG_OK;
+}
+
+void dfree(void* p, hipStream_t s) {
+    if (p) (void)hipFreeAsync(p, s);
+}
+
+static void tree_release(pg_tree* t) {
+    if (!t) return;
+    dfree(t->pts, t->stream);
+    dfree(t->pidx, t->stream);
+    dfree(t->split, t->stream);
+    dfree(t->bbox, t->stream);
+    delete t;
+}
+
+}  // namespace pg
+
+using namespace pg;
+
+extern "C" {
+
+const char* pg_last_error(void) { return g_last_error.c_str(); }
+
+const char* pg_version(void) { return "pargeo_hip 0.1 (gfx950)"; }
+
+pg_status pg_kdtree_build(const void* points, int64_t n, int32_t d, int32_t leaf, int32_t dtype,
+                          void* stream, pg_tree** out) {
+    if (!out) return fail(PG_ERR_INVALID, "pg_kdtree_build: out is NULL");
+    if (d < 1 || d > 8) return fail(PG_ERR_INVALID, "pg_kdtree_build: d must be in [1, 8]");
+    if (leaf < 1 || leaf > 64) return fail(PG_ERR_INVALID, "pg_kdtree_build: leaf must be in [1, 64]");
+    if (n < 0 || n >= ((int64_t)1 << 31)) return fail(PG_ERR_INVALID, "pg_kdtree_build: n must be in [0, 2^31)");
+    if (dtype != PG_INT32 && dtype != PG_FLOAT32) return fail(PG_ERR_INVALID, "pg_kdtree_build: bad dtype");
+    if (n > 0 && !points) return fail(PG_ERR_INVALID, "pg_kdtree_build: points is NULL");
+    pg_tree* t = new (std::nothrow) pg_tree();
+    if (!t) return fail(PG_ERR_NOMEM, "pg_kdtree_build: host allocation failed");
+    pg_status st = build_tree(points, n, d, leaf, dtype, (hipStream_t)stream, t);
+    if (st != PG_OK) {
+        tree_release(t);
+        return st;
+    }
+    *out = t;
+    return PG_OK;
+}
+
+pg_status pg_knn(const pg_tree* t, const void* queries, int64_t m, int32_t k, int32_t* out_idx,
+                 void* out_dist, void* stream) {
+    if (!t) return fail(PG_ERR_INVALID, "pg_knn: tree is NULL");
+    if (k < 1 || k > 64) return fail(PG_ERR_INVALID, "pg_knn: k must be in [1, 64]");
+    if (m < 0 || m >= ((int64_t)1 << 31)) return fail(PG_ERR_INVALID, "pg_knn: m must be in [0, 2^31)");
+    if (m > 0 && (!queries || !out_idx || !out_dist)) return fail(PG_ERR_INVALID, "pg_knn: NULL pointer");
+    hipStream_t s = (hipStream_t)stream;
+    PG_TRY(check_queries(queries, m, t->d, t->dtype == PG_FLOAT32, s));
+    return knn_static(t, queries, m, k, false, out_idx, out_dist, s);
+}
+
+pg_status pg_knn_all(const pg_tree* t, int32_t k, int32_t* out_idx, void* out_dist, void* stream) {
+    if (!t) return fail(PG_ERR_INVALID, "pg_knn_all: tree is NULL");
+    if (k < 1 || k > 64) return fail(PG_ERR_INVALID, "pg_knn_all: k must be in [1, 64]");
+    if (t->n > 0 && (!out_idx || !out_dist)) return fail(PG_ERR_INVALID, "pg_knn_all: NULL pointer");
+    return knn_static(t, nullptr, t->n, k, true, out_idx, out_dist, (hipStream_t)stream);
+}
+
+pg_status pg_tree_info(const pg_tree* t, int64_t* n, int32_t* d, int32_t* leaf, int32_t* levels,
+                       int32_t* dtype) {
+    if (!t) return fail(PG_ERR_INVALID, "pg_tree_info: tree is NULL");
+    if (n) *n = t->n;
+    if (d) *d = t->d;
+    if (leaf) *leaf = t->leaf;
+    if (levels) *levels = t->L;
+    if (dtype) *dtype = t->dtype;
+    return PG_OK;
+}
+
+pg_status pg_tree_export(const pg_tree* t, void* splits_host, int32_t* perm_host, void* stream) {
+    if (!t) return fail(PG_ERR_INVALID, "pg_tree_export: tree is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t ni = ((int64_t)1 << t->L) - 1;
+    if (splits_host && ni > 0)
+        PG_HIP(hipMemcpyAsync(splits_host, t->split + 1, sizeof(uint32_t) * ni,
+                              hipMemcpyDeviceToHost, s));
+    if (perm_host && t->n > 0)
+        PG_HIP(hipMemcpyAsync(perm_host, t->pidx, sizeof(int32_t) * t->n, hipMemcpyDeviceToHost, s));
+    PG_HIP(hipStreamSynchronize(s));
+    return PG_OK;
+}
+
+void pg_tree_free(pg_tree* t) { tree_release(t); }
+
+}  // extern "C"

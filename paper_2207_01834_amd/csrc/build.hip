@@ -1,0 +1,587 @@
+// Static kd-tree construction on the GPU (level-synchronous object-median
+// splits).
+//
+// What is computed (Section 5 and Appendix C, "Parallel vEB Construction":
+// one median partition per level, O(n) work per level): node j of level l
+// owns leaf-order positions [floor(j n/2^l), floor((j+1) n/2^l)); its left
+// child receives the r = floor((2j+1)n/2^(l+1)) - floor(j n/2^l) smallest
+// points under (coordinate along dimension l mod d, input row), its right
+// child the rest, and the split value is the coordinate of the rank-r point.
+//
+// How (MI355X): coordinates become order-preserving 32-bit keys stored as SoA
+// planes.  Every partition is stable, so each node segment stays in input-row
+// order and "ties by input row" becomes "ties by position in the segment".
+//   * wide levels (< 512 nodes): radix select over 11-bit digits with
+//     multi-workgroup LDS histograms merged by global atomics, then a stable
+//     scatter whose per-workgroup offsets come from a per-node scan;
+//   * middle levels (>= 512 nodes, node > S points): one workgroup per node
+//     does an 8-bit radix select and the stable partition itself;
+//   * bottom levels (node <= S points): one workgroup per subtree loads it into
+//     LDS, and each wave selects (bitwise radix with ballots) and partitions
+//     whole nodes until the leaves, then writes the coordinates, the input
+//     rows, the split values and the per-leaf bounding boxes.
+#include <utility>
+
+#include "build.hpp"
+#include "wave.hpp"
+
+namespace pg {
+
+namespace {
+
+constexpr int kNT = 256;            // threads per workgroup
+constexpr int kChunk = 16384;       // elements per workgroup in the wide levels
+constexpr int kWideDigit = 11;      // radix digit width in the wide levels
+constexpr int kWideNodes = 512;     // levels with fewer nodes use the wide path
+
+struct NodeSel {
+    uint32_t prefix;  // selected key bits so far; the pivot key at the end
+    uint32_t rank;    // target rank among keys matching prefix; at the end the
+                      // number of pivot-equal keys that go left
+};
+
+__device__ inline int64_t split_rank_pos(int64_t n, int l, int64_t j, int64_t* lo,
+                                         int64_t* hi, int64_t* mid) {
+    *lo = node_start(n, l, j);
+    *hi = node_start(n, l, j + 1);
+    *mid = node_start(n, l + 1, 2 * j + 1);
+    return (*mid < *hi ? *mid : *hi - 1) - *lo;
+}
+
+// ---------------------------------------------------------------------------
+// Ingest: caller's [n][d] rows -> key planes + input-row plane; range check;
+// -0.0 -> +0.0; per-dimension OR of (key ^ key of row 0).
+// ---------------------------------------------------------------------------
+__global__ void ingest_kernel(const uint32_t* __restrict__ in, int64_t n, int d, int fl,
+                              uint32_t* __restrict__ keys, int32_t* __restrict__ idx,
+                              uint32_t* __restrict__ vary, uint32_t* __restrict__ keybase,
+                              uint32_t* __restrict__ err) {
+    __shared__ uint32_t s_vary[8];
+    __shared__ uint32_t s_err;
+    if (threadIdx.x < 8) s_vary[threadIdx.x] = 0;
+    if (threadIdx.x == 0) s_err = 0;
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t bad = 0;
+    if (i < n) {
+        for (int c = 0; c < d; c++) {
+            uint32_t b = in[i * d + c];
+            uint32_t b0 = in[c];
+            if (fl) {
+                if (b == 0x80000000u) b = 0;
+                if (b0 == 0x80000000u) b0 = 0;
+                float x = __uint_as_float(b);
+                if (!(fabsf(x) <= 1e18f)) bad = 1;  // also catches NaN and inf
+            } else {
+                int32_t x = (int32_t)b;
+                if (x < -(1 << 29) || x >= (1 << 29)) bad = 1;
+            }
+            uint32_t k = coord_to_key(b, fl), k0 = coord_to_key(b0, fl);
+            keys[(int64_t)c * n + i] = k;
+            uint32_t v = k ^ k0;
+            if (v) atomicOr(&s_vary[c], v);
+            if (i == 0) keybase[c] = k0;
+        }
+        idx[i] = (int32_t)i;
+    }
+    if (bad) atomicOr(&s_err, 1u);
+    __syncthreads();
+    if (threadIdx.x < d && s_vary[threadIdx.x]) atomicOr(&vary[threadIdx.x], s_vary[threadIdx.x]);
+    if (threadIdx.x == 0 && s_err) atomicOr(err, 1u);
+}
+
+// ---------------------------------------------------------------------------
+// Wide levels.
+// ---------------------------------------------------------------------------
+__global__ void wide_init_kernel(NodeSel* ns, int64_t J, int64_t n, int l, uint32_t prefix0,
+                                 int write_split, uint32_t* split_level, int fl) {
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= J) return;
+    int64_t lo, hi, mid;
+    int64_t r = split_rank_pos(n, l, j, &lo, &hi, &mid);
+    ns[j].prefix = prefix0;
+    ns[j].rank = (uint32_t)r;
+    if (write_split) split_level[j] = key_to_coord(prefix0, fl);
+}
+
+__global__ void __launch_bounds__(kNT)
+wide_hist_kernel(const uint32_t* __restrict__ keys, int64_t n, int l, int bpn,
+                 const NodeSel* __restrict__ ns, int shift, int width,
+                 uint32_t* __restrict__ ghist) {
+    extern __shared__ uint32_t lh[];
+    const int64_t j = blockIdx.x / bpn;
+    const int t = blockIdx.x % bpn;
+    const int64_t lo = node_start(n, l, j), hi = node_start(n, l, j + 1);
+    const int64_t e0 = lo + (int64_t)t * kChunk;
+    const int64_t e1 = min(e0 + kChunk, hi);
+    const int nb = 1 << width;
+    for (int b = threadIdx.x; b < nb; b += kNT) lh[b] = 0;
+    __syncthreads();
+    const int hs = shift + width;
+    const uint64_t pre = (uint64_t)ns[j].prefix >> hs;
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += kNT) {
+        uint32_t k = keys[e];
+        if (((uint64_t)k >> hs) == pre) atomicAdd(&lh[(k >> shift) & (nb - 1)], 1u);
+    }
+    __syncthreads();
+    uint32_t* gh = ghist + j * nb;
+    for (int b = threadIdx.x; b < nb; b += kNT) {
+        uint32_t c = lh[b];
+        if (c) atomicAdd(&gh[b], c);
+    }
+}
+
+__global__ void __launch_bounds__(kNT)
+wide_select_kernel(uint32_t* __restrict__ ghist, NodeSel* __restrict__ ns, int shift, int width,
+                   int last, uint32_t* __restrict__ split_level, int fl) {
+    __shared__ uint32_t lds[kNT / kWave + 1];
+    const int64_t j = blockIdx.x;
+    const int nb = 1 << width;
+    const int per = (nb + kNT - 1) / kNT;  // <= 8
+    uint32_t* gh = ghist + j * nb;
+    uint32_t loc[8];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int i = 0; i < 8; i++) {
+        int b = threadIdx.x * per + i;
+        loc[i] = (i < per && b < nb) ? gh[b] : 0u;
+        sum += loc[i];
+    }
+    const uint32_t prefix = ns[j].prefix, r = ns[j].rank;
+    uint32_t tot;
+    uint32_t excl = block_excl_scan<kNT>(sum, lds, &tot);
+    if (sum > 0 && excl <= r && r < excl + sum) {
+        uint32_t cum = excl;
+        for (int i = 0; i < per; i++) {
+            if (r < cum + loc[i]) {
+                uint32_t bin = threadIdx.x * per + i;
+                uint32_t np = prefix | (bin << shift);
+                ns[j].prefix = np;
+                ns[j].rank = r - cum;
+                if (last) split_level[j] = key_to_coord(np, fl);
+                break;
+            }
+            cum += loc[i];
+        }
+    }
+    for (int i = 0; i < per; i++) {
+        int b = threadIdx.x * per + i;
+        if (b < nb) gh[b] = 0;
+    }
+}
+
+__global__ void __launch_bounds__(kNT)
+wide_count_kernel(const uint32_t* __restrict__ keys, int64_t n, int l, int bpn,
+                  const NodeSel* __restrict__ ns, uint64_t* __restrict__ bcnt) {
+    __shared__ uint64_t red[kNT / kWave];
+    const int64_t j = blockIdx.x / bpn;
+    const int t = blockIdx.x % bpn;
+    const int64_t lo = node_start(n, l, j), hi = node_start(n, l, j + 1);
+    const int64_t e0 = lo + (int64_t)t * kChunk;
+    const int64_t e1 = min(e0 + kChunk, hi);
+    const uint32_t v = ns[j].prefix;
+    uint64_t acc = 0;  // lt in the low 32 bits, eq in the high 32 bits
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += kNT) {
+        uint32_t k = keys[e];
+        acc += (k < v) ? 1ull : ((k == v) ? (1ull << 32) : 0ull);
+    }
+    acc = wave_sum(acc);
+    if (lane_id() == 0) red[threadIdx.x / kWave] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t s = 0;
+        for (int w = 0; w < kNT / kWave; w++) s += red[w];
+        bcnt[blockIdx.x] = s;
+    }
+}
+
+// Per node: exclusive scan of the per-workgroup (lt, eq) counts.
+__global__ void __launch_bounds__(kNT)
+wide_scan_kernel(uint64_t* __restrict__ bcnt, int bpn) {
+    __shared__ uint64_t lds[kNT / kWave + 1];
+    uint64_t* b = bcnt + (int64_t)blockIdx.x * bpn;
+    uint64_t run = 0;
+    for (int t0 = 0; t0 < bpn; t0 += kNT) {
+        int t = t0 + threadIdx.x;
+        uint64_t v = t < bpn ? b[t] : 0ull;
+        uint64_t tot;
+        uint64_t ex = block_excl_scan<kNT>(v, lds, &tot);
+        if (t < bpn) b[t] = run + ex;
+        run += tot;
+    }
+}
+
+// Stable partition of one tile of consecutive elements [base, base+NT) of a
+// node; run_lt / run_eq count the node's elements before the tile.
+__device__ inline void partition_tile(const uint32_t* __restrict__ in, const int32_t* __restrict__ in_idx,
+                                      uint32_t* __restrict__ out, int32_t* __restrict__ out_idx,
+                                      int d, int c, int64_t n, int64_t base, int64_t end,
+                                      int64_t lo, int64_t mid, int64_t end_node, uint32_t v,
+                                      uint32_t teq,
+                                      uint32_t& run_lt, uint32_t& run_eq, uint32_t* lds) {
+    const int64_t e = base + threadIdx.x;
+    const bool valid = e < end;
+    const uint32_t k = valid ? in[(int64_t)c * n + e] : 0u;
+    const bool lt = valid && k < v;
+    const bool eq = valid && k == v;
+    uint32_t tot;
+    uint32_t ex = block_excl_scan<kNT>((lt ? 1u : 0u) | (eq ? 0x10000u : 0u), lds, &tot);
+    const uint32_t ltb = run_lt + (ex & 0xffffu);
+    const uint32_t eqb = run_eq + (ex >> 16);
+    if (valid) {
+        const uint32_t el = eqb < teq ? eqb : teq;
+        int64_t dest;
+        if (lt) dest = lo + ltb + el;
+        else if (eq && eqb < teq) dest = lo + ltb + eqb;
+        else dest = mid + (e - lo) - (int64_t)(ltb + el);
+        if (dest >= lo && dest < end_node) {  // always true for a consistent split
+            for (int cc = 0; cc < d; cc++)
+                out[(int64_t)cc * n + dest] = cc == c ? k : in[(int64_t)cc * n + e];
+            out_idx[dest] = in_idx[e];
+        }
+    }
+    run_lt += tot & 0xffffu;
+    run_eq += tot >> 16;
+}
+
+__global__ void __launch_bounds__(kNT)
+wide_scatter_kernel(const uint32_t* __restrict__ in, const int32_t* __restrict__ in_idx,
+                    uint32_t* __restrict__ out, int32_t* __restrict__ out_idx, int d, int c,
+                    int64_t n, int l, int bpn, const NodeSel* __restrict__ ns,
+                    const uint64_t* __restrict__ boff) {
+    __shared__ uint32_t lds[kNT / kWave + 1];
+    const int64_t j = blockIdx.x / bpn;
+    const int t = blockIdx.x % bpn;
+    int64_t lo, hi, mid;
+    split_rank_pos(n, l, j, &lo, &hi, &mid);
+    const int64_t e0 = lo + (int64_t)t * kChunk;
+    const int64_t e1 = min(e0 + kChunk, hi);
+    const uint32_t v = ns[j].prefix, teq = ns[j].rank;
+    uint32_t run_lt = (uint32_t)(boff[blockIdx.x] & 0xffffffffull);
+    uint32_t run_eq = (uint32_t)(boff[blockIdx.x] >> 32);
+    for (int64_t base = e0; base < e1; base += kNT)
+        partition_tile(in, in_idx, out, out_idx, d, c, n, base, e1, lo, mid, hi, v, teq, run_lt,
+                       run_eq, lds);
+}
+
+// ---------------------------------------------------------------------------
+// Middle levels: one workgroup per node selects (8-bit digits) and partitions.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kNT)
+node_kernel(const uint32_t* __restrict__ in, const int32_t* __restrict__ in_idx,
+            uint32_t* __restrict__ out, int32_t* __restrict__ out_idx, int d, int c, int64_t n,
+            int l, uint32_t prefix0, int sb, uint32_t* __restrict__ split_level, int fl) {
+    __shared__ uint32_t hist[kNT];
+    __shared__ uint32_t lds[kNT / kWave + 1];
+    __shared__ uint32_t sel[2];
+    const int64_t j = blockIdx.x;
+    int64_t lo, hi, mid;
+    uint32_t r = (uint32_t)split_rank_pos(n, l, j, &lo, &hi, &mid);
+    const uint32_t* keys = in + (int64_t)c * n;
+    uint32_t prefix = prefix0;
+    for (int hb = sb; hb > 0; hb -= 8) {
+        const int shift = hb > 8 ? hb - 8 : 0;
+        const uint32_t wmask = (1u << (hb - shift)) - 1u;
+        hist[threadIdx.x] = 0;
+        __syncthreads();
+        const uint64_t pre = (uint64_t)prefix >> hb;
+        for (int64_t e = lo + threadIdx.x; e < hi; e += kNT) {
+            uint32_t k = keys[e];
+            if (((uint64_t)k >> hb) == pre) atomicAdd(&hist[(k >> shift) & wmask], 1u);
+        }
+        __syncthreads();
+        const uint32_t cnt = hist[threadIdx.x];
+        uint32_t tot;
+        const uint32_t ex = block_excl_scan<kNT>(cnt, lds, &tot);
+        if (cnt > 0 && ex <= r && r < ex + cnt) {
+            sel[0] = prefix | ((uint32_t)threadIdx.x << shift);
+            sel[1] = r - ex;
+        }
+        __syncthreads();
+        prefix = sel[0];
+        r = sel[1];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) split_level[j] = key_to_coord(prefix, fl);
+    uint32_t run_lt = 0, run_eq = 0;
+    for (int64_t base = lo; base < hi; base += kNT)
+        partition_tile(in, in_idx, out, out_idx, d, c, n, base, hi, lo, mid, hi, prefix, r,
+                       run_lt, run_eq, lds);
+}
+
+// ---------------------------------------------------------------------------
+// Bottom levels: one workgroup per subtree, in LDS.
+// ---------------------------------------------------------------------------
+
+// One wave selects the rank-r key of node [lo, hi) (local positions, order
+// given by pin) and writes the stable partition into pout.  Returns the
+// split key.  mid == hi (right child empty) splits at the largest key and
+// sends everything left.
+__device__ uint32_t wave_select_partition(const uint32_t* keys, const uint16_t* pin,
+                                          uint16_t* pout, int lo, int hi, int mid) {
+    const int lane = lane_id();
+    const bool right_empty = mid >= hi;
+    uint32_t r = (uint32_t)((right_empty ? hi - 1 : mid) - lo);
+    uint32_t mn = 0xffffffffu, mx = 0;
+    for (int e = lo + lane; e < hi; e += kWave) {
+        uint32_t k = keys[pin[e]];
+        mn = k < mn ? k : mn;
+        mx = k > mx ? k : mx;
+    }
+    mn = wave_min_u32(mn);
+    mx = wave_max_u32(mx);
+    uint32_t prefix = mn;
+    if (mn != mx) {
+        const int hb = 31 - __clz(mn ^ mx);
+        prefix = hb == 31 ? 0u : (mn & ~((2u << hb) - 1u));
+        for (int b = hb; b >= 0; --b) {
+            const uint32_t want = (prefix >> b) >> 1;
+            uint32_t cnt0 = 0;
+            for (int e0 = lo; e0 < hi; e0 += kWave) {
+                const int e = e0 + lane;
+                bool p = false;
+                if (e < hi) {
+                    const uint32_t k = keys[pin[e]];
+                    p = ((k >> b) >> 1) == want && !((k >> b) & 1u);
+                }
+                cnt0 += (uint32_t)__popcll(ballot(p));
+            }
+            if (r >= cnt0) {
+                prefix |= 1u << b;
+                r -= cnt0;
+            }
+        }
+    }
+    const uint32_t v = prefix;
+    const uint32_t teq = right_empty ? 0xffffffffu : r;
+    uint32_t run_lt = 0, run_eq = 0;
+    for (int e0 = lo; e0 < hi; e0 += kWave) {
+        const int e = e0 + lane;
+        const bool valid = e < hi;
+        const uint16_t p = valid ? pin[e] : (uint16_t)0;
+        const uint32_t k = valid ? keys[p] : 0u;
+        const bool lt = valid && k < v;
+        const bool eq = valid && k == v;
+        const uint64_t mlt = ballot(lt), meq = ballot(eq);
+        const uint32_t ltb = run_lt + lane_prefix(mlt);
+        const uint32_t eqb = run_eq + lane_prefix(meq);
+        if (valid) {
+            const uint32_t el = eqb < teq ? eqb : teq;
+            int dest;
+            if (lt) dest = lo + (int)(ltb + el);
+            else if (eq && eqb < teq) dest = lo + (int)(ltb + eqb);
+            else dest = mid + (e - lo) - (int)(ltb + el);
+            if (dest >= lo && dest < hi) pout[dest] = p;  // always true for a consistent split
+        }
+        run_lt += (uint32_t)__popcll(mlt);
+        run_eq += (uint32_t)__popcll(meq);
+    }
+    return v;
+}
+
+__global__ void __launch_bounds__(kNT)
+subtree_kernel(const uint32_t* __restrict__ in, const int32_t* __restrict__ in_idx, int64_t n,
+               int d, int L, int ls, int S, int fl, uint32_t* __restrict__ out_pts,
+               int32_t* __restrict__ out_idx, uint32_t* __restrict__ split,
+               uint32_t* __restrict__ bbox) {
+    extern __shared__ uint32_t sm[];
+    uint32_t* skeys = sm;                                    // [d][S]
+    int32_t* sidx = (int32_t*)(sm + (size_t)d * S);          // [S]
+    uint16_t* pa = (uint16_t*)(sidx + S);                    // [S]
+    uint16_t* pb = pa + S;                                   // [S]
+    const int64_t j0 = blockIdx.x;
+    const int64_t base = node_start(n, ls, j0);
+    const int s = (int)(node_start(n, ls, j0 + 1) - base);
+    for (int e = threadIdx.x; e < s; e += kNT) {
+        for (int c = 0; c < d; c++) skeys[c * S + e] = in[(int64_t)c * n + base + e];
+        sidx[e] = in_idx[base + e];
+        pa[e] = (uint16_t)e;
+    }
+    __syncthreads();
+    const int w = threadIdx.x / kWave;
+    constexpr int NW = kNT / kWave;
+    uint16_t* pin = pa;
+    uint16_t* pout = pb;
+    for (int t = 0; t < L - ls; t++) {
+        const int l = ls + t;
+        const int c = l % d;
+        const int nodes = 1 << t;
+        for (int u = w; u < nodes; u += NW) {
+            const int64_t jj = (j0 << t) + u;
+            const int lo = (int)(node_start(n, l, jj) - base);
+            const int hi = (int)(node_start(n, l, jj + 1) - base);
+            const int mid = (int)(node_start(n, l + 1, 2 * jj + 1) - base);
+            const uint32_t v = wave_select_partition(skeys + c * S, pin, pout, lo, hi, mid);
+            if (lane_id() == 0) split[((int64_t)1 << l) + jj] = key_to_coord(v, fl);
+        }
+        __syncthreads();
+        uint16_t* tmp = pin;
+        pin = pout;
+        pout = tmp;
+    }
+    for (int e = threadIdx.x; e < s; e += kNT) {
+        const int p = pin[e];
+        for (int c = 0; c < d; c++)
+            out_pts[(int64_t)c * n + base + e] = key_to_coord(skeys[c * S + p], fl);
+        out_idx[base + e] = sidx[p];
+    }
+    const int nl = 1 << (L - ls);
+    for (int q = threadIdx.x; q < nl * d; q += kNT) {
+        const int leafl = q / d, c = q % d;
+        const int64_t jj = (j0 << (L - ls)) + leafl;
+        const int llo = (int)(node_start(n, L, jj) - base);
+        const int lhi = (int)(node_start(n, L, jj + 1) - base);
+        uint32_t mn = 0xffffffffu, mx = 0;
+        for (int e = llo; e < lhi; e++) {
+            const uint32_t k = skeys[c * S + pin[e]];
+            mn = k < mn ? k : mn;
+            mx = k > mx ? k : mx;
+        }
+        if (llo == lhi) mn = mx = 0x80000000u;  // empty leaf (leaf size 1 only)
+        bbox[jj * 2 * d + c] = key_to_coord(mn, fl);
+        bbox[jj * 2 * d + d + c] = key_to_coord(mx, fl);
+    }
+}
+
+}  // namespace
+
+int subtree_capacity(int d) { return d <= 5 ? 2048 : 1024; }
+
+pg_status ingest_points(const void* points, int64_t n, int d, bool fl, uint32_t* keys,
+                        int32_t* idx, uint32_t* vary_host, uint32_t* keybase_host,
+                        hipStream_t s) {
+    DevBuf aux(s);
+    PG_TRY(aux.alloc(sizeof(uint32_t) * 17));
+    uint32_t* vary = aux.as<uint32_t>();
+    uint32_t* keybase = vary + 8;
+    uint32_t* err = vary + 16;
+    PG_HIP(hipMemsetAsync(vary, 0, sizeof(uint32_t) * 17, s));
+    if (n > 0) {
+        hipLaunchKernelGGL(ingest_kernel, dim3(cdiv(n, kNT)), dim3(kNT), 0, s,
+                           (const uint32_t*)points, n, d, fl ? 1 : 0, keys, idx, vary, keybase,
+                           err);
+        PG_LAUNCH_CHECK();
+    }
+    uint32_t host[17];
+    PG_HIP(hipMemcpyAsync(host, vary, sizeof(host), hipMemcpyDeviceToHost, s));
+    PG_HIP(hipStreamSynchronize(s));
+    if (host[16]) return fail(PG_ERR_RANGE, "coordinate out of range (int32: [-2^29, 2^29); float32: finite, |x| <= 1e18)");
+    for (int c = 0; c < d; c++) {
+        vary_host[c] = host[c];
+        keybase_host[c] = host[8 + c];
+    }
+    return PG_OK;
+}
+
+pg_status build_from_keys(uint32_t* kA, int32_t* iA, uint32_t* kB, int32_t* iB, int64_t n,
+                          int d, int leaf, bool fl, const uint32_t* vary,
+                          const uint32_t* keybase, hipStream_t s, pg_tree* T) {
+    const int L = T->L;
+    const int S = subtree_capacity(d);
+    int ls = 0;
+    while (((n + ((int64_t)1 << ls) - 1) >> ls) > S) ls++;
+    const int ifl = fl ? 1 : 0;
+
+    uint32_t* cur_k = kA;
+    int32_t* cur_i = iA;
+    uint32_t* oth_k = kB;
+    int32_t* oth_i = iB;
+
+    DevBuf nsel(s), ghist(s), bcnt(s);
+    int wide_levels = 0;
+    while (wide_levels < ls && ((int64_t)1 << wide_levels) < kWideNodes) wide_levels++;
+    if (wide_levels > 0) {
+        const int64_t Jmax = (int64_t)1 << (wide_levels - 1);
+        int64_t blocks_max = 1;
+        for (int l = 0; l < wide_levels; l++) {
+            const int64_t J = (int64_t)1 << l;
+            const int64_t b = J * (int64_t)cdiv((n + J - 1) / J, kChunk);
+            blocks_max = b > blocks_max ? b : blocks_max;
+        }
+        PG_TRY(nsel.alloc(sizeof(NodeSel) * Jmax));
+        PG_TRY(ghist.alloc(sizeof(uint32_t) * Jmax * (1 << kWideDigit)));
+        PG_TRY(bcnt.alloc(sizeof(uint64_t) * blocks_max));
+        PG_HIP(hipMemsetAsync(ghist.p, 0, sizeof(uint32_t) * Jmax * (1 << kWideDigit), s));
+    }
+
+    for (int l = 0; l < ls; l++) {
+        const int64_t J = (int64_t)1 << l;
+        const int c = l % d;
+        const int sb = vary[c] ? 32 - __builtin_clz(vary[c]) : 0;
+        const uint32_t lowmask = sb >= 32 ? 0xffffffffu : ((1u << sb) - 1u);
+        const uint32_t prefix0 = keybase[c] & ~lowmask;
+        uint32_t* split_level = T->split + J;
+        if (l < wide_levels) {
+            const int64_t smax = (n + J - 1) / J;
+            const int bpn = (int)cdiv(smax, kChunk);
+            const unsigned nblk = (unsigned)(J * bpn);
+            NodeSel* ns = nsel.as<NodeSel>();
+            hipLaunchKernelGGL(wide_init_kernel, dim3(cdiv(J, kNT)), dim3(kNT), 0, s, ns, J, n, l,
+                               prefix0, sb == 0 ? 1 : 0, split_level, ifl);
+            PG_LAUNCH_CHECK();
+            for (int hb = sb; hb > 0; hb -= kWideDigit) {
+                const int shift = hb > kWideDigit ? hb - kWideDigit : 0;
+                const int width = hb - shift;
+                const uint32_t* keys = cur_k + (int64_t)c * n;
+                hipLaunchKernelGGL(wide_hist_kernel, dim3(nblk), dim3(kNT),
+                                   sizeof(uint32_t) << width, s, keys, n, l, bpn, ns, shift,
+                                   width, ghist.as<uint32_t>());
+                PG_LAUNCH_CHECK();
+                hipLaunchKernelGGL(wide_select_kernel, dim3((unsigned)J), dim3(kNT), 0, s,
+                                   ghist.as<uint32_t>(), ns, shift, width, shift == 0 ? 1 : 0,
+                                   split_level, ifl);
+                PG_LAUNCH_CHECK();
+            }
+            hipLaunchKernelGGL(wide_count_kernel, dim3(nblk), dim3(kNT), 0, s,
+                               cur_k + (int64_t)c * n, n, l, bpn, ns, bcnt.as<uint64_t>());
+            PG_LAUNCH_CHECK();
+            hipLaunchKernelGGL(wide_scan_kernel, dim3((unsigned)J), dim3(kNT), 0, s,
+                               bcnt.as<uint64_t>(), bpn);
+            PG_LAUNCH_CHECK();
+            hipLaunchKernelGGL(wide_scatter_kernel, dim3(nblk), dim3(kNT), 0, s, cur_k, cur_i,
+                               oth_k, oth_i, d, c, n, l, bpn, ns, bcnt.as<uint64_t>());
+            PG_LAUNCH_CHECK();
+        } else {
+            hipLaunchKernelGGL(node_kernel, dim3((unsigned)J), dim3(kNT), 0, s, cur_k, cur_i,
+                               oth_k, oth_i, d, c, n, l, prefix0, sb, split_level, ifl);
+            PG_LAUNCH_CHECK();
+        }
+        std::swap(cur_k, oth_k);
+        std::swap(cur_i, oth_i);
+    }
+
+    const size_t lds = (size_t)d * S * 4 + (size_t)S * 4 + (size_t)S * 4;
+    hipLaunchKernelGGL(subtree_kernel, dim3((unsigned)((int64_t)1 << ls)), dim3(kNT), lds, s,
+                       cur_k, cur_i, n, d, L, ls, S, ifl, T->pts, T->pidx, T->split, T->bbox);
+    PG_LAUNCH_CHECK();
+    return PG_OK;
+}
+
+pg_status build_tree(const void* points, int64_t n, int d, int leaf, int dtype, hipStream_t s,
+                     pg_tree* T) {
+    const bool fl = dtype == PG_FLOAT32;
+    T->n = n;
+    T->d = d;
+    T->leaf = leaf;
+    T->dtype = dtype;
+    T->stream = s;
+    T->L = tree_levels(n, leaf);
+    const int64_t nleaves = (int64_t)1 << T->L;
+    const int64_t nn = n > 0 ? n : 1;
+    PG_TRY(dalloc(&T->pts, (size_t)d * nn, s));
+    PG_TRY(dalloc(&T->pidx, (size_t)nn, s));
+    PG_TRY(dalloc(&T->split, (size_t)nleaves, s));
+    PG_TRY(dalloc(&T->bbox, (size_t)nleaves * 2 * d, s));
+    if (n == 0) return PG_OK;
+    DevBuf tmpk(s), tmpi(s);
+    PG_TRY(tmpk.alloc(sizeof(uint32_t) * (size_t)d * n));
+    PG_TRY(tmpi.alloc(sizeof(int32_t) * (size_t)n));
+    uint32_t vary[8] = {0}, keybase[8] = {0};
+    // Keys go into the tree's own arrays first; the bottom-level pass reads
+    // each subtree into LDS before writing coordinates back in place.
+    PG_TRY(ingest_points(points, n, d, fl, T->pts, T->pidx, vary, keybase, s));
+    return build_from_keys(T->pts, T->pidx, tmpk.as<uint32_t>(), tmpi.as<int32_t>(), n, d, leaf,
+                           fl, vary, keybase, s, T);
+}
+
+}  // namespace pg

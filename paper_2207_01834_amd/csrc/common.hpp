@@ -1,0 +1,121 @@
+// Internal helpers shared by the kernels and the host runtime of
+// libpargeo_hip.so (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string>
+
+#include "pargeo_hip.h"
+
+namespace pg {
+
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------------------
+// Errors: thread-local last-error text plus status propagation.
+// ---------------------------------------------------------------------------
+void set_error(const std::string& msg);
+pg_status fail(pg_status st, const std::string& msg);
+
+#define PG_HIP(call)                                                              \
+    do {                                                                          \
+        hipError_t e_ = (call);                                                   \
+        if (e_ != hipSuccess)                                                     \
+            return ::pg::fail(e_ == hipErrorOutOfMemory ? PG_ERR_NOMEM : PG_ERR_DEVICE, \
+                              std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define PG_LAUNCH_CHECK()                                                         \
+    do {                                                                          \
+        hipError_t e_ = hipGetLastError();                                        \
+        if (e_ != hipSuccess)                                                     \
+            return ::pg::fail(PG_ERR_DEVICE, std::string("kernel launch: ") +     \
+                                                 hipGetErrorString(e_));         \
+    } while (0)
+
+#define PG_TRY(expr)                                                              \
+    do {                                                                          \
+        pg_status s_ = (expr);                                                    \
+        if (s_ != PG_OK) return s_;                                               \
+    } while (0)
+
+// Stream-ordered device memory (pool-backed).
+pg_status dmalloc(void** p, size_t bytes, hipStream_t s);
+void dfree(void* p, hipStream_t s);
+
+template <typename T>
+pg_status dalloc(T** p, size_t count, hipStream_t s) {
+    return dmalloc(reinterpret_cast<void**>(p), count * sizeof(T), s);
+}
+
+// RAII holder for temporaries released in stream order.
+struct DevBuf {
+    void* p = nullptr;
+    hipStream_t s = nullptr;
+    DevBuf() = default;
+    explicit DevBuf(hipStream_t st) : s(st) {}
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf() { if (p) dfree(p, s); }
+    template <typename T> T* as() const { return reinterpret_cast<T*>(p); }
+    pg_status alloc(size_t bytes) {
+        if (p) { dfree(p, s); p = nullptr; }
+        return dmalloc(&p, bytes ? bytes : 4, s);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Order-preserving 32-bit keys of the stored coordinates.
+//   int32 : offset binary (x + 2^31)
+//   float : sign-magnitude flip (negative: all bits inverted; else sign set)
+// Keys compare as unsigned integers exactly as the coordinates compare.
+// ---------------------------------------------------------------------------
+__host__ __device__ inline uint32_t coord_to_key(uint32_t bits, bool fl) {
+    if (!fl) return bits ^ 0x80000000u;
+    return (bits & 0x80000000u) ? ~bits : (bits | 0x80000000u);
+}
+__host__ __device__ inline uint32_t key_to_coord(uint32_t key, bool fl) {
+    if (!fl) return key ^ 0x80000000u;
+    return (key & 0x80000000u) ? (key & 0x7fffffffu) : ~key;
+}
+
+// Leaf-order position where node j of level l starts: floor(j n / 2^l).
+// Exact in 64 bits: n < 2^31 and j <= 2^32 (levels <= 31).
+__host__ __device__ inline int64_t node_start(int64_t n, int l, int64_t j) {
+    return (int64_t)(((uint64_t)j * (uint64_t)n) >> l);
+}
+
+__host__ inline int tree_levels(int64_t n, int leaf) {
+    int L = 0;
+    while (((n + ((int64_t)1 << L) - 1) >> L) > leaf) L++;
+    return L;
+}
+
+// Device view of a static kd-tree (what the search kernels read).
+struct TreeView {
+    int64_t n;
+    int d, L;
+    const uint32_t* pts;    // [d][n] coordinates in leaf order (SoA planes)
+    const int32_t* pidx;    // [n] input row of each leaf-order point
+    const uint32_t* split;  // [2^L] split coordinate of heap node h (h >= 1)
+    const uint32_t* bbox;   // [2^L][2d] per leaf: min[d], max[d] coordinates
+};
+
+inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
+
+}  // namespace pg
+
+// Handle layout (host side).
+struct pg_tree {
+    int64_t n = 0;
+    int d = 0, leaf = 0, L = 0, dtype = 0;
+    hipStream_t stream = nullptr;
+    uint32_t* pts = nullptr;
+    int32_t* pidx = nullptr;
+    uint32_t* split = nullptr;
+    uint32_t* bbox = nullptr;
+    pg::TreeView view() const {
+        return pg::TreeView{n, d, L, pts, pidx, split, bbox};
+    }
+};

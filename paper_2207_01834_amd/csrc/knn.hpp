@@ -1,0 +1,108 @@
+// k-NN search over static kd-trees: device-side pieces shared by the static,
+// BDL and batched searches, and the host entry points of knn.hip.
+#pragma once
+
+#include <float.h>
+
+#include "common.hpp"
+
+namespace pg {
+
+template <typename T> struct Metric;
+
+// int32 coordinates: exact int64 squared distances (|diff| < 2^30).
+template <> struct Metric<int32_t> {
+    using D = int64_t;
+    static __device__ __host__ inline D inf() { return INT64_MAX; }
+    static __device__ inline int32_t load(uint32_t b) { return (int32_t)b; }
+    static __device__ inline D sq(int32_t a, int32_t b) {
+        const int32_t t = a - b;
+        return (int64_t)t * (int64_t)t;
+    }
+    static __device__ inline D acc(D s, int32_t a, int32_t b) { return s + sq(a, b); }
+    // distance from a to the interval [lo, hi] along one axis, squared, added to s
+    static __device__ inline D acc_gap(D s, int32_t a, int32_t lo, int32_t hi) {
+        const int32_t g = a < lo ? lo - a : (a > hi ? a - hi : 0);
+        return s + (int64_t)g * (int64_t)g;
+    }
+};
+
+// float32 coordinates: float32 squared distances accumulated with fused
+// multiply-adds in dimension order.  The plane and box bounds use the same
+// operations on smaller-or-equal magnitudes, and rounding is monotone, so a
+// bound never exceeds the computed distance of a point it covers.
+template <> struct Metric<float> {
+    using D = float;
+    static __device__ __host__ inline D inf() { return __builtin_huge_valf(); }
+    static __device__ inline float load(uint32_t b) { return __uint_as_float(b); }
+    static __device__ inline D sq(float a, float b) {
+        const float t = a - b;
+        return t * t;
+    }
+    static __device__ inline D acc(D s, float a, float b) {
+        const float t = a - b;
+        return __builtin_fmaf(t, t, s);
+    }
+    static __device__ inline D acc_gap(D s, float a, float lo, float hi) {
+        const float g = a < lo ? lo - a : (a > hi ? a - hi : 0.0f);
+        return __builtin_fmaf(g, g, s);
+    }
+};
+
+// Sorted list of the k best (distance, id) keys held in registers.  KT is a
+// compile-time capacity >= k; slots >= k are never touched (uniform guards).
+template <typename DT, typename IT, int KT>
+struct KList {
+    DT d[KT];
+    IT id[KT];
+    DT kd;   // distance of slot k-1 (the pruning radius, squared)
+    IT kid;  // id of slot k-1
+
+    __device__ inline void init(int k, DT inf, IT none) {
+#pragma unroll
+        for (int s = 0; s < KT; s++) {
+            d[s] = inf;
+            id[s] = none;
+        }
+        kd = inf;
+        kid = none;
+        (void)k;
+    }
+    __device__ static inline bool less(DT a, IT ai, DT b, IT bi) {
+        return a < b || (a == b && ai < bi);
+    }
+    // True when (dd, ii) belongs in the list.
+    __device__ inline bool admits(DT dd, IT ii) const { return less(dd, ii, kd, kid); }
+    // Inserts (dd, ii); requires admits(dd, ii).
+    // Slot s receives the old slot s-1 when the new key sorts before it, the
+    // new key when it sorts before the old slot s but not before slot s-1,
+    // and keeps its key otherwise.
+    __device__ inline void insert(DT dd, IT ii, int k) {
+        bool before_cur = true;  // new key sorts before the old key of slot s
+#pragma unroll
+        for (int s = KT - 1; s >= 0; --s) {
+            if (s < k) {
+                const int p = s > 0 ? s - 1 : 0;
+                const bool before_prev = s > 0 && less(dd, ii, d[p], id[p]);
+                const DT nd = before_prev ? d[p] : (before_cur ? dd : d[s]);
+                const IT ni = before_prev ? id[p] : (before_cur ? ii : id[s]);
+                d[s] = nd;
+                id[s] = ni;
+                if (s == k - 1) {
+                    kd = nd;
+                    kid = ni;
+                }
+                before_cur = before_prev;
+            }
+        }
+    }
+};
+
+// Host entry points.
+pg_status knn_static(const pg_tree* t, const void* queries, int64_t m, int k, bool all_points,
+                     int32_t* out_idx, void* out_dist, hipStream_t s);
+
+// Validates query coordinates (range / finite); synchronises.
+pg_status check_queries(const void* q, int64_t m, int d, bool fl, hipStream_t s);
+
+}  // namespace pg

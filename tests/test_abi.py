@@ -1,0 +1,74 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function include/pargeo_hip.h declares, and rejects bad arguments
+before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pargeo_hip.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pg_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2207_01834_amd import _binding
+    if not os.path.exists(_binding.SO):
+        pytest.fail("libpargeo_hip.so is not built (run __graft_entry__.build())")
+    return _binding.lib()
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("pg_kdtree_build", "pg_knn", "pg_knn_all", "pg_tree_free", "pg_last_error"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(L):
+    missing = [n for n in declared_functions() if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_every_declared_symbol():
+    from paper_2207_01834_amd import _binding
+    assert set(declared_functions()) <= set(_binding.SIGNATURES)
+
+
+def _err(L):
+    return L.pg_last_error().decode()
+
+
+def test_build_argument_errors(L):
+    out = ctypes.c_void_p()
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+    cases = [
+        (fake, 10, 0, 16, 0, "d must be"),
+        (fake, 10, 9, 16, 0, "d must be"),
+        (fake, 10, 3, 0, 0, "leaf must be"),
+        (fake, 10, 3, 65, 0, "leaf must be"),
+        (fake, -1, 3, 16, 0, "n must be"),
+        (fake, 1 << 31, 3, 16, 0, "n must be"),
+        (fake, 10, 3, 16, 7, "bad dtype"),
+        (None, 10, 3, 16, 0, "points is NULL"),
+    ]
+    for pts, n, d, leaf, dt, msg in cases:
+        st = L.pg_kdtree_build(pts, n, d, leaf, dt, None, ctypes.byref(out))
+        assert st == 1, (n, d, leaf, dt)
+        assert msg in _err(L)
+    assert L.pg_kdtree_build(fake, 10, 3, 16, 0, None, None) == 1
+
+
+def test_knn_argument_errors(L):
+    assert L.pg_knn(None, None, 1, 1, None, None, None) == 1
+    assert "tree is NULL" in _err(L)
+    assert L.pg_knn_all(None, 3, None, None, None) == 1
+    assert L.pg_tree_info(None, None, None, None, None, None) == 1
+    assert L.pg_tree_export(None, None, None, None) == 1
+    L.pg_tree_free(None)  # no-op
