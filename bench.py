@@ -68,6 +68,26 @@ def measured_traffic(dtype):
     return rec.get("hbm_bytes_per_launch")
 
 
+def copy_probe(torch, dev, mib):
+    """Plain device-to-device copy of `mib` MiB: the achievable HBM rate in
+    this run, and a kernel of known traffic for scaling counter readings."""
+    if mib <= 0:
+        return None
+    n = mib * (1 << 20) // 4
+    a = torch.empty(n, dtype=torch.int32, device=dev).fill_(1)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 5
+    del a, b
+    return 2.0 * mib * (1 << 20) / (ms * 1e-3) / 1e9
+
+
 def cpu_baseline(pts, sample):
     import numpy as np
 
@@ -100,6 +120,8 @@ def main():
     ap.add_argument("--dtype", choices=["int", "float"], default="int")
     ap.add_argument("--cpu-sample", type=int, default=100_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=1024,
+                    help="size of the device copy that measures achievable HBM bandwidth (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -138,6 +160,8 @@ def main():
         t = step()
         del t
     torch.cuda.synchronize()
+
+    copy_gbs = copy_probe(torch, dev, args.copy_probe_mib)
 
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
     torch.cuda.synchronize()
@@ -180,6 +204,7 @@ def main():
         "build_mpts_s": N / (build_ms * 1e-3) / 1e6,
         "knn_qps": N / (knn_ms * 1e-3),
         "build_ms": build_ms,
+        "hbm_copy_gbs": copy_gbs,
         "knn_ms": knn_ms,
         "roofline": {
             "bound": "hbm",
