@@ -108,6 +108,59 @@ pg_status pg_tree_export(const pg_tree* t, void* splits_host, int32_t* perm_host
 /* Releases the tree (stream-ordered on the stream it was built on). */
 void pg_tree_free(pg_tree* t);
 
+/* ---------------------------------------------------------------------- */
+/* BDL-tree (batch-dynamic kd-tree, Section 5; Appendix C)                 */
+/* ---------------------------------------------------------------------- */
+/* A buffer tree of fewer than X points plus static kd-trees i = 0, 1, ...
+ * of capacity X * 2^i (the logarithmic method).  Every point carries an
+ * int64 id: the value of a global insertion counter (0, 1, 2, ... in batch
+ * order).  Readings where the paper is silent: bit i of F is set iff static
+ * tree i is non-empty; F_new = F + floor(|P|/X); a destroyed tree moves whole
+ * into the smallest new tree above it; tree-bound points fill new trees in
+ * ascending order; a tree is rebuilt when fewer than X 2^i / 2 of its points
+ * are live (the buffer is exempt).
+ *
+ * Creates an empty BDL-tree (host only; no device work).
+ *   d : 1..8   dtype : PG_INT32 / PG_FLOAT32   leaf : 1..64
+ *   buffer_X : X in [1, 2^31) */
+pg_status pg_bdl_create(int32_t d, int32_t dtype, int32_t leaf, int64_t buffer_X, pg_bdl** out);
+
+/* Batch insertion (Section 5 "Parallel Batch Insertion"; Algorithm 3).
+ *   points   : [m][d] device, the tree's dtype; copied
+ *   first_id : (host, may be NULL) id of points[0]; points[r] gets first_id+r
+ * Synchronises (range check, tree builds).  PG_ERR_RANGE leaves the tree
+ * unchanged; PG_ERR_UNSUPPORTED when a tree would exceed 2^31 points. */
+pg_status pg_bdl_insert(pg_bdl* b, const void* points, int64_t m, void* stream,
+                        int64_t* first_id);
+
+/* Batch deletion (Algorithms 2 and 4): every live point whose coordinates
+ * equal one of the m given points is removed (absent points are no-ops);
+ * static trees left below half capacity are gathered and reinserted.
+ *   n_erased : (host, may be NULL) number of points removed
+ * Synchronises. */
+pg_status pg_bdl_erase(pg_bdl* b, const void* points, int64_t m, void* stream,
+                       int64_t* n_erased);
+
+/* Data-parallel k-NN over the live points of all trees (Section 5
+ * "Data-Parallel k-NN": one k-NN buffer per query carried across the
+ * trees).
+ *   out_id   : [m][k] int64 ids (-1 = none)
+ *   out_dist : [m][k] int64 / float32 squared distances
+ * Synchronises (query range check). */
+pg_status pg_bdl_knn(const pg_bdl* b, const void* queries, int64_t m, int32_t k,
+                     int64_t* out_id, void* out_dist, void* stream);
+
+/* Number of live points (host; -1 for a NULL handle). */
+int64_t pg_bdl_size(const pg_bdl* b);
+
+/* Host-side state: F (bit i = static tree i non-empty), live buffer points,
+ * live points of static trees 0..max_trees-1 (any output may be NULL). */
+pg_status pg_bdl_stats(const pg_bdl* b, int64_t* tree_mask, int64_t* buffer_count,
+                       int64_t* live_counts, int32_t max_trees);
+
+/* Releases every tree (stream-ordered on the streams they were built on). */
+void pg_bdl_free(pg_bdl* b);
+
 #ifdef __cplusplus
 }
 #endif

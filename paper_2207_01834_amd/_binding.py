@@ -46,6 +46,13 @@ SIGNATURES = {
     "pg_tree_info": (i32, [vp, P64, P32, P32, P32, P32]),
     "pg_tree_export": (i32, [vp, vp, vp, vp]),
     "pg_tree_free": (None, [vp]),
+    "pg_bdl_create": (i32, [i32, i32, i32, i64, ctypes.POINTER(vp)]),
+    "pg_bdl_insert": (i32, [vp, vp, i64, vp, P64]),
+    "pg_bdl_erase": (i32, [vp, vp, i64, vp, P64]),
+    "pg_bdl_knn": (i32, [vp, vp, i64, i32, vp, vp, vp]),
+    "pg_bdl_size": (i64, [vp]),
+    "pg_bdl_stats": (i32, [vp, P64, P64, P64, i32]),
+    "pg_bdl_free": (None, [vp]),
 }
 
 
@@ -159,3 +166,66 @@ def kdtree_build(points: torch.Tensor, leaf: int = 16) -> KdTree:
     check(lib().pg_kdtree_build(ctypes.c_void_p(p.data_ptr()), p.shape[0], p.shape[1], leaf, code,
                                 stream_ptr(p.device), ctypes.byref(h)))
     return KdTree(h, code, p.device)
+
+
+class BDLTree:
+    """Batch-dynamic kd-tree (Section 5): insert / erase batches, k-NN over the
+    live points.  Ids are a global insertion counter."""
+
+    def __init__(self, d: int, dtype=torch.int32, leaf: int = 16, X: int = 1 << 14,
+                 device="cuda"):
+        self.d, self.leaf, self.X = d, leaf, X
+        self.dtype = dtype
+        self.code = PG_INT32 if dtype == torch.int32 else PG_FLOAT32
+        self.device = torch.device(device)
+        h = ctypes.c_void_p()
+        check(lib().pg_bdl_create(d, self.code, leaf, X, ctypes.byref(h)))
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.pg_bdl_free(h)
+            self._h = None
+
+    def _rows(self, pts):
+        p = _points(pts, "points")
+        if p.shape[1] != self.d or _dtype_code(p) != self.code:
+            raise TypeError("points must be [m][d] of the tree's dtype")
+        return p
+
+    def insert(self, pts) -> int:
+        p = self._rows(pts)
+        first = ctypes.c_int64()
+        check(lib().pg_bdl_insert(self._h, ctypes.c_void_p(p.data_ptr()), p.shape[0],
+                                  stream_ptr(p.device), ctypes.byref(first)))
+        return first.value
+
+    def erase(self, pts) -> int:
+        p = self._rows(pts)
+        cnt = ctypes.c_int64()
+        check(lib().pg_bdl_erase(self._h, ctypes.c_void_p(p.data_ptr()), p.shape[0],
+                                 stream_ptr(p.device), ctypes.byref(cnt)))
+        return cnt.value
+
+    def knn(self, queries, k: int, out=None):
+        q = self._rows(queries)
+        m = q.shape[0]
+        if out is None:
+            ids = torch.empty((m, k), dtype=torch.int64, device=q.device)
+            dist = torch.empty((m, k), dtype=_dist_dtype(self.code), device=q.device)
+        else:
+            ids, dist = out
+        check(lib().pg_bdl_knn(self._h, ctypes.c_void_p(q.data_ptr()), m, k,
+                               ctypes.c_void_p(ids.data_ptr()), ctypes.c_void_p(dist.data_ptr()),
+                               stream_ptr(q.device)))
+        return ids, dist
+
+    def size(self) -> int:
+        return lib().pg_bdl_size(self._h)
+
+    def stats(self, max_trees: int = 64):
+        F, b = ctypes.c_int64(), ctypes.c_int64()
+        live = (ctypes.c_int64 * max_trees)()
+        check(lib().pg_bdl_stats(self._h, ctypes.byref(F), ctypes.byref(b), live, max_trees))
+        return F.value, b.value, list(live)

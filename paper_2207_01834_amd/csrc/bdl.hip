@@ -1,0 +1,592 @@
+// BDL-tree: the batch-dynamic kd-tree of Section 5 (logarithmic method:
+// a buffer tree of fewer than X points plus static trees i of capacity X 2^i),
+// with batch insertion (Algorithm 3), batch deletion (Algorithms 2 and 4) and
+// data-parallel k-NN over all trees with one k-list per query.
+//
+// GPU design:
+//   * every tree (and the buffer) is an ordinary static tree (build.hip) plus
+//     int64 point ids in leaf order and a liveness bitmask (tombstones);
+//   * insert plans on the host from counts it already knows (no device
+//     round-trip): F, buffer size, floor(|P|/X); gathers the live points of
+//     destroyed trees in their staging order (scatter of liveness flags to
+//     staging positions, prefix sum, gather), appends the tree-bound slice of
+//     the batch, and builds each new tree;
+//   * erase runs one lane per (erase point, tree): a stack-free walk that
+//     enters both children where the coordinate equals the split, and clears
+//     the liveness bit of every live point with equal coordinates (atomic AND,
+//     so duplicates count once); the per-tree counts come back in one read;
+//   * k-NN walks the trees largest first with one register k-list per lane,
+//     skipping tombstones.
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "build.hpp"
+#include "knn.hpp"
+#include "scan.hpp"
+#include "search.hpp"
+#include "wave.hpp"
+
+namespace pg {
+
+constexpr int kMaxTrees = 31;        // static trees 0..30
+constexpr int kSlots = kMaxTrees + 1;  // + the buffer tree
+
+struct BdlTree {
+    pg_tree* t = nullptr;
+    int64_t* ids = nullptr;     // [n] ids in leaf order
+    uint32_t* alive = nullptr;  // [(n+31)/32] liveness bits
+    int64_t live = 0;
+    int64_t n() const { return t ? t->n : 0; }
+};
+
+struct ForestSlot {
+    TreeView tv;
+    const int64_t* ids;
+    uint32_t* alive;
+};
+
+struct Forest {
+    ForestSlot s[kSlots];
+    int count;
+};
+
+namespace {
+
+constexpr int kNT = 256;
+
+struct BdlIds {
+    const int64_t* ids;
+    const uint32_t* alive;
+    __device__ inline int64_t id(int64_t i) const { return ids[i]; }
+    __device__ inline bool live(int64_t i) const { return (alive[i >> 5] >> (i & 31)) & 1u; }
+};
+
+// flags[pidx[i]] = liveness of leaf-order point i (staging order).
+__global__ void stage_flags_kernel(const int32_t* __restrict__ pidx, const uint32_t* __restrict__ alive,
+                                   int64_t n, uint32_t* __restrict__ flags) {
+    const int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x;
+    if (i < n) flags[pidx[i]] = (alive[i >> 5] >> (i & 31)) & 1u;
+}
+
+// Appends the live points of a tree in staging order: point i goes to row
+// off + rank[pidx[i]] (rank == NULL: every point is live, rank = pidx).
+__global__ void gather_live_kernel(TreeView tv, const int64_t* __restrict__ ids,
+                                   const uint32_t* __restrict__ alive,
+                                   const uint32_t* __restrict__ rank, int d,
+                                   uint32_t* __restrict__ rows, int64_t* __restrict__ out_ids,
+                                   int64_t off) {
+    const int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x;
+    if (i >= tv.n) return;
+    if (!((alive[i >> 5] >> (i & 31)) & 1u)) return;
+    const int64_t st = tv.pidx[i];
+    const int64_t r = off + (rank ? (int64_t)rank[st] : st);
+    for (int c = 0; c < d; c++) rows[r * d + c] = tv.pts[(int64_t)c * tv.n + i];
+    out_ids[r] = ids[i];
+}
+
+__global__ void iota64_kernel(int64_t* __restrict__ out, int64_t count, int64_t first) {
+    const int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x;
+    if (i < count) out[i] = first + i;
+}
+
+__global__ void leaf_ids_kernel(const int32_t* __restrict__ pidx, const int64_t* __restrict__ staged,
+                                int64_t n, int64_t* __restrict__ ids) {
+    const int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x;
+    if (i < n) ids[i] = staged[pidx[i]];
+}
+
+// Erase: lane = erase point, blockIdx.y = tree slot.  Walks every node whose
+// cell can hold the exact coordinates (both children where the coordinate
+// equals the split) and clears live points with equal coordinates.
+template <typename T, int MD>
+__global__ void __launch_bounds__(kNT)
+erase_kernel(Forest f, const uint32_t* __restrict__ pts, int64_t m, int d,
+             unsigned long long* __restrict__ erased) {
+    using M = Metric<T>;
+    const int64_t qi = (int64_t)blockIdx.x * kNT + threadIdx.x;
+    const int slot = blockIdx.y;
+    if (qi >= m) return;
+    const ForestSlot& S = f.s[slot];
+    const TreeView& tv = S.tv;
+    if (tv.n == 0) return;
+    T q[MD];
+#pragma unroll
+    for (int c = 0; c < MD; c++) q[c] = M::load(c < d ? pts[qi * d + c] : 0u);
+    const uint32_t first_leaf = 1u << tv.L;
+    uint32_t cur = 1, prev = 0;
+    int dim = 0;
+    uint32_t hits = 0;
+    while (cur != 0) {
+        while (cur != 0 && cur < first_leaf) {
+            const T s = M::load(tv.split[cur]);
+            const T qd = pick<MD>(q, dim);
+            const uint32_t nearc = 2u * cur + (qd >= s ? 1u : 0u);
+            uint32_t next;
+            if (prev == (cur >> 1)) next = nearc;
+            else if (prev == nearc && qd == s) next = nearc ^ 1u;
+            else next = cur >> 1;
+            if (next > cur) dim = (dim + 1 == d) ? 0 : dim + 1;
+            else dim = (dim == 0) ? d - 1 : dim - 1;
+            prev = cur;
+            cur = next;
+        }
+        if (cur == 0) break;
+        const uint32_t leaf = cur - first_leaf;
+        const uint32_t* bb = tv.bbox + (size_t)leaf * 2 * d;
+        bool inside = true;
+#pragma unroll
+        for (int c = 0; c < MD; c++)
+            if (c < d) inside = inside && !(q[c] < M::load(bb[c])) && !(q[c] > M::load(bb[d + c]));
+        if (inside) {
+            const int64_t lo = node_start(tv.n, tv.L, leaf), hi = node_start(tv.n, tv.L, leaf + 1);
+            for (int64_t i = lo; i < hi; i++) {
+                bool eq = true;
+#pragma unroll
+                for (int c = 0; c < MD; c++)
+                    if (c < d) eq = eq && (M::load(tv.pts[(int64_t)c * tv.n + i]) == q[c]);
+                if (eq) {
+                    const uint32_t bit = 1u << (i & 31);
+                    const uint32_t old = atomicAnd(&S.alive[i >> 5], ~bit);
+                    if (old & bit) hits++;
+                }
+            }
+        }
+        prev = cur;
+        cur >>= 1;
+        dim = (dim == 0) ? d - 1 : dim - 1;
+    }
+    if (hits) atomicAdd(&erased[slot], (unsigned long long)hits);
+}
+
+template <typename T, int MD, int KT>
+__global__ void __launch_bounds__(kNT)
+bdl_knn_kernel(Forest f, const uint32_t* __restrict__ queries, int64_t m, int d, int k,
+               int64_t* __restrict__ out_id, typename Metric<T>::D* __restrict__ out_dist) {
+    using M = Metric<T>;
+    const int64_t qi = (int64_t)blockIdx.x * kNT + threadIdx.x;
+    if (qi >= m) return;
+    T q[MD];
+#pragma unroll
+    for (int c = 0; c < MD; c++) q[c] = M::load(c < d ? queries[qi * d + c] : 0u);
+    KList<typename M::D, int64_t, KT> kl;
+    kl.init(k, M::inf(), INT64_MAX);
+    for (int t = 0; t < f.count; t++)
+        kd_search<T, MD, KT, int64_t>(f.s[t].tv, BdlIds{f.s[t].ids, f.s[t].alive}, q, d, kl, k);
+#pragma unroll
+    for (int s = 0; s < KT; s++) {
+        if (s < k) {
+            out_id[qi * k + s] = kl.id[s] == INT64_MAX ? -1 : kl.id[s];
+            out_dist[qi * k + s] = kl.d[s];
+        }
+    }
+}
+
+template <typename T, int MD>
+pg_status launch_erase(const Forest& f, const void* pts, int64_t m, int d,
+                       unsigned long long* erased, hipStream_t s) {
+    hipLaunchKernelGGL((erase_kernel<T, MD>), dim3(cdiv(m, kNT), f.count), dim3(kNT), 0, s, f,
+                       (const uint32_t*)pts, m, d, erased);
+    PG_LAUNCH_CHECK();
+    return PG_OK;
+}
+
+template <typename T>
+pg_status erase_d(const Forest& f, const void* pts, int64_t m, int d, unsigned long long* e,
+                  hipStream_t s) {
+    switch (d) {
+        case 2: return launch_erase<T, 2>(f, pts, m, d, e, s);
+        case 3: return launch_erase<T, 3>(f, pts, m, d, e, s);
+        case 5: return launch_erase<T, 5>(f, pts, m, d, e, s);
+        default: return launch_erase<T, 8>(f, pts, m, d, e, s);
+    }
+}
+
+template <typename T, int MD, int KT>
+pg_status launch_bdl_knn(const Forest& f, const void* q, int64_t m, int d, int k, int64_t* oi,
+                         void* od, hipStream_t s) {
+    using DT = typename Metric<T>::D;
+    hipLaunchKernelGGL((bdl_knn_kernel<T, MD, KT>), dim3(cdiv(m, kNT)), dim3(kNT), 0, s, f,
+                       (const uint32_t*)q, m, d, k, oi, (DT*)od);
+    PG_LAUNCH_CHECK();
+    return PG_OK;
+}
+
+template <typename T, int MD>
+pg_status bdl_knn_k(const Forest& f, const void* q, int64_t m, int d, int k, int64_t* oi,
+                    void* od, hipStream_t s) {
+    if (k <= 2) return launch_bdl_knn<T, MD, 2>(f, q, m, d, k, oi, od, s);
+    if (k <= 4) return launch_bdl_knn<T, MD, 4>(f, q, m, d, k, oi, od, s);
+    if (k <= 8) return launch_bdl_knn<T, MD, 8>(f, q, m, d, k, oi, od, s);
+    if (k <= 16) return launch_bdl_knn<T, MD, 16>(f, q, m, d, k, oi, od, s);
+    if (k <= 32) return launch_bdl_knn<T, MD, 32>(f, q, m, d, k, oi, od, s);
+    return launch_bdl_knn<T, MD, 64>(f, q, m, d, k, oi, od, s);
+}
+
+template <typename T>
+pg_status bdl_knn_d(const Forest& f, const void* q, int64_t m, int d, int k, int64_t* oi,
+                    void* od, hipStream_t s) {
+    switch (d) {
+        case 2: return bdl_knn_k<T, 2>(f, q, m, d, k, oi, od, s);
+        case 3: return bdl_knn_k<T, 3>(f, q, m, d, k, oi, od, s);
+        case 5: return bdl_knn_k<T, 5>(f, q, m, d, k, oi, od, s);
+        default: return bdl_knn_k<T, 8>(f, q, m, d, k, oi, od, s);
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Host side.
+// ---------------------------------------------------------------------------
+struct Bdl {
+    int d = 0, leaf = 0, dtype = 0;
+    int64_t X = 0;
+    BdlTree tree[kMaxTrees];
+    BdlTree buf;
+    int64_t next_id = 0;
+
+    uint64_t F() const {
+        uint64_t f = 0;
+        for (int i = 0; i < kMaxTrees; i++)
+            if (tree[i].t) f |= 1ull << i;
+        return f;
+    }
+};
+
+static void free_tree(BdlTree& T) {
+    if (T.t) {
+        hipStream_t s = T.t->stream;
+        dfree(T.ids, s);
+        dfree(T.alive, s);
+        pg_tree_free(T.t);
+    }
+    T = BdlTree();
+}
+
+// A contiguous set of staged points (rows [count][d] + ids), device memory.
+struct Staged {
+    uint32_t* rows = nullptr;
+    int64_t* ids = nullptr;
+    int64_t count = 0;
+};
+
+static pg_status append_live(const Bdl& B, const BdlTree& T, Staged& dst, int64_t off,
+                             hipStream_t s) {
+    if (!T.t || T.live == 0) return PG_OK;
+    const int64_t n = T.t->n;
+    DevBuf flags(s);
+    const uint32_t* rank = nullptr;
+    if (T.live != n) {
+        PG_TRY(flags.alloc(sizeof(uint32_t) * n));
+        hipLaunchKernelGGL(stage_flags_kernel, dim3(cdiv(n, kNT)), dim3(kNT), 0, s, T.t->pidx,
+                           T.alive, n, flags.as<uint32_t>());
+        PG_LAUNCH_CHECK();
+        PG_TRY(exclusive_scan_u32(flags.as<uint32_t>(), flags.as<uint32_t>(), n, nullptr, s));
+        rank = flags.as<uint32_t>();
+    }
+    hipLaunchKernelGGL(gather_live_kernel, dim3(cdiv(n, kNT)), dim3(kNT), 0, s, T.t->view(),
+                       T.ids, T.alive, rank, B.d, dst.rows, dst.ids, off);
+    PG_LAUNCH_CHECK();
+    return PG_OK;
+}
+
+static pg_status copy_slice(const Bdl& B, const Staged& src, int64_t from, int64_t count,
+                            Staged& dst, int64_t off, hipStream_t s) {
+    if (count <= 0) return PG_OK;
+    PG_HIP(hipMemcpyAsync(dst.rows + off * B.d, src.rows + from * B.d,
+                          sizeof(uint32_t) * B.d * count, hipMemcpyDeviceToDevice, s));
+    PG_HIP(hipMemcpyAsync(dst.ids + off, src.ids + from, sizeof(int64_t) * count,
+                          hipMemcpyDeviceToDevice, s));
+    return PG_OK;
+}
+
+// Builds a BDL tree over staged points.
+static pg_status build_bdl_tree(const Bdl& B, const Staged& S, hipStream_t s, BdlTree& out) {
+    pg_tree* t = new (std::nothrow) pg_tree();
+    if (!t) return fail(PG_ERR_NOMEM, "host allocation failed");
+    pg_status st = build_tree(S.rows, S.count, B.d, B.leaf, B.dtype, s, t);
+    if (st != PG_OK) {
+        pg_tree_free(t);
+        return st;
+    }
+    out.t = t;
+    out.live = S.count;
+    const int64_t n = S.count;
+    const int64_t words = (n + 31) / 32;
+    PG_TRY(dalloc(&out.ids, n > 0 ? n : 1, s));
+    PG_TRY(dalloc(&out.alive, words > 0 ? words : 1, s));
+    if (n > 0) {
+        hipLaunchKernelGGL(leaf_ids_kernel, dim3(cdiv(n, kNT)), dim3(kNT), 0, s, t->pidx, S.ids, n,
+                           out.ids);
+        PG_LAUNCH_CHECK();
+        PG_HIP(hipMemsetAsync(out.alive, 0xff, sizeof(uint32_t) * words, s));
+    }
+    return PG_OK;
+}
+
+// Algorithm 3 on a staged batch (the batch's rows/ids stay the caller's).
+static pg_status insert_core(Bdl& B, const Staged& S, hipStream_t s) {
+    const int64_t X = B.X, m = S.count;
+    const int64_t b = B.buf.live;
+    const int64_t r = m % X;
+    int64_t A = m / X;
+    const bool overflow = b + r >= X;
+    const int64_t n_fresh = overflow ? A * X + (X - b) : A * X;  // batch points bound for trees
+    if (overflow) A++;
+    const uint64_t F = B.F();
+    const uint64_t Fnew = F + (uint64_t)A;
+    const uint64_t nw = Fnew & ~F, destroyed = F & ~Fnew;
+    for (int j = 0; j < 64; j++)
+        if ((nw >> j) & 1ull) {
+            if (j >= kMaxTrees || (X << j) >= ((int64_t)1 << 31))
+                return fail(PG_ERR_UNSUPPORTED, "BDL-tree capacity exceeded (tree index or size)");
+        }
+
+    // Tree-bound points: the old buffer's live points first (on overflow), then
+    // the first n_fresh batch points.
+    Staged TB;
+    DevBuf tb_rows(s), tb_ids(s);
+    const int64_t tb_count = (overflow ? b : 0) + n_fresh;
+    if (overflow && b > 0) {
+        PG_TRY(tb_rows.alloc(sizeof(uint32_t) * B.d * tb_count));
+        PG_TRY(tb_ids.alloc(sizeof(int64_t) * tb_count));
+        TB.rows = tb_rows.as<uint32_t>();
+        TB.ids = tb_ids.as<int64_t>();
+        TB.count = tb_count;
+        PG_TRY(append_live(B, B.buf, TB, 0, s));
+        PG_TRY(copy_slice(B, S, 0, n_fresh, TB, b, s));
+    } else {
+        TB.rows = S.rows;
+        TB.ids = S.ids;
+        TB.count = n_fresh;
+    }
+
+    // New trees, ascending: destroyed trees assigned whole, then quota points.
+    BdlTree built[kMaxTrees];
+    int64_t pos = 0;
+    for (int j = 0; j < kMaxTrees; j++) {
+        if (!((nw >> j) & 1ull)) continue;
+        int64_t assigned_cap = 0, assigned_live = 0;
+        std::vector<int> from;
+        for (int i = j - 1; i >= 0; i--) {
+            if ((nw >> i) & 1ull) break;  // a lower new tree takes the rest
+            if ((destroyed >> i) & 1ull) {
+                from.push_back(i);
+                assigned_cap += X << i;
+                assigned_live += B.tree[i].live;
+            }
+        }
+        std::sort(from.begin(), from.end());
+        const int64_t quota = (X << j) - assigned_cap;
+        Staged st;
+        DevBuf rows(s), ids(s);
+        st.count = assigned_live + quota;
+        PG_TRY(rows.alloc(sizeof(uint32_t) * B.d * (st.count > 0 ? st.count : 1)));
+        PG_TRY(ids.alloc(sizeof(int64_t) * (st.count > 0 ? st.count : 1)));
+        st.rows = rows.as<uint32_t>();
+        st.ids = ids.as<int64_t>();
+        int64_t off = 0;
+        for (int i : from) {
+            PG_TRY(append_live(B, B.tree[i], st, off, s));
+            off += B.tree[i].live;
+        }
+        PG_TRY(copy_slice(B, TB, pos, quota, st, off, s));
+        pos += quota;
+        PG_TRY(build_bdl_tree(B, st, s, built[j]));
+    }
+    if (pos != TB.count) return fail(PG_ERR_DEVICE, "BDL insert: internal count mismatch");
+
+    // New buffer: (no overflow) old live buffer points + the last r batch
+    // points; (overflow) the batch points after the tree-bound ones.
+    const int64_t keep_old = overflow ? 0 : b;
+    const int64_t from_batch = m - (overflow ? n_fresh : (m - r));
+    Staged nb;
+    DevBuf nb_rows(s), nb_ids(s);
+    nb.count = keep_old + from_batch;
+    const bool buffer_changes = overflow || from_batch > 0;
+    BdlTree newbuf;
+    if (buffer_changes) {
+        PG_TRY(nb_rows.alloc(sizeof(uint32_t) * B.d * (nb.count > 0 ? nb.count : 1)));
+        PG_TRY(nb_ids.alloc(sizeof(int64_t) * (nb.count > 0 ? nb.count : 1)));
+        nb.rows = nb_rows.as<uint32_t>();
+        nb.ids = nb_ids.as<int64_t>();
+        if (keep_old) PG_TRY(append_live(B, B.buf, nb, 0, s));
+        PG_TRY(copy_slice(B, S, m - from_batch, from_batch, nb, keep_old, s));
+        if (nb.count > 0) PG_TRY(build_bdl_tree(B, nb, s, newbuf));
+    }
+
+    for (int i = 0; i < kMaxTrees; i++)
+        if ((destroyed >> i) & 1ull) free_tree(B.tree[i]);
+    for (int j = 0; j < kMaxTrees; j++)
+        if ((nw >> j) & 1ull) B.tree[j] = built[j];
+    if (buffer_changes) {
+        free_tree(B.buf);
+        B.buf = newbuf;
+    }
+    return PG_OK;
+}
+
+static Forest make_forest(const Bdl& B) {
+    Forest f{};
+    f.count = 0;
+    for (int i = kMaxTrees - 1; i >= 0; i--)  // largest first
+        if (B.tree[i].t) f.s[f.count++] = ForestSlot{B.tree[i].t->view(), B.tree[i].ids, B.tree[i].alive};
+    if (B.buf.t) f.s[f.count++] = ForestSlot{B.buf.t->view(), B.buf.ids, B.buf.alive};
+    return f;
+}
+
+}  // namespace pg
+
+struct pg_bdl {
+    pg::Bdl b;
+};
+
+using namespace pg;
+
+extern "C" {
+
+pg_status pg_bdl_create(int32_t d, int32_t dtype, int32_t leaf, int64_t buffer_X, pg_bdl** out) {
+    if (!out) return fail(PG_ERR_INVALID, "pg_bdl_create: out is NULL");
+    if (d < 1 || d > 8) return fail(PG_ERR_INVALID, "pg_bdl_create: d must be in [1, 8]");
+    if (leaf < 1 || leaf > 64) return fail(PG_ERR_INVALID, "pg_bdl_create: leaf must be in [1, 64]");
+    if (dtype != PG_INT32 && dtype != PG_FLOAT32) return fail(PG_ERR_INVALID, "pg_bdl_create: bad dtype");
+    if (buffer_X < 1 || buffer_X >= ((int64_t)1 << 31))
+        return fail(PG_ERR_INVALID, "pg_bdl_create: buffer_X must be in [1, 2^31)");
+    pg_bdl* h = new (std::nothrow) pg_bdl();
+    if (!h) return fail(PG_ERR_NOMEM, "pg_bdl_create: host allocation failed");
+    h->b.d = d;
+    h->b.dtype = dtype;
+    h->b.leaf = leaf;
+    h->b.X = buffer_X;
+    *out = h;
+    return PG_OK;
+}
+
+pg_status pg_bdl_insert(pg_bdl* h, const void* points, int64_t m, void* stream, int64_t* first_id) {
+    if (!h) return fail(PG_ERR_INVALID, "pg_bdl_insert: handle is NULL");
+    if (m < 0 || m >= ((int64_t)1 << 31)) return fail(PG_ERR_INVALID, "pg_bdl_insert: m must be in [0, 2^31)");
+    if (m > 0 && !points) return fail(PG_ERR_INVALID, "pg_bdl_insert: points is NULL");
+    Bdl& B = h->b;
+    hipStream_t s = (hipStream_t)stream;
+    if (first_id) *first_id = B.next_id;
+    if (m == 0) return PG_OK;
+    PG_TRY(check_queries(points, m, B.d, B.dtype == PG_FLOAT32, s));
+    DevBuf ids(s);
+    PG_TRY(ids.alloc(sizeof(int64_t) * m));
+    hipLaunchKernelGGL(iota64_kernel, dim3(cdiv(m, kNT)), dim3(kNT), 0, s, ids.as<int64_t>(), m,
+                       B.next_id);
+    PG_LAUNCH_CHECK();
+    Staged S;
+    S.rows = (uint32_t*)points;
+    S.ids = ids.as<int64_t>();
+    S.count = m;
+    PG_TRY(insert_core(B, S, s));
+    B.next_id += m;
+    return PG_OK;
+}
+
+pg_status pg_bdl_erase(pg_bdl* h, const void* points, int64_t m, void* stream, int64_t* n_erased) {
+    if (!h) return fail(PG_ERR_INVALID, "pg_bdl_erase: handle is NULL");
+    if (m < 0 || m >= ((int64_t)1 << 31)) return fail(PG_ERR_INVALID, "pg_bdl_erase: m must be in [0, 2^31)");
+    if (m > 0 && !points) return fail(PG_ERR_INVALID, "pg_bdl_erase: points is NULL");
+    Bdl& B = h->b;
+    hipStream_t s = (hipStream_t)stream;
+    if (n_erased) *n_erased = 0;
+    if (m == 0) return PG_OK;
+    PG_TRY(check_queries(points, m, B.d, B.dtype == PG_FLOAT32, s));
+    Forest f = make_forest(B);
+    if (f.count == 0) return PG_OK;
+    // slot -> tree index (-1: buffer), same order as make_forest
+    int slot_tree[kSlots];
+    {
+        int c = 0;
+        for (int i = kMaxTrees - 1; i >= 0; i--)
+            if (B.tree[i].t) slot_tree[c++] = i;
+        if (B.buf.t) slot_tree[c++] = -1;
+    }
+    DevBuf cnt(s);
+    PG_TRY(cnt.alloc(sizeof(unsigned long long) * kSlots));
+    PG_HIP(hipMemsetAsync(cnt.p, 0, sizeof(unsigned long long) * kSlots, s));
+    unsigned long long* e = cnt.as<unsigned long long>();
+    if (B.dtype == PG_FLOAT32) PG_TRY(erase_d<float>(f, points, m, B.d, e, s));
+    else PG_TRY(erase_d<int32_t>(f, points, m, B.d, e, s));
+    unsigned long long host[kSlots];
+    PG_HIP(hipMemcpyAsync(host, e, sizeof(host), hipMemcpyDeviceToHost, s));
+    PG_HIP(hipStreamSynchronize(s));
+    int64_t total = 0;
+    for (int c = 0; c < f.count; c++) {
+        BdlTree& T = slot_tree[c] < 0 ? B.buf : B.tree[slot_tree[c]];
+        T.live -= (int64_t)host[c];
+        total += (int64_t)host[c];
+    }
+    if (n_erased) *n_erased = total;
+
+    // Trees below half capacity: gather their live points (ascending tree
+    // index, each in staging order) into R, clear them, reinsert R.
+    int64_t r_count = 0;
+    std::vector<int> dep;
+    for (int i = 0; i < kMaxTrees; i++)
+        if (B.tree[i].t && 2 * B.tree[i].live < (B.X << i)) {
+            dep.push_back(i);
+            r_count += B.tree[i].live;
+        }
+    if (dep.empty()) return PG_OK;
+    Staged R;
+    DevBuf rrows(s), rids(s);
+    PG_TRY(rrows.alloc(sizeof(uint32_t) * B.d * (r_count > 0 ? r_count : 1)));
+    PG_TRY(rids.alloc(sizeof(int64_t) * (r_count > 0 ? r_count : 1)));
+    R.rows = rrows.as<uint32_t>();
+    R.ids = rids.as<int64_t>();
+    R.count = r_count;
+    int64_t off = 0;
+    for (int i : dep) {
+        PG_TRY(append_live(B, B.tree[i], R, off, s));
+        off += B.tree[i].live;
+    }
+    for (int i : dep) free_tree(B.tree[i]);
+    if (r_count > 0) PG_TRY(insert_core(B, R, s));
+    return PG_OK;
+}
+
+pg_status pg_bdl_knn(const pg_bdl* h, const void* queries, int64_t m, int32_t k, int64_t* out_id,
+                     void* out_dist, void* stream) {
+    if (!h) return fail(PG_ERR_INVALID, "pg_bdl_knn: handle is NULL");
+    if (k < 1 || k > 64) return fail(PG_ERR_INVALID, "pg_bdl_knn: k must be in [1, 64]");
+    if (m < 0 || m >= ((int64_t)1 << 31)) return fail(PG_ERR_INVALID, "pg_bdl_knn: m must be in [0, 2^31)");
+    if (m > 0 && (!queries || !out_id || !out_dist)) return fail(PG_ERR_INVALID, "pg_bdl_knn: NULL pointer");
+    if (m == 0) return PG_OK;
+    const Bdl& B = h->b;
+    hipStream_t s = (hipStream_t)stream;
+    PG_TRY(check_queries(queries, m, B.d, B.dtype == PG_FLOAT32, s));
+    Forest f = make_forest(B);
+    if (B.dtype == PG_FLOAT32) return bdl_knn_d<float>(f, queries, m, B.d, k, out_id, out_dist, s);
+    return bdl_knn_d<int32_t>(f, queries, m, B.d, k, out_id, out_dist, s);
+}
+
+int64_t pg_bdl_size(const pg_bdl* h) {
+    if (!h) return -1;
+    int64_t tot = h->b.buf.live;
+    for (int i = 0; i < kMaxTrees; i++) tot += h->b.tree[i].live;
+    return tot;
+}
+
+pg_status pg_bdl_stats(const pg_bdl* h, int64_t* tree_mask, int64_t* buffer_count,
+                       int64_t* live_counts, int32_t max_trees) {
+    if (!h) return fail(PG_ERR_INVALID, "pg_bdl_stats: handle is NULL");
+    if (max_trees < 0) return fail(PG_ERR_INVALID, "pg_bdl_stats: max_trees < 0");
+    if (tree_mask) *tree_mask = (int64_t)h->b.F();
+    if (buffer_count) *buffer_count = h->b.buf.live;
+    if (live_counts)
+        for (int i = 0; i < max_trees; i++) live_counts[i] = i < kMaxTrees ? h->b.tree[i].live : 0;
+    return PG_OK;
+}
+
+void pg_bdl_free(pg_bdl* h) {
+    if (!h) return;
+    for (int i = 0; i < kMaxTrees; i++) free_tree(h->b.tree[i]);
+    free_tree(h->b.buf);
+    delete h;
+}
+
+}  // extern "C"

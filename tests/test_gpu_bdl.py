@@ -1,0 +1,192 @@
+"""GPU parity of the BDL-tree (Section 5, Algorithms 3 and 4) against the
+oracle's BDL model: per-step state (F, buffer count, live points per tree),
+erase counts, and k-NN over the live points (byte-identical for int32)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle.bdl_model import BDLModel
+from paper_2207_01834_amd import datagen
+from parity import assert_float_close, assert_int_equal, say
+
+pytestmark = pytest.mark.gpu
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "bdl_insert_example.json")
+
+
+@pytest.fixture(scope="module")
+def pg(dev):
+    import paper_2207_01834_amd._binding as b
+    b.lib()
+    return b
+
+
+def to_dev(a, dev):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def host(*ts):
+    import torch
+    torch.cuda.synchronize()
+    return [t.cpu().numpy() for t in ts]
+
+
+def same_state(G, M, tag=""):
+    gF, gb, glive = G.stats(40)
+    mF, mb, mlive = M.stats(40)
+    assert (gF, gb) == (mF, mb), f"{tag}: F/buffer gpu {(gF, gb)} model {(mF, mb)}"
+    assert glive == mlive, f"{tag}: live per tree gpu {glive} model {mlive}"
+    assert G.size() == M.size()
+
+
+def knn_check(pg, dev, G, M, q, k):
+    gi, gd = host(*G.knn(to_dev(q, dev), k))
+    pts, ids = M.live()
+    oi, od = oracle.knn_brute(pts, q, k, ids=ids, nthreads=8)
+    assert_int_equal(gi, gd, oi, od)
+
+
+def test_paper_insert_example(pg, dev):
+    import torch
+    gold = json.load(open(GOLD))
+    X = 8
+    g = np.random.default_rng(0)
+    G = pg.BDLTree(2, torch.int32, leaf=4, X=X, device=dev)
+    M = BDLModel(2, X)
+    size = lambda e: eval(e, {"X": X})
+    P = g.integers(0, 50, size=(size(gold["start"]["points"]), 2)).astype(np.int32)
+    assert G.insert(to_dev(P, dev)) == M.insert(P) == 0
+    same_state(G, M, "start")
+    assert G.stats()[:2] == (gold["start"]["F"], gold["start"]["buffer"])
+    for st in gold["steps"]:
+        P = g.integers(0, 50, size=(size(st["insert"]), 2)).astype(np.int32)
+        assert G.insert(to_dev(P, dev)) == M.insert(P)
+        same_state(G, M, st["insert"])
+        assert G.stats()[:2] == (st["F"], st["buffer"])
+        knn_check(pg, dev, G, M, g.integers(0, 50, size=(40, 2)).astype(np.int32), 5)
+
+
+def _run_sequence(pg, dev, d, X, steps, coord_hi, dtype, seed, k=7, leaf=8):
+    import torch
+    g = np.random.default_rng(seed)
+    G = pg.BDLTree(d, torch.int32 if dtype == np.int32 else torch.float32, leaf=leaf, X=X, device=dev)
+    M = BDLModel(d, X, dtype=dtype)
+
+    def draw(cnt):
+        if dtype == np.int32:
+            return g.integers(0, coord_hi, size=(cnt, d)).astype(np.int32)
+        return (np.floor(g.random((cnt, d)) * coord_hi) / coord_hi).astype(np.float32)
+
+    for step in range(steps):
+        op = step % 3
+        if op != 2:
+            P = draw(int(g.integers(0, 6 * X)))
+            say(f"step {step}: insert {len(P)}")
+            assert G.insert(to_dev(P, dev)) == M.insert(P)
+        else:
+            pts, _ = M.live()
+            cnt = int(g.integers(0, max(1, len(pts) // 2)))
+            E = pts[np.sort(g.choice(len(pts), size=min(cnt, len(pts)), replace=False))] if len(pts) else pts
+            E = np.concatenate([E, draw(5), E[:3]]) if len(E) else draw(5)  # absent + duplicates
+            say(f"step {step}: erase {len(E)}")
+            ne_g = G.erase(to_dev(E, dev))
+            ne_m = M.erase(E)
+            assert ne_g == ne_m, (ne_g, ne_m)
+        same_state(G, M, f"step {step}")
+        if M.size():
+            q = draw(60)
+            gi, gd = host(*G.knn(to_dev(q, dev), k))
+            pts, ids = M.live()
+            oi, od = oracle.knn_brute(pts, q, k, ids=ids, nthreads=8)
+            if dtype == np.int32:
+                assert_int_equal(gi, gd, oi, od)
+            else:
+                # map ids to rows of the live set for the distance recheck
+                pos = {int(t): r for r, t in enumerate(ids.tolist())}
+                gr = np.vectorize(lambda t: pos.get(int(t), -1))(gi)
+                orr = np.vectorize(lambda t: pos.get(int(t), -1))(oi)
+                assert_float_close(gr, gd, orr, od, pts, q)
+
+
+def test_random_sequence_int_duplicates(pg, dev):
+    _run_sequence(pg, dev, d=3, X=16, steps=30, coord_hi=10, dtype=np.int32, seed=1)
+
+
+def test_random_sequence_int_wide(pg, dev):
+    _run_sequence(pg, dev, d=2, X=64, steps=24, coord_hi=1 << 20, dtype=np.int32, seed=2, k=10)
+
+
+def test_random_sequence_float(pg, dev):
+    _run_sequence(pg, dev, d=3, X=32, steps=18, coord_hi=64, dtype=np.float32, seed=3)
+
+
+def test_random_sequence_d5_leaf1(pg, dev):
+    _run_sequence(pg, dev, d=5, X=4, steps=21, coord_hi=6, dtype=np.int32, seed=4, k=3, leaf=1)
+
+
+def test_cfg5_shaped_reduced(pg, dev):
+    """10% rounds as in the BDL experiments: 200k initial points, 3 rounds of
+    20k inserts, 20k erases of live points, 20k fresh queries (k = 10)."""
+    import torch
+    init, rounds = datagen.bdl_rounds(200_000, 3, 20_000, 20_000, 3, seed=5)
+    G = pg.BDLTree(3, torch.int32, leaf=16, X=1024, device=dev)
+    M = BDLModel(3, 1024)
+    G.insert(to_dev(init, dev))
+    M.insert(init)
+    same_state(G, M, "init")
+    for r, rd in enumerate(rounds):
+        say(f"round {r}")
+        assert G.insert(to_dev(rd["insert"], dev)) == M.insert(rd["insert"])
+        same_state(G, M, f"round {r} insert")
+        pts, _ = M.live()
+        E = datagen.choose_erase(pts, 20_000, rd["erase_seed"])
+        assert G.erase(to_dev(E, dev)) == M.erase(E)
+        same_state(G, M, f"round {r} erase")
+        q = rd["queries"]
+        gi, gd = host(*G.knn(to_dev(q, dev), 10))
+        pts, ids = M.live()
+        t = oracle.KdTree(pts, leaf=16)
+        oi, od, _ = t.knn(q, 10, ids=ids)
+        assert_int_equal(gi, gd, oi, od)
+
+
+def test_cfg5_full_size_sampled(pg, dev):
+    """The benchmarked batch-dynamic configuration: 10M initial points, rounds
+    of 1M inserts, 1M erases of live points, 1M queries (k = 10); 3 rounds,
+    invariants on every round, 400 sampled query rows against the definition
+    over the live set."""
+    import torch
+    init, rounds = datagen.bdl_rounds(10_000_000, 3, 1_000_000, 1_000_000, 3, seed=5)
+    X = 1 << 14
+    G = pg.BDLTree(3, torch.int32, leaf=16, X=X, device=dev)
+    say("cfg5: initial insert")
+    G.insert(to_dev(init, dev))
+    F, b, live = G.stats()
+    assert F == len(init) // X and b == len(init) % X
+    pts = init
+    ids = np.arange(len(init), dtype=np.int64)
+    nxt = len(init)
+    key = lambda a: a[:, 0].astype(np.int64) | (a[:, 1].astype(np.int64) << 20) | (a[:, 2].astype(np.int64) << 40)
+    for r, rd in enumerate(rounds):
+        say(f"cfg5 round {r}")
+        assert G.insert(to_dev(rd["insert"], dev)) == nxt
+        pts = np.concatenate([pts, rd["insert"]])
+        ids = np.concatenate([ids, np.arange(nxt, nxt + len(rd["insert"]), dtype=np.int64)])
+        nxt += len(rd["insert"])
+        E = datagen.choose_erase(pts, 1_000_000, rd["erase_seed"])
+        hit = np.isin(key(pts), key(E))
+        assert G.erase(to_dev(E, dev)) == int(hit.sum())
+        pts, ids = pts[~hit], ids[~hit]
+        F, b, live = G.stats()
+        assert G.size() == len(pts) and 0 <= b < X
+        for i in range(40):
+            if (F >> i) & 1:
+                assert 2 * live[i] >= (X << i) and live[i] <= (X << i)
+        gi, gd = host(*G.knn(to_dev(rd["queries"], dev), 10))
+        rows = np.random.default_rng(r).choice(len(rd["queries"]), 400, replace=False)
+        oi, od = oracle.knn_brute(pts, rd["queries"][rows], 10, ids=ids, nthreads=16)
+        assert_int_equal(gi[rows], gd[rows], oi, od)
