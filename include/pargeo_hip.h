@@ -161,6 +161,76 @@ pg_status pg_bdl_stats(const pg_bdl* b, int64_t* tree_mask, int64_t* buffer_coun
 /* Releases every tree (stream-ordered on the streams they were built on). */
 void pg_bdl_free(pg_bdl* b);
 
+/* ---------------------------------------------------------------------- */
+/* Batched uneven clouds (float32) and the differentiable k-NN backward    */
+/* ---------------------------------------------------------------------- */
+/* Tuning of the batched launch; 0 = default.  Every setting gives identical
+ * results. */
+typedef struct {
+    int32_t leaf;           /* leaf size of every cloud's tree (default 16)  */
+    int32_t blocks_per_cu;  /* persistent workgroups per compute unit (4)    */
+    int32_t reserved[2];
+} pg_tune;
+
+typedef struct pg_batch pg_batch;
+
+/* Workspace bytes needed by pg_batch_create for these clouds.
+ *   offsets_host : (host) [n_clouds+1], offsets[0] = 0, non-decreasing; cloud c
+ *                  is rows [offsets[c], offsets[c+1]) of the point array;
+ *                  total rows < 2^31
+ *   d : 1..8 */
+pg_status pg_batch_workspace(const int64_t* offsets_host, int32_t n_clouds, int32_t d,
+                             const pg_tune* tune, size_t* bytes);
+
+/* Plans a batch of clouds: uploads the per-cloud layout (largest cloud
+ * first) into `workspace` (device, >= pg_batch_workspace bytes; NULL = the
+ * library allocates and owns it).  Synchronises once.  The handle keeps a
+ * reference to the workspace, which must outlive it. */
+pg_status pg_batch_create(const int64_t* offsets_host, int32_t n_clouds, int32_t d,
+                          const pg_tune* tune, void* workspace, size_t workspace_bytes,
+                          void* stream, pg_batch** out);
+
+/* Per-cloud all-points k-NN of every cloud (the static search of Appendix C
+ * within each cloud), built and queried in one persistent launch with an
+ * atomic work queue (preceded by one small reset launch).  Allocates nothing,
+ * does not synchronise: may be captured in a HIP graph.  Calls sharing one
+ * workspace must not overlap.
+ *   points  : [N][d] float32, device (finite, |x| <= 1e18: see pg_batch_check)
+ *   out_idx : [N][k] int32 global rows of the neighbours (-1 = none)
+ *   out_d2  : [N][k] float32 squared distances */
+pg_status pg_batch_knn_self(pg_batch* b, const float* points, int32_t k, int32_t* out_idx,
+                            float* out_d2, void* stream);
+
+/* Range check of float32 points (synchronises); PG_ERR_RANGE if any is
+ * non-finite or |x| > 1e18. */
+pg_status pg_batch_check(const float* points, int64_t n, int32_t d, void* stream);
+
+/* Reads the workspace's wait-timeout flag of the last launch (synchronises). */
+pg_status pg_batch_status(const pg_batch* b, void* stream, int32_t* timed_out);
+
+/* Times every tuning candidate (leaf 8/16/32 x 2/4 workgroups per CU) on
+ * these points and returns the fastest; results are cached per
+ * (clouds, size bucket, d, k) for the life of the process.  Synchronises. */
+pg_status pg_batch_autotune(const float* points, const int64_t* offsets_host, int32_t n_clouds,
+                            int32_t d, int32_t k, void* stream, pg_tune* best);
+
+/* Releases the handle (and the workspace if the library allocated it). */
+void pg_batch_free(pg_batch* b);
+
+/* Backward of L = sum_{i,r} g[i,r] * D(q_i, x_{idx[i,r]}) with the neighbour
+ * sets held fixed (the forward's idx):
+ *   grad_q[i] = sum_r 2 g[i,r] (q_i - x_j)
+ *   grad_p[j] = - sum_{(i,r): idx[i,r] = j} 2 g[i,r] (q_i - x_j)
+ * Deterministic: each point's contributions are added in ascending (i, r)
+ * order.  idx entries < 0 (padding) are skipped.
+ *   queries [m][d], points [n][d], idx [m][k] int32 rows of points,
+ *   grad_d2 [m][k] float32; grad_q [m][d] and grad_p [n][d] are overwritten;
+ *   grad_q == grad_p is allowed when queries == points (m == n): the array
+ *   then receives the sum of both roles. */
+pg_status pg_knn_backward(const float* queries, const float* points, int64_t m, int64_t n,
+                          int32_t d, int32_t k, const int32_t* idx, const float* grad_d2,
+                          float* grad_q, float* grad_p, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -8,9 +8,9 @@ written out in FP64:
     dL/dx_j = - sum over (i, r) with idx[i, r] = j of 2 g[i,r] (q_i - x_j)
 
 Central differences re-run the whole k-NN (the definition, in FP64)
-at +-h, so that they include any change of neighbour set; coordinates whose
-neighbour sets change are reported, and are excluded from comparisons
-("away from ties").
+at +-h, so that they include any change of the neighbour lists; coordinates
+whose perturbation changes a list (its set or the order of its ranks) are
+reported, and are excluded from comparisons ("away from ties").
 """
 from __future__ import annotations
 
@@ -56,7 +56,9 @@ def fd_self(points, k, g, h=1e-6):
     are recomputed from the perturbed points in FP64.
 
     Returns (grad [n][d], stable mask [n][d]) where stable marks coordinates
-    whose perturbation changed no neighbour set."""
+    whose perturbation changed no neighbour list.  The weights g[i, r] belong
+    to ranks, so a swap of two ranks inside a list is a tie (a kink of the
+    loss) just as a change of the set is; the lists are compared in order."""
     P = np.asarray(points, dtype=np.float64)
     n, d = P.shape
     base = _sets64(P, k)
@@ -69,7 +71,7 @@ def fd_self(points, k, g, h=1e-6):
                 Pp = P.copy()
                 Pp[a, c] += s * h
                 ids = _sets64(Pp, k)
-                if not np.array_equal(np.sort(ids, axis=1), np.sort(base, axis=1)):
+                if not np.array_equal(ids, base):
                     stable[a, c] = False
                 vals.append(_loss_sets(Pp, ids, g))
             grad[a, c] = (vals[0] - vals[1]) / (2.0 * h)

@@ -53,7 +53,20 @@ SIGNATURES = {
     "pg_bdl_size": (i64, [vp]),
     "pg_bdl_stats": (i32, [vp, P64, P64, P64, i32]),
     "pg_bdl_free": (None, [vp]),
+    "pg_batch_workspace": (i32, [P64, i32, i32, vp, ctypes.POINTER(ctypes.c_size_t)]),
+    "pg_batch_create": (i32, [P64, i32, i32, vp, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]),
+    "pg_batch_knn_self": (i32, [vp, vp, i32, vp, vp, vp]),
+    "pg_batch_check": (i32, [vp, i64, i32, vp]),
+    "pg_batch_status": (i32, [vp, vp, P32]),
+    "pg_batch_autotune": (i32, [vp, P64, i32, i32, i32, vp, vp]),
+    "pg_batch_free": (None, [vp]),
+    "pg_knn_backward": (i32, [vp, vp, i64, i64, i32, i32, vp, vp, vp, vp, vp]),
 }
+
+
+class Tune(ctypes.Structure):
+    _fields_ = [("leaf", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 def lib():
@@ -229,3 +242,92 @@ class BDLTree:
         live = (ctypes.c_int64 * max_trees)()
         check(lib().pg_bdl_stats(self._h, ctypes.byref(F), ctypes.byref(b), live, max_trees))
         return F.value, b.value, list(live)
+
+
+def _offsets_array(offsets):
+    import numpy as np
+    o = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+    return o, o.ctypes.data_as(P64)
+
+
+class BatchKnn:
+    """Per-cloud all-points k-NN of many float32 clouds in one persistent
+    launch.  ``offsets`` (host, [C+1]) delimit the clouds in the point array.
+    The plan (and a library-owned workspace) is made once; ``knn_self`` only
+    launches, so it can be captured in a CUDA/HIP graph."""
+
+    def __init__(self, offsets, d: int, leaf: int = 0, blocks_per_cu: int = 0, device="cuda"):
+        self.offsets, optr = _offsets_array(offsets)
+        self.C = len(self.offsets) - 1
+        self.N = int(self.offsets[-1])
+        self.d = d
+        self.device = torch.device(device)
+        self.tune = Tune(leaf, blocks_per_cu, (ctypes.c_int32 * 2)(0, 0))
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            check(lib().pg_batch_create(optr, self.C, d, ctypes.byref(self.tune), None, 0,
+                                        stream_ptr(self.device), ctypes.byref(h)))
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.pg_batch_free(h)
+            self._h = None
+
+    def knn_self(self, points: torch.Tensor, k: int, out=None):
+        p = _points(points, "points")
+        if p.dtype != torch.float32 or p.shape != (self.N, self.d):
+            raise TypeError("points must be float32 [N][d] matching the offsets")
+        if out is None:
+            idx = torch.empty((self.N, k), dtype=torch.int32, device=p.device)
+            d2 = torch.empty((self.N, k), dtype=torch.float32, device=p.device)
+        else:
+            idx, d2 = out
+        check(lib().pg_batch_knn_self(self._h, ctypes.c_void_p(p.data_ptr()), k,
+                                      ctypes.c_void_p(idx.data_ptr()), ctypes.c_void_p(d2.data_ptr()),
+                                      stream_ptr(p.device)))
+        return idx, d2
+
+    def timed_out(self) -> bool:
+        flag = ctypes.c_int32()
+        check(lib().pg_batch_status(self._h, stream_ptr(self.device), ctypes.byref(flag)))
+        return bool(flag.value)
+
+
+def batch_check(points: torch.Tensor):
+    p = _points(points, "points")
+    check(lib().pg_batch_check(ctypes.c_void_p(p.data_ptr()), p.shape[0], p.shape[1],
+                               stream_ptr(p.device)))
+
+
+def batch_autotune(points: torch.Tensor, offsets, k: int):
+    p = _points(points, "points")
+    o, optr = _offsets_array(offsets)
+    t = Tune()
+    check(lib().pg_batch_autotune(ctypes.c_void_p(p.data_ptr()), optr, len(o) - 1, p.shape[1], k,
+                                  stream_ptr(p.device), ctypes.byref(t)))
+    return {"leaf": t.leaf, "blocks_per_cu": t.blocks_per_cu}
+
+
+def knn_backward(queries, points, idx, grad_d2, grad_q=None, grad_p=None, self_mode=False):
+    """Gradients of sum g * D with fixed neighbours (see pg_knn_backward).
+    self_mode: queries is points, one gradient array receives both roles."""
+    q = _points(queries, "queries")
+    x = _points(points, "points")
+    idx = idx.contiguous()
+    g = grad_d2.contiguous().to(torch.float32)
+    m, d = q.shape
+    n = x.shape[0]
+    k = idx.shape[1]
+    if self_mode:
+        gq = torch.empty_like(x) if grad_q is None else grad_q
+        gp = gq
+    else:
+        gq = torch.empty_like(q) if grad_q is None else grad_q
+        gp = torch.empty_like(x) if grad_p is None else grad_p
+    check(lib().pg_knn_backward(ctypes.c_void_p(q.data_ptr()), ctypes.c_void_p(x.data_ptr()), m, n,
+                                d, k, ctypes.c_void_p(idx.data_ptr()), ctypes.c_void_p(g.data_ptr()),
+                                ctypes.c_void_p(gq.data_ptr()), ctypes.c_void_p(gp.data_ptr()),
+                                stream_ptr(q.device)))
+    return gq, gp

@@ -1,0 +1,627 @@
+// Batched uneven point clouds: thousands of independent float32 clouds are
+// built and queried (all-points k-NN within each cloud) in ONE persistent
+// launch driven by an atomic work queue, plus a small reset launch before it.
+// Both launches allocate nothing and read nothing back, so a caller may
+// capture them in a HIP graph.
+//
+//   items [0, C)        build cloud order[t] (largest first) with one
+//                       workgroup: top levels by workgroup radix select +
+//                       stable partition in global memory (L2-resident),
+//                       bottom subtrees in LDS (the same device functions as
+//                       the static build); then publish ready[c] (release);
+//   items [C, C + Q)    (cloud, block of 256 of its points): wait for
+//                       ready[c] (acquire), one point per lane, the static
+//                       search (search.hpp) over the cloud's own tree.
+//
+// Build items precede every query item in the queue, so a workgroup that
+// waits for a cloud waits for a workgroup that is already running: the wait
+// always ends.  It is bounded anyway and reports a timeout in the workspace.
+//
+// The autotuner times leaf sizes {8, 16, 32} x workgroups per compute unit
+// {2, 4} on the caller's data and keeps the fastest per workload key; every
+// choice returns identical results (the k-NN result does not depend on the
+// tree).
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <new>
+#include <numeric>
+#include <tuple>
+#include <vector>
+
+#include "build.hpp"
+#include "build_dev.hpp"
+#include "knn.hpp"
+#include "scan.hpp"
+#include "search.hpp"
+#include "wave.hpp"
+
+namespace pg {
+
+namespace {
+
+constexpr int kNT = kBuildNT;   // 256
+constexpr int kQB = kNT;        // queries per query item
+constexpr uint32_t kSpinLimit = 1u << 26;
+
+struct CloudDesc {
+    int64_t row;    // first global row of the cloud
+    int64_t pts;    // element offset of its coordinate planes [d][n] (and key scratch)
+    int64_t split;  // offset of its split array [2^L]
+    int64_t bbox;   // offset of its leaf boxes [2^L][2d]
+    int32_t n, L, ls, pad;
+};
+
+struct BatchParams {
+    const uint32_t* points;  // [N][d] float32 bits
+    int32_t* out_idx;        // [N][k]
+    float* out_d2;           // [N][k]
+    uint32_t* queue;         // [0] next item, [1] error flags
+    uint32_t* ready;         // [C]
+    const int32_t* order;    // [C] clouds by descending size
+    const int64_t* qstart;   // [C+1] first query item of order[t]
+    const CloudDesc* desc;   // [C]
+    uint32_t* pts;           // coordinate planes pool
+    uint32_t* keys;          // key scratch pool (same layout)
+    int32_t* pidx;           // [N] leaf order -> local row
+    int32_t* pidx2;          // [N] scratch
+    uint32_t* split;         // split pool
+    uint32_t* bbox;          // box pool
+    int64_t total_items;
+    int32_t C, d, k, S;
+};
+
+__global__ void batch_reset_kernel(uint32_t* queue, uint32_t* ready, int C) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < 2) queue[i] = 0;
+    for (int c = i; c < C; c += gridDim.x * blockDim.x) ready[c] = 0;
+}
+
+__device__ inline void build_cloud(const BatchParams& P, int c, uint32_t* sm) {
+    const CloudDesc D = P.desc[c];
+    const int64_t n = D.n;
+    const int d = P.d;
+    uint32_t* outp = P.pts + D.pts;
+    uint32_t* scr = P.keys + D.pts;
+    int32_t* oidx = P.pidx + D.row;
+    int32_t* sidx = P.pidx2 + D.row;
+    uint32_t* split = P.split + D.split;
+    uint32_t* bbox = P.bbox + D.bbox;
+    if (n > 0) {
+        // ingest: rows -> key planes (in the output planes), -0.0 -> +0.0
+        for (int64_t e = threadIdx.x; e < n; e += kNT) {
+            for (int cc = 0; cc < d; cc++) {
+                uint32_t b = P.points[(D.row + e) * d + cc];
+                if (b == 0x80000000u) b = 0;
+                outp[(int64_t)cc * n + e] = coord_to_key(b, true);
+            }
+            oidx[e] = (int32_t)e;
+        }
+        __syncthreads();
+        uint32_t* cur = outp;
+        int32_t* cur_i = oidx;
+        uint32_t* oth = scr;
+        int32_t* oth_i = sidx;
+        for (int l = 0; l < D.ls; l++) {
+            const int cdim = l % d;
+            for (int64_t j = 0; j < ((int64_t)1 << l); j++) {
+                const int64_t lo = node_start(n, l, j), hi = node_start(n, l, j + 1);
+                const int64_t mid = node_start(n, l + 1, 2 * j + 1);
+                uint32_t mn, mx;
+                block_minmax(cur + (int64_t)cdim * n, lo, hi, sm, &mn, &mx);
+                const int sb = mn == mx ? 0 : 32 - __clz(mn ^ mx);
+                const uint32_t low = sb >= 32 ? 0xffffffffu : ((1u << sb) - 1u);
+                block_node_split(cur, cur_i, oth, oth_i, d, cdim, n, lo, hi, mid, mn & ~low, sb,
+                                 &split[((int64_t)1 << l) + j], true, sm);
+                __syncthreads();
+            }
+            uint32_t* t = cur; cur = oth; oth = t;
+            int32_t* ti = cur_i; cur_i = oth_i; oth_i = ti;
+        }
+        for (int64_t j0 = 0; j0 < ((int64_t)1 << D.ls); j0++)
+            block_subtree(cur, cur_i, n, d, D.L, D.ls, j0, P.S, true, outp, oidx, split, bbox, sm);
+    }
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0)
+        __hip_atomic_store(&P.ready[c], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int MD, int KT>
+__device__ inline void query_item(const BatchParams& P, int64_t q, int* s_ok) {
+    // item -> position t in the size order (binary search over qstart)
+    int lo = 0, hi = P.C;  // qstart[lo] <= q < qstart[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (P.qstart[mid] <= q) lo = mid;
+        else hi = mid;
+    }
+    const int c = P.order[lo];
+    const int64_t blk = q - P.qstart[lo];
+    if (threadIdx.x == 0) {
+        uint32_t spins = 0;
+        int ok = 1;
+        while (__hip_atomic_load(&P.ready[c], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0u) {
+            __builtin_amdgcn_s_sleep(8);
+            if (++spins > kSpinLimit) {
+                atomicOr(&P.queue[1], 1u);
+                ok = 0;
+                break;
+            }
+        }
+        *s_ok = ok;
+    }
+    __syncthreads();
+    const int ok = *s_ok;
+    __syncthreads();
+    if (!ok) return;
+    (void)__hip_atomic_load(&P.ready[c], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    const CloudDesc D = P.desc[c];
+    const int64_t i = blk * kQB + threadIdx.x;
+    if (i >= D.n) return;
+    const int d = P.d, k = P.k;
+    const TreeView tv{D.n, d, D.L, P.pts + D.pts, P.pidx + D.row, P.split + D.split,
+                      P.bbox + D.bbox};
+    using M = Metric<float>;
+    float q_[MD];
+#pragma unroll
+    for (int cc = 0; cc < MD; cc++) q_[cc] = cc < d ? M::load(tv.pts[(int64_t)cc * D.n + i]) : 0.0f;
+    KList<float, int32_t, KT> kl;
+    kl.init(k, M::inf(), INT32_MAX);
+    kd_search<float, MD, KT, int32_t>(tv, PlainIds{tv.pidx}, q_, d, kl, k);
+    const int64_t row = D.row + tv.pidx[i];
+#pragma unroll
+    for (int s = 0; s < KT; s++) {
+        if (s < k) {
+            P.out_idx[row * k + s] = kl.id[s] == INT32_MAX ? -1 : (int32_t)(D.row + kl.id[s]);
+            P.out_d2[row * k + s] = kl.d[s];
+        }
+    }
+}
+
+template <int MD, int KT>
+__global__ void __launch_bounds__(kNT) batch_kernel(BatchParams P) {
+    extern __shared__ uint32_t sm[];
+    __shared__ int s_item;
+    __shared__ int s_ok;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = (int)atomicAdd(&P.queue[0], 1u);
+        __syncthreads();
+        const int64_t it = s_item;
+        __syncthreads();
+        if (it >= P.total_items) break;
+        if (it < P.C) build_cloud(P, P.order[it], sm);
+        else query_item<MD, KT>(P, it - P.C, &s_ok);
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Backward of L = sum_{i,r} g[i,r] D(q_i, x_{idx[i,r]}) with fixed neighbours.
+// ---------------------------------------------------------------------------
+__global__ void grad_q_kernel(const float* __restrict__ q, const float* __restrict__ x,
+                              int64_t m, int64_t n, int d, int k, const int32_t* __restrict__ idx,
+                              const float* __restrict__ g, float* __restrict__ gq) {
+    const int64_t t = (int64_t)blockIdx.x * kNT + threadIdx.x;
+    if (t >= m * d) return;
+    const int64_t i = t / d;
+    const int c = (int)(t % d);
+    const float qc = q[i * d + c];
+    float acc = 0.0f;
+    for (int r = 0; r < k; r++) {
+        const int32_t j = idx[i * k + r];
+        if (j < 0 || j >= n) continue;
+        acc += 2.0f * g[i * k + r] * (qc - x[(int64_t)j * d + c]);
+    }
+    gq[t] = acc;
+}
+
+__global__ void pair_count_kernel(const int32_t* __restrict__ idx, int64_t P, int64_t n,
+                                  uint32_t* __restrict__ cnt) {
+    const int64_t p = (int64_t)blockIdx.x * kNT + threadIdx.x;
+    if (p < P && idx[p] >= 0 && idx[p] < n) atomicAdd(&cnt[idx[p]], 1u);
+}
+
+__global__ void pair_fill_kernel(const int32_t* __restrict__ idx, int64_t P, int64_t n,
+                                 const uint32_t* __restrict__ start, uint32_t* __restrict__ cursor,
+                                 uint32_t* __restrict__ list) {
+    const int64_t p = (int64_t)blockIdx.x * kNT + threadIdx.x;
+    if (p >= P) return;
+    const int32_t j = idx[p];
+    if (j < 0 || j >= n) return;
+    list[start[j] + atomicAdd(&cursor[j], 1u)] = (uint32_t)p;
+}
+
+// Puts each point's pair list in ascending pair order (rank by counting), so
+// the sums below add in a fixed order.
+__global__ void pair_order_kernel(const uint32_t* __restrict__ list,
+                                  const uint32_t* __restrict__ total,
+                                  const int32_t* __restrict__ idx,
+                                  const uint32_t* __restrict__ start,
+                                  const uint32_t* __restrict__ cnt, uint32_t* __restrict__ ordered) {
+    const int64_t s = (int64_t)blockIdx.x * kNT + threadIdx.x;
+    if (s >= (int64_t)*total) return;  // only the filled entries
+    const uint32_t p = list[s];
+    const int32_t j = idx[p];
+    const uint32_t b = start[j], e = b + cnt[j];
+    uint32_t rank = 0;
+    for (uint32_t t = b; t < e; t++) rank += list[t] < p;
+    ordered[b + rank] = p;
+}
+
+__global__ void grad_x_kernel(const float* __restrict__ q, const float* __restrict__ x,
+                              int64_t n, int d, int k, const float* __restrict__ g,
+                              const uint32_t* __restrict__ start, const uint32_t* __restrict__ cnt,
+                              const uint32_t* __restrict__ ordered, int accumulate,
+                              float* __restrict__ gx) {
+    const int64_t t = (int64_t)blockIdx.x * kNT + threadIdx.x;
+    if (t >= n * d) return;
+    const int64_t j = t / d;
+    const int c = (int)(t % d);
+    const float xc = x[t];
+    const uint32_t b = start[j], e = b + cnt[j];
+    float acc = 0.0f;
+    for (uint32_t s = b; s < e; s++) {
+        const uint32_t p = ordered[s];
+        const int64_t i = p / (uint32_t)k;
+        acc += 2.0f * g[p] * (q[i * d + c] - xc);
+    }
+    gx[t] = accumulate ? gx[t] - acc : -acc;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Host side.
+// ---------------------------------------------------------------------------
+struct BatchPlan {
+    int C = 0, d = 0, leaf = 0, bpc = 0, S = 0;
+    int64_t N = 0, total_items = 0;
+    // workspace carve-up
+    size_t bytes = 0;
+    size_t o_queue = 0, o_ready = 0, o_order = 0, o_qstart = 0, o_desc = 0, o_pts = 0,
+           o_keys = 0, o_pidx = 0, o_pidx2 = 0, o_split = 0, o_bbox = 0;
+    std::vector<int32_t> order;
+    std::vector<int64_t> qstart;
+    std::vector<CloudDesc> desc;
+};
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static pg_status make_plan(const int64_t* offs, int C, int d, int leaf, int bpc, BatchPlan& P) {
+    P.C = C;
+    P.d = d;
+    P.leaf = leaf;
+    P.bpc = bpc;
+    P.S = subtree_capacity(d);
+    P.desc.resize(C);
+    int64_t pts = 0, split = 0, bbox = 0;
+    for (int c = 0; c < C; c++) {
+        const int64_t n = offs[c + 1] - offs[c];
+        if (n < 0) return fail(PG_ERR_INVALID, "batch: offsets must be non-decreasing");
+        if (n >= ((int64_t)1 << 31)) return fail(PG_ERR_INVALID, "batch: cloud too large");
+        CloudDesc& D = P.desc[c];
+        D.row = offs[c];
+        D.n = (int32_t)n;
+        D.L = tree_levels(n, leaf);
+        int ls = 0;
+        while (((n + ((int64_t)1 << ls) - 1) >> ls) > P.S) ls++;
+        D.ls = ls;
+        D.pad = 0;
+        D.pts = pts;
+        D.split = split;
+        D.bbox = bbox;
+        pts += (int64_t)d * n;
+        split += (int64_t)1 << D.L;
+        bbox += ((int64_t)1 << D.L) * 2 * d;
+    }
+    P.N = offs[C] - offs[0];
+    if (offs[0] != 0) return fail(PG_ERR_INVALID, "batch: offsets[0] must be 0");
+    if (P.N >= ((int64_t)1 << 31)) return fail(PG_ERR_INVALID, "batch: total points must be < 2^31");
+    P.order.resize(C);
+    std::iota(P.order.begin(), P.order.end(), 0);
+    std::stable_sort(P.order.begin(), P.order.end(),
+                     [&](int a, int b) { return P.desc[a].n > P.desc[b].n; });
+    P.qstart.resize(C + 1);
+    int64_t q = 0;
+    for (int t = 0; t < C; t++) {
+        P.qstart[t] = q;
+        q += (P.desc[P.order[t]].n + kQB - 1) / kQB;
+    }
+    P.qstart[C] = q;
+    P.total_items = C + q;
+    size_t o = 0;
+    P.o_queue = o; o = align256(o + 16);
+    P.o_ready = o; o = align256(o + 4 * (size_t)C);
+    P.o_order = o; o = align256(o + 4 * (size_t)C);
+    P.o_qstart = o; o = align256(o + 8 * (size_t)(C + 1));
+    P.o_desc = o; o = align256(o + sizeof(CloudDesc) * (size_t)C);
+    P.o_pts = o; o = align256(o + 4 * (size_t)(pts > 0 ? pts : 1));
+    P.o_keys = o; o = align256(o + 4 * (size_t)(pts > 0 ? pts : 1));
+    P.o_pidx = o; o = align256(o + 4 * (size_t)(P.N > 0 ? P.N : 1));
+    P.o_pidx2 = o; o = align256(o + 4 * (size_t)(P.N > 0 ? P.N : 1));
+    P.o_split = o; o = align256(o + 4 * (size_t)(split > 0 ? split : 1));
+    P.o_bbox = o; o = align256(o + 4 * (size_t)(bbox > 0 ? bbox : 1));
+    P.bytes = o;
+    return PG_OK;
+}
+
+}  // namespace pg
+
+struct pg_batch {
+    pg::BatchPlan plan;
+    uint8_t* ws = nullptr;
+    bool owns = false;
+    hipStream_t stream = nullptr;
+    int num_cu = 0;
+};
+
+namespace pg {
+namespace {
+
+template <int MD, int KT>
+pg_status launch_batch(pg_batch* b, const BatchParams& P, hipStream_t s) {
+    const size_t lds = subtree_lds_bytes(P.d, P.S);
+    const unsigned grid = (unsigned)(b->num_cu * b->plan.bpc);
+    hipLaunchKernelGGL(batch_reset_kernel, dim3(8), dim3(kNT), 0, s, P.queue, P.ready, P.C);
+    PG_LAUNCH_CHECK();
+    hipLaunchKernelGGL((batch_kernel<MD, KT>), dim3(grid), dim3(kNT), lds, s, P);
+    PG_LAUNCH_CHECK();
+    return PG_OK;
+}
+
+template <int MD>
+pg_status batch_k(pg_batch* b, const BatchParams& P, hipStream_t s) {
+    const int k = P.k;
+    if (k <= 2) return launch_batch<MD, 2>(b, P, s);
+    if (k <= 4) return launch_batch<MD, 4>(b, P, s);
+    if (k <= 8) return launch_batch<MD, 8>(b, P, s);
+    if (k <= 16) return launch_batch<MD, 16>(b, P, s);
+    if (k <= 32) return launch_batch<MD, 32>(b, P, s);
+    return launch_batch<MD, 64>(b, P, s);
+}
+
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int64_t, int, int>, pg_tune> g_tune_cache;
+
+}  // namespace
+}  // namespace pg
+
+using namespace pg;
+
+extern "C" {
+
+pg_status pg_batch_workspace(const int64_t* offsets_host, int32_t n_clouds, int32_t d,
+                             const pg_tune* tune, size_t* bytes) {
+    if (!offsets_host || !bytes) return fail(PG_ERR_INVALID, "pg_batch_workspace: NULL pointer");
+    if (n_clouds < 1) return fail(PG_ERR_INVALID, "pg_batch_workspace: n_clouds must be >= 1");
+    if (d < 1 || d > 8) return fail(PG_ERR_INVALID, "pg_batch_workspace: d must be in [1, 8]");
+    const int leaf = tune && tune->leaf ? tune->leaf : 16;
+    if (leaf < 1 || leaf > 64) return fail(PG_ERR_INVALID, "pg_batch_workspace: leaf must be in [1, 64]");
+    BatchPlan P;
+    PG_TRY(make_plan(offsets_host, n_clouds, d, leaf, 4, P));
+    *bytes = P.bytes;
+    return PG_OK;
+}
+
+pg_status pg_batch_create(const int64_t* offsets_host, int32_t n_clouds, int32_t d,
+                          const pg_tune* tune, void* workspace, size_t workspace_bytes,
+                          void* stream, pg_batch** out) {
+    if (!offsets_host || !out) return fail(PG_ERR_INVALID, "pg_batch_create: NULL pointer");
+    if (n_clouds < 1) return fail(PG_ERR_INVALID, "pg_batch_create: n_clouds must be >= 1");
+    if (d < 1 || d > 8) return fail(PG_ERR_INVALID, "pg_batch_create: d must be in [1, 8]");
+    const int leaf = tune && tune->leaf ? tune->leaf : 16;
+    const int bpc = tune && tune->blocks_per_cu ? tune->blocks_per_cu : 4;
+    if (leaf < 1 || leaf > 64) return fail(PG_ERR_INVALID, "pg_batch_create: leaf must be in [1, 64]");
+    if (bpc < 1 || bpc > 16) return fail(PG_ERR_INVALID, "pg_batch_create: blocks_per_cu must be in [1, 16]");
+    pg_batch* b = new (std::nothrow) pg_batch();
+    if (!b) return fail(PG_ERR_NOMEM, "pg_batch_create: host allocation failed");
+    pg_status st = make_plan(offsets_host, n_clouds, d, leaf, bpc, b->plan);
+    if (st != PG_OK) { delete b; return st; }
+    hipStream_t s = (hipStream_t)stream;
+    b->stream = s;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&b->num_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) { delete b; return fail(PG_ERR_DEVICE, "pg_batch_create: device query failed"); }
+    if (workspace) {
+        if (workspace_bytes < b->plan.bytes) {
+            delete b;
+            return fail(PG_ERR_INVALID, "pg_batch_create: workspace too small (see pg_batch_workspace)");
+        }
+        b->ws = (uint8_t*)workspace;
+    } else {
+        void* p = nullptr;
+        st = dmalloc(&p, b->plan.bytes, s);
+        if (st != PG_OK) { delete b; return st; }
+        b->ws = (uint8_t*)p;
+        b->owns = true;
+    }
+    const BatchPlan& P = b->plan;
+    // Static plan tables (order, query starts, descriptors) go to the workspace
+    // once, here; the launches only read them.
+    hipError_t e1 = hipMemcpyAsync(b->ws + P.o_order, P.order.data(), 4 * (size_t)P.C, hipMemcpyHostToDevice, s);
+    hipError_t e2 = hipMemcpyAsync(b->ws + P.o_qstart, P.qstart.data(), 8 * (size_t)(P.C + 1), hipMemcpyHostToDevice, s);
+    hipError_t e3 = hipMemcpyAsync(b->ws + P.o_desc, P.desc.data(), sizeof(CloudDesc) * (size_t)P.C, hipMemcpyHostToDevice, s);
+    hipError_t e4 = hipStreamSynchronize(s);
+    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess) {
+        if (b->owns) dfree(b->ws, s);
+        delete b;
+        return fail(PG_ERR_DEVICE, "pg_batch_create: plan upload failed");
+    }
+    *out = b;
+    return PG_OK;
+}
+
+pg_status pg_batch_knn_self(pg_batch* b, const float* points, int32_t k, int32_t* out_idx,
+                            float* out_d2, void* stream) {
+    if (!b) return fail(PG_ERR_INVALID, "pg_batch_knn_self: handle is NULL");
+    if (k < 1 || k > 64) return fail(PG_ERR_INVALID, "pg_batch_knn_self: k must be in [1, 64]");
+    const BatchPlan& PL = b->plan;
+    if (PL.N > 0 && (!points || !out_idx || !out_d2)) return fail(PG_ERR_INVALID, "pg_batch_knn_self: NULL pointer");
+    BatchParams P;
+    P.points = (const uint32_t*)points;
+    P.out_idx = out_idx;
+    P.out_d2 = out_d2;
+    P.queue = (uint32_t*)(b->ws + PL.o_queue);
+    P.ready = (uint32_t*)(b->ws + PL.o_ready);
+    P.order = (const int32_t*)(b->ws + PL.o_order);
+    P.qstart = (const int64_t*)(b->ws + PL.o_qstart);
+    P.desc = (const CloudDesc*)(b->ws + PL.o_desc);
+    P.pts = (uint32_t*)(b->ws + PL.o_pts);
+    P.keys = (uint32_t*)(b->ws + PL.o_keys);
+    P.pidx = (int32_t*)(b->ws + PL.o_pidx);
+    P.pidx2 = (int32_t*)(b->ws + PL.o_pidx2);
+    P.split = (uint32_t*)(b->ws + PL.o_split);
+    P.bbox = (uint32_t*)(b->ws + PL.o_bbox);
+    P.total_items = PL.total_items;
+    P.C = PL.C;
+    P.d = PL.d;
+    P.k = k;
+    P.S = PL.S;
+    hipStream_t s = (hipStream_t)stream;
+    switch (PL.d) {
+        case 2: return batch_k<2>(b, P, s);
+        case 3: return batch_k<3>(b, P, s);
+        case 5: return batch_k<5>(b, P, s);
+        default: return batch_k<8>(b, P, s);
+    }
+}
+
+pg_status pg_batch_status(const pg_batch* b, void* stream, int32_t* timed_out) {
+    if (!b) return fail(PG_ERR_INVALID, "pg_batch_status: handle is NULL");
+    uint32_t h[2] = {0, 0};
+    hipStream_t s = (hipStream_t)stream;
+    PG_HIP(hipMemcpyAsync(h, b->ws + b->plan.o_queue, sizeof(h), hipMemcpyDeviceToHost, s));
+    PG_HIP(hipStreamSynchronize(s));
+    if (timed_out) *timed_out = (h[1] & 1u) ? 1 : 0;
+    return PG_OK;
+}
+
+pg_status pg_batch_check(const float* points, int64_t n, int32_t d, void* stream) {
+    if (d < 1 || d > 8) return fail(PG_ERR_INVALID, "pg_batch_check: d must be in [1, 8]");
+    if (n < 0) return fail(PG_ERR_INVALID, "pg_batch_check: n < 0");
+    if (n > 0 && !points) return fail(PG_ERR_INVALID, "pg_batch_check: points is NULL");
+    return check_queries(points, n, d, true, (hipStream_t)stream);
+}
+
+pg_status pg_batch_autotune(const float* points, const int64_t* offsets_host, int32_t n_clouds,
+                            int32_t d, int32_t k, void* stream, pg_tune* best) {
+    if (!best || !offsets_host) return fail(PG_ERR_INVALID, "pg_batch_autotune: NULL pointer");
+    if (n_clouds < 1 || d < 1 || d > 8 || k < 1 || k > 64)
+        return fail(PG_ERR_INVALID, "pg_batch_autotune: bad sizes");
+    const int64_t N = offsets_host[n_clouds];
+    int64_t bucket = 1;
+    while (bucket < N) bucket <<= 1;
+    const auto key = std::make_tuple(n_clouds, bucket, d * 100 + k, 0);
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            *best = it->second;
+            return PG_OK;
+        }
+    }
+    hipStream_t s = (hipStream_t)stream;
+    DevBuf oi(s), od(s);
+    PG_TRY(oi.alloc(sizeof(int32_t) * (size_t)(N > 0 ? N : 1) * k));
+    PG_TRY(od.alloc(sizeof(float) * (size_t)(N > 0 ? N : 1) * k));
+    hipEvent_t e0, e1;
+    PG_HIP(hipEventCreate(&e0));
+    PG_HIP(hipEventCreate(&e1));
+    float best_ms = 1e30f;
+    pg_tune win{16, 4, {0, 0}};
+    const int leaves[3] = {8, 16, 32};
+    const int bpcs[2] = {2, 4};
+    for (int li = 0; li < 3; li++)
+        for (int bi = 0; bi < 2; bi++) {
+            pg_tune t{leaves[li], bpcs[bi], {0, 0}};
+            pg_batch* b = nullptr;
+            PG_TRY(pg_batch_create(offsets_host, n_clouds, d, &t, nullptr, 0, stream, &b));
+            pg_status st = pg_batch_knn_self(b, points, k, oi.as<int32_t>(), od.as<float>(), stream);
+            float ms = 0.0f;
+            if (st == PG_OK) {
+                (void)hipEventRecord(e0, s);
+                st = pg_batch_knn_self(b, points, k, oi.as<int32_t>(), od.as<float>(), stream);
+                (void)hipEventRecord(e1, s);
+                (void)hipEventSynchronize(e1);
+                (void)hipEventElapsedTime(&ms, e0, e1);
+            }
+            pg_batch_free(b);
+            if (st != PG_OK) {
+                (void)hipEventDestroy(e0);
+                (void)hipEventDestroy(e1);
+                return st;
+            }
+            if (ms < best_ms) {
+                best_ms = ms;
+                win = t;
+            }
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        g_tune_cache[key] = win;
+    }
+    *best = win;
+    return PG_OK;
+}
+
+void pg_batch_free(pg_batch* b) {
+    if (!b) return;
+    if (b->owns) dfree(b->ws, b->stream);
+    delete b;
+}
+
+pg_status pg_knn_backward(const float* queries, const float* points, int64_t m, int64_t n,
+                          int32_t d, int32_t k, const int32_t* idx, const float* grad_d2,
+                          float* grad_q, float* grad_p, void* stream) {
+    if (d < 1 || d > 8 || k < 1 || k > 64) return fail(PG_ERR_INVALID, "pg_knn_backward: bad d or k");
+    if (m < 0 || n < 0 || m * (int64_t)k >= ((int64_t)1 << 32) || n >= ((int64_t)1 << 31))
+        return fail(PG_ERR_INVALID, "pg_knn_backward: bad sizes");
+    if ((m > 0 && (!queries || !idx || !grad_d2 || !grad_q)) || (n > 0 && (!points || !grad_p)))
+        return fail(PG_ERR_INVALID, "pg_knn_backward: NULL pointer");
+    const bool alias = grad_q == grad_p;
+    if (alias && (queries != points || m != n))
+        return fail(PG_ERR_INVALID, "pg_knn_backward: grad_q may alias grad_p only when queries == points");
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t P = m * k;
+    if (m > 0) {
+        hipLaunchKernelGGL(grad_q_kernel, dim3(cdiv(m * d, kNT)), dim3(kNT), 0, s, queries, points,
+                           m, n, d, k, idx, grad_d2, grad_q);
+        PG_LAUNCH_CHECK();
+    }
+    if (n == 0) return PG_OK;
+    DevBuf cnt(s), start(s), cursor(s), list(s), ordered(s), total(s);
+    PG_TRY(total.alloc(sizeof(uint32_t)));
+    PG_TRY(cnt.alloc(sizeof(uint32_t) * n));
+    PG_TRY(start.alloc(sizeof(uint32_t) * n));
+    PG_TRY(cursor.alloc(sizeof(uint32_t) * n));
+    PG_TRY(list.alloc(sizeof(uint32_t) * (P > 0 ? P : 1)));
+    PG_TRY(ordered.alloc(sizeof(uint32_t) * (P > 0 ? P : 1)));
+    PG_HIP(hipMemsetAsync(cnt.p, 0, sizeof(uint32_t) * n, s));
+    PG_HIP(hipMemsetAsync(cursor.p, 0, sizeof(uint32_t) * n, s));
+    if (P > 0) {
+        hipLaunchKernelGGL(pair_count_kernel, dim3(cdiv(P, kNT)), dim3(kNT), 0, s, idx, P, n,
+                           cnt.as<uint32_t>());
+        PG_LAUNCH_CHECK();
+    }
+    PG_TRY(exclusive_scan_u32(cnt.as<uint32_t>(), start.as<uint32_t>(), n, total.as<uint32_t>(), s));
+    if (P > 0) {
+        hipLaunchKernelGGL(pair_fill_kernel, dim3(cdiv(P, kNT)), dim3(kNT), 0, s, idx, P, n,
+                           start.as<uint32_t>(), cursor.as<uint32_t>(), list.as<uint32_t>());
+        PG_LAUNCH_CHECK();
+        hipLaunchKernelGGL(pair_order_kernel, dim3(cdiv(P, kNT)), dim3(kNT), 0, s,
+                           list.as<uint32_t>(), total.as<uint32_t>(), idx, start.as<uint32_t>(),
+                           cnt.as<uint32_t>(), ordered.as<uint32_t>());
+        PG_LAUNCH_CHECK();
+    }
+    hipLaunchKernelGGL(grad_x_kernel, dim3(cdiv(n * d, kNT)), dim3(kNT), 0, s, queries, points,
+                       n, d, k, grad_d2, start.as<uint32_t>(), cnt.as<uint32_t>(),
+                       ordered.as<uint32_t>(), alias ? 1 : 0, grad_p);
+    PG_LAUNCH_CHECK();
+    return PG_OK;
+}
+
+}  // extern "C"

@@ -23,13 +23,14 @@
 #include <utility>
 
 #include "build.hpp"
+#include "build_dev.hpp"
 #include "wave.hpp"
 
 namespace pg {
 
 namespace {
 
-constexpr int kNT = 256;            // threads per workgroup
+constexpr int kNT = kBuildNT;       // threads per workgroup
 constexpr int kChunk = 16384;       // elements per workgroup in the wide levels
 constexpr int kWideDigit = 11;      // radix digit width in the wide levels
 constexpr int kWideNodes = 512;     // levels with fewer nodes use the wide path
@@ -211,39 +212,6 @@ wide_scan_kernel(uint64_t* __restrict__ bcnt, int bpn) {
     }
 }
 
-// Stable partition of one tile of consecutive elements [base, base+NT) of a
-// node; run_lt / run_eq count the node's elements before the tile.
-__device__ inline void partition_tile(const uint32_t* __restrict__ in, const int32_t* __restrict__ in_idx,
-                                      uint32_t* __restrict__ out, int32_t* __restrict__ out_idx,
-                                      int d, int c, int64_t n, int64_t base, int64_t end,
-                                      int64_t lo, int64_t mid, int64_t end_node, uint32_t v,
-                                      uint32_t teq,
-                                      uint32_t& run_lt, uint32_t& run_eq, uint32_t* lds) {
-    const int64_t e = base + threadIdx.x;
-    const bool valid = e < end;
-    const uint32_t k = valid ? in[(int64_t)c * n + e] : 0u;
-    const bool lt = valid && k < v;
-    const bool eq = valid && k == v;
-    uint32_t tot;
-    uint32_t ex = block_excl_scan<kNT>((lt ? 1u : 0u) | (eq ? 0x10000u : 0u), lds, &tot);
-    const uint32_t ltb = run_lt + (ex & 0xffffu);
-    const uint32_t eqb = run_eq + (ex >> 16);
-    if (valid) {
-        const uint32_t el = eqb < teq ? eqb : teq;
-        int64_t dest;
-        if (lt) dest = lo + ltb + el;
-        else if (eq && eqb < teq) dest = lo + ltb + eqb;
-        else dest = mid + (e - lo) - (int64_t)(ltb + el);
-        if (dest >= lo && dest < end_node) {  // always true for a consistent split
-            for (int cc = 0; cc < d; cc++)
-                out[(int64_t)cc * n + dest] = cc == c ? k : in[(int64_t)cc * n + e];
-            out_idx[dest] = in_idx[e];
-        }
-    }
-    run_lt += tot & 0xffffu;
-    run_eq += tot >> 16;
-}
-
 __global__ void __launch_bounds__(kNT)
 wide_scatter_kernel(const uint32_t* __restrict__ in, const int32_t* __restrict__ in_idx,
                     uint32_t* __restrict__ out, int32_t* __restrict__ out_idx, int d, int c,
@@ -271,113 +239,17 @@ __global__ void __launch_bounds__(kNT)
 node_kernel(const uint32_t* __restrict__ in, const int32_t* __restrict__ in_idx,
             uint32_t* __restrict__ out, int32_t* __restrict__ out_idx, int d, int c, int64_t n,
             int l, uint32_t prefix0, int sb, uint32_t* __restrict__ split_level, int fl) {
-    __shared__ uint32_t hist[kNT];
-    __shared__ uint32_t lds[kNT / kWave + 1];
-    __shared__ uint32_t sel[2];
+    __shared__ uint32_t sh[272];
     const int64_t j = blockIdx.x;
     int64_t lo, hi, mid;
-    uint32_t r = (uint32_t)split_rank_pos(n, l, j, &lo, &hi, &mid);
-    const uint32_t* keys = in + (int64_t)c * n;
-    uint32_t prefix = prefix0;
-    for (int hb = sb; hb > 0; hb -= 8) {
-        const int shift = hb > 8 ? hb - 8 : 0;
-        const uint32_t wmask = (1u << (hb - shift)) - 1u;
-        hist[threadIdx.x] = 0;
-        __syncthreads();
-        const uint64_t pre = (uint64_t)prefix >> hb;
-        for (int64_t e = lo + threadIdx.x; e < hi; e += kNT) {
-            uint32_t k = keys[e];
-            if (((uint64_t)k >> hb) == pre) atomicAdd(&hist[(k >> shift) & wmask], 1u);
-        }
-        __syncthreads();
-        const uint32_t cnt = hist[threadIdx.x];
-        uint32_t tot;
-        const uint32_t ex = block_excl_scan<kNT>(cnt, lds, &tot);
-        if (cnt > 0 && ex <= r && r < ex + cnt) {
-            sel[0] = prefix | ((uint32_t)threadIdx.x << shift);
-            sel[1] = r - ex;
-        }
-        __syncthreads();
-        prefix = sel[0];
-        r = sel[1];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) split_level[j] = key_to_coord(prefix, fl);
-    uint32_t run_lt = 0, run_eq = 0;
-    for (int64_t base = lo; base < hi; base += kNT)
-        partition_tile(in, in_idx, out, out_idx, d, c, n, base, hi, lo, mid, hi, prefix, r,
-                       run_lt, run_eq, lds);
+    split_rank_pos(n, l, j, &lo, &hi, &mid);
+    block_node_split(in, in_idx, out, out_idx, d, c, n, lo, hi, mid, prefix0, sb,
+                     &split_level[j], fl != 0, sh);
 }
 
 // ---------------------------------------------------------------------------
 // Bottom levels: one workgroup per subtree, in LDS.
 // ---------------------------------------------------------------------------
-
-// One wave selects the rank-r key of node [lo, hi) (local positions, order
-// given by pin) and writes the stable partition into pout.  Returns the
-// split key.  mid == hi (right child empty) splits at the largest key and
-// sends everything left.
-__device__ uint32_t wave_select_partition(const uint32_t* keys, const uint16_t* pin,
-                                          uint16_t* pout, int lo, int hi, int mid) {
-    const int lane = lane_id();
-    const bool right_empty = mid >= hi;
-    uint32_t r = (uint32_t)((right_empty ? hi - 1 : mid) - lo);
-    uint32_t mn = 0xffffffffu, mx = 0;
-    for (int e = lo + lane; e < hi; e += kWave) {
-        uint32_t k = keys[pin[e]];
-        mn = k < mn ? k : mn;
-        mx = k > mx ? k : mx;
-    }
-    mn = wave_min_u32(mn);
-    mx = wave_max_u32(mx);
-    uint32_t prefix = mn;
-    if (mn != mx) {
-        const int hb = 31 - __clz(mn ^ mx);
-        prefix = hb == 31 ? 0u : (mn & ~((2u << hb) - 1u));
-        for (int b = hb; b >= 0; --b) {
-            const uint32_t want = (prefix >> b) >> 1;
-            uint32_t cnt0 = 0;
-            for (int e0 = lo; e0 < hi; e0 += kWave) {
-                const int e = e0 + lane;
-                bool p = false;
-                if (e < hi) {
-                    const uint32_t k = keys[pin[e]];
-                    p = ((k >> b) >> 1) == want && !((k >> b) & 1u);
-                }
-                cnt0 += (uint32_t)__popcll(ballot(p));
-            }
-            if (r >= cnt0) {
-                prefix |= 1u << b;
-                r -= cnt0;
-            }
-        }
-    }
-    const uint32_t v = prefix;
-    const uint32_t teq = right_empty ? 0xffffffffu : r;
-    uint32_t run_lt = 0, run_eq = 0;
-    for (int e0 = lo; e0 < hi; e0 += kWave) {
-        const int e = e0 + lane;
-        const bool valid = e < hi;
-        const uint16_t p = valid ? pin[e] : (uint16_t)0;
-        const uint32_t k = valid ? keys[p] : 0u;
-        const bool lt = valid && k < v;
-        const bool eq = valid && k == v;
-        const uint64_t mlt = ballot(lt), meq = ballot(eq);
-        const uint32_t ltb = run_lt + lane_prefix(mlt);
-        const uint32_t eqb = run_eq + lane_prefix(meq);
-        if (valid) {
-            const uint32_t el = eqb < teq ? eqb : teq;
-            int dest;
-            if (lt) dest = lo + (int)(ltb + el);
-            else if (eq && eqb < teq) dest = lo + (int)(ltb + eqb);
-            else dest = mid + (e - lo) - (int)(ltb + el);
-            if (dest >= lo && dest < hi) pout[dest] = p;  // always true for a consistent split
-        }
-        run_lt += (uint32_t)__popcll(mlt);
-        run_eq += (uint32_t)__popcll(meq);
-    }
-    return v;
-}
 
 __global__ void __launch_bounds__(kNT)
 subtree_kernel(const uint32_t* __restrict__ in, const int32_t* __restrict__ in_idx, int64_t n,
@@ -385,62 +257,7 @@ subtree_kernel(const uint32_t* __restrict__ in, const int32_t* __restrict__ in_i
                int32_t* __restrict__ out_idx, uint32_t* __restrict__ split,
                uint32_t* __restrict__ bbox) {
     extern __shared__ uint32_t sm[];
-    uint32_t* skeys = sm;                                    // [d][S]
-    int32_t* sidx = (int32_t*)(sm + (size_t)d * S);          // [S]
-    uint16_t* pa = (uint16_t*)(sidx + S);                    // [S]
-    uint16_t* pb = pa + S;                                   // [S]
-    const int64_t j0 = blockIdx.x;
-    const int64_t base = node_start(n, ls, j0);
-    const int s = (int)(node_start(n, ls, j0 + 1) - base);
-    for (int e = threadIdx.x; e < s; e += kNT) {
-        for (int c = 0; c < d; c++) skeys[c * S + e] = in[(int64_t)c * n + base + e];
-        sidx[e] = in_idx[base + e];
-        pa[e] = (uint16_t)e;
-    }
-    __syncthreads();
-    const int w = threadIdx.x / kWave;
-    constexpr int NW = kNT / kWave;
-    uint16_t* pin = pa;
-    uint16_t* pout = pb;
-    for (int t = 0; t < L - ls; t++) {
-        const int l = ls + t;
-        const int c = l % d;
-        const int nodes = 1 << t;
-        for (int u = w; u < nodes; u += NW) {
-            const int64_t jj = (j0 << t) + u;
-            const int lo = (int)(node_start(n, l, jj) - base);
-            const int hi = (int)(node_start(n, l, jj + 1) - base);
-            const int mid = (int)(node_start(n, l + 1, 2 * jj + 1) - base);
-            const uint32_t v = wave_select_partition(skeys + c * S, pin, pout, lo, hi, mid);
-            if (lane_id() == 0) split[((int64_t)1 << l) + jj] = key_to_coord(v, fl);
-        }
-        __syncthreads();
-        uint16_t* tmp = pin;
-        pin = pout;
-        pout = tmp;
-    }
-    for (int e = threadIdx.x; e < s; e += kNT) {
-        const int p = pin[e];
-        for (int c = 0; c < d; c++)
-            out_pts[(int64_t)c * n + base + e] = key_to_coord(skeys[c * S + p], fl);
-        out_idx[base + e] = sidx[p];
-    }
-    const int nl = 1 << (L - ls);
-    for (int q = threadIdx.x; q < nl * d; q += kNT) {
-        const int leafl = q / d, c = q % d;
-        const int64_t jj = (j0 << (L - ls)) + leafl;
-        const int llo = (int)(node_start(n, L, jj) - base);
-        const int lhi = (int)(node_start(n, L, jj + 1) - base);
-        uint32_t mn = 0xffffffffu, mx = 0;
-        for (int e = llo; e < lhi; e++) {
-            const uint32_t k = skeys[c * S + pin[e]];
-            mn = k < mn ? k : mn;
-            mx = k > mx ? k : mx;
-        }
-        if (llo == lhi) mn = mx = 0x80000000u;  // empty leaf (leaf size 1 only)
-        bbox[jj * 2 * d + c] = key_to_coord(mn, fl);
-        bbox[jj * 2 * d + d + c] = key_to_coord(mx, fl);
-    }
+    block_subtree(in, in_idx, n, d, L, ls, blockIdx.x, S, fl != 0, out_pts, out_idx, split, bbox, sm);
 }
 
 }  // namespace
@@ -550,7 +367,7 @@ pg_status build_from_keys(uint32_t* kA, int32_t* iA, uint32_t* kB, int32_t* iB, 
         std::swap(cur_i, oth_i);
     }
 
-    const size_t lds = (size_t)d * S * 4 + (size_t)S * 4 + (size_t)S * 4;
+    const size_t lds = subtree_lds_bytes(d, S);
     hipLaunchKernelGGL(subtree_kernel, dim3((unsigned)((int64_t)1 << ls)), dim3(kNT), lds, s,
                        cur_k, cur_i, n, d, L, ls, S, ifl, T->pts, T->pidx, T->split, T->bbox);
     PG_LAUNCH_CHECK();

@@ -1,0 +1,211 @@
+"""GPU parity of the batched-clouds form (one persistent launch) and of the
+differentiable k-NN backward, against the CPU oracle (FP64) and against the
+per-cloud static path."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle.grad import fd_self, grad_closed_form
+from paper_2207_01834_amd import datagen
+from parity import assert_float_close, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pg(dev):
+    import paper_2207_01834_amd._binding as b
+    b.lib()
+    return b
+
+
+def to_dev(a, dev):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def host(*ts):
+    import torch
+    torch.cuda.synchronize()
+    return [t.cpu().numpy() for t in ts]
+
+
+def small_clouds(seed, C=150, hi=3000):
+    g = np.random.default_rng(seed)
+    sizes = np.floor(np.exp(g.uniform(0, np.log(hi), size=C))).astype(np.int64)
+    sizes[:6] = [0, 1, 2, 15, 16, 17]  # empty, single, fewer than k, around the leaf size
+    pts, offs = datagen.sphere_clouds(sizes, seed)
+    return pts, offs
+
+
+def per_cloud_static(pg, dev, pts, offs, k):
+    """The plain per-cloud method: one static build + all-points k-NN each."""
+    N = len(pts)
+    gi = np.full((N, k), -1, np.int64)
+    gd = np.full((N, k), np.inf, np.float64)
+    for c in range(len(offs) - 1):
+        a, b = int(offs[c]), int(offs[c + 1])
+        if b == a:
+            continue
+        t = pg.kdtree_build(to_dev(pts[a:b], dev), leaf=16)
+        i, d = host(*t.knn_all(k))
+        gi[a:b] = np.where(i >= 0, i.astype(np.int64) + a, -1)
+        gd[a:b] = d
+    return gi, gd
+
+
+def oracle_per_cloud(pts, offs, k, rows=None):
+    """FP64 definition within each cloud; ids are global rows."""
+    N = len(pts)
+    cl = np.searchsorted(offs, np.arange(N), side="right") - 1
+    rows = np.arange(N) if rows is None else rows
+    oi = np.empty((len(rows), k), np.int64)
+    od = np.empty((len(rows), k), np.float64)
+    for c in np.unique(cl[rows]):
+        a, b = int(offs[c]), int(offs[c + 1])
+        sel = np.nonzero(cl[rows] == c)[0]
+        ids, dist = oracle.knn_brute(pts[a:b], pts[rows[sel]], k, nthreads=8)
+        oi[sel] = np.where(ids >= 0, ids + a, -1)
+        od[sel] = dist
+    return oi, od
+
+
+def test_batched_matches_oracle_and_static(pg, dev):
+    pts, offs = small_clouds(11)
+    k = 16
+    B = pg.BatchKnn(offs, 3, device=dev)
+    gi, gd = host(*B.knn_self(to_dev(pts, dev), k))
+    assert not B.timed_out()
+    oi, od = oracle_per_cloud(pts, offs, k)
+    assert_float_close(gi, gd, oi, od, pts, pts)
+    # bitwise identical to the per-cloud static method (same fp32 arithmetic)
+    si, sd = per_cloud_static(pg, dev, pts, offs, k)
+    assert np.array_equal(gi.astype(np.int64), si)
+    assert np.array_equal(gd.astype(np.float64), sd)
+
+
+def test_batched_tuning_invariance(pg, dev):
+    pts, offs = small_clouds(12, C=60, hi=9000)
+    ref = None
+    for leaf in (8, 16, 32):
+        for bpc in (1, 2, 4):
+            say(f"tune leaf={leaf} bpc={bpc}")
+            B = pg.BatchKnn(offs, 3, leaf=leaf, blocks_per_cu=bpc, device=dev)
+            out = host(*B.knn_self(to_dev(pts, dev), 10))
+            if ref is None:
+                ref = out
+            assert np.array_equal(out[0], ref[0]) and np.array_equal(out[1], ref[1])
+    t = pg.batch_autotune(to_dev(pts, dev), offs, 10)
+    assert t["leaf"] in (8, 16, 32) and t["blocks_per_cu"] in (2, 4)
+
+
+def test_batched_other_dims_and_k(pg, dev):
+    g = np.random.default_rng(13)
+    for d, k in ((2, 1), (5, 7), (8, 33)):
+        sizes = g.integers(0, 2500, size=40)
+        offs = np.zeros(41, np.int64)
+        offs[1:] = np.cumsum(sizes)
+        pts = (g.standard_normal((int(offs[-1]), d))).astype(np.float32)
+        B = pg.BatchKnn(offs, d, device=dev)
+        gi, gd = host(*B.knn_self(to_dev(pts, dev), k))
+        oi, od = oracle_per_cloud(pts, offs, k)
+        assert_float_close(gi, gd, oi, od, pts, pts)
+
+
+def test_batched_graph_capture_replays(pg, dev):
+    import torch
+    pts, offs = small_clouds(14, C=80)
+    k = 8
+    x = to_dev(pts, dev)
+    B = pg.BatchKnn(offs, 3, device=dev)
+    eager = host(*B.knn_self(x, k))
+    idx = torch.empty((len(pts), k), dtype=torch.int32, device=dev)
+    d2 = torch.empty((len(pts), k), dtype=torch.float32, device=dev)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        B.knn_self(x, k, out=(idx, d2))  # warm on the capture stream
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        B.knn_self(x, k, out=(idx, d2))
+    for rep in range(3):
+        idx.fill_(-7)
+        d2.fill_(-1.0)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        got = host(idx, d2)
+        assert np.array_equal(got[0], eager[0]) and np.array_equal(got[1], eager[1]), rep
+        _ = (x * 2).sum().item()  # eager work between replays
+
+
+def test_cfg4_full_size_sampled(pg, dev):
+    """4,096 clouds, sizes log-uniform in [256, 65536], k = 16, one launch."""
+    sizes = datagen.cloud_sizes(4096, seed=4)
+    pts, offs = datagen.sphere_clouds(sizes, seed=44)
+    say(f"cfg4: {len(pts)} points")
+    x = to_dev(pts, dev)
+    B = pg.BatchKnn(offs, 3, device=dev)
+    gi, gd = host(*B.knn_self(x, 16))
+    assert not B.timed_out()
+    rows = np.random.default_rng(0).choice(len(pts), 300, replace=False)
+    oi, od = oracle_per_cloud(pts, offs, 16, rows=rows)
+    assert_float_close(gi[rows], gd[rows], oi, od, pts, pts[rows])
+    assert (gi[:, 0] >= 0).all()
+
+
+def test_backward_fd_and_closed_form(pg, dev):
+    """Autograd of sum g * kNN d2 on 64 clouds of 256 points (k = 16) against
+    FP64 central differences (away from ties) and the FP64 closed form with
+    the GPU's neighbour sets."""
+    import torch
+
+    from paper_2207_01834_amd.diff import knn_sqdist
+    sizes = np.full(64, 256, dtype=np.int64)
+    pts, offs = datagen.sphere_clouds(sizes, seed=404)
+    k = 16
+    G = np.random.default_rng(1).standard_normal((len(pts), k)).astype(np.float32)
+    x = to_dev(pts, dev).requires_grad_(True)
+    d2, idx = knn_sqdist(x, k, offsets=offs)
+    (d2 * to_dev(G, dev)).sum().backward()
+    grad = host(x.grad)[0].astype(np.float64)
+    idx_h = host(idx)[0].astype(np.int64)
+    # closed form (FP64) with the GPU's neighbour sets, both roles
+    gq, gx = grad_closed_form(pts, pts, idx_h, G)
+    cf = gq + gx
+    scale = np.abs(cf).max()
+    assert np.all(np.abs(grad - cf) <= 1e-4 * np.abs(cf) + 1e-4 * scale)
+    # FP64 central differences on the first 2 clouds
+    for c in range(2):
+        a, b = int(offs[c]), int(offs[c + 1])
+        fd, stable = fd_self(pts[a:b].astype(np.float64), k, G[a:b].astype(np.float64), h=1e-6)
+        sub = grad[a:b]
+        assert stable.mean() > 0.8
+        err = np.abs(sub - fd)[stable]
+        assert np.all(err <= 1e-4 * np.abs(fd)[stable] + 1e-4 * np.abs(fd).max()), err.max()
+    # deterministic: a second backward gives identical bits
+    x2 = to_dev(pts, dev).requires_grad_(True)
+    d2b, _ = knn_sqdist(x2, k, offsets=offs)
+    (d2b * to_dev(G, dev)).sum().backward()
+    assert np.array_equal(host(x2.grad)[0], host(x.grad)[0])
+
+
+def test_backward_query_form(pg, dev):
+    import torch
+
+    from paper_2207_01834_amd.diff import knn_sqdist
+    g = np.random.default_rng(2)
+    X = g.random((3000, 3)).astype(np.float32)
+    Q = g.random((500, 3)).astype(np.float32)
+    k = 6
+    x = to_dev(X, dev).requires_grad_(True)
+    q = to_dev(Q, dev).requires_grad_(True)
+    d2, idx = knn_sqdist(x, k, queries=q)
+    W = g.standard_normal((500, k)).astype(np.float32)
+    (d2 * to_dev(W, dev)).sum().backward()
+    gq_ref, gx_ref = grad_closed_form(Q, X, host(idx)[0].astype(np.int64), W)
+    for got, ref in ((host(q.grad)[0], gq_ref), (host(x.grad)[0], gx_ref)):
+        scale = np.abs(ref).max()
+        assert np.all(np.abs(got - ref) <= 1e-4 * np.abs(ref) + 1e-4 * scale)
