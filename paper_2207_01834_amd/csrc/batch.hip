@@ -67,6 +67,7 @@ struct BatchParams {
     int32_t* pidx2;          // [N] scratch
     uint32_t* split;         // split pool
     uint32_t* bbox;          // box pool
+    uint32_t* rec;           // [N][rw] packed leaf records
     int64_t total_items;
     int32_t C, d, k, S;
 };
@@ -119,7 +120,8 @@ __device__ inline void build_cloud(const BatchParams& P, int c, uint32_t* sm) {
             int32_t* ti = cur_i; cur_i = oth_i; oth_i = ti;
         }
         for (int64_t j0 = 0; j0 < ((int64_t)1 << D.ls); j0++)
-            block_subtree(cur, cur_i, n, d, D.L, D.ls, j0, P.S, true, outp, oidx, split, bbox, sm);
+            block_subtree(cur, cur_i, n, d, D.L, D.ls, j0, P.S, true, outp, oidx, split, bbox,
+                          P.rec + D.row * record_words(d), sm);
     }
     __threadfence();
     __syncthreads();
@@ -127,7 +129,7 @@ __device__ inline void build_cloud(const BatchParams& P, int c, uint32_t* sm) {
         __hip_atomic_store(&P.ready[c], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-template <int MD, int KT>
+template <int MD, int KT, bool EX>
 __device__ inline void query_item(const BatchParams& P, int64_t q, int* s_ok) {
     // item -> position t in the size order (binary search over qstart)
     int lo = 0, hi = P.C;  // qstart[lo] <= q < qstart[hi]
@@ -160,26 +162,27 @@ __device__ inline void query_item(const BatchParams& P, int64_t q, int* s_ok) {
     const int64_t i = blk * kQB + threadIdx.x;
     if (i >= D.n) return;
     const int d = P.d, k = P.k;
-    const TreeView tv{D.n, d, D.L, P.pts + D.pts, P.pidx + D.row, P.split + D.split,
-                      P.bbox + D.bbox};
+    const TreeView tv{D.n, d, D.L, record_words(d), P.pts + D.pts, P.pidx + D.row,
+                      P.split + D.split, P.bbox + D.bbox, P.rec + D.row * record_words(d)};
     using M = Metric<float>;
     float q_[MD];
 #pragma unroll
     for (int cc = 0; cc < MD; cc++) q_[cc] = cc < d ? M::load(tv.pts[(int64_t)cc * D.n + i]) : 0.0f;
-    KList<float, int32_t, KT> kl;
-    kl.init(k, M::inf(), INT32_MAX);
-    kd_search<float, MD, KT, int32_t>(tv, PlainIds{tv.pidx}, q_, d, kl, k);
+    KList<float, int32_t, KT, EX> kl;
+    kl.init(M::inf(), INT32_MAX);
+    kd_search<float, MD, KT, EX, int32_t>(tv, PlainIds{}, q_, d, kl, k,
+                                          (1u << D.L) + leaf_of(D.n, D.L, i));
     const int64_t row = D.row + tv.pidx[i];
 #pragma unroll
     for (int s = 0; s < KT; s++) {
-        if (s < k) {
+        if (EX || s < k) {
             P.out_idx[row * k + s] = kl.id[s] == INT32_MAX ? -1 : (int32_t)(D.row + kl.id[s]);
             P.out_d2[row * k + s] = kl.d[s];
         }
     }
 }
 
-template <int MD, int KT>
+template <int MD, int KT, bool EX>
 __global__ void __launch_bounds__(kNT) batch_kernel(BatchParams P) {
     extern __shared__ uint32_t sm[];
     __shared__ int s_item;
@@ -191,7 +194,7 @@ __global__ void __launch_bounds__(kNT) batch_kernel(BatchParams P) {
         __syncthreads();
         if (it >= P.total_items) break;
         if (it < P.C) build_cloud(P, P.order[it], sm);
-        else query_item<MD, KT>(P, it - P.C, &s_ok);
+        else query_item<MD, KT, EX>(P, it - P.C, &s_ok);
         __syncthreads();
     }
 }
@@ -280,7 +283,7 @@ struct BatchPlan {
     // workspace carve-up
     size_t bytes = 0;
     size_t o_queue = 0, o_ready = 0, o_order = 0, o_qstart = 0, o_desc = 0, o_pts = 0,
-           o_keys = 0, o_pidx = 0, o_pidx2 = 0, o_split = 0, o_bbox = 0;
+           o_keys = 0, o_pidx = 0, o_pidx2 = 0, o_split = 0, o_bbox = 0, o_rec = 0;
     std::vector<int32_t> order;
     std::vector<int64_t> qstart;
     std::vector<CloudDesc> desc;
@@ -342,6 +345,7 @@ static pg_status make_plan(const int64_t* offs, int C, int d, int leaf, int bpc,
     P.o_pidx2 = o; o = align256(o + 4 * (size_t)(P.N > 0 ? P.N : 1));
     P.o_split = o; o = align256(o + 4 * (size_t)(split > 0 ? split : 1));
     P.o_bbox = o; o = align256(o + 4 * (size_t)(bbox > 0 ? bbox : 1));
+    P.o_rec = o; o = align256(o + 4 * (size_t)record_words(d) * (size_t)(P.N > 0 ? P.N : 1));
     P.bytes = o;
     return PG_OK;
 }
@@ -359,13 +363,13 @@ struct pg_batch {
 namespace pg {
 namespace {
 
-template <int MD, int KT>
+template <int MD, int KT, bool EX>
 pg_status launch_batch(pg_batch* b, const BatchParams& P, hipStream_t s) {
     const size_t lds = subtree_lds_bytes(P.d, P.S);
     const unsigned grid = (unsigned)(b->num_cu * b->plan.bpc);
     hipLaunchKernelGGL(batch_reset_kernel, dim3(8), dim3(kNT), 0, s, P.queue, P.ready, P.C);
     PG_LAUNCH_CHECK();
-    hipLaunchKernelGGL((batch_kernel<MD, KT>), dim3(grid), dim3(kNT), lds, s, P);
+    hipLaunchKernelGGL((batch_kernel<MD, KT, EX>), dim3(grid), dim3(kNT), lds, s, P);
     PG_LAUNCH_CHECK();
     return PG_OK;
 }
@@ -373,12 +377,15 @@ pg_status launch_batch(pg_batch* b, const BatchParams& P, hipStream_t s) {
 template <int MD>
 pg_status batch_k(pg_batch* b, const BatchParams& P, hipStream_t s) {
     const int k = P.k;
-    if (k <= 2) return launch_batch<MD, 2>(b, P, s);
-    if (k <= 4) return launch_batch<MD, 4>(b, P, s);
-    if (k <= 8) return launch_batch<MD, 8>(b, P, s);
-    if (k <= 16) return launch_batch<MD, 16>(b, P, s);
-    if (k <= 32) return launch_batch<MD, 32>(b, P, s);
-    return launch_batch<MD, 64>(b, P, s);
+    if (k == 5) return launch_batch<MD, 5, true>(b, P, s);
+    if (k == 10) return launch_batch<MD, 10, true>(b, P, s);
+    if (k == 16) return launch_batch<MD, 16, true>(b, P, s);
+    if (k <= 2) return launch_batch<MD, 2, false>(b, P, s);
+    if (k <= 4) return launch_batch<MD, 4, false>(b, P, s);
+    if (k <= 8) return launch_batch<MD, 8, false>(b, P, s);
+    if (k <= 16) return launch_batch<MD, 16, false>(b, P, s);
+    if (k <= 32) return launch_batch<MD, 32, false>(b, P, s);
+    return launch_batch<MD, 64, false>(b, P, s);
 }
 
 std::mutex g_tune_mu;
@@ -474,6 +481,7 @@ pg_status pg_batch_knn_self(pg_batch* b, const float* points, int32_t k, int32_t
     P.pidx2 = (int32_t*)(b->ws + PL.o_pidx2);
     P.split = (uint32_t*)(b->ws + PL.o_split);
     P.bbox = (uint32_t*)(b->ws + PL.o_bbox);
+    P.rec = (uint32_t*)(b->ws + PL.o_rec);
     P.total_items = PL.total_items;
     P.C = PL.C;
     P.d = PL.d;

@@ -58,7 +58,7 @@ constexpr int kNT = 256;
 struct BdlIds {
     const int64_t* ids;
     const uint32_t* alive;
-    __device__ inline int64_t id(int64_t i) const { return ids[i]; }
+    __device__ inline int64_t id(int64_t i, uint32_t) const { return ids[i]; }
     __device__ inline bool live(int64_t i) const { return (alive[i >> 5] >> (i & 31)) & 1u; }
 };
 
@@ -159,23 +159,23 @@ erase_kernel(Forest f, const uint32_t* __restrict__ pts, int64_t m, int d,
     if (hits) atomicAdd(&erased[slot], (unsigned long long)hits);
 }
 
-template <typename T, int MD, int KT>
+template <typename T, int MD, int KT, bool EX>
 __global__ void __launch_bounds__(kNT)
 bdl_knn_kernel(Forest f, const uint32_t* __restrict__ queries, int64_t m, int d, int k,
                int64_t* __restrict__ out_id, typename Metric<T>::D* __restrict__ out_dist) {
     using M = Metric<T>;
-    const int64_t qi = (int64_t)blockIdx.x * kNT + threadIdx.x;
+    const int64_t qi = xcd_block() * kNT + threadIdx.x;
     if (qi >= m) return;
     T q[MD];
 #pragma unroll
     for (int c = 0; c < MD; c++) q[c] = M::load(c < d ? queries[qi * d + c] : 0u);
-    KList<typename M::D, int64_t, KT> kl;
-    kl.init(k, M::inf(), INT64_MAX);
+    KList<typename M::D, int64_t, KT, EX> kl;
+    kl.init(M::inf(), INT64_MAX);
     for (int t = 0; t < f.count; t++)
-        kd_search<T, MD, KT, int64_t>(f.s[t].tv, BdlIds{f.s[t].ids, f.s[t].alive}, q, d, kl, k);
+        kd_search<T, MD, KT, EX, int64_t>(f.s[t].tv, BdlIds{f.s[t].ids, f.s[t].alive}, q, d, kl, k);
 #pragma unroll
     for (int s = 0; s < KT; s++) {
-        if (s < k) {
+        if (EX || s < k) {
             out_id[qi * k + s] = kl.id[s] == INT64_MAX ? -1 : kl.id[s];
             out_dist[qi * k + s] = kl.d[s];
         }
@@ -202,12 +202,12 @@ pg_status erase_d(const Forest& f, const void* pts, int64_t m, int d, unsigned l
     }
 }
 
-template <typename T, int MD, int KT>
+template <typename T, int MD, int KT, bool EX>
 pg_status launch_bdl_knn(const Forest& f, const void* q, int64_t m, int d, int k, int64_t* oi,
                          void* od, hipStream_t s) {
     using DT = typename Metric<T>::D;
-    hipLaunchKernelGGL((bdl_knn_kernel<T, MD, KT>), dim3(cdiv(m, kNT)), dim3(kNT), 0, s, f,
-                       (const uint32_t*)q, m, d, k, oi, (DT*)od);
+    hipLaunchKernelGGL((bdl_knn_kernel<T, MD, KT, EX>), dim3(grid_for_xcd(cdiv(m, kNT))), dim3(kNT),
+                       0, s, f, (const uint32_t*)q, m, d, k, oi, (DT*)od);
     PG_LAUNCH_CHECK();
     return PG_OK;
 }
@@ -215,12 +215,15 @@ pg_status launch_bdl_knn(const Forest& f, const void* q, int64_t m, int d, int k
 template <typename T, int MD>
 pg_status bdl_knn_k(const Forest& f, const void* q, int64_t m, int d, int k, int64_t* oi,
                     void* od, hipStream_t s) {
-    if (k <= 2) return launch_bdl_knn<T, MD, 2>(f, q, m, d, k, oi, od, s);
-    if (k <= 4) return launch_bdl_knn<T, MD, 4>(f, q, m, d, k, oi, od, s);
-    if (k <= 8) return launch_bdl_knn<T, MD, 8>(f, q, m, d, k, oi, od, s);
-    if (k <= 16) return launch_bdl_knn<T, MD, 16>(f, q, m, d, k, oi, od, s);
-    if (k <= 32) return launch_bdl_knn<T, MD, 32>(f, q, m, d, k, oi, od, s);
-    return launch_bdl_knn<T, MD, 64>(f, q, m, d, k, oi, od, s);
+    if (k == 5) return launch_bdl_knn<T, MD, 5, true>(f, q, m, d, k, oi, od, s);
+    if (k == 10) return launch_bdl_knn<T, MD, 10, true>(f, q, m, d, k, oi, od, s);
+    if (k == 16) return launch_bdl_knn<T, MD, 16, true>(f, q, m, d, k, oi, od, s);
+    if (k <= 2) return launch_bdl_knn<T, MD, 2, false>(f, q, m, d, k, oi, od, s);
+    if (k <= 4) return launch_bdl_knn<T, MD, 4, false>(f, q, m, d, k, oi, od, s);
+    if (k <= 8) return launch_bdl_knn<T, MD, 8, false>(f, q, m, d, k, oi, od, s);
+    if (k <= 16) return launch_bdl_knn<T, MD, 16, false>(f, q, m, d, k, oi, od, s);
+    if (k <= 32) return launch_bdl_knn<T, MD, 32, false>(f, q, m, d, k, oi, od, s);
+    return launch_bdl_knn<T, MD, 64, false>(f, q, m, d, k, oi, od, s);
 }
 
 template <typename T>

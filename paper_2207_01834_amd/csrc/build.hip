@@ -255,9 +255,10 @@ __global__ void __launch_bounds__(kNT)
 subtree_kernel(const uint32_t* __restrict__ in, const int32_t* __restrict__ in_idx, int64_t n,
                int d, int L, int ls, int S, int fl, uint32_t* __restrict__ out_pts,
                int32_t* __restrict__ out_idx, uint32_t* __restrict__ split,
-               uint32_t* __restrict__ bbox) {
+               uint32_t* __restrict__ bbox, uint32_t* __restrict__ rec) {
     extern __shared__ uint32_t sm[];
-    block_subtree(in, in_idx, n, d, L, ls, blockIdx.x, S, fl != 0, out_pts, out_idx, split, bbox, sm);
+    block_subtree(in, in_idx, n, d, L, ls, blockIdx.x, S, fl != 0, out_pts, out_idx, split, bbox,
+                  rec, sm);
 }
 
 }  // namespace
@@ -369,7 +370,8 @@ pg_status build_from_keys(uint32_t* kA, int32_t* iA, uint32_t* kB, int32_t* iB, 
 
     const size_t lds = subtree_lds_bytes(d, S);
     hipLaunchKernelGGL(subtree_kernel, dim3((unsigned)((int64_t)1 << ls)), dim3(kNT), lds, s,
-                       cur_k, cur_i, n, d, L, ls, S, ifl, T->pts, T->pidx, T->split, T->bbox);
+                       cur_k, cur_i, n, d, L, ls, S, ifl, T->pts, T->pidx, T->split, T->bbox,
+                       T->rec);
     PG_LAUNCH_CHECK();
     return PG_OK;
 }
@@ -389,6 +391,7 @@ pg_status build_tree(const void* points, int64_t n, int d, int leaf, int dtype, 
     PG_TRY(dalloc(&T->pidx, (size_t)nn, s));
     PG_TRY(dalloc(&T->split, (size_t)nleaves, s));
     PG_TRY(dalloc(&T->bbox, (size_t)nleaves * 2 * d, s));
+    PG_TRY(dalloc(&T->rec, (size_t)nn * record_words(d), s));
     if (n == 0) return PG_OK;
     DevBuf tmpk(s), tmpi(s);
     PG_TRY(tmpk.alloc(sizeof(uint32_t) * (size_t)d * n));

@@ -194,13 +194,15 @@ __host__ __device__ inline size_t subtree_lds_bytes(int d, int S) {
 // One workgroup finishes the subtree rooted at node j0 of level ls (at most S
 // points): loads it into LDS, and a wave per node selects (bitwise radix with
 // ballots) and stable-partitions every node down to the leaves at level L.
-// Writes the coordinates and input rows in leaf order, the split values of
-// the subtree's nodes and its leaves' bounding boxes.  `in` and `out_pts` may
+// Writes the coordinates and input rows in leaf order (as planes and as packed
+// records), the split values of the subtree's nodes and its leaves' bounding
+// boxes.  `in` and `out_pts` may
 // alias (the subtree is read completely before it is written).
 __device__ inline void block_subtree(const uint32_t* in, const int32_t* in_idx, int64_t n, int d,
                                      int L, int ls, int64_t j0, int S, bool fl, uint32_t* out_pts,
                                      int32_t* out_idx, uint32_t* __restrict__ split,
-                                     uint32_t* __restrict__ bbox, uint32_t* sm) {
+                                     uint32_t* __restrict__ bbox, uint32_t* __restrict__ rec,
+                                     uint32_t* sm) {
     uint32_t* skeys = sm;                                    // [d][S]
     int32_t* sidx = (int32_t*)(sm + (size_t)d * S);          // [S]
     uint16_t* pa = (uint16_t*)(sidx + S);                    // [S]
@@ -234,11 +236,18 @@ __device__ inline void block_subtree(const uint32_t* in, const int32_t* in_idx, 
         pin = pout;
         pout = tmp;
     }
+    const int rw = record_words(d);
     for (int e = threadIdx.x; e < s; e += kBuildNT) {
         const int p = pin[e];
-        for (int c = 0; c < d; c++)
-            out_pts[(int64_t)c * n + base + e] = key_to_coord(skeys[c * S + p], fl);
+        uint32_t* r = rec + (base + e) * rw;
+        for (int c = 0; c < d; c++) {
+            const uint32_t v = key_to_coord(skeys[c * S + p], fl);
+            out_pts[(int64_t)c * n + base + e] = v;
+            r[c] = v;
+        }
         out_idx[base + e] = sidx[p];
+        r[d] = (uint32_t)sidx[p];
+        for (int c = d + 1; c < rw; c++) r[c] = 0;
     }
     const int nl = 1 << (L - ls);
     for (int q = threadIdx.x; q < nl * d; q += kBuildNT) {

@@ -92,14 +92,19 @@ __host__ inline int tree_levels(int64_t n, int leaf) {
     return L;
 }
 
+// Words of one packed leaf record: d coordinates, the input row, zero
+// padding to 4, 8 or 16 words (16, 32 or 64 bytes: whole 16-byte loads).
+__host__ __device__ inline int record_words(int d) { return d <= 3 ? 4 : (d <= 7 ? 8 : 16); }
+
 // Device view of a static kd-tree (what the search kernels read).
 struct TreeView {
     int64_t n;
-    int d, L;
+    int d, L, rw;
     const uint32_t* pts;    // [d][n] coordinates in leaf order (SoA planes)
     const int32_t* pidx;    // [n] input row of each leaf-order point
     const uint32_t* split;  // [2^L] split coordinate of heap node h (h >= 1)
     const uint32_t* bbox;   // [2^L][2d] per leaf: min[d], max[d] coordinates
+    const uint32_t* rec;    // [n][rw] leaf-order records: coordinates, row, 0...
 };
 
 inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
@@ -115,7 +120,8 @@ struct pg_tree {
     int32_t* pidx = nullptr;
     uint32_t* split = nullptr;
     uint32_t* bbox = nullptr;
+    uint32_t* rec = nullptr;
     pg::TreeView view() const {
-        return pg::TreeView{n, d, L, pts, pidx, split, bbox};
+        return pg::TreeView{n, d, L, pg::record_words(d), pts, pidx, split, bbox, rec};
     }
 };

@@ -50,15 +50,16 @@ template <> struct Metric<float> {
 };
 
 // Sorted list of the k best (distance, id) keys held in registers.  KT is a
-// compile-time capacity >= k; slots >= k are never touched (uniform guards).
-template <typename DT, typename IT, int KT>
+// compile-time capacity >= k; with EX the list length is exactly KT (= k),
+// otherwise slots >= k are never touched (uniform guards).
+template <typename DT, typename IT, int KT, bool EX>
 struct KList {
     DT d[KT];
     IT id[KT];
     DT kd;   // distance of slot k-1 (the pruning radius, squared)
     IT kid;  // id of slot k-1
 
-    __device__ inline void init(int k, DT inf, IT none) {
+    __device__ inline void init(DT inf, IT none) {
 #pragma unroll
         for (int s = 0; s < KT; s++) {
             d[s] = inf;
@@ -66,7 +67,6 @@ struct KList {
         }
         kd = inf;
         kid = none;
-        (void)k;
     }
     __device__ static inline bool less(DT a, IT ai, DT b, IT bi) {
         return a < b || (a == b && ai < bi);
@@ -81,14 +81,14 @@ struct KList {
         bool before_cur = true;  // new key sorts before the old key of slot s
 #pragma unroll
         for (int s = KT - 1; s >= 0; --s) {
-            if (s < k) {
+            if (EX || s < k) {
                 const int p = s > 0 ? s - 1 : 0;
                 const bool before_prev = s > 0 && less(dd, ii, d[p], id[p]);
                 const DT nd = before_prev ? d[p] : (before_cur ? dd : d[s]);
                 const IT ni = before_prev ? id[p] : (before_cur ? ii : id[s]);
                 d[s] = nd;
                 id[s] = ni;
-                if (s == k - 1) {
+                if (EX ? s == KT - 1 : s == k - 1) {
                     kd = nd;
                     kid = ni;
                 }

@@ -10,8 +10,16 @@
 //     child it enters the other child unless the squared distance to the
 //     split plane exceeds the current k-th distance (strict, so equal keys
 //     with smaller ids are still found); otherwise it returns to the parent;
+//   * when the query is a point of the tree (all-points mode) the walk starts
+//     at the leaf holding it: on the way up, the child it came from along that
+//     path counts as the first-visited child (the split-plane bound is valid
+//     for the other child whichever side the query lies on, since a point on
+//     the wrong side can only lie on the plane);
 //   * a leaf is scanned only when the squared distance from the query to the
 //     leaf's bounding box does not exceed the current k-th distance;
+//   * leaf points are read as packed records (coordinates + row: one 16-byte
+//     load for d <= 3), the next record is requested before the current one
+//     is used;
 //   * candidates go into a register-resident sorted k-list (KList).
 #pragma once
 
@@ -27,35 +35,81 @@ __device__ inline T pick(const T (&q)[MD], int dim) {
     return r;
 }
 
+// Coordinates and the row word of leaf-order record i.  MD <= 3 and
+// MD in 4..7 use compile-time record widths 4 and 8; MD == 8 reads a record
+// of tv.rw words for the runtime dimension d.
+template <typename T, int MD>
+__device__ inline void load_point(const TreeView& tv, int64_t i, int d, T (&p)[MD], uint32_t& idw) {
+    using M = Metric<T>;
+    if constexpr (MD <= 3) {
+        const uint4 r = reinterpret_cast<const uint4*>(tv.rec)[i];
+        const uint32_t w[4] = {r.x, r.y, r.z, r.w};
+#pragma unroll
+        for (int c = 0; c < MD; c++) p[c] = M::load(w[c]);
+        idw = w[MD];
+    } else if constexpr (MD <= 7) {
+        const uint4* b = reinterpret_cast<const uint4*>(tv.rec) + i * 2;
+        const uint4 r0 = b[0], r1 = b[1];
+        const uint32_t w[8] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w};
+#pragma unroll
+        for (int c = 0; c < MD; c++) p[c] = M::load(w[c]);
+        idw = w[MD];
+    } else {
+        const uint32_t* r = tv.rec + i * tv.rw;
+#pragma unroll
+        for (int c = 0; c < MD; c++) p[c] = c < d ? M::load(r[c]) : T(0);
+        idw = r[d];
+    }
+}
+
 // Points of leaf-order position i: id and liveness.
 struct PlainIds {
-    const int32_t* pidx;
-    __device__ inline int32_t id(int64_t i) const { return pidx[i]; }
+    __device__ inline int32_t id(int64_t, uint32_t idw) const { return (int32_t)idw; }
     __device__ inline bool live(int64_t) const { return true; }
 };
 
-template <typename T, int MD, int KT, typename IT, typename Ids>
+// Leaf j of a tree with n points at depth L that holds leaf-order position i.
+__device__ inline uint32_t leaf_of(int64_t n, int L, int64_t i) {
+    return (uint32_t)((((uint64_t)(i + 1) << L) - 1) / (uint64_t)n);
+}
+
+// k-NN walk of one query.  start: 0 = from the root; otherwise the heap index
+// of the leaf holding the query (all-points mode).
+template <typename T, int MD, int KT, bool EX, typename IT, typename Ids>
 __device__ inline void kd_search(const TreeView& tv, const Ids& ids, const T (&q)[MD], int d,
-                                 KList<typename Metric<T>::D, IT, KT>& kl, int k) {
+                                 KList<typename Metric<T>::D, IT, KT, EX>& kl, int k,
+                                 uint32_t start = 0) {
     using M = Metric<T>;
     using DT = typename M::D;
     const int64_t n = tv.n;
     if (n == 0) return;
     const int L = tv.L;
     const uint32_t first_leaf = 1u << L;
-    uint32_t cur = 1, prev = 0;
-    int dim = 0;
+    const bool self = start != 0;
+    uint32_t cur = self ? start : 1u, prev = 0;
+    int lvl = self ? L : 0;
+    int dim = lvl % d;
     while (cur != 0) {
         while (cur != 0 && cur < first_leaf) {
             const T s = M::load(tv.split[cur]);
             const T qd = pick<MD>(q, dim);
             const uint32_t nearc = 2u * cur + (qd >= s ? 1u : 0u);
             uint32_t next;
-            if (prev == (cur >> 1)) next = nearc;
-            else if (prev == nearc && !(M::sq(qd, s) > kl.kd)) next = nearc ^ 1u;
-            else next = cur >> 1;
-            if (next > cur) dim = (dim + 1 == d) ? 0 : dim + 1;
-            else dim = (dim == 0) ? d - 1 : dim - 1;
+            if (prev == (cur >> 1) && !(self && (start >> (L - lvl)) == cur)) {
+                next = nearc;
+            } else {
+                uint32_t first = nearc;
+                if (self && (start >> (L - lvl)) == cur) first = start >> (L - lvl - 1);
+                if (prev == first && !(M::sq(qd, s) > kl.kd)) next = first ^ 1u;
+                else next = cur >> 1;
+            }
+            if (next > cur) {
+                lvl++;
+                dim = (dim + 1 == d) ? 0 : dim + 1;
+            } else {
+                lvl--;
+                dim = (dim == 0) ? d - 1 : dim - 1;
+            }
             prev = cur;
             cur = next;
         }
@@ -65,23 +119,46 @@ __device__ inline void kd_search(const TreeView& tv, const Ids& ids, const T (&q
         DT lb = 0;
 #pragma unroll
         for (int c = 0; c < MD; c++)
-            if (c < d) lb = M::acc_gap(lb, q[c], M::load(bb[c]), M::load(bb[d + c]));
+            if (MD < 8 || c < d) lb = M::acc_gap(lb, q[c], M::load(bb[c]), M::load(bb[d + c]));
         if (!(lb > kl.kd)) {
             const int64_t lo = node_start(n, L, leaf), hi = node_start(n, L, leaf + 1);
+            T p[MD];
+            uint32_t idw = 0;
+            if (lo < hi) load_point<T, MD>(tv, lo, d, p, idw);
             for (int64_t i = lo; i < hi; i++) {
-                if (!ids.live(i)) continue;
-                DT dd = 0;
+                T pn[MD];
+                uint32_t idn = 0;
 #pragma unroll
-                for (int c = 0; c < MD; c++)
-                    if (c < d) dd = M::acc(dd, q[c], M::load(tv.pts[(int64_t)c * n + i]));
-                const IT id = ids.id(i);
-                if (kl.admits(dd, id)) kl.insert(dd, id, k);
+                for (int c = 0; c < MD; c++) pn[c] = p[c];
+                if (i + 1 < hi) load_point<T, MD>(tv, i + 1, d, pn, idn);
+                if (ids.live(i)) {
+                    DT dd = 0;
+#pragma unroll
+                    for (int c = 0; c < MD; c++)
+                        if (MD < 8 || c < d) dd = M::acc(dd, q[c], p[c]);
+                    const IT id = ids.id(i, idw);
+                    if (kl.admits(dd, id)) kl.insert(dd, id, k);
+                }
+#pragma unroll
+                for (int c = 0; c < MD; c++) p[c] = pn[c];
+                idw = idn;
             }
         }
         prev = cur;
         cur >>= 1;
+        lvl--;
         dim = (dim == 0) ? d - 1 : dim - 1;
     }
 }
+
+// Workgroup index for a grid whose size is a multiple of 8: consecutive
+// workgroups are dealt round-robin to the 8 XCDs, so hand each XCD one
+// contiguous eighth of the work (its L2 then holds one region of the tree).
+__device__ inline int64_t xcd_block() {
+    const int64_t per = gridDim.x / 8;
+    return (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+}
+
+inline unsigned grid_for_xcd(int64_t blocks) { return (unsigned)((blocks + 7) / 8 * 8); }
 
 }  // namespace pg
