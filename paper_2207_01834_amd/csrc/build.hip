@@ -64,6 +64,7 @@ __global__ void ingest_kernel(const uint32_t* __restrict__ in, int64_t n, int d,
     __syncthreads();
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     uint32_t bad = 0;
+    uint32_t vl[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     if (i < n) {
         for (int c = 0; c < d; c++) {
             uint32_t b = in[i * d + c];
@@ -79,13 +80,20 @@ __global__ void ingest_kernel(const uint32_t* __restrict__ in, int64_t n, int d,
             }
             uint32_t k = coord_to_key(b, fl), k0 = coord_to_key(b0, fl);
             keys[(int64_t)c * n + i] = k;
-            uint32_t v = k ^ k0;
-            if (v) atomicOr(&s_vary[c], v);
+            vl[c] = k ^ k0;
             if (i == 0) keybase[c] = k0;
         }
         idx[i] = (int32_t)i;
     }
-    if (bad) atomicOr(&s_err, 1u);
+    // one LDS atomic per wave and dimension (a per-element atomic on one
+    // word serialises the whole workgroup)
+    for (int c = 0; c < d; c++) {
+        uint32_t v = vl[c];
+#pragma unroll
+        for (int off = kWave / 2; off > 0; off >>= 1) v |= __shfl_xor(v, off, kWave);
+        if (lane_id() == 0 && v) atomicOr(&s_vary[c], v);
+    }
+    if (__ballot(bad != 0) != 0 && lane_id() == 0) atomicOr(&s_err, 1u);
     __syncthreads();
     if (threadIdx.x < d && s_vary[threadIdx.x]) atomicOr(&vary[threadIdx.x], s_vary[threadIdx.x]);
     if (threadIdx.x == 0 && s_err) atomicOr(err, 1u);
@@ -217,7 +225,7 @@ wide_scatter_kernel(const uint32_t* __restrict__ in, const int32_t* __restrict__
                     uint32_t* __restrict__ out, int32_t* __restrict__ out_idx, int d, int c,
                     int64_t n, int l, int bpn, const NodeSel* __restrict__ ns,
                     const uint64_t* __restrict__ boff) {
-    __shared__ uint32_t lds[kNT / kWave + 1];
+    __shared__ uint32_t lds[2 * (kNT / kWave)];
     const int64_t j = blockIdx.x / bpn;
     const int t = blockIdx.x % bpn;
     int64_t lo, hi, mid;
@@ -225,11 +233,9 @@ wide_scatter_kernel(const uint32_t* __restrict__ in, const int32_t* __restrict__
     const int64_t e0 = lo + (int64_t)t * kChunk;
     const int64_t e1 = min(e0 + kChunk, hi);
     const uint32_t v = ns[j].prefix, teq = ns[j].rank;
-    uint32_t run_lt = (uint32_t)(boff[blockIdx.x] & 0xffffffffull);
-    uint32_t run_eq = (uint32_t)(boff[blockIdx.x] >> 32);
-    for (int64_t base = e0; base < e1; base += kNT)
-        partition_tile(in, in_idx, out, out_idx, d, c, n, base, e1, lo, mid, hi, v, teq, run_lt,
-                       run_eq, lds);
+    block_partition_range(in, in_idx, out, out_idx, d, c, n, e0, e1, lo, mid, hi, v, teq,
+                          (uint32_t)(boff[blockIdx.x] & 0xffffffffull),
+                          (uint32_t)(boff[blockIdx.x] >> 32), lds);
 }
 
 // ---------------------------------------------------------------------------

@@ -11,51 +11,87 @@ namespace pg {
 
 constexpr int kBuildNT = 256;  // threads of every build workgroup
 
-// Stable partition of one tile of consecutive elements [base, base+NT) of a
-// node; run_lt / run_eq count the node's elements before the tile.
-__device__ inline void partition_tile(const uint32_t* __restrict__ in, const int32_t* __restrict__ in_idx,
-                                      uint32_t* __restrict__ out, int32_t* __restrict__ out_idx,
-                                      int d, int c, int64_t n, int64_t base, int64_t end,
-                                      int64_t lo, int64_t mid, int64_t end_node, uint32_t v,
-                                      uint32_t teq,
-                                      uint32_t& run_lt, uint32_t& run_eq, uint32_t* lds) {
-    const int64_t e = base + threadIdx.x;
-    const bool valid = e < end;
-    const uint32_t k = valid ? in[(int64_t)c * n + e] : 0u;
-    const bool lt = valid && k < v;
-    const bool eq = valid && k == v;
-    uint32_t tot;
-    uint32_t ex = block_excl_scan<kBuildNT>((lt ? 1u : 0u) | (eq ? 0x10000u : 0u), lds, &tot);
-    const uint32_t ltb = run_lt + (ex & 0xffffu);
-    const uint32_t eqb = run_eq + (ex >> 16);
-    if (valid) {
-        const uint32_t el = eqb < teq ? eqb : teq;
-        int64_t dest;
-        if (lt) dest = lo + ltb + el;
-        else if (eq && eqb < teq) dest = lo + ltb + eqb;
-        else dest = mid + (e - lo) - (int64_t)(ltb + el);
-        if (dest >= lo && dest < end_node) {  // always true for a consistent split
-            for (int cc = 0; cc < d; cc++)
-                out[(int64_t)cc * n + dest] = cc == c ? k : in[(int64_t)cc * n + e];
-            out_idx[dest] = in_idx[e];
-        }
+// Stable partition of the elements [c0, c1) of a node [lo, end_node) whose
+// left child ends at mid, around pivot key v (keys < v go left, then the
+// first teq keys == v, the rest right); base_lt / base_eq count the node's
+// keys < v / == v before c0.  The workgroup's waves each take one contiguous
+// part of the chunk: they count it with ballots, exchange their totals
+// through LDS (lds: >= 2 * waves words), then scatter their part in order,
+// positions from ballot prefix counts.  Contains barriers.
+__device__ inline void block_partition_range(const uint32_t* __restrict__ in,
+                                             const int32_t* __restrict__ in_idx,
+                                             uint32_t* __restrict__ out,
+                                             int32_t* __restrict__ out_idx, int d, int c,
+                                             int64_t n, int64_t c0, int64_t c1, int64_t lo,
+                                             int64_t mid, int64_t end_node, uint32_t v,
+                                             uint32_t teq, uint32_t base_lt, uint32_t base_eq,
+                                             uint32_t* lds) {
+    constexpr int NW = kBuildNT / kWave;
+    const int w = threadIdx.x / kWave, lane = lane_id();
+    const int64_t part = (c1 - c0 + NW - 1) / NW;
+    const int64_t s0 = c0 + w * part < c1 ? c0 + w * part : c1;
+    const int64_t s1 = s0 + part < c1 ? s0 + part : c1;
+    const uint32_t* keys = in + (int64_t)c * n;
+    uint32_t nlt = 0, neq = 0;
+    for (int64_t e0 = s0; e0 < s1; e0 += kWave) {
+        const int64_t e = e0 + lane;
+        const bool valid = e < s1;
+        const uint32_t k = valid ? keys[e] : 0u;
+        nlt += (uint32_t)__popcll(ballot(valid && k < v));
+        neq += (uint32_t)__popcll(ballot(valid && k == v));
     }
-    run_lt += tot & 0xffffu;
-    run_eq += tot >> 16;
+    if (lane == 0) {
+        lds[w] = nlt;
+        lds[NW + w] = neq;
+    }
+    __syncthreads();
+    uint32_t run_lt = base_lt, run_eq = base_eq;
+    for (int i = 0; i < w; i++) {
+        run_lt += lds[i];
+        run_eq += lds[NW + i];
+    }
+    __syncthreads();
+    for (int64_t e0 = s0; e0 < s1; e0 += kWave) {
+        const int64_t e = e0 + lane;
+        const bool valid = e < s1;
+        const uint32_t k = valid ? keys[e] : 0u;
+        const bool lt = valid && k < v;
+        const bool eq = valid && k == v;
+        const uint64_t mlt = ballot(lt), meq = ballot(eq);
+        const uint32_t ltb = run_lt + lane_prefix(mlt);
+        const uint32_t eqb = run_eq + lane_prefix(meq);
+        if (valid) {
+            const uint32_t el = eqb < teq ? eqb : teq;
+            int64_t dest;
+            if (lt) dest = lo + ltb + el;
+            else if (eq && eqb < teq) dest = lo + ltb + eqb;
+            else dest = mid + (e - lo) - (int64_t)(ltb + el);
+            if (dest >= lo && dest < end_node) {  // always true for a consistent split
+                for (int cc = 0; cc < d; cc++)
+                    out[(int64_t)cc * n + dest] = cc == c ? k : in[(int64_t)cc * n + e];
+                out_idx[dest] = in_idx[e];
+            }
+        }
+        run_lt += (uint32_t)__popcll(mlt);
+        run_eq += (uint32_t)__popcll(meq);
+    }
 }
 
 // One wave selects the rank-r key of node [lo, hi) (local positions, order
 // given by pin) and writes the stable partition into pout.  Returns the
 // split key.  mid == hi (right child empty) splits at the largest key and
-// sends everything left.
+// sends everything left.  Selection: the node's min and max fix the common
+// high key bits; the bits below are resolved 8 at a time with a 256-bin LDS
+// histogram private to the wave (whist).
 __device__ inline uint32_t wave_select_partition(const uint32_t* keys, const uint16_t* pin,
-                                          uint16_t* pout, int lo, int hi, int mid) {
+                                                 uint16_t* pout, int lo, int hi, int mid,
+                                                 uint32_t* whist) {
     const int lane = lane_id();
     const bool right_empty = mid >= hi;
     uint32_t r = (uint32_t)((right_empty ? hi - 1 : mid) - lo);
     uint32_t mn = 0xffffffffu, mx = 0;
     for (int e = lo + lane; e < hi; e += kWave) {
-        uint32_t k = keys[pin[e]];
+        const uint32_t k = keys[pin[e]];
         mn = k < mn ? k : mn;
         mx = k > mx ? k : mx;
     }
@@ -63,24 +99,42 @@ __device__ inline uint32_t wave_select_partition(const uint32_t* keys, const uin
     mx = wave_max_u32(mx);
     uint32_t prefix = mn;
     if (mn != mx) {
-        const int hb = 31 - __clz(mn ^ mx);
+        const int hb = 31 - __clz(mn ^ mx);  // highest differing bit
         prefix = hb == 31 ? 0u : (mn & ~((2u << hb) - 1u));
-        for (int b = hb; b >= 0; --b) {
-            const uint32_t want = (prefix >> b) >> 1;
-            uint32_t cnt0 = 0;
-            for (int e0 = lo; e0 < hi; e0 += kWave) {
-                const int e = e0 + lane;
-                bool p = false;
-                if (e < hi) {
-                    const uint32_t k = keys[pin[e]];
-                    p = ((k >> b) >> 1) == want && !((k >> b) & 1u);
-                }
-                cnt0 += (uint32_t)__popcll(ballot(p));
+        for (int top = hb + 1; top > 0; top -= 8) {  // digit = key bits [shift, top)
+            const int shift = top > 8 ? top - 8 : 0;
+            const uint32_t wmask = (1u << (top - shift)) - 1u;
+            const uint64_t want = (uint64_t)prefix >> top;
+            whist[4 * lane] = 0;
+            whist[4 * lane + 1] = 0;
+            whist[4 * lane + 2] = 0;
+            whist[4 * lane + 3] = 0;
+            wave_lds_sync();
+            for (int e = lo + lane; e < hi; e += kWave) {
+                const uint32_t k = keys[pin[e]];
+                if (((uint64_t)k >> top) == want) atomicAdd(&whist[(k >> shift) & wmask], 1u);
             }
-            if (r >= cnt0) {
-                prefix |= 1u << b;
-                r -= cnt0;
+            wave_lds_sync();
+            const uint32_t c0 = whist[4 * lane], c1 = whist[4 * lane + 1];
+            const uint32_t c2 = whist[4 * lane + 2], c3 = whist[4 * lane + 3];
+            const uint32_t sum = c0 + c1 + c2 + c3;
+            const uint32_t incl = wave_incl_scan(sum);
+            const uint32_t excl = incl - sum;
+            const bool mine = excl <= r && r < incl;
+            const uint64_t who = ballot(mine);
+            const int owner = __ffsll((unsigned long long)who) - 1;
+            uint32_t bin = 0, below = excl;
+            if (mine) {
+                if (r < below + c0) bin = 0;
+                else if (r < below + c0 + c1) { bin = 1; below += c0; }
+                else if (r < below + c0 + c1 + c2) { bin = 2; below += c0 + c1; }
+                else { bin = 3; below += c0 + c1 + c2; }
             }
+            bin = __shfl(bin + 4u * (uint32_t)lane, owner, kWave);
+            below = __shfl(below, owner, kWave);
+            wave_lds_sync();  // every lane has read the bins before the next clear
+            prefix |= bin << shift;
+            r -= below;
         }
     }
     const uint32_t v = prefix;
@@ -180,15 +234,13 @@ __device__ inline void block_node_split(const uint32_t* __restrict__ in,
         __syncthreads();
     }
     if (threadIdx.x == 0) *split_out = key_to_coord(prefix, fl);
-    uint32_t run_lt = 0, run_eq = 0;
-    for (int64_t base = lo; base < hi; base += kBuildNT)
-        partition_tile(in, in_idx, out, out_idx, d, c, n, base, hi, lo, mid, hi, prefix, r,
-                       run_lt, run_eq, lds);
+    block_partition_range(in, in_idx, out, out_idx, d, c, n, lo, hi, lo, mid, hi, prefix, r, 0u,
+                          0u, lds);
 }
 
 // LDS bytes of block_subtree for subtrees of up to S points.
 __host__ __device__ inline size_t subtree_lds_bytes(int d, int S) {
-    return (size_t)d * S * 4 + (size_t)S * 4 + (size_t)S * 4;
+    return (size_t)d * S * 4 + (size_t)S * 4 + (size_t)S * 4 + (kBuildNT / kWave) * 256 * 4;
 }
 
 // One workgroup finishes the subtree rooted at node j0 of level ls (at most S
@@ -207,6 +259,7 @@ __device__ inline void block_subtree(const uint32_t* in, const int32_t* in_idx, 
     int32_t* sidx = (int32_t*)(sm + (size_t)d * S);          // [S]
     uint16_t* pa = (uint16_t*)(sidx + S);                    // [S]
     uint16_t* pb = pa + S;                                   // [S]
+    uint32_t* hists = (uint32_t*)(pb + S);                   // [waves][256]
     const int64_t base = node_start(n, ls, j0);
     const int s = (int)(node_start(n, ls, j0 + 1) - base);
     for (int e = threadIdx.x; e < s; e += kBuildNT) {
@@ -228,7 +281,8 @@ __device__ inline void block_subtree(const uint32_t* in, const int32_t* in_idx, 
             const int lo = (int)(node_start(n, l, jj) - base);
             const int hi = (int)(node_start(n, l, jj + 1) - base);
             const int mid = (int)(node_start(n, l + 1, 2 * jj + 1) - base);
-            const uint32_t v = wave_select_partition(skeys + c * S, pin, pout, lo, hi, mid);
+            const uint32_t v = wave_select_partition(skeys + c * S, pin, pout, lo, hi, mid,
+                                                     hists + 256 * w);
             if (lane_id() == 0) split[((int64_t)1 << l) + jj] = key_to_coord(v, fl);
         }
         __syncthreads();

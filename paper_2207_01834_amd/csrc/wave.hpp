@@ -17,6 +17,14 @@ __device__ inline uint32_t lane_prefix(uint64_t mask) {
 
 __device__ inline uint64_t ballot(bool p) { return __ballot(p); }
 
+// Orders the LDS accesses of the lanes of one wave around this point: the
+// compiler may neither move memory operations across it nor assume LDS still
+// holds what this lane last wrote (other lanes' writes before it are seen).
+__device__ inline void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+}
+
 template <typename T>
 __device__ inline T wave_incl_scan(T v) {
 #pragma unroll
