@@ -31,7 +31,8 @@ namespace pg {
 namespace {
 
 constexpr int kNT = kBuildNT;       // threads per workgroup
-constexpr int kChunk = 16384;       // elements per workgroup in the wide levels
+constexpr int kChunk = 16384;       // elements per histogram workgroup in the wide levels
+constexpr int kScat = 4096;         // elements per count/scatter workgroup in the wide levels
 constexpr int kWideDigit = 11;      // radix digit width in the wide levels
 constexpr int kWideNodes = 512;     // levels with fewer nodes use the wide path
 
@@ -53,45 +54,60 @@ __device__ inline int64_t split_rank_pos(int64_t n, int l, int64_t j, int64_t* l
 // Ingest: caller's [n][d] rows -> key planes + input-row plane; range check;
 // -0.0 -> +0.0; per-dimension OR of (key ^ key of row 0).
 // ---------------------------------------------------------------------------
-__global__ void ingest_kernel(const uint32_t* __restrict__ in, int64_t n, int d, int fl,
-                              uint32_t* __restrict__ keys, int32_t* __restrict__ idx,
-                              uint32_t* __restrict__ vary, uint32_t* __restrict__ keybase,
-                              uint32_t* __restrict__ err) {
+__global__ void __launch_bounds__(kNT)
+ingest_kernel(const uint32_t* __restrict__ in, int64_t n, int d, int fl,
+              uint32_t* __restrict__ keys, int32_t* __restrict__ idx,
+              uint32_t* __restrict__ vary, uint32_t* __restrict__ keybase,
+              uint32_t* __restrict__ err) {
     __shared__ uint32_t s_vary[8];
     __shared__ uint32_t s_err;
     if (threadIdx.x < 8) s_vary[threadIdx.x] = 0;
     if (threadIdx.x == 0) s_err = 0;
     __syncthreads();
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t k0[8], vl[8];
+#pragma unroll
+    for (int c = 0; c < 8; c++) {
+        uint32_t b0 = c < d ? in[c] : 0u;
+        if (fl && b0 == 0x80000000u) b0 = 0;
+        k0[c] = coord_to_key(b0, fl);
+        vl[c] = 0;
+    }
     uint32_t bad = 0;
-    uint32_t vl[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    if (i < n) {
-        for (int c = 0; c < d; c++) {
-            uint32_t b = in[i * d + c];
-            uint32_t b0 = in[c];
-            if (fl) {
-                if (b == 0x80000000u) b = 0;
-                if (b0 == 0x80000000u) b0 = 0;
-                float x = __uint_as_float(b);
-                if (!(fabsf(x) <= 1e18f)) bad = 1;  // also catches NaN and inf
-            } else {
-                int32_t x = (int32_t)b;
-                if (x < -(1 << 29) || x >= (1 << 29)) bad = 1;
+    // grid-stride: few workgroups, so the per-workgroup global atomics stay few
+    const int64_t stride = (int64_t)gridDim.x * kNT;
+    for (int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x; i < n; i += stride) {
+#pragma unroll
+        for (int c = 0; c < 8; c++) {
+            if (c < d) {
+                uint32_t b = in[i * d + c];
+                if (fl) {
+                    if (b == 0x80000000u) b = 0;
+                    if (!(fabsf(__uint_as_float(b)) <= 1e18f)) bad = 1;  // also NaN, inf
+                } else {
+                    const int32_t x = (int32_t)b;
+                    if (x < -(1 << 29) || x >= (1 << 29)) bad = 1;
+                }
+                const uint32_t k = coord_to_key(b, fl);
+                keys[(int64_t)c * n + i] = k;
+                vl[c] |= k ^ k0[c];
             }
-            uint32_t k = coord_to_key(b, fl), k0 = coord_to_key(b0, fl);
-            keys[(int64_t)c * n + i] = k;
-            vl[c] = k ^ k0;
-            if (i == 0) keybase[c] = k0;
         }
         idx[i] = (int32_t)i;
     }
-    // one LDS atomic per wave and dimension (a per-element atomic on one
-    // word serialises the whole workgroup)
-    for (int c = 0; c < d; c++) {
-        uint32_t v = vl[c];
+    if (blockIdx.x == 0 && threadIdx.x < d) {
+        uint32_t kb = 0;
 #pragma unroll
-        for (int off = kWave / 2; off > 0; off >>= 1) v |= __shfl_xor(v, off, kWave);
-        if (lane_id() == 0 && v) atomicOr(&s_vary[c], v);
+        for (int c = 0; c < 8; c++) kb = (int)threadIdx.x == c ? k0[c] : kb;
+        keybase[threadIdx.x] = kb;
+    }
+#pragma unroll
+    for (int c = 0; c < 8; c++) {
+        if (c < d) {
+            uint32_t v = vl[c];
+#pragma unroll
+            for (int off = kWave / 2; off > 0; off >>= 1) v |= __shfl_xor(v, off, kWave);
+            if (lane_id() == 0 && v) atomicOr(&s_vary[c], v);
+        }
     }
     if (__ballot(bad != 0) != 0 && lane_id() == 0) atomicOr(&s_err, 1u);
     __syncthreads();
@@ -186,8 +202,8 @@ wide_count_kernel(const uint32_t* __restrict__ keys, int64_t n, int l, int bpn,
     const int64_t j = blockIdx.x / bpn;
     const int t = blockIdx.x % bpn;
     const int64_t lo = node_start(n, l, j), hi = node_start(n, l, j + 1);
-    const int64_t e0 = lo + (int64_t)t * kChunk;
-    const int64_t e1 = min(e0 + kChunk, hi);
+    const int64_t e0 = lo + (int64_t)t * kScat;
+    const int64_t e1 = min(e0 + kScat, hi);
     const uint32_t v = ns[j].prefix;
     uint64_t acc = 0;  // lt in the low 32 bits, eq in the high 32 bits
     for (int64_t e = e0 + threadIdx.x; e < e1; e += kNT) {
@@ -230,8 +246,8 @@ wide_scatter_kernel(const uint32_t* __restrict__ in, const int32_t* __restrict__
     const int t = blockIdx.x % bpn;
     int64_t lo, hi, mid;
     split_rank_pos(n, l, j, &lo, &hi, &mid);
-    const int64_t e0 = lo + (int64_t)t * kChunk;
-    const int64_t e1 = min(e0 + kChunk, hi);
+    const int64_t e0 = lo + (int64_t)t * kScat;
+    const int64_t e1 = min(e0 + kScat, hi);
     const uint32_t v = ns[j].prefix, teq = ns[j].rank;
     block_partition_range(in, in_idx, out, out_idx, d, c, n, e0, e1, lo, mid, hi, v, teq,
                           (uint32_t)(boff[blockIdx.x] & 0xffffffffull),
@@ -281,7 +297,8 @@ pg_status ingest_points(const void* points, int64_t n, int d, bool fl, uint32_t*
     uint32_t* err = vary + 16;
     PG_HIP(hipMemsetAsync(vary, 0, sizeof(uint32_t) * 17, s));
     if (n > 0) {
-        hipLaunchKernelGGL(ingest_kernel, dim3(cdiv(n, kNT)), dim3(kNT), 0, s,
+        const unsigned grid = cdiv(n, kNT) < 2048u ? cdiv(n, kNT) : 2048u;
+        hipLaunchKernelGGL(ingest_kernel, dim3(grid), dim3(kNT), 0, s,
                            (const uint32_t*)points, n, d, fl ? 1 : 0, keys, idx, vary, keybase,
                            err);
         PG_LAUNCH_CHECK();
@@ -319,7 +336,7 @@ pg_status build_from_keys(uint32_t* kA, int32_t* iA, uint32_t* kB, int32_t* iB, 
         int64_t blocks_max = 1;
         for (int l = 0; l < wide_levels; l++) {
             const int64_t J = (int64_t)1 << l;
-            const int64_t b = J * (int64_t)cdiv((n + J - 1) / J, kChunk);
+            const int64_t b = J * (int64_t)cdiv((n + J - 1) / J, kScat);
             blocks_max = b > blocks_max ? b : blocks_max;
         }
         PG_TRY(nsel.alloc(sizeof(NodeSel) * Jmax));
@@ -339,6 +356,8 @@ pg_status build_from_keys(uint32_t* kA, int32_t* iA, uint32_t* kB, int32_t* iB, 
             const int64_t smax = (n + J - 1) / J;
             const int bpn = (int)cdiv(smax, kChunk);
             const unsigned nblk = (unsigned)(J * bpn);
+            const int spn = (int)cdiv(smax, kScat);
+            const unsigned nsblk = (unsigned)(J * spn);
             NodeSel* ns = nsel.as<NodeSel>();
             hipLaunchKernelGGL(wide_init_kernel, dim3(cdiv(J, kNT)), dim3(kNT), 0, s, ns, J, n, l,
                                prefix0, sb == 0 ? 1 : 0, split_level, ifl);
@@ -356,14 +375,14 @@ pg_status build_from_keys(uint32_t* kA, int32_t* iA, uint32_t* kB, int32_t* iB, 
                                    split_level, ifl);
                 PG_LAUNCH_CHECK();
             }
-            hipLaunchKernelGGL(wide_count_kernel, dim3(nblk), dim3(kNT), 0, s,
-                               cur_k + (int64_t)c * n, n, l, bpn, ns, bcnt.as<uint64_t>());
+            hipLaunchKernelGGL(wide_count_kernel, dim3(nsblk), dim3(kNT), 0, s,
+                               cur_k + (int64_t)c * n, n, l, spn, ns, bcnt.as<uint64_t>());
             PG_LAUNCH_CHECK();
             hipLaunchKernelGGL(wide_scan_kernel, dim3((unsigned)J), dim3(kNT), 0, s,
-                               bcnt.as<uint64_t>(), bpn);
+                               bcnt.as<uint64_t>(), spn);
             PG_LAUNCH_CHECK();
-            hipLaunchKernelGGL(wide_scatter_kernel, dim3(nblk), dim3(kNT), 0, s, cur_k, cur_i,
-                               oth_k, oth_i, d, c, n, l, bpn, ns, bcnt.as<uint64_t>());
+            hipLaunchKernelGGL(wide_scatter_kernel, dim3(nsblk), dim3(kNT), 0, s, cur_k, cur_i,
+                               oth_k, oth_i, d, c, n, l, spn, ns, bcnt.as<uint64_t>());
             PG_LAUNCH_CHECK();
         } else {
             hipLaunchKernelGGL(node_kernel, dim3((unsigned)J), dim3(kNT), 0, s, cur_k, cur_i,
