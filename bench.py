@@ -112,6 +112,130 @@ def cpu_baseline(pts, sample):
     }
 
 
+def timed(torch, fn, reps=3):
+    """Median milliseconds of fn() over reps runs (HIP events on the current
+    stream, which the library launches on)."""
+    import numpy as np
+    out = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        out.append(e0.elapsed_time(e1))
+    return float(np.median(out))
+
+
+def form_static_float(torch, pg, datagen, dev):
+    """The same workload with float32 coordinates (int grid / 2^20)."""
+    pts = datagen.int_to_unit_float(datagen.uniform_int(N, D, seed=2))
+    x = torch.from_numpy(pts).to(dev)
+    idx = torch.empty((N, K), dtype=torch.int32, device=dev)
+    dist = torch.empty((N, K), dtype=torch.float32, device=dev)
+    holder = {}
+    build_ms = timed(torch, lambda: holder.__setitem__("t", pg.kdtree_build(x, leaf=LEAF)))
+    knn_ms = timed(torch, lambda: holder["t"].knn_all(K, out=(idx, dist)))
+    return {"workload": "3-D n=10M float32 uniform, k=10, leaf 16, all points",
+            "build_ms": build_ms, "knn_ms": knn_ms, "knn_qps": N / (knn_ms * 1e-3),
+            "build_mpts_s": N / (build_ms * 1e-3) / 1e6}
+
+
+def form_clustered(torch, pg, datagen, dev):
+    """5-D clustered float32 (1,000 Gaussian clusters, Zipf sizes), 1M queries
+    from the same mixture, k = 5."""
+    pts, q = datagen.clustered(N, 5, seed=3, n_queries=1_000_000, query_seed=33)
+    x = torch.from_numpy(pts).to(dev)
+    qd = torch.from_numpy(q).to(dev)
+    holder = {}
+    build_ms = timed(torch, lambda: holder.__setitem__("t", pg.kdtree_build(x, leaf=LEAF)))
+    knn_ms = timed(torch, lambda: holder["t"].knn(qd, 5))
+    return {"workload": "5-D n=10M clustered float32, 1M queries, k=5, leaf 16",
+            "build_ms": build_ms, "knn_ms": knn_ms, "knn_qps": len(q) / (knn_ms * 1e-3),
+            "build_mpts_s": N / (build_ms * 1e-3) / 1e6}
+
+
+def form_bdl(torch, pg, datagen, dev, rounds):
+    """Batch-dynamic: 10M initial 3-D int points, then rounds of 1M inserts,
+    1M erases of inserted points, 1M fresh queries (k = 10), X = 2^14."""
+    import numpy as np
+    init, rds = datagen.bdl_rounds(N, rounds, 1_000_000, 1_000_000, 3, seed=5)
+    B = pg.BDLTree(3, torch.int32, leaf=LEAF, X=1 << 14, device=dev)
+    xi = torch.from_numpy(init).to(dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    B.insert(xi)
+    torch.cuda.synchronize()
+    build_ms = (time.perf_counter() - t0) * 1e3
+    pool = init
+    ins, era, knn = [], [], []
+    erased_total = 0
+    for r, rd in enumerate(rds):
+        xr = torch.from_numpy(rd["insert"]).to(dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        B.insert(xr)
+        torch.cuda.synchronize()
+        ins.append((time.perf_counter() - t0) * 1e3)
+        pool = np.concatenate([pool, rd["insert"]])
+        g = np.random.default_rng(rd["erase_seed"])
+        pick = g.choice(len(pool), size=1_000_000, replace=False)
+        E = torch.from_numpy(np.ascontiguousarray(pool[pick])).to(dev)
+        keep = np.ones(len(pool), bool)
+        keep[pick] = False
+        pool = pool[keep]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        erased_total += B.erase(E)
+        torch.cuda.synchronize()
+        era.append((time.perf_counter() - t0) * 1e3)
+        qd = torch.from_numpy(rd["queries"]).to(dev)
+        knn.append(timed(torch, lambda: B.knn(qd, 10), reps=1))
+    med = lambda a: float(np.median(a))
+    return {"workload": "BDL 3-D int, 10M initial, rounds of 1M insert / 1M erase / 1M kNN (k=10), X=2^14",
+            "rounds": rounds, "initial_insert_ms": build_ms,
+            "insert_ms": med(ins), "erase_ms": med(era), "knn_ms": med(knn),
+            "insert_mpts_s": 1.0 / med(ins) * 1e3, "erase_mpts_s": 1.0 / med(era) * 1e3,
+            "knn_qps": 1e6 / (med(knn) * 1e-3), "erased_per_round": erased_total / rounds,
+            "live_points": B.size()}
+
+
+def form_batch(torch, pg, datagen, dev, loop_clouds):
+    """4,096 sphere clouds (sizes log-uniform in [256, 65536]), per-cloud
+    all-points k = 16 in one persistent launch, against the per-cloud static
+    method; plus the k-NN backward over the same clouds."""
+    import numpy as np
+    sizes = datagen.cloud_sizes(4096, seed=4)
+    pts, offs = datagen.sphere_clouds(sizes, seed=44)
+    Ntot = len(pts)
+    x = torch.from_numpy(pts).to(dev)
+    tune = pg.batch_autotune(x, offs, 16)
+    Bk = pg.BatchKnn(offs, 3, leaf=tune["leaf"], blocks_per_cu=tune["blocks_per_cu"], device=dev)
+    idx = torch.empty((Ntot, 16), dtype=torch.int32, device=dev)
+    d2 = torch.empty((Ntot, 16), dtype=torch.float32, device=dev)
+    batch_ms = timed(torch, lambda: Bk.knn_self(x, 16, out=(idx, d2)))
+    # per-cloud static method on the first loop_clouds clouds (projected)
+    nc = min(loop_clouds, 4096)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for c in range(nc):
+        t = pg.kdtree_build(x[int(offs[c]):int(offs[c + 1])], leaf=16)
+        t.knn_all(16)
+    torch.cuda.synchronize()
+    loop_s = (time.perf_counter() - t0) * 4096 / nc
+    g = torch.randn((Ntot, 16), dtype=torch.float32, device=dev)
+    grad = torch.empty_like(x)
+    bwd_ms = timed(torch, lambda: pg.knn_backward(x, x, idx, g, grad_q=grad, self_mode=True))
+    return {"workload": "4,096 unit-sphere clouds (+N(0,0.01^2)), sizes log-uniform [256,65536], "
+                        f"{Ntot} points, per-cloud all-points k=16, float32",
+            "tune": tune, "batched_ms": batch_ms, "clouds_per_s": 4096 / (batch_ms * 1e-3),
+            "points_per_s": Ntot / (batch_ms * 1e-3),
+            "per_cloud_loop_ms": loop_s * 1e3, "per_cloud_loop_sample_clouds": nc,
+            "speedup_vs_per_cloud_loop": loop_s * 1e3 / batch_ms,
+            "backward_ms": bwd_ms, "backward_pairs_per_s": Ntot * 16 / (bwd_ms * 1e-3)}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -120,6 +244,12 @@ def main():
     ap.add_argument("--dtype", choices=["int", "float"], default="int")
     ap.add_argument("--cpu-sample", type=int, default=100_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--forms", default="all",
+                    help="other forms to measure after the headline step: all, none, or a "
+                         "comma list of static_float,clustered,bdl,batch")
+    ap.add_argument("--bdl-rounds", type=int, default=3)
+    ap.add_argument("--loop-clouds", type=int, default=512,
+                    help="clouds timed for the per-cloud comparison (projected to 4,096)")
     ap.add_argument("--copy-probe-mib", type=int, default=1024,
                     help="size of the device copy that measures achievable HBM bandwidth (0: skip)")
     args = ap.parse_args()
@@ -218,6 +348,26 @@ def main():
             "algorithmic_bytes_per_query": bytes_per_query(dbytes),
         },
     }
+    del idx, dist, x
+    torch.cuda.empty_cache()
+    forms = ["static_float", "clustered", "bdl", "batch"] if args.forms == "all" else \
+        [f for f in args.forms.split(",") if f and f != "none"]
+    out = {}
+    for f in forms:
+        log(f"form {f}")
+        if f == "static_float":
+            out[f] = form_static_float(torch, pg, datagen, dev)
+        elif f == "clustered":
+            out[f] = form_clustered(torch, pg, datagen, dev)
+        elif f == "bdl":
+            out[f] = form_bdl(torch, pg, datagen, dev, args.bdl_rounds)
+        elif f == "batch":
+            out[f] = form_batch(torch, pg, datagen, dev, args.loop_clouds)
+        else:
+            raise SystemExit(f"unknown form {f}")
+        torch.cuda.empty_cache()
+    if out:
+        line["forms"] = out
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(pts, args.cpu_sample)
     print(json.dumps(line), flush=True)
