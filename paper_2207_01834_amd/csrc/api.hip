@@ -52,7 +52,7 @@ static void tree_release(pg_tree* t) {
     dfree(t->pts, t->stream);
     dfree(t->pidx, t->stream);
     dfree(t->split, t->stream);
-    dfree(t->bbox, t->stream);
+    dfree(t->nbox, t->stream);
     dfree(t->rec, t->stream);
     delete t;
 }

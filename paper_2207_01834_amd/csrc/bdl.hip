@@ -161,11 +161,13 @@ erase_kernel(Forest f, const uint32_t* __restrict__ pts, int64_t m, int d,
 
 template <typename T, int MD, int KT, bool EX>
 __global__ void __launch_bounds__(kNT)
-bdl_knn_kernel(Forest f, const uint32_t* __restrict__ queries, int64_t m, int d, int k,
-               int64_t* __restrict__ out_id, typename Metric<T>::D* __restrict__ out_dist) {
+bdl_knn_kernel(Forest f, const uint32_t* __restrict__ queries, const int32_t* __restrict__ order,
+               int64_t m, int d, int k, int64_t* __restrict__ out_id,
+               typename Metric<T>::D* __restrict__ out_dist) {
     using M = Metric<T>;
-    const int64_t qi = xcd_block() * kNT + threadIdx.x;
-    if (qi >= m) return;
+    const int64_t i0 = xcd_block() * kNT + threadIdx.x;
+    if (i0 >= m) return;
+    const int64_t qi = order ? (int64_t)order[i0] : i0;  // leaf order of the largest tree
     T q[MD];
 #pragma unroll
     for (int c = 0; c < MD; c++) q[c] = M::load(c < d ? queries[qi * d + c] : 0u);
@@ -203,37 +205,37 @@ pg_status erase_d(const Forest& f, const void* pts, int64_t m, int d, unsigned l
 }
 
 template <typename T, int MD, int KT, bool EX>
-pg_status launch_bdl_knn(const Forest& f, const void* q, int64_t m, int d, int k, int64_t* oi,
-                         void* od, hipStream_t s) {
+pg_status launch_bdl_knn(const Forest& f, const void* q, const int32_t* o, int64_t m, int d, int k,
+                         int64_t* oi, void* od, hipStream_t s) {
     using DT = typename Metric<T>::D;
     hipLaunchKernelGGL((bdl_knn_kernel<T, MD, KT, EX>), dim3(grid_for_xcd(cdiv(m, kNT))), dim3(kNT),
-                       0, s, f, (const uint32_t*)q, m, d, k, oi, (DT*)od);
+                       0, s, f, (const uint32_t*)q, o, m, d, k, oi, (DT*)od);
     PG_LAUNCH_CHECK();
     return PG_OK;
 }
 
 template <typename T, int MD>
-pg_status bdl_knn_k(const Forest& f, const void* q, int64_t m, int d, int k, int64_t* oi,
-                    void* od, hipStream_t s) {
-    if (k == 5) return launch_bdl_knn<T, MD, 5, true>(f, q, m, d, k, oi, od, s);
-    if (k == 10) return launch_bdl_knn<T, MD, 10, true>(f, q, m, d, k, oi, od, s);
-    if (k == 16) return launch_bdl_knn<T, MD, 16, true>(f, q, m, d, k, oi, od, s);
-    if (k <= 2) return launch_bdl_knn<T, MD, 2, false>(f, q, m, d, k, oi, od, s);
-    if (k <= 4) return launch_bdl_knn<T, MD, 4, false>(f, q, m, d, k, oi, od, s);
-    if (k <= 8) return launch_bdl_knn<T, MD, 8, false>(f, q, m, d, k, oi, od, s);
-    if (k <= 16) return launch_bdl_knn<T, MD, 16, false>(f, q, m, d, k, oi, od, s);
-    if (k <= 32) return launch_bdl_knn<T, MD, 32, false>(f, q, m, d, k, oi, od, s);
-    return launch_bdl_knn<T, MD, 64, false>(f, q, m, d, k, oi, od, s);
+pg_status bdl_knn_k(const Forest& f, const void* q, const int32_t* o, int64_t m, int d, int k,
+                    int64_t* oi, void* od, hipStream_t s) {
+    if (k == 5) return launch_bdl_knn<T, MD, 5, true>(f, q, o, m, d, k, oi, od, s);
+    if (k == 10) return launch_bdl_knn<T, MD, 10, true>(f, q, o, m, d, k, oi, od, s);
+    if (k == 16) return launch_bdl_knn<T, MD, 16, true>(f, q, o, m, d, k, oi, od, s);
+    if (k <= 2) return launch_bdl_knn<T, MD, 2, false>(f, q, o, m, d, k, oi, od, s);
+    if (k <= 4) return launch_bdl_knn<T, MD, 4, false>(f, q, o, m, d, k, oi, od, s);
+    if (k <= 8) return launch_bdl_knn<T, MD, 8, false>(f, q, o, m, d, k, oi, od, s);
+    if (k <= 16) return launch_bdl_knn<T, MD, 16, false>(f, q, o, m, d, k, oi, od, s);
+    if (k <= 32) return launch_bdl_knn<T, MD, 32, false>(f, q, o, m, d, k, oi, od, s);
+    return launch_bdl_knn<T, MD, 64, false>(f, q, o, m, d, k, oi, od, s);
 }
 
 template <typename T>
-pg_status bdl_knn_d(const Forest& f, const void* q, int64_t m, int d, int k, int64_t* oi,
-                    void* od, hipStream_t s) {
+pg_status bdl_knn_d(const Forest& f, const void* q, const int32_t* o, int64_t m, int d, int k,
+                    int64_t* oi, void* od, hipStream_t s) {
     switch (d) {
-        case 2: return bdl_knn_k<T, 2>(f, q, m, d, k, oi, od, s);
-        case 3: return bdl_knn_k<T, 3>(f, q, m, d, k, oi, od, s);
-        case 5: return bdl_knn_k<T, 5>(f, q, m, d, k, oi, od, s);
-        default: return bdl_knn_k<T, 8>(f, q, m, d, k, oi, od, s);
+        case 2: return bdl_knn_k<T, 2>(f, q, o, m, d, k, oi, od, s);
+        case 3: return bdl_knn_k<T, 3>(f, q, o, m, d, k, oi, od, s);
+        case 5: return bdl_knn_k<T, 5>(f, q, o, m, d, k, oi, od, s);
+        default: return bdl_knn_k<T, 8>(f, q, o, m, d, k, oi, od, s);
     }
 }
 
@@ -563,8 +565,14 @@ pg_status pg_bdl_knn(const pg_bdl* h, const void* queries, int64_t m, int32_t k,
     hipStream_t s = (hipStream_t)stream;
     PG_TRY(check_queries(queries, m, B.d, B.dtype == PG_FLOAT32, s));
     Forest f = make_forest(B);
-    if (B.dtype == PG_FLOAT32) return bdl_knn_d<float>(f, queries, m, B.d, k, out_id, out_dist, s);
-    return bdl_knn_d<int32_t>(f, queries, m, B.d, k, out_id, out_dist, s);
+    DevBuf order(s);
+    const int32_t* o = nullptr;
+    if (f.count > 0 && m >= kOrderMin) {
+        PG_TRY(order_queries(f.s[0].tv, B.dtype == PG_FLOAT32, queries, m, s, order));
+        o = order.as<int32_t>();
+    }
+    if (B.dtype == PG_FLOAT32) return bdl_knn_d<float>(f, queries, o, m, B.d, k, out_id, out_dist, s);
+    return bdl_knn_d<int32_t>(f, queries, o, m, B.d, k, out_id, out_dist, s);
 }
 
 int64_t pg_bdl_size(const pg_bdl* h) {

@@ -35,6 +35,7 @@ constexpr int kChunk = 16384;       // elements per histogram workgroup in the w
 constexpr int kScat = 4096;         // elements per count/scatter workgroup in the wide levels
 constexpr int kWideDigit = 11;      // radix digit width in the wide levels
 constexpr int kWideNodes = 512;     // levels with fewer nodes use the wide path
+constexpr int kBoxLevels = 8;       // tree levels of internal boxes per launch
 
 struct NodeSel {
     uint32_t prefix;  // selected key bits so far; the pivot key at the end
@@ -283,6 +284,42 @@ subtree_kernel(const uint32_t* __restrict__ in, const int32_t* __restrict__ in_i
                   rec, sm);
 }
 
+// ---------------------------------------------------------------------------
+// Internal bounding boxes (the subtree boxes the search of Appendix C prunes
+// by): box(h) = union of box(2h) and box(2h+1), heap-indexed, min[d] then
+// max[d].  A workgroup reads the 2^b boxes of level lt below one node of
+// level lt-b and writes the b levels above them, ping-ponging two LDS tiles
+// of order-preserving keys.  An empty leaf (leaf size 1 only) carries the box
+// of the point 0, which only widens its ancestors' boxes.
+// ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(kNT)
+node_box_kernel(uint32_t* __restrict__ box, int d, int lt, int b, int fl) {
+    extern __shared__ uint32_t sm[];
+    const int w = 2 * d;
+    const int G = 1 << b;
+    uint32_t* cur = sm;
+    uint32_t* nxt = sm + G * w;
+    const int64_t base = (((int64_t)1 << lt) + (int64_t)blockIdx.x * G) * w;
+    for (int e = threadIdx.x; e < G * w; e += kNT) cur[e] = coord_to_key(box[base + e], fl != 0);
+    __syncthreads();
+    for (int r = 1; r <= b; r++) {
+        const int cnt = G >> r;
+        const int64_t out = (((int64_t)1 << (lt - r)) + (int64_t)blockIdx.x * cnt) * w;
+        for (int e = threadIdx.x; e < cnt * w; e += kNT) {
+            const int u = e / w, c = e - u * w;
+            const uint32_t a = cur[2 * u * w + c], o = cur[(2 * u + 1) * w + c];
+            const uint32_t v = c < d ? (a < o ? a : o) : (a > o ? a : o);
+            nxt[e] = v;
+            box[out + e] = key_to_coord(v, fl != 0);
+        }
+        __syncthreads();
+        uint32_t* t = cur;
+        cur = nxt;
+        nxt = t;
+    }
+}
+
 }  // namespace
 
 int subtree_capacity(int d) { return d <= 5 ? 2048 : 1024; }
@@ -398,6 +435,14 @@ pg_status build_from_keys(uint32_t* kA, int32_t* iA, uint32_t* kB, int32_t* iB, 
                        cur_k, cur_i, n, d, L, ls, S, ifl, T->pts, T->pidx, T->split, T->bbox,
                        T->rec);
     PG_LAUNCH_CHECK();
+    // internal boxes, bottom-up, kBoxLevels levels per launch
+    for (int lt = L; lt > 0;) {
+        const int b = lt < kBoxLevels ? lt : kBoxLevels;
+        hipLaunchKernelGGL(node_box_kernel, dim3((unsigned)((int64_t)1 << (lt - b))), dim3(kNT),
+                           sizeof(uint32_t) * 2 * (2 * d) << b, s, T->nbox, d, lt, b, ifl);
+        PG_LAUNCH_CHECK();
+        lt -= b;
+    }
     return PG_OK;
 }
 
@@ -415,7 +460,8 @@ pg_status build_tree(const void* points, int64_t n, int d, int leaf, int dtype, 
     PG_TRY(dalloc(&T->pts, (size_t)d * nn, s));
     PG_TRY(dalloc(&T->pidx, (size_t)nn, s));
     PG_TRY(dalloc(&T->split, (size_t)nleaves, s));
-    PG_TRY(dalloc(&T->bbox, (size_t)nleaves * 2 * d, s));
+    PG_TRY(dalloc(&T->nbox, (size_t)nleaves * 2 * 2 * d, s));
+    T->bbox = T->nbox + (size_t)nleaves * 2 * d;
     PG_TRY(dalloc(&T->rec, (size_t)nn * record_words(d), s));
     if (n == 0) return PG_OK;
     DevBuf tmpk(s), tmpi(s);

@@ -105,6 +105,8 @@ struct TreeView {
     const uint32_t* split;  // [2^L] split coordinate of heap node h (h >= 1)
     const uint32_t* bbox;   // [2^L][2d] per leaf: min[d], max[d] coordinates
     const uint32_t* rec;    // [n][rw] leaf-order records: coordinates, row, 0...
+    const uint32_t* nbox;   // [2^(L+1)][2d] box of heap node h at h*2d (leaves: = bbox);
+                            // null when only the leaf boxes exist
 };
 
 inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
@@ -119,9 +121,10 @@ struct pg_tree {
     uint32_t* pts = nullptr;
     int32_t* pidx = nullptr;
     uint32_t* split = nullptr;
+    uint32_t* nbox = nullptr;  // allocation of every node's box; bbox points into it
     uint32_t* bbox = nullptr;
     uint32_t* rec = nullptr;
     pg::TreeView view() const {
-        return pg::TreeView{n, d, L, pg::record_words(d), pts, pidx, split, bbox, rec};
+        return pg::TreeView{n, d, L, pg::record_words(d), pts, pidx, split, bbox, rec, nbox};
     }
 };

@@ -2,6 +2,7 @@
 // "Data-Parallel k-NN").  In all-points mode lane i takes the tree's own
 // leaf-order point i, so the lanes of a wave hold neighbouring points and
 // walk nearly the same nodes; the result row is the point's input row.
+#include "scan.hpp"
 #include "search.hpp"
 #include "wave.hpp"
 
@@ -13,12 +14,16 @@ constexpr int kNT = 256;
 
 template <typename T, int MD, int KT, bool EX>
 __global__ void __launch_bounds__(kNT)
-knn_static_kernel(TreeView tv, const uint32_t* __restrict__ queries, int64_t m, int k, int all,
+knn_static_kernel(TreeView tv, const uint32_t* __restrict__ queries,
+                  const int32_t* __restrict__ order, int64_t m, int k, int all,
                   int32_t* __restrict__ out_idx, typename Metric<T>::D* __restrict__ out_dist) {
     using M = Metric<T>;
     const int d = MD < 8 ? MD : tv.d;
-    const int64_t i = xcd_block() * kNT + threadIdx.x;
-    if (i >= m) return;
+    const int64_t i0 = xcd_block() * kNT + threadIdx.x;
+    if (i0 >= m) return;
+    // queries are taken in leaf order when an order is given (neighbouring
+    // lanes then walk nearly the same nodes); results go to the query's row
+    const int64_t i = order ? (int64_t)order[i0] : i0;
     T q[MD];
 #pragma unroll
     for (int c = 0; c < MD; c++) {
@@ -40,6 +45,41 @@ knn_static_kernel(TreeView tv, const uint32_t* __restrict__ queries, int64_t m, 
     }
 }
 
+// Sort key of each query: the leaf its descent reaches (left below the
+// split, right at or above it), coarsened by `shift` bits.
+__global__ void query_leaf_kernel(TreeView tv, int fl, const uint32_t* __restrict__ queries,
+                                  int64_t m, int shift, uint32_t* __restrict__ key) {
+    const int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x;
+    if (i >= m) return;
+    const int d = tv.d;
+    const uint32_t first_leaf = 1u << tv.L;
+    uint32_t cur = 1;
+    int dim = 0;
+    while (cur < first_leaf) {
+        const uint32_t qb = queries[i * d + dim], sb = tv.split[cur];
+        const bool right = fl ? __uint_as_float(qb) >= __uint_as_float(sb) : (int32_t)qb >= (int32_t)sb;
+        cur = 2u * cur + (right ? 1u : 0u);
+        dim = dim + 1 == d ? 0 : dim + 1;
+    }
+    key[i] = (cur - first_leaf) >> shift;
+}
+
+__global__ void bucket_count_kernel(const uint32_t* __restrict__ key, int64_t m,
+                                    uint32_t* __restrict__ cnt) {
+    const int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x;
+    if (i < m) atomicAdd(&cnt[key[i]], 1u);
+}
+
+__global__ void bucket_fill_kernel(const uint32_t* __restrict__ key, int64_t m,
+                                   const uint32_t* __restrict__ start, uint32_t* __restrict__ cursor,
+                                   int32_t* __restrict__ order) {
+    const int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x;
+    if (i < m) {
+        const uint32_t b = key[i];
+        order[start[b] + atomicAdd(&cursor[b], 1u)] = (int32_t)i;
+    }
+}
+
 __global__ void check_queries_kernel(const uint32_t* __restrict__ q, int64_t count, int fl,
                                      uint32_t* __restrict__ err) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -53,12 +93,12 @@ __global__ void check_queries_kernel(const uint32_t* __restrict__ q, int64_t cou
 }
 
 template <typename T, int MD, int KT, bool EX>
-pg_status launch_static(const pg_tree* t, const void* queries, int64_t m, int k, bool all,
-                        int32_t* out_idx, void* out_dist, hipStream_t s) {
+pg_status launch_static(const pg_tree* t, const void* queries, const int32_t* order, int64_t m,
+                        int k, bool all, int32_t* out_idx, void* out_dist, hipStream_t s) {
     using DT = typename Metric<T>::D;
     hipLaunchKernelGGL((knn_static_kernel<T, MD, KT, EX>), dim3(grid_for_xcd(cdiv(m, kNT))),
-                       dim3(kNT), 0, s, t->view(), (const uint32_t*)queries, m, k, all ? 1 : 0,
-                       out_idx, (DT*)out_dist);
+                       dim3(kNT), 0, s, t->view(), (const uint32_t*)queries, order, m, k,
+                       all ? 1 : 0, out_idx, (DT*)out_dist);
     PG_LAUNCH_CHECK();
     return PG_OK;
 }
@@ -66,27 +106,27 @@ pg_status launch_static(const pg_tree* t, const void* queries, int64_t m, int k,
 // k-list capacities: exact lists for the common k = 5, 10, 16, otherwise the
 // next power of two with uniform guards.
 template <typename T, int MD>
-pg_status dispatch_k(const pg_tree* t, const void* q, int64_t m, int k, bool all, int32_t* oi,
-                     void* od, hipStream_t s) {
-    if (k == 5) return launch_static<T, MD, 5, true>(t, q, m, k, all, oi, od, s);
-    if (k == 10) return launch_static<T, MD, 10, true>(t, q, m, k, all, oi, od, s);
-    if (k == 16) return launch_static<T, MD, 16, true>(t, q, m, k, all, oi, od, s);
-    if (k <= 2) return launch_static<T, MD, 2, false>(t, q, m, k, all, oi, od, s);
-    if (k <= 4) return launch_static<T, MD, 4, false>(t, q, m, k, all, oi, od, s);
-    if (k <= 8) return launch_static<T, MD, 8, false>(t, q, m, k, all, oi, od, s);
-    if (k <= 16) return launch_static<T, MD, 16, false>(t, q, m, k, all, oi, od, s);
-    if (k <= 32) return launch_static<T, MD, 32, false>(t, q, m, k, all, oi, od, s);
-    return launch_static<T, MD, 64, false>(t, q, m, k, all, oi, od, s);
+pg_status dispatch_k(const pg_tree* t, const void* q, const int32_t* o, int64_t m, int k, bool all,
+                     int32_t* oi, void* od, hipStream_t s) {
+    if (k == 5) return launch_static<T, MD, 5, true>(t, q, o, m, k, all, oi, od, s);
+    if (k == 10) return launch_static<T, MD, 10, true>(t, q, o, m, k, all, oi, od, s);
+    if (k == 16) return launch_static<T, MD, 16, true>(t, q, o, m, k, all, oi, od, s);
+    if (k <= 2) return launch_static<T, MD, 2, false>(t, q, o, m, k, all, oi, od, s);
+    if (k <= 4) return launch_static<T, MD, 4, false>(t, q, o, m, k, all, oi, od, s);
+    if (k <= 8) return launch_static<T, MD, 8, false>(t, q, o, m, k, all, oi, od, s);
+    if (k <= 16) return launch_static<T, MD, 16, false>(t, q, o, m, k, all, oi, od, s);
+    if (k <= 32) return launch_static<T, MD, 32, false>(t, q, o, m, k, all, oi, od, s);
+    return launch_static<T, MD, 64, false>(t, q, o, m, k, all, oi, od, s);
 }
 
 template <typename T>
-pg_status dispatch_d(const pg_tree* t, const void* q, int64_t m, int k, bool all, int32_t* oi,
-                     void* od, hipStream_t s) {
+pg_status dispatch_d(const pg_tree* t, const void* q, const int32_t* o, int64_t m, int k, bool all,
+                     int32_t* oi, void* od, hipStream_t s) {
     switch (t->d) {
-        case 2: return dispatch_k<T, 2>(t, q, m, k, all, oi, od, s);
-        case 3: return dispatch_k<T, 3>(t, q, m, k, all, oi, od, s);
-        case 5: return dispatch_k<T, 5>(t, q, m, k, all, oi, od, s);
-        default: return dispatch_k<T, 8>(t, q, m, k, all, oi, od, s);
+        case 2: return dispatch_k<T, 2>(t, q, o, m, k, all, oi, od, s);
+        case 3: return dispatch_k<T, 3>(t, q, o, m, k, all, oi, od, s);
+        case 5: return dispatch_k<T, 5>(t, q, o, m, k, all, oi, od, s);
+        default: return dispatch_k<T, 8>(t, q, o, m, k, all, oi, od, s);
     }
 }
 
@@ -108,11 +148,46 @@ pg_status check_queries(const void* q, int64_t m, int d, bool fl, hipStream_t s)
     return PG_OK;
 }
 
+pg_status order_queries(const TreeView& tv, bool fl, const void* queries, int64_t m,
+                        hipStream_t s, DevBuf& order) {
+    // buckets: the leaves, coarsened to about one bucket per 4 queries
+    int bits = 0;
+    while (bits < 24 && ((int64_t)1 << (bits + 1)) * 4 <= m) bits++;
+    const int shift = tv.L > bits ? tv.L - bits : 0;
+    const int64_t nb = ((int64_t)1 << tv.L) >> shift;
+    DevBuf key(s), cnt(s), start(s), cursor(s);
+    PG_TRY(key.alloc(sizeof(uint32_t) * m));
+    PG_TRY(cnt.alloc(sizeof(uint32_t) * nb));
+    PG_TRY(start.alloc(sizeof(uint32_t) * nb));
+    PG_TRY(cursor.alloc(sizeof(uint32_t) * nb));
+    PG_TRY(order.alloc(sizeof(int32_t) * m));
+    PG_HIP(hipMemsetAsync(cnt.p, 0, sizeof(uint32_t) * nb, s));
+    PG_HIP(hipMemsetAsync(cursor.p, 0, sizeof(uint32_t) * nb, s));
+    hipLaunchKernelGGL(query_leaf_kernel, dim3(cdiv(m, kNT)), dim3(kNT), 0, s, tv, fl ? 1 : 0,
+                       (const uint32_t*)queries, m, shift, key.as<uint32_t>());
+    PG_LAUNCH_CHECK();
+    hipLaunchKernelGGL(bucket_count_kernel, dim3(cdiv(m, kNT)), dim3(kNT), 0, s,
+                       key.as<uint32_t>(), m, cnt.as<uint32_t>());
+    PG_LAUNCH_CHECK();
+    PG_TRY(exclusive_scan_u32(cnt.as<uint32_t>(), start.as<uint32_t>(), nb, nullptr, s));
+    hipLaunchKernelGGL(bucket_fill_kernel, dim3(cdiv(m, kNT)), dim3(kNT), 0, s,
+                       key.as<uint32_t>(), m, start.as<uint32_t>(), cursor.as<uint32_t>(),
+                       order.as<int32_t>());
+    PG_LAUNCH_CHECK();
+    return PG_OK;
+}
+
 pg_status knn_static(const pg_tree* t, const void* queries, int64_t m, int k, bool all,
                      int32_t* out_idx, void* out_dist, hipStream_t s) {
     if (m == 0) return PG_OK;
-    if (t->dtype == PG_FLOAT32) return dispatch_d<float>(t, queries, m, k, all, out_idx, out_dist, s);
-    return dispatch_d<int32_t>(t, queries, m, k, all, out_idx, out_dist, s);
+    DevBuf order(s);
+    const int32_t* o = nullptr;
+    if (!all && m >= kOrderMin && t->n > 0) {
+        PG_TRY(order_queries(t->view(), t->dtype == PG_FLOAT32, queries, m, s, order));
+        o = order.as<int32_t>();
+    }
+    if (t->dtype == PG_FLOAT32) return dispatch_d<float>(t, queries, o, m, k, all, out_idx, out_dist, s);
+    return dispatch_d<int32_t>(t, queries, o, m, k, all, out_idx, out_dist, s);
 }
 
 }  // namespace pg

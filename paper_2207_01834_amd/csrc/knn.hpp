@@ -99,6 +99,15 @@ struct KList {
 };
 
 // Host entry points.
+
+// Queries below this count are searched in the caller's order.
+constexpr int64_t kOrderMin = 4096;
+
+// A permutation of the m queries that follows the leaf order of tree tv (a
+// counting sort by the leaf each query's descent reaches); order receives
+// m int32 query indices.
+pg_status order_queries(const TreeView& tv, bool fl, const void* queries, int64_t m,
+                        hipStream_t s, DevBuf& order);
 pg_status knn_static(const pg_tree* t, const void* queries, int64_t m, int k, bool all_points,
                      int32_t* out_idx, void* out_dist, hipStream_t s);
 

@@ -15,8 +15,11 @@
 //     path counts as the first-visited child (the split-plane bound is valid
 //     for the other child whichever side the query lies on, since a point on
 //     the wrong side can only lie on the plane);
-//   * a leaf is scanned only when the squared distance from the query to the
-//     leaf's bounding box does not exceed the current k-th distance;
+//   * entering the other child also needs the squared distance from the
+//     query to that child's bounding box to be at most the current k-th
+//     distance (the subtree-box test of Appendix C; the plane test alone lets
+//     a query beside a dense cluster walk every node of it), and a leaf is
+//     scanned only when the same holds for the leaf's box;
 //   * leaf points are read as packed records (coordinates + row: one 16-byte
 //     load for d <= 3), the next record is requested before the current one
 //     is used;
@@ -100,8 +103,22 @@ __device__ inline void kd_search(const TreeView& tv, const Ids& ids, const T (&q
             } else {
                 uint32_t first = nearc;
                 if (self && (start >> (L - lvl)) == cur) first = start >> (L - lvl - 1);
-                if (prev == first && !(M::sq(qd, s) > kl.kd)) next = first ^ 1u;
-                else next = cur >> 1;
+                if (prev == first && !(M::sq(qd, s) > kl.kd)) {
+                    next = first ^ 1u;
+                    // an internal far child is entered only when its box
+                    // reaches the k-th distance (leaves are tested on arrival)
+                    if (tv.nbox != nullptr && next < first_leaf) {
+                        const uint32_t* nb = tv.nbox + (size_t)next * 2 * d;
+                        DT lb = 0;
+#pragma unroll
+                        for (int c = 0; c < MD; c++)
+                            if (MD < 8 || c < d)
+                                lb = M::acc_gap(lb, q[c], M::load(nb[c]), M::load(nb[d + c]));
+                        if (lb > kl.kd) next = cur >> 1;
+                    }
+                } else {
+                    next = cur >> 1;
+                }
             }
             if (next > cur) {
                 lvl++;
