@@ -168,16 +168,17 @@ __device__ inline void query_item(const BatchParams& P, int64_t q, int* s_ok) {
     float q_[MD];
 #pragma unroll
     for (int cc = 0; cc < MD; cc++) q_[cc] = cc < d ? M::load(tv.pts[(int64_t)cc * D.n + i]) : 0.0f;
-    KList<float, int32_t, KT, EX> kl;
-    kl.init(M::inf(), INT32_MAX);
-    kd_search<float, MD, KT, EX, int32_t>(tv, PlainIds{}, q_, d, kl, k,
+    PackedList<float, KT, EX> kl;
+    kl.init(32);
+    kd_search<float, MD>(tv, PlainIds{}, q_, d, kl, k,
                                           (1u << D.L) + leaf_of(D.n, D.L, i));
     const int64_t row = D.row + tv.pidx[i];
 #pragma unroll
     for (int s = 0; s < KT; s++) {
         if (EX || s < k) {
-            P.out_idx[row * k + s] = kl.id[s] == INT32_MAX ? -1 : (int32_t)(D.row + kl.id[s]);
-            P.out_d2[row * k + s] = kl.d[s];
+            const int32_t id = kl.id_of(kl.key[s]);
+            P.out_idx[row * k + s] = id < 0 ? -1 : (int32_t)(D.row + id);
+            P.out_d2[row * k + s] = kl.dist_of(kl.key[s]);
         }
     }
 }

@@ -174,7 +174,7 @@ bdl_knn_kernel(Forest f, const uint32_t* __restrict__ queries, const int32_t* __
     KList<typename M::D, int64_t, KT, EX> kl;
     kl.init(M::inf(), INT64_MAX);
     for (int t = 0; t < f.count; t++)
-        kd_search<T, MD, KT, EX, int64_t>(f.s[t].tv, BdlIds{f.s[t].ids, f.s[t].alive}, q, d, kl, k);
+        kd_search<T, MD>(f.s[t].tv, BdlIds{f.s[t].ids, f.s[t].alive}, q, d, kl, k);
 #pragma unroll
     for (int s = 0; s < KT; s++) {
         if (EX || s < k) {

@@ -12,12 +12,26 @@ namespace {
 
 constexpr int kNT = 256;
 
+template <typename T, int MD>
+__device__ inline void load_query(const TreeView& tv, const uint32_t* queries, int all, int64_t i,
+                                  int d, T (&q)[MD]) {
+#pragma unroll
+    for (int c = 0; c < MD; c++) {
+        uint32_t b = 0;
+        if (MD < 8 || c < d) b = all ? tv.pts[(int64_t)c * tv.n + i] : queries[i * d + c];
+        q[c] = Metric<T>::load(b);
+    }
+}
+
+// Searches with packed (distance, id) keys.  A query whose k-th key ends
+// clamped (int32 coordinates: a distance of 2^(64-B) or more, or fewer than
+// k points) is appended to `redo` for knn_redo_kernel instead of written.
 template <typename T, int MD, int KT, bool EX>
 __global__ void __launch_bounds__(kNT)
 knn_static_kernel(TreeView tv, const uint32_t* __restrict__ queries,
-                  const int32_t* __restrict__ order, int64_t m, int k, int all,
-                  int32_t* __restrict__ out_idx, typename Metric<T>::D* __restrict__ out_dist) {
-    using M = Metric<T>;
+                  const int32_t* __restrict__ order, int64_t m, int k, int all, int idbits,
+                  int32_t* __restrict__ out_idx, typename Metric<T>::D* __restrict__ out_dist,
+                  int32_t* __restrict__ redo, uint32_t* __restrict__ nredo) {
     const int d = MD < 8 ? MD : tv.d;
     const int64_t i0 = xcd_block() * kNT + threadIdx.x;
     if (i0 >= m) return;
@@ -25,22 +39,50 @@ knn_static_kernel(TreeView tv, const uint32_t* __restrict__ queries,
     // lanes then walk nearly the same nodes); results go to the query's row
     const int64_t i = order ? (int64_t)order[i0] : i0;
     T q[MD];
-#pragma unroll
-    for (int c = 0; c < MD; c++) {
-        uint32_t b = 0;
-        if (MD < 8 || c < d) b = all ? tv.pts[(int64_t)c * tv.n + i] : queries[i * d + c];
-        q[c] = M::load(b);
-    }
-    KList<typename M::D, int32_t, KT, EX> kl;
-    kl.init(M::inf(), INT32_MAX);
+    load_query<T, MD>(tv, queries, all, i, d, q);
+    PackedList<T, KT, EX> kl;
+    kl.init(idbits);
     const uint32_t start = all ? (1u << tv.L) + leaf_of(tv.n, tv.L, i) : 0u;
-    kd_search<T, MD, KT, EX, int32_t>(tv, PlainIds{}, q, d, kl, k, start);
+    kd_search<T, MD>(tv, PlainIds{}, q, d, kl, k, start);
+    if (kl.clamped()) {
+        redo[atomicAdd(nredo, 1u)] = (int32_t)i;
+        return;
+    }
     const int64_t row = all ? (int64_t)tv.pidx[i] : i;
 #pragma unroll
     for (int s = 0; s < KT; s++) {
         if (EX || s < k) {
-            out_idx[row * k + s] = kl.id[s] == INT32_MAX ? -1 : kl.id[s];
-            out_dist[row * k + s] = kl.d[s];
+            out_idx[row * k + s] = kl.id_of(kl.key[s]);
+            out_dist[row * k + s] = kl.dist_of(kl.key[s]);
+        }
+    }
+}
+
+// The queries knn_static_kernel left clamped, searched with exact
+// (distance, id) pairs.
+template <typename T, int MD, int KT, bool EX>
+__global__ void __launch_bounds__(kNT)
+knn_redo_kernel(TreeView tv, const uint32_t* __restrict__ queries, int k, int all,
+                const int32_t* __restrict__ redo, const uint32_t* __restrict__ nredo,
+                int32_t* __restrict__ out_idx, typename Metric<T>::D* __restrict__ out_dist) {
+    using M = Metric<T>;
+    const int d = MD < 8 ? MD : tv.d;
+    const int64_t cnt = *nredo;
+    for (int64_t r = (int64_t)blockIdx.x * kNT + threadIdx.x; r < cnt; r += (int64_t)gridDim.x * kNT) {
+        const int64_t i = redo[r];
+        T q[MD];
+        load_query<T, MD>(tv, queries, all, i, d, q);
+        KList<typename M::D, int32_t, KT, EX> kl;
+        kl.init(M::inf(), INT32_MAX);
+        const uint32_t start = all ? (1u << tv.L) + leaf_of(tv.n, tv.L, i) : 0u;
+        kd_search<T, MD>(tv, PlainIds{}, q, d, kl, k, start);
+        const int64_t row = all ? (int64_t)tv.pidx[i] : i;
+#pragma unroll
+        for (int s = 0; s < KT; s++) {
+            if (EX || s < k) {
+                out_idx[row * k + s] = kl.id[s] == INT32_MAX ? -1 : kl.id[s];
+                out_dist[row * k + s] = kl.d[s];
+            }
         }
     }
 }
@@ -92,14 +134,30 @@ __global__ void check_queries_kernel(const uint32_t* __restrict__ q, int64_t cou
     if (__ballot(bad) != 0 && lane_id() == 0) atomicOr(err, 1u);
 }
 
+constexpr unsigned kRedoBlocks = 512;
+
 template <typename T, int MD, int KT, bool EX>
 pg_status launch_static(const pg_tree* t, const void* queries, const int32_t* order, int64_t m,
                         int k, bool all, int32_t* out_idx, void* out_dist, hipStream_t s) {
     using DT = typename Metric<T>::D;
+    constexpr bool exact = PackedList<T, KT, EX>::kFloat;  // no clamping: no redo pass
+    DevBuf redo(s), nredo(s);
+    if (!exact) {
+        PG_TRY(redo.alloc(sizeof(int32_t) * m));
+        PG_TRY(nredo.alloc(sizeof(uint32_t)));
+        PG_HIP(hipMemsetAsync(nredo.p, 0, sizeof(uint32_t), s));
+    }
     hipLaunchKernelGGL((knn_static_kernel<T, MD, KT, EX>), dim3(grid_for_xcd(cdiv(m, kNT))),
                        dim3(kNT), 0, s, t->view(), (const uint32_t*)queries, order, m, k,
-                       all ? 1 : 0, out_idx, (DT*)out_dist);
+                       all ? 1 : 0, id_bits(t->n), out_idx, (DT*)out_dist, redo.as<int32_t>(),
+                       nredo.as<uint32_t>());
     PG_LAUNCH_CHECK();
+    if (!exact) {
+        hipLaunchKernelGGL((knn_redo_kernel<T, MD, KT, EX>), dim3(kRedoBlocks), dim3(kNT), 0, s,
+                           t->view(), (const uint32_t*)queries, k, all ? 1 : 0,
+                           redo.as<int32_t>(), nredo.as<uint32_t>(), out_idx, (DT*)out_dist);
+        PG_LAUNCH_CHECK();
+    }
     return PG_OK;
 }
 

@@ -73,6 +73,10 @@ struct KList {
     }
     // True when (dd, ii) belongs in the list.
     __device__ inline bool admits(DT dd, IT ii) const { return less(dd, ii, kd, kid); }
+    // Adds (dd, ii) when it belongs in the list.
+    __device__ inline void offer(DT dd, IT ii, int k) {
+        if (admits(dd, ii)) insert(dd, ii, k);
+    }
     // Inserts (dd, ii); requires admits(dd, ii).
     // Slot s receives the old slot s-1 when the new key sorts before it, the
     // new key when it sorts before the old slot s but not before slot s-1,
@@ -97,6 +101,78 @@ struct KList {
         }
     }
 };
+
+// Sorted list of the k best keys, each (squared distance, id) packed into one
+// 64-bit word -- the distance in the high bits, the id (< 2^B) in the low B --
+// so that one unsigned compare orders two (distance, id) pairs and moving an
+// entry is one 64-bit select.  float32: the distance's bits (non-negative, so
+// ordered as unsigned) over a 32-bit id: exact.  int32 coordinates: the
+// int64 distance clamped to 2^(64-B) - 1; a clamped distance is ambiguous, so
+// a search whose k-th key ends clamped (or unfilled) is redone with KList.
+// Pruning with the clamped radius only discards points beyond the clamp, which
+// cannot be in a list whose k-th key is not clamped.
+template <typename T, int KT, bool EX>
+struct PackedList {
+    using DT = typename Metric<T>::D;
+    static constexpr bool kFloat = sizeof(DT) == 4;
+    static constexpr uint64_t kEmpty = kFloat ? 0x7f800000ffffffffull : ~0ull;
+    uint64_t key[KT];
+    uint64_t kk;  // key of slot k-1
+    DT kd;        // its distance: the pruning radius, squared
+    int B;        // id bits
+
+    __device__ inline void init(int idbits) {
+        B = kFloat ? 32 : idbits;
+#pragma unroll
+        for (int s = 0; s < KT; s++) key[s] = kEmpty;
+        kk = kEmpty;
+        kd = dist_of(kEmpty);
+    }
+    __device__ inline DT dist_of(uint64_t x) const {
+        if constexpr (kFloat) return __uint_as_float((uint32_t)(x >> 32));
+        else return (DT)(x >> B);
+    }
+    __device__ inline int32_t id_of(uint64_t x) const {
+        return (int32_t)(uint32_t)(x & (~0ull >> (64 - B)));
+    }
+    // True when the k-th key may not be exact (int32 coordinates only).
+    __device__ inline bool clamped() const {
+        if constexpr (kFloat) return false;
+        else return (kk >> B) == (~0ull >> B);
+    }
+    __device__ inline void offer(DT dd, int32_t ii, int k) {
+        uint64_t x;
+        if constexpr (kFloat) {
+            x = ((uint64_t)__float_as_uint(dd) << 32) | (uint32_t)ii;
+        } else {
+            const uint64_t c = ~0ull >> B, du = (uint64_t)dd;
+            x = ((du < c ? du : c) << B) | (uint32_t)ii;
+        }
+        if (x < kk) insert(x, k);
+    }
+    __device__ inline void insert(uint64_t x, int k) {
+        bool before_cur = true;
+#pragma unroll
+        for (int s = KT - 1; s >= 0; --s) {
+            if (EX || s < k) {
+                const int p = s > 0 ? s - 1 : 0;
+                const bool before_prev = s > 0 && x < key[p];
+                const uint64_t nk = before_prev ? key[p] : (before_cur ? x : key[s]);
+                key[s] = nk;
+                if (EX ? s == KT - 1 : s == k - 1) kk = nk;
+                before_cur = before_prev;
+            }
+        }
+        kd = dist_of(kk);
+    }
+};
+
+// Id bits of the packed keys of a tree of n points (ids are rows < n).
+inline int id_bits(int64_t n) {
+    int b = 1;
+    while (b < 31 && ((int64_t)1 << b) < n) b++;
+    return b;
+}
 
 // Host entry points.
 

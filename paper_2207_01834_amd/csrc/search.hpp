@@ -23,7 +23,8 @@
 //   * leaf points are read as packed records (coordinates + row: one 16-byte
 //     load for d <= 3), the next record is requested before the current one
 //     is used;
-//   * candidates go into a register-resident sorted k-list (KList).
+//   * candidates go into a register-resident sorted k-list (KList, or
+//     PackedList where ids fit beside the distance in 64 bits).
 #pragma once
 
 #include "knn.hpp"
@@ -78,10 +79,9 @@ __device__ inline uint32_t leaf_of(int64_t n, int L, int64_t i) {
 
 // k-NN walk of one query.  start: 0 = from the root; otherwise the heap index
 // of the leaf holding the query (all-points mode).
-template <typename T, int MD, int KT, bool EX, typename IT, typename Ids>
+template <typename T, int MD, typename List, typename Ids>
 __device__ inline void kd_search(const TreeView& tv, const Ids& ids, const T (&q)[MD], int d,
-                                 KList<typename Metric<T>::D, IT, KT, EX>& kl, int k,
-                                 uint32_t start = 0) {
+                                 List& kl, int k, uint32_t start = 0) {
     using M = Metric<T>;
     using DT = typename M::D;
     const int64_t n = tv.n;
@@ -153,8 +153,7 @@ __device__ inline void kd_search(const TreeView& tv, const Ids& ids, const T (&q
 #pragma unroll
                     for (int c = 0; c < MD; c++)
                         if (MD < 8 || c < d) dd = M::acc(dd, q[c], p[c]);
-                    const IT id = ids.id(i, idw);
-                    if (kl.admits(dd, id)) kl.insert(dd, id, k);
+                    kl.offer(dd, ids.id(i, idw), k);
                 }
 #pragma unroll
                 for (int c = 0; c < MD; c++) p[c] = pn[c];

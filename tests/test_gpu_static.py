@@ -122,6 +122,25 @@ def test_ties_identical_grid_planes(pg, dev):
     run_case(pg, dev, planes, 12, 8, queries=planes[:500].copy())
 
 
+def test_wide_distances_exact_redo(pg, dev):
+    # int32 searches order packed (distance, id) keys with the distance
+    # clamped to 64 - ceil(log2 n) bits; queries whose k-th distance reaches
+    # the clamp are searched again with exact pairs.  Full-range coordinates
+    # make most k-th distances exceed the clamp, a dense core next to them
+    # mixes clamped and exact queries in one wave.
+    g = np.random.default_rng(11)
+    lo, hi = -(1 << 29), (1 << 29)
+    wide = g.integers(lo, hi, size=(20000, 3)).astype(np.int32)
+    run_case(pg, dev, wide, 10, 16)
+    core = g.integers(0, 1 << 12, size=(15000, 3)).astype(np.int32)
+    mixed = np.concatenate([core, wide[:5000]])
+    g.shuffle(mixed)
+    run_case(pg, dev, mixed, 10, 16)
+    q = np.concatenate([g.integers(lo, hi, size=(3000, 3)), g.integers(0, 1 << 12, size=(3000, 3))]).astype(np.int32)
+    run_case(pg, dev, mixed, 7, 8, queries=q, check_tree=False)
+    run_case(pg, dev, g.integers(lo, hi, size=(5000, 8)).astype(np.int32), 16, 16)
+
+
 def test_wide_and_middle_levels(pg, dev):
     # 1.2M points: levels 0-8 take the multi-workgroup path, level 9 the
     # one-workgroup-per-node path, the rest the LDS subtree path.
