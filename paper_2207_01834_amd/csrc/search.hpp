@@ -20,6 +20,7 @@
 //     distance (the subtree-box test of Appendix C; the plane test alone lets
 //     a query beside a dense cluster walk every node of it), and a leaf is
 //     scanned only when the same holds for the leaf's box;
+//   * a lane may walk one leaf ahead of its scans (see kd_search);
 //   * leaf points are read as packed records (coordinates + row: one 16-byte
 //     load for d <= 3), the next record is requested before the current one
 //     is used;
@@ -79,6 +80,14 @@ __device__ inline uint32_t leaf_of(int64_t n, int L, int64_t i) {
 
 // k-NN walk of one query.  start: 0 = from the root; otherwise the heap index
 // of the leaf holding the query (all-points mode).
+//
+// The walk (cur, entered from prev: its parent when prev < cur) hands leaves
+// to a scan phase.  A lane holds up to two reached-but-unscanned leaves: all
+// lanes walk while some lane has none, so a lane that reaches its leaf early
+// walks on to its next one instead of idling (that step sees the k-th
+// distance before the pending scan: it may enter more nodes, never fewer).
+// Stepping into a leaf only records it; the walk then stands at the leaf's
+// parent as if back from it.
 template <typename T, int MD, typename List, typename Ids>
 __device__ inline void kd_search(const TreeView& tv, const Ids& ids, const T (&q)[MD], int d,
                                  List& kl, int k, uint32_t start = 0) {
@@ -88,83 +97,97 @@ __device__ inline void kd_search(const TreeView& tv, const Ids& ids, const T (&q
     if (n == 0) return;
     const int L = tv.L;
     const uint32_t first_leaf = 1u << L;
-    const bool self = start != 0;
-    uint32_t cur = self ? start : 1u, prev = 0;
-    int lvl = self ? L : 0;
-    int dim = lvl % d;
-    while (cur != 0) {
-        while (cur != 0 && cur < first_leaf) {
-            const T s = M::load(tv.split[cur]);
-            const T qd = pick<MD>(q, dim);
-            const uint32_t nearc = 2u * cur + (qd >= s ? 1u : 0u);
-            uint32_t next;
-            if (prev == (cur >> 1) && !(self && (start >> (L - lvl)) == cur)) {
-                next = nearc;
-            } else {
-                uint32_t first = nearc;
-                if (self && (start >> (L - lvl)) == cur) first = start >> (L - lvl - 1);
-                if (prev == first && !(M::sq(qd, s) > kl.kd)) {
-                    next = first ^ 1u;
-                    // an internal far child is entered only when its box
-                    // reaches the k-th distance (leaves are tested on arrival)
-                    if (tv.nbox != nullptr && next < first_leaf) {
-                        const uint32_t* nb = tv.nbox + (size_t)next * 2 * d;
-                        DT lb = 0;
+    uint32_t cur, prev, p0, p1 = 0;
+    if (start != 0) {
+        p0 = start;
+        prev = start;
+        cur = start >> 1;
+    } else if (L == 0) {
+        p0 = 1;
+        prev = 0;
+        cur = 0;
+    } else {
+        p0 = 0;
+        prev = 0;
+        cur = 1;
+    }
+    bool more;
+    do {
+        while (__ballot(p0 == 0 && cur != 0) != 0) {
+            if (cur != 0 && p1 == 0) {
+                const int lvl = 31 - __clz(cur);
+                const T s = M::load(tv.split[cur]);
+                const T qd = pick<MD>(q, MD < 8 ? lvl % MD : lvl % d);
+                const uint32_t nearc = 2u * cur + (qd >= s ? 1u : 0u);
+                uint32_t next = nearc;
+                if (prev > cur) {
+                    // back from child prev: the other child is due when prev
+                    // was entered first -- the start leaf's side on its path,
+                    // the query's side elsewhere -- and is not out of reach
+                    const bool prev_on_path = (start >> (L - lvl - 1)) == prev;
+                    const bool cur_on_path = (start >> (L - lvl)) == cur;
+                    const bool from_first = prev_on_path || (!cur_on_path && prev == nearc);
+                    next = cur >> 1;
+                    if (from_first && !(M::sq(qd, s) > kl.kd)) {
+                        const uint32_t other = prev ^ 1u;
+                        bool reach = true;
+                        if (tv.nbox != nullptr && other < first_leaf) {
+                            const uint32_t* nb = tv.nbox + (size_t)other * 2 * d;
+                            DT lb = 0;
+#pragma unroll
+                            for (int c = 0; c < MD; c++)
+                                if (MD < 8 || c < d)
+                                    lb = M::acc_gap(lb, q[c], M::load(nb[c]), M::load(nb[d + c]));
+                            reach = !(lb > kl.kd);
+                        }
+                        if (reach) next = other;
+                    }
+                }
+                if (next >= first_leaf) {
+                    if (p0 == 0) p0 = next;
+                    else p1 = next;
+                    prev = next;
+                } else {
+                    prev = cur;
+                    cur = next;
+                }
+            }
+        }
+        more = __ballot(p0 != 0) != 0;
+        if (p0 != 0) {
+            const uint32_t leaf = p0 - first_leaf;
+            const uint32_t* bb = tv.bbox + (size_t)leaf * 2 * d;
+            DT lb = 0;
+#pragma unroll
+            for (int c = 0; c < MD; c++)
+                if (MD < 8 || c < d) lb = M::acc_gap(lb, q[c], M::load(bb[c]), M::load(bb[d + c]));
+            if (!(lb > kl.kd)) {
+                const int64_t lo = node_start(n, L, leaf), hi = node_start(n, L, leaf + 1);
+                T p[MD];
+                uint32_t idw = 0;
+                if (lo < hi) load_point<T, MD>(tv, lo, d, p, idw);
+                for (int64_t i = lo; i < hi; i++) {
+                    T pn[MD];
+                    uint32_t idn = 0;
+#pragma unroll
+                    for (int c = 0; c < MD; c++) pn[c] = p[c];
+                    if (i + 1 < hi) load_point<T, MD>(tv, i + 1, d, pn, idn);
+                    if (ids.live(i)) {
+                        DT dd = 0;
 #pragma unroll
                         for (int c = 0; c < MD; c++)
-                            if (MD < 8 || c < d)
-                                lb = M::acc_gap(lb, q[c], M::load(nb[c]), M::load(nb[d + c]));
-                        if (lb > kl.kd) next = cur >> 1;
+                            if (MD < 8 || c < d) dd = M::acc(dd, q[c], p[c]);
+                        kl.offer(dd, ids.id(i, idw), k);
                     }
-                } else {
-                    next = cur >> 1;
+#pragma unroll
+                    for (int c = 0; c < MD; c++) p[c] = pn[c];
+                    idw = idn;
                 }
             }
-            if (next > cur) {
-                lvl++;
-                dim = (dim + 1 == d) ? 0 : dim + 1;
-            } else {
-                lvl--;
-                dim = (dim == 0) ? d - 1 : dim - 1;
-            }
-            prev = cur;
-            cur = next;
         }
-        if (cur == 0) break;
-        const uint32_t leaf = cur - first_leaf;
-        const uint32_t* bb = tv.bbox + (size_t)leaf * 2 * d;
-        DT lb = 0;
-#pragma unroll
-        for (int c = 0; c < MD; c++)
-            if (MD < 8 || c < d) lb = M::acc_gap(lb, q[c], M::load(bb[c]), M::load(bb[d + c]));
-        if (!(lb > kl.kd)) {
-            const int64_t lo = node_start(n, L, leaf), hi = node_start(n, L, leaf + 1);
-            T p[MD];
-            uint32_t idw = 0;
-            if (lo < hi) load_point<T, MD>(tv, lo, d, p, idw);
-            for (int64_t i = lo; i < hi; i++) {
-                T pn[MD];
-                uint32_t idn = 0;
-#pragma unroll
-                for (int c = 0; c < MD; c++) pn[c] = p[c];
-                if (i + 1 < hi) load_point<T, MD>(tv, i + 1, d, pn, idn);
-                if (ids.live(i)) {
-                    DT dd = 0;
-#pragma unroll
-                    for (int c = 0; c < MD; c++)
-                        if (MD < 8 || c < d) dd = M::acc(dd, q[c], p[c]);
-                    kl.offer(dd, ids.id(i, idw), k);
-                }
-#pragma unroll
-                for (int c = 0; c < MD; c++) p[c] = pn[c];
-                idw = idn;
-            }
-        }
-        prev = cur;
-        cur >>= 1;
-        lvl--;
-        dim = (dim == 0) ? d - 1 : dim - 1;
-    }
+        p0 = p1;
+        p1 = 0;
+    } while (more);
 }
 
 // Workgroup index for a grid whose size is a multiple of 8: consecutive
