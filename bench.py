@@ -49,7 +49,7 @@ def log(*a):
 
 def knn_source_hash():
     h = hashlib.sha256()
-    for f in ("knn.hip", "search.hpp", "knn.hpp", "common.hpp"):
+    for f in ("knn.hip", "search.hpp", "knn.hpp", "common.hpp", "wave.hpp"):
         with open(os.path.join(ROOT, "paper_2207_01834_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -66,6 +66,46 @@ def measured_traffic(dtype):
     if rec.get("source_hash") != knn_source_hash():
         return None
     return rec.get("hbm_bytes_per_launch")
+
+
+def write_traffic(fetch_csv, write_csv, dtype, mib, command):
+    """Turns two rocprofv3 --pmc counter CSVs (FETCH_SIZE, WRITE_SIZE; KiB per
+    dispatch) of a bench run with the copy probe into the traffic summary the
+    roofline line reads.  Each counter is scaled by what it reads for the
+    probe's device copy, which moves `mib` MiB in and `mib` MiB out."""
+    import csv
+    import statistics
+
+    def per_kernel(path):
+        rows = list(csv.DictReader(open(path)))
+        knn = [float(r["Counter_Value"]) for r in rows if "knn_static_kernel" in r["Kernel_Name"]]
+        cp = [float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"]]
+        return knn, cp
+
+    fk, fc = per_kernel(fetch_csv)
+    wk, wc = per_kernel(write_csv)
+    want = mib * 1024.0  # KiB each way
+    # the probe's copies are the largest copy dispatches
+    fc = sorted(fc)[-5:]
+    wc = sorted(wc)[-5:]
+    f_scale = want / statistics.median(fc)
+    w_scale = want / statistics.median(wc)
+    f_kib, w_kib = statistics.median(fk), statistics.median(wk)
+    rec = {
+        "kernel": "knn_static_kernel (all-points)",
+        "workload": f"3-D n=10M {dtype} uniform, k=10, leaf 16",
+        "fetch_kib_per_launch": f_kib, "write_kib_per_launch": w_kib,
+        "fetch_scale": round(f_scale, 4), "write_scale": round(w_scale, 4),
+        "copy_probe_mib": mib,
+        "hbm_bytes_per_launch": (f_kib * f_scale + w_kib * w_scale) * 1024.0,
+        "source_hash": knn_source_hash(),
+        "command": command,
+    }
+    path = os.path.join(ROOT, "profiles", f"knn_all_{dtype}3d_10M_traffic.json")
+    with open(path, "w") as fh:
+        json.dump(rec, fh, indent=1)
+        fh.write("\n")
+    print(json.dumps(rec))
 
 
 def copy_probe(torch, dev, mib):
@@ -252,10 +292,18 @@ def main():
                     help="clouds timed for the per-cloud comparison (projected to 4,096)")
     ap.add_argument("--copy-probe-mib", type=int, default=1024,
                     help="size of the device copy that measures achievable HBM bandwidth (0: skip)")
+    ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write the k-NN traffic summary from two rocprofv3 --pmc counter "
+                         "CSVs (FETCH_SIZE, WRITE_SIZE) of a run of this script, then exit")
+    ap.add_argument("--traffic-command", default="",
+                    help="the profiling command recorded with --write-traffic")
     args = ap.parse_args()
+    if args.write_traffic:
+        write_traffic(args.write_traffic[0], args.write_traffic[1], args.dtype,
+                      args.copy_probe_mib, args.traffic_command)
+        return
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU: this library has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
