@@ -23,9 +23,9 @@ __device__ inline void load_query(const TreeView& tv, const uint32_t* queries, i
     }
 }
 
-// Searches with packed (distance, id) keys.  A query whose k-th key ends
-// clamped (int32 coordinates: a distance of 2^(64-B) or more, or fewer than
-// k points) is appended to `redo` for knn_redo_kernel instead of written.
+// Searches with packed (distance, id) keys.  A query whose k-th distance
+// reached the packed range's limit (int32 coordinates: 2^(64-B) - 1, or fewer
+// than k points) is appended to `redo` for knn_redo_kernel instead of written.
 template <typename T, int MD, int KT, bool EX>
 __global__ void __launch_bounds__(kNT)
 knn_static_kernel(TreeView tv, const uint32_t* __restrict__ queries,
@@ -44,7 +44,7 @@ knn_static_kernel(TreeView tv, const uint32_t* __restrict__ queries,
     kl.init(idbits);
     const uint32_t start = all ? (1u << tv.L) + leaf_of(tv.n, tv.L, i) : 0u;
     kd_search<T, MD>(tv, PlainIds{}, q, d, kl, k, start);
-    if (kl.clamped()) {
+    if (kl.needs_redo()) {
         redo[atomicAdd(nredo, 1u)] = (int32_t)i;
         return;
     }
@@ -58,7 +58,7 @@ knn_static_kernel(TreeView tv, const uint32_t* __restrict__ queries,
     }
 }
 
-// The queries knn_static_kernel left clamped, searched with exact
+// The queries knn_static_kernel handed over, searched with exact
 // (distance, id) pairs.
 template <typename T, int MD, int KT, bool EX>
 __global__ void __launch_bounds__(kNT)
@@ -140,7 +140,7 @@ template <typename T, int MD, int KT, bool EX>
 pg_status launch_static(const pg_tree* t, const void* queries, const int32_t* order, int64_t m,
                         int k, bool all, int32_t* out_idx, void* out_dist, hipStream_t s) {
     using DT = typename Metric<T>::D;
-    constexpr bool exact = PackedList<T, KT, EX>::kFloat;  // no clamping: no redo pass
+    constexpr bool exact = PackedList<T, KT, EX>::kFloat;  // float keys: no redo pass
     DevBuf redo(s), nredo(s);
     if (!exact) {
         PG_TRY(redo.alloc(sizeof(int32_t) * m));

@@ -107,10 +107,11 @@ struct KList {
 // so that one unsigned compare orders two (distance, id) pairs and moving an
 // entry is one 64-bit select.  float32: the distance's bits (non-negative, so
 // ordered as unsigned) over a 32-bit id: exact.  int32 coordinates: the
-// int64 distance clamped to 2^(64-B) - 1; a clamped distance is ambiguous, so
-// a search whose k-th key ends clamped (or unfilled) is redone with KList.
-// Pruning with the clamped radius only discards points beyond the clamp, which
-// cannot be in a list whose k-th key is not clamped.
+// int64 distance over B id bits, so only distances up to C = 2^(64-B) - 1
+// fit; the radius starts at C and a point farther than the radius never
+// enters, so every stored key is exact.  A search whose k-th key ends at C
+// (or unfilled) may have missed points beyond C and is redone with KList;
+// pruning with a radius of C only discards such points.
 template <typename T, int KT, bool EX>
 struct PackedList {
     using DT = typename Metric<T>::D;
@@ -135,20 +136,21 @@ struct PackedList {
     __device__ inline int32_t id_of(uint64_t x) const {
         return (int32_t)(uint32_t)(x & (~0ull >> (64 - B)));
     }
-    // True when the k-th key may not be exact (int32 coordinates only).
-    __device__ inline bool clamped() const {
+    // True when the k-th distance is C or the list is not full (int32
+    // coordinates only): the result may miss points beyond C.
+    __device__ inline bool needs_redo() const {
         if constexpr (kFloat) return false;
         else return (kk >> B) == (~0ull >> B);
     }
     __device__ inline void offer(DT dd, int32_t ii, int k) {
-        uint64_t x;
         if constexpr (kFloat) {
-            x = ((uint64_t)__float_as_uint(dd) << 32) | (uint32_t)ii;
+            const uint64_t x = ((uint64_t)__float_as_uint(dd) << 32) | (uint32_t)ii;
+            if (x < kk) insert(x, k);
         } else {
-            const uint64_t c = ~0ull >> B, du = (uint64_t)dd;
-            x = ((du < c ? du : c) << B) | (uint32_t)ii;
+            // exact whenever dd <= kd, since kd <= 2^(64-B) - 1
+            const uint64_t x = ((uint64_t)dd << B) | (uint32_t)ii;
+            if (!(dd > kd) && x < kk) insert(x, k);
         }
-        if (x < kk) insert(x, k);
     }
     __device__ inline void insert(uint64_t x, int k) {
         bool before_cur = true;

@@ -73,6 +73,20 @@ struct PlainIds {
     __device__ inline bool live(int64_t) const { return true; }
 };
 
+// Offers leaf-order point i (coordinates p, row word idw) to the k-list.
+template <typename T, int MD, typename List, typename Ids>
+__device__ inline void visit_point(const Ids& ids, const T (&q)[MD], int d, List& kl, int k,
+                                   uint32_t i, const T (&p)[MD], uint32_t idw) {
+    using M = Metric<T>;
+    if (ids.live(i)) {
+        typename M::D dd = 0;
+#pragma unroll
+        for (int c = 0; c < MD; c++)
+            if (MD < 8 || c < d) dd = M::acc(dd, q[c], p[c]);
+        kl.offer(dd, ids.id(i, idw), k);
+    }
+}
+
 // Leaf j of a tree with n points at depth L that holds leaf-order position i.
 __device__ inline uint32_t leaf_of(int64_t n, int L, int64_t i) {
     return (uint32_t)((((uint64_t)(i + 1) << L) - 1) / (uint64_t)n);
@@ -162,26 +176,21 @@ __device__ inline void kd_search(const TreeView& tv, const Ids& ids, const T (&q
             for (int c = 0; c < MD; c++)
                 if (MD < 8 || c < d) lb = M::acc_gap(lb, q[c], M::load(bb[c]), M::load(bb[d + c]));
             if (!(lb > kl.kd)) {
-                const int64_t lo = node_start(n, L, leaf), hi = node_start(n, L, leaf + 1);
-                T p[MD];
-                uint32_t idw = 0;
-                if (lo < hi) load_point<T, MD>(tv, lo, d, p, idw);
-                for (int64_t i = lo; i < hi; i++) {
-                    T pn[MD];
-                    uint32_t idn = 0;
-#pragma unroll
-                    for (int c = 0; c < MD; c++) pn[c] = p[c];
-                    if (i + 1 < hi) load_point<T, MD>(tv, i + 1, d, pn, idn);
-                    if (ids.live(i)) {
-                        DT dd = 0;
-#pragma unroll
-                        for (int c = 0; c < MD; c++)
-                            if (MD < 8 || c < d) dd = M::acc(dd, q[c], p[c]);
-                        kl.offer(dd, ids.id(i, idw), k);
+                const uint32_t lo = (uint32_t)node_start(n, L, leaf);
+                const uint32_t hi = (uint32_t)node_start(n, L, leaf + 1);
+                if (lo < hi) {
+                    // two record registers, alternately loading and in use;
+                    // positions past the leaf reread its last record
+                    const uint32_t last = hi - 1;
+                    T pa[MD], pb[MD];
+                    uint32_t ia, ib;
+                    load_point<T, MD>(tv, lo, d, pa, ia);
+                    for (uint32_t i = lo; i < hi; i += 2) {
+                        load_point<T, MD>(tv, i + 1 < last ? i + 1 : last, d, pb, ib);
+                        visit_point(ids, q, d, kl, k, i, pa, ia);
+                        load_point<T, MD>(tv, i + 2 < last ? i + 2 : last, d, pa, ia);
+                        if (i + 1 < hi) visit_point(ids, q, d, kl, k, i + 1, pb, ib);
                     }
-#pragma unroll
-                    for (int c = 0; c < MD; c++) p[c] = pn[c];
-                    idw = idn;
                 }
             }
         }

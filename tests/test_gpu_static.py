@@ -123,11 +123,11 @@ def test_ties_identical_grid_planes(pg, dev):
 
 
 def test_wide_distances_exact_redo(pg, dev):
-    # int32 searches order packed (distance, id) keys with the distance
-    # clamped to 64 - ceil(log2 n) bits; queries whose k-th distance reaches
-    # the clamp are searched again with exact pairs.  Full-range coordinates
-    # make most k-th distances exceed the clamp, a dense core next to them
-    # mixes clamped and exact queries in one wave.
+    # int32 searches order packed (distance, id) keys whose distance field
+    # has 64 - ceil(log2 n) bits; queries whose k-th distance does not fit
+    # are searched again with exact pairs.  Full-range coordinates make most
+    # k-th distances too large, a dense core next to them mixes redone and
+    # packed queries in one wave.
     g = np.random.default_rng(11)
     lo, hi = -(1 << 29), (1 << 29)
     wide = g.integers(lo, hi, size=(20000, 3)).astype(np.int32)
