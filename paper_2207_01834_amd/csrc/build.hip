@@ -16,10 +16,13 @@
 //     scatter whose per-workgroup offsets come from a per-node scan;
 //   * middle levels (>= 512 nodes, node > S points): one workgroup per node
 //     does an 8-bit radix select and the stable partition itself;
-//   * bottom levels (node <= S points): one workgroup per subtree loads it into
-//     LDS, and each wave selects (bitwise radix with ballots) and partitions
-//     whole nodes until the leaves, then writes the coordinates, the input
-//     rows, the split values and the per-leaf bounding boxes.
+//   * bottom levels (node <= S = 1024 points): one workgroup per subtree loads
+//     it into LDS, and each wave selects (8-bit digit histograms, or direct
+//     ranks for nodes of at most 64 points) and partitions whole nodes until
+//     the leaves, then writes the coordinates, the input rows, the split
+//     values and the per-leaf bounding boxes.  A small S keeps several
+//     subtrees per compute unit, which hides the latency of the top subtree
+//     levels, where only one or two waves of a workgroup have a node.
 #include <utility>
 
 #include "build.hpp"
@@ -322,7 +325,7 @@ node_box_kernel(uint32_t* __restrict__ box, int d, int lt, int b, int fl) {
 
 }  // namespace
 
-int subtree_capacity(int d) { return d <= 5 ? 2048 : 1024; }
+int subtree_capacity(int) { return 1024; }
 
 pg_status ingest_points(const void* points, int64_t n, int d, bool fl, uint32_t* keys,
                         int32_t* idx, uint32_t* vary_host, uint32_t* keybase_host,

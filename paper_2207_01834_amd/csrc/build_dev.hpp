@@ -77,18 +77,70 @@ __device__ inline void block_partition_range(const uint32_t* __restrict__ in,
     }
 }
 
+// wave_select_partition for a node of at most NS * 64 elements: lane t
+// holds elements t, t + 64, ... (pin order); each element's rank under
+// (key, position) is counted against every element, broadcast with
+// readlane (a uniform loop); the left child takes the ranks below mid - lo,
+// in order.  Returns the key of rank r.
+template <int NS>
+__device__ inline uint32_t wave_rank_partition(const uint32_t* keys, const uint16_t* pin,
+                                               uint16_t* pout, int lo, int hi, int mid,
+                                               uint32_t r) {
+    const int lane = lane_id();
+    const int m = hi - lo;
+    const bool right_empty = mid >= hi;
+    uint16_t p[NS];
+    uint32_t k[NS], rank[NS];
+#pragma unroll
+    for (int u = 0; u < NS; u++) {
+        const int e = u * kWave + lane;
+        p[u] = e < m ? pin[lo + e] : (uint16_t)0;
+        k[u] = e < m ? keys[p[u]] : 0u;
+        rank[u] = 0;
+    }
+#pragma unroll
+    for (int sv = 0; sv < NS; sv++) {
+        const int cnt = m - sv * kWave < kWave ? m - sv * kWave : kWave;
+        for (int j = 0; j < cnt; j++) {
+            const uint32_t kj = __builtin_amdgcn_readlane(k[sv], j);
+            const int pj = sv * kWave + j;
+#pragma unroll
+            for (int u = 0; u < NS; u++) {
+                const int pi = u * kWave + lane;
+                rank[u] += (kj < k[u] || (kj == k[u] && pj < pi)) ? 1u : 0u;
+            }
+        }
+    }
+    uint32_t v = 0;
+    int nl = 0, nr = 0;  // left / right elements of the earlier slots
+#pragma unroll
+    for (int u = 0; u < NS; u++) {
+        const bool valid = u * kWave + lane < m;
+        const uint64_t hit = ballot(valid && rank[u] == r);
+        if (hit != 0) v = __builtin_amdgcn_readlane(k[u], __ffsll((unsigned long long)hit) - 1);
+        const bool left = right_empty || rank[u] < (uint32_t)(mid - lo);
+        const uint64_t ml = ballot(valid && left), mr = ballot(valid && !left);
+        if (valid) pout[left ? lo + nl + (int)lane_prefix(ml) : mid + nr + (int)lane_prefix(mr)] = p[u];
+        nl += __popcll(ml);
+        nr += __popcll(mr);
+    }
+    return v;
+}
+
 // One wave selects the rank-r key of node [lo, hi) (local positions, order
 // given by pin) and writes the stable partition into pout.  Returns the
 // split key.  mid == hi (right child empty) splits at the largest key and
-// sends everything left.  Selection: the node's min and max fix the common
-// high key bits; the bits below are resolved 8 at a time with a 256-bin LDS
-// histogram private to the wave (whist).
+// sends everything left.  Selection: a node of at most 64 elements ranks
+// them directly (wave_rank_partition); a larger node's min and max fix
+// the common high key bits and the bits below are resolved 8 at a time with
+// a 256-bin LDS histogram private to the wave (whist).
 __device__ inline uint32_t wave_select_partition(const uint32_t* keys, const uint16_t* pin,
                                                  uint16_t* pout, int lo, int hi, int mid,
                                                  uint32_t* whist) {
     const int lane = lane_id();
     const bool right_empty = mid >= hi;
     uint32_t r = (uint32_t)((right_empty ? hi - 1 : mid) - lo);
+    if (hi - lo <= kWave) return wave_rank_partition<1>(keys, pin, pout, lo, hi, mid, r);
     uint32_t mn = 0xffffffffu, mx = 0;
     for (int e = lo + lane; e < hi; e += kWave) {
         const uint32_t k = keys[pin[e]];
