@@ -11,10 +11,10 @@
 // How (MI355X): coordinates become order-preserving 32-bit keys stored as SoA
 // planes.  Every partition is stable, so each node segment stays in input-row
 // order and "ties by input row" becomes "ties by position in the segment".
-//   * wide levels (< 512 nodes): radix select over 11-bit digits with
+//   * wide levels (< 1024 nodes): radix select over 11-bit digits with
 //     multi-workgroup LDS histograms merged by global atomics, then a stable
 //     scatter whose per-workgroup offsets come from a per-node scan;
-//   * middle levels (>= 512 nodes, node > S points): one workgroup per node
+//   * middle levels (>= 1024 nodes, node > S points): one workgroup per node
 //     does an 8-bit radix select and the stable partition itself;
 //   * bottom levels (node <= S = 1024 points): one workgroup per subtree loads
 //     it into LDS, and each wave selects (8-bit digit histograms, or direct
@@ -34,10 +34,10 @@ namespace pg {
 namespace {
 
 constexpr int kNT = kBuildNT;       // threads per workgroup
-constexpr int kChunk = 16384;       // elements per histogram workgroup in the wide levels
-constexpr int kScat = 4096;         // elements per count/scatter workgroup in the wide levels
+constexpr int kChunk = 8192;        // elements per histogram workgroup in the wide levels
+constexpr int kScat = 1024;         // elements per count/scatter workgroup in the wide levels
 constexpr int kWideDigit = 11;      // radix digit width in the wide levels
-constexpr int kWideNodes = 512;     // levels with fewer nodes use the wide path
+constexpr int kWideNodes = 1024;    // levels with fewer nodes use the wide path
 constexpr int kBoxLevels = 8;       // tree levels of internal boxes per launch
 
 struct NodeSel {
