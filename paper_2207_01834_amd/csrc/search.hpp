@@ -110,16 +110,22 @@ __device__ inline void kd_search(const TreeView& tv, const Ids& ids, const T (&q
     const int64_t n = tv.n;
     if (n == 0) return;
     const int L = tv.L;
+    // the walk stops one level above the leaves: a walk leaf is a parent of
+    // two leaves (or the root leaf itself when L = 0)
+    const int sub = L > 0 ? 1 : 0;
+    const int W = L - sub;
+    const uint32_t first_wleaf = 1u << W;
     const uint32_t first_leaf = 1u << L;
+    const uint32_t wstart = start >> sub;
     uint32_t cur, prev, p0, p1 = 0;
-    if (start != 0) {
-        p0 = start;
-        prev = start;
-        cur = start >> 1;
-    } else if (L == 0) {
+    if (W == 0) {
         p0 = 1;
         prev = 0;
         cur = 0;
+    } else if (start != 0) {
+        p0 = wstart;
+        prev = wstart;
+        cur = wstart >> 1;
     } else {
         p0 = 0;
         prev = 0;
@@ -138,14 +144,14 @@ __device__ inline void kd_search(const TreeView& tv, const Ids& ids, const T (&q
                     // back from child prev: the other child is due when prev
                     // was entered first -- the start leaf's side on its path,
                     // the query's side elsewhere -- and is not out of reach
-                    const bool prev_on_path = (start >> (L - lvl - 1)) == prev;
-                    const bool cur_on_path = (start >> (L - lvl)) == cur;
+                    const bool prev_on_path = (wstart >> (W - lvl - 1)) == prev;
+                    const bool cur_on_path = (wstart >> (W - lvl)) == cur;
                     const bool from_first = prev_on_path || (!cur_on_path && prev == nearc);
                     next = cur >> 1;
                     if (from_first && !(M::sq(qd, s) > kl.kd)) {
                         const uint32_t other = prev ^ 1u;
                         bool reach = true;
-                        if (tv.nbox != nullptr && other < first_leaf) {
+                        if (tv.nbox != nullptr) {
                             const uint32_t* nb = tv.nbox + (size_t)other * 2 * d;
                             DT lb = 0;
 #pragma unroll
@@ -157,7 +163,7 @@ __device__ inline void kd_search(const TreeView& tv, const Ids& ids, const T (&q
                         if (reach) next = other;
                     }
                 }
-                if (next >= first_leaf) {
+                if (next >= first_wleaf) {
                     if (p0 == 0) p0 = next;
                     else p1 = next;
                     prev = next;
@@ -169,27 +175,38 @@ __device__ inline void kd_search(const TreeView& tv, const Ids& ids, const T (&q
         }
         more = __ballot(p0 != 0) != 0;
         if (p0 != 0) {
-            const uint32_t leaf = p0 - first_leaf;
-            const uint32_t* bb = tv.bbox + (size_t)leaf * 2 * d;
-            DT lb = 0;
+            // the walk leaf's leaves, the query's side first; each is scanned
+            // when its box is within reach
+            uint32_t first = p0;
+            if (sub) {
+                const T s = M::load(tv.split[p0]);
+                const T qd = pick<MD>(q, MD < 8 ? W % MD : W % d);
+                first = 2u * p0 + (qd >= s ? 1u : 0u);
+            }
+            for (int t = 0; t <= sub; t++) {
+                const uint32_t leaf = (first ^ (uint32_t)t) - first_leaf;
+                const uint32_t* bb = tv.bbox + (size_t)leaf * 2 * d;
+                DT lb = 0;
 #pragma unroll
-            for (int c = 0; c < MD; c++)
-                if (MD < 8 || c < d) lb = M::acc_gap(lb, q[c], M::load(bb[c]), M::load(bb[d + c]));
-            if (!(lb > kl.kd)) {
-                const uint32_t lo = (uint32_t)node_start(n, L, leaf);
-                const uint32_t hi = (uint32_t)node_start(n, L, leaf + 1);
-                if (lo < hi) {
-                    // two record registers, alternately loading and in use;
-                    // positions past the leaf reread its last record
-                    const uint32_t last = hi - 1;
-                    T pa[MD], pb[MD];
-                    uint32_t ia, ib;
-                    load_point<T, MD>(tv, lo, d, pa, ia);
-                    for (uint32_t i = lo; i < hi; i += 2) {
-                        load_point<T, MD>(tv, i + 1 < last ? i + 1 : last, d, pb, ib);
-                        visit_point(ids, q, d, kl, k, i, pa, ia);
-                        load_point<T, MD>(tv, i + 2 < last ? i + 2 : last, d, pa, ia);
-                        if (i + 1 < hi) visit_point(ids, q, d, kl, k, i + 1, pb, ib);
+                for (int c = 0; c < MD; c++)
+                    if (MD < 8 || c < d)
+                        lb = M::acc_gap(lb, q[c], M::load(bb[c]), M::load(bb[d + c]));
+                if (!(lb > kl.kd)) {
+                    const uint32_t lo = (uint32_t)node_start(n, L, leaf);
+                    const uint32_t hi = (uint32_t)node_start(n, L, leaf + 1);
+                    if (lo < hi) {
+                        // two record registers, alternately loading and in
+                        // use; positions past the leaf reread its last record
+                        const uint32_t last = hi - 1;
+                        T pa[MD], pb[MD];
+                        uint32_t ia, ib;
+                        load_point<T, MD>(tv, lo, d, pa, ia);
+                        for (uint32_t i = lo; i < hi; i += 2) {
+                            load_point<T, MD>(tv, i + 1 < last ? i + 1 : last, d, pb, ib);
+                            visit_point(ids, q, d, kl, k, i, pa, ia);
+                            load_point<T, MD>(tv, i + 2 < last ? i + 2 : last, d, pa, ia);
+                            if (i + 1 < hi) visit_point(ids, q, d, kl, k, i + 1, pb, ib);
+                        }
                     }
                 }
             }
