@@ -20,7 +20,11 @@
 //     distance (the subtree-box test of Appendix C; the plane test alone lets
 //     a query beside a dense cluster walk every node of it), and a leaf is
 //     scanned only when the same holds for the leaf's box;
-//   * a lane may walk one leaf ahead of its scans (see kd_search);
+//   * the walk's leaves are the grandparents of the tree's leaves: a walk
+//     leaf box-tests and scans its four leaves in near-first order (leaf
+//     boxes prune at least as tightly as the split planes they replace,
+//     and a wave takes fewer, fuller rounds of walk and scan);
+//   * a lane may walk one walk leaf ahead of its scans (see kd_search);
 //   * leaf points are read as packed records (coordinates + row: one 16-byte
 //     load for d <= 3), the next record is requested before the current one
 //     is used;
@@ -110,9 +114,10 @@ __device__ inline void kd_search(const TreeView& tv, const Ids& ids, const T (&q
     const int64_t n = tv.n;
     if (n == 0) return;
     const int L = tv.L;
-    // the walk stops one level above the leaves: a walk leaf is a parent of
-    // two leaves (or the root leaf itself when L = 0)
-    const int sub = L > 0 ? 1 : 0;
+    // the walk stops two levels above the leaves: a walk leaf is the
+    // grandparent of four leaves (the parent of two when L = 1, the root
+    // leaf itself when L = 0)
+    const int sub = L < 2 ? L : 2;
     const int W = L - sub;
     const uint32_t first_wleaf = 1u << W;
     const uint32_t first_leaf = 1u << L;
@@ -175,16 +180,26 @@ __device__ inline void kd_search(const TreeView& tv, const Ids& ids, const T (&q
         }
         more = __ballot(p0 != 0) != 0;
         if (p0 != 0) {
-            // the walk leaf's leaves, the query's side first; each is scanned
-            // when its box is within reach
-            uint32_t first = p0;
-            if (sub) {
+            // the walk leaf's leaves, the query's side first at each of the
+            // two levels; each is scanned when its box is within reach
+            uint32_t c0 = p0, g0 = 0, g1 = 0;
+            if (sub >= 1) {
                 const T s = M::load(tv.split[p0]);
                 const T qd = pick<MD>(q, MD < 8 ? W % MD : W % d);
-                first = 2u * p0 + (qd >= s ? 1u : 0u);
+                c0 = 2u * p0 + (qd >= s ? 1u : 0u);
             }
-            for (int t = 0; t <= sub; t++) {
-                const uint32_t leaf = (first ^ (uint32_t)t) - first_leaf;
+            if (sub == 2) {
+                const T qd = pick<MD>(q, MD < 8 ? (W + 1) % MD : (W + 1) % d);
+                g0 = qd >= M::load(tv.split[c0]) ? 1u : 0u;
+                g1 = qd >= M::load(tv.split[c0 ^ 1u]) ? 1u : 0u;
+            }
+            for (int t = 0; t < (1 << sub); t++) {
+                uint32_t lh = c0 ^ (uint32_t)t;
+                if (sub == 2) {
+                    const uint32_t ch = (t >> 1) ? c0 ^ 1u : c0;
+                    lh = 2u * ch + (((t >> 1) ? g1 : g0) ^ (uint32_t)(t & 1));
+                }
+                const uint32_t leaf = lh - first_leaf;
                 const uint32_t* bb = tv.bbox + (size_t)leaf * 2 * d;
                 DT lb = 0;
 #pragma unroll
