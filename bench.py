@@ -198,7 +198,7 @@ def form_clustered(torch, pg, datagen, dev):
 
 def form_bdl(torch, pg, datagen, dev, rounds):
     """Batch-dynamic: 10M initial 3-D int points, then rounds of 1M inserts,
-    1M erases of inserted points, 1M fresh queries (k = 10), X = 2^14."""
+    1M erases of live points, 1M fresh queries (k = 10), X = 2^14."""
     import numpy as np
     init, rds = datagen.bdl_rounds(N, rounds, 1_000_000, 1_000_000, 3, seed=5)
     B = pg.BDLTree(3, torch.int32, leaf=LEAF, X=1 << 14, device=dev)
@@ -287,7 +287,7 @@ def main():
     ap.add_argument("--forms", default="all",
                     help="other forms to measure after the headline step: all, none, or a "
                          "comma list of static_float,clustered,bdl,batch")
-    ap.add_argument("--bdl-rounds", type=int, default=3)
+    ap.add_argument("--bdl-rounds", type=int, default=10)
     ap.add_argument("--loop-clouds", type=int, default=512,
                     help="clouds timed for the per-cloud comparison (projected to 4,096)")
     ap.add_argument("--copy-probe-mib", type=int, default=1024,

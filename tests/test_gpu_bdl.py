@@ -155,12 +155,12 @@ def test_cfg5_shaped_reduced(pg, dev):
 
 
 def test_cfg5_full_size_sampled(pg, dev):
-    """The benchmarked batch-dynamic configuration: 10M initial points, rounds
-    of 1M inserts, 1M erases of live points, 1M queries (k = 10); 3 rounds,
-    invariants on every round, 400 sampled query rows against the definition
-    over the live set."""
+    """The benchmarked batch-dynamic configuration: 10M initial points, 10
+    rounds of 1M inserts, 1M erases of live points, 1M queries (k = 10);
+    invariants on every round, 300 sampled query rows per round against the
+    definition over the live set."""
     import torch
-    init, rounds = datagen.bdl_rounds(10_000_000, 3, 1_000_000, 1_000_000, 3, seed=5)
+    init, rounds = datagen.bdl_rounds(10_000_000, 10, 1_000_000, 1_000_000, 3, seed=5)
     X = 1 << 14
     G = pg.BDLTree(3, torch.int32, leaf=16, X=X, device=dev)
     say("cfg5: initial insert")
@@ -187,6 +187,6 @@ def test_cfg5_full_size_sampled(pg, dev):
             if (F >> i) & 1:
                 assert 2 * live[i] >= (X << i) and live[i] <= (X << i)
         gi, gd = host(*G.knn(to_dev(rd["queries"], dev), 10))
-        rows = np.random.default_rng(r).choice(len(rd["queries"]), 400, replace=False)
+        rows = np.random.default_rng(r).choice(len(rd["queries"]), 300, replace=False)
         oi, od = oracle.knn_brute(pts, rd["queries"][rows], 10, ids=ids, nthreads=16)
         assert_int_equal(gi[rows], gd[rows], oi, od)

@@ -181,6 +181,21 @@ def test_full_size_cfg2_sampled(pg, dev):
     assert_float_close(gi[rows], gd[rows], oi, od, f, f[rows])
 
 
+def test_full_size_clustered_5d_sampled(pg, dev):
+    # The benchmarked 5-D clustered configuration: 10M float32 points from a
+    # 1,000-cluster mixture, 1M queries from the same mixture, k = 5, leaf 16
+    # (the query set is large enough to be reordered by leaf).
+    f, q = datagen.clustered(10_000_000, 5, seed=3, n_queries=1_000_000, query_seed=33)
+    say("cfg3 clustered 5-D 10M, 1M queries")
+    t = pg.kdtree_build(to_dev(f, dev), leaf=16)
+    assert t.levels == 20
+    gi, gd = host(*t.knn(to_dev(q, dev), 5))
+    assert (gi >= 0).all() and (np.diff(gd, axis=1) >= 0).all()
+    rows = np.random.default_rng(3).choice(len(q), 300, replace=False)
+    oi, od = oracle.knn_brute(f, q[rows], 5, nthreads=16)
+    assert_float_close(gi[rows], gd[rows], oi, od, f, q[rows])
+
+
 def test_determinism(pg, dev):
     pts = datagen.uniform_int(300_000, 3, seed=9)
     a = pg.kdtree_build(to_dev(pts, dev), leaf=16)
