@@ -251,7 +251,7 @@ def form_batch(torch, pg, datagen, dev, loop_clouds):
     Ntot = len(pts)
     x = torch.from_numpy(pts).to(dev)
     tune = pg.batch_autotune(x, offs, 16)
-    Bk = pg.BatchKnn(offs, 3, leaf=tune["leaf"], blocks_per_cu=tune["blocks_per_cu"], device=dev)
+    Bk = pg.BatchKnn(offs, 3, device=dev, **tune)
     idx = torch.empty((Ntot, 16), dtype=torch.int32, device=dev)
     d2 = torch.empty((Ntot, 16), dtype=torch.float32, device=dev)
     batch_ms = timed(torch, lambda: Bk.knn_self(x, 16, out=(idx, d2)))

@@ -164,12 +164,17 @@ void pg_bdl_free(pg_bdl* b);
 /* ---------------------------------------------------------------------- */
 /* Batched uneven clouds (float32) and the differentiable k-NN backward    */
 /* ---------------------------------------------------------------------- */
+/* Where the per-query k-list of the batched launch lives. */
+typedef enum { PG_KLIST_DEFAULT = 0, PG_KLIST_VGPR = 1, PG_KLIST_LDS = 2 } pg_klist;
+
 /* Tuning of the batched launch; 0 = default.  Every setting gives identical
  * results. */
 typedef struct {
     int32_t leaf;           /* leaf size of every cloud's tree (default 16)  */
     int32_t blocks_per_cu;  /* persistent workgroups per compute unit (4)    */
-    int32_t reserved[2];
+    int32_t lane_queries;   /* queries each lane searches per work item,
+                               1..8 (1): a wave takes 64 x lane_queries     */
+    int32_t klist;          /* pg_klist: registers (default) or LDS          */
 } pg_tune;
 
 typedef struct pg_batch pg_batch;
@@ -208,8 +213,9 @@ pg_status pg_batch_check(const float* points, int64_t n, int32_t d, void* stream
 /* Reads the workspace's wait-timeout flag of the last launch (synchronises). */
 pg_status pg_batch_status(const pg_batch* b, void* stream, int32_t* timed_out);
 
-/* Times every tuning candidate (leaf 8/16/32 x 2/4 workgroups per CU) on
- * these points and returns the fastest; results are cached per
+/* Times every tuning candidate (leaf 8/16/32 x 2/4 workgroups per CU x 1/4
+ * queries per lane x k-list in registers/LDS: 24 launches) on these points
+ * and returns the fastest; results are cached per
  * (clouds, size bucket, d, k) for the life of the process.  Synchronises. */
 pg_status pg_batch_autotune(const float* points, const int64_t* offsets_host, int32_t n_clouds,
                             int32_t d, int32_t k, void* stream, pg_tune* best);

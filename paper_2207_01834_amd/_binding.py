@@ -64,9 +64,12 @@ SIGNATURES = {
 }
 
 
+KLIST_VGPR, KLIST_LDS = 1, 2
+
+
 class Tune(ctypes.Structure):
     _fields_ = [("leaf", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("lane_queries", ctypes.c_int32), ("klist", ctypes.c_int32)]
 
 
 def lib():
@@ -256,13 +259,14 @@ class BatchKnn:
     The plan (and a library-owned workspace) is made once; ``knn_self`` only
     launches, so it can be captured in a CUDA/HIP graph."""
 
-    def __init__(self, offsets, d: int, leaf: int = 0, blocks_per_cu: int = 0, device="cuda"):
+    def __init__(self, offsets, d: int, leaf: int = 0, blocks_per_cu: int = 0,
+                 lane_queries: int = 0, klist: int = 0, device="cuda"):
         self.offsets, optr = _offsets_array(offsets)
         self.C = len(self.offsets) - 1
         self.N = int(self.offsets[-1])
         self.d = d
         self.device = torch.device(device)
-        self.tune = Tune(leaf, blocks_per_cu, (ctypes.c_int32 * 2)(0, 0))
+        self.tune = Tune(leaf, blocks_per_cu, lane_queries, klist)
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             check(lib().pg_batch_create(optr, self.C, d, ctypes.byref(self.tune), None, 0,
@@ -307,7 +311,8 @@ def batch_autotune(points: torch.Tensor, offsets, k: int):
     t = Tune()
     check(lib().pg_batch_autotune(ctypes.c_void_p(p.data_ptr()), optr, len(o) - 1, p.shape[1], k,
                                   stream_ptr(p.device), ctypes.byref(t)))
-    return {"leaf": t.leaf, "blocks_per_cu": t.blocks_per_cu}
+    return {"leaf": t.leaf, "blocks_per_cu": t.blocks_per_cu, "lane_queries": t.lane_queries,
+            "klist": t.klist}
 
 
 def knn_backward(queries, points, idx, grad_d2, grad_q=None, grad_p=None, self_mode=False):

@@ -18,9 +18,10 @@
 // always ends.  It is bounded anyway and reports a timeout in the workspace.
 //
 // The autotuner times leaf sizes {8, 16, 32} x workgroups per compute unit
-// {2, 4} on the caller's data and keeps the fastest per workload key; every
-// choice returns identical results (the k-NN result does not depend on the
-// tree).
+// {2, 4} x queries per lane and item {1, 4} (64 or 256 queries per wave) x
+// k-list placement {registers, LDS} on the caller's data and keeps the
+// fastest per workload key; every choice returns identical results (the k-NN
+// result depends neither on the tree nor on where the list lives).
 #include <algorithm>
 #include <map>
 #include <mutex>
@@ -70,6 +71,7 @@ struct BatchParams {
     uint32_t* rec;           // [N][rw] packed leaf records
     int64_t total_items;
     int32_t C, d, k, S;
+    int32_t lq;  // queries each lane searches per query item
 };
 
 __global__ void batch_reset_kernel(uint32_t* queue, uint32_t* ready, int C) {
@@ -129,8 +131,10 @@ __device__ inline void build_cloud(const BatchParams& P, int c, uint32_t* sm) {
         __hip_atomic_store(&P.ready[c], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-template <int MD, int KT, bool EX>
-__device__ inline void query_item(const BatchParams& P, int64_t q, int* s_ok) {
+// One query item: the cloud's points [blk * kQB * lq, ...), lane t taking
+// points t, t + kQB, ... (lq of them).  LDSL: the k-list lives in LDS (sm).
+template <int MD, int KT, bool EX, bool LDSL>
+__device__ inline void query_item(const BatchParams& P, int64_t q, int* s_ok, uint32_t* sm) {
     // item -> position t in the size order (binary search over qstart)
     int lo = 0, hi = P.C;  // qstart[lo] <= q < qstart[hi]
     while (hi - lo > 1) {
@@ -159,33 +163,47 @@ __device__ inline void query_item(const BatchParams& P, int64_t q, int* s_ok) {
     if (!ok) return;
     (void)__hip_atomic_load(&P.ready[c], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
     const CloudDesc D = P.desc[c];
-    const int64_t i = blk * kQB + threadIdx.x;
-    if (i >= D.n) return;
     const int d = P.d, k = P.k;
     const TreeView tv{D.n, d, D.L, record_words(d), P.pts + D.pts, P.pidx + D.row,
                       P.split + D.split, P.bbox + D.bbox, P.rec + D.row * record_words(d)};
     using M = Metric<float>;
-    float q_[MD];
+    for (int r = 0; r < P.lq; r++) {
+        const int64_t i = (blk * P.lq + r) * kQB + threadIdx.x;
+        if (i >= D.n) break;
+        float q_[MD];
 #pragma unroll
-    for (int cc = 0; cc < MD; cc++) q_[cc] = cc < d ? M::load(tv.pts[(int64_t)cc * D.n + i]) : 0.0f;
-    PackedList<float, KT, EX> kl;
-    kl.init(32);
-    kd_search<float, MD>(tv, PlainIds{}, q_, d, kl, k,
-                                          (1u << D.L) + leaf_of(D.n, D.L, i));
-    const int64_t row = D.row + tv.pidx[i];
+        for (int cc = 0; cc < MD; cc++) q_[cc] = cc < d ? M::load(tv.pts[(int64_t)cc * D.n + i]) : 0.0f;
+        const uint32_t start = (1u << D.L) + leaf_of(D.n, D.L, i);
+        const int64_t row = D.row + tv.pidx[i];
+        if constexpr (LDSL) {
+            LdsList<KT, EX> kl;
+            kl.init(reinterpret_cast<uint64_t*>(sm) + threadIdx.x, kNT);
+            kd_search<float, MD>(tv, PlainIds{}, q_, d, kl, k, start);
+            for (int s = 0; s < (EX ? KT : k); s++) {
+                const uint64_t x = kl.at(s);
+                const int32_t id = kl.id_of(x);
+                P.out_idx[row * k + s] = id < 0 ? -1 : (int32_t)(D.row + id);
+                P.out_d2[row * k + s] = kl.dist_of(x);
+            }
+        } else {
+            PackedList<float, KT, EX> kl;
+            kl.init(32);
+            kd_search<float, MD>(tv, PlainIds{}, q_, d, kl, k, start);
 #pragma unroll
-    for (int s = 0; s < KT; s++) {
-        if (EX || s < k) {
-            const int32_t id = kl.id_of(kl.key[s]);
-            P.out_idx[row * k + s] = id < 0 ? -1 : (int32_t)(D.row + id);
-            P.out_d2[row * k + s] = kl.dist_of(kl.key[s]);
+            for (int s = 0; s < KT; s++) {
+                if (EX || s < k) {
+                    const int32_t id = kl.id_of(kl.key[s]);
+                    P.out_idx[row * k + s] = id < 0 ? -1 : (int32_t)(D.row + id);
+                    P.out_d2[row * k + s] = kl.dist_of(kl.key[s]);
+                }
+            }
         }
     }
 }
 
-template <int MD, int KT, bool EX>
+template <int MD, int KT, bool EX, bool LDSL>
 __global__ void __launch_bounds__(kNT) batch_kernel(BatchParams P) {
-    extern __shared__ uint32_t sm[];
+    extern __shared__ __align__(16) uint32_t sm[];
     __shared__ int s_item;
     __shared__ int s_ok;
     for (;;) {
@@ -195,7 +213,7 @@ __global__ void __launch_bounds__(kNT) batch_kernel(BatchParams P) {
         __syncthreads();
         if (it >= P.total_items) break;
         if (it < P.C) build_cloud(P, P.order[it], sm);
-        else query_item<MD, KT, EX>(P, it - P.C, &s_ok);
+        else query_item<MD, KT, EX, LDSL>(P, it - P.C, &s_ok, sm);
         __syncthreads();
     }
 }
@@ -279,7 +297,7 @@ __global__ void grad_x_kernel(const float* __restrict__ q, const float* __restri
 // Host side.
 // ---------------------------------------------------------------------------
 struct BatchPlan {
-    int C = 0, d = 0, leaf = 0, bpc = 0, S = 0;
+    int C = 0, d = 0, leaf = 0, bpc = 0, S = 0, lq = 1, klist = PG_KLIST_VGPR;
     int64_t N = 0, total_items = 0;
     // workspace carve-up
     size_t bytes = 0;
@@ -292,11 +310,14 @@ struct BatchPlan {
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-static pg_status make_plan(const int64_t* offs, int C, int d, int leaf, int bpc, BatchPlan& P) {
+static pg_status make_plan(const int64_t* offs, int C, int d, int leaf, int bpc, int lq, int klist,
+                           BatchPlan& P) {
     P.C = C;
     P.d = d;
     P.leaf = leaf;
     P.bpc = bpc;
+    P.lq = lq;
+    P.klist = klist;
     P.S = subtree_capacity(d);
     P.desc.resize(C);
     int64_t pts = 0, split = 0, bbox = 0;
@@ -330,7 +351,7 @@ static pg_status make_plan(const int64_t* offs, int C, int d, int leaf, int bpc,
     int64_t q = 0;
     for (int t = 0; t < C; t++) {
         P.qstart[t] = q;
-        q += (P.desc[P.order[t]].n + kQB - 1) / kQB;
+        q += (P.desc[P.order[t]].n + (int64_t)kQB * lq - 1) / ((int64_t)kQB * lq);
     }
     P.qstart[C] = q;
     P.total_items = C + q;
@@ -366,11 +387,16 @@ namespace {
 
 template <int MD, int KT, bool EX>
 pg_status launch_batch(pg_batch* b, const BatchParams& P, hipStream_t s) {
-    const size_t lds = subtree_lds_bytes(P.d, P.S);
+    const bool lds_list = b->plan.klist == PG_KLIST_LDS;
+    size_t lds = subtree_lds_bytes(P.d, P.S);  // build items and LDS k-lists share it
+    if (lds_list) lds = std::max(lds, sizeof(uint64_t) * KT * kNT);
     const unsigned grid = (unsigned)(b->num_cu * b->plan.bpc);
     hipLaunchKernelGGL(batch_reset_kernel, dim3(8), dim3(kNT), 0, s, P.queue, P.ready, P.C);
     PG_LAUNCH_CHECK();
-    hipLaunchKernelGGL((batch_kernel<MD, KT, EX>), dim3(grid), dim3(kNT), lds, s, P);
+    if (lds_list)
+        hipLaunchKernelGGL((batch_kernel<MD, KT, EX, true>), dim3(grid), dim3(kNT), lds, s, P);
+    else
+        hipLaunchKernelGGL((batch_kernel<MD, KT, EX, false>), dim3(grid), dim3(kNT), lds, s, P);
     PG_LAUNCH_CHECK();
     return PG_OK;
 }
@@ -407,7 +433,7 @@ pg_status pg_batch_workspace(const int64_t* offsets_host, int32_t n_clouds, int3
     const int leaf = tune && tune->leaf ? tune->leaf : 16;
     if (leaf < 1 || leaf > 64) return fail(PG_ERR_INVALID, "pg_batch_workspace: leaf must be in [1, 64]");
     BatchPlan P;
-    PG_TRY(make_plan(offsets_host, n_clouds, d, leaf, 4, P));
+    PG_TRY(make_plan(offsets_host, n_clouds, d, leaf, 4, 1, PG_KLIST_VGPR, P));
     *bytes = P.bytes;
     return PG_OK;
 }
@@ -421,10 +447,15 @@ pg_status pg_batch_create(const int64_t* offsets_host, int32_t n_clouds, int32_t
     const int leaf = tune && tune->leaf ? tune->leaf : 16;
     const int bpc = tune && tune->blocks_per_cu ? tune->blocks_per_cu : 4;
     if (leaf < 1 || leaf > 64) return fail(PG_ERR_INVALID, "pg_batch_create: leaf must be in [1, 64]");
+    const int lq = tune && tune->lane_queries ? tune->lane_queries : 1;
+    const int kl = tune && tune->klist ? tune->klist : PG_KLIST_VGPR;
     if (bpc < 1 || bpc > 16) return fail(PG_ERR_INVALID, "pg_batch_create: blocks_per_cu must be in [1, 16]");
+    if (lq < 1 || lq > 8) return fail(PG_ERR_INVALID, "pg_batch_create: lane_queries must be in [1, 8]");
+    if (kl != PG_KLIST_VGPR && kl != PG_KLIST_LDS)
+        return fail(PG_ERR_INVALID, "pg_batch_create: klist must be PG_KLIST_VGPR or PG_KLIST_LDS");
     pg_batch* b = new (std::nothrow) pg_batch();
     if (!b) return fail(PG_ERR_NOMEM, "pg_batch_create: host allocation failed");
-    pg_status st = make_plan(offsets_host, n_clouds, d, leaf, bpc, b->plan);
+    pg_status st = make_plan(offsets_host, n_clouds, d, leaf, bpc, lq, kl, b->plan);
     if (st != PG_OK) { delete b; return st; }
     hipStream_t s = (hipStream_t)stream;
     b->stream = s;
@@ -488,6 +519,7 @@ pg_status pg_batch_knn_self(pg_batch* b, const float* points, int32_t k, int32_t
     P.d = PL.d;
     P.k = k;
     P.S = PL.S;
+    P.lq = PL.lq;
     hipStream_t s = (hipStream_t)stream;
     switch (PL.d) {
         case 2: return batch_k<2>(b, P, s);
@@ -539,34 +571,36 @@ pg_status pg_batch_autotune(const float* points, const int64_t* offsets_host, in
     PG_HIP(hipEventCreate(&e0));
     PG_HIP(hipEventCreate(&e1));
     float best_ms = 1e30f;
-    pg_tune win{16, 4, {0, 0}};
+    pg_tune win{16, 4, 1, PG_KLIST_VGPR};
     const int leaves[3] = {8, 16, 32};
     const int bpcs[2] = {2, 4};
-    for (int li = 0; li < 3; li++)
-        for (int bi = 0; bi < 2; bi++) {
-            pg_tune t{leaves[li], bpcs[bi], {0, 0}};
-            pg_batch* b = nullptr;
-            PG_TRY(pg_batch_create(offsets_host, n_clouds, d, &t, nullptr, 0, stream, &b));
-            pg_status st = pg_batch_knn_self(b, points, k, oi.as<int32_t>(), od.as<float>(), stream);
-            float ms = 0.0f;
-            if (st == PG_OK) {
-                (void)hipEventRecord(e0, s);
-                st = pg_batch_knn_self(b, points, k, oi.as<int32_t>(), od.as<float>(), stream);
-                (void)hipEventRecord(e1, s);
-                (void)hipEventSynchronize(e1);
-                (void)hipEventElapsedTime(&ms, e0, e1);
-            }
-            pg_batch_free(b);
-            if (st != PG_OK) {
-                (void)hipEventDestroy(e0);
-                (void)hipEventDestroy(e1);
-                return st;
-            }
-            if (ms < best_ms) {
-                best_ms = ms;
-                win = t;
-            }
+    const int lqs[2] = {1, 4};
+    const int kls[2] = {PG_KLIST_VGPR, PG_KLIST_LDS};
+    for (int ci = 0; ci < 24; ci++) {
+        const int li = ci / 8, bi = (ci / 4) % 2, qi = (ci / 2) % 2, ki = ci % 2;
+        pg_tune t{leaves[li], bpcs[bi], lqs[qi], kls[ki]};
+        pg_batch* b = nullptr;
+        PG_TRY(pg_batch_create(offsets_host, n_clouds, d, &t, nullptr, 0, stream, &b));
+        pg_status st = pg_batch_knn_self(b, points, k, oi.as<int32_t>(), od.as<float>(), stream);
+        float ms = 0.0f;
+        if (st == PG_OK) {
+            (void)hipEventRecord(e0, s);
+            st = pg_batch_knn_self(b, points, k, oi.as<int32_t>(), od.as<float>(), stream);
+            (void)hipEventRecord(e1, s);
+            (void)hipEventSynchronize(e1);
+            (void)hipEventElapsedTime(&ms, e0, e1);
         }
+        pg_batch_free(b);
+        if (st != PG_OK) {
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            return st;
+        }
+        if (ms < best_ms) {
+            best_ms = ms;
+            win = t;
+        }
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     {

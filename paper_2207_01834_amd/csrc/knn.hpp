@@ -169,6 +169,51 @@ struct PackedList {
     }
 };
 
+// The float32 packed keys of PackedList held in LDS instead of registers:
+// slot s of a lane at key[s * stride] (neighbouring lanes at neighbouring
+// 8-byte words, so a slot access is conflict-free).  Frees 2*KT registers per
+// lane (more waves per SIMD) and costs one LDS read and write per slot of an
+// insertion; the batched launch's tuner picks the placement.
+template <int KT, bool EX>
+struct LdsList {
+    using DT = float;
+    static constexpr uint64_t kEmpty = 0x7f800000ffffffffull;
+    uint64_t* key;  // this lane's slot 0
+    int stride;     // words between a lane's slots
+    uint64_t kk;    // key of slot k-1
+    float kd;       // its distance: the pruning radius, squared
+
+    __device__ inline void init(uint64_t* base, int stride_) {
+        key = base;
+        stride = stride_;
+#pragma unroll
+        for (int s = 0; s < KT; s++) key[s * stride] = kEmpty;
+        kk = kEmpty;
+        kd = dist_of(kEmpty);
+    }
+    __device__ static inline float dist_of(uint64_t x) { return __uint_as_float((uint32_t)(x >> 32)); }
+    __device__ static inline int32_t id_of(uint64_t x) { return (int32_t)(uint32_t)x; }
+    __device__ inline uint64_t at(int s) const { return key[s * stride]; }
+    __device__ inline void offer(float dd, int32_t ii, int k) {
+        const uint64_t x = ((uint64_t)__float_as_uint(dd) << 32) | (uint32_t)ii;
+        if (x < kk) insert(x, k);
+    }
+    // As PackedList::insert, from the top slot down; the slot below is read
+    // once and carried to the next step.
+    __device__ inline void insert(uint64_t x, int k) {
+        const int top = EX ? KT - 1 : k - 1;
+        uint64_t cur = key[top * stride];
+        for (int s = top; s >= 0; --s) {
+            const uint64_t below = s > 0 ? key[(s - 1) * stride] : 0ull;
+            const uint64_t nk = (s > 0 && x < below) ? below : (x < cur ? x : cur);
+            key[s * stride] = nk;
+            if (s == top) kk = nk;
+            cur = below;
+        }
+        kd = dist_of(kk);
+    }
+};
+
 // Id bits of the packed keys of a tree of n points (ids are rows < n).
 inline int id_bits(int64_t n) {
     int b = 1;

@@ -89,14 +89,22 @@ def test_batched_tuning_invariance(pg, dev):
     ref = None
     for leaf in (8, 16, 32):
         for bpc in (1, 2, 4):
-            say(f"tune leaf={leaf} bpc={bpc}")
-            B = pg.BatchKnn(offs, 3, leaf=leaf, blocks_per_cu=bpc, device=dev)
-            out = host(*B.knn_self(to_dev(pts, dev), 10))
-            if ref is None:
-                ref = out
-            assert np.array_equal(out[0], ref[0]) and np.array_equal(out[1], ref[1])
+            for lq, kl in ((1, pg.KLIST_VGPR), (4, pg.KLIST_LDS), (3, pg.KLIST_VGPR), (1, pg.KLIST_LDS)):
+                say(f"tune leaf={leaf} bpc={bpc} lane_queries={lq} klist={kl}")
+                B = pg.BatchKnn(offs, 3, leaf=leaf, blocks_per_cu=bpc, lane_queries=lq, klist=kl,
+                                device=dev)
+                out = host(*B.knn_self(to_dev(pts, dev), 10))
+                if ref is None:
+                    ref = out
+                assert np.array_equal(out[0], ref[0]) and np.array_equal(out[1], ref[1])
+    # the LDS list with a guarded (non-exact) capacity, against the register list
+    for k in (7, 33):
+        a = host(*pg.BatchKnn(offs, 3, klist=pg.KLIST_VGPR, device=dev).knn_self(to_dev(pts, dev), k))
+        b = host(*pg.BatchKnn(offs, 3, klist=pg.KLIST_LDS, lane_queries=2, device=dev).knn_self(to_dev(pts, dev), k))
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
     t = pg.batch_autotune(to_dev(pts, dev), offs, 10)
     assert t["leaf"] in (8, 16, 32) and t["blocks_per_cu"] in (2, 4)
+    assert t["lane_queries"] in (1, 4) and t["klist"] in (pg.KLIST_VGPR, pg.KLIST_LDS)
 
 
 def test_batched_other_dims_and_k(pg, dev):
