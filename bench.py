@@ -244,7 +244,8 @@ def form_bdl(torch, pg, datagen, dev, rounds):
 def form_batch(torch, pg, datagen, dev, loop_clouds):
     """4,096 sphere clouds (sizes log-uniform in [256, 65536]), per-cloud
     all-points k = 16 in one persistent launch, against the per-cloud static
-    method; plus the k-NN backward over the same clouds."""
+    method; plus the k-NN backward over the same clouds (leaf-order batched
+    kernel, and the generic one)."""
     import numpy as np
     sizes = datagen.cloud_sizes(4096, seed=4)
     pts, offs = datagen.sphere_clouds(sizes, seed=44)
@@ -266,14 +267,18 @@ def form_batch(torch, pg, datagen, dev, loop_clouds):
     loop_s = (time.perf_counter() - t0) * 4096 / nc
     g = torch.randn((Ntot, 16), dtype=torch.float32, device=dev)
     grad = torch.empty_like(x)
-    bwd_ms = timed(torch, lambda: pg.knn_backward(x, x, idx, g, grad_q=grad, self_mode=True))
+    # the leaf-order backward of the batched launch (its trees are the last
+    # knn_self's), and the generic reverse-CSR backward for comparison
+    bwd_ms = timed(torch, lambda: Bk.backward(x, idx, d2, g, out=grad))
+    gen_ms = timed(torch, lambda: pg.knn_backward(x, x, idx, g, grad_q=grad, self_mode=True))
     return {"workload": "4,096 unit-sphere clouds (+N(0,0.01^2)), sizes log-uniform [256,65536], "
                         f"{Ntot} points, per-cloud all-points k=16, float32",
             "tune": tune, "batched_ms": batch_ms, "clouds_per_s": 4096 / (batch_ms * 1e-3),
             "points_per_s": Ntot / (batch_ms * 1e-3),
             "per_cloud_loop_ms": loop_s * 1e3, "per_cloud_loop_sample_clouds": nc,
             "speedup_vs_per_cloud_loop": loop_s * 1e3 / batch_ms,
-            "backward_ms": bwd_ms, "backward_pairs_per_s": Ntot * 16 / (bwd_ms * 1e-3)}
+            "backward_ms": bwd_ms, "backward_pairs_per_s": Ntot * 16 / (bwd_ms * 1e-3),
+            "backward_generic_ms": gen_ms}
 
 
 def main():

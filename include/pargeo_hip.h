@@ -223,6 +223,24 @@ pg_status pg_batch_autotune(const float* points, const int64_t* offsets_host, in
 /* Releases the handle (and the workspace if the library allocated it). */
 void pg_batch_free(pg_batch* b);
 
+/* Backward of L = sum_{i,r} g[i,r] * D[i,r] for the handle's last
+ * pg_batch_knn_self (same points, same k; the clouds' trees are still in the
+ * workspace), with the neighbour sets held fixed.  Every point is a query and
+ * a neighbour, so one gradient receives both roles:
+ *   grad_points[j] = sum_r 2 g[j,r] (x_j - x_{idx[j,r]})
+ *                  - sum_{(i,r): idx[i,r] = j} 2 g[i,r] (x_i - x_j)
+ * Queries are taken in each cloud's leaf order, so most neighbour terms are
+ * summed in LDS; all sums are int64 fixed point scaled from the largest term
+ * (about 38 bits per term), hence independent of the order of the adds:
+ * deterministic.  Not in the paper (the gradient of its k-NN distances).
+ *   idx, d2  : [N][k] device, the forward's outputs (global rows, float32 D)
+ *   grad_d2  : [N][k] device float32, finite
+ *   grad_points : [N][d] device float32, written (not accumulated)
+ * Allocates scratch (stream-ordered pool); does not synchronise. */
+pg_status pg_batch_backward(pg_batch* b, const float* points, int32_t k, const int32_t* idx,
+                            const float* d2, const float* grad_d2, float* grad_points,
+                            void* stream);
+
 /* Backward of L = sum_{i,r} g[i,r] * D(q_i, x_{idx[i,r]}) with the neighbour
  * sets held fixed (the forward's idx):
  *   grad_q[i] = sum_r 2 g[i,r] (q_i - x_j)

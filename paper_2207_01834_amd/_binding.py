@@ -61,6 +61,7 @@ SIGNATURES = {
     "pg_batch_autotune": (i32, [vp, P64, i32, i32, i32, vp, vp]),
     "pg_batch_free": (None, [vp]),
     "pg_knn_backward": (i32, [vp, vp, i64, i64, i32, i32, vp, vp, vp, vp, vp]),
+    "pg_batch_backward": (i32, [vp, vp, i32, vp, vp, vp, vp, vp]),
 }
 
 
@@ -267,6 +268,7 @@ class BatchKnn:
         self.d = d
         self.device = torch.device(device)
         self.tune = Tune(leaf, blocks_per_cu, lane_queries, klist)
+        self.generation = 0  # knn_self calls so far (the trees belong to the last)
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             check(lib().pg_batch_create(optr, self.C, d, ctypes.byref(self.tune), None, 0,
@@ -291,7 +293,24 @@ class BatchKnn:
         check(lib().pg_batch_knn_self(self._h, ctypes.c_void_p(p.data_ptr()), k,
                                       ctypes.c_void_p(idx.data_ptr()), ctypes.c_void_p(d2.data_ptr()),
                                       stream_ptr(p.device)))
+        self.generation += 1
         return idx, d2
+
+    def backward(self, points: torch.Tensor, idx: torch.Tensor, d2: torch.Tensor,
+                 grad_d2: torch.Tensor, out=None):
+        """Gradient of sum grad_d2 * d2 w.r.t. the points for the last
+        knn_self (see pg_batch_backward); deterministic."""
+        p = _points(points, "points")
+        k = idx.shape[1]
+        idx = idx.contiguous()
+        d2 = d2.contiguous()
+        g = grad_d2.contiguous().to(torch.float32)
+        gp = torch.empty_like(p) if out is None else out
+        check(lib().pg_batch_backward(self._h, ctypes.c_void_p(p.data_ptr()), k,
+                                      ctypes.c_void_p(idx.data_ptr()), ctypes.c_void_p(d2.data_ptr()),
+                                      ctypes.c_void_p(g.data_ptr()), ctypes.c_void_p(gp.data_ptr()),
+                                      stream_ptr(p.device)))
+        return gp
 
     def timed_out(self) -> bool:
         flag = ctypes.c_int32()

@@ -291,6 +291,239 @@ __global__ void grad_x_kernel(const float* __restrict__ q, const float* __restri
     gx[t] = accumulate ? gx[t] - acc : -acc;
 }
 
+// ---------------------------------------------------------------------------
+// Batched backward in leaf order.  The queries of a cloud are taken in the
+// order of its tree's leaves (work items of kBwdItem positions), so the
+// neighbours of an item's queries lie mostly in the window of positions
+// [p0 - kBwdMargin, p0 + kBwdItem + kBwdMargin): their terms are summed in
+// LDS and the window is stored whole to the item's slot (plain stores); the
+// few pairs whose neighbour lies outside it are listed in LDS and their terms
+// go to global row accumulators after the loop (a global atomic inside the
+// loop would make every later load of the wave wait for it).  A finishing pass adds,
+// for each position, its own item's window entry and the one neighbouring
+// item's window that also covers it.  All sums are integer (int64 fixed
+// point, each term rounded once), so they do not depend on the order of the
+// adds: the result is deterministic.  Scale: every term is at most
+// T = 2 max|g| sqrt(max D) in magnitude (with the forward's D); terms are
+// multiplied by 2^(30 - ceil(log2 T)) and rounded to int32, so a sum of up
+// to 2^32 of them fits in int64.
+// ---------------------------------------------------------------------------
+constexpr int kBwdItem = 1024;                    // leaf positions per backward work item
+constexpr int kBwdMargin = 448;                   // window margin on each side (<= kBwdItem / 2)
+static_assert(2 * kBwdMargin <= kBwdItem, "a position lies in at most one neighbour's window");
+constexpr int kBwdWin = kBwdItem + 2 * kBwdMargin;  // window positions
+constexpr int kBwdSpill = 1536;                   // out-of-window pairs deferred per item
+// the spilled pairs' records ((d + 1) words each) reuse the window's LDS
+static_assert(kBwdSpill * 2 * 4 <= kBwdWin * 8, "spill records must fit the window (d = 1)");
+
+__device__ inline int cloud_of_item(const int64_t* __restrict__ start, int C, int64_t it) {
+    int lo = 0, hi = C;  // start[lo] <= it < start[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (start[mid] <= it) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// inv[row] = leaf position of the row within its cloud.
+__global__ void bwd_inv_kernel(const CloudDesc* __restrict__ desc, const int64_t* __restrict__ start,
+                               int C, const int32_t* __restrict__ pidx, int32_t* __restrict__ inv) {
+    const int c = cloud_of_item(start, C, blockIdx.x);
+    const CloudDesc D = desc[c];
+    const int64_t p0 = ((int64_t)blockIdx.x - start[c]) * kBwdItem;
+    for (int e = threadIdx.x; e < kBwdItem; e += kNT) {
+        const int64_t pos = p0 + e;
+        if (pos < D.n) inv[D.row + pidx[D.row + pos]] = (int32_t)pos;
+    }
+}
+
+// maxes[0] = max |g|, maxes[1] = max D over the pairs with a neighbour (as
+// float bits: non-negative floats order like their bits).
+__global__ void bwd_scale_kernel(const int32_t* __restrict__ idx, const float* __restrict__ g,
+                                 const float* __restrict__ d2, int64_t P, uint32_t* __restrict__ maxes) {
+    uint32_t mg = 0, md = 0;
+    for (int64_t p = (int64_t)blockIdx.x * kNT + threadIdx.x; p < P; p += (int64_t)gridDim.x * kNT) {
+        if (idx[p] < 0) continue;
+        const uint32_t a = __float_as_uint(fabsf(g[p])), b = __float_as_uint(d2[p]);
+        mg = a > mg ? a : mg;
+        md = b > md ? b : md;
+    }
+    mg = wave_max_u32(mg);
+    md = wave_max_u32(md);
+    if (lane_id() == 0) {
+        atomicMax(&maxes[0], mg);
+        atomicMax(&maxes[1], md);
+    }
+}
+
+// Power-of-two scale of the terms (see above); 1 when every term is 0.
+__device__ inline float bwd_scale(const uint32_t* maxes) {
+    const float t = 2.0f * __uint_as_float(maxes[0]) * sqrtf(__uint_as_float(maxes[1]));
+    if (!(t > 0.0f) || !(t <= 3.0e38f)) return 1.0f;
+    int e = 0;
+    (void)frexpf(t, &e);  // t < 2^e
+    return ldexpf(1.0f, 30 - e);
+}
+
+// One work item: kBwdItem leaf positions of one cloud.  Lane queries i (in
+// leaf order) accumulate their own gradient in registers (fixed order) and
+// write it to gout; the neighbour terms go to the LDS window, or the pair to
+// the spill list; the window is then stored to the item's slot of wbuf and the
+// spilled pairs' terms are added to acc.
+template <int MD>
+__global__ void __launch_bounds__(kNT)
+bwd_main_kernel(const CloudDesc* __restrict__ desc, const int64_t* __restrict__ start, int C,
+                const int32_t* __restrict__ pidx, const int32_t* __restrict__ inv,
+                const float* __restrict__ x, int d_, int k, const int32_t* __restrict__ idx,
+                const float* __restrict__ g, const uint32_t* __restrict__ maxes,
+                unsigned long long* __restrict__ acc, unsigned long long* __restrict__ wbuf,
+                float* __restrict__ gout) {
+    extern __shared__ __align__(16) unsigned long long win[];  // [kBwdWin][d]
+    __shared__ uint32_t spill[kBwdSpill];
+    __shared__ uint32_t nspill;
+    const int d = MD < 8 ? MD : d_;
+    const int c = cloud_of_item(start, C, blockIdx.x);
+    const CloudDesc D = desc[c];
+    const int64_t p0 = ((int64_t)blockIdx.x - start[c]) * kBwdItem;
+    const int64_t org = p0 - kBwdMargin;  // position of window entry 0
+    for (int e = threadIdx.x; e < kBwdWin * d; e += kNT) win[e] = 0ull;
+    if (threadIdx.x == 0) nspill = 0;
+    __syncthreads();
+    const float scale = bwd_scale(maxes);
+    for (int e = threadIdx.x; e < kBwdItem; e += kNT) {
+        const int64_t pos = p0 + e;
+        if (pos >= D.n) break;
+        const int64_t i = D.row + pidx[D.row + pos];
+        float xi[MD], gq[MD];
+#pragma unroll
+        for (int cc = 0; cc < MD; cc++) {
+            xi[cc] = (MD < 8 || cc < d) ? x[i * d + cc] : 0.0f;
+            gq[cc] = 0.0f;
+        }
+        // the row's neighbours four at a time: 16-byte loads of the index and
+        // gradient rows (each row is read once, not word by word across the
+        // loop), then the four neighbours' coordinates and leaf positions
+        for (int r0 = 0; r0 < k; r0 += 4) {
+            int32_t jj[4];
+            float gg[4];
+            if ((k & 3) == 0) {
+                const int4 jv = *reinterpret_cast<const int4*>(idx + i * k + r0);
+                const float4 gv = *reinterpret_cast<const float4*>(g + i * k + r0);
+                jj[0] = jv.x; jj[1] = jv.y; jj[2] = jv.z; jj[3] = jv.w;
+                gg[0] = gv.x; gg[1] = gv.y; gg[2] = gv.z; gg[3] = gv.w;
+            } else {
+#pragma unroll
+                for (int u = 0; u < 4; u++) {
+                    jj[u] = r0 + u < k ? idx[i * k + r0 + u] : -1;
+                    gg[u] = r0 + u < k ? g[i * k + r0 + u] : 0.0f;
+                }
+            }
+            float xj[4][MD];
+            int64_t w[4];
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                const int32_t j = jj[u] >= 0 ? jj[u] : (int32_t)i;  // a safe row for the loads
+#pragma unroll
+                for (int cc = 0; cc < MD; cc++)
+                    xj[u][cc] = (MD < 8 || cc < d) ? x[(int64_t)j * d + cc] : 0.0f;
+                // a neighbour of the same cloud inside the window sums in LDS
+                const bool same = jj[u] >= 0 && j >= D.row && j < D.row + D.n;
+                w[u] = same ? (int64_t)inv[j] - org : -1;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                if (jj[u] < 0) continue;
+                const float gr = gg[u];
+                const bool in_win = w[u] >= 0 && w[u] < kBwdWin;
+                int32_t t[MD];
+#pragma unroll
+                for (int cc = 0; cc < MD; cc++) {
+                    const float diff = xi[cc] - xj[u][cc];
+                    gq[cc] += 2.0f * gr * diff;
+                    t[cc] = (int32_t)rintf(-2.0f * gr * diff * scale);
+                }
+                if (in_win) {
+#pragma unroll
+                    for (int cc = 0; cc < MD; cc++)
+                        if (MD < 8 || cc < d)
+                            atomicAdd(&win[w[u] * d + cc], (unsigned long long)(long long)t[cc]);
+                } else {
+                    const uint32_t sl = atomicAdd(&nspill, 1u);
+                    if (sl < (uint32_t)kBwdSpill) {
+                        spill[sl] = (uint32_t)(i * k + r0 + u);
+                    } else {  // list full (only with pathological data): directly
+#pragma unroll
+                        for (int cc = 0; cc < MD; cc++)
+                            if (MD < 8 || cc < d)
+                                atomicAdd(&acc[(int64_t)jj[u] * d + cc], (unsigned long long)(long long)t[cc]);
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int cc = 0; cc < MD; cc++)
+            if (MD < 8 || cc < d) gout[i * d + cc] = gq[cc];
+    }
+    __syncthreads();
+    unsigned long long* slot = wbuf + (int64_t)blockIdx.x * kBwdWin * d;
+    for (int e = threadIdx.x; e < kBwdWin * d; e += kNT) slot[e] = win[e];
+    __syncthreads();
+    // spilled pairs: terms into the (now free) window space, then the atomics
+    const int ns = nspill < (uint32_t)kBwdSpill ? (int)nspill : kBwdSpill;
+    int32_t* rec = reinterpret_cast<int32_t*>(win);  // [ns][d + 1]: row j, terms
+    for (int e = threadIdx.x; e < ns; e += kNT) {
+        const uint32_t pp = spill[e];
+        const int64_t i = pp / (uint32_t)k;
+        const int32_t j = idx[pp];
+        const float gr = g[pp];
+        rec[e * (d + 1)] = j;
+        for (int cc = 0; cc < d; cc++) {
+            const float diff = x[i * d + cc] - x[(int64_t)j * d + cc];
+            rec[e * (d + 1) + 1 + cc] = (int32_t)rintf(-2.0f * gr * diff * scale);
+        }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < ns * d; e += kNT) {
+        const int q = e / d, cc = e - q * d;
+        const int64_t j = rec[q * (d + 1)];
+        atomicAdd(&acc[j * d + cc], (unsigned long long)(long long)rec[q * (d + 1) + 1 + cc]);
+    }
+}
+
+// Per item: each of its positions takes its own window entry, the entry of
+// the neighbouring item of the same cloud whose window also covers it, if any
+// (the previous item's below p0 + kBwdMargin, the next item's from
+// p0 + kBwdItem - kBwdMargin on), and its row accumulator; gout += that sum /
+// scale.
+__global__ void __launch_bounds__(kNT)
+bwd_finish_kernel(const CloudDesc* __restrict__ desc, const int64_t* __restrict__ start, int C,
+                  const int32_t* __restrict__ pidx, int d,
+                  const unsigned long long* __restrict__ wbuf,
+                  const unsigned long long* __restrict__ acc, const uint32_t* __restrict__ maxes,
+                  float* __restrict__ gout) {
+    const int c = cloud_of_item(start, C, blockIdx.x);
+    const CloudDesc D = desc[c];
+    const int64_t b = blockIdx.x, b0 = start[c], b1 = start[c + 1];
+    const int64_t p0 = (b - b0) * kBwdItem;
+    const float inv_scale = 1.0f / bwd_scale(maxes);
+    const unsigned long long* own = wbuf + b * kBwdWin * d;
+    for (int e = threadIdx.x; e < kBwdItem * d; e += kNT) {
+        const int64_t pos = p0 + e / d;
+        const int cc = e % d;
+        if (pos >= D.n) break;
+        const int64_t row = D.row + pidx[D.row + pos];
+        long long v = (long long)own[(pos - (p0 - kBwdMargin)) * d + cc];
+        if (pos < p0 + kBwdMargin) {
+            if (b > b0) v += (long long)wbuf[(b - 1) * kBwdWin * d + (pos - (p0 - kBwdItem - kBwdMargin)) * d + cc];
+        } else if (pos >= p0 + kBwdItem - kBwdMargin) {
+            if (b + 1 < b1) v += (long long)wbuf[(b + 1) * kBwdWin * d + (pos - (p0 + kBwdItem - kBwdMargin)) * d + cc];
+        }
+        v += (long long)acc[row * d + cc];
+        gout[row * d + cc] += (float)((double)v * (double)inv_scale);
+    }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -305,6 +538,7 @@ struct BatchPlan {
            o_keys = 0, o_pidx = 0, o_pidx2 = 0, o_split = 0, o_bbox = 0, o_rec = 0;
     std::vector<int32_t> order;
     std::vector<int64_t> qstart;
+    std::vector<int64_t> bstart;  // first backward work item of cloud c (cloud order)
     std::vector<CloudDesc> desc;
 };
 
@@ -355,6 +589,13 @@ static pg_status make_plan(const int64_t* offs, int C, int d, int leaf, int bpc,
     }
     P.qstart[C] = q;
     P.total_items = C + q;
+    P.bstart.resize(C + 1);
+    int64_t bi = 0;
+    for (int c = 0; c < C; c++) {
+        P.bstart[c] = bi;
+        bi += (P.desc[c].n + kBwdItem - 1) / kBwdItem;
+    }
+    P.bstart[C] = bi;
     size_t o = 0;
     P.o_queue = o; o = align256(o + 16);
     P.o_ready = o; o = align256(o + 4 * (size_t)C);
@@ -380,6 +621,7 @@ struct pg_batch {
     bool owns = false;
     hipStream_t stream = nullptr;
     int num_cu = 0;
+    int64_t* bstart_dev = nullptr;  // plan.bstart on the device (first backward call)
 };
 
 namespace pg {
@@ -614,7 +856,59 @@ pg_status pg_batch_autotune(const float* points, const int64_t* offsets_host, in
 void pg_batch_free(pg_batch* b) {
     if (!b) return;
     if (b->owns) dfree(b->ws, b->stream);
+    if (b->bstart_dev) dfree(b->bstart_dev, b->stream);
     delete b;
+}
+
+pg_status pg_batch_backward(pg_batch* b, const float* points, int32_t k, const int32_t* idx,
+                            const float* d2, const float* grad_d2, float* grad_points,
+                            void* stream) {
+    if (!b) return fail(PG_ERR_INVALID, "pg_batch_backward: handle is NULL");
+    if (k < 1 || k > 64) return fail(PG_ERR_INVALID, "pg_batch_backward: k must be in [1, 64]");
+    const BatchPlan& PL = b->plan;
+    const int64_t N = PL.N;
+    if (N == 0) return PG_OK;
+    if (!points || !idx || !d2 || !grad_d2 || !grad_points)
+        return fail(PG_ERR_INVALID, "pg_batch_backward: NULL pointer");
+    if (N * (int64_t)k >= ((int64_t)1 << 32)) return fail(PG_ERR_INVALID, "pg_batch_backward: N * k too large");
+    hipStream_t s = (hipStream_t)stream;
+    const int C = PL.C, d = PL.d;
+    if (!b->bstart_dev) {
+        PG_TRY(dalloc(&b->bstart_dev, (size_t)(C + 1), s));
+        PG_HIP(hipMemcpyAsync(b->bstart_dev, PL.bstart.data(), sizeof(int64_t) * (C + 1),
+                              hipMemcpyHostToDevice, s));
+    }
+    const int64_t items = PL.bstart[C];
+    const CloudDesc* desc = (const CloudDesc*)(b->ws + PL.o_desc);
+    const int32_t* pidx = (const int32_t*)(b->ws + PL.o_pidx);
+    DevBuf inv(s), acc(s), maxes(s), wbuf(s);
+    PG_TRY(inv.alloc(sizeof(int32_t) * (size_t)N));
+    PG_TRY(acc.alloc(sizeof(unsigned long long) * (size_t)N * d));
+    PG_TRY(maxes.alloc(sizeof(uint32_t) * 2));
+    PG_TRY(wbuf.alloc(sizeof(unsigned long long) * (size_t)items * kBwdWin * d));
+    PG_HIP(hipMemsetAsync(acc.p, 0, sizeof(unsigned long long) * (size_t)N * d, s));
+    PG_HIP(hipMemsetAsync(maxes.p, 0, sizeof(uint32_t) * 2, s));
+    hipLaunchKernelGGL(bwd_inv_kernel, dim3((unsigned)items), dim3(kNT), 0, s, desc,
+                       (const int64_t*)b->bstart_dev, C, pidx, inv.as<int32_t>());
+    PG_LAUNCH_CHECK();
+    const int64_t P = N * k;
+    hipLaunchKernelGGL(bwd_scale_kernel, dim3(cdiv(P, kNT) < 4096u ? cdiv(P, kNT) : 4096u), dim3(kNT),
+                       0, s, idx, grad_d2, d2, P, maxes.as<uint32_t>());
+    PG_LAUNCH_CHECK();
+    const size_t lds = sizeof(unsigned long long) * (size_t)kBwdWin * d;
+    auto main_kernel = d == 2 ? bwd_main_kernel<2>
+                     : d == 3 ? bwd_main_kernel<3>
+                     : d == 5 ? bwd_main_kernel<5> : bwd_main_kernel<8>;
+    hipLaunchKernelGGL(main_kernel, dim3((unsigned)items), dim3(kNT), lds, s, desc,
+                       (const int64_t*)b->bstart_dev, C, pidx, inv.as<int32_t>(), points, d, k, idx,
+                       grad_d2, maxes.as<uint32_t>(), acc.as<unsigned long long>(),
+                       wbuf.as<unsigned long long>(), grad_points);
+    PG_LAUNCH_CHECK();
+    hipLaunchKernelGGL(bwd_finish_kernel, dim3((unsigned)items), dim3(kNT), 0, s, desc,
+                       (const int64_t*)b->bstart_dev, C, pidx, d, wbuf.as<unsigned long long>(),
+                       acc.as<unsigned long long>(), maxes.as<uint32_t>(), grad_points);
+    PG_LAUNCH_CHECK();
+    return PG_OK;
 }
 
 pg_status pg_knn_backward(const float* queries, const float* points, int64_t m, int64_t n,

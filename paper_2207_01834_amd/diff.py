@@ -1,8 +1,10 @@
 """Differentiable k-NN squared distances (torch.autograd.Function).
 
 Forward: the GPU k-NN (batched clouds in one persistent launch, or a static
-tree for a separate query set).  Backward: the library's hand-written kernel
-(pg_knn_backward), with the neighbour sets held fixed from the forward pass.
+tree for a separate query set).  Backward: the library's hand-written kernels
+(pg_batch_backward in the clouds' leaf order while the forward's trees are
+still current, else pg_knn_backward), with the neighbour sets held fixed from
+the forward pass.
 """
 from __future__ import annotations
 
@@ -15,16 +17,22 @@ class _SelfKnn(torch.autograd.Function):
     @staticmethod
     def forward(ctx, x, k, batch):
         idx, d2 = batch.knn_self(x.detach(), k)
-        ctx.save_for_backward(x, idx)
+        ctx.save_for_backward(x, idx, d2)
+        ctx.batch = batch
+        ctx.generation = batch.generation
         ctx.mark_non_differentiable(idx)
         return d2, idx
 
     @staticmethod
     def backward(ctx, g_d2, g_idx):
-        x, idx = ctx.saved_tensors
+        x, idx, d2 = ctx.saved_tensors
         if g_d2 is None:
             return None, None, None
-        gx, _ = B.knn_backward(x.detach(), x.detach(), idx, g_d2, self_mode=True)
+        if ctx.batch.generation == ctx.generation:
+            # the clouds' trees of this forward are still in the workspace
+            gx = ctx.batch.backward(x.detach(), idx, d2, g_d2)
+        else:
+            gx, _ = B.knn_backward(x.detach(), x.detach(), idx, g_d2, self_mode=True)
         return gx, None, None
 
 

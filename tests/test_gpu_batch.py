@@ -200,6 +200,42 @@ def test_backward_fd_and_closed_form(pg, dev):
     assert np.array_equal(host(x2.grad)[0], host(x.grad)[0])
 
 
+@pytest.mark.parametrize("d,k", [(3, 16), (3, 7), (5, 10)])
+def test_batched_backward_leaf_order(pg, dev, d, k):
+    """pg_batch_backward (leaf-order windows, int64 fixed point) against the
+    FP64 closed form with the GPU's neighbour sets, on uneven clouds with an
+    empty cloud, clouds smaller than k and a cloud of identical points (its
+    first k rows are every point's neighbours: far outside any window); and
+    against the generic backward; deterministic over two calls."""
+    import torch
+    g = np.random.default_rng(40 + d + k)
+    sizes = np.floor(np.exp(g.uniform(0, np.log(9000), size=40))).astype(np.int64)
+    sizes[:4] = [0, 3, 2500, 6000]
+    if d == 3:
+        pts, offs = datagen.sphere_clouds(sizes, 40 + k)
+    else:
+        offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+        pts = g.standard_normal((int(offs[-1]), d)).astype(np.float32)
+    a, b = int(offs[2]), int(offs[3])
+    pts[a:b] = pts[a]  # identical points
+    G = g.standard_normal((len(pts), k)).astype(np.float32)
+    B = pg.BatchKnn(offs, d, device=dev)
+    x = to_dev(pts, dev)
+    idx, d2 = B.knn_self(x, k)
+    gb = B.backward(x, idx, d2, to_dev(G, dev))
+    gb2 = B.backward(x, idx, d2, to_dev(G, dev))
+    grad = host(gb)[0].astype(np.float64)
+    assert np.array_equal(host(gb2)[0], host(gb)[0])
+    idx_h = host(idx)[0].astype(np.int64)
+    gq, gx = grad_closed_form(pts, pts, idx_h, G)
+    cf = gq + gx
+    scale = np.abs(cf).max()
+    assert np.all(np.abs(grad - cf) <= 1e-5 * np.abs(cf) + 1e-5 * scale)
+    gen, _ = pg.knn_backward(x, x, idx, to_dev(G, dev), self_mode=True)
+    gen = host(gen)[0].astype(np.float64)
+    assert np.all(np.abs(grad - gen) <= 1e-5 * np.abs(cf) + 1e-5 * scale)
+
+
 def test_backward_query_form(pg, dev):
     import torch
 
