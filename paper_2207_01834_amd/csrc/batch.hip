@@ -338,14 +338,16 @@ __global__ void bwd_inv_kernel(const CloudDesc* __restrict__ desc, const int64_t
     }
 }
 
-// maxes[0] = max |g|, maxes[1] = max D over the pairs with a neighbour (as
-// float bits: non-negative floats order like their bits).
-__global__ void bwd_scale_kernel(const int32_t* __restrict__ idx, const float* __restrict__ g,
-                                 const float* __restrict__ d2, int64_t P, uint32_t* __restrict__ maxes) {
+// maxes[0] = max |g|, maxes[1] = max D over the pairs with a neighbour (the
+// padding of a cloud smaller than k has D = +inf); as float bits:
+// non-negative floats order like their bits.
+__global__ void bwd_scale_kernel(const float* __restrict__ g, const float* __restrict__ d2,
+                                 int64_t P, uint32_t* __restrict__ maxes) {
     uint32_t mg = 0, md = 0;
     for (int64_t p = (int64_t)blockIdx.x * kNT + threadIdx.x; p < P; p += (int64_t)gridDim.x * kNT) {
-        if (idx[p] < 0) continue;
-        const uint32_t a = __float_as_uint(fabsf(g[p])), b = __float_as_uint(d2[p]);
+        const float dp = d2[p];
+        if (!(dp < __builtin_huge_valf())) continue;
+        const uint32_t a = __float_as_uint(fabsf(g[p])), b = __float_as_uint(dp);
         mg = a > mg ? a : mg;
         md = b > md ? b : md;
     }
@@ -893,7 +895,7 @@ pg_status pg_batch_backward(pg_batch* b, const float* points, int32_t k, const i
     PG_LAUNCH_CHECK();
     const int64_t P = N * k;
     hipLaunchKernelGGL(bwd_scale_kernel, dim3(cdiv(P, kNT) < 4096u ? cdiv(P, kNT) : 4096u), dim3(kNT),
-                       0, s, idx, grad_d2, d2, P, maxes.as<uint32_t>());
+                       0, s, grad_d2, d2, P, maxes.as<uint32_t>());
     PG_LAUNCH_CHECK();
     const size_t lds = sizeof(unsigned long long) * (size_t)kBwdWin * d;
     auto main_kernel = d == 2 ? bwd_main_kernel<2>
