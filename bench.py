@@ -9,10 +9,12 @@ end-to-end rate (queries per second of the whole step, build included);
 ``build_mpts_s`` and ``knn_qps`` give the two parts.
 
 The roofline object covers the dominant kernel (the k-NN search): its
-algorithmic bytes per query come from the oracle's visit counts on this
-workload (see the design doc and ``python -m oracle.visit_counts``), multiplied by
-the n queries of one launch and divided by the launch time measured with HIP
-events on the stream the kernel runs on.
+algorithmic bytes per query, 4d + k(4 + 8) + 4 N_int + 4(d+1) N_pts, take
+the internal nodes and points the oracle's canonical search visits per query
+on this workload (``python -m oracle.visit_counts``), are multiplied by the n
+queries of one launch and divided by the launch time measured with HIP events
+on the stream the kernel runs on.  ``traffic`` is the HBM bytes the kernel
+really moved, from rocprofv3 counters (``--write-traffic``).
 
 The cpu_baseline object times the CPU oracle (serial C) on the same points:
 the full tree build and the k-NN search of a sample of queries, projected to
