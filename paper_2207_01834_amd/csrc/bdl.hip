@@ -11,7 +11,8 @@
 //     destroyed trees in their staging order (scatter of liveness flags to
 //     staging positions, prefix sum, gather), appends the tree-bound slice of
 //     the batch, and builds each new tree;
-//   * erase runs one lane per (erase point, tree): a stack-free walk that
+//   * erase runs one lane per (erase point, tree), the points in the largest
+//     tree's leaf order: a stack-free walk that
 //     enters both children where the coordinate equals the split, and clears
 //     the liveness bit of every live point with equal coordinates (atomic AND,
 //     so duplicates count once); the per-tree counts come back in one read;
@@ -101,12 +102,15 @@ __global__ void leaf_ids_kernel(const int32_t* __restrict__ pidx, const int64_t*
 // equals the split) and clears live points with equal coordinates.
 template <typename T, int MD>
 __global__ void __launch_bounds__(kNT)
-erase_kernel(Forest f, const uint32_t* __restrict__ pts, int64_t m, int d,
-             unsigned long long* __restrict__ erased) {
+erase_kernel(Forest f, const uint32_t* __restrict__ pts, const int32_t* __restrict__ order,
+             int64_t m, int d, unsigned long long* __restrict__ erased) {
     using M = Metric<T>;
-    const int64_t qi = (int64_t)blockIdx.x * kNT + threadIdx.x;
+    const int64_t q0 = (int64_t)blockIdx.x * kNT + threadIdx.x;
     const int slot = blockIdx.y;
-    if (qi >= m) return;
+    if (q0 >= m) return;
+    // points taken in the largest tree's leaf order when an order is given:
+    // neighbouring lanes then walk nearly the same nodes
+    const int64_t qi = order ? (int64_t)order[q0] : q0;
     const ForestSlot& S = f.s[slot];
     const TreeView& tv = S.tv;
     if (tv.n == 0) return;
@@ -141,10 +145,13 @@ erase_kernel(Forest f, const uint32_t* __restrict__ pts, int64_t m, int d,
         if (inside) {
             const int64_t lo = node_start(tv.n, tv.L, leaf), hi = node_start(tv.n, tv.L, leaf + 1);
             for (int64_t i = lo; i < hi; i++) {
+                T p[MD];
+                uint32_t idw;
+                load_point<T, MD>(tv, i, d, p, idw);
                 bool eq = true;
 #pragma unroll
                 for (int c = 0; c < MD; c++)
-                    if (c < d) eq = eq && (M::load(tv.pts[(int64_t)c * tv.n + i]) == q[c]);
+                    if (c < d) eq = eq && (p[c] == q[c]);
                 if (eq) {
                     const uint32_t bit = 1u << (i & 31);
                     const uint32_t old = atomicAnd(&S.alive[i >> 5], ~bit);
@@ -185,22 +192,22 @@ bdl_knn_kernel(Forest f, const uint32_t* __restrict__ queries, const int32_t* __
 }
 
 template <typename T, int MD>
-pg_status launch_erase(const Forest& f, const void* pts, int64_t m, int d,
+pg_status launch_erase(const Forest& f, const void* pts, const int32_t* order, int64_t m, int d,
                        unsigned long long* erased, hipStream_t s) {
     hipLaunchKernelGGL((erase_kernel<T, MD>), dim3(cdiv(m, kNT), f.count), dim3(kNT), 0, s, f,
-                       (const uint32_t*)pts, m, d, erased);
+                       (const uint32_t*)pts, order, m, d, erased);
     PG_LAUNCH_CHECK();
     return PG_OK;
 }
 
 template <typename T>
-pg_status erase_d(const Forest& f, const void* pts, int64_t m, int d, unsigned long long* e,
-                  hipStream_t s) {
+pg_status erase_d(const Forest& f, const void* pts, const int32_t* o, int64_t m, int d,
+                  unsigned long long* e, hipStream_t s) {
     switch (d) {
-        case 2: return launch_erase<T, 2>(f, pts, m, d, e, s);
-        case 3: return launch_erase<T, 3>(f, pts, m, d, e, s);
-        case 5: return launch_erase<T, 5>(f, pts, m, d, e, s);
-        default: return launch_erase<T, 8>(f, pts, m, d, e, s);
+        case 2: return launch_erase<T, 2>(f, pts, o, m, d, e, s);
+        case 3: return launch_erase<T, 3>(f, pts, o, m, d, e, s);
+        case 5: return launch_erase<T, 5>(f, pts, o, m, d, e, s);
+        default: return launch_erase<T, 8>(f, pts, o, m, d, e, s);
     }
 }
 
@@ -514,8 +521,14 @@ pg_status pg_bdl_erase(pg_bdl* h, const void* points, int64_t m, void* stream, i
     PG_TRY(cnt.alloc(sizeof(unsigned long long) * kSlots));
     PG_HIP(hipMemsetAsync(cnt.p, 0, sizeof(unsigned long long) * kSlots, s));
     unsigned long long* e = cnt.as<unsigned long long>();
-    if (B.dtype == PG_FLOAT32) PG_TRY(erase_d<float>(f, points, m, B.d, e, s));
-    else PG_TRY(erase_d<int32_t>(f, points, m, B.d, e, s));
+    DevBuf order(s);
+    const int32_t* o = nullptr;
+    if (m >= kOrderMin) {
+        PG_TRY(order_queries(f.s[0].tv, B.dtype == PG_FLOAT32, points, m, s, order));
+        o = order.as<int32_t>();
+    }
+    if (B.dtype == PG_FLOAT32) PG_TRY(erase_d<float>(f, points, o, m, B.d, e, s));
+    else PG_TRY(erase_d<int32_t>(f, points, o, m, B.d, e, s));
     unsigned long long host[kSlots];
     PG_HIP(hipMemcpyAsync(host, e, sizeof(host), hipMemcpyDeviceToHost, s));
     PG_HIP(hipStreamSynchronize(s));
