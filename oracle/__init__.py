@@ -12,7 +12,10 @@ Parts (each function cites the passage it follows):
   * ``bdl_model``  -- the BDL-tree's logarithmic method on point sets
                       (Algorithms 3 and 4), in Python;
   * ``grad``       -- the closed-form FP64 gradient of summed k-NN squared
-                      distances and central finite differences, in NumPy.
+                      distances and central finite differences, in NumPy;
+  * ``range_brute`` / ``KdTree.range`` -- the orthogonal range query written
+                      out, and on the tree (C, ``or_range_brute`` /
+                      ``or_kd_range``).
 
 Readings of the paper adopted where it is silent (also listed in the design
 notes): ties in distance go to the smaller id; squared distances are exact
@@ -54,6 +57,10 @@ def lib():
         L.or_kd_export.restype = None
         L.or_kd_knn.argtypes = [vp, vp, vp, vp, i64, i32, vp, vp, vp]
         L.or_kd_knn.restype = i32
+        L.or_range_brute.argtypes = [vp, vp, vp, i64, i32, i32, vp, i64, vp, vp, vp]
+        L.or_range_brute.restype = i32
+        L.or_kd_range.argtypes = [vp, vp, vp, vp, i64, vp, vp, vp, vp]
+        L.or_kd_range.restype = i32
         _lib = L
     return _lib
 
@@ -95,6 +102,38 @@ def knn_brute(points, queries, k, ids=None, alive=None, nthreads=1):
     if rc != 0:
         raise ValueError("or_knn_brute: bad arguments")
     return out_id, out_d
+
+
+def _offsets(counts):
+    off = np.zeros(counts.shape[0] + 1, dtype=np.int64)
+    np.cumsum(counts, out=off[1:])
+    return off
+
+
+def range_brute(points, boxes, ids=None, alive=None):
+    """The orthogonal range query written out (reading: a query is a closed
+    box [lo, hi], boxes [m][2][d] = lo then hi; the result is every live
+    point inside it).  Returns (counts int64 [m], offsets int64 [m+1],
+    ids int64 [total]) with each box's ids in row order."""
+    points = np.ascontiguousarray(points)
+    dt = _dtype_code(points)
+    n, d = points.shape
+    boxes = np.ascontiguousarray(boxes, dtype=points.dtype).reshape(-1, 2, d)
+    m = boxes.shape[0]
+    if ids is not None:
+        ids = np.ascontiguousarray(ids, dtype=np.int64)
+    if alive is not None:
+        alive = np.ascontiguousarray(alive, dtype=np.uint8)
+    counts = np.zeros(m, dtype=np.int64)
+    rc = lib().or_range_brute(_ptr(points), _ptr(ids), _ptr(alive), n, d, dt, _ptr(boxes), m,
+                              _ptr(counts), None, None)
+    if rc != 0:
+        raise ValueError("or_range_brute: bad arguments")
+    off = _offsets(counts)
+    out = np.empty(int(off[-1]), dtype=np.int64)
+    lib().or_range_brute(_ptr(points), _ptr(ids), _ptr(alive), n, d, dt, _ptr(boxes), m,
+                         _ptr(counts), _ptr(off), _ptr(out))
+    return counts, off, out
 
 
 class KdTree:
@@ -149,6 +188,28 @@ class KdTree:
         if rc != 0:
             raise ValueError("or_kd_knn: bad arguments")
         return out_id, out_d, counters
+
+    def range(self, boxes, ids=None, alive=None):
+        """Range search on the tree (boxes inside the query report whole,
+        boxes missing it are skipped); returns (counts, offsets, ids in leaf
+        order, counters = [node boxes tested, points tested])."""
+        boxes = np.ascontiguousarray(boxes, dtype=self.points.dtype).reshape(-1, 2, self.d)
+        m = boxes.shape[0]
+        if ids is not None:
+            ids = np.ascontiguousarray(ids, dtype=np.int64)
+        if alive is not None:
+            alive = np.ascontiguousarray(alive, dtype=np.uint8)
+        counts = np.zeros(m, dtype=np.int64)
+        counters = np.zeros(2, dtype=np.int64)
+        rc = lib().or_kd_range(self._h, _ptr(ids), _ptr(alive), _ptr(boxes), m, _ptr(counts),
+                               None, None, None)
+        if rc != 0:
+            raise ValueError("or_kd_range: bad arguments")
+        off = _offsets(counts)
+        out = np.empty(int(off[-1]), dtype=np.int64)
+        lib().or_kd_range(self._h, _ptr(ids), _ptr(alive), _ptr(boxes), m, _ptr(counts),
+                          _ptr(off), _ptr(out), _ptr(counters))
+        return counts, off, out, counters
 
 
 def tree_depth(n: int, leaf: int) -> int:

@@ -33,6 +33,10 @@
  *                     intersecting subtree boxes), run for every query, with
  *                     the 2k candidate buffer the same passage describes.
  *                     Counts visited internal nodes, leaves and points.
+ *   or_range_brute -- the orthogonal range query (Section 2, first module;
+ *                     Table 1) written out: every point inside a closed box.
+ *   or_kd_range    -- the same query on the tree (whole subtrees inside the
+ *                     box are reported, subtrees outside it skipped).
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -396,5 +400,117 @@ int or_kd_knn(const or_tree* T, const int64_t* ids, const uint8_t* alive,
     }
     free(B.buf);
     if (counters) { counters[0] = ci; counters[1] = cl; counters[2] = cp; }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* O7: orthogonal range search (the kd-tree range query of Section 2's      */
+/* first module and of Table 1).  The paper does not spell the query out;   */
+/* the reading used: a query is a closed axis-aligned box [lo, hi], and its */
+/* result is every (live) point p with lo_c <= p_c <= hi_c for all c.  A box */
+/* with lo_c > hi_c in some dimension is empty.  Coordinates are compared as */
+/* values (float32 widened to double, so -0.0 equals +0.0).                 */
+/* ------------------------------------------------------------------------ */
+static int in_box(const void* pts, int64_t j, const void* boxes, int64_t i, int d, int dt) {
+    for (int c = 0; c < d; c++) {
+        double p, lo, hi;
+        if (dt == OR_DT_INT) {
+            const int32_t* P = (const int32_t*)pts; const int32_t* B = (const int32_t*)boxes;
+            p = P[j * d + c]; lo = B[i * 2 * d + c]; hi = B[i * 2 * d + d + c];
+        } else {
+            const float* P = (const float*)pts; const float* B = (const float*)boxes;
+            p = P[j * d + c]; lo = B[i * 2 * d + c]; hi = B[i * 2 * d + d + c];
+        }
+        if (!(lo <= p && p <= hi)) return 0;
+    }
+    return 1;
+}
+
+/* The definition written out.  boxes [m][2][d] (lo[d] then hi[d]).
+ * counts [m] receives each box's number of live points.  When offsets is not
+ * NULL (offsets[i] = first output slot of box i), out_id also receives the
+ * ids of those points in row order (ids NULL: id = row). */
+int or_range_brute(const void* pts, const int64_t* ids, const uint8_t* alive, int64_t n,
+                   int d, int dt, const void* boxes, int64_t m,
+                   int64_t* counts, const int64_t* offsets, int64_t* out_id) {
+    if (d < 1 || n < 0 || m < 0 || !counts) return 1;
+    for (int64_t i = 0; i < m; i++) {
+        int64_t c = 0;
+        for (int64_t j = 0; j < n; j++) {
+            if (alive && !alive[j]) continue;
+            if (!in_box(pts, j, boxes, i, d, dt)) continue;
+            if (offsets) out_id[offsets[i] + c] = ids ? ids[j] : j;
+            c++;
+        }
+        counts[i] = c;
+    }
+    return 0;
+}
+
+/* Range search on the oracle's kd-tree: a node whose box lies inside the
+ * query reports all its points, a node whose box misses the query is
+ * skipped, otherwise its children are searched (leaves test every point).
+ * Counts the nodes whose box was tested and the points tested one by one. */
+typedef struct {
+    const or_tree* T; const void* boxes; int64_t i; const int64_t* ids; const uint8_t* alive;
+    int64_t c; const int64_t* offsets; int64_t* out_id; int64_t n_nodes, n_points;
+} range_ctx;
+
+static void range_emit(range_ctx* C, int64_t row) {
+    if (C->alive && !C->alive[row]) return;
+    if (C->offsets) C->out_id[C->offsets[C->i] + C->c] = C->ids ? C->ids[row] : row;
+    C->c++;
+}
+
+static void range_rec(range_ctx* C, int l, int64_t j) {
+    const or_tree* T = C->T;
+    const int d = T->d;
+    const int64_t h = ((int64_t)1 << l) + j;
+    const int64_t lo = node_lo(T->n, l, j), hi = node_lo(T->n, l, j + 1);
+    if (lo == hi) return;
+    C->n_nodes++;
+    int inside = 1, miss = 0;
+    for (int c = 0; c < d; c++) {
+        double qlo, qhi;
+        if (T->dt == OR_DT_INT) {
+            const int32_t* B = (const int32_t*)C->boxes;
+            qlo = B[C->i * 2 * d + c]; qhi = B[C->i * 2 * d + d + c];
+        } else {
+            const float* B = (const float*)C->boxes;
+            qlo = B[C->i * 2 * d + c]; qhi = B[C->i * 2 * d + d + c];
+        }
+        const double bl = T->bmin[h * d + c], bh = T->bmax[h * d + c];
+        if (bh < qlo || bl > qhi) miss = 1;
+        if (bl < qlo || bh > qhi) inside = 0;
+    }
+    if (miss) return;
+    if (inside || l == T->L) {
+        for (int64_t p = lo; p < hi; p++) {
+            if (!inside) {
+                C->n_points++;
+                if (!in_box(T->pts, T->perm[p], C->boxes, C->i, d, T->dt)) continue;
+            }
+            range_emit(C, T->perm[p]);
+        }
+        return;
+    }
+    range_rec(C, l + 1, 2 * j);
+    range_rec(C, l + 1, 2 * j + 1);
+}
+
+/* Arguments as or_range_brute (ids of a box come in leaf order here).
+ * counters (may be NULL): [0] node boxes tested, [1] points tested. */
+int or_kd_range(const or_tree* T, const int64_t* ids, const uint8_t* alive,
+                const void* boxes, int64_t m, int64_t* counts, const int64_t* offsets,
+                int64_t* out_id, int64_t* counters) {
+    if (!T || m < 0 || !counts) return 1;
+    int64_t cn = 0, cp = 0;
+    for (int64_t i = 0; i < m; i++) {
+        range_ctx C = {T, boxes, i, ids, alive, 0, offsets, out_id, 0, 0};
+        if (T->n > 0) range_rec(&C, 0, 0);
+        counts[i] = C.c;
+        cn += C.n_nodes; cp += C.n_points;
+    }
+    if (counters) { counters[0] = cn; counters[1] = cp; }
     return 0;
 }
