@@ -283,6 +283,57 @@ def form_batch(torch, pg, datagen, dev, loop_clouds):
             "backward_generic_ms": gen_ms}
 
 
+# Oracle visit counts per box on the range workload (100,000 sampled boxes):
+# node boxes tested 52.222, points tested 33.489, results 10.552.
+R_NODES, R_PTS = 52.222, 33.489
+
+
+def range_bytes_per_query(d, results, report):
+    """Algorithmic bytes of one range query: the box (8d), node boxes tested
+    (8d each), points tested (4(d+1) each), and the output: the count (4) in
+    the counting pass, the offset (8) and 4 bytes per result in the
+    reporting pass."""
+    tree = 8 * d + 8 * d * R_NODES + 4 * (d + 1) * R_PTS
+    return tree + (8 + 4 * results if report else 4)
+
+
+def form_range(torch, pg, datagen, dev, with_oracle):
+    """Orthogonal range search, the 2-D row of the paper's Table 1 read as:
+    10M uniform int32 points in [0,2^20)^2 and one closed square of half side
+    512 around every point (about 9.5 points per square); counting pass with
+    prefix sum, then the reporting pass."""
+    import numpy as np
+    pts = datagen.uniform_int(N, 2, seed=2)
+    boxes = datagen.range_boxes(pts, 512)
+    x = torch.from_numpy(pts).to(dev)
+    b = torch.from_numpy(boxes).to(dev)
+    holder = {}
+    build_ms = timed(torch, lambda: holder.__setitem__("t", pg.kdtree_build(x, leaf=LEAF)))
+    t = holder["t"]
+    counts, off, total = t.range_count(b, offsets=True)
+    rows = torch.empty(total, dtype=torch.int32, device=dev)
+    count_ms = timed(torch, lambda: t.range_count(b, offsets=True))
+    report_ms = timed(torch, lambda: t.range_report(b, off, rows))
+    out = {"workload": "2-D n=10M int32 uniform, a closed square of half side 512 around "
+                       "every point, leaf 16",
+           "build_ms": build_ms, "count_ms": count_ms, "report_ms": report_ms,
+           "results_per_query": total / N,
+           "qps": N / ((count_ms + report_ms) * 1e-3)}
+    res = total / N
+    for name, ms, rep in (("count", count_ms, False), ("report", report_ms, True)):
+        gbs = range_bytes_per_query(2, res, rep) * N / (ms * 1e-3) / 1e9
+        out[f"{name}_algorithmic_gbs"] = gbs
+        out[f"{name}_roofline_frac"] = gbs / HBM_PEAK_GBS
+    if with_oracle:
+        import oracle
+        sample = 100_000
+        T = oracle.KdTree(pts, leaf=LEAF)
+        t0 = time.perf_counter()
+        T.range(boxes[:sample])
+        out["oracle_qps_1core"] = sample / (time.perf_counter() - t0)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -293,7 +344,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms", default="all",
                     help="other forms to measure after the headline step: all, none, or a "
-                         "comma list of static_float,clustered,bdl,batch")
+                         "comma list of static_float,clustered,bdl,batch,range")
     ap.add_argument("--bdl-rounds", type=int, default=10)
     ap.add_argument("--loop-clouds", type=int, default=512,
                     help="clouds timed for the per-cloud comparison (projected to 4,096)")
@@ -405,7 +456,7 @@ def main():
     }
     del idx, dist, x
     torch.cuda.empty_cache()
-    forms = ["static_float", "clustered", "bdl", "batch"] if args.forms == "all" else \
+    forms = ["static_float", "clustered", "bdl", "batch", "range"] if args.forms == "all" else \
         [f for f in args.forms.split(",") if f and f != "none"]
     out = {}
     for f in forms:
@@ -418,6 +469,8 @@ def main():
             out[f] = form_bdl(torch, pg, datagen, dev, args.bdl_rounds)
         elif f == "batch":
             out[f] = form_batch(torch, pg, datagen, dev, args.loop_clouds)
+        elif f == "range":
+            out[f] = form_range(torch, pg, datagen, dev, not args.no_cpu_baseline)
         else:
             raise SystemExit(f"unknown form {f}")
         torch.cuda.empty_cache()

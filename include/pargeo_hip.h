@@ -108,6 +108,37 @@ pg_status pg_tree_export(const pg_tree* t, void* splits_host, int32_t* perm_host
 /* Releases the tree (stream-ordered on the stream it was built on). */
 void pg_tree_free(pg_tree* t);
 
+/* Orthogonal range search over the tree (the kd-tree range query of the
+ * paper's first module, Section 2, timed in Table 1; queries in parallel as
+ * in Appendix C).  Reading, where the paper does not define the query: a
+ * query is a closed axis-aligned box, and its result is every point p with
+ * lo_c <= p_c <= hi_c for all c (empty when lo_c > hi_c for some c);
+ * coordinates compare as values (-0.0 == +0.0).
+ *   boxes : [m][2][d] device, the tree's dtype: lo[d] then hi[d] per box;
+ *           coordinates obey the build's range rules
+ *   0 <= m < 2^31
+ *
+ * Counting pass.
+ *   counts     : [m] int32, number of points in each box
+ *   offsets    : [m+1] int64 or NULL; receives the exclusive prefix sum of
+ *                counts (offsets[m] = total), the layout pg_range_report
+ *                writes
+ *   total_host : (host, may be NULL) receives the total; then synchronises
+ * Synchronises (box range check). */
+pg_status pg_range_count(const pg_tree* t, const void* boxes, int64_t m, int32_t* counts,
+                         int64_t* offsets, int64_t* total_host, void* stream);
+
+/* Reporting pass: the input rows of box i's points go to
+ * out_idx[offsets[i] ...], in the tree's leaf order (deterministic for a
+ * given tree; sort a box's slice for row order).
+ *   offsets  : [m] int64 device, normally from pg_range_count
+ *   out_idx  : [capacity] int32 device
+ * A slot at or beyond `capacity` is never written; if one was needed the
+ * call returns PG_ERR_INVALID after the launch (the other slots are
+ * written).  Synchronises (box range check, overflow flag). */
+pg_status pg_range_report(const pg_tree* t, const void* boxes, int64_t m, const int64_t* offsets,
+                          int32_t* out_idx, int64_t capacity, void* stream);
+
 /* ---------------------------------------------------------------------- */
 /* BDL-tree (batch-dynamic kd-tree, Section 5; Appendix C)                 */
 /* ---------------------------------------------------------------------- */

@@ -46,6 +46,8 @@ SIGNATURES = {
     "pg_tree_info": (i32, [vp, P64, P32, P32, P32, P32]),
     "pg_tree_export": (i32, [vp, vp, vp, vp]),
     "pg_tree_free": (None, [vp]),
+    "pg_range_count": (i32, [vp, vp, i64, vp, vp, P64, vp]),
+    "pg_range_report": (i32, [vp, vp, i64, vp, vp, i64, vp]),
     "pg_bdl_create": (i32, [i32, i32, i32, i64, ctypes.POINTER(vp)]),
     "pg_bdl_insert": (i32, [vp, vp, i64, vp, P64]),
     "pg_bdl_erase": (i32, [vp, vp, i64, vp, P64]),
@@ -163,6 +165,56 @@ class KdTree:
         check(lib().pg_knn_all(self._h, k, ctypes.c_void_p(idx.data_ptr()),
                                ctypes.c_void_p(dist.data_ptr()), stream_ptr(self.device)))
         return idx, dist
+
+    def _boxes(self, boxes):
+        b = boxes.contiguous()
+        if b.dim() != 3 or b.shape[1] != 2 or b.shape[2] != self.d:
+            raise ValueError(f"boxes must be [m][2][{self.d}] (lo, hi)")
+        if not b.is_cuda:
+            raise ValueError("boxes must be a GPU tensor")
+        if _dtype_code(b) != self.dtype_code:
+            raise TypeError("boxes must have the tree's dtype")
+        return b
+
+    def range_count(self, boxes: torch.Tensor, offsets: bool = False):
+        """Number of points in each closed box (boxes [m][2][d]: lo, hi) as
+        int32 [m]; with ``offsets`` also the int64 [m+1] exclusive prefix sum
+        and the total."""
+        b = self._boxes(boxes)
+        m = b.shape[0]
+        counts = torch.empty(m, dtype=torch.int32, device=b.device)
+        if not offsets:
+            check(lib().pg_range_count(self._h, ctypes.c_void_p(b.data_ptr()), m,
+                                       ctypes.c_void_p(counts.data_ptr()), None, None,
+                                       stream_ptr(b.device)))
+            return counts
+        off = torch.empty(m + 1, dtype=torch.int64, device=b.device)
+        total = ctypes.c_int64()
+        check(lib().pg_range_count(self._h, ctypes.c_void_p(b.data_ptr()), m,
+                                   ctypes.c_void_p(counts.data_ptr()), ctypes.c_void_p(off.data_ptr()),
+                                   ctypes.byref(total), stream_ptr(b.device)))
+        return counts, off, total.value
+
+    def range_report(self, boxes: torch.Tensor, offsets: torch.Tensor, out: torch.Tensor):
+        """Writes the input rows of box i's points to out[offsets[i]:], in
+        leaf order (the layout :meth:`range_count` gives)."""
+        b = self._boxes(boxes)
+        if offsets.dtype != torch.int64 or not offsets.is_contiguous() or offsets.numel() < b.shape[0]:
+            raise ValueError("offsets must be a contiguous int64 tensor of at least m entries")
+        if out.dtype != torch.int32 or not out.is_contiguous():
+            raise ValueError("out must be a contiguous int32 tensor")
+        check(lib().pg_range_report(self._h, ctypes.c_void_p(b.data_ptr()), b.shape[0],
+                                    ctypes.c_void_p(offsets.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                    out.numel(), stream_ptr(b.device)))
+        return out
+
+    def range_search(self, boxes: torch.Tensor):
+        """Range search: (offsets int64 [m+1], rows int32 [total]); box i's
+        points are rows[offsets[i]:offsets[i+1]], in leaf order."""
+        counts, off, total = self.range_count(boxes, offsets=True)
+        out = torch.empty(max(total, 1), dtype=torch.int32, device=off.device)
+        self.range_report(boxes, off, out)
+        return off, out[:total]
 
     def export(self):
         """(split values of heap nodes 1..2^L-1, input rows in leaf order) as

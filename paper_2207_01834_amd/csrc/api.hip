@@ -5,6 +5,7 @@
 
 #include "build.hpp"
 #include "knn.hpp"
+#include "range.hpp"
 
 namespace pg {
 
@@ -102,6 +103,28 @@ pg_status pg_knn_all(const pg_tree* t, int32_t k, int32_t* out_idx, void* out_di
     if (k < 1 || k > 64) return fail(PG_ERR_INVALID, "pg_knn_all: k must be in [1, 64]");
     if (t->n > 0 && (!out_idx || !out_dist)) return fail(PG_ERR_INVALID, "pg_knn_all: NULL pointer");
     return knn_static(t, nullptr, t->n, k, true, out_idx, out_dist, (hipStream_t)stream);
+}
+
+pg_status pg_range_count(const pg_tree* t, const void* boxes, int64_t m, int32_t* counts,
+                         int64_t* offsets, int64_t* total_host, void* stream) {
+    if (!t) return fail(PG_ERR_INVALID, "pg_range_count: tree is NULL");
+    if (m < 0 || m >= ((int64_t)1 << 31)) return fail(PG_ERR_INVALID, "pg_range_count: m must be in [0, 2^31)");
+    if (m > 0 && (!boxes || !counts)) return fail(PG_ERR_INVALID, "pg_range_count: NULL pointer");
+    hipStream_t s = (hipStream_t)stream;
+    PG_TRY(check_queries(boxes, 2 * m, t->d, t->dtype == PG_FLOAT32, s));
+    return range_count(t, boxes, m, counts, offsets, total_host, s);
+}
+
+pg_status pg_range_report(const pg_tree* t, const void* boxes, int64_t m, const int64_t* offsets,
+                          int32_t* out_idx, int64_t capacity, void* stream) {
+    if (!t) return fail(PG_ERR_INVALID, "pg_range_report: tree is NULL");
+    if (m < 0 || m >= ((int64_t)1 << 31)) return fail(PG_ERR_INVALID, "pg_range_report: m must be in [0, 2^31)");
+    if (capacity < 0) return fail(PG_ERR_INVALID, "pg_range_report: capacity < 0");
+    if (m > 0 && (!boxes || !offsets || (capacity > 0 && !out_idx)))
+        return fail(PG_ERR_INVALID, "pg_range_report: NULL pointer");
+    hipStream_t s = (hipStream_t)stream;
+    PG_TRY(check_queries(boxes, 2 * m, t->d, t->dtype == PG_FLOAT32, s));
+    return range_report(t, boxes, m, offsets, out_idx, capacity, s);
 }
 
 pg_status pg_tree_info(const pg_tree* t, int64_t* n, int32_t* d, int32_t* leaf, int32_t* levels,

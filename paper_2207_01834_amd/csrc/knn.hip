@@ -88,18 +88,27 @@ knn_redo_kernel(TreeView tv, const uint32_t* __restrict__ queries, int k, int al
 }
 
 // Sort key of each query: the leaf its descent reaches (left below the
-// split, right at or above it), coarsened by `shift` bits.
+// split, right at or above it), coarsened by `shift` bits.  A box query
+// (rows lo[d], hi[d]) descends by its centre.
 __global__ void query_leaf_kernel(TreeView tv, int fl, const uint32_t* __restrict__ queries,
-                                  int64_t m, int shift, uint32_t* __restrict__ key) {
+                                  int64_t m, int shift, int box, uint32_t* __restrict__ key) {
     const int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x;
     if (i >= m) return;
     const int d = tv.d;
+    const int64_t row = box ? i * 2 * d : i * d;
     const uint32_t first_leaf = 1u << tv.L;
     uint32_t cur = 1;
     int dim = 0;
     while (cur < first_leaf) {
-        const uint32_t qb = queries[i * d + dim], sb = tv.split[cur];
-        const bool right = fl ? __uint_as_float(qb) >= __uint_as_float(sb) : (int32_t)qb >= (int32_t)sb;
+        const uint32_t qb = queries[row + dim], sb = tv.split[cur];
+        bool right;
+        if (box) {
+            const uint32_t hb = queries[row + d + dim];
+            right = fl ? 0.5f * __uint_as_float(qb) + 0.5f * __uint_as_float(hb) >= __uint_as_float(sb)
+                       : (int64_t)(int32_t)qb + (int32_t)hb >= 2 * (int64_t)(int32_t)sb;
+        } else {
+            right = fl ? __uint_as_float(qb) >= __uint_as_float(sb) : (int32_t)qb >= (int32_t)sb;
+        }
         cur = 2u * cur + (right ? 1u : 0u);
         dim = dim + 1 == d ? 0 : dim + 1;
     }
@@ -207,7 +216,7 @@ pg_status check_queries(const void* q, int64_t m, int d, bool fl, hipStream_t s)
 }
 
 pg_status order_queries(const TreeView& tv, bool fl, const void* queries, int64_t m,
-                        hipStream_t s, DevBuf& order) {
+                        hipStream_t s, DevBuf& order, bool boxes) {
     // buckets: the leaves, coarsened to about one bucket per 4 queries
     int bits = 0;
     while (bits < 24 && ((int64_t)1 << (bits + 1)) * 4 <= m) bits++;
@@ -222,7 +231,7 @@ pg_status order_queries(const TreeView& tv, bool fl, const void* queries, int64_
     PG_HIP(hipMemsetAsync(cnt.p, 0, sizeof(uint32_t) * nb, s));
     PG_HIP(hipMemsetAsync(cursor.p, 0, sizeof(uint32_t) * nb, s));
     hipLaunchKernelGGL(query_leaf_kernel, dim3(cdiv(m, kNT)), dim3(kNT), 0, s, tv, fl ? 1 : 0,
-                       (const uint32_t*)queries, m, shift, key.as<uint32_t>());
+                       (const uint32_t*)queries, m, shift, boxes ? 1 : 0, key.as<uint32_t>());
     PG_LAUNCH_CHECK();
     hipLaunchKernelGGL(bucket_count_kernel, dim3(cdiv(m, kNT)), dim3(kNT), 0, s,
                        key.as<uint32_t>(), m, cnt.as<uint32_t>());

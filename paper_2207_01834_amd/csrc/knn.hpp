@@ -228,9 +228,10 @@ constexpr int64_t kOrderMin = 4096;
 
 // A permutation of the m queries that follows the leaf order of tree tv (a
 // counting sort by the leaf each query's descent reaches); order receives
-// m int32 query indices.
+// m int32 query indices.  With `boxes` the queries are boxes [m][2][d]
+// (lo, hi) and each descends by its centre.
 pg_status order_queries(const TreeView& tv, bool fl, const void* queries, int64_t m,
-                        hipStream_t s, DevBuf& order);
+                        hipStream_t s, DevBuf& order, bool boxes = false);
 pg_status knn_static(const pg_tree* t, const void* queries, int64_t m, int k, bool all_points,
                      int32_t* out_idx, void* out_dist, hipStream_t s);
 

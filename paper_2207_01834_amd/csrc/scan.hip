@@ -1,4 +1,4 @@
-// Device-wide exclusive prefix sum of uint32 values (the parallel prefix sum
+// Device-wide exclusive prefix sums (the parallel prefix sum
 // the paper's construction and batch gathers rely on, Appendix C).
 // Three passes: per-workgroup totals, a scan of the totals by one workgroup,
 // then per-workgroup scans offset by their total's prefix.
@@ -13,74 +13,88 @@ constexpr int kNT = 256;
 constexpr int kItems = 16;
 constexpr int kTile = kNT * kItems;
 
+// IT: input type, AT: sum type.
+template <typename IT, typename AT>
 __global__ void __launch_bounds__(kNT)
-tile_sum_kernel(const uint32_t* __restrict__ in, int64_t n, uint32_t* __restrict__ sums) {
-    __shared__ uint32_t red[kNT / kWave];
+tile_sum_kernel(const IT* __restrict__ in, int64_t n, AT* __restrict__ sums) {
+    __shared__ AT red[kNT / kWave];
     const int64_t base = (int64_t)blockIdx.x * kTile;
-    uint32_t s = 0;
+    AT s = 0;
     for (int i = 0; i < kItems; i++) {
         const int64_t e = base + (int64_t)i * kNT + threadIdx.x;
-        if (e < n) s += in[e];
+        if (e < n) s += (AT)in[e];
     }
     s = wave_sum(s);
     if (lane_id() == 0) red[threadIdx.x / kWave] = s;
     __syncthreads();
     if (threadIdx.x == 0) {
-        uint32_t t = 0;
+        AT t = 0;
         for (int w = 0; w < kNT / kWave; w++) t += red[w];
         sums[blockIdx.x] = t;
     }
 }
 
+template <typename AT>
 __global__ void __launch_bounds__(kNT)
-scan_sums_kernel(uint32_t* __restrict__ sums, int64_t count, uint32_t* __restrict__ total) {
-    __shared__ uint32_t lds[kNT / kWave + 1];
-    uint32_t run = 0;
+scan_sums_kernel(AT* __restrict__ sums, int64_t count, AT* __restrict__ total) {
+    __shared__ AT lds[kNT / kWave + 1];
+    AT run = 0;
     for (int64_t b = 0; b < count; b += kNT) {
         const int64_t e = b + threadIdx.x;
-        const uint32_t v = e < count ? sums[e] : 0u;
-        uint32_t tot;
-        const uint32_t ex = block_excl_scan<kNT>(v, lds, &tot);
+        const AT v = e < count ? sums[e] : AT(0);
+        AT tot;
+        const AT ex = block_excl_scan<kNT>(v, lds, &tot);
         if (e < count) sums[e] = run + ex;
         run += tot;
     }
     if (threadIdx.x == 0 && total) *total = run;
 }
 
+template <typename IT, typename AT>
 __global__ void __launch_bounds__(kNT)
-tile_scan_kernel(const uint32_t* __restrict__ in, int64_t n, const uint32_t* __restrict__ sums,
-                 uint32_t* __restrict__ out) {
-    __shared__ uint32_t lds[kNT / kWave + 1];
+tile_scan_kernel(const IT* __restrict__ in, int64_t n, const AT* __restrict__ sums,
+                 AT* __restrict__ out) {
+    __shared__ AT lds[kNT / kWave + 1];
     const int64_t base = (int64_t)blockIdx.x * kTile;
-    uint32_t run = sums[blockIdx.x];
+    AT run = sums[blockIdx.x];
     for (int i = 0; i < kItems; i++) {
         const int64_t e = base + (int64_t)i * kNT + threadIdx.x;
-        const uint32_t v = e < n ? in[e] : 0u;
-        uint32_t tot;
-        const uint32_t ex = block_excl_scan<kNT>(v, lds, &tot);
+        const AT v = e < n ? (AT)in[e] : AT(0);
+        AT tot;
+        const AT ex = block_excl_scan<kNT>(v, lds, &tot);
         if (e < n) out[e] = run + ex;
         run += tot;
     }
+}
+
+template <typename IT, typename AT>
+pg_status exclusive_scan(const IT* in, AT* out, int64_t n, AT* total, hipStream_t s) {
+    if (n <= 0) return PG_OK;
+    const int64_t tiles = (n + kTile - 1) / kTile;
+    DevBuf sums(s);
+    PG_TRY(sums.alloc(sizeof(AT) * tiles));
+    hipLaunchKernelGGL((tile_sum_kernel<IT, AT>), dim3((unsigned)tiles), dim3(kNT), 0, s, in, n,
+                       sums.as<AT>());
+    PG_LAUNCH_CHECK();
+    hipLaunchKernelGGL((scan_sums_kernel<AT>), dim3(1), dim3(kNT), 0, s, sums.as<AT>(), tiles,
+                       total);
+    PG_LAUNCH_CHECK();
+    hipLaunchKernelGGL((tile_scan_kernel<IT, AT>), dim3((unsigned)tiles), dim3(kNT), 0, s, in, n,
+                       sums.as<AT>(), out);
+    PG_LAUNCH_CHECK();
+    return PG_OK;
 }
 
 }  // namespace
 
 pg_status exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total,
                              hipStream_t s) {
-    if (n <= 0) return PG_OK;
-    const int64_t tiles = (n + kTile - 1) / kTile;
-    DevBuf sums(s);
-    PG_TRY(sums.alloc(sizeof(uint32_t) * tiles));
-    hipLaunchKernelGGL(tile_sum_kernel, dim3((unsigned)tiles), dim3(kNT), 0, s, in, n,
-                       sums.as<uint32_t>());
-    PG_LAUNCH_CHECK();
-    hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(kNT), 0, s, sums.as<uint32_t>(), tiles,
-                       total);
-    PG_LAUNCH_CHECK();
-    hipLaunchKernelGGL(tile_scan_kernel, dim3((unsigned)tiles), dim3(kNT), 0, s, in, n,
-                       sums.as<uint32_t>(), out);
-    PG_LAUNCH_CHECK();
-    return PG_OK;
+    return exclusive_scan<uint32_t, uint32_t>(in, out, n, total, s);
+}
+
+pg_status exclusive_scan_i32_i64(const int32_t* in, int64_t* out, int64_t n, int64_t* total,
+                                 hipStream_t s) {
+    return exclusive_scan<int32_t, int64_t>(in, out, n, total, s);
 }
 
 }  // namespace pg

@@ -8,5 +8,8 @@ namespace pg {
 // in and out may alias.  n < 2^31.
 pg_status exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total,
                              hipStream_t s);
+// The same over int32 inputs with int64 sums (in and out do not alias).
+pg_status exclusive_scan_i32_i64(const int32_t* in, int64_t* out, int64_t n, int64_t* total,
+                                 hipStream_t s);
 
 }  // namespace pg

@@ -124,3 +124,24 @@ def choose_erase(live_points: np.ndarray, count: int, seed: int) -> np.ndarray:
     count = min(count, len(live_points))
     sel = g.choice(len(live_points), size=count, replace=False)
     return np.ascontiguousarray(live_points[np.sort(sel)])
+
+
+def range_boxes(points: np.ndarray, half, seed: int | None = None, m: int | None = None) -> np.ndarray:
+    """Closed query boxes [m][2][d] (lo, hi) centred on data points.
+
+    With ``seed`` None every point is a centre, in row order, and ``half`` is
+    the fixed half side (the all-points range workload: squares of side
+    2 half + 1 around each point of a uniform set).  Otherwise ``m`` centres are
+    drawn from the points and each box takes a half side per axis uniform in
+    [0, half] (test inputs of mixed sizes)."""
+    p = np.asarray(points)
+    if seed is None:
+        c = p.astype(np.float64)
+        h = np.full(c.shape, float(half))
+    else:
+        g = rng(seed)
+        c = p[g.integers(0, p.shape[0], m)].astype(np.float64)
+        h = g.uniform(0.0, float(half), c.shape)
+    if p.dtype == np.int32:
+        h = np.floor(h)
+    return np.ascontiguousarray(np.stack([c - h, c + h], axis=1).astype(p.dtype))
