@@ -461,11 +461,11 @@ pg_status build_tree(const void* points, int64_t n, int d, int leaf, int dtype, 
     const int64_t nleaves = (int64_t)1 << T->L;
     const int64_t nn = n > 0 ? n : 1;
     PG_TRY(dalloc(&T->pts, (size_t)d * nn, s));
-    PG_TRY(dalloc(&T->pidx, (size_t)nn, s));
+    PG_TRY(dalloc(&T->pidx, (size_t)nn + kTreePad, s));
     PG_TRY(dalloc(&T->split, (size_t)nleaves, s));
     PG_TRY(dalloc(&T->nbox, (size_t)nleaves * 2 * 2 * d, s));
     T->bbox = T->nbox + (size_t)nleaves * 2 * d;
-    PG_TRY(dalloc(&T->rec, (size_t)nn * record_words(d), s));
+    PG_TRY(dalloc(&T->rec, ((size_t)nn + kTreePad) * record_words(d), s));
     if (n == 0) return PG_OK;
     DevBuf tmpk(s), tmpi(s);
     PG_TRY(tmpk.alloc(sizeof(uint32_t) * (size_t)d * n));

@@ -96,6 +96,11 @@ __host__ inline int tree_levels(int64_t n, int leaf) {
 // padding to 4, 8 or 16 words (16, 32 or 64 bytes: whole 16-byte loads).
 __host__ __device__ inline int record_words(int d) { return d <= 3 ? 4 : (d <= 7 ? 8 : 16); }
 
+// Static trees allocate this many spare entries after the last leaf-order
+// record and row, so a loop that reads them in groups may overrun the last
+// group without leaving the allocation (the spare entries hold no data).
+constexpr int kTreePad = 4;
+
 // Device view of a static kd-tree (what the search kernels read).
 struct TreeView {
     int64_t n;

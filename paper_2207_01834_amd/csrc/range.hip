@@ -6,13 +6,15 @@
 // lo_c <= p_c <= hi_c in every dimension c (an empty box when lo_c > hi_c).
 // Coordinates are compared as values, so -0.0 and +0.0 are equal.
 //
-// Traversal: depth-first over the implicit heap without a stack.  A node
-// whose bounding box misses the query is skipped, a node whose box lies
+// Traversal: depth-first over the implicit heap without a stack.  For one
+// box: a node whose bounding box misses it is skipped, a node whose box lies
 // inside it reports its whole leaf-order range [floor(j n/2^l),
 // floor((j+1) n/2^l)) without touching its points, and a leaf that the box
 // cuts tests each of its points.  After a node is done the walk moves to the
 // right sibling of its lowest left-child ancestor-or-self, found in one step
-// by stripping the heap index's trailing one bits.
+// by stripping the heap index's trailing one bits.  The 64 boxes of a wave
+// (neighbours in the tree's leaf order) share one walk over the union of
+// the nodes they need.
 //
 // A query is run twice: a counting pass, then (after a prefix sum of the
 // counts) a pass that writes the input rows, in leaf order, from the query's
@@ -21,12 +23,16 @@
 #include "knn.hpp"
 #include "scan.hpp"
 #include "search.hpp"
+#include "wave.hpp"
 
 namespace pg {
 
 namespace {
 
 constexpr int kNT = 256;
+// Boxes are taken in the tree's leaf order from this many on, so that the
+// 64 boxes of a wave lie close together.
+constexpr int64_t kRangeOrderMin = 256;
 
 // Bounding box of heap node h (2d words: min[d], max[d]).
 template <typename T, int MD>
@@ -58,6 +64,42 @@ __device__ inline void load_node_box(const TreeView& tv, uint32_t h, int d, T (&
     }
 }
 
+// Leaf records and rows are read this many at a time.
+constexpr int kGroup = kTreePad;
+
+// A value that is the same in every lane, as a scalar (the builtin returns
+// a signed int: widen without sign extension).
+__device__ inline uint64_t scalar_u64(uint64_t w) {
+    const uint32_t whi = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(w >> 32));
+    const uint32_t wlo = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)w);
+    return ((uint64_t)whi << 32) | wlo;
+}
+
+// Lane masks of the wave: boxes that miss node box [bl, bh] (disjoint) and
+// boxes that contain it (and do not miss it: empty boxes only miss).
+template <typename T, int MD>
+__device__ inline void box_masks(const T (&bl)[MD], const T (&bh)[MD], const T (&lo)[MD],
+                                 const T (&hi)[MD], int d, uint64_t& miss, uint64_t& inside) {
+    miss = 0;
+    inside = ~0ull;
+#pragma unroll
+    for (int c = 0; c < MD; c++) {
+        if (MD < 8 || c < d) {
+            miss |= __ballot(bh[c] < lo[c]) | __ballot(bl[c] > hi[c]);
+            inside &= __ballot(lo[c] <= bl[c]) & __ballot(bh[c] <= hi[c]);
+        }
+    }
+    inside &= ~miss;
+}
+
+// One box per lane, one walk per wave.  The wave enters an internal node
+// when some lane's box cuts it (neither misses nor contains its bounding
+// box); entering a node tests both children against every lane's box: a
+// child inside a lane's box adds its whole leaf-order range to that lane, a
+// cut leaf has its points tested, a cut internal child is entered (the left
+// one first; the right sibling then waits, with the lanes that contain it,
+// on a small per-wave stack of lane masks, one entry per level).  The node index, the masks and every tree
+// load are the same across the wave: scalar loads and no divergence.
 // REPORT = false: counts[i] = number of points in box i.
 // REPORT = true:  rows of those points go to out_idx[offsets[i] ...]; a slot
 // at or beyond `capacity` is not written and raises *overflow.
@@ -67,79 +109,153 @@ range_kernel(TreeView tv, const uint32_t* __restrict__ boxes, const int32_t* __r
              int64_t m, int32_t* __restrict__ counts, const int64_t* __restrict__ offsets,
              int32_t* __restrict__ out_idx, int64_t capacity, uint32_t* __restrict__ overflow) {
     using M = Metric<T>;
+    // per wave, by level: lanes that cut / contain a right child not yet visited
+    __shared__ uint64_t pend[kNT / kWave][32][2];
     const int d = MD < 8 ? MD : tv.d;
     const int64_t i0 = xcd_block() * kNT + threadIdx.x;
-    if (i0 >= m) return;
-    const int64_t i = order ? (int64_t)order[i0] : i0;
+    const bool valid = i0 < m;
+    if (__ballot(valid) == 0) return;  // whole wave past the end
+    uint64_t(*stk)[2] = pend[threadIdx.x / kWave];
+    const uint64_t me = 1ull << lane_id();
+    const int64_t i = valid ? (order ? (int64_t)order[i0] : i0) : 0;
     T lo[MD], hi[MD];
 #pragma unroll
     for (int c = 0; c < MD; c++) {
-        lo[c] = (MD < 8 || c < d) ? M::load(boxes[i * 2 * d + c]) : T(0);
-        hi[c] = (MD < 8 || c < d) ? M::load(boxes[i * 2 * d + d + c]) : T(0);
+        lo[c] = (valid && (MD < 8 || c < d)) ? M::load(boxes[i * 2 * d + c]) : T(0);
+        hi[c] = (valid && (MD < 8 || c < d)) ? M::load(boxes[i * 2 * d + d + c]) : T(0);
     }
-    const int64_t base = REPORT ? offsets[i] : 0;
+    const int64_t base = (REPORT && valid) ? offsets[i] : 0;
     bool over = false;
     int64_t cnt = 0;
-    const uint32_t first_leaf = 1u << tv.L;
-    uint32_t h = 1;
-    int l = 0;
-    for (;;) {
-        T bl[MD], bh[MD];
-        load_node_box<T, MD>(tv, h, d, bl, bh);
-        bool miss = false, inside = true;
+
+    // every point of leaf-order range [s, e) is in the boxes of lanes `mask`
+    auto take_range = [&](int64_t s, int64_t e, uint64_t mask) {
+        if ((mask & me) == 0) return;
+        if (REPORT) {
+            for (int64_t p = s; p < e; p += kGroup) {  // the row array is padded
+                int32_t r[kGroup];
 #pragma unroll
-        for (int c = 0; c < MD; c++) {
-            if (MD < 8 || c < d) {
-                miss = miss || bh[c] < lo[c] || bl[c] > hi[c];
-                inside = inside && lo[c] <= bl[c] && bh[c] <= hi[c];
-            }
-        }
-        if (!miss && !inside && h < first_leaf) {
-            h = 2u * h;
-            l++;
-            continue;
-        }
-        if (!miss) {
-            const int64_t j = (int64_t)h - ((int64_t)1 << l);
-            const int64_t s = node_start(tv.n, l, j), e = node_start(tv.n, l, j + 1);
-            if (inside) {
-                if (REPORT) {
-                    for (int64_t p = s; p < e; p++) {
-                        const int64_t slot = base + cnt + (p - s);
-                        if (slot < capacity) out_idx[slot] = tv.pidx[p];
+                for (int t = 0; t < kGroup; t++) r[t] = tv.pidx[p + t];
+#pragma unroll
+                for (int t = 0; t < kGroup; t++) {
+                    const int64_t slot = base + cnt + (p - s) + t;
+                    if (p + t < e) {
+                        if (slot < capacity) out_idx[slot] = r[t];
                         else over = true;
                     }
                 }
-                cnt += e - s;
-            } else {
-                for (int64_t p = s; p < e; p++) {
-                    T pt[MD];
-                    uint32_t idw;
-                    load_point<T, MD>(tv, p, d, pt, idw);
-                    bool in = true;
+            }
+        }
+        cnt += e - s;
+    };
+    // test the points of leaf-order range [s, e) against the boxes of `mask`
+    auto scan_leaf = [&](int64_t s, int64_t e, uint64_t mask) {
+        const bool mine = (mask & me) != 0;
+        for (int64_t p = s; p < e; p += kGroup) {  // the records are padded
+            T pt[kGroup][MD];
+            uint32_t idw[kGroup];
 #pragma unroll
-                    for (int c = 0; c < MD; c++)
-                        if (MD < 8 || c < d) in = in && lo[c] <= pt[c] && pt[c] <= hi[c];
-                    if (in) {
-                        if (REPORT) {
-                            if (base + cnt < capacity) out_idx[base + cnt] = (int32_t)idw;
-                            else over = true;
-                        }
-                        cnt++;
+            for (int t = 0; t < kGroup; t++) load_point<T, MD>(tv, p + t, d, pt[t], idw[t]);
+#pragma unroll
+            for (int t = 0; t < kGroup; t++) {
+                bool in = mine & (p + t < e);
+#pragma unroll
+                for (int c = 0; c < MD; c++)
+                    if (MD < 8 || c < d) in = in & (lo[c] <= pt[t][c]) & (pt[t][c] <= hi[c]);
+                if (in) {
+                    if (REPORT) {
+                        if (base + cnt < capacity) out_idx[base + cnt] = (int32_t)idw[t];
+                        else over = true;
                     }
+                    cnt++;
                 }
             }
         }
-        // done with h: climb while h is a right child, then step to the
-        // right sibling (the rightmost path, all ones, ends the walk)
-        if (~h == 0u) break;
-        const int up = __builtin_ctz(~h);
-        h >>= up;
-        l -= up;
-        if (h == 0u) break;
-        h += 1u;
+    };
+
+    const uint64_t live = __ballot(valid);
+    uint64_t act;  // lanes whose box cuts the node the walk enters
+    {
+        T bl[MD], bh[MD];
+        load_node_box<T, MD>(tv, 1, d, bl, bh);
+        uint64_t miss, inside;
+        box_masks<T, MD>(bl, bh, lo, hi, d, miss, inside);
+        const uint64_t take = live & inside;
+        act = live & ~miss & ~inside;
+        if (take != 0) take_range(0, tv.n, take);
+        if (tv.L == 0) {
+            if (act != 0) scan_leaf(0, tv.n, act);
+            act = 0;
+        }
     }
-    if (!REPORT) counts[i] = (int32_t)cnt;
+    uint32_t h = 1;          // node entered (internal), level l
+    int l = 0;
+    uint32_t pending = 0;    // bit k: stk[k] holds the right child at level k+1
+    while (act != 0) {
+        T bl0[MD], bh0[MD], bl1[MD], bh1[MD];
+        load_node_box<T, MD>(tv, 2u * h, d, bl0, bh0);
+        load_node_box<T, MD>(tv, 2u * h + 1u, d, bl1, bh1);
+        uint64_t miss0, in0, miss1, in1;
+        box_masks<T, MD>(bl0, bh0, lo, hi, d, miss0, in0);
+        box_masks<T, MD>(bl1, bh1, lo, hi, d, miss1, in1);
+        const uint64_t take0 = act & in0, take1 = act & in1;
+        const uint64_t cut0 = act & ~miss0 & ~in0, cut1 = act & ~miss1 & ~in1;
+        // a lane's rows come out in leaf order: everything under the left
+        // child before anything under the right one
+        const int64_t j = 2 * ((int64_t)h - ((int64_t)1 << l));  // left child at level l+1
+        if (l + 1 == tv.L) {
+            if ((take0 | take1 | cut0 | cut1) != 0) {
+                const int64_t s0 = node_start(tv.n, l + 1, j), s1 = node_start(tv.n, l + 1, j + 1),
+                              s2 = node_start(tv.n, l + 1, j + 2);
+                if (take0 != 0) take_range(s0, s1, take0);
+                if (cut0 != 0) scan_leaf(s0, s1, cut0);
+                if (take1 != 0) take_range(s1, s2, take1);
+                if (cut1 != 0) scan_leaf(s1, s2, cut1);
+            }
+            act = 0;
+        } else {
+            if (take0 != 0)
+                take_range(node_start(tv.n, l + 1, j), node_start(tv.n, l + 1, j + 1), take0);
+            if (cut0 != 0) {
+                if ((cut1 | take1) != 0) {  // the right child waits (same value in every lane)
+                    stk[l][0] = cut1;
+                    stk[l][1] = take1;
+                    pending |= 1u << l;
+                }
+                h = 2u * h;
+                l++;
+                act = cut0;
+                continue;
+            }
+            if (take1 != 0)
+                take_range(node_start(tv.n, l + 1, j + 1), node_start(tv.n, l + 1, j + 2), take1);
+            if (cut1 != 0) {
+                h = 2u * h + 1u;
+                l++;
+                act = cut1;
+                continue;
+            }
+            act = 0;
+        }
+        // subtree done: the deepest waiting right child, its whole-range
+        // lanes first; entered when some lane's box cuts it
+        while (pending != 0) {
+            const int k = 31 - __builtin_clz(pending);
+            pending &= ~(1u << k);
+            h = 2u * (h >> (l - k)) + 1u;
+            l = k + 1;
+            const uint64_t ct = scalar_u64(stk[k][0]), tk = scalar_u64(stk[k][1]);
+            if (tk != 0) {
+                const int64_t jr = (int64_t)h - ((int64_t)1 << l);
+                take_range(node_start(tv.n, l, jr), node_start(tv.n, l, jr + 1), tk);
+            }
+            if (ct != 0) {
+                act = ct;
+                break;
+            }
+        }
+    }
+    if (valid && !REPORT) counts[i] = (int32_t)cnt;
     if (REPORT && over) atomicOr(overflow, 1u);
 }
 
@@ -177,7 +293,7 @@ pg_status range_pass(const pg_tree* t, const void* boxes, int64_t m, int32_t* co
                      uint32_t* overflow, hipStream_t s) {
     DevBuf order(s);
     const int32_t* o = nullptr;
-    if (m >= kOrderMin) {
+    if (m >= kRangeOrderMin) {
         PG_TRY(order_queries(t->view(), t->dtype == PG_FLOAT32, boxes, m, s, order, true));
         o = order.as<int32_t>();
     }
