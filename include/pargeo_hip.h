@@ -139,6 +139,21 @@ pg_status pg_range_count(const pg_tree* t, const void* boxes, int64_t m, int32_t
 pg_status pg_range_report(const pg_tree* t, const void* boxes, int64_t m, const int64_t* offsets,
                           int32_t* out_idx, int64_t capacity, void* stream);
 
+/* Both passes in one call (the boxes are checked and put in walking order
+ * once): counts, offsets and, when the total fits, the rows.
+ *   counts     : [m] int32 device, or NULL (a temporary is used)
+ *   offsets    : [m+1] int64 device (required): exclusive prefix sum of the
+ *                counts, offsets[m] = total
+ *   out_idx    : [capacity] int32 device; box i's rows at offsets[i] ...,
+ *                leaf order as in pg_range_report
+ *   total_host : (host, may be NULL) receives the total
+ * When the total exceeds `capacity`, returns PG_ERR_INVALID with counts,
+ * offsets and *total_host written and out_idx untouched; a caller can then
+ * size out_idx and call pg_range_report with these offsets.  Synchronises. */
+pg_status pg_range_search(const pg_tree* t, const void* boxes, int64_t m, int32_t* counts,
+                          int64_t* offsets, int32_t* out_idx, int64_t capacity,
+                          int64_t* total_host, void* stream);
+
 /* ---------------------------------------------------------------------- */
 /* BDL-tree (batch-dynamic kd-tree, Section 5; Appendix C)                 */
 /* ---------------------------------------------------------------------- */

@@ -48,6 +48,7 @@ SIGNATURES = {
     "pg_tree_free": (None, [vp]),
     "pg_range_count": (i32, [vp, vp, i64, vp, vp, P64, vp]),
     "pg_range_report": (i32, [vp, vp, i64, vp, vp, i64, vp]),
+    "pg_range_search": (i32, [vp, vp, i64, vp, vp, vp, i64, P64, vp]),
     "pg_bdl_create": (i32, [i32, i32, i32, i64, ctypes.POINTER(vp)]),
     "pg_bdl_insert": (i32, [vp, vp, i64, vp, P64]),
     "pg_bdl_erase": (i32, [vp, vp, i64, vp, P64]),
@@ -208,13 +209,31 @@ class KdTree:
                                     out.numel(), stream_ptr(b.device)))
         return out
 
-    def range_search(self, boxes: torch.Tensor):
+    def range_search(self, boxes: torch.Tensor, capacity: int = None):
         """Range search: (offsets int64 [m+1], rows int32 [total]); box i's
-        points are rows[offsets[i]:offsets[i+1]], in leaf order."""
-        counts, off, total = self.range_count(boxes, offsets=True)
-        out = torch.empty(max(total, 1), dtype=torch.int32, device=off.device)
-        self.range_report(boxes, off, out)
-        return off, out[:total]
+        points are rows[offsets[i]:offsets[i+1]], in leaf order.  One call
+        does both passes when the rows fit ``capacity`` (default: a guess
+        from earlier calls on this tree); otherwise the rows buffer is sized
+        from the counts and the reporting pass runs again."""
+        b = self._boxes(boxes)
+        m = b.shape[0]
+        if capacity is None:
+            per = getattr(self, "_range_per_box", 16.0)
+            capacity = int(per * 1.25 * m) + 1024
+        off = torch.empty(m + 1, dtype=torch.int64, device=b.device)
+        out = torch.empty(max(capacity, 1), dtype=torch.int32, device=b.device)
+        total = ctypes.c_int64()
+        st = lib().pg_range_search(self._h, ctypes.c_void_p(b.data_ptr()), m, None,
+                                   ctypes.c_void_p(off.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                   capacity, ctypes.byref(total), stream_ptr(b.device))
+        if m > 0:
+            self._range_per_box = max(total.value / m, 1.0)
+        if st != 0 and total.value > capacity:
+            out = torch.empty(max(total.value, 1), dtype=torch.int32, device=b.device)
+            self.range_report(b, off, out)
+        else:
+            check(st)
+        return off, out[:total.value]
 
     def export(self):
         """(split values of heap nodes 1..2^L-1, input rows in leaf order) as

@@ -127,6 +127,19 @@ pg_status pg_range_report(const pg_tree* t, const void* boxes, int64_t m, const 
     return range_report(t, boxes, m, offsets, out_idx, capacity, s);
 }
 
+pg_status pg_range_search(const pg_tree* t, const void* boxes, int64_t m, int32_t* counts,
+                          int64_t* offsets, int32_t* out_idx, int64_t capacity, int64_t* total_host,
+                          void* stream) {
+    if (!t) return fail(PG_ERR_INVALID, "pg_range_search: tree is NULL");
+    if (m < 0 || m >= ((int64_t)1 << 31)) return fail(PG_ERR_INVALID, "pg_range_search: m must be in [0, 2^31)");
+    if (capacity < 0) return fail(PG_ERR_INVALID, "pg_range_search: capacity < 0");
+    if (!offsets || (m > 0 && !boxes) || (capacity > 0 && !out_idx))
+        return fail(PG_ERR_INVALID, "pg_range_search: NULL pointer");
+    hipStream_t s = (hipStream_t)stream;
+    PG_TRY(check_queries(boxes, 2 * m, t->d, t->dtype == PG_FLOAT32, s));
+    return range_search(t, boxes, m, counts, offsets, out_idx, capacity, total_host, s);
+}
+
 pg_status pg_tree_info(const pg_tree* t, int64_t* n, int32_t* d, int32_t* leaf, int32_t* levels,
                        int32_t* dtype) {
     if (!t) return fail(PG_ERR_INVALID, "pg_tree_info: tree is NULL");

@@ -87,32 +87,44 @@ knn_redo_kernel(TreeView tv, const uint32_t* __restrict__ queries, int k, int al
     }
 }
 
-// Sort key of each query: the leaf its descent reaches (left below the
-// split, right at or above it), coarsened by `shift` bits.  A box query
-// (rows lo[d], hi[d]) descends by its centre.
-__global__ void query_leaf_kernel(TreeView tv, int fl, const uint32_t* __restrict__ queries,
-                                  int64_t m, int shift, int box, uint32_t* __restrict__ key) {
-    const int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x;
-    if (i >= m) return;
+// Sort key of each query: the node of level `levels` its descent reaches
+// (left below the split, right at or above it).  A box query (rows lo[d],
+// hi[d]) descends by its centre.  The splits of the top kTopLevels levels
+// are read from LDS (the deeper ones are gathers from the split array), and
+// a workgroup takes kLeafQpt * kNT queries to share that copy.
+constexpr int kTopLevels = 12;
+constexpr int kLeafQpt = 4;
+
+__global__ void __launch_bounds__(kNT)
+query_leaf_kernel(TreeView tv, int fl, const uint32_t* __restrict__ queries, int64_t m,
+                  int levels, int box, uint32_t* __restrict__ key) {
+    __shared__ uint32_t top[1 << kTopLevels];
+    const int tl = levels < kTopLevels ? levels : kTopLevels;
+    for (int e = threadIdx.x; e < (1 << tl); e += kNT) top[e] = e ? tv.split[e] : 0u;
+    __syncthreads();
     const int d = tv.d;
-    const int64_t row = box ? i * 2 * d : i * d;
-    const uint32_t first_leaf = 1u << tv.L;
-    uint32_t cur = 1;
-    int dim = 0;
-    while (cur < first_leaf) {
-        const uint32_t qb = queries[row + dim], sb = tv.split[cur];
-        bool right;
-        if (box) {
-            const uint32_t hb = queries[row + d + dim];
-            right = fl ? 0.5f * __uint_as_float(qb) + 0.5f * __uint_as_float(hb) >= __uint_as_float(sb)
-                       : (int64_t)(int32_t)qb + (int32_t)hb >= 2 * (int64_t)(int32_t)sb;
-        } else {
-            right = fl ? __uint_as_float(qb) >= __uint_as_float(sb) : (int32_t)qb >= (int32_t)sb;
+    for (int r = 0; r < kLeafQpt; r++) {
+        const int64_t i = ((int64_t)blockIdx.x * kLeafQpt + r) * kNT + threadIdx.x;
+        if (i >= m) return;
+        const int64_t row = box ? i * 2 * d : i * d;
+        uint32_t cur = 1;
+        int dim = 0;
+        for (int lvl = 0; lvl < levels; lvl++) {
+            const uint32_t qb = queries[row + dim];
+            const uint32_t sb = lvl < tl ? top[cur] : tv.split[cur];
+            bool right;
+            if (box) {
+                const uint32_t hb = queries[row + d + dim];
+                right = fl ? 0.5f * __uint_as_float(qb) + 0.5f * __uint_as_float(hb) >= __uint_as_float(sb)
+                           : (int64_t)(int32_t)qb + (int32_t)hb >= 2 * (int64_t)(int32_t)sb;
+            } else {
+                right = fl ? __uint_as_float(qb) >= __uint_as_float(sb) : (int32_t)qb >= (int32_t)sb;
+            }
+            cur = 2u * cur + (right ? 1u : 0u);
+            dim = dim + 1 == d ? 0 : dim + 1;
         }
-        cur = 2u * cur + (right ? 1u : 0u);
-        dim = dim + 1 == d ? 0 : dim + 1;
+        key[i] = cur - (1u << levels);
     }
-    key[i] = (cur - first_leaf) >> shift;
 }
 
 __global__ void bucket_count_kernel(const uint32_t* __restrict__ key, int64_t m,
@@ -230,8 +242,9 @@ pg_status order_queries(const TreeView& tv, bool fl, const void* queries, int64_
     PG_TRY(order.alloc(sizeof(int32_t) * m));
     PG_HIP(hipMemsetAsync(cnt.p, 0, sizeof(uint32_t) * nb, s));
     PG_HIP(hipMemsetAsync(cursor.p, 0, sizeof(uint32_t) * nb, s));
-    hipLaunchKernelGGL(query_leaf_kernel, dim3(cdiv(m, kNT)), dim3(kNT), 0, s, tv, fl ? 1 : 0,
-                       (const uint32_t*)queries, m, shift, boxes ? 1 : 0, key.as<uint32_t>());
+    hipLaunchKernelGGL(query_leaf_kernel, dim3(cdiv(m, (int64_t)kNT * kLeafQpt)), dim3(kNT), 0, s,
+                       tv, fl ? 1 : 0, (const uint32_t*)queries, m, tv.L - shift, boxes ? 1 : 0,
+                       key.as<uint32_t>());
     PG_LAUNCH_CHECK();
     hipLaunchKernelGGL(bucket_count_kernel, dim3(cdiv(m, kNT)), dim3(kNT), 0, s,
                        key.as<uint32_t>(), m, cnt.as<uint32_t>());

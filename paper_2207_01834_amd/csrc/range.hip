@@ -288,45 +288,73 @@ pg_status dispatch_range(const pg_tree* t, const void* boxes, const int32_t* ord
     }
 }
 
-pg_status range_pass(const pg_tree* t, const void* boxes, int64_t m, int32_t* counts,
-                     const int64_t* offsets, int32_t* out_idx, int64_t capacity,
-                     uint32_t* overflow, hipStream_t s) {
-    DevBuf order(s);
-    const int32_t* o = nullptr;
+// The order in which the boxes are walked (the tree's leaf order of their
+// centres), or none for few boxes.
+pg_status range_order(const pg_tree* t, const void* boxes, int64_t m, hipStream_t s,
+                      DevBuf& order, const int32_t** o) {
+    *o = nullptr;
     if (m >= kRangeOrderMin) {
         PG_TRY(order_queries(t->view(), t->dtype == PG_FLOAT32, boxes, m, s, order, true));
-        o = order.as<int32_t>();
+        *o = order.as<int32_t>();
     }
+    return PG_OK;
+}
+
+pg_status range_pass(const pg_tree* t, const void* boxes, const int32_t* o, int64_t m,
+                     int32_t* counts, const int64_t* offsets, int32_t* out_idx, int64_t capacity,
+                     uint32_t* overflow, hipStream_t s) {
     if (t->dtype == PG_FLOAT32)
         return dispatch_range<float>(t, boxes, o, m, counts, offsets, out_idx, capacity, overflow, s);
     return dispatch_range<int32_t>(t, boxes, o, m, counts, offsets, out_idx, capacity, overflow, s);
+}
+
+// Counting pass into counts (caller's), the prefix sum into offsets when
+// given.
+pg_status count_pass(const pg_tree* t, const void* boxes, const int32_t* o, int64_t m,
+                     int32_t* counts, int64_t* offsets, hipStream_t s) {
+    if (m > 0) {
+        if (t->n == 0) PG_HIP(hipMemsetAsync(counts, 0, sizeof(int32_t) * m, s));
+        else PG_TRY(range_pass(t, boxes, o, m, counts, nullptr, nullptr, 0, nullptr, s));
+    }
+    if (offsets) {
+        if (m > 0) PG_TRY(exclusive_scan_i32_i64(counts, offsets, m, offsets + m, s));
+        else PG_HIP(hipMemsetAsync(offsets, 0, sizeof(int64_t), s));
+    }
+    return PG_OK;
+}
+
+// Reporting pass; PG_ERR_INVALID when a slot at or beyond capacity was
+// needed.  Synchronises.
+pg_status report_pass(const pg_tree* t, const void* boxes, const int32_t* o, int64_t m,
+                      const int64_t* offsets, int32_t* out_idx, int64_t capacity, hipStream_t s) {
+    if (m == 0 || t->n == 0) return PG_OK;
+    DevBuf flag(s);
+    PG_TRY(flag.alloc(sizeof(uint32_t)));
+    PG_HIP(hipMemsetAsync(flag.p, 0, sizeof(uint32_t), s));
+    PG_TRY(range_pass(t, boxes, o, m, nullptr, offsets, out_idx, capacity, flag.as<uint32_t>(), s));
+    uint32_t h = 0;
+    PG_HIP(hipMemcpyAsync(&h, flag.p, sizeof(h), hipMemcpyDeviceToHost, s));
+    PG_HIP(hipStreamSynchronize(s));
+    if (h) return fail(PG_ERR_INVALID, "range report: a result slot lies at or beyond `capacity` (offsets do not match the counts)");
+    return PG_OK;
 }
 
 }  // namespace
 
 pg_status range_count(const pg_tree* t, const void* boxes, int64_t m, int32_t* counts,
                       int64_t* offsets, int64_t* total_host, hipStream_t s) {
-    if (m > 0) {
-        if (t->n == 0) PG_HIP(hipMemsetAsync(counts, 0, sizeof(int32_t) * m, s));
-        else PG_TRY(range_pass(t, boxes, m, counts, nullptr, nullptr, 0, nullptr, s));
+    DevBuf order(s), tmp(s);
+    const int32_t* o = nullptr;
+    if (t->n > 0) PG_TRY(range_order(t, boxes, m, s, order, &o));
+    int64_t* off = offsets;
+    if (!off && total_host) {
+        PG_TRY(tmp.alloc(sizeof(int64_t) * (m + 1)));
+        off = tmp.as<int64_t>();
     }
-    if (offsets) {
-        if (m > 0) PG_TRY(exclusive_scan_i32_i64(counts, offsets, m, offsets + m, s));
-        else PG_HIP(hipMemsetAsync(offsets, 0, sizeof(int64_t), s));
-    }
+    PG_TRY(count_pass(t, boxes, o, m, counts, off, s));
     if (total_host) {
-        *total_host = 0;
-        if (offsets) {
-            PG_HIP(hipMemcpyAsync(total_host, offsets + m, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-            PG_HIP(hipStreamSynchronize(s));
-        } else if (m > 0) {
-            DevBuf tmp(s);
-            PG_TRY(tmp.alloc(sizeof(int64_t) * (m + 1)));
-            PG_TRY(exclusive_scan_i32_i64(counts, tmp.as<int64_t>(), m, tmp.as<int64_t>() + m, s));
-            PG_HIP(hipMemcpyAsync(total_host, tmp.as<int64_t>() + m, sizeof(int64_t),
-                                  hipMemcpyDeviceToHost, s));
-            PG_HIP(hipStreamSynchronize(s));
-        }
+        PG_HIP(hipMemcpyAsync(total_host, off + m, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        PG_HIP(hipStreamSynchronize(s));
     }
     return PG_OK;
 }
@@ -334,15 +362,32 @@ pg_status range_count(const pg_tree* t, const void* boxes, int64_t m, int32_t* c
 pg_status range_report(const pg_tree* t, const void* boxes, int64_t m, const int64_t* offsets,
                        int32_t* out_idx, int64_t capacity, hipStream_t s) {
     if (m == 0 || t->n == 0) return PG_OK;
-    DevBuf flag(s);
-    PG_TRY(flag.alloc(sizeof(uint32_t)));
-    PG_HIP(hipMemsetAsync(flag.p, 0, sizeof(uint32_t), s));
-    PG_TRY(range_pass(t, boxes, m, nullptr, offsets, out_idx, capacity, flag.as<uint32_t>(), s));
-    uint32_t h = 0;
-    PG_HIP(hipMemcpyAsync(&h, flag.p, sizeof(h), hipMemcpyDeviceToHost, s));
+    DevBuf order(s);
+    const int32_t* o = nullptr;
+    PG_TRY(range_order(t, boxes, m, s, order, &o));
+    return report_pass(t, boxes, o, m, offsets, out_idx, capacity, s);
+}
+
+pg_status range_search(const pg_tree* t, const void* boxes, int64_t m, int32_t* counts,
+                       int64_t* offsets, int32_t* out_idx, int64_t capacity, int64_t* total_host,
+                       hipStream_t s) {
+    DevBuf order(s), cbuf(s);
+    const int32_t* o = nullptr;
+    if (t->n > 0) PG_TRY(range_order(t, boxes, m, s, order, &o));
+    if (!counts) {
+        PG_TRY(cbuf.alloc(sizeof(int32_t) * (m > 0 ? m : 1)));
+        counts = cbuf.as<int32_t>();
+    }
+    PG_TRY(count_pass(t, boxes, o, m, counts, offsets, s));
+    int64_t total = 0;
+    PG_HIP(hipMemcpyAsync(&total, offsets + m, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     PG_HIP(hipStreamSynchronize(s));
-    if (h) return fail(PG_ERR_INVALID, "pg_range_report: a result slot lies at or beyond `capacity` (offsets do not match the counts)");
-    return PG_OK;
+    if (total_host) *total_host = total;
+    if (total > capacity)
+        return fail(PG_ERR_INVALID, "pg_range_search: " + std::to_string(total) +
+                                        " results exceed capacity " + std::to_string(capacity) +
+                                        " (counts, offsets and the total are written)");
+    return report_pass(t, boxes, o, m, offsets, out_idx, capacity, s);
 }
 
 }  // namespace pg

@@ -1,5 +1,5 @@
-"""GPU parity of the orthogonal range search (pg_range_count /
-pg_range_report through the C ABI) against the CPU oracle's definition:
+"""GPU parity of the orthogonal range search (pg_range_count,
+pg_range_report and pg_range_search through the C ABI) against the CPU oracle's definition:
 counts and reported rows bit-exact (no arithmetic, only comparisons, so
 float32 is exact too), rows in the tree's leaf order, edge cases, the
 overflow guard and full-size sampled boxes."""
@@ -168,3 +168,23 @@ def test_full_size_2d_sampled(pg, dev):
     p = pts[r_host[:lim]]
     lo, hi = boxes[owner, 0], boxes[owner, 1]
     assert np.all((p >= lo) & (p <= hi))
+
+
+def test_search_capacity_fallback(pg, dev):
+    """pg_range_search: a capacity below the total writes counts and offsets
+    and leaves the rows to the reporting pass (the binding's fallback); an
+    exact capacity does both passes in one call."""
+    import torch
+    pts = datagen.uniform_int(8_000, 3, seed=21, bits=10)
+    t = pg.kdtree_build(to_dev(pts, dev), leaf=8)
+    boxes = datagen.range_boxes(pts, 90, seed=22, m=3_000)
+    B = to_dev(boxes, dev)
+    oc, oo, oi = oracle.range_brute(pts, boxes)
+    total = int(oo[-1])
+    for cap in (0, 5, total - 1, total, total + 100):
+        off, rows = t.range_search(B, capacity=cap)
+        torch.cuda.synchronize()
+        off, rows = off.cpu().numpy(), rows.cpu().numpy()
+        assert np.array_equal(off, oo) and rows.shape[0] == total
+        for i in range(0, 3_000, 37):
+            assert np.array_equal(np.sort(rows[off[i]:off[i + 1]].astype(np.int64)), oi[oo[i]:oo[i + 1]])
