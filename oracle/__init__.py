@@ -13,6 +13,8 @@ Parts (each function cites the passage it follows):
                       (Algorithms 3 and 4), in Python;
   * ``grad``       -- the closed-form FP64 gradient of summed k-NN squared
                       distances and central finite differences, in NumPy;
+  * ``knn_graph_brute`` -- the k-NN graph (each point's k nearest other
+                      points) from the k-NN definition;
   * ``range_brute`` / ``KdTree.range`` -- the orthogonal range query written
                       out, and on the tree (C, ``or_range_brute`` /
                       ``or_kd_range``).
@@ -102,6 +104,25 @@ def knn_brute(points, queries, k, ids=None, alive=None, nthreads=1):
     if rc != 0:
         raise ValueError("or_knn_brute: bad arguments")
     return out_id, out_d
+
+
+def knn_graph_brute(points, k, nthreads=1):
+    """The k-NN graph (Section 2, third module: graphs generated from the
+    kd-tree's k-NN search), written out: row i holds the k smallest
+    (D(p_i, p_j), j) keys over the points j != i, ascending; missing slots
+    hold id -1 and distance INT64_MAX / +inf.  Built from the definition's
+    k+1 nearest of every point with row i's own entry removed (when more
+    than k identical points precede it, its own entry is not among them and
+    the first k are kept)."""
+    points = np.ascontiguousarray(points)
+    n = points.shape[0]
+    ids, dist = knn_brute(points, points, k + 1, nthreads=nthreads)
+    own = ids == np.arange(n, dtype=np.int64)[:, None]
+    keep = ~own
+    keep[own.sum(axis=1) == 0, k] = False  # self not listed: drop the (k+1)-th
+    out_i = ids[keep].reshape(n, k)
+    out_d = dist[keep].reshape(n, k)
+    return out_i, out_d
 
 
 def _offsets(counts):

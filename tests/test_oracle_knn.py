@@ -155,3 +155,37 @@ def test_all_identical_points():
     ids, dist, _ = t.knn(p[:10], 7)
     assert (dist == 0).all()
     assert np.array_equal(ids, np.tile(np.arange(7), (10, 1)))
+
+
+def _graph_loops(pts, k):
+    # pure-Python definition on tiny inputs: sort the other points by (D, j)
+    n = len(pts)
+    rows_i, rows_d = [], []
+    for i in range(n):
+        keys = sorted((int(((pts[i].astype(np.int64) - pts[j]) ** 2).sum()), j)
+                      for j in range(n) if j != i)[:k]
+        keys += [(INT64_MAX, -1)] * (k - len(keys))
+        rows_i.append([j for _, j in keys])
+        rows_d.append([dd for dd, _ in keys])
+    return np.array(rows_i), np.array(rows_d)
+
+
+@pytest.mark.parametrize("n,k,span", [(1, 3, 5), (2, 3, 5), (7, 3, 2), (40, 5, 3), (60, 4, 100)])
+def test_knn_graph_excludes_only_self(n, k, span):
+    # small coordinate spans force many identical points: an identical point
+    # is a neighbour at distance 0, the point itself never is
+    rng = np.random.default_rng(n * 31 + k)
+    pts = rng.integers(0, span, (n, 2)).astype(np.int32)
+    gi, gd = oracle.knn_graph_brute(pts, k)
+    wi, wd = _graph_loops(pts, k)
+    assert gi.tolist() == wi.tolist() and gd.tolist() == wd.tolist()
+    assert not np.any(gi == np.arange(n)[:, None])
+
+
+def test_knn_graph_many_duplicates_drop_last():
+    # 12 identical points, k = 10: for row 11 the k+1 nearest (ids 0..10)
+    # do not include itself; the graph row is ids 0..9
+    pts = np.zeros((12, 3), dtype=np.int32)
+    gi, gd = oracle.knn_graph_brute(pts, 10)
+    assert gi[11].tolist() == list(range(10)) and gd[11].tolist() == [0] * 10
+    assert gi[0].tolist() == list(range(1, 11))
