@@ -184,6 +184,19 @@ def form_static_float(torch, pg, datagen, dev):
             "build_mpts_s": N / (build_ms * 1e-3) / 1e6}
 
 
+def form_graph(torch, pg, datagen, dev):
+    """k-NN graph on the headline points (3-D 10M int uniform, k = 10, leaf
+    16): each point's 10 nearest other points, from a built tree."""
+    pts = datagen.uniform_int(N, D, seed=2)
+    x = torch.from_numpy(pts).to(dev)
+    t = pg.kdtree_build(x, leaf=LEAF)
+    idx = torch.empty((N, K), dtype=torch.int32, device=dev)
+    dist = torch.empty((N, K), dtype=torch.int64, device=dev)
+    graph_ms = timed(torch, lambda: t.knn_graph(K, out=(idx, dist)))
+    return {"workload": "k-NN graph, 3-D n=10M int32 uniform, k=10 other points per point, leaf 16",
+            "graph_ms": graph_ms, "edges_per_s": N * K / (graph_ms * 1e-3)}
+
+
 def form_clustered(torch, pg, datagen, dev):
     """5-D clustered float32 (1,000 Gaussian clusters, Zipf sizes), 1M queries
     from the same mixture, k = 5."""
@@ -347,7 +360,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms", default="all",
                     help="other forms to measure after the headline step: all, none, or a "
-                         "comma list of static_float,clustered,bdl,batch,range")
+                         "comma list of static_float,clustered,bdl,batch,range,graph")
     ap.add_argument("--bdl-rounds", type=int, default=10)
     ap.add_argument("--loop-clouds", type=int, default=512,
                     help="clouds timed for the per-cloud comparison (projected to 4,096)")
@@ -459,7 +472,7 @@ def main():
     }
     del idx, dist, x
     torch.cuda.empty_cache()
-    forms = ["static_float", "clustered", "bdl", "batch", "range"] if args.forms == "all" else \
+    forms = ["static_float", "clustered", "bdl", "batch", "range", "graph"] if args.forms == "all" else \
         [f for f in args.forms.split(",") if f and f != "none"]
     out = {}
     for f in forms:
@@ -472,6 +485,8 @@ def main():
             out[f] = form_bdl(torch, pg, datagen, dev, args.bdl_rounds)
         elif f == "batch":
             out[f] = form_batch(torch, pg, datagen, dev, args.loop_clouds)
+        elif f == "graph":
+            out[f] = form_graph(torch, pg, datagen, dev)
         elif f == "range":
             out[f] = form_range(torch, pg, datagen, dev, not args.no_cpu_baseline)
         else:

@@ -92,6 +92,15 @@ pg_status pg_knn(const pg_tree* t, const void* queries, int64_t m, int32_t k,
 pg_status pg_knn_all(const pg_tree* t, int32_t k, int32_t* out_idx, void* out_dist,
                      void* stream);
 
+/* k-NN graph (the graph generator of Section 2's third module, built on the
+ * tree's k-NN search): row i holds the k points nearest to input row i
+ * other than row i itself, in the pg_knn_all layout and order (an
+ * identical point is a neighbour at distance 0).  When fewer than k other
+ * points exist the remaining slots are padded.  Rows are directed edges
+ * i -> out_idx[i][r].  Does not synchronise. */
+pg_status pg_knn_graph(const pg_tree* t, int32_t k, int32_t* out_idx, void* out_dist,
+                       void* stream);
+
 /* Tree facts (host outputs; any may be NULL). */
 pg_status pg_tree_info(const pg_tree* t, int64_t* n, int32_t* d, int32_t* leaf,
                        int32_t* levels, int32_t* dtype);

@@ -43,6 +43,7 @@ SIGNATURES = {
     "pg_kdtree_build": (i32, [vp, i64, i32, i32, i32, vp, ctypes.POINTER(vp)]),
     "pg_knn": (i32, [vp, vp, i64, i32, vp, vp, vp]),
     "pg_knn_all": (i32, [vp, i32, vp, vp, vp]),
+    "pg_knn_graph": (i32, [vp, i32, vp, vp, vp]),
     "pg_tree_info": (i32, [vp, P64, P32, P32, P32, P32]),
     "pg_tree_export": (i32, [vp, vp, vp, vp]),
     "pg_tree_free": (None, [vp]),
@@ -165,6 +166,18 @@ class KdTree:
             idx, dist = out
         check(lib().pg_knn_all(self._h, k, ctypes.c_void_p(idx.data_ptr()),
                                ctypes.c_void_p(dist.data_ptr()), stream_ptr(self.device)))
+        return idx, dist
+
+    def knn_graph(self, k: int, out=None):
+        """k-NN graph: row i holds the k nearest points other than input
+        row i itself (directed edges i -> idx[i][r]), as (idx, dist)."""
+        if out is None:
+            idx = torch.empty((self.n, k), dtype=torch.int32, device=self.device)
+            dist = torch.empty((self.n, k), dtype=_dist_dtype(self.dtype_code), device=self.device)
+        else:
+            idx, dist = out
+        check(lib().pg_knn_graph(self._h, k, ctypes.c_void_p(idx.data_ptr()),
+                                 ctypes.c_void_p(dist.data_ptr()), stream_ptr(self.device)))
         return idx, dist
 
     def _boxes(self, boxes):

@@ -140,6 +140,13 @@ pg_status pg_range_search(const pg_tree* t, const void* boxes, int64_t m, int32_
     return range_search(t, boxes, m, counts, offsets, out_idx, capacity, total_host, s);
 }
 
+pg_status pg_knn_graph(const pg_tree* t, int32_t k, int32_t* out_idx, void* out_dist, void* stream) {
+    if (!t) return fail(PG_ERR_INVALID, "pg_knn_graph: tree is NULL");
+    if (k < 1 || k > 64) return fail(PG_ERR_INVALID, "pg_knn_graph: k must be in [1, 64]");
+    if (t->n > 0 && (!out_idx || !out_dist)) return fail(PG_ERR_INVALID, "pg_knn_graph: NULL pointer");
+    return knn_static(t, nullptr, t->n, k, true, out_idx, out_dist, (hipStream_t)stream, true);
+}
+
 pg_status pg_tree_info(const pg_tree* t, int64_t* n, int32_t* d, int32_t* leaf, int32_t* levels,
                        int32_t* dtype) {
     if (!t) return fail(PG_ERR_INVALID, "pg_tree_info: tree is NULL");

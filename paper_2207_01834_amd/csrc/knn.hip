@@ -26,7 +26,8 @@ __device__ inline void load_query(const TreeView& tv, const uint32_t* queries, i
 // Searches with packed (distance, id) keys.  A query whose k-th distance
 // reached the packed range's limit (int32 coordinates: 2^(64-B) - 1, or fewer
 // than k points) is appended to `redo` for knn_redo_kernel instead of written.
-template <typename T, int MD, int KT, bool EX>
+// NS (all-points only): the query's own point is not a candidate (k-NN graph).
+template <typename T, int MD, int KT, bool EX, bool NS>
 __global__ void __launch_bounds__(kNT)
 knn_static_kernel(TreeView tv, const uint32_t* __restrict__ queries,
                   const int32_t* __restrict__ order, int64_t m, int k, int all, int idbits,
@@ -43,7 +44,8 @@ knn_static_kernel(TreeView tv, const uint32_t* __restrict__ queries,
     PackedList<T, KT, EX> kl;
     kl.init(idbits);
     const uint32_t start = all ? (1u << tv.L) + leaf_of(tv.n, tv.L, i) : 0u;
-    kd_search<T, MD>(tv, PlainIds{}, q, d, kl, k, start);
+    if constexpr (NS) kd_search<T, MD>(tv, OtherIds{i}, q, d, kl, k, start);
+    else kd_search<T, MD>(tv, PlainIds{}, q, d, kl, k, start);
     if (kl.needs_redo()) {
         redo[atomicAdd(nredo, 1u)] = (int32_t)i;
         return;
@@ -60,7 +62,7 @@ knn_static_kernel(TreeView tv, const uint32_t* __restrict__ queries,
 
 // The queries knn_static_kernel handed over, searched with exact
 // (distance, id) pairs.
-template <typename T, int MD, int KT, bool EX>
+template <typename T, int MD, int KT, bool EX, bool NS>
 __global__ void __launch_bounds__(kNT)
 knn_redo_kernel(TreeView tv, const uint32_t* __restrict__ queries, int k, int all,
                 const int32_t* __restrict__ redo, const uint32_t* __restrict__ nredo,
@@ -75,7 +77,8 @@ knn_redo_kernel(TreeView tv, const uint32_t* __restrict__ queries, int k, int al
         KList<typename M::D, int32_t, KT, EX> kl;
         kl.init(M::inf(), INT32_MAX);
         const uint32_t start = all ? (1u << tv.L) + leaf_of(tv.n, tv.L, i) : 0u;
-        kd_search<T, MD>(tv, PlainIds{}, q, d, kl, k, start);
+        if constexpr (NS) kd_search<T, MD>(tv, OtherIds{i}, q, d, kl, k, start);
+        else kd_search<T, MD>(tv, PlainIds{}, q, d, kl, k, start);
         const int64_t row = all ? (int64_t)tv.pidx[i] : i;
 #pragma unroll
         for (int s = 0; s < KT; s++) {
@@ -157,7 +160,7 @@ __global__ void check_queries_kernel(const uint32_t* __restrict__ q, int64_t cou
 
 constexpr unsigned kRedoBlocks = 512;
 
-template <typename T, int MD, int KT, bool EX>
+template <typename T, int MD, int KT, bool EX, bool NS>
 pg_status launch_static(const pg_tree* t, const void* queries, const int32_t* order, int64_t m,
                         int k, bool all, int32_t* out_idx, void* out_dist, hipStream_t s) {
     using DT = typename Metric<T>::D;
@@ -168,13 +171,13 @@ pg_status launch_static(const pg_tree* t, const void* queries, const int32_t* or
         PG_TRY(nredo.alloc(sizeof(uint32_t)));
         PG_HIP(hipMemsetAsync(nredo.p, 0, sizeof(uint32_t), s));
     }
-    hipLaunchKernelGGL((knn_static_kernel<T, MD, KT, EX>), dim3(grid_for_xcd(cdiv(m, kNT))),
+    hipLaunchKernelGGL((knn_static_kernel<T, MD, KT, EX, NS>), dim3(grid_for_xcd(cdiv(m, kNT))),
                        dim3(kNT), 0, s, t->view(), (const uint32_t*)queries, order, m, k,
                        all ? 1 : 0, id_bits(t->n), out_idx, (DT*)out_dist, redo.as<int32_t>(),
                        nredo.as<uint32_t>());
     PG_LAUNCH_CHECK();
     if (!exact) {
-        hipLaunchKernelGGL((knn_redo_kernel<T, MD, KT, EX>), dim3(kRedoBlocks), dim3(kNT), 0, s,
+        hipLaunchKernelGGL((knn_redo_kernel<T, MD, KT, EX, NS>), dim3(kRedoBlocks), dim3(kNT), 0, s,
                            t->view(), (const uint32_t*)queries, k, all ? 1 : 0,
                            redo.as<int32_t>(), nredo.as<uint32_t>(), out_idx, (DT*)out_dist);
         PG_LAUNCH_CHECK();
@@ -184,28 +187,28 @@ pg_status launch_static(const pg_tree* t, const void* queries, const int32_t* or
 
 // k-list capacities: exact lists for the common k = 5, 10, 16, otherwise the
 // next power of two with uniform guards.
-template <typename T, int MD>
+template <typename T, int MD, bool NS>
 pg_status dispatch_k(const pg_tree* t, const void* q, const int32_t* o, int64_t m, int k, bool all,
                      int32_t* oi, void* od, hipStream_t s) {
-    if (k == 5) return launch_static<T, MD, 5, true>(t, q, o, m, k, all, oi, od, s);
-    if (k == 10) return launch_static<T, MD, 10, true>(t, q, o, m, k, all, oi, od, s);
-    if (k == 16) return launch_static<T, MD, 16, true>(t, q, o, m, k, all, oi, od, s);
-    if (k <= 2) return launch_static<T, MD, 2, false>(t, q, o, m, k, all, oi, od, s);
-    if (k <= 4) return launch_static<T, MD, 4, false>(t, q, o, m, k, all, oi, od, s);
-    if (k <= 8) return launch_static<T, MD, 8, false>(t, q, o, m, k, all, oi, od, s);
-    if (k <= 16) return launch_static<T, MD, 16, false>(t, q, o, m, k, all, oi, od, s);
-    if (k <= 32) return launch_static<T, MD, 32, false>(t, q, o, m, k, all, oi, od, s);
-    return launch_static<T, MD, 64, false>(t, q, o, m, k, all, oi, od, s);
+    if (k == 5) return launch_static<T, MD, 5, true, NS>(t, q, o, m, k, all, oi, od, s);
+    if (k == 10) return launch_static<T, MD, 10, true, NS>(t, q, o, m, k, all, oi, od, s);
+    if (k == 16) return launch_static<T, MD, 16, true, NS>(t, q, o, m, k, all, oi, od, s);
+    if (k <= 2) return launch_static<T, MD, 2, false, NS>(t, q, o, m, k, all, oi, od, s);
+    if (k <= 4) return launch_static<T, MD, 4, false, NS>(t, q, o, m, k, all, oi, od, s);
+    if (k <= 8) return launch_static<T, MD, 8, false, NS>(t, q, o, m, k, all, oi, od, s);
+    if (k <= 16) return launch_static<T, MD, 16, false, NS>(t, q, o, m, k, all, oi, od, s);
+    if (k <= 32) return launch_static<T, MD, 32, false, NS>(t, q, o, m, k, all, oi, od, s);
+    return launch_static<T, MD, 64, false, NS>(t, q, o, m, k, all, oi, od, s);
 }
 
-template <typename T>
+template <typename T, bool NS>
 pg_status dispatch_d(const pg_tree* t, const void* q, const int32_t* o, int64_t m, int k, bool all,
                      int32_t* oi, void* od, hipStream_t s) {
     switch (t->d) {
-        case 2: return dispatch_k<T, 2>(t, q, o, m, k, all, oi, od, s);
-        case 3: return dispatch_k<T, 3>(t, q, o, m, k, all, oi, od, s);
-        case 5: return dispatch_k<T, 5>(t, q, o, m, k, all, oi, od, s);
-        default: return dispatch_k<T, 8>(t, q, o, m, k, all, oi, od, s);
+        case 2: return dispatch_k<T, 2, NS>(t, q, o, m, k, all, oi, od, s);
+        case 3: return dispatch_k<T, 3, NS>(t, q, o, m, k, all, oi, od, s);
+        case 5: return dispatch_k<T, 5, NS>(t, q, o, m, k, all, oi, od, s);
+        default: return dispatch_k<T, 8, NS>(t, q, o, m, k, all, oi, od, s);
     }
 }
 
@@ -258,7 +261,7 @@ pg_status order_queries(const TreeView& tv, bool fl, const void* queries, int64_
 }
 
 pg_status knn_static(const pg_tree* t, const void* queries, int64_t m, int k, bool all,
-                     int32_t* out_idx, void* out_dist, hipStream_t s) {
+                     int32_t* out_idx, void* out_dist, hipStream_t s, bool no_self) {
     if (m == 0) return PG_OK;
     DevBuf order(s);
     const int32_t* o = nullptr;
@@ -266,8 +269,14 @@ pg_status knn_static(const pg_tree* t, const void* queries, int64_t m, int k, bo
         PG_TRY(order_queries(t->view(), t->dtype == PG_FLOAT32, queries, m, s, order));
         o = order.as<int32_t>();
     }
-    if (t->dtype == PG_FLOAT32) return dispatch_d<float>(t, queries, o, m, k, all, out_idx, out_dist, s);
-    return dispatch_d<int32_t>(t, queries, o, m, k, all, out_idx, out_dist, s);
+    if (no_self) {
+        if (t->dtype == PG_FLOAT32)
+            return dispatch_d<float, true>(t, nullptr, nullptr, m, k, true, out_idx, out_dist, s);
+        return dispatch_d<int32_t, true>(t, nullptr, nullptr, m, k, true, out_idx, out_dist, s);
+    }
+    if (t->dtype == PG_FLOAT32)
+        return dispatch_d<float, false>(t, queries, o, m, k, all, out_idx, out_dist, s);
+    return dispatch_d<int32_t, false>(t, queries, o, m, k, all, out_idx, out_dist, s);
 }
 
 }  // namespace pg

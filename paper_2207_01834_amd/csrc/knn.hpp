@@ -232,8 +232,9 @@ constexpr int64_t kOrderMin = 4096;
 // (lo, hi) and each descends by its centre.
 pg_status order_queries(const TreeView& tv, bool fl, const void* queries, int64_t m,
                         hipStream_t s, DevBuf& order, bool boxes = false);
+// no_self (all-points only): each point's own row is not a candidate.
 pg_status knn_static(const pg_tree* t, const void* queries, int64_t m, int k, bool all_points,
-                     int32_t* out_idx, void* out_dist, hipStream_t s);
+                     int32_t* out_idx, void* out_dist, hipStream_t s, bool no_self = false);
 
 // Validates query coordinates (range / finite); synchronises.
 pg_status check_queries(const void* q, int64_t m, int d, bool fl, hipStream_t s);

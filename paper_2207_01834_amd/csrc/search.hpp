@@ -77,6 +77,14 @@ struct PlainIds {
     __device__ inline bool live(int64_t) const { return true; }
 };
 
+// Every point but the one at leaf-order position `self` (the query's own
+// point, for the k-NN graph).
+struct OtherIds {
+    int64_t self;
+    __device__ inline int32_t id(int64_t, uint32_t idw) const { return (int32_t)idw; }
+    __device__ inline bool live(int64_t i) const { return i != self; }
+};
+
 // Offers leaf-order point i (coordinates p, row word idw) to the k-list.
 template <typename T, int MD, typename List, typename Ids>
 __device__ inline void visit_point(const Ids& ids, const T (&q)[MD], int d, List& kl, int k,

@@ -223,3 +223,48 @@ def test_range_errors(pg, dev):
     t = pg.kdtree_build(to_dev(z, dev), leaf=1)
     gi, gd = host(*t.knn_all(2))
     assert (gd == 0).all() and gi.tolist() == [[0, 1], [0, 1]]
+
+
+def graph_oracle_rows(pts, rows, k):
+    """k-NN graph rows of the sampled points from the definition: the k+1
+    nearest of each sampled point over all points, its own entry removed."""
+    oi, od = oracle.knn_brute(pts, pts[rows], k + 1, nthreads=16)
+    own = oi == rows[:, None]
+    keep = ~own
+    keep[own.sum(axis=1) == 0, k] = False
+    return oi[keep].reshape(len(rows), k), od[keep].reshape(len(rows), k)
+
+
+@pytest.mark.parametrize("n,d,k,leaf,dtype,span", [
+    (1, 2, 3, 16, np.int32, 100), (2, 3, 1, 1, np.int32, 100), (5, 2, 4, 1, np.int32, 3),
+    (3_000, 3, 10, 16, np.int32, 8), (10_000, 2, 7, 16, np.int32, 1 << 20),
+    (9_000, 3, 16, 8, np.float32, 0), (6_000, 5, 5, 16, np.float32, 0), (4_000, 8, 33, 4, np.int32, 50),
+])
+def test_knn_graph(pg, dev, n, d, k, leaf, dtype, span):
+    say(f"knn graph n={n} d={d} k={k} leaf={leaf} {dtype.__name__}")
+    rng = np.random.default_rng(n + d * 7 + k)
+    if dtype == np.int32:
+        pts = rng.integers(0, span, (n, d)).astype(np.int32)
+    else:
+        pts = rng.standard_normal((n, d)).astype(np.float32)
+    t = pg.kdtree_build(to_dev(pts, dev), leaf=leaf)
+    gi, gd = host(*t.knn_graph(k))
+    oi, od = oracle.knn_graph_brute(pts, k, nthreads=8)
+    assert not np.any(gi == np.arange(n)[:, None])
+    if dtype == np.int32:
+        assert_int_equal(gi, gd, oi, od)
+    else:
+        assert_float_close(gi, gd, oi, od, pts, pts)
+
+
+def test_knn_graph_full_size_sampled(pg, dev):
+    # the headline shape (10M 3-D int uniform, leaf 16), k = 10, no self edges
+    pts = datagen.uniform_int(10_000_000, 3, seed=2)
+    say("knn graph 10M 3-D")
+    t = pg.kdtree_build(to_dev(pts, dev), leaf=16)
+    gi, gd = host(*t.knn_graph(10))
+    assert (gi >= 0).all() and (np.diff(gd, axis=1) >= 0).all()
+    assert not np.any(gi == np.arange(len(pts))[:, None])
+    rows = np.random.default_rng(12).choice(len(pts), 300, replace=False)
+    oi, od = graph_oracle_rows(pts, rows, 10)
+    assert_int_equal(gi[rows], gd[rows], oi, od)
