@@ -217,6 +217,41 @@ pg_status pg_bdl_stats(const pg_bdl* b, int64_t* tree_mask, int64_t* buffer_coun
 void pg_bdl_free(pg_bdl* b);
 
 /* ---------------------------------------------------------------------- */
+/* B2: the second baseline of Section 6.3 (batch updates without           */
+/* rebalancing)                                                            */
+/* ---------------------------------------------------------------------- */
+/* One static kd-tree built over the initial points whose splits never
+ * change: an inserted point joins the leaf its descent reaches (right at or
+ * above a split), so leaves grow without bound; an erased point becomes a
+ * tombstone.  Ids as in the BDL-tree: the initial points get 0..n-1, then
+ * an insertion counter continues.  k-NN and erase results are those of the
+ * BDL-tree on the same live set (same definition); only the cost differs. */
+typedef struct pg_b2 pg_b2;
+
+/* Builds the tree over points [n][d] (device, copied); leaf and ranges as
+ * pg_kdtree_build.  Synchronises.  PG_ERR_RANGE on an out-of-range point. */
+pg_status pg_b2_create(const void* points, int64_t n, int32_t d, int32_t leaf, int32_t dtype,
+                       void* stream, pg_b2** out);
+/* Inserts m device points in place (new arrays of the grown size; leaf and
+ * internal boxes recomputed).  first_id as in pg_bdl_insert.  Synchronises
+ * (range check).  PG_ERR_UNSUPPORTED beyond 2^31 - 1 stored points. */
+pg_status pg_b2_insert(pg_b2* b, const void* points, int64_t m, void* stream, int64_t* first_id);
+/* Tombstones every live point equal to one of the m given points (no
+ * rebalancing, no rebuild).  n_erased as in pg_bdl_erase.  Synchronises. */
+pg_status pg_b2_erase(pg_b2* b, const void* points, int64_t m, void* stream, int64_t* n_erased);
+/* k-NN over the live points; layout and order as pg_bdl_knn.
+ * Synchronises (query range check). */
+pg_status pg_b2_knn(const pg_b2* b, const void* queries, int64_t m, int32_t k, int64_t* out_id,
+                    void* out_dist, void* stream);
+/* Live points (host; -1 for a NULL handle). */
+int64_t pg_b2_size(const pg_b2* b);
+/* Stored points including tombstones, and the tree's depth (host outputs,
+ * either may be NULL). */
+pg_status pg_b2_stats(const pg_b2* b, int64_t* stored, int32_t* levels);
+/* Releases the tree. */
+void pg_b2_free(pg_b2* b);
+
+/* ---------------------------------------------------------------------- */
 /* Batched uneven clouds (float32) and the differentiable k-NN backward    */
 /* ---------------------------------------------------------------------- */
 /* Where the per-query k-list of the batched launch lives. */

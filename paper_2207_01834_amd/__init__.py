@@ -8,11 +8,11 @@ Submodules are imported lazily so that ``datagen`` (seeded inputs) can be
 used without loading the GPU library.
 """
 
-__all__ = ["kdtree_build", "KdTree", "BDLTree", "lib"]
+__all__ = ["kdtree_build", "KdTree", "BDLTree", "B2Tree", "lib"]
 
 
 def __getattr__(name):
-    if name in ("kdtree_build", "KdTree", "BDLTree", "lib", "PargeoError", "RangeError"):
+    if name in ("kdtree_build", "KdTree", "BDLTree", "B2Tree", "lib", "PargeoError", "RangeError"):
         from . import _binding
         return getattr(_binding, name)
     raise AttributeError(name)

@@ -57,6 +57,13 @@ SIGNATURES = {
     "pg_bdl_size": (i64, [vp]),
     "pg_bdl_stats": (i32, [vp, P64, P64, P64, i32]),
     "pg_bdl_free": (None, [vp]),
+    "pg_b2_create": (i32, [vp, i64, i32, i32, i32, vp, ctypes.POINTER(vp)]),
+    "pg_b2_insert": (i32, [vp, vp, i64, vp, P64]),
+    "pg_b2_erase": (i32, [vp, vp, i64, vp, P64]),
+    "pg_b2_knn": (i32, [vp, vp, i64, i32, vp, vp, vp]),
+    "pg_b2_size": (i64, [vp]),
+    "pg_b2_stats": (i32, [vp, P64, P32]),
+    "pg_b2_free": (None, [vp]),
     "pg_batch_workspace": (i32, [P64, i32, i32, vp, ctypes.POINTER(ctypes.c_size_t)]),
     "pg_batch_create": (i32, [P64, i32, i32, vp, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]),
     "pg_batch_knn_self": (i32, [vp, vp, i32, vp, vp, vp]),
@@ -439,3 +446,66 @@ def knn_backward(queries, points, idx, grad_d2, grad_q=None, grad_p=None, self_m
                                 ctypes.c_void_p(gq.data_ptr()), ctypes.c_void_p(gp.data_ptr()),
                                 stream_ptr(q.device)))
     return gq, gp
+
+
+class B2Tree:
+    """The second baseline of Section 6.3: one kd-tree over the initial
+    points whose splits never change; inserts join the leaf they reach,
+    erases leave tombstones.  Same interface as :class:`BDLTree`."""
+
+    def __init__(self, points: torch.Tensor, leaf: int = 16):
+        p = _points(points, "points")
+        self.d, self.leaf = p.shape[1], leaf
+        self.code = _dtype_code(p)
+        self.device = p.device
+        h = ctypes.c_void_p()
+        check(lib().pg_b2_create(ctypes.c_void_p(p.data_ptr()), p.shape[0], self.d, leaf, self.code,
+                                 stream_ptr(p.device), ctypes.byref(h)))
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.pg_b2_free(h)
+            self._h = None
+
+    def _rows(self, pts):
+        p = _points(pts, "points")
+        if p.shape[1] != self.d or _dtype_code(p) != self.code:
+            raise TypeError("points must be [m][d] of the tree's dtype")
+        return p
+
+    def insert(self, pts) -> int:
+        p = self._rows(pts)
+        first = ctypes.c_int64()
+        check(lib().pg_b2_insert(self._h, ctypes.c_void_p(p.data_ptr()), p.shape[0],
+                                 stream_ptr(p.device), ctypes.byref(first)))
+        return first.value
+
+    def erase(self, pts) -> int:
+        p = self._rows(pts)
+        cnt = ctypes.c_int64()
+        check(lib().pg_b2_erase(self._h, ctypes.c_void_p(p.data_ptr()), p.shape[0],
+                                stream_ptr(p.device), ctypes.byref(cnt)))
+        return cnt.value
+
+    def knn(self, queries, k: int, out=None):
+        q = self._rows(queries)
+        m = q.shape[0]
+        if out is None:
+            ids = torch.empty((m, k), dtype=torch.int64, device=q.device)
+            dist = torch.empty((m, k), dtype=_dist_dtype(self.code), device=q.device)
+        else:
+            ids, dist = out
+        check(lib().pg_b2_knn(self._h, ctypes.c_void_p(q.data_ptr()), m, k,
+                              ctypes.c_void_p(ids.data_ptr()), ctypes.c_void_p(dist.data_ptr()),
+                              stream_ptr(q.device)))
+        return ids, dist
+
+    def size(self) -> int:
+        return lib().pg_b2_size(self._h)
+
+    def stats(self):
+        stored, levels = ctypes.c_int64(), ctypes.c_int32()
+        check(lib().pg_b2_stats(self._h, ctypes.byref(stored), ctypes.byref(levels)))
+        return stored.value, levels.value

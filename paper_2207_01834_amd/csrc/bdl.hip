@@ -100,7 +100,7 @@ __global__ void leaf_ids_kernel(const int32_t* __restrict__ pidx, const int64_t*
 // Erase: lane = erase point, blockIdx.y = tree slot.  Walks every node whose
 // cell can hold the exact coordinates (both children where the coordinate
 // equals the split) and clears live points with equal coordinates.
-template <typename T, int MD>
+template <typename T, int MD, bool LOFF>
 __global__ void __launch_bounds__(kNT)
 erase_kernel(Forest f, const uint32_t* __restrict__ pts, const int32_t* __restrict__ order,
              int64_t m, int d, unsigned long long* __restrict__ erased) {
@@ -143,7 +143,8 @@ erase_kernel(Forest f, const uint32_t* __restrict__ pts, const int32_t* __restri
         for (int c = 0; c < MD; c++)
             if (c < d) inside = inside && !(q[c] < M::load(bb[c])) && !(q[c] > M::load(bb[d + c]));
         if (inside) {
-            const int64_t lo = node_start(tv.n, tv.L, leaf), hi = node_start(tv.n, tv.L, leaf + 1);
+            const int64_t lo = LOFF ? tv.loff[leaf] : node_start(tv.n, tv.L, leaf);
+            const int64_t hi = LOFF ? tv.loff[leaf + 1] : node_start(tv.n, tv.L, leaf + 1);
             for (int64_t i = lo; i < hi; i++) {
                 T p[MD];
                 uint32_t idw;
@@ -166,7 +167,7 @@ erase_kernel(Forest f, const uint32_t* __restrict__ pts, const int32_t* __restri
     if (hits) atomicAdd(&erased[slot], (unsigned long long)hits);
 }
 
-template <typename T, int MD, int KT, bool EX>
+template <typename T, int MD, int KT, bool EX, bool LOFF>
 __global__ void __launch_bounds__(kNT)
 bdl_knn_kernel(Forest f, const uint32_t* __restrict__ queries, const int32_t* __restrict__ order,
                int64_t m, int d, int k, int64_t* __restrict__ out_id,
@@ -181,7 +182,8 @@ bdl_knn_kernel(Forest f, const uint32_t* __restrict__ queries, const int32_t* __
     KList<typename M::D, int64_t, KT, EX> kl;
     kl.init(M::inf(), INT64_MAX);
     for (int t = 0; t < f.count; t++)
-        kd_search<T, MD>(f.s[t].tv, BdlIds{f.s[t].ids, f.s[t].alive}, q, d, kl, k);
+        kd_search<T, MD, decltype(kl), BdlIds, LOFF>(f.s[t].tv, BdlIds{f.s[t].ids, f.s[t].alive}, q,
+                                                     d, kl, k);
 #pragma unroll
     for (int s = 0; s < KT; s++) {
         if (EX || s < k) {
@@ -191,59 +193,165 @@ bdl_knn_kernel(Forest f, const uint32_t* __restrict__ queries, const int32_t* __
     }
 }
 
-template <typename T, int MD>
+template <typename T, int MD, bool LOFF>
 pg_status launch_erase(const Forest& f, const void* pts, const int32_t* order, int64_t m, int d,
                        unsigned long long* erased, hipStream_t s) {
-    hipLaunchKernelGGL((erase_kernel<T, MD>), dim3(cdiv(m, kNT), f.count), dim3(kNT), 0, s, f,
+    hipLaunchKernelGGL((erase_kernel<T, MD, LOFF>), dim3(cdiv(m, kNT), f.count), dim3(kNT), 0, s, f,
                        (const uint32_t*)pts, order, m, d, erased);
     PG_LAUNCH_CHECK();
     return PG_OK;
 }
 
-template <typename T>
+template <typename T, bool LOFF = false>
 pg_status erase_d(const Forest& f, const void* pts, const int32_t* o, int64_t m, int d,
                   unsigned long long* e, hipStream_t s) {
     switch (d) {
-        case 2: return launch_erase<T, 2>(f, pts, o, m, d, e, s);
-        case 3: return launch_erase<T, 3>(f, pts, o, m, d, e, s);
-        case 5: return launch_erase<T, 5>(f, pts, o, m, d, e, s);
-        default: return launch_erase<T, 8>(f, pts, o, m, d, e, s);
+        case 2: return launch_erase<T, 2, LOFF>(f, pts, o, m, d, e, s);
+        case 3: return launch_erase<T, 3, LOFF>(f, pts, o, m, d, e, s);
+        case 5: return launch_erase<T, 5, LOFF>(f, pts, o, m, d, e, s);
+        default: return launch_erase<T, 8, LOFF>(f, pts, o, m, d, e, s);
     }
 }
 
-template <typename T, int MD, int KT, bool EX>
+template <typename T, int MD, int KT, bool EX, bool LOFF>
 pg_status launch_bdl_knn(const Forest& f, const void* q, const int32_t* o, int64_t m, int d, int k,
                          int64_t* oi, void* od, hipStream_t s) {
     using DT = typename Metric<T>::D;
-    hipLaunchKernelGGL((bdl_knn_kernel<T, MD, KT, EX>), dim3(grid_for_xcd(cdiv(m, kNT))), dim3(kNT),
-                       0, s, f, (const uint32_t*)q, o, m, d, k, oi, (DT*)od);
+    hipLaunchKernelGGL((bdl_knn_kernel<T, MD, KT, EX, LOFF>), dim3(grid_for_xcd(cdiv(m, kNT))),
+                       dim3(kNT), 0, s, f, (const uint32_t*)q, o, m, d, k, oi, (DT*)od);
     PG_LAUNCH_CHECK();
     return PG_OK;
 }
 
-template <typename T, int MD>
+template <typename T, int MD, bool LOFF>
 pg_status bdl_knn_k(const Forest& f, const void* q, const int32_t* o, int64_t m, int d, int k,
                     int64_t* oi, void* od, hipStream_t s) {
-    if (k == 5) return launch_bdl_knn<T, MD, 5, true>(f, q, o, m, d, k, oi, od, s);
-    if (k == 10) return launch_bdl_knn<T, MD, 10, true>(f, q, o, m, d, k, oi, od, s);
-    if (k == 16) return launch_bdl_knn<T, MD, 16, true>(f, q, o, m, d, k, oi, od, s);
-    if (k <= 2) return launch_bdl_knn<T, MD, 2, false>(f, q, o, m, d, k, oi, od, s);
-    if (k <= 4) return launch_bdl_knn<T, MD, 4, false>(f, q, o, m, d, k, oi, od, s);
-    if (k <= 8) return launch_bdl_knn<T, MD, 8, false>(f, q, o, m, d, k, oi, od, s);
-    if (k <= 16) return launch_bdl_knn<T, MD, 16, false>(f, q, o, m, d, k, oi, od, s);
-    if (k <= 32) return launch_bdl_knn<T, MD, 32, false>(f, q, o, m, d, k, oi, od, s);
-    return launch_bdl_knn<T, MD, 64, false>(f, q, o, m, d, k, oi, od, s);
+    if (k == 5) return launch_bdl_knn<T, MD, 5, true, LOFF>(f, q, o, m, d, k, oi, od, s);
+    if (k == 10) return launch_bdl_knn<T, MD, 10, true, LOFF>(f, q, o, m, d, k, oi, od, s);
+    if (k == 16) return launch_bdl_knn<T, MD, 16, true, LOFF>(f, q, o, m, d, k, oi, od, s);
+    if (k <= 2) return launch_bdl_knn<T, MD, 2, false, LOFF>(f, q, o, m, d, k, oi, od, s);
+    if (k <= 4) return launch_bdl_knn<T, MD, 4, false, LOFF>(f, q, o, m, d, k, oi, od, s);
+    if (k <= 8) return launch_bdl_knn<T, MD, 8, false, LOFF>(f, q, o, m, d, k, oi, od, s);
+    if (k <= 16) return launch_bdl_knn<T, MD, 16, false, LOFF>(f, q, o, m, d, k, oi, od, s);
+    if (k <= 32) return launch_bdl_knn<T, MD, 32, false, LOFF>(f, q, o, m, d, k, oi, od, s);
+    return launch_bdl_knn<T, MD, 64, false, LOFF>(f, q, o, m, d, k, oi, od, s);
 }
 
-template <typename T>
+template <typename T, bool LOFF = false>
 pg_status bdl_knn_d(const Forest& f, const void* q, const int32_t* o, int64_t m, int d, int k,
                     int64_t* oi, void* od, hipStream_t s) {
     switch (d) {
-        case 2: return bdl_knn_k<T, 2>(f, q, o, m, d, k, oi, od, s);
-        case 3: return bdl_knn_k<T, 3>(f, q, o, m, d, k, oi, od, s);
-        case 5: return bdl_knn_k<T, 5>(f, q, o, m, d, k, oi, od, s);
-        default: return bdl_knn_k<T, 8>(f, q, o, m, d, k, oi, od, s);
+        case 2: return bdl_knn_k<T, 2, LOFF>(f, q, o, m, d, k, oi, od, s);
+        case 3: return bdl_knn_k<T, 3, LOFF>(f, q, o, m, d, k, oi, od, s);
+        case 5: return bdl_knn_k<T, 5, LOFF>(f, q, o, m, d, k, oi, od, s);
+        default: return bdl_knn_k<T, 8, LOFF>(f, q, o, m, d, k, oi, od, s);
     }
+}
+
+// ---- B2 (Section 6.3's second baseline): one static tree whose splits stay
+// fixed; inserted points join the leaf their descent reaches, erased points
+// become tombstones.  Leaf ranges are explicit offsets from then on.
+
+// Leaf of each new point (right at or above a split, as the search assumes)
+// and its rank among the new points of that leaf.
+__global__ void b2_leaf_kernel(TreeView tv, int fl, const uint32_t* __restrict__ pts, int64_t m,
+                               uint32_t* __restrict__ leaf, uint32_t* __restrict__ rank,
+                               uint32_t* __restrict__ cnt) {
+    const int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x;
+    if (i >= m) return;
+    const int d = tv.d;
+    const uint32_t first_leaf = 1u << tv.L;
+    uint32_t cur = 1;
+    int dim = 0;
+    while (cur < first_leaf) {
+        const uint32_t qb = pts[i * d + dim], sb = tv.split[cur];
+        const bool right = fl ? __uint_as_float(qb) >= __uint_as_float(sb) : (int32_t)qb >= (int32_t)sb;
+        cur = 2u * cur + (right ? 1u : 0u);
+        dim = dim + 1 == d ? 0 : dim + 1;
+    }
+    const uint32_t j = cur - first_leaf;
+    leaf[i] = j;
+    rank[i] = atomicAdd(&cnt[j], 1u);
+}
+
+// loff2[j] = loff[j] + (new points in leaves before j), j in [0, 2^L].
+__global__ void b2_offsets_kernel(const int64_t* __restrict__ loff, const uint32_t* __restrict__ nstart,
+                                  int64_t leaves, int64_t added, int64_t* __restrict__ loff2) {
+    const int64_t j = (int64_t)blockIdx.x * kNT + threadIdx.x;
+    if (j < leaves) loff2[j] = loff[j] + nstart[j];
+    else if (j == leaves) loff2[j] = loff[j] + added;
+}
+
+// Old point at position p moves to p + (new points in leaves before its leaf).
+__global__ void b2_move_kernel(TreeView tv, const int64_t* __restrict__ ids,
+                               const uint32_t* __restrict__ alive, const uint32_t* __restrict__ nstart,
+                               int64_t n2, uint32_t* __restrict__ pts2, uint32_t* __restrict__ rec2,
+                               int32_t* __restrict__ pidx2, int64_t* __restrict__ ids2,
+                               uint32_t* __restrict__ alive2) {
+    const int64_t p = (int64_t)blockIdx.x * kNT + threadIdx.x;
+    if (p >= tv.n) return;
+    // leaf of p: the last j with loff[j] <= p (upper bound over 2^L + 1 offsets)
+    int64_t lo = 0, hi = ((int64_t)1 << tv.L);
+    while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (tv.loff[mid] <= p) lo = mid;
+        else hi = mid;
+    }
+    const int64_t p2 = p + nstart[lo];
+    for (int c = 0; c < tv.d; c++) pts2[(int64_t)c * n2 + p2] = tv.pts[(int64_t)c * tv.n + p];
+    for (int w = 0; w < tv.rw; w++) rec2[p2 * tv.rw + w] = tv.rec[p * tv.rw + w];
+    pidx2[p2] = tv.pidx[p];
+    ids2[p2] = ids[p];
+    if ((alive[p >> 5] >> (p & 31)) & 1u) atomicOr(&alive2[p2 >> 5], 1u << (p2 & 31));
+}
+
+// New point i goes after its leaf's old points, at its rank.
+__global__ void b2_place_kernel(TreeView tv, int fl, const uint32_t* __restrict__ pts, int64_t m,
+                                const uint32_t* __restrict__ leaf, const uint32_t* __restrict__ rank,
+                                const int64_t* __restrict__ loff2, int64_t first_id, int64_t n2,
+                                uint32_t* __restrict__ pts2, uint32_t* __restrict__ rec2,
+                                int32_t* __restrict__ pidx2, int64_t* __restrict__ ids2,
+                                uint32_t* __restrict__ alive2) {
+    const int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x;
+    if (i >= m) return;
+    const uint32_t j = leaf[i];
+    const int64_t p2 = loff2[j] + (tv.loff[j + 1] - tv.loff[j]) + rank[i];
+    const int d = tv.d;
+    for (int w = 0; w < tv.rw; w++) {
+        uint32_t v = 0;
+        if (w < d) {
+            v = pts[i * d + w];
+            if (fl && v == 0x80000000u) v = 0u;  // -0.0 is stored as +0.0
+            pts2[(int64_t)w * n2 + p2] = v;
+        }
+        rec2[p2 * tv.rw + w] = v;
+    }
+    pidx2[p2] = 0;
+    ids2[p2] = first_id + i;
+    atomicOr(&alive2[p2 >> 5], 1u << (p2 & 31));
+}
+
+// Leaf boxes from the leaves' points (order-preserving keys; an empty leaf
+// gets the inverted box the build gives it).
+__global__ void b2_leaf_box_kernel(TreeView tv, int fl, uint32_t* __restrict__ bbox) {
+    const int64_t j = (int64_t)blockIdx.x * kNT + threadIdx.x;
+    if (j >= ((int64_t)1 << tv.L)) return;
+    const int d = tv.d;
+    for (int c = 0; c < d; c++) {
+        uint32_t mn = 0xffffffffu, mx = 0u;
+        for (int64_t p = tv.loff[j]; p < tv.loff[j + 1]; p++) {
+            const uint32_t kk = coord_to_key(tv.pts[(int64_t)c * tv.n + p], fl != 0);
+            mn = kk < mn ? kk : mn;
+            mx = kk > mx ? kk : mx;
+        }
+        bbox[j * 2 * d + c] = key_to_coord(mn, fl != 0);
+        bbox[j * 2 * d + d + c] = key_to_coord(mx, fl != 0);
+    }
+}
+
+__global__ void closed_offsets_kernel(int64_t n, int L, int64_t* __restrict__ loff) {
+    const int64_t j = (int64_t)blockIdx.x * kNT + threadIdx.x;
+    if (j <= ((int64_t)1 << L)) loff[j] = node_start(n, L, j);
 }
 
 }  // namespace
@@ -448,10 +556,101 @@ static Forest make_forest(const Bdl& B) {
     return f;
 }
 
+// B2 baseline handle: the tree (with ids and liveness) and its leaf offsets.
+struct B2 {
+    int d = 0, leaf = 0, dtype = 0;
+    BdlTree T;
+    int64_t* loff = nullptr;  // [2^L + 1]
+    int64_t next_id = 0;
+};
+
+static Forest b2_forest(const B2& B) {
+    Forest f{};
+    f.count = 0;
+    if (B.T.t) {
+        TreeView tv = B.T.t->view();
+        tv.loff = B.loff;
+        f.s[f.count++] = ForestSlot{tv, B.T.ids, B.T.alive};
+    }
+    return f;
+}
+
+// Inserts m device rows into the leaves their descent reaches.
+static pg_status b2_insert(B2& B, const void* points, int64_t m, hipStream_t s) {
+    pg_tree* t = B.T.t;
+    const int d = B.d;
+    const int fl = B.dtype == PG_FLOAT32 ? 1 : 0;
+    const int64_t n = t->n, n2 = n + m;
+    if (n2 >= ((int64_t)1 << 31)) return fail(PG_ERR_UNSUPPORTED, "B2: more than 2^31 - 1 points");
+    const int64_t leaves = (int64_t)1 << t->L;
+    const int rw = record_words(d);
+    TreeView tv = t->view();
+    tv.loff = B.loff;
+    DevBuf leaf(s), rank(s), cnt(s), nstart(s);
+    PG_TRY(leaf.alloc(sizeof(uint32_t) * m));
+    PG_TRY(rank.alloc(sizeof(uint32_t) * m));
+    PG_TRY(cnt.alloc(sizeof(uint32_t) * leaves));
+    PG_TRY(nstart.alloc(sizeof(uint32_t) * leaves));
+    PG_HIP(hipMemsetAsync(cnt.p, 0, sizeof(uint32_t) * leaves, s));
+    hipLaunchKernelGGL(b2_leaf_kernel, dim3(cdiv(m, kNT)), dim3(kNT), 0, s, tv, fl,
+                       (const uint32_t*)points, m, leaf.as<uint32_t>(), rank.as<uint32_t>(),
+                       cnt.as<uint32_t>());
+    PG_LAUNCH_CHECK();
+    PG_TRY(exclusive_scan_u32(cnt.as<uint32_t>(), nstart.as<uint32_t>(), leaves, nullptr, s));
+    uint32_t *pts2 = nullptr, *rec2 = nullptr, *alive2 = nullptr;
+    int32_t* pidx2 = nullptr;
+    int64_t *ids2 = nullptr, *loff2 = nullptr;
+    const int64_t words = (n2 + 31) / 32;
+    pg_status st = PG_OK;
+    if ((st = dalloc(&pts2, (size_t)d * n2, s)) != PG_OK ||
+        (st = dalloc(&rec2, ((size_t)n2 + kTreePad) * rw, s)) != PG_OK ||
+        (st = dalloc(&pidx2, (size_t)n2 + kTreePad, s)) != PG_OK ||
+        (st = dalloc(&ids2, (size_t)n2, s)) != PG_OK ||
+        (st = dalloc(&alive2, (size_t)words, s)) != PG_OK ||
+        (st = dalloc(&loff2, (size_t)leaves + 1, s)) != PG_OK) {
+        dfree(pts2, s); dfree(rec2, s); dfree(pidx2, s); dfree(ids2, s); dfree(alive2, s); dfree(loff2, s);
+        return st;
+    }
+    PG_HIP(hipMemsetAsync(alive2, 0, sizeof(uint32_t) * words, s));
+    hipLaunchKernelGGL(b2_offsets_kernel, dim3(cdiv(leaves + 1, kNT)), dim3(kNT), 0, s, B.loff,
+                       nstart.as<uint32_t>(), leaves, m, loff2);
+    PG_LAUNCH_CHECK();
+    if (n > 0) {
+        hipLaunchKernelGGL(b2_move_kernel, dim3(cdiv(n, kNT)), dim3(kNT), 0, s, tv, B.T.ids,
+                           B.T.alive, nstart.as<uint32_t>(), n2, pts2, rec2, pidx2, ids2, alive2);
+        PG_LAUNCH_CHECK();
+    }
+    hipLaunchKernelGGL(b2_place_kernel, dim3(cdiv(m, kNT)), dim3(kNT), 0, s, tv, fl,
+                       (const uint32_t*)points, m, leaf.as<uint32_t>(), rank.as<uint32_t>(), loff2,
+                       B.next_id, n2, pts2, rec2, pidx2, ids2, alive2);
+    PG_LAUNCH_CHECK();
+    // swap in the grown arrays
+    dfree(t->pts, s); dfree(t->rec, s); dfree(t->pidx, s); dfree(B.T.ids, s); dfree(B.T.alive, s);
+    dfree(B.loff, s);
+    t->pts = pts2;
+    t->rec = rec2;
+    t->pidx = pidx2;
+    t->n = n2;
+    B.T.ids = ids2;
+    B.T.alive = alive2;
+    B.T.live += m;
+    B.loff = loff2;
+    TreeView tv2 = t->view();
+    tv2.loff = B.loff;
+    hipLaunchKernelGGL(b2_leaf_box_kernel, dim3(cdiv(leaves, kNT)), dim3(kNT), 0, s, tv2, fl,
+                       t->bbox);
+    PG_LAUNCH_CHECK();
+    return internal_boxes(t, s);
+}
+
 }  // namespace pg
 
 struct pg_bdl {
     pg::Bdl b;
+};
+
+struct pg_b2 {
+    pg::B2 b;
 };
 
 using namespace pg;
@@ -610,6 +809,138 @@ void pg_bdl_free(pg_bdl* h) {
     if (!h) return;
     for (int i = 0; i < kMaxTrees; i++) free_tree(h->b.tree[i]);
     free_tree(h->b.buf);
+    delete h;
+}
+
+pg_status pg_b2_create(const void* points, int64_t n, int32_t d, int32_t leaf, int32_t dtype,
+                       void* stream, pg_b2** out) {
+    if (!out) return fail(PG_ERR_INVALID, "pg_b2_create: out is NULL");
+    if (d < 1 || d > 8) return fail(PG_ERR_INVALID, "pg_b2_create: d must be in [1, 8]");
+    if (leaf < 1 || leaf > 64) return fail(PG_ERR_INVALID, "pg_b2_create: leaf must be in [1, 64]");
+    if (dtype != PG_INT32 && dtype != PG_FLOAT32) return fail(PG_ERR_INVALID, "pg_b2_create: bad dtype");
+    if (n < 0 || n >= ((int64_t)1 << 31)) return fail(PG_ERR_INVALID, "pg_b2_create: n must be in [0, 2^31)");
+    if (n > 0 && !points) return fail(PG_ERR_INVALID, "pg_b2_create: points is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    pg_b2* h = new (std::nothrow) pg_b2();
+    if (!h) return fail(PG_ERR_NOMEM, "pg_b2_create: host allocation failed");
+    B2& B = h->b;
+    B.d = d;
+    B.leaf = leaf;
+    B.dtype = dtype;
+    Bdl shape;
+    shape.d = d;
+    shape.leaf = leaf;
+    shape.dtype = dtype;
+    DevBuf ids(s);
+    pg_status st = ids.alloc(sizeof(int64_t) * (n > 0 ? n : 1));
+    if (st == PG_OK && n > 0) {
+        hipLaunchKernelGGL(iota64_kernel, dim3(cdiv(n, kNT)), dim3(kNT), 0, s, ids.as<int64_t>(), n,
+                           (int64_t)0);
+        if (hipGetLastError() != hipSuccess) st = fail(PG_ERR_DEVICE, "pg_b2_create: launch failed");
+    }
+    Staged S;
+    S.rows = (uint32_t*)points;
+    S.ids = ids.as<int64_t>();
+    S.count = n;
+    if (st == PG_OK) st = build_bdl_tree(shape, S, s, B.T);
+    const int64_t leaves = B.T.t ? ((int64_t)1 << B.T.t->L) : 0;
+    if (st == PG_OK) st = dalloc(&B.loff, (size_t)leaves + 1, s);
+    if (st == PG_OK) {
+        hipLaunchKernelGGL(closed_offsets_kernel, dim3(cdiv(leaves + 1, kNT)), dim3(kNT), 0, s, n,
+                           B.T.t->L, B.loff);
+        if (hipGetLastError() != hipSuccess) st = fail(PG_ERR_DEVICE, "pg_b2_create: launch failed");
+    }
+    if (st != PG_OK) {
+        free_tree(B.T);
+        if (B.loff) dfree(B.loff, s);
+        delete h;
+        return st;
+    }
+    B.next_id = n;
+    *out = h;
+    return PG_OK;
+}
+
+pg_status pg_b2_insert(pg_b2* h, const void* points, int64_t m, void* stream, int64_t* first_id) {
+    if (!h) return fail(PG_ERR_INVALID, "pg_b2_insert: handle is NULL");
+    if (m < 0 || m >= ((int64_t)1 << 31)) return fail(PG_ERR_INVALID, "pg_b2_insert: m must be in [0, 2^31)");
+    if (m > 0 && !points) return fail(PG_ERR_INVALID, "pg_b2_insert: points is NULL");
+    B2& B = h->b;
+    hipStream_t s = (hipStream_t)stream;
+    if (first_id) *first_id = B.next_id;
+    if (m == 0) return PG_OK;
+    PG_TRY(check_queries(points, m, B.d, B.dtype == PG_FLOAT32, s));
+    PG_TRY(b2_insert(B, points, m, s));
+    B.next_id += m;
+    return PG_OK;
+}
+
+pg_status pg_b2_erase(pg_b2* h, const void* points, int64_t m, void* stream, int64_t* n_erased) {
+    if (!h) return fail(PG_ERR_INVALID, "pg_b2_erase: handle is NULL");
+    if (m < 0 || m >= ((int64_t)1 << 31)) return fail(PG_ERR_INVALID, "pg_b2_erase: m must be in [0, 2^31)");
+    if (m > 0 && !points) return fail(PG_ERR_INVALID, "pg_b2_erase: points is NULL");
+    B2& B = h->b;
+    hipStream_t s = (hipStream_t)stream;
+    if (n_erased) *n_erased = 0;
+    if (m == 0 || !B.T.t || B.T.t->n == 0) return PG_OK;
+    PG_TRY(check_queries(points, m, B.d, B.dtype == PG_FLOAT32, s));
+    Forest f = b2_forest(B);
+    DevBuf cnt(s), order(s);
+    PG_TRY(cnt.alloc(sizeof(unsigned long long)));
+    PG_HIP(hipMemsetAsync(cnt.p, 0, sizeof(unsigned long long), s));
+    const int32_t* o = nullptr;
+    if (m >= kOrderMin) {
+        PG_TRY(order_queries(f.s[0].tv, B.dtype == PG_FLOAT32, points, m, s, order));
+        o = order.as<int32_t>();
+    }
+    unsigned long long* e = cnt.as<unsigned long long>();
+    if (B.dtype == PG_FLOAT32) PG_TRY((erase_d<float, true>(f, points, o, m, B.d, e, s)));
+    else PG_TRY((erase_d<int32_t, true>(f, points, o, m, B.d, e, s)));
+    unsigned long long host = 0;
+    PG_HIP(hipMemcpyAsync(&host, e, sizeof(host), hipMemcpyDeviceToHost, s));
+    PG_HIP(hipStreamSynchronize(s));
+    B.T.live -= (int64_t)host;
+    if (n_erased) *n_erased = (int64_t)host;
+    return PG_OK;
+}
+
+pg_status pg_b2_knn(const pg_b2* h, const void* queries, int64_t m, int32_t k, int64_t* out_id,
+                    void* out_dist, void* stream) {
+    if (!h) return fail(PG_ERR_INVALID, "pg_b2_knn: handle is NULL");
+    if (k < 1 || k > 64) return fail(PG_ERR_INVALID, "pg_b2_knn: k must be in [1, 64]");
+    if (m < 0 || m >= ((int64_t)1 << 31)) return fail(PG_ERR_INVALID, "pg_b2_knn: m must be in [0, 2^31)");
+    if (m > 0 && (!queries || !out_id || !out_dist)) return fail(PG_ERR_INVALID, "pg_b2_knn: NULL pointer");
+    if (m == 0) return PG_OK;
+    const B2& B = h->b;
+    hipStream_t s = (hipStream_t)stream;
+    PG_TRY(check_queries(queries, m, B.d, B.dtype == PG_FLOAT32, s));
+    Forest f = b2_forest(B);
+    DevBuf order(s);
+    const int32_t* o = nullptr;
+    if (f.count > 0 && m >= kOrderMin) {
+        PG_TRY(order_queries(f.s[0].tv, B.dtype == PG_FLOAT32, queries, m, s, order));
+        o = order.as<int32_t>();
+    }
+    if (B.dtype == PG_FLOAT32) return bdl_knn_d<float, true>(f, queries, o, m, B.d, k, out_id, out_dist, s);
+    return bdl_knn_d<int32_t, true>(f, queries, o, m, B.d, k, out_id, out_dist, s);
+}
+
+int64_t pg_b2_size(const pg_b2* h) { return h ? h->b.T.live : -1; }
+
+pg_status pg_b2_stats(const pg_b2* h, int64_t* stored, int32_t* levels) {
+    if (!h) return fail(PG_ERR_INVALID, "pg_b2_stats: handle is NULL");
+    if (stored) *stored = h->b.T.n();
+    if (levels) *levels = h->b.T.t ? h->b.T.t->L : 0;
+    return PG_OK;
+}
+
+void pg_b2_free(pg_b2* h) {
+    if (!h) return;
+    if (h->b.T.t) {
+        hipStream_t s = h->b.T.t->stream;
+        if (h->b.loff) dfree(h->b.loff, s);
+    }
+    free_tree(h->b.T);
     delete h;
 }
 

@@ -438,8 +438,14 @@ pg_status build_from_keys(uint32_t* kA, int32_t* iA, uint32_t* kB, int32_t* iB, 
                        cur_k, cur_i, n, d, L, ls, S, ifl, T->pts, T->pidx, T->split, T->bbox,
                        T->rec);
     PG_LAUNCH_CHECK();
-    // internal boxes, bottom-up, kBoxLevels levels per launch
-    for (int lt = L; lt > 0;) {
+    return internal_boxes(T, s);
+}
+
+pg_status internal_boxes(pg_tree* T, hipStream_t s) {
+    // bottom-up, kBoxLevels levels per launch
+    const int d = T->d;
+    const int ifl = T->dtype == PG_FLOAT32 ? 1 : 0;
+    for (int lt = T->L; lt > 0;) {
         const int b = lt < kBoxLevels ? lt : kBoxLevels;
         hipLaunchKernelGGL(node_box_kernel, dim3((unsigned)((int64_t)1 << (lt - b))), dim3(kNT),
                            sizeof(uint32_t) * 2 * (2 * d) << b, s, T->nbox, d, lt, b, ifl);

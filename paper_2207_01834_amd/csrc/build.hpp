@@ -21,6 +21,9 @@ pg_status build_from_keys(uint32_t* kA, int32_t* iA, uint32_t* kB, int32_t* iB, 
                           int d, int leaf, bool fl, const uint32_t* vary,
                           const uint32_t* keybase, hipStream_t s, pg_tree* T);
 
+// Boxes of T's internal nodes from its leaf boxes (bottom-up).
+pg_status internal_boxes(pg_tree* T, hipStream_t s);
+
 // Allocates T's arrays and builds it from device rows [n][d].
 pg_status build_tree(const void* points, int64_t n, int d, int leaf, int dtype, hipStream_t s,
                      pg_tree* T);

@@ -112,6 +112,9 @@ struct TreeView {
     const uint32_t* rec;    // [n][rw] leaf-order records: coordinates, row, 0...
     const uint32_t* nbox;   // [2^(L+1)][2d] box of heap node h at h*2d (leaves: = bbox);
                             // null when only the leaf boxes exist
+    const int64_t* loff;    // [2^L + 1] leaf j holds positions [loff[j], loff[j+1]);
+                            // null: the closed form floor(j n / 2^L) (trees grown
+                            // in place keep their splits but not that form)
 };
 
 inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
@@ -130,6 +133,6 @@ struct pg_tree {
     uint32_t* bbox = nullptr;
     uint32_t* rec = nullptr;
     pg::TreeView view() const {
-        return pg::TreeView{n, d, L, pg::record_words(d), pts, pidx, split, bbox, rec, nbox};
+        return pg::TreeView{n, d, L, pg::record_words(d), pts, pidx, split, bbox, rec, nbox, nullptr};
     }
 };

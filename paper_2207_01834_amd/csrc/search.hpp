@@ -114,7 +114,8 @@ __device__ inline uint32_t leaf_of(int64_t n, int L, int64_t i) {
 // distance before the pending scan: it may enter more nodes, never fewer).
 // Stepping into a leaf only records it; the walk then stands at the leaf's
 // parent as if back from it.
-template <typename T, int MD, typename List, typename Ids>
+// LOFF: leaf ranges come from tv.loff (trees grown in place).
+template <typename T, int MD, typename List, typename Ids, bool LOFF = false>
 __device__ inline void kd_search(const TreeView& tv, const Ids& ids, const T (&q)[MD], int d,
                                  List& kl, int k, uint32_t start = 0) {
     using M = Metric<T>;
@@ -215,8 +216,9 @@ __device__ inline void kd_search(const TreeView& tv, const Ids& ids, const T (&q
                     if (MD < 8 || c < d)
                         lb = M::acc_gap(lb, q[c], M::load(bb[c]), M::load(bb[d + c]));
                 if (!(lb > kl.kd)) {
-                    const uint32_t lo = (uint32_t)node_start(n, L, leaf);
-                    const uint32_t hi = (uint32_t)node_start(n, L, leaf + 1);
+                    const uint32_t lo = LOFF ? (uint32_t)tv.loff[leaf] : (uint32_t)node_start(n, L, leaf);
+                    const uint32_t hi = LOFF ? (uint32_t)tv.loff[leaf + 1]
+                                             : (uint32_t)node_start(n, L, leaf + 1);
                     if (lo < hi) {
                         // two record registers, alternately loading and in
                         // use; positions past the leaf reread its last record

@@ -1,0 +1,143 @@
+"""GPU parity of the B2 baseline (Section 6.3: one kd-tree whose splits stay
+fixed; inserts join the leaf they reach, erases leave tombstones) against the
+oracle's live-set model: erase counts and k-NN over the live points
+(byte-identical for int32, within the float bar for float32)."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle.bdl_model import BDLModel
+from paper_2207_01834_amd import datagen
+from parity import assert_float_close, assert_int_equal, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pg(dev):
+    import paper_2207_01834_amd._binding as b
+    b.lib()
+    return b
+
+
+def to_dev(a, dev):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def host(*ts):
+    import torch
+    torch.cuda.synchronize()
+    return [t.cpu().numpy() for t in ts]
+
+
+def check_knn(G, M, q, k, dtype, dev):
+    gi, gd = host(*G.knn(to_dev(q, dev), k))
+    pts, ids = M.live()
+    oi, od = oracle.knn_brute(pts, q, k, ids=ids, nthreads=8)
+    if dtype == np.int32:
+        assert_int_equal(gi, gd, oi, od)
+    else:
+        pos = {int(t): r for r, t in enumerate(ids.tolist())}
+        gr = np.vectorize(lambda t: pos.get(int(t), -1))(gi)
+        orr = np.vectorize(lambda t: pos.get(int(t), -1))(oi)
+        assert_float_close(gr, gd, orr, od, pts, q)
+
+
+def run(pg, dev, d, n0, steps, coord_hi, dtype, seed, k=7, leaf=8, batch=300):
+    g = np.random.default_rng(seed)
+
+    def draw(cnt):
+        if dtype == np.int32:
+            return g.integers(0, coord_hi, size=(cnt, d)).astype(np.int32)
+        return (np.floor(g.random((cnt, d)) * coord_hi) / coord_hi).astype(np.float32)
+
+    init = draw(n0)
+    say(f"B2 d={d} n0={n0} leaf={leaf} {np.dtype(dtype).name}")
+    G = pg.B2Tree(to_dev(init, dev), leaf=leaf)
+    M = BDLModel(d, 1 << 20, dtype=dtype)
+    M.insert(init)
+    assert G.size() == n0
+    stored = n0
+    for step in range(steps):
+        if step % 3 != 2:
+            P = draw(int(g.integers(0, batch)))
+            # clustered inserts into a few leaves, so leaves grow well past `leaf`
+            if step % 2 and len(P):
+                P[:] = P[0]
+            assert G.insert(to_dev(P, dev)) == M.insert(P)
+            stored += len(P)
+        else:
+            pts, _ = M.live()
+            cnt = int(g.integers(0, max(1, len(pts) // 2)))
+            E = pts[np.sort(g.choice(len(pts), size=min(cnt, len(pts)), replace=False))] if len(pts) else pts
+            E = np.concatenate([E, draw(5), E[:3]]) if len(E) else draw(5)
+            assert G.erase(to_dev(E, dev)) == M.erase(E)
+        assert G.size() == M.size()
+        assert G.stats()[0] == stored
+        if M.size():
+            check_knn(G, M, draw(80), k, dtype, dev)
+
+
+def test_b2_int_duplicates(pg, dev):
+    run(pg, dev, d=3, n0=500, steps=24, coord_hi=10, dtype=np.int32, seed=1)
+
+
+def test_b2_int_wide(pg, dev):
+    run(pg, dev, d=2, n0=3000, steps=18, coord_hi=1 << 20, dtype=np.int32, seed=2, k=10, leaf=16)
+
+
+def test_b2_float(pg, dev):
+    run(pg, dev, d=3, n0=2000, steps=15, coord_hi=64, dtype=np.float32, seed=3)
+
+
+def test_b2_d5_leaf1_and_empty_start(pg, dev):
+    run(pg, dev, d=5, n0=40, steps=15, coord_hi=6, dtype=np.int32, seed=4, k=3, leaf=1, batch=60)
+    run(pg, dev, d=2, n0=0, steps=12, coord_hi=100, dtype=np.int32, seed=5, k=4, leaf=4, batch=50)
+
+
+def test_b2_many_queries_ordered(pg, dev):
+    # enough queries and erase points to take the leaf-ordered path
+    init, rounds = datagen.bdl_rounds(100_000, 2, 10_000, 8_000, 3, seed=7)
+    G = pg.B2Tree(to_dev(init, dev), leaf=16)
+    M = BDLModel(3, 1 << 20)
+    M.insert(init)
+    for r, rd in enumerate(rounds):
+        assert G.insert(to_dev(rd["insert"], dev)) == M.insert(rd["insert"])
+        pts, _ = M.live()
+        E = datagen.choose_erase(pts, 6_000, rd["erase_seed"])
+        assert G.erase(to_dev(E, dev)) == M.erase(E)
+        q = rd["queries"]
+        gi, gd = host(*G.knn(to_dev(q, dev), 10))
+        pts, ids = M.live()
+        t = oracle.KdTree(pts, leaf=16)
+        oi, od, _ = t.knn(q, 10, ids=ids)
+        assert_int_equal(gi, gd, oi, od)
+
+
+def test_b2_full_size_sampled(pg, dev):
+    """The batch-dynamic workload on B2: 10M initial points, 3 rounds of 1M
+    inserts, 1M erases of live points, 1M queries (k = 10); 300 sampled rows
+    per round against the definition over the live set."""
+    init, rounds = datagen.bdl_rounds(10_000_000, 3, 1_000_000, 1_000_000, 3, seed=5)
+    say("B2 full size: build")
+    G = pg.B2Tree(to_dev(init, dev), leaf=16)
+    pts = init
+    ids = np.arange(len(init), dtype=np.int64)
+    nxt = len(init)
+    key = lambda a: a[:, 0].astype(np.int64) | (a[:, 1].astype(np.int64) << 20) | (a[:, 2].astype(np.int64) << 40)
+    for r, rd in enumerate(rounds):
+        say(f"B2 full size: round {r}")
+        assert G.insert(to_dev(rd["insert"], dev)) == nxt
+        pts = np.concatenate([pts, rd["insert"]])
+        ids = np.concatenate([ids, np.arange(nxt, nxt + len(rd["insert"]), dtype=np.int64)])
+        nxt += len(rd["insert"])
+        E = datagen.choose_erase(pts, 1_000_000, rd["erase_seed"])
+        hit = np.isin(key(pts), key(E))
+        assert G.erase(to_dev(E, dev)) == int(hit.sum())
+        pts, ids = pts[~hit], ids[~hit]
+        assert G.size() == len(pts)
+        gi, gd = host(*G.knn(to_dev(rd["queries"], dev), 10))
+        rows = np.random.default_rng(r).choice(len(rd["queries"]), 300, replace=False)
+        oi, od = oracle.knn_brute(pts, rd["queries"][rows], 10, ids=ids, nthreads=16)
+        assert_int_equal(gi[rows], gd[rows], oi, od)
