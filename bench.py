@@ -256,6 +256,44 @@ def form_bdl(torch, pg, datagen, dev, rounds):
             "live_points": B.size()}
 
 
+def form_baselines(torch, pg, datagen, dev, rounds):
+    """The two baselines of Section 6.3 on the BDL rounds (10M initial 3-D
+    int points; per round 1M inserts, 1M erases of live points, 1M fresh
+    queries, k = 10): B1 rebuilds one tree after every batch, B2 keeps its
+    splits (inserts join leaves, erases leave tombstones).  Median per round."""
+    import numpy as np
+    init, rds = datagen.bdl_rounds(N, rounds, 1_000_000, 1_000_000, 3, seed=5)
+    out = {"workload": f"10M initial 3-D int32 uniform points, {rounds} rounds of 1M insert / "
+                       "1M erase / 1M k-NN (k=10), leaf 16"}
+    for name in ("b1", "b2"):
+        x = torch.from_numpy(init).to(dev)
+        if name == "b1":
+            G = pg.B1Tree(3, torch.int32, leaf=LEAF, device=dev)
+            G.insert(x)
+        else:
+            G = pg.B2Tree(x, leaf=LEAF)
+        pool = init
+        ins, era, knn = [], [], []
+        for rd in rds:  # the same batches as the BDL form
+            P = torch.from_numpy(rd["insert"]).to(dev)
+            ins.append(timed(torch, lambda: G.insert(P), reps=1))
+            pool = np.concatenate([pool, rd["insert"]])
+            g = np.random.default_rng(rd["erase_seed"])
+            pick = g.choice(len(pool), size=1_000_000, replace=False)
+            E = torch.from_numpy(np.ascontiguousarray(pool[pick])).to(dev)
+            keep = np.ones(len(pool), bool)
+            keep[pick] = False
+            pool = pool[keep]
+            era.append(timed(torch, lambda: G.erase(E), reps=1))
+            Q = torch.from_numpy(rd["queries"]).to(dev)
+            knn.append(timed(torch, lambda: G.knn(Q, 10), reps=1))
+        out[name] = {"insert_ms": float(np.median(ins)), "erase_ms": float(np.median(era)),
+                     "knn_ms": float(np.median(knn)), "knn_ms_last": knn[-1]}
+        del G
+        torch.cuda.empty_cache()
+    return out
+
+
 def form_batch(torch, pg, datagen, dev, loop_clouds):
     """4,096 sphere clouds (sizes log-uniform in [256, 65536]), per-cloud
     all-points k = 16 in one persistent launch, against the per-cloud static
@@ -360,7 +398,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms", default="all",
                     help="other forms to measure after the headline step: all, none, or a "
-                         "comma list of static_float,clustered,bdl,batch,range,graph")
+                         "comma list of static_float,clustered,bdl,baselines,batch,range,graph")
     ap.add_argument("--bdl-rounds", type=int, default=10)
     ap.add_argument("--loop-clouds", type=int, default=512,
                     help="clouds timed for the per-cloud comparison (projected to 4,096)")
@@ -472,7 +510,8 @@ def main():
     }
     del idx, dist, x
     torch.cuda.empty_cache()
-    forms = ["static_float", "clustered", "bdl", "batch", "range", "graph"] if args.forms == "all" else \
+    forms = ["static_float", "clustered", "bdl", "baselines", "batch", "range", "graph"] \
+        if args.forms == "all" else \
         [f for f in args.forms.split(",") if f and f != "none"]
     out = {}
     for f in forms:
@@ -485,6 +524,8 @@ def main():
             out[f] = form_bdl(torch, pg, datagen, dev, args.bdl_rounds)
         elif f == "batch":
             out[f] = form_batch(torch, pg, datagen, dev, args.loop_clouds)
+        elif f == "baselines":
+            out[f] = form_baselines(torch, pg, datagen, dev, args.bdl_rounds)
         elif f == "graph":
             out[f] = form_graph(torch, pg, datagen, dev)
         elif f == "range":

@@ -217,6 +217,31 @@ pg_status pg_bdl_stats(const pg_bdl* b, int64_t* tree_mask, int64_t* buffer_coun
 void pg_bdl_free(pg_bdl* b);
 
 /* ---------------------------------------------------------------------- */
+/* B1: the first baseline of Section 6.3 (rebuild on every batch)          */
+/* ---------------------------------------------------------------------- */
+/* One static kd-tree over all live points, rebuilt from scratch after every
+ * insert batch and after every erase batch that removes a point.  Ids and
+ * results as in the BDL-tree (same definition on the same live set). */
+typedef struct pg_b1 pg_b1;
+
+/* Creates an empty B1 tree (host only).  d 1..8, leaf 1..64. */
+pg_status pg_b1_create(int32_t d, int32_t dtype, int32_t leaf, pg_b1** out);
+/* Inserts m device points and rebuilds.  first_id as in pg_bdl_insert.
+ * Synchronises.  PG_ERR_UNSUPPORTED beyond 2^31 - 1 points. */
+pg_status pg_b1_insert(pg_b1* b, const void* points, int64_t m, void* stream, int64_t* first_id);
+/* Removes every live point equal to one of the m given points, then
+ * rebuilds over the rest.  n_erased as in pg_bdl_erase.  Synchronises. */
+pg_status pg_b1_erase(pg_b1* b, const void* points, int64_t m, void* stream, int64_t* n_erased);
+/* k-NN over the live points; layout and order as pg_bdl_knn.
+ * Synchronises (query range check). */
+pg_status pg_b1_knn(const pg_b1* b, const void* queries, int64_t m, int32_t k, int64_t* out_id,
+                    void* out_dist, void* stream);
+/* Live points (host; -1 for a NULL handle). */
+int64_t pg_b1_size(const pg_b1* b);
+/* Releases the tree. */
+void pg_b1_free(pg_b1* b);
+
+/* ---------------------------------------------------------------------- */
 /* B2: the second baseline of Section 6.3 (batch updates without           */
 /* rebalancing)                                                            */
 /* ---------------------------------------------------------------------- */

@@ -8,11 +8,11 @@ Submodules are imported lazily so that ``datagen`` (seeded inputs) can be
 used without loading the GPU library.
 """
 
-__all__ = ["kdtree_build", "KdTree", "BDLTree", "B2Tree", "lib"]
+__all__ = ["kdtree_build", "KdTree", "BDLTree", "B1Tree", "B2Tree", "lib"]
 
 
 def __getattr__(name):
-    if name in ("kdtree_build", "KdTree", "BDLTree", "B2Tree", "lib", "PargeoError", "RangeError"):
+    if name in ("kdtree_build", "KdTree", "BDLTree", "B1Tree", "B2Tree", "lib", "PargeoError", "RangeError"):
         from . import _binding
         return getattr(_binding, name)
     raise AttributeError(name)

@@ -57,6 +57,12 @@ SIGNATURES = {
     "pg_bdl_size": (i64, [vp]),
     "pg_bdl_stats": (i32, [vp, P64, P64, P64, i32]),
     "pg_bdl_free": (None, [vp]),
+    "pg_b1_create": (i32, [i32, i32, i32, ctypes.POINTER(vp)]),
+    "pg_b1_insert": (i32, [vp, vp, i64, vp, P64]),
+    "pg_b1_erase": (i32, [vp, vp, i64, vp, P64]),
+    "pg_b1_knn": (i32, [vp, vp, i64, i32, vp, vp, vp]),
+    "pg_b1_size": (i64, [vp]),
+    "pg_b1_free": (None, [vp]),
     "pg_b2_create": (i32, [vp, i64, i32, i32, i32, vp, ctypes.POINTER(vp)]),
     "pg_b2_insert": (i32, [vp, vp, i64, vp, P64]),
     "pg_b2_erase": (i32, [vp, vp, i64, vp, P64]),
@@ -509,3 +515,55 @@ class B2Tree:
         stored, levels = ctypes.c_int64(), ctypes.c_int32()
         check(lib().pg_b2_stats(self._h, ctypes.byref(stored), ctypes.byref(levels)))
         return stored.value, levels.value
+
+
+class B1Tree:
+    """The first baseline of Section 6.3: one static kd-tree over the live
+    points, rebuilt from scratch after every batch.  Same interface as
+    :class:`BDLTree`."""
+
+    def __init__(self, d: int, dtype=torch.int32, leaf: int = 16, device="cuda"):
+        self.d, self.leaf = d, leaf
+        self.code = PG_INT32 if dtype == torch.int32 else PG_FLOAT32
+        self.device = torch.device(device)
+        h = ctypes.c_void_p()
+        check(lib().pg_b1_create(d, self.code, leaf, ctypes.byref(h)))
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.pg_b1_free(h)
+            self._h = None
+
+    _rows = B2Tree._rows
+
+    def insert(self, pts) -> int:
+        p = self._rows(pts)
+        first = ctypes.c_int64()
+        check(lib().pg_b1_insert(self._h, ctypes.c_void_p(p.data_ptr()), p.shape[0],
+                                 stream_ptr(p.device), ctypes.byref(first)))
+        return first.value
+
+    def erase(self, pts) -> int:
+        p = self._rows(pts)
+        cnt = ctypes.c_int64()
+        check(lib().pg_b1_erase(self._h, ctypes.c_void_p(p.data_ptr()), p.shape[0],
+                                stream_ptr(p.device), ctypes.byref(cnt)))
+        return cnt.value
+
+    def knn(self, queries, k: int, out=None):
+        q = self._rows(queries)
+        m = q.shape[0]
+        if out is None:
+            ids = torch.empty((m, k), dtype=torch.int64, device=q.device)
+            dist = torch.empty((m, k), dtype=_dist_dtype(self.code), device=q.device)
+        else:
+            ids, dist = out
+        check(lib().pg_b1_knn(self._h, ctypes.c_void_p(q.data_ptr()), m, k,
+                              ctypes.c_void_p(ids.data_ptr()), ctypes.c_void_p(dist.data_ptr()),
+                              stream_ptr(q.device)))
+        return ids, dist
+
+    def size(self) -> int:
+        return lib().pg_b1_size(self._h)

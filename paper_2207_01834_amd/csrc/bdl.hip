@@ -643,10 +643,41 @@ static pg_status b2_insert(B2& B, const void* points, int64_t m, hipStream_t s) 
     return internal_boxes(t, s);
 }
 
+// B1 baseline handle: one static tree over the live points, rebuilt whole
+// after every batch.
+struct B1 {
+    Bdl shape;  // d, leaf, dtype
+    BdlTree T;
+    int64_t next_id = 0;
+};
+
+// Rebuilds B1's tree over its live points followed by `extra` (may be empty).
+static pg_status b1_rebuild(B1& B, const Staged& extra, hipStream_t s) {
+    const int64_t live = B.T.t ? B.T.live : 0;
+    Staged S;
+    DevBuf rows(s), ids(s);
+    S.count = live + extra.count;
+    PG_TRY(rows.alloc(sizeof(uint32_t) * B.shape.d * (S.count > 0 ? S.count : 1)));
+    PG_TRY(ids.alloc(sizeof(int64_t) * (S.count > 0 ? S.count : 1)));
+    S.rows = rows.as<uint32_t>();
+    S.ids = ids.as<int64_t>();
+    if (live > 0) PG_TRY(append_live(B.shape, B.T, S, 0, s));
+    PG_TRY(copy_slice(B.shape, extra, 0, extra.count, S, live, s));
+    BdlTree fresh;
+    PG_TRY(build_bdl_tree(B.shape, S, s, fresh));
+    free_tree(B.T);
+    B.T = fresh;
+    return PG_OK;
+}
+
 }  // namespace pg
 
 struct pg_bdl {
     pg::Bdl b;
+};
+
+struct pg_b1 {
+    pg::B1 b;
 };
 
 struct pg_b2 {
@@ -809,6 +840,109 @@ void pg_bdl_free(pg_bdl* h) {
     if (!h) return;
     for (int i = 0; i < kMaxTrees; i++) free_tree(h->b.tree[i]);
     free_tree(h->b.buf);
+    delete h;
+}
+
+pg_status pg_b1_create(int32_t d, int32_t dtype, int32_t leaf, pg_b1** out) {
+    if (!out) return fail(PG_ERR_INVALID, "pg_b1_create: out is NULL");
+    if (d < 1 || d > 8) return fail(PG_ERR_INVALID, "pg_b1_create: d must be in [1, 8]");
+    if (leaf < 1 || leaf > 64) return fail(PG_ERR_INVALID, "pg_b1_create: leaf must be in [1, 64]");
+    if (dtype != PG_INT32 && dtype != PG_FLOAT32) return fail(PG_ERR_INVALID, "pg_b1_create: bad dtype");
+    pg_b1* h = new (std::nothrow) pg_b1();
+    if (!h) return fail(PG_ERR_NOMEM, "pg_b1_create: host allocation failed");
+    h->b.shape.d = d;
+    h->b.shape.dtype = dtype;
+    h->b.shape.leaf = leaf;
+    *out = h;
+    return PG_OK;
+}
+
+pg_status pg_b1_insert(pg_b1* h, const void* points, int64_t m, void* stream, int64_t* first_id) {
+    if (!h) return fail(PG_ERR_INVALID, "pg_b1_insert: handle is NULL");
+    if (m < 0 || m >= ((int64_t)1 << 31)) return fail(PG_ERR_INVALID, "pg_b1_insert: m must be in [0, 2^31)");
+    if (m > 0 && !points) return fail(PG_ERR_INVALID, "pg_b1_insert: points is NULL");
+    B1& B = h->b;
+    hipStream_t s = (hipStream_t)stream;
+    if (first_id) *first_id = B.next_id;
+    if (m == 0) return PG_OK;
+    if ((B.T.t ? B.T.live : 0) + m >= ((int64_t)1 << 31))
+        return fail(PG_ERR_UNSUPPORTED, "B1: more than 2^31 - 1 points");
+    PG_TRY(check_queries(points, m, B.shape.d, B.shape.dtype == PG_FLOAT32, s));
+    DevBuf ids(s);
+    PG_TRY(ids.alloc(sizeof(int64_t) * m));
+    hipLaunchKernelGGL(iota64_kernel, dim3(cdiv(m, kNT)), dim3(kNT), 0, s, ids.as<int64_t>(), m,
+                       B.next_id);
+    PG_LAUNCH_CHECK();
+    Staged S;
+    S.rows = (uint32_t*)points;
+    S.ids = ids.as<int64_t>();
+    S.count = m;
+    PG_TRY(b1_rebuild(B, S, s));
+    B.next_id += m;
+    return PG_OK;
+}
+
+pg_status pg_b1_erase(pg_b1* h, const void* points, int64_t m, void* stream, int64_t* n_erased) {
+    if (!h) return fail(PG_ERR_INVALID, "pg_b1_erase: handle is NULL");
+    if (m < 0 || m >= ((int64_t)1 << 31)) return fail(PG_ERR_INVALID, "pg_b1_erase: m must be in [0, 2^31)");
+    if (m > 0 && !points) return fail(PG_ERR_INVALID, "pg_b1_erase: points is NULL");
+    B1& B = h->b;
+    hipStream_t s = (hipStream_t)stream;
+    if (n_erased) *n_erased = 0;
+    if (m == 0 || !B.T.t || B.T.t->n == 0) return PG_OK;
+    PG_TRY(check_queries(points, m, B.shape.d, B.shape.dtype == PG_FLOAT32, s));
+    Forest f{};
+    f.count = 1;
+    f.s[0] = ForestSlot{B.T.t->view(), B.T.ids, B.T.alive};
+    DevBuf cnt(s), order(s);
+    PG_TRY(cnt.alloc(sizeof(unsigned long long)));
+    PG_HIP(hipMemsetAsync(cnt.p, 0, sizeof(unsigned long long), s));
+    const int32_t* o = nullptr;
+    if (m >= kOrderMin) {
+        PG_TRY(order_queries(f.s[0].tv, B.shape.dtype == PG_FLOAT32, points, m, s, order));
+        o = order.as<int32_t>();
+    }
+    unsigned long long* e = cnt.as<unsigned long long>();
+    if (B.shape.dtype == PG_FLOAT32) PG_TRY(erase_d<float>(f, points, o, m, B.shape.d, e, s));
+    else PG_TRY(erase_d<int32_t>(f, points, o, m, B.shape.d, e, s));
+    unsigned long long host = 0;
+    PG_HIP(hipMemcpyAsync(&host, e, sizeof(host), hipMemcpyDeviceToHost, s));
+    PG_HIP(hipStreamSynchronize(s));
+    B.T.live -= (int64_t)host;
+    if (n_erased) *n_erased = (int64_t)host;
+    if (host == 0) return PG_OK;
+    Staged none;
+    return b1_rebuild(B, none, s);
+}
+
+pg_status pg_b1_knn(const pg_b1* h, const void* queries, int64_t m, int32_t k, int64_t* out_id,
+                    void* out_dist, void* stream) {
+    if (!h) return fail(PG_ERR_INVALID, "pg_b1_knn: handle is NULL");
+    if (k < 1 || k > 64) return fail(PG_ERR_INVALID, "pg_b1_knn: k must be in [1, 64]");
+    if (m < 0 || m >= ((int64_t)1 << 31)) return fail(PG_ERR_INVALID, "pg_b1_knn: m must be in [0, 2^31)");
+    if (m > 0 && (!queries || !out_id || !out_dist)) return fail(PG_ERR_INVALID, "pg_b1_knn: NULL pointer");
+    if (m == 0) return PG_OK;
+    const B1& B = h->b;
+    hipStream_t s = (hipStream_t)stream;
+    PG_TRY(check_queries(queries, m, B.shape.d, B.shape.dtype == PG_FLOAT32, s));
+    Forest f{};
+    f.count = 0;
+    if (B.T.t) f.s[f.count++] = ForestSlot{B.T.t->view(), B.T.ids, B.T.alive};
+    DevBuf order(s);
+    const int32_t* o = nullptr;
+    if (f.count > 0 && m >= kOrderMin) {
+        PG_TRY(order_queries(f.s[0].tv, B.shape.dtype == PG_FLOAT32, queries, m, s, order));
+        o = order.as<int32_t>();
+    }
+    if (B.shape.dtype == PG_FLOAT32) return bdl_knn_d<float>(f, queries, o, m, B.shape.d, k, out_id, out_dist, s);
+    return bdl_knn_d<int32_t>(f, queries, o, m, B.shape.d, k, out_id, out_dist, s);
+}
+
+int64_t pg_b1_size(const pg_b1* h) { return h ? (h->b.T.t ? h->b.T.live : 0) : -1; }
+
+void pg_b1_free(pg_b1* h) {
+    if (!h) return;
+    free_tree(h->b.T);
     delete h;
 }
 

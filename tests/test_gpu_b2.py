@@ -1,5 +1,6 @@
-"""GPU parity of the B2 baseline (Section 6.3: one kd-tree whose splits stay
-fixed; inserts join the leaf they reach, erases leave tombstones) against the
+"""GPU parity of the two baselines of Section 6.3 -- B1 (one static tree
+rebuilt after every batch) and B2 (one kd-tree whose splits stay fixed;
+inserts join the leaf they reach, erases leave tombstones) -- against the
 oracle's live-set model: erase counts and k-NN over the live points
 (byte-identical for int32, within the float bar for float32)."""
 import numpy as np
@@ -44,7 +45,8 @@ def check_knn(G, M, q, k, dtype, dev):
         assert_float_close(gr, gd, orr, od, pts, q)
 
 
-def run(pg, dev, d, n0, steps, coord_hi, dtype, seed, k=7, leaf=8, batch=300):
+def run(pg, dev, d, n0, steps, coord_hi, dtype, seed, k=7, leaf=8, batch=300, kind="b2"):
+    import torch
     g = np.random.default_rng(seed)
 
     def draw(cnt):
@@ -53,8 +55,12 @@ def run(pg, dev, d, n0, steps, coord_hi, dtype, seed, k=7, leaf=8, batch=300):
         return (np.floor(g.random((cnt, d)) * coord_hi) / coord_hi).astype(np.float32)
 
     init = draw(n0)
-    say(f"B2 d={d} n0={n0} leaf={leaf} {np.dtype(dtype).name}")
-    G = pg.B2Tree(to_dev(init, dev), leaf=leaf)
+    say(f"{kind} d={d} n0={n0} leaf={leaf} {np.dtype(dtype).name}")
+    if kind == "b2":
+        G = pg.B2Tree(to_dev(init, dev), leaf=leaf)
+    else:
+        G = pg.B1Tree(d, torch.int32 if dtype == np.int32 else torch.float32, leaf=leaf, device=dev)
+        assert G.insert(to_dev(init, dev)) == 0
     M = BDLModel(d, 1 << 20, dtype=dtype)
     M.insert(init)
     assert G.size() == n0
@@ -74,7 +80,8 @@ def run(pg, dev, d, n0, steps, coord_hi, dtype, seed, k=7, leaf=8, batch=300):
             E = np.concatenate([E, draw(5), E[:3]]) if len(E) else draw(5)
             assert G.erase(to_dev(E, dev)) == M.erase(E)
         assert G.size() == M.size()
-        assert G.stats()[0] == stored
+        if kind == "b2":
+            assert G.stats()[0] == stored
         if M.size():
             check_knn(G, M, draw(80), k, dtype, dev)
 
@@ -94,6 +101,15 @@ def test_b2_float(pg, dev):
 def test_b2_d5_leaf1_and_empty_start(pg, dev):
     run(pg, dev, d=5, n0=40, steps=15, coord_hi=6, dtype=np.int32, seed=4, k=3, leaf=1, batch=60)
     run(pg, dev, d=2, n0=0, steps=12, coord_hi=100, dtype=np.int32, seed=5, k=4, leaf=4, batch=50)
+
+
+@pytest.mark.parametrize("d,n0,coord_hi,dtype,leaf", [(3, 500, 10, np.int32, 8),
+                                                    (2, 2000, 1 << 20, np.int32, 16),
+                                                    (3, 1500, 64, np.float32, 8),
+                                                    (5, 30, 6, np.int32, 1), (2, 0, 100, np.int32, 4)])
+def test_b1_sequences(pg, dev, d, n0, coord_hi, dtype, leaf):
+    run(pg, dev, d=d, n0=n0, steps=12, coord_hi=coord_hi, dtype=dtype, seed=d + n0, k=5, leaf=leaf,
+        batch=200, kind="b1")
 
 
 def test_b2_many_queries_ordered(pg, dev):
