@@ -13,6 +13,8 @@ Parts (each function cites the passage it follows):
                       (Algorithms 3 and 4), in Python;
   * ``grad``       -- the closed-form FP64 gradient of summed k-NN squared
                       distances and central finite differences, in NumPy;
+  * ``spatial_tree`` -- the kd-tree by spatial-median splits (C,
+                      ``or_kd_build_spatial``);
   * ``knn_graph_brute`` -- the k-NN graph (each point's k nearest other
                       points) from the k-NN definition;
   * ``range_brute`` / ``KdTree.range`` -- the orthogonal range query written
@@ -59,6 +61,8 @@ def lib():
         L.or_kd_export.restype = None
         L.or_kd_knn.argtypes = [vp, vp, vp, vp, i64, i32, vp, vp, vp]
         L.or_kd_knn.restype = i32
+        L.or_kd_build_spatial.argtypes = [vp, i64, i32, i32, i32, vp, vp, vp, vp]
+        L.or_kd_build_spatial.restype = i32
         L.or_range_brute.argtypes = [vp, vp, vp, i64, i32, i32, vp, i64, vp, vp, vp]
         L.or_range_brute.restype = i32
         L.or_kd_range.argtypes = [vp, vp, vp, vp, i64, vp, vp, vp, vp]
@@ -231,6 +235,32 @@ class KdTree:
         lib().or_kd_range(self._h, _ptr(ids), _ptr(alive), _ptr(boxes), m, _ptr(counts),
                           _ptr(off), _ptr(out), _ptr(counters))
         return counts, off, out, counters
+
+
+def spatial_tree(points, leaf=16):
+    """Spatial-median kd-tree (Section 6.3: the node's space cut in half along
+    a dimension), read as: root space = bounding box of the points; node
+    (l, j) cuts its cell along dimension l mod d at the cell's midpoint
+    (int: floor((lo + hi + 1) / 2), cells [lo, s-1] / [s, hi]; float: the
+    float nearest (lo + hi) / 2, cells [lo, s] / [s, hi]); coordinate < s
+    goes left, each side keeps the parent's order; depth L as the
+    object-median tree, so leaf sizes vary.  Returns (levels, splits float64
+    [2^L] with index 0 unused, rows int64 [n] in leaf order, leaf offsets
+    int64 [2^L + 1])."""
+    points = np.ascontiguousarray(points)
+    dt = _dtype_code(points)
+    n, d = points.shape
+    lv = ctypes.c_int()
+    rc = lib().or_kd_build_spatial(_ptr(points), n, d, dt, leaf, ctypes.byref(lv), None, None, None)
+    if rc != 0:
+        raise ValueError("or_kd_build_spatial: bad arguments")
+    L = lv.value
+    splits = np.zeros(1 << L, dtype=np.float64)
+    perm = np.empty(n, dtype=np.int64)
+    loff = np.empty((1 << L) + 1, dtype=np.int64)
+    lib().or_kd_build_spatial(_ptr(points), n, d, dt, leaf, ctypes.byref(lv), _ptr(splits),
+                              _ptr(perm), _ptr(loff))
+    return L, splits, perm, loff
 
 
 def tree_depth(n: int, leaf: int) -> int:

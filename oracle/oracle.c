@@ -37,6 +37,8 @@
  *                     Table 1) written out: every point inside a closed box.
  *   or_kd_range    -- the same query on the tree (whole subtrees inside the
  *                     box are reported, subtrees outside it skipped).
+ *   or_kd_build_spatial -- the tree by spatial-median splits (cell halving),
+ *                     with the readings stated at its definition.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -512,5 +514,85 @@ int or_kd_range(const or_tree* T, const int64_t* ids, const uint8_t* alive,
         cn += C.n_nodes; cp += C.n_points;
     }
     if (counters) { counters[0] = cn; counters[1] = cp; }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* O8: kd-tree by spatial-median splits (Section 6.3 compares them with the */
+/* object-median splits: a node's space is cut in half along a dimension).  */
+/* Readings: the space of the root is the bounding box of the points; node  */
+/* (l, j) cuts its cell along dimension l mod d at the cell's midpoint s;   */
+/* its points with coordinate < s go left, the others right, each side in   */
+/* the parent's order; the tree keeps the object-median tree's depth        */
+/* L = min{L : ceil(n/2^L) <= leaf}, so leaves hold varying numbers of      */
+/* points.  Midpoints: int cells [lo, hi] cut at floor((lo + hi + 1) / 2)    */
+/* into [lo, s-1] and [s, hi]; float cells [lo, hi] at the float nearest   */
+/* to (lo + hi) / 2 (sum in double) into [lo, s] and [s, hi].               */
+/* ------------------------------------------------------------------------ */
+static double sp_mid(double lo, double hi, int dt) {
+    if (dt == OR_DT_INT) {
+        int64_t t = (int64_t)lo + (int64_t)hi + 1;
+        int64_t s = t >= 0 ? t / 2 : -((-t + 1) / 2);
+        return (double)s;
+    }
+    return (double)(float)(0.5 * (lo + hi));
+}
+
+typedef struct {
+    const void* pts; int64_t n; int d, dt, L;
+    int64_t* perm; int64_t* tmp; double* split; int64_t* loff;
+} sp_ctx;
+
+static void sp_rec(sp_ctx* C, int l, int64_t j, int64_t lo, int64_t hi, double* clo, double* chi) {
+    if (l == C->L) { C->loff[j] = lo; return; }
+    int c = l % C->d;
+    double s = sp_mid(clo[c], chi[c], C->dt);
+    C->split[((int64_t)1 << l) + j] = s;
+    /* stable partition of perm[lo, hi) by coordinate < s */
+    int64_t nl = 0, w = lo;
+    for (int64_t p = lo; p < hi; p++) {
+        double x = C->dt == OR_DT_INT ? (double)((const int32_t*)C->pts)[C->perm[p] * C->d + c]
+                                      : (double)((const float*)C->pts)[C->perm[p] * C->d + c];
+        if (x < s) C->perm[w++] = C->perm[p];
+        else C->tmp[nl++] = C->perm[p];
+    }
+    for (int64_t t = 0; t < nl; t++) C->perm[w + t] = C->tmp[t];
+    double save_lo = clo[c], save_hi = chi[c];
+    chi[c] = C->dt == OR_DT_INT ? s - 1 : s;
+    sp_rec(C, l + 1, 2 * j, lo, w, clo, chi);
+    chi[c] = save_hi;
+    clo[c] = s;
+    sp_rec(C, l + 1, 2 * j + 1, w, hi, clo, chi);
+    clo[c] = save_lo;
+}
+
+/* Builds the spatial-median tree.  Outputs: split_out [2^L] (node h at h,
+ * index 0 unused), perm_out [n] rows in leaf order, loff_out [2^L + 1] leaf
+ * offsets; *levels = L.  Arrays must hold 2^L(+1) entries: call with NULL
+ * outputs first to get L. */
+int or_kd_build_spatial(const void* pts, int64_t n, int d, int dt, int leaf, int* levels,
+                        double* split_out, int64_t* perm_out, int64_t* loff_out) {
+    if (d < 1 || d > 8 || leaf < 1 || n < 0 || !levels) return 1;
+    int L = tree_depth(n, leaf);
+    *levels = L;
+    if (!split_out || !perm_out || !loff_out) return 0;
+    sp_ctx C = {pts, n, d, dt, L, perm_out, (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1)),
+                split_out, loff_out};
+    for (int64_t i = 0; i < n; i++) perm_out[i] = i;
+    split_out[0] = 0.0;
+    double clo[8], chi[8];
+    for (int c = 0; c < d; c++) { clo[c] = INFINITY; chi[c] = -INFINITY; }
+    for (int64_t i = 0; i < n; i++)
+        for (int c = 0; c < d; c++) {
+            double x = dt == OR_DT_INT ? (double)((const int32_t*)pts)[i * d + c]
+                                       : (double)((const float*)pts)[i * d + c];
+            if (x < clo[c]) clo[c] = x;
+            if (x > chi[c]) chi[c] = x;
+        }
+    if (n == 0)
+        for (int c = 0; c < d; c++) { clo[c] = 0; chi[c] = 0; }
+    sp_rec(&C, 0, 0, 0, n, clo, chi);
+    loff_out[(int64_t)1 << L] = n;
+    free(C.tmp);
     return 0;
 }

@@ -94,3 +94,76 @@ def test_cfg1_depth_and_leaves():
     pts = datagen.uniform_int(10_000, 2, seed=1)
     t = check_tree(pts, 16)
     assert t.levels == 10
+
+
+# --- spatial-median tree (cell halving) -------------------------------------
+
+def test_spatial_hand_worked_int_and_float():
+    # 1-D int 0..9: root cell [0, 9] cut at floor(10/2) = 5; [0, 4] at
+    # floor(5/2) = 2; [5, 9] at floor(15/2) = 7.  Depth 2 for leaf 3.
+    pts = np.arange(10, dtype=np.int32).reshape(-1, 1)
+    L, s, perm, loff = oracle.spatial_tree(pts, leaf=3)
+    assert L == 2 and s[1:].tolist() == [5, 2, 7]
+    assert loff.tolist() == [0, 2, 5, 7, 10] and perm.tolist() == list(range(10))
+    # 1-D float {0, .25, .5, .75, 1}: [0, 1] at .5; [0, .5] at .25; [.5, 1] at .75
+    f = np.array([1.0, 0.5, 0.0, 0.75, 0.25], dtype=np.float32).reshape(-1, 1)
+    L, s, perm, loff = oracle.spatial_tree(f, leaf=2)
+    assert L == 2 and s[1:].tolist() == [0.5, 0.25, 0.75]
+    # stable: rows 0 (1.0) and 3 (0.75) keep their input order in the last leaf
+    assert loff.tolist() == [0, 1, 2, 3, 5] and perm.tolist() == [2, 4, 1, 0, 3]
+
+
+def test_spatial_full_grid_is_morton_order():
+    # all of {0..15}^2 with one point per leaf: the cells are dyadic, so the
+    # leaf of (x, y) interleaves the bits of x and y (x first, high bits first)
+    k = 4
+    xs, ys = np.meshgrid(np.arange(1 << k), np.arange(1 << k), indexing="ij")
+    pts = np.stack([xs.ravel(), ys.ravel()], axis=1).astype(np.int32)
+    rng = np.random.default_rng(0)
+    pts = pts[rng.permutation(len(pts))]
+    L, s, perm, loff = oracle.spatial_tree(pts, leaf=1)
+    assert L == 2 * k and np.all(np.diff(loff) == 1)
+
+    def morton(x, y):
+        m = 0
+        for b in range(k - 1, -1, -1):
+            m = (m << 2) | (((x >> b) & 1) << 1) | ((y >> b) & 1)
+        return m
+
+    want = np.argsort([morton(int(x), int(y)) for x, y in pts])
+    assert perm.tolist() == want.tolist()
+
+
+def test_spatial_identical_points_go_right():
+    pts = np.full((37, 3), 5, dtype=np.int32)
+    L, s, perm, loff = oracle.spatial_tree(pts, leaf=4)
+    sizes = np.diff(loff)
+    assert sizes[-1] == 37 and sizes[:-1].sum() == 0 and perm.tolist() == list(range(37))
+
+
+@pytest.mark.parametrize("d,leaf,dtype", [(2, 4, np.int32), (3, 8, np.float32), (5, 2, np.int32)])
+def test_spatial_invariants(d, leaf, dtype):
+    rng = np.random.default_rng(d * 10 + leaf)
+    n = 3000
+    if dtype == np.int32:
+        pts = rng.integers(-500, 500, (n, d)).astype(np.int32)
+        pts[::5] = pts[7]
+    else:
+        pts = (rng.standard_normal((n, d)) ** 3).astype(np.float32)
+    L, s, perm, loff = oracle.spatial_tree(pts, leaf=leaf)
+    assert L == oracle.tree_depth(n, leaf)
+    assert sorted(perm.tolist()) == list(range(n))
+    leaf_of = np.repeat(np.arange(1 << L), np.diff(loff))
+    # rows ascending inside every leaf (each side keeps the parent's order)
+    for j in range(1 << L):
+        rows = perm[loff[j]:loff[j + 1]]
+        assert np.all(np.diff(rows) > 0)
+    # every internal node separates: left coordinates < split <= right ones
+    P = pts[perm].astype(np.float64)
+    for h in range(1, 1 << L):
+        l = h.bit_length() - 1
+        j = h - (1 << l)
+        c = l % d
+        span = 1 << (L - l)
+        lo, mid, hi = loff[j * span], loff[j * span + span // 2], loff[(j + 1) * span]
+        assert np.all(P[lo:mid, c] < s[h]) and np.all(P[mid:hi, c] >= s[h])
