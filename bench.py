@@ -197,6 +197,38 @@ def form_graph(torch, pg, datagen, dev):
             "graph_ms": graph_ms, "edges_per_s": N * K / (graph_ms * 1e-3)}
 
 
+def form_spatial(torch, pg, datagen, dev):
+    """Spatial-median splits (cells cut at their midpoints, the object-median
+    tree's depth) on the headline points and on the 5-D clustered set: build
+    and k-NN beside the object-median numbers of the other forms."""
+    import numpy as np
+    out = {}
+    pts = datagen.uniform_int(N, D, seed=2)
+    x = torch.from_numpy(pts).to(dev)
+    holder = {}
+    b_ms = timed(torch, lambda: holder.__setitem__("t", pg.kdtree_build(x, leaf=LEAF, split="spatial")))
+    t = holder["t"]
+    idx = torch.empty((N, K), dtype=torch.int32, device=dev)
+    dist = torch.empty((N, K), dtype=torch.int64, device=dev)
+    k_ms = timed(torch, lambda: t.knn_all(K, out=(idx, dist)))
+    sizes = np.diff(t.offsets())
+    out["uniform_3d"] = {"workload": "3-D n=10M int32 uniform, k=10, leaf 16, all points",
+                         "build_ms": b_ms, "knn_ms": k_ms, "max_leaf": int(sizes.max()),
+                         "empty_leaves": int((sizes == 0).sum())}
+    del t, holder["t"], idx, dist, x
+    f, q = datagen.clustered(N, 5, seed=3, n_queries=1_000_000, query_seed=33)
+    xf = torch.from_numpy(f).to(dev)
+    qd = torch.from_numpy(q).to(dev)
+    b_ms = timed(torch, lambda: holder.__setitem__("t", pg.kdtree_build(xf, leaf=LEAF, split="spatial")))
+    t = holder["t"]
+    k_ms = timed(torch, lambda: t.knn(qd, 5))
+    sizes = np.diff(t.offsets())
+    out["clustered_5d"] = {"workload": "5-D n=10M clustered float32, 1M queries, k=5, leaf 16",
+                           "build_ms": b_ms, "knn_ms": k_ms, "max_leaf": int(sizes.max()),
+                           "empty_leaves": int((sizes == 0).sum())}
+    return out
+
+
 def form_clustered(torch, pg, datagen, dev):
     """5-D clustered float32 (1,000 Gaussian clusters, Zipf sizes), 1M queries
     from the same mixture, k = 5."""
@@ -398,7 +430,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms", default="all",
                     help="other forms to measure after the headline step: all, none, or a "
-                         "comma list of static_float,clustered,bdl,baselines,batch,range,graph")
+                         "comma list of static_float,clustered,spatial,bdl,baselines,batch,range,graph")
     ap.add_argument("--bdl-rounds", type=int, default=10)
     ap.add_argument("--loop-clouds", type=int, default=512,
                     help="clouds timed for the per-cloud comparison (projected to 4,096)")
@@ -510,7 +542,7 @@ def main():
     }
     del idx, dist, x
     torch.cuda.empty_cache()
-    forms = ["static_float", "clustered", "bdl", "baselines", "batch", "range", "graph"] \
+    forms = ["static_float", "clustered", "spatial", "bdl", "baselines", "batch", "range", "graph"] \
         if args.forms == "all" else \
         [f for f in args.forms.split(",") if f and f != "none"]
     out = {}
@@ -524,6 +556,8 @@ def main():
             out[f] = form_bdl(torch, pg, datagen, dev, args.bdl_rounds)
         elif f == "batch":
             out[f] = form_batch(torch, pg, datagen, dev, args.loop_clouds)
+        elif f == "spatial":
+            out[f] = form_spatial(torch, pg, datagen, dev)
         elif f == "baselines":
             out[f] = form_baselines(torch, pg, datagen, dev, args.bdl_rounds)
         elif f == "graph":

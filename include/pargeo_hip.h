@@ -76,6 +76,26 @@ const char* pg_version(void);
 pg_status pg_kdtree_build(const void* points, int64_t n, int32_t d, int32_t leaf,
                           int32_t dtype, void* stream, pg_tree** out);
 
+/* Builds a kd-tree by spatial-median splits (the alternative split rule
+ * Section 6.3 measures: a node's space is cut in half along a dimension).
+ * Readings: the root's space is the bounding box of the points; node
+ * (l, j) cuts its cell along dimension l mod d at the cell's midpoint s
+ * (int32: floor((lo + hi + 1) / 2), halves [lo, s-1] and [s, hi]; float32:
+ * the float nearest (lo + hi) / 2, halves [lo, s] and [s, hi]); points with
+ * coordinate < s go left.  The depth L and heap layout are those of
+ * pg_kdtree_build, so leaves hold varying numbers of points (possibly more
+ * than `leaf`, or none); pg_tree_offsets gives the leaf ranges.  The order
+ * of points inside a leaf is unspecified.  Every query call accepts the
+ * result (pg_knn, pg_knn_all, pg_knn_graph, pg_range_*).  Arguments and
+ * errors as pg_kdtree_build. */
+pg_status pg_kdtree_build_spatial(const void* points, int64_t n, int32_t d, int32_t leaf,
+                                  int32_t dtype, void* stream, pg_tree** out);
+
+/* Leaf offsets (host, [2^L + 1]): leaf j holds leaf-order positions
+ * [loff[j], loff[j+1]) (the closed form floor(j n / 2^L) for trees from
+ * pg_kdtree_build).  Synchronises for spatial-median trees. */
+pg_status pg_tree_offsets(const pg_tree* t, int64_t* loff_host, void* stream);
+
 /* k-NN of m query points over the tree (Appendix C, "Data-Parallel k-NN":
  * queries in parallel, each search serial).
  *   queries  : [m][d], same dtype as the tree, device

@@ -41,6 +41,8 @@ SIGNATURES = {
     "pg_last_error": (ctypes.c_char_p, []),
     "pg_version": (ctypes.c_char_p, []),
     "pg_kdtree_build": (i32, [vp, i64, i32, i32, i32, vp, ctypes.POINTER(vp)]),
+    "pg_kdtree_build_spatial": (i32, [vp, i64, i32, i32, i32, vp, ctypes.POINTER(vp)]),
+    "pg_tree_offsets": (i32, [vp, vp, vp]),
     "pg_knn": (i32, [vp, vp, i64, i32, vp, vp, vp]),
     "pg_knn_all": (i32, [vp, i32, vp, vp, vp]),
     "pg_knn_graph": (i32, [vp, i32, vp, vp, vp]),
@@ -261,6 +263,13 @@ class KdTree:
             check(st)
         return off, out[:total.value]
 
+    def offsets(self):
+        """Leaf offsets (NumPy int64 [2^L + 1])."""
+        import numpy as np
+        loff = np.empty((1 << self.levels) + 1, dtype=np.int64)
+        check(lib().pg_tree_offsets(self._h, ctypes.c_void_p(loff.ctypes.data), stream_ptr(self.device)))
+        return loff
+
     def export(self):
         """(split values of heap nodes 1..2^L-1, input rows in leaf order) as
         NumPy arrays."""
@@ -273,12 +282,21 @@ class KdTree:
         return splits, perm
 
 
-def kdtree_build(points: torch.Tensor, leaf: int = 16) -> KdTree:
+def kdtree_build(points: torch.Tensor, leaf: int = 16, split: str = "object") -> KdTree:
+    """Builds a kd-tree: ``split="object"`` (object median, every leaf at most
+    ``leaf`` points) or ``"spatial"`` (cells cut at their midpoints, the same
+    depth, leaf sizes vary)."""
     p = _points(points, "points")
     code = _dtype_code(p)
     h = ctypes.c_void_p()
-    check(lib().pg_kdtree_build(ctypes.c_void_p(p.data_ptr()), p.shape[0], p.shape[1], leaf, code,
-                                stream_ptr(p.device), ctypes.byref(h)))
+    if split == "object":
+        fn = lib().pg_kdtree_build
+    elif split == "spatial":
+        fn = lib().pg_kdtree_build_spatial
+    else:
+        raise ValueError("split must be 'object' or 'spatial'")
+    check(fn(ctypes.c_void_p(p.data_ptr()), p.shape[0], p.shape[1], leaf, code,
+             stream_ptr(p.device), ctypes.byref(h)))
     return KdTree(h, code, p.device)
 
 

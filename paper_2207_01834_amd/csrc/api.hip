@@ -55,6 +55,7 @@ static void tree_release(pg_tree* t) {
     dfree(t->split, t->stream);
     dfree(t->nbox, t->stream);
     dfree(t->rec, t->stream);
+    if (t->loff) dfree(t->loff, t->stream);
     delete t;
 }
 
@@ -84,6 +85,40 @@ pg_status pg_kdtree_build(const void* points, int64_t n, int32_t d, int32_t leaf
         return st;
     }
     *out = t;
+    return PG_OK;
+}
+
+pg_status pg_kdtree_build_spatial(const void* points, int64_t n, int32_t d, int32_t leaf,
+                                  int32_t dtype, void* stream, pg_tree** out) {
+    if (!out) return fail(PG_ERR_INVALID, "pg_kdtree_build_spatial: out is NULL");
+    if (d < 1 || d > 8) return fail(PG_ERR_INVALID, "pg_kdtree_build_spatial: d must be in [1, 8]");
+    if (leaf < 1 || leaf > 64) return fail(PG_ERR_INVALID, "pg_kdtree_build_spatial: leaf must be in [1, 64]");
+    if (n < 0 || n >= ((int64_t)1 << 31)) return fail(PG_ERR_INVALID, "pg_kdtree_build_spatial: n must be in [0, 2^31)");
+    if (dtype != PG_INT32 && dtype != PG_FLOAT32) return fail(PG_ERR_INVALID, "pg_kdtree_build_spatial: bad dtype");
+    if (n > 0 && !points) return fail(PG_ERR_INVALID, "pg_kdtree_build_spatial: points is NULL");
+    pg_tree* t = new (std::nothrow) pg_tree();
+    if (!t) return fail(PG_ERR_NOMEM, "pg_kdtree_build_spatial: host allocation failed");
+    pg_status st = build_tree_spatial(points, n, d, leaf, dtype, (hipStream_t)stream, t);
+    if (st != PG_OK) {
+        tree_release(t);
+        return st;
+    }
+    *out = t;
+    return PG_OK;
+}
+
+pg_status pg_tree_offsets(const pg_tree* t, int64_t* loff_host, void* stream) {
+    if (!t) return fail(PG_ERR_INVALID, "pg_tree_offsets: tree is NULL");
+    if (!loff_host) return fail(PG_ERR_INVALID, "pg_tree_offsets: loff_host is NULL");
+    const int64_t leaves = (int64_t)1 << t->L;
+    if (t->loff) {
+        hipStream_t s = (hipStream_t)stream;
+        PG_HIP(hipMemcpyAsync(loff_host, t->loff, sizeof(int64_t) * (leaves + 1),
+                              hipMemcpyDeviceToHost, s));
+        PG_HIP(hipStreamSynchronize(s));
+    } else {
+        for (int64_t j = 0; j <= leaves; j++) loff_host[j] = node_start(t->n, t->L, j);
+    }
     return PG_OK;
 }
 

@@ -331,24 +331,6 @@ __global__ void b2_place_kernel(TreeView tv, int fl, const uint32_t* __restrict_
     atomicOr(&alive2[p2 >> 5], 1u << (p2 & 31));
 }
 
-// Leaf boxes from the leaves' points (order-preserving keys; an empty leaf
-// gets the inverted box the build gives it).
-__global__ void b2_leaf_box_kernel(TreeView tv, int fl, uint32_t* __restrict__ bbox) {
-    const int64_t j = (int64_t)blockIdx.x * kNT + threadIdx.x;
-    if (j >= ((int64_t)1 << tv.L)) return;
-    const int d = tv.d;
-    for (int c = 0; c < d; c++) {
-        uint32_t mn = 0xffffffffu, mx = 0u;
-        for (int64_t p = tv.loff[j]; p < tv.loff[j + 1]; p++) {
-            const uint32_t kk = coord_to_key(tv.pts[(int64_t)c * tv.n + p], fl != 0);
-            mn = kk < mn ? kk : mn;
-            mx = kk > mx ? kk : mx;
-        }
-        bbox[j * 2 * d + c] = key_to_coord(mn, fl != 0);
-        bbox[j * 2 * d + d + c] = key_to_coord(mx, fl != 0);
-    }
-}
-
 __global__ void closed_offsets_kernel(int64_t n, int L, int64_t* __restrict__ loff) {
     const int64_t j = (int64_t)blockIdx.x * kNT + threadIdx.x;
     if (j <= ((int64_t)1 << L)) loff[j] = node_start(n, L, j);
@@ -556,22 +538,18 @@ static Forest make_forest(const Bdl& B) {
     return f;
 }
 
-// B2 baseline handle: the tree (with ids and liveness) and its leaf offsets.
+// B2 baseline handle: the tree (with ids, liveness and explicit leaf
+// offsets).
 struct B2 {
     int d = 0, leaf = 0, dtype = 0;
     BdlTree T;
-    int64_t* loff = nullptr;  // [2^L + 1]
     int64_t next_id = 0;
 };
 
 static Forest b2_forest(const B2& B) {
     Forest f{};
     f.count = 0;
-    if (B.T.t) {
-        TreeView tv = B.T.t->view();
-        tv.loff = B.loff;
-        f.s[f.count++] = ForestSlot{tv, B.T.ids, B.T.alive};
-    }
+    if (B.T.t) f.s[f.count++] = ForestSlot{B.T.t->view(), B.T.ids, B.T.alive};
     return f;
 }
 
@@ -584,8 +562,7 @@ static pg_status b2_insert(B2& B, const void* points, int64_t m, hipStream_t s) 
     if (n2 >= ((int64_t)1 << 31)) return fail(PG_ERR_UNSUPPORTED, "B2: more than 2^31 - 1 points");
     const int64_t leaves = (int64_t)1 << t->L;
     const int rw = record_words(d);
-    TreeView tv = t->view();
-    tv.loff = B.loff;
+    const TreeView tv = t->view();
     DevBuf leaf(s), rank(s), cnt(s), nstart(s);
     PG_TRY(leaf.alloc(sizeof(uint32_t) * m));
     PG_TRY(rank.alloc(sizeof(uint32_t) * m));
@@ -612,7 +589,7 @@ static pg_status b2_insert(B2& B, const void* points, int64_t m, hipStream_t s) 
         return st;
     }
     PG_HIP(hipMemsetAsync(alive2, 0, sizeof(uint32_t) * words, s));
-    hipLaunchKernelGGL(b2_offsets_kernel, dim3(cdiv(leaves + 1, kNT)), dim3(kNT), 0, s, B.loff,
+    hipLaunchKernelGGL(b2_offsets_kernel, dim3(cdiv(leaves + 1, kNT)), dim3(kNT), 0, s, t->loff,
                        nstart.as<uint32_t>(), leaves, m, loff2);
     PG_LAUNCH_CHECK();
     if (n > 0) {
@@ -626,7 +603,7 @@ static pg_status b2_insert(B2& B, const void* points, int64_t m, hipStream_t s) 
     PG_LAUNCH_CHECK();
     // swap in the grown arrays
     dfree(t->pts, s); dfree(t->rec, s); dfree(t->pidx, s); dfree(B.T.ids, s); dfree(B.T.alive, s);
-    dfree(B.loff, s);
+    dfree(t->loff, s);
     t->pts = pts2;
     t->rec = rec2;
     t->pidx = pidx2;
@@ -634,13 +611,8 @@ static pg_status b2_insert(B2& B, const void* points, int64_t m, hipStream_t s) 
     B.T.ids = ids2;
     B.T.alive = alive2;
     B.T.live += m;
-    B.loff = loff2;
-    TreeView tv2 = t->view();
-    tv2.loff = B.loff;
-    hipLaunchKernelGGL(b2_leaf_box_kernel, dim3(cdiv(leaves, kNT)), dim3(kNT), 0, s, tv2, fl,
-                       t->bbox);
-    PG_LAUNCH_CHECK();
-    return internal_boxes(t, s);
+    t->loff = loff2;
+    return offset_boxes(t, s);
 }
 
 // B1 baseline handle: one static tree over the live points, rebuilt whole
@@ -978,15 +950,14 @@ pg_status pg_b2_create(const void* points, int64_t n, int32_t d, int32_t leaf, i
     S.count = n;
     if (st == PG_OK) st = build_bdl_tree(shape, S, s, B.T);
     const int64_t leaves = B.T.t ? ((int64_t)1 << B.T.t->L) : 0;
-    if (st == PG_OK) st = dalloc(&B.loff, (size_t)leaves + 1, s);
+    if (st == PG_OK) st = dalloc(&B.T.t->loff, (size_t)leaves + 1, s);
     if (st == PG_OK) {
         hipLaunchKernelGGL(closed_offsets_kernel, dim3(cdiv(leaves + 1, kNT)), dim3(kNT), 0, s, n,
-                           B.T.t->L, B.loff);
+                           B.T.t->L, B.T.t->loff);
         if (hipGetLastError() != hipSuccess) st = fail(PG_ERR_DEVICE, "pg_b2_create: launch failed");
     }
     if (st != PG_OK) {
         free_tree(B.T);
-        if (B.loff) dfree(B.loff, s);
         delete h;
         return st;
     }
@@ -1070,10 +1041,6 @@ pg_status pg_b2_stats(const pg_b2* h, int64_t* stored, int32_t* levels) {
 
 void pg_b2_free(pg_b2* h) {
     if (!h) return;
-    if (h->b.T.t) {
-        hipStream_t s = h->b.T.t->stream;
-        if (h->b.loff) dfree(h->b.loff, s);
-    }
     free_tree(h->b.T);
     delete h;
 }

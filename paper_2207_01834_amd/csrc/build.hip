@@ -441,6 +441,34 @@ pg_status build_from_keys(uint32_t* kA, int32_t* iA, uint32_t* kB, int32_t* iB, 
     return internal_boxes(T, s);
 }
 
+namespace {
+// Leaf boxes of a tree with explicit leaf offsets, from its points
+// (order-preserving keys; an empty leaf gets the inverted box).
+__global__ void offset_leaf_box_kernel(TreeView tv, int fl, uint32_t* __restrict__ bbox) {
+    const int64_t j = (int64_t)blockIdx.x * kNT + threadIdx.x;
+    if (j >= ((int64_t)1 << tv.L)) return;
+    const int d = tv.d;
+    for (int c = 0; c < d; c++) {
+        uint32_t mn = 0xffffffffu, mx = 0u;
+        for (int64_t p = tv.loff[j]; p < tv.loff[j + 1]; p++) {
+            const uint32_t kk = coord_to_key(tv.pts[(int64_t)c * tv.n + p], fl != 0);
+            mn = kk < mn ? kk : mn;
+            mx = kk > mx ? kk : mx;
+        }
+        bbox[j * 2 * d + c] = key_to_coord(mn, fl != 0);
+        bbox[j * 2 * d + d + c] = key_to_coord(mx, fl != 0);
+    }
+}
+}  // namespace
+
+pg_status offset_boxes(pg_tree* T, hipStream_t s) {
+    const int64_t leaves = (int64_t)1 << T->L;
+    hipLaunchKernelGGL(offset_leaf_box_kernel, dim3(cdiv(leaves, kNT)), dim3(kNT), 0, s, T->view(),
+                       T->dtype == PG_FLOAT32 ? 1 : 0, T->bbox);
+    PG_LAUNCH_CHECK();
+    return internal_boxes(T, s);
+}
+
 pg_status internal_boxes(pg_tree* T, hipStream_t s) {
     // bottom-up, kBoxLevels levels per launch
     const int d = T->d;

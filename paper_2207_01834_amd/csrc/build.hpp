@@ -23,9 +23,16 @@ pg_status build_from_keys(uint32_t* kA, int32_t* iA, uint32_t* kB, int32_t* iB, 
 
 // Boxes of T's internal nodes from its leaf boxes (bottom-up).
 pg_status internal_boxes(pg_tree* T, hipStream_t s);
+// Every box of a tree with explicit leaf offsets (T->loff), from its points.
+pg_status offset_boxes(pg_tree* T, hipStream_t s);
 
 // Allocates T's arrays and builds it from device rows [n][d].
 pg_status build_tree(const void* points, int64_t n, int d, int leaf, int dtype, hipStream_t s,
                      pg_tree* T);
+
+// Allocates T's arrays and builds the spatial-median tree (explicit leaf
+// offsets in T->loff) from device rows [n][d].
+pg_status build_tree_spatial(const void* points, int64_t n, int d, int leaf, int dtype,
+                             hipStream_t s, pg_tree* T);
 
 }  // namespace pg

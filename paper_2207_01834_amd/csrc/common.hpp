@@ -132,7 +132,8 @@ struct pg_tree {
     uint32_t* nbox = nullptr;  // allocation of every node's box; bbox points into it
     uint32_t* bbox = nullptr;
     uint32_t* rec = nullptr;
+    int64_t* loff = nullptr;   // explicit leaf offsets [2^L + 1]; null: closed form
     pg::TreeView view() const {
-        return pg::TreeView{n, d, L, pg::record_words(d), pts, pidx, split, bbox, rec, nbox, nullptr};
+        return pg::TreeView{n, d, L, pg::record_words(d), pts, pidx, split, bbox, rec, nbox, loff};
     }
 };

@@ -64,6 +64,12 @@ __device__ inline void load_node_box(const TreeView& tv, uint32_t h, int d, T (&
     }
 }
 
+// Leaf-order position where node j of level l starts (explicit offsets when
+// the tree has them, else the closed form).
+__device__ inline int64_t node_begin(const TreeView& tv, int l, int64_t j) {
+    return tv.loff ? tv.loff[j << (tv.L - l)] : node_start(tv.n, l, j);
+}
+
 // Leaf records and rows are read this many at a time.
 constexpr int kGroup = kTreePad;
 
@@ -205,8 +211,8 @@ range_kernel(TreeView tv, const uint32_t* __restrict__ boxes, const int32_t* __r
         const int64_t j = 2 * ((int64_t)h - ((int64_t)1 << l));  // left child at level l+1
         if (l + 1 == tv.L) {
             if ((take0 | take1 | cut0 | cut1) != 0) {
-                const int64_t s0 = node_start(tv.n, l + 1, j), s1 = node_start(tv.n, l + 1, j + 1),
-                              s2 = node_start(tv.n, l + 1, j + 2);
+                const int64_t s0 = node_begin(tv, l + 1, j), s1 = node_begin(tv, l + 1, j + 1),
+                              s2 = node_begin(tv, l + 1, j + 2);
                 if (take0 != 0) take_range(s0, s1, take0);
                 if (cut0 != 0) scan_leaf(s0, s1, cut0);
                 if (take1 != 0) take_range(s1, s2, take1);
@@ -215,7 +221,7 @@ range_kernel(TreeView tv, const uint32_t* __restrict__ boxes, const int32_t* __r
             act = 0;
         } else {
             if (take0 != 0)
-                take_range(node_start(tv.n, l + 1, j), node_start(tv.n, l + 1, j + 1), take0);
+                take_range(node_begin(tv, l + 1, j), node_begin(tv, l + 1, j + 1), take0);
             if (cut0 != 0) {
                 if ((cut1 | take1) != 0) {  // the right child waits (same value in every lane)
                     stk[l][0] = cut1;
@@ -228,7 +234,7 @@ range_kernel(TreeView tv, const uint32_t* __restrict__ boxes, const int32_t* __r
                 continue;
             }
             if (take1 != 0)
-                take_range(node_start(tv.n, l + 1, j + 1), node_start(tv.n, l + 1, j + 2), take1);
+                take_range(node_begin(tv, l + 1, j + 1), node_begin(tv, l + 1, j + 2), take1);
             if (cut1 != 0) {
                 h = 2u * h + 1u;
                 l++;
@@ -247,7 +253,7 @@ range_kernel(TreeView tv, const uint32_t* __restrict__ boxes, const int32_t* __r
             const uint64_t ct = scalar_u64(stk[k][0]), tk = scalar_u64(stk[k][1]);
             if (tk != 0) {
                 const int64_t jr = (int64_t)h - ((int64_t)1 << l);
-                take_range(node_start(tv.n, l, jr), node_start(tv.n, l, jr + 1), tk);
+                take_range(node_begin(tv, l, jr), node_begin(tv, l, jr + 1), tk);
             }
             if (ct != 0) {
                 act = ct;

@@ -104,6 +104,17 @@ __device__ inline uint32_t leaf_of(int64_t n, int L, int64_t i) {
     return (uint32_t)((((uint64_t)(i + 1) << L) - 1) / (uint64_t)n);
 }
 
+// The same with explicit leaf offsets: the last leaf j with loff[j] <= i.
+__device__ inline uint32_t leaf_at(const int64_t* loff, int L, int64_t i) {
+    uint32_t lo = 0, hi = 1u << L;  // loff[lo] <= i < loff[hi]
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (loff[mid] <= i) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
 // k-NN walk of one query.  start: 0 = from the root; otherwise the heap index
 // of the leaf holding the query (all-points mode).
 //

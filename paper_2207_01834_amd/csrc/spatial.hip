@@ -1,0 +1,237 @@
+// Static kd-tree by spatial-median splits: the alternative to the object
+// median that Section 6.3 measures (a node's space is cut in half along a
+// dimension instead of at the median point).
+//
+// Readings (the paper gives the rule only in words): the space of the root
+// is the bounding box of the points; node (l, j) cuts its cell along
+// dimension l mod d at the cell's midpoint s; its points with coordinate < s
+// go left, the others right.  Midpoints: an int32 cell [lo, hi] is cut at
+// floor((lo + hi + 1) / 2) into [lo, s - 1] and [s, hi]; a float32 cell at
+// the float nearest (lo + hi) / 2 (sum in double) into [lo, s] and [s, hi].
+// The tree keeps the object-median tree's depth L = min{L : ceil(n/2^L) <=
+// leaf} and heap layout, so leaves hold varying numbers of points and their
+// ranges are explicit offsets.
+//
+// GPU form: since every cut depends only on the cell, the leaf of a point
+// follows from its own coordinates (L comparisons against midpoints computed
+// on the fly), so the build is one pass for leaf keys, a counting sort by
+// leaf and a scatter, instead of one partition pass per level.  The order of
+// points inside a leaf is the order the counting sort's atomics give (leaf
+// membership, splits and offsets are deterministic; results do not depend on
+// the order inside a leaf).
+#include "build.hpp"
+#include "scan.hpp"
+#include "wave.hpp"
+
+namespace pg {
+
+namespace {
+
+constexpr int kNT = 256;
+
+// Midpoint of cell [lo, hi] (coordinate values as doubles) and the cells of
+// the two halves.
+__device__ inline double cell_mid(double lo, double hi, bool fl) {
+    if (!fl) {
+        const int64_t t = (int64_t)lo + (int64_t)hi + 1;
+        return (double)(t >= 0 ? t / 2 : -((-t + 1) / 2));
+    }
+    return (double)(float)(0.5 * (lo + hi));
+}
+
+__device__ inline double coord_value(uint32_t bits, bool fl) {
+    return fl ? (double)__uint_as_float(bits) : (double)(int32_t)bits;
+}
+
+// Root cell: min / max key per dimension (box[c], box[d + c]).
+__global__ void __launch_bounds__(kNT)
+key_box_kernel(const uint32_t* __restrict__ keys, int64_t n, int d, uint32_t* __restrict__ box) {
+    for (int c = 0; c < d; c++) {
+        uint32_t mn = 0xffffffffu, mx = 0u;
+        for (int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kNT) {
+            const uint32_t k = keys[(int64_t)c * n + i];
+            mn = k < mn ? k : mn;
+            mx = k > mx ? k : mx;
+        }
+        mn = wave_min_u32(mn);
+        mx = wave_max_u32(mx);
+        if (lane_id() == 0) {
+            atomicMin(&box[c], mn);
+            atomicMax(&box[d + c], mx);
+        }
+    }
+}
+
+// Cell of the root from the key box, as coordinate values.
+__device__ inline void root_cell(const uint32_t* box, int d, bool fl, double (&lo)[8], double (&hi)[8]) {
+#pragma unroll
+    for (int c = 0; c < 8; c++) {
+        lo[c] = c < d ? coord_value(key_to_coord(box[c], fl), fl) : 0.0;
+        hi[c] = c < d ? coord_value(key_to_coord(box[d + c], fl), fl) : 0.0;
+    }
+}
+
+// Halves cell dimension c (runtime) toward `right`; returns the cut.
+__device__ inline double cut_cell(double (&lo)[8], double (&hi)[8], int c, bool right_of, bool fl,
+                                  bool go_right) {
+    double s = 0.0;
+#pragma unroll
+    for (int cc = 0; cc < 8; cc++) {
+        if (cc == c) {
+            s = cell_mid(lo[cc], hi[cc], fl);
+            if (right_of) {
+                if (go_right) lo[cc] = s;
+                else hi[cc] = fl ? s : s - 1.0;
+            }
+        }
+    }
+    return s;
+}
+
+// Leaf of every point (input order) and its rank among its leaf's points.
+__global__ void __launch_bounds__(kNT)
+spatial_leaf_kernel(const uint32_t* __restrict__ keys, int64_t n, int d, int L, int fl,
+                    const uint32_t* __restrict__ box, uint32_t* __restrict__ leaf,
+                    uint32_t* __restrict__ rank, uint32_t* __restrict__ cnt) {
+    const int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x;
+    if (i >= n) return;
+    double lo[8], hi[8], x[8];
+    root_cell(box, d, fl != 0, lo, hi);
+#pragma unroll
+    for (int c = 0; c < 8; c++) x[c] = c < d ? coord_value(key_to_coord(keys[(int64_t)c * n + i], fl != 0), fl != 0) : 0.0;
+    uint32_t j = 0;
+    int c = 0;
+    for (int l = 0; l < L; l++) {
+        double xc = x[0];
+#pragma unroll
+        for (int cc = 1; cc < 8; cc++) xc = cc == c ? x[cc] : xc;
+        double s = 0.0;
+#pragma unroll
+        for (int cc = 0; cc < 8; cc++)
+            if (cc == c) s = cell_mid(lo[cc], hi[cc], fl != 0);
+        const bool right = xc >= s;
+        cut_cell(lo, hi, c, true, fl != 0, right);
+        j = 2u * j + (right ? 1u : 0u);
+        c = c + 1 == d ? 0 : c + 1;
+    }
+    leaf[i] = j;
+    rank[i] = atomicAdd(&cnt[j], 1u);
+}
+
+// Split of internal node h: replay its path from the root, then cut.
+__global__ void __launch_bounds__(kNT)
+spatial_split_kernel(int d, int L, int fl, const uint32_t* __restrict__ box,
+                     uint32_t* __restrict__ split) {
+    const int64_t h = (int64_t)blockIdx.x * kNT + threadIdx.x;
+    if (h >= ((int64_t)1 << L)) return;
+    if (h == 0) {
+        split[0] = 0u;
+        return;
+    }
+    const int l = 63 - __builtin_clzll((unsigned long long)h);
+    double lo[8], hi[8];
+    root_cell(box, d, fl != 0, lo, hi);
+    int c = 0;
+    for (int t = 0; t < l; t++) {
+        const bool right = ((h >> (l - 1 - t)) & 1) != 0;
+        cut_cell(lo, hi, c, true, fl != 0, right);
+        c = c + 1 == d ? 0 : c + 1;
+    }
+    const double s = cut_cell(lo, hi, c, false, fl != 0, false);
+    split[h] = fl ? __float_as_uint((float)s) : (uint32_t)(int32_t)s;
+}
+
+__global__ void spatial_offsets_kernel(const uint32_t* __restrict__ start, int64_t leaves, int64_t n,
+                                       int64_t* __restrict__ loff) {
+    const int64_t j = (int64_t)blockIdx.x * kNT + threadIdx.x;
+    if (j < leaves) loff[j] = start[j];
+    else if (j == leaves) loff[j] = n;
+}
+
+// Point i to position start[leaf] + rank: coordinate planes, records, rows.
+__global__ void __launch_bounds__(kNT)
+spatial_scatter_kernel(const uint32_t* __restrict__ keys, const int32_t* __restrict__ idx, int64_t n,
+                       int d, int rw, int fl, const uint32_t* __restrict__ leaf,
+                       const uint32_t* __restrict__ rank, const uint32_t* __restrict__ start,
+                       uint32_t* __restrict__ pts, uint32_t* __restrict__ rec,
+                       int32_t* __restrict__ pidx) {
+    const int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x;
+    if (i >= n) return;
+    const int64_t p = (int64_t)start[leaf[i]] + rank[i];
+    for (int w = 0; w < rw; w++) {
+        uint32_t v = 0;
+        if (w < d) {
+            v = key_to_coord(keys[(int64_t)w * n + i], fl != 0);
+            pts[(int64_t)w * n + p] = v;
+        } else if (w == d) {
+            v = (uint32_t)idx[i];
+        }
+        rec[p * rw + w] = v;
+    }
+    pidx[p] = idx[i];
+}
+
+}  // namespace
+
+pg_status build_tree_spatial(const void* points, int64_t n, int d, int leaf, int dtype,
+                             hipStream_t s, pg_tree* T) {
+    const bool fl = dtype == PG_FLOAT32;
+    T->n = n;
+    T->d = d;
+    T->leaf = leaf;
+    T->dtype = dtype;
+    T->stream = s;
+    T->L = tree_levels(n, leaf);
+    const int L = T->L;
+    const int64_t leaves = (int64_t)1 << L;
+    const int64_t nn = n > 0 ? n : 1;
+    const int rw = record_words(d);
+    PG_TRY(dalloc(&T->pts, (size_t)d * nn, s));
+    PG_TRY(dalloc(&T->pidx, (size_t)nn + kTreePad, s));
+    PG_TRY(dalloc(&T->split, (size_t)leaves, s));
+    PG_TRY(dalloc(&T->nbox, (size_t)leaves * 2 * 2 * d, s));
+    T->bbox = T->nbox + (size_t)leaves * 2 * d;
+    PG_TRY(dalloc(&T->rec, ((size_t)nn + kTreePad) * rw, s));
+    PG_TRY(dalloc(&T->loff, (size_t)leaves + 1, s));
+    if (n == 0) {
+        PG_HIP(hipMemsetAsync(T->loff, 0, sizeof(int64_t) * (leaves + 1), s));
+        PG_HIP(hipMemsetAsync(T->split, 0, sizeof(uint32_t) * leaves, s));
+        return offset_boxes(T, s);
+    }
+    DevBuf keys(s), idx(s), box(s), lf(s), rk(s), cnt(s), start(s);
+    PG_TRY(keys.alloc(sizeof(uint32_t) * (size_t)d * n));
+    PG_TRY(idx.alloc(sizeof(int32_t) * (size_t)n));
+    uint32_t vary[8] = {0}, keybase[8] = {0};
+    PG_TRY(ingest_points(points, n, d, fl, keys.as<uint32_t>(), idx.as<int32_t>(), vary, keybase, s));
+    PG_TRY(box.alloc(sizeof(uint32_t) * 2 * d));
+    PG_HIP(hipMemsetAsync(box.p, 0xff, sizeof(uint32_t) * d, s));
+    PG_HIP(hipMemsetAsync(box.as<uint32_t>() + d, 0, sizeof(uint32_t) * d, s));
+    const unsigned grid = cdiv(n, kNT) < 1024u ? cdiv(n, kNT) : 1024u;
+    hipLaunchKernelGGL(key_box_kernel, dim3(grid), dim3(kNT), 0, s, keys.as<uint32_t>(), n, d,
+                       box.as<uint32_t>());
+    PG_LAUNCH_CHECK();
+    PG_TRY(lf.alloc(sizeof(uint32_t) * n));
+    PG_TRY(rk.alloc(sizeof(uint32_t) * n));
+    PG_TRY(cnt.alloc(sizeof(uint32_t) * leaves));
+    PG_TRY(start.alloc(sizeof(uint32_t) * leaves));
+    PG_HIP(hipMemsetAsync(cnt.p, 0, sizeof(uint32_t) * leaves, s));
+    hipLaunchKernelGGL(spatial_leaf_kernel, dim3(cdiv(n, kNT)), dim3(kNT), 0, s,
+                       keys.as<uint32_t>(), n, d, L, fl ? 1 : 0, box.as<uint32_t>(),
+                       lf.as<uint32_t>(), rk.as<uint32_t>(), cnt.as<uint32_t>());
+    PG_LAUNCH_CHECK();
+    PG_TRY(exclusive_scan_u32(cnt.as<uint32_t>(), start.as<uint32_t>(), leaves, nullptr, s));
+    hipLaunchKernelGGL(spatial_offsets_kernel, dim3(cdiv(leaves + 1, kNT)), dim3(kNT), 0, s,
+                       start.as<uint32_t>(), leaves, n, T->loff);
+    PG_LAUNCH_CHECK();
+    hipLaunchKernelGGL(spatial_scatter_kernel, dim3(cdiv(n, kNT)), dim3(kNT), 0, s,
+                       keys.as<uint32_t>(), idx.as<int32_t>(), n, d, rw, fl ? 1 : 0,
+                       lf.as<uint32_t>(), rk.as<uint32_t>(), start.as<uint32_t>(), T->pts, T->rec,
+                       T->pidx);
+    PG_LAUNCH_CHECK();
+    hipLaunchKernelGGL(spatial_split_kernel, dim3(cdiv(leaves, kNT)), dim3(kNT), 0, s, d, L,
+                       fl ? 1 : 0, box.as<uint32_t>(), T->split);
+    PG_LAUNCH_CHECK();
+    return offset_boxes(T, s);
+}
+
+}  // namespace pg

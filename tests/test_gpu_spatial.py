@@ -1,0 +1,126 @@
+"""GPU parity of the spatial-median kd-tree (pg_kdtree_build_spatial) against
+the oracle's: split values, leaf offsets and leaf membership identical; k-NN
+(queries, all points, graph) and range search on it exact against the
+definitions."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2207_01834_amd import datagen
+from parity import assert_float_close, assert_int_equal, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pg(dev):
+    import paper_2207_01834_amd._binding as b
+    b.lib()
+    return b
+
+
+def to_dev(a, dev):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def host(*ts):
+    import torch
+    torch.cuda.synchronize()
+    return [t.cpu().numpy() for t in ts]
+
+
+def membership(perm, loff):
+    leaf = np.repeat(np.arange(len(loff) - 1, dtype=np.int64), np.diff(loff))
+    return np.sort(leaf * max(len(perm), 1) + perm.astype(np.int64))
+
+
+def check_tree(pg, dev, pts, leaf):
+    t = pg.kdtree_build(to_dev(pts, dev), leaf=leaf, split="spatial")
+    L, s, perm, loff = oracle.spatial_tree(pts, leaf=leaf)
+    assert t.levels == L
+    gs, gperm = t.export()
+    gloff = t.offsets()
+    assert np.array_equal(gloff, loff), "leaf offsets differ"
+    assert np.array_equal(gs.astype(np.float64), s[1:]), "split values differ"
+    assert np.array_equal(membership(gperm, gloff), membership(perm, loff)), "leaf membership differs"
+    return t
+
+
+def check_knn(t, pts, q, k, dev):
+    if q is None:
+        gi, gd = host(*t.knn_all(k))
+        q = pts
+    else:
+        gi, gd = host(*t.knn(to_dev(q, dev), k))
+    oi, od = oracle.knn_brute(pts, q, k, nthreads=8)
+    if pts.dtype == np.int32:
+        assert_int_equal(gi, gd, oi, od)
+    else:
+        assert_float_close(gi, gd, oi, od, pts, q)
+
+
+@pytest.mark.parametrize("n,d,leaf,dtype,span", [
+    (20_000, 2, 16, np.int32, 1 << 20), (9_000, 3, 8, np.float32, 0), (5_000, 5, 16, np.int32, 1 << 12),
+    (3_000, 1, 4, np.int32, 100), (2_000, 8, 2, np.float32, 0), (4_000, 3, 1, np.int32, 6),
+])
+def test_spatial_tree_and_knn(pg, dev, n, d, leaf, dtype, span):
+    say(f"spatial n={n} d={d} leaf={leaf} {np.dtype(dtype).name}")
+    rng = np.random.default_rng(n + d + leaf)
+    if dtype == np.int32:
+        pts = rng.integers(-span // 2, span // 2 + 1, (n, d)).astype(np.int32)
+    else:
+        pts = (rng.standard_normal((n, d)) ** 3).astype(np.float32)  # skewed: uneven leaves
+    t = check_tree(pg, dev, pts, leaf)
+    check_knn(t, pts, None, 10, dev)
+    q = pts[rng.integers(0, n, 5_000)] + (1 if dtype == np.int32 else np.float32(0.01))
+    check_knn(t, pts, q.astype(dtype), 7, dev)
+    gi, gd = host(*t.knn_graph(5))
+    oi, od = oracle.knn_graph_brute(pts, 5, nthreads=8)
+    if dtype == np.int32:
+        assert_int_equal(gi, gd, oi, od)
+    else:
+        assert_float_close(gi, gd, oi, od, pts, pts)
+
+
+def test_spatial_clustered_and_duplicates(pg, dev):
+    f, q = datagen.clustered(30_000, 5, seed=3, n_queries=2_000, query_seed=33)
+    t = check_tree(pg, dev, f, 16)
+    sizes = np.diff(t.offsets())
+    assert sizes.max() > 16  # spatial cuts leave dense leaves
+    check_knn(t, f, q, 5, dev)
+    same = np.full((500, 2), 3, dtype=np.int32)
+    t = check_tree(pg, dev, same, 4)
+    check_knn(t, same, None, 3, dev)
+
+
+def test_spatial_small_and_empty(pg, dev):
+    for n in (0, 1, 2, 5):
+        pts = np.arange(2 * n, dtype=np.int32).reshape(n, 2)
+        t = check_tree(pg, dev, pts, 1)
+        if n:
+            check_knn(t, pts, None, 3, dev)
+
+
+def test_spatial_range(pg, dev):
+    pts = datagen.uniform_int(20_000, 2, seed=5, bits=12)
+    t = pg.kdtree_build(to_dev(pts, dev), leaf=16, split="spatial")
+    boxes = datagen.range_boxes(pts, 300, seed=6, m=3_000)
+    off, rows = t.range_search(to_dev(boxes, dev))
+    off, rows = host(off, rows)
+    oc, oo, oi = oracle.range_brute(pts, boxes)
+    assert np.array_equal(off, oo)
+    for i in range(0, 3_000, 7):
+        assert np.array_equal(np.sort(rows[off[i]:off[i + 1]].astype(np.int64)), oi[oo[i]:oo[i + 1]])
+
+
+def test_spatial_full_size(pg, dev):
+    """The headline points (10M 3-D int uniform, leaf 16) with spatial-median
+    splits: the whole tree against the oracle's, sampled all-points rows."""
+    pts = datagen.uniform_int(10_000_000, 3, seed=2)
+    say("spatial 10M: build")
+    t = check_tree(pg, dev, pts, 16)
+    gi, gd = host(*t.knn_all(10))
+    rows = np.random.default_rng(4).choice(len(pts), 300, replace=False)
+    oi, od = oracle.knn_brute(pts, pts[rows], 10, nthreads=16)
+    assert_int_equal(gi[rows], gd[rows], oi, od)
