@@ -442,29 +442,75 @@ pg_status build_from_keys(uint32_t* kA, int32_t* iA, uint32_t* kB, int32_t* iB, 
 }
 
 namespace {
-// Leaf boxes of a tree with explicit leaf offsets, from its points
-// (order-preserving keys; an empty leaf gets the inverted box).
-__global__ void offset_leaf_box_kernel(TreeView tv, int fl, uint32_t* __restrict__ bbox) {
-    const int64_t j = (int64_t)blockIdx.x * kNT + threadIdx.x;
-    if (j >= ((int64_t)1 << tv.L)) return;
+// Leaf boxes of a tree with explicit leaf offsets, from its points, as
+// order-preserving keys first (min starts at all ones, max at zero, so an
+// empty leaf keeps the inverted box), then converted to coordinates.
+__global__ void box_keys_init_kernel(uint32_t* __restrict__ box, int64_t leaves, int d) {
+    const int64_t e = (int64_t)blockIdx.x * kNT + threadIdx.x;
+    if (e < leaves * 2 * d) box[e] = (e % (2 * d)) < d ? 0xffffffffu : 0u;
+}
+
+// One lane per leaf-order position.  Positions of a wave are consecutive,
+// so lanes of one leaf are contiguous: a segmented min/max toward the first
+// lane of each leaf, then one atomic per (leaf, dimension) and wave.
+__global__ void __launch_bounds__(kNT)
+offset_leaf_box_kernel(TreeView tv, int fl, uint32_t* __restrict__ box) {
+    const int64_t p = (int64_t)blockIdx.x * kNT + threadIdx.x;
+    const bool valid = p < tv.n;
+    if (__ballot(valid) == 0) return;
+    uint32_t j = 0xffffffffu;
+    if (valid) {
+        uint32_t lo = 0, hi = 1u << tv.L;  // loff[lo] <= p < loff[hi]
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (tv.loff[mid] <= p) lo = mid;
+            else hi = mid;
+        }
+        j = lo;
+    }
+    const int lane = lane_id();
+    const uint32_t jprev = __shfl_up(j, 1, kWave);
+    const bool head = valid && (lane == 0 || jprev != j);
     const int d = tv.d;
     for (int c = 0; c < d; c++) {
-        uint32_t mn = 0xffffffffu, mx = 0u;
-        for (int64_t p = tv.loff[j]; p < tv.loff[j + 1]; p++) {
-            const uint32_t kk = coord_to_key(tv.pts[(int64_t)c * tv.n + p], fl != 0);
-            mn = kk < mn ? kk : mn;
-            mx = kk > mx ? kk : mx;
+        const uint32_t k = valid ? coord_to_key(tv.pts[(int64_t)c * tv.n + p], fl != 0) : 0u;
+        uint32_t mn = valid ? k : 0xffffffffu, mx = k;
+#pragma unroll
+        for (int off = 1; off < kWave; off <<= 1) {
+            const uint32_t omn = __shfl_down(mn, off, kWave), omx = __shfl_down(mx, off, kWave);
+            const uint32_t oj = __shfl_down(j, off, kWave);
+            if (lane + off < kWave && oj == j) {
+                mn = omn < mn ? omn : mn;
+                mx = omx > mx ? omx : mx;
+            }
         }
-        bbox[j * 2 * d + c] = key_to_coord(mn, fl != 0);
-        bbox[j * 2 * d + d + c] = key_to_coord(mx, fl != 0);
+        if (head) {
+            atomicMin(&box[(int64_t)j * 2 * d + c], mn);
+            atomicMax(&box[(int64_t)j * 2 * d + d + c], mx);
+        }
     }
+}
+
+__global__ void box_keys_to_coords_kernel(uint32_t* __restrict__ box, int64_t count, int fl) {
+    const int64_t e = (int64_t)blockIdx.x * kNT + threadIdx.x;
+    if (e < count) box[e] = key_to_coord(box[e], fl != 0);
 }
 }  // namespace
 
 pg_status offset_boxes(pg_tree* T, hipStream_t s) {
     const int64_t leaves = (int64_t)1 << T->L;
-    hipLaunchKernelGGL(offset_leaf_box_kernel, dim3(cdiv(leaves, kNT)), dim3(kNT), 0, s, T->view(),
-                       T->dtype == PG_FLOAT32 ? 1 : 0, T->bbox);
+    const int64_t count = leaves * 2 * T->d;
+    const int fl = T->dtype == PG_FLOAT32 ? 1 : 0;
+    hipLaunchKernelGGL(box_keys_init_kernel, dim3(cdiv(count, kNT)), dim3(kNT), 0, s, T->bbox,
+                       leaves, T->d);
+    PG_LAUNCH_CHECK();
+    if (T->n > 0) {
+        hipLaunchKernelGGL(offset_leaf_box_kernel, dim3(cdiv(T->n, kNT)), dim3(kNT), 0, s,
+                           T->view(), fl, T->bbox);
+        PG_LAUNCH_CHECK();
+    }
+    hipLaunchKernelGGL(box_keys_to_coords_kernel, dim3(cdiv(count, kNT)), dim3(kNT), 0, s, T->bbox,
+                       count, fl);
     PG_LAUNCH_CHECK();
     return internal_boxes(T, s);
 }
