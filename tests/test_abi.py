@@ -72,3 +72,45 @@ def test_knn_argument_errors(L):
     assert L.pg_tree_info(None, None, None, None, None, None) == 1
     assert L.pg_tree_export(None, None, None, None) == 1
     L.pg_tree_free(None)  # no-op
+
+
+def test_range_graph_spatial_argument_errors(L):
+    fake = ctypes.c_void_p(0x1000)
+    out = ctypes.c_void_p()
+    assert L.pg_range_count(None, fake, 1, fake, None, None, None) == 1
+    assert "tree is NULL" in _err(L)
+    assert L.pg_range_report(None, fake, 1, fake, fake, 1, None) == 1
+    assert L.pg_range_search(None, fake, 1, None, fake, fake, 1, None, None) == 1
+    assert L.pg_knn_graph(None, 3, fake, fake, None) == 1
+    assert L.pg_tree_offsets(None, fake, None) == 1
+    st = L.pg_kdtree_build_spatial(fake, 10, 0, 16, 0, None, ctypes.byref(out))
+    assert st == 1 and "d must be" in _err(L)
+    st = L.pg_kdtree_build_spatial(None, 10, 3, 16, 0, None, ctypes.byref(out))
+    assert st == 1 and "points is NULL" in _err(L)
+
+
+def test_baseline_argument_errors(L):
+    fake = ctypes.c_void_p(0x1000)
+    out = ctypes.c_void_p()
+    assert L.pg_b1_create(0, 0, 16, ctypes.byref(out)) == 1 and "d must be" in _err(L)
+    assert L.pg_b1_create(3, 7, 16, ctypes.byref(out)) == 1 and "bad dtype" in _err(L)
+    assert L.pg_b1_insert(None, fake, 1, None, None) == 1 and "handle is NULL" in _err(L)
+    assert L.pg_b1_erase(None, fake, 1, None, None) == 1
+    assert L.pg_b1_knn(None, fake, 1, 3, fake, fake, None) == 1
+    assert L.pg_b1_size(None) == -1
+    L.pg_b1_free(None)
+    assert L.pg_b2_create(fake, 10, 3, 0, 0, None, ctypes.byref(out)) == 1 and "leaf must be" in _err(L)
+    assert L.pg_b2_create(fake, -5, 3, 16, 0, None, ctypes.byref(out)) == 1 and "n must be" in _err(L)
+    assert L.pg_b2_insert(None, fake, 1, None, None) == 1
+    assert L.pg_b2_erase(None, fake, 1, None, None) == 1
+    assert L.pg_b2_knn(None, fake, 1, 65, fake, fake, None) == 1
+    assert L.pg_b2_stats(None, None, None) == 1
+    assert L.pg_b2_size(None) == -1
+    L.pg_b2_free(None)
+    # a host-only B1 handle: argument checks on it need no device
+    h = ctypes.c_void_p()
+    assert L.pg_b1_create(3, 0, 16, ctypes.byref(h)) == 0
+    assert L.pg_b1_insert(h, None, 5, None, None) == 1 and "points is NULL" in _err(L)
+    assert L.pg_b1_knn(h, fake, 1, 0, fake, fake, None) == 1 and "k must be" in _err(L)
+    assert L.pg_b1_size(h) == 0
+    L.pg_b1_free(h)
