@@ -236,6 +236,15 @@ pg_status order_queries(const TreeView& tv, bool fl, const void* queries, int64_
 pg_status knn_static(const pg_tree* t, const void* queries, int64_t m, int k, bool all_points,
                      int32_t* out_idx, void* out_dist, hipStream_t s, bool no_self = false);
 
+// The static-tree k-NN launch for one coordinate type (order: the query
+// permutation or null; no_self: all-points without each point's own row).
+pg_status knn_static_int(const pg_tree* t, const void* queries, const int32_t* order, int64_t m,
+                         int k, bool all, int32_t* out_idx, void* out_dist, hipStream_t s,
+                         bool no_self);
+pg_status knn_static_float(const pg_tree* t, const void* queries, const int32_t* order, int64_t m,
+                           int k, bool all, int32_t* out_idx, void* out_dist, hipStream_t s,
+                           bool no_self);
+
 // Validates query coordinates (range / finite); synchronises.
 pg_status check_queries(const void* q, int64_t m, int d, bool fl, hipStream_t s);
 

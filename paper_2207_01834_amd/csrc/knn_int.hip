@@ -1,0 +1,19 @@
+// Static-tree k-NN kernels instantiated for int32_t coordinates (a translation
+// unit per coordinate type keeps the build parallel).
+#include "knn.hpp"
+#include "knn_static.hpp"
+
+namespace pg {
+
+pg_status knn_static_int(const pg_tree* t, const void* queries, const int32_t* o, int64_t m, int k,
+                 bool all, int32_t* out_idx, void* out_dist, hipStream_t s, bool no_self) {
+    using namespace knn_detail;
+    if (t->loff) {
+        if (no_self) return dispatch_d<int32_t, true, true>(t, nullptr, nullptr, m, k, true, out_idx, out_dist, s);
+        return dispatch_d<int32_t, false, true>(t, queries, o, m, k, all, out_idx, out_dist, s);
+    }
+    if (no_self) return dispatch_d<int32_t, true, false>(t, nullptr, nullptr, m, k, true, out_idx, out_dist, s);
+    return dispatch_d<int32_t, false, false>(t, queries, o, m, k, all, out_idx, out_dist, s);
+}
+
+}  // namespace pg

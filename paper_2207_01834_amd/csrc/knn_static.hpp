@@ -1,0 +1,155 @@
+// Static-tree k-NN kernels and their launch dispatch (one query per lane,
+// Appendix C "Data-Parallel k-NN"), instantiated per coordinate type in
+// knn_int.hip and knn_float.hip.  In all-points mode lane i takes the tree's
+// own leaf-order point i, so the lanes of a wave hold neighbouring points and
+// walk nearly the same nodes; the result row is the point's input row.
+#pragma once
+
+#include "scan.hpp"
+#include "search.hpp"
+#include "wave.hpp"
+
+namespace pg {
+namespace knn_detail {
+
+constexpr int kNT = 256;
+
+template <typename T, int MD>
+__device__ inline void load_query(const TreeView& tv, const uint32_t* queries, int all, int64_t i,
+                                  int d, T (&q)[MD]) {
+#pragma unroll
+    for (int c = 0; c < MD; c++) {
+        uint32_t b = 0;
+        if (MD < 8 || c < d) b = all ? tv.pts[(int64_t)c * tv.n + i] : queries[i * d + c];
+        q[c] = Metric<T>::load(b);
+    }
+}
+
+// Searches with packed (distance, id) keys.  A query whose k-th distance
+// reached the packed range's limit (int32 coordinates: 2^(64-B) - 1, or fewer
+// than k points) is appended to `redo` for knn_redo_kernel instead of written.
+// NS (all-points only): the query's own point is not a candidate (k-NN graph).
+// LOFF: the tree's leaf ranges are explicit offsets (spatial-median trees).
+template <typename T, int MD, int KT, bool EX, bool NS, bool LOFF>
+__global__ void __launch_bounds__(kNT)
+knn_static_kernel(TreeView tv, const uint32_t* __restrict__ queries,
+                  const int32_t* __restrict__ order, int64_t m, int k, int all, int idbits,
+                  int32_t* __restrict__ out_idx, typename Metric<T>::D* __restrict__ out_dist,
+                  int32_t* __restrict__ redo, uint32_t* __restrict__ nredo) {
+    const int d = MD < 8 ? MD : tv.d;
+    const int64_t i0 = xcd_block() * kNT + threadIdx.x;
+    if (i0 >= m) return;
+    // queries are taken in leaf order when an order is given (neighbouring
+    // lanes then walk nearly the same nodes); results go to the query's row
+    const int64_t i = order ? (int64_t)order[i0] : i0;
+    T q[MD];
+    load_query<T, MD>(tv, queries, all, i, d, q);
+    using KL = PackedList<T, KT, EX>;
+    KL kl;
+    kl.init(idbits);
+    const uint32_t start =
+        all ? (1u << tv.L) + (LOFF ? leaf_at(tv.loff, tv.L, i) : leaf_of(tv.n, tv.L, i)) : 0u;
+    if constexpr (NS) kd_search<T, MD, KL, OtherIds, LOFF>(tv, OtherIds{i}, q, d, kl, k, start);
+    else kd_search<T, MD, KL, PlainIds, LOFF>(tv, PlainIds{}, q, d, kl, k, start);
+    if (kl.needs_redo()) {
+        redo[atomicAdd(nredo, 1u)] = (int32_t)i;
+        return;
+    }
+    const int64_t row = all ? (int64_t)tv.pidx[i] : i;
+#pragma unroll
+    for (int s = 0; s < KT; s++) {
+        if (EX || s < k) {
+            out_idx[row * k + s] = kl.id_of(kl.key[s]);
+            out_dist[row * k + s] = kl.dist_of(kl.key[s]);
+        }
+    }
+}
+
+// The queries knn_static_kernel handed over, searched with exact
+// (distance, id) pairs.
+template <typename T, int MD, int KT, bool EX, bool NS, bool LOFF>
+__global__ void __launch_bounds__(kNT)
+knn_redo_kernel(TreeView tv, const uint32_t* __restrict__ queries, int k, int all,
+                const int32_t* __restrict__ redo, const uint32_t* __restrict__ nredo,
+                int32_t* __restrict__ out_idx, typename Metric<T>::D* __restrict__ out_dist) {
+    using M = Metric<T>;
+    const int d = MD < 8 ? MD : tv.d;
+    const int64_t cnt = *nredo;
+    for (int64_t r = (int64_t)blockIdx.x * kNT + threadIdx.x; r < cnt; r += (int64_t)gridDim.x * kNT) {
+        const int64_t i = redo[r];
+        T q[MD];
+        load_query<T, MD>(tv, queries, all, i, d, q);
+        using KL = KList<typename M::D, int32_t, KT, EX>;
+        KL kl;
+        kl.init(M::inf(), INT32_MAX);
+        const uint32_t start =
+            all ? (1u << tv.L) + (LOFF ? leaf_at(tv.loff, tv.L, i) : leaf_of(tv.n, tv.L, i)) : 0u;
+        if constexpr (NS) kd_search<T, MD, KL, OtherIds, LOFF>(tv, OtherIds{i}, q, d, kl, k, start);
+        else kd_search<T, MD, KL, PlainIds, LOFF>(tv, PlainIds{}, q, d, kl, k, start);
+        const int64_t row = all ? (int64_t)tv.pidx[i] : i;
+#pragma unroll
+        for (int s = 0; s < KT; s++) {
+            if (EX || s < k) {
+                out_idx[row * k + s] = kl.id[s] == INT32_MAX ? -1 : kl.id[s];
+                out_dist[row * k + s] = kl.d[s];
+            }
+        }
+    }
+}
+
+constexpr unsigned kRedoBlocks = 512;
+
+template <typename T, int MD, int KT, bool EX, bool NS, bool LOFF>
+pg_status launch_static(const pg_tree* t, const void* queries, const int32_t* order, int64_t m,
+                        int k, bool all, int32_t* out_idx, void* out_dist, hipStream_t s) {
+    using DT = typename Metric<T>::D;
+    constexpr bool exact = PackedList<T, KT, EX>::kFloat;  // float keys: no redo pass
+    DevBuf redo(s), nredo(s);
+    if (!exact) {
+        PG_TRY(redo.alloc(sizeof(int32_t) * m));
+        PG_TRY(nredo.alloc(sizeof(uint32_t)));
+        PG_HIP(hipMemsetAsync(nredo.p, 0, sizeof(uint32_t), s));
+    }
+    hipLaunchKernelGGL((knn_static_kernel<T, MD, KT, EX, NS, LOFF>), dim3(grid_for_xcd(cdiv(m, kNT))),
+                       dim3(kNT), 0, s, t->view(), (const uint32_t*)queries, order, m, k,
+                       all ? 1 : 0, id_bits(t->n), out_idx, (DT*)out_dist, redo.as<int32_t>(),
+                       nredo.as<uint32_t>());
+    PG_LAUNCH_CHECK();
+    if (!exact) {
+        hipLaunchKernelGGL((knn_redo_kernel<T, MD, KT, EX, NS, LOFF>), dim3(kRedoBlocks), dim3(kNT), 0, s,
+                           t->view(), (const uint32_t*)queries, k, all ? 1 : 0,
+                           redo.as<int32_t>(), nredo.as<uint32_t>(), out_idx, (DT*)out_dist);
+        PG_LAUNCH_CHECK();
+    }
+    return PG_OK;
+}
+
+// k-list capacities: exact lists for the common k = 5, 10, 16, otherwise the
+// next power of two with uniform guards.
+template <typename T, int MD, bool NS, bool LOFF>
+pg_status dispatch_k(const pg_tree* t, const void* q, const int32_t* o, int64_t m, int k, bool all,
+                     int32_t* oi, void* od, hipStream_t s) {
+    if (k == 5) return launch_static<T, MD, 5, true, NS, LOFF>(t, q, o, m, k, all, oi, od, s);
+    if (k == 10) return launch_static<T, MD, 10, true, NS, LOFF>(t, q, o, m, k, all, oi, od, s);
+    if (k == 16) return launch_static<T, MD, 16, true, NS, LOFF>(t, q, o, m, k, all, oi, od, s);
+    if (k <= 2) return launch_static<T, MD, 2, false, NS, LOFF>(t, q, o, m, k, all, oi, od, s);
+    if (k <= 4) return launch_static<T, MD, 4, false, NS, LOFF>(t, q, o, m, k, all, oi, od, s);
+    if (k <= 8) return launch_static<T, MD, 8, false, NS, LOFF>(t, q, o, m, k, all, oi, od, s);
+    if (k <= 16) return launch_static<T, MD, 16, false, NS, LOFF>(t, q, o, m, k, all, oi, od, s);
+    if (k <= 32) return launch_static<T, MD, 32, false, NS, LOFF>(t, q, o, m, k, all, oi, od, s);
+    return launch_static<T, MD, 64, false, NS, LOFF>(t, q, o, m, k, all, oi, od, s);
+}
+
+template <typename T, bool NS, bool LOFF>
+pg_status dispatch_d(const pg_tree* t, const void* q, const int32_t* o, int64_t m, int k, bool all,
+                     int32_t* oi, void* od, hipStream_t s) {
+    switch (t->d) {
+        case 2: return dispatch_k<T, 2, NS, LOFF>(t, q, o, m, k, all, oi, od, s);
+        case 3: return dispatch_k<T, 3, NS, LOFF>(t, q, o, m, k, all, oi, od, s);
+        case 5: return dispatch_k<T, 5, NS, LOFF>(t, q, o, m, k, all, oi, od, s);
+        default: return dispatch_k<T, 8, NS, LOFF>(t, q, o, m, k, all, oi, od, s);
+    }
+}
+
+}  // namespace knn_detail
+}  // namespace pg
