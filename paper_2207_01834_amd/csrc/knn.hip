@@ -57,14 +57,12 @@ __global__ void bucket_count_kernel(const uint32_t* __restrict__ key, int64_t m,
     if (i < m) atomicAdd(&cnt[key[i]], 1u);
 }
 
+// start[b] is the next free slot of bucket b (its exclusive prefix sum
+// first); each query takes one.
 __global__ void bucket_fill_kernel(const uint32_t* __restrict__ key, int64_t m,
-                                   const uint32_t* __restrict__ start, uint32_t* __restrict__ cursor,
-                                   int32_t* __restrict__ order) {
+                                   uint32_t* __restrict__ start, int32_t* __restrict__ order) {
     const int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x;
-    if (i < m) {
-        const uint32_t b = key[i];
-        order[start[b] + atomicAdd(&cursor[b], 1u)] = (int32_t)i;
-    }
+    if (i < m) order[atomicAdd(&start[key[i]], 1u)] = (int32_t)i;
 }
 
 __global__ void check_queries_kernel(const uint32_t* __restrict__ q, int64_t count, int fl,
@@ -104,24 +102,21 @@ pg_status order_queries(const TreeView& tv, bool fl, const void* queries, int64_
     while (bits < 24 && ((int64_t)1 << (bits + 1)) * 4 <= m) bits++;
     const int shift = tv.L > bits ? tv.L - bits : 0;
     const int64_t nb = ((int64_t)1 << tv.L) >> shift;
-    DevBuf key(s), cnt(s), start(s), cursor(s);
-    PG_TRY(key.alloc(sizeof(uint32_t) * m));
-    PG_TRY(cnt.alloc(sizeof(uint32_t) * nb));
-    PG_TRY(start.alloc(sizeof(uint32_t) * nb));
-    PG_TRY(cursor.alloc(sizeof(uint32_t) * nb));
+    // one temporary: the queries' bucket keys, then the bucket counts (which
+    // the scan turns, in place, into each bucket's next free slot)
+    DevBuf work(s);
+    PG_TRY(work.alloc(sizeof(uint32_t) * (m + nb)));
+    uint32_t* key = work.as<uint32_t>();
+    uint32_t* cnt = key + m;
     PG_TRY(order.alloc(sizeof(int32_t) * m));
-    PG_HIP(hipMemsetAsync(cnt.p, 0, sizeof(uint32_t) * nb, s));
-    PG_HIP(hipMemsetAsync(cursor.p, 0, sizeof(uint32_t) * nb, s));
+    PG_HIP(hipMemsetAsync(cnt, 0, sizeof(uint32_t) * nb, s));
     hipLaunchKernelGGL(query_leaf_kernel, dim3(cdiv(m, (int64_t)kNT * kLeafQpt)), dim3(kNT), 0, s,
-                       tv, fl ? 1 : 0, (const uint32_t*)queries, m, tv.L - shift, boxes ? 1 : 0,
-                       key.as<uint32_t>());
+                       tv, fl ? 1 : 0, (const uint32_t*)queries, m, tv.L - shift, boxes ? 1 : 0, key);
     PG_LAUNCH_CHECK();
-    hipLaunchKernelGGL(bucket_count_kernel, dim3(cdiv(m, kNT)), dim3(kNT), 0, s,
-                       key.as<uint32_t>(), m, cnt.as<uint32_t>());
+    hipLaunchKernelGGL(bucket_count_kernel, dim3(cdiv(m, kNT)), dim3(kNT), 0, s, key, m, cnt);
     PG_LAUNCH_CHECK();
-    PG_TRY(exclusive_scan_u32(cnt.as<uint32_t>(), start.as<uint32_t>(), nb, nullptr, s));
-    hipLaunchKernelGGL(bucket_fill_kernel, dim3(cdiv(m, kNT)), dim3(kNT), 0, s,
-                       key.as<uint32_t>(), m, start.as<uint32_t>(), cursor.as<uint32_t>(),
+    PG_TRY(exclusive_scan_u32(cnt, cnt, nb, nullptr, s));
+    hipLaunchKernelGGL(bucket_fill_kernel, dim3(cdiv(m, kNT)), dim3(kNT), 0, s, key, m, cnt,
                        order.as<int32_t>());
     PG_LAUNCH_CHECK();
     return PG_OK;

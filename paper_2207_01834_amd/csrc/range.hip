@@ -70,6 +70,13 @@ __device__ inline int64_t node_begin(const TreeView& tv, int l, int64_t j) {
     return tv.loff ? tv.loff[j << (tv.L - l)] : node_start(tv.n, l, j);
 }
 
+// Walk modes of range_kernel, and the rows a box keeps in the stash.
+constexpr int kCount = 0, kReport = 1, kStash = 2;
+constexpr int kStashRows = 32;
+// pg_range_search stashes rows for at most this many boxes (beyond, the
+// reporting pass walks every box again).
+constexpr int64_t kStashMaxBoxes = (int64_t)1 << 25;
+
 // Leaf records and rows are read this many at a time.
 constexpr int kGroup = kTreePad;
 
@@ -106,14 +113,19 @@ __device__ inline void box_masks(const T (&bl)[MD], const T (&bh)[MD], const T (
 // one first; the right sibling then waits, with the lanes that contain it,
 // on a small per-wave stack of lane masks, one entry per level).  The node index, the masks and every tree
 // load are the same across the wave: scalar loads and no divergence.
-// REPORT = false: counts[i] = number of points in box i.
-// REPORT = true:  rows of those points go to out_idx[offsets[i] ...]; a slot
-// at or beyond `capacity` is not written and raises *overflow.
-template <typename T, int MD, bool REPORT>
+// kCount:  counts[i] = number of points in box i.
+// kReport: rows of those points go to out_idx[offsets[i] ...]; a slot at or
+//          beyond `capacity` is not written and raises *overflow.
+// kStash:  counts as kCount, and the first kStashRows rows of the box walked
+//          i0-th go to out_idx[i0 * kStashRows ...], with i0 in where[i] (a
+//          later gather moves them; boxes with more rows are walked again by
+//          kReport).
+template <typename T, int MD, int MODE>
 __global__ void __launch_bounds__(kNT)
 range_kernel(TreeView tv, const uint32_t* __restrict__ boxes, const int32_t* __restrict__ order,
              int64_t m, int32_t* __restrict__ counts, const int64_t* __restrict__ offsets,
-             int32_t* __restrict__ out_idx, int64_t capacity, uint32_t* __restrict__ overflow) {
+             int32_t* __restrict__ out_idx, int64_t capacity, uint32_t* __restrict__ overflow,
+             int32_t* __restrict__ where) {
     using M = Metric<T>;
     // per wave, by level: lanes that cut / contain a right child not yet visited
     __shared__ uint64_t pend[kNT / kWave][32][2];
@@ -130,23 +142,27 @@ range_kernel(TreeView tv, const uint32_t* __restrict__ boxes, const int32_t* __r
         lo[c] = (valid && (MD < 8 || c < d)) ? M::load(boxes[i * 2 * d + c]) : T(0);
         hi[c] = (valid && (MD < 8 || c < d)) ? M::load(boxes[i * 2 * d + d + c]) : T(0);
     }
-    const int64_t base = (REPORT && valid) ? offsets[i] : 0;
+    constexpr bool WR = MODE != kCount;  // rows are written
+    const int64_t base = !valid ? 0 : (MODE == kReport ? offsets[i] : (MODE == kStash ? i0 * kStashRows : 0));
+    const int64_t limit = MODE == kReport ? capacity : base + kStashRows;
     bool over = false;
     int64_t cnt = 0;
 
     // every point of leaf-order range [s, e) is in the boxes of lanes `mask`
     auto take_range = [&](int64_t s, int64_t e, uint64_t mask) {
         if ((mask & me) == 0) return;
-        if (REPORT) {
-            for (int64_t p = s; p < e; p += kGroup) {  // the row array is padded
+        if (WR) {
+            // stashing stops at the box's kStashRows slots
+            const int64_t pe = MODE == kStash ? min(e, s + max((int64_t)0, limit - base - cnt)) : e;
+            for (int64_t p = s; p < pe; p += kGroup) {  // the row array is padded
                 int32_t r[kGroup];
 #pragma unroll
                 for (int t = 0; t < kGroup; t++) r[t] = tv.pidx[p + t];
 #pragma unroll
                 for (int t = 0; t < kGroup; t++) {
                     const int64_t slot = base + cnt + (p - s) + t;
-                    if (p + t < e) {
-                        if (slot < capacity) out_idx[slot] = r[t];
+                    if (p + t < pe) {
+                        if (slot < limit) out_idx[slot] = r[t];
                         else over = true;
                     }
                 }
@@ -169,8 +185,8 @@ range_kernel(TreeView tv, const uint32_t* __restrict__ boxes, const int32_t* __r
                 for (int c = 0; c < MD; c++)
                     if (MD < 8 || c < d) in = in & (lo[c] <= pt[t][c]) & (pt[t][c] <= hi[c]);
                 if (in) {
-                    if (REPORT) {
-                        if (base + cnt < capacity) out_idx[base + cnt] = (int32_t)idw[t];
+                    if (WR) {
+                        if (base + cnt < limit) out_idx[base + cnt] = (int32_t)idw[t];
                         else over = true;
                     }
                     cnt++;
@@ -261,37 +277,104 @@ range_kernel(TreeView tv, const uint32_t* __restrict__ boxes, const int32_t* __r
             }
         }
     }
-    if (valid && !REPORT) counts[i] = (int32_t)cnt;
-    if (REPORT && over) atomicOr(overflow, 1u);
+    if (valid && MODE != kReport) counts[i] = (int32_t)cnt;
+    if (valid && MODE == kStash) where[i] = (int32_t)i0;
+    if (MODE == kReport && over) atomicOr(overflow, 1u);
 }
 
 template <typename T, int MD>
 pg_status launch_range(const pg_tree* t, const void* boxes, const int32_t* order, int64_t m,
-                       int32_t* counts, const int64_t* offsets, int32_t* out_idx,
-                       int64_t capacity, uint32_t* overflow, hipStream_t s) {
+                       int mode, int32_t* counts, const int64_t* offsets, int32_t* out_idx,
+                       int64_t capacity, uint32_t* overflow, int32_t* where, hipStream_t s) {
     const dim3 grid(grid_for_xcd(cdiv(m, kNT)));
-    if (offsets)
-        hipLaunchKernelGGL((range_kernel<T, MD, true>), grid, dim3(kNT), 0, s, t->view(),
+    if (mode == kReport)
+        hipLaunchKernelGGL((range_kernel<T, MD, kReport>), grid, dim3(kNT), 0, s, t->view(),
                            (const uint32_t*)boxes, order, m, nullptr, offsets, out_idx, capacity,
-                           overflow);
+                           overflow, nullptr);
+    else if (mode == kStash)
+        hipLaunchKernelGGL((range_kernel<T, MD, kStash>), grid, dim3(kNT), 0, s, t->view(),
+                           (const uint32_t*)boxes, order, m, counts, nullptr, out_idx, 0, nullptr,
+                           where);
     else
-        hipLaunchKernelGGL((range_kernel<T, MD, false>), grid, dim3(kNT), 0, s, t->view(),
+        hipLaunchKernelGGL((range_kernel<T, MD, kCount>), grid, dim3(kNT), 0, s, t->view(),
                            (const uint32_t*)boxes, order, m, counts, nullptr, nullptr, 0,
-                           nullptr);
+                           nullptr, nullptr);
     PG_LAUNCH_CHECK();
     return PG_OK;
 }
 
 template <typename T>
 pg_status dispatch_range(const pg_tree* t, const void* boxes, const int32_t* order, int64_t m,
-                         int32_t* counts, const int64_t* offsets, int32_t* out_idx,
-                         int64_t capacity, uint32_t* overflow, hipStream_t s) {
+                         int mode, int32_t* counts, const int64_t* offsets, int32_t* out_idx,
+                         int64_t capacity, uint32_t* overflow, int32_t* where, hipStream_t s) {
     switch (t->d) {
-        case 2: return launch_range<T, 2>(t, boxes, order, m, counts, offsets, out_idx, capacity, overflow, s);
-        case 3: return launch_range<T, 3>(t, boxes, order, m, counts, offsets, out_idx, capacity, overflow, s);
-        case 5: return launch_range<T, 5>(t, boxes, order, m, counts, offsets, out_idx, capacity, overflow, s);
-        default: return launch_range<T, 8>(t, boxes, order, m, counts, offsets, out_idx, capacity, overflow, s);
+        case 2: return launch_range<T, 2>(t, boxes, order, m, mode, counts, offsets, out_idx, capacity, overflow, where, s);
+        case 3: return launch_range<T, 3>(t, boxes, order, m, mode, counts, offsets, out_idx, capacity, overflow, where, s);
+        case 5: return launch_range<T, 5>(t, boxes, order, m, mode, counts, offsets, out_idx, capacity, overflow, where, s);
+        default: return launch_range<T, 8>(t, boxes, order, m, mode, counts, offsets, out_idx, capacity, overflow, where, s);
     }
+}
+
+// Stashed rows to their final slots, one thread per box in box order.  A
+// wave's boxes own one contiguous stretch of the output, so when none of
+// them was flagged the rows are staged in LDS and written out as whole
+// 64-lane runs; stash rows are read 16 bytes at a time.  Boxes with more
+// than kStashRows rows are flagged, by walking position, for the reporting
+// pass (their waves write per lane and leave those boxes' slots alone).
+__global__ void __launch_bounds__(kNT)
+range_gather_kernel(int64_t m, const int32_t* __restrict__ counts,
+                    const int64_t* __restrict__ offsets, const int32_t* __restrict__ where,
+                    const int32_t* __restrict__ stash, int32_t* __restrict__ out_idx,
+                    int64_t capacity, uint32_t* __restrict__ redo_flag,
+                    uint32_t* __restrict__ overflow) {
+    __shared__ int32_t stage[kNT / kWave][kWave * kStashRows];
+    const int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x;
+    const bool valid = i < m;
+    if (__ballot(valid) == 0) return;
+    int32_t* st = stage[threadIdx.x / kWave];
+    const int32_t c = valid ? counts[i] : 0;
+    const int64_t i0 = valid ? where[i] : 0;
+    const int64_t o = valid ? offsets[i] : 0;
+    const bool redo = c > kStashRows;
+    if (redo) redo_flag[i0] = 1u;
+    const int lane = lane_id();
+    bool over = false;
+    if (__ballot(redo) == 0) {
+        const int64_t w0 = __shfl(o, 0, kWave);
+        const uint64_t live = __ballot(valid);
+        const int last = 63 - __builtin_clzll(live);
+        const int64_t w1 = __shfl(o + c, last, kWave);  // end of the wave's stretch
+        const int rel = (int)(o - w0);
+        const int4* src = reinterpret_cast<const int4*>(stash + i0 * kStashRows);
+        for (int q = 0; q < (c + 3) / 4; q++) {
+            const int4 v = src[q];
+            const int r = rel + 4 * q;
+            if (4 * q + 0 < c) st[r + 0] = v.x;
+            if (4 * q + 1 < c) st[r + 1] = v.y;
+            if (4 * q + 2 < c) st[r + 2] = v.z;
+            if (4 * q + 3 < c) st[r + 3] = v.w;
+        }
+        wave_lds_sync();
+        const int total = (int)(w1 - w0);
+        for (int e = lane; e < total; e += kWave) {
+            if (w0 + e < capacity) out_idx[w0 + e] = st[e];
+            else over = true;
+        }
+    } else if (valid && !redo) {
+        for (int t = 0; t < c; t++) {
+            if (o + t < capacity) out_idx[o + t] = stash[i0 * kStashRows + t];
+            else over = true;
+        }
+    }
+    if (over) atomicOr(overflow, 1u);
+}
+
+// The flagged boxes, in walking order (pos: exclusive prefix sum of flags).
+__global__ void range_redo_list_kernel(const int32_t* __restrict__ order, int64_t m,
+                                       const uint32_t* __restrict__ flag,
+                                       const uint32_t* __restrict__ pos, int32_t* __restrict__ redo) {
+    const int64_t i0 = (int64_t)blockIdx.x * kNT + threadIdx.x;
+    if (i0 < m && flag[i0]) redo[pos[i0]] = order ? order[i0] : (int32_t)i0;
 }
 
 // The order in which the boxes are walked (the tree's leaf order of their
@@ -306,12 +389,12 @@ pg_status range_order(const pg_tree* t, const void* boxes, int64_t m, hipStream_
     return PG_OK;
 }
 
-pg_status range_pass(const pg_tree* t, const void* boxes, const int32_t* o, int64_t m,
+pg_status range_pass(const pg_tree* t, const void* boxes, const int32_t* o, int64_t m, int mode,
                      int32_t* counts, const int64_t* offsets, int32_t* out_idx, int64_t capacity,
-                     uint32_t* overflow, hipStream_t s) {
+                     uint32_t* overflow, hipStream_t s, int32_t* where = nullptr) {
     if (t->dtype == PG_FLOAT32)
-        return dispatch_range<float>(t, boxes, o, m, counts, offsets, out_idx, capacity, overflow, s);
-    return dispatch_range<int32_t>(t, boxes, o, m, counts, offsets, out_idx, capacity, overflow, s);
+        return dispatch_range<float>(t, boxes, o, m, mode, counts, offsets, out_idx, capacity, overflow, where, s);
+    return dispatch_range<int32_t>(t, boxes, o, m, mode, counts, offsets, out_idx, capacity, overflow, where, s);
 }
 
 // Counting pass into counts (caller's), the prefix sum into offsets when
@@ -320,7 +403,7 @@ pg_status count_pass(const pg_tree* t, const void* boxes, const int32_t* o, int6
                      int32_t* counts, int64_t* offsets, hipStream_t s) {
     if (m > 0) {
         if (t->n == 0) PG_HIP(hipMemsetAsync(counts, 0, sizeof(int32_t) * m, s));
-        else PG_TRY(range_pass(t, boxes, o, m, counts, nullptr, nullptr, 0, nullptr, s));
+        else PG_TRY(range_pass(t, boxes, o, m, kCount, counts, nullptr, nullptr, 0, nullptr, s));
     }
     if (offsets) {
         if (m > 0) PG_TRY(exclusive_scan_i32_i64(counts, offsets, m, offsets + m, s));
@@ -337,7 +420,8 @@ pg_status report_pass(const pg_tree* t, const void* boxes, const int32_t* o, int
     DevBuf flag(s);
     PG_TRY(flag.alloc(sizeof(uint32_t)));
     PG_HIP(hipMemsetAsync(flag.p, 0, sizeof(uint32_t), s));
-    PG_TRY(range_pass(t, boxes, o, m, nullptr, offsets, out_idx, capacity, flag.as<uint32_t>(), s));
+    PG_TRY(range_pass(t, boxes, o, m, kReport, nullptr, offsets, out_idx, capacity,
+                      flag.as<uint32_t>(), s));
     uint32_t h = 0;
     PG_HIP(hipMemcpyAsync(&h, flag.p, sizeof(h), hipMemcpyDeviceToHost, s));
     PG_HIP(hipStreamSynchronize(s));
@@ -377,14 +461,31 @@ pg_status range_report(const pg_tree* t, const void* boxes, int64_t m, const int
 pg_status range_search(const pg_tree* t, const void* boxes, int64_t m, int32_t* counts,
                        int64_t* offsets, int32_t* out_idx, int64_t capacity, int64_t* total_host,
                        hipStream_t s) {
-    DevBuf order(s), cbuf(s);
+    DevBuf order(s), work(s);
     const int32_t* o = nullptr;
     if (t->n > 0) PG_TRY(range_order(t, boxes, m, s, order, &o));
-    if (!counts) {
-        PG_TRY(cbuf.alloc(sizeof(int32_t) * (m > 0 ? m : 1)));
-        counts = cbuf.as<int32_t>();
+    // counting pass; with few enough boxes it also keeps each box's first
+    // kStashRows rows, so the reporting pass only walks the boxes with more
+    const bool stashing = t->n > 0 && m > 0 && m <= kStashMaxBoxes;
+    // one temporary, carved: stash [m][kStashRows], counts (when the caller
+    // gives none), where, flags, flag positions, redo list [m], and two words
+    const size_t mm = (size_t)(m > 0 ? m : 1);
+    const size_t stash_w = stashing ? mm * kStashRows : 0;
+    PG_TRY(work.alloc(sizeof(int32_t) * (stash_w + (stashing ? 5 * mm : mm) + 2)));
+    int32_t* stash = work.as<int32_t>();
+    int32_t* cnts = stash + stash_w;
+    if (!counts) counts = cnts;
+    int32_t* where = cnts + mm;
+    uint32_t* flag = (uint32_t*)(where + mm);
+    uint32_t* pos = flag + mm;
+    int32_t* redo = (int32_t*)(pos + mm);
+    uint32_t* aux = stashing ? (uint32_t*)(redo + mm) : (uint32_t*)(cnts + mm);  // overflow, redo count
+    if (stashing) {
+        PG_TRY(range_pass(t, boxes, o, m, kStash, counts, nullptr, stash, 0, nullptr, s, where));
+        PG_TRY(exclusive_scan_i32_i64(counts, offsets, m, offsets + m, s));
+    } else {
+        PG_TRY(count_pass(t, boxes, o, m, counts, offsets, s));
     }
-    PG_TRY(count_pass(t, boxes, o, m, counts, offsets, s));
     int64_t total = 0;
     PG_HIP(hipMemcpyAsync(&total, offsets + m, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     PG_HIP(hipStreamSynchronize(s));
@@ -393,7 +494,28 @@ pg_status range_search(const pg_tree* t, const void* boxes, int64_t m, int32_t* 
         return fail(PG_ERR_INVALID, "pg_range_search: " + std::to_string(total) +
                                         " results exceed capacity " + std::to_string(capacity) +
                                         " (counts, offsets and the total are written)");
-    return report_pass(t, boxes, o, m, offsets, out_idx, capacity, s);
+    if (!stashing) return report_pass(t, boxes, o, m, offsets, out_idx, capacity, s);
+    uint32_t* over = aux;
+    uint32_t* nredo = aux + 1;
+    PG_HIP(hipMemsetAsync(aux, 0, sizeof(uint32_t) * 2, s));
+    PG_HIP(hipMemsetAsync(flag, 0, sizeof(uint32_t) * m, s));
+    hipLaunchKernelGGL(range_gather_kernel, dim3(cdiv(m, kNT)), dim3(kNT), 0, s, m, counts, offsets,
+                       where, stash, out_idx, capacity, flag, over);
+    PG_LAUNCH_CHECK();
+    PG_TRY(exclusive_scan_u32(flag, pos, m, nredo, s));
+    uint32_t h[2] = {0, 0};
+    PG_HIP(hipMemcpyAsync(h, aux, sizeof(h), hipMemcpyDeviceToHost, s));
+    PG_HIP(hipStreamSynchronize(s));
+    if (h[1] > 0) {
+        hipLaunchKernelGGL(range_redo_list_kernel, dim3(cdiv(m, kNT)), dim3(kNT), 0, s, o, m, flag,
+                           pos, redo);
+        PG_LAUNCH_CHECK();
+        PG_TRY(range_pass(t, boxes, redo, h[1], kReport, nullptr, offsets, out_idx, capacity, over, s));
+        PG_HIP(hipMemcpyAsync(h, aux, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        PG_HIP(hipStreamSynchronize(s));
+    }
+    if (h[0]) return fail(PG_ERR_INVALID, "pg_range_search: a result slot lies at or beyond `capacity`");
+    return PG_OK;
 }
 
 }  // namespace pg
