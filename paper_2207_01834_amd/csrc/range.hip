@@ -6,19 +6,18 @@
 // lo_c <= p_c <= hi_c in every dimension c (an empty box when lo_c > hi_c).
 // Coordinates are compared as values, so -0.0 and +0.0 are equal.
 //
-// Traversal: depth-first over the implicit heap without a stack.  For one
-// box: a node whose bounding box misses it is skipped, a node whose box lies
-// inside it reports its whole leaf-order range [floor(j n/2^l),
-// floor((j+1) n/2^l)) without touching its points, and a leaf that the box
-// cuts tests each of its points.  After a node is done the walk moves to the
-// right sibling of its lowest left-child ancestor-or-self, found in one step
-// by stripping the heap index's trailing one bits.  The 64 boxes of a wave
-// (neighbours in the tree's leaf order) share one walk over the union of
-// the nodes they need.
+// Traversal: depth-first over the implicit heap.  For one box: a node whose
+// bounding box misses it is skipped, a node whose box lies inside it reports
+// its whole leaf-order range (closed form floor(j n/2^l), or the leaf
+// offsets of trees that have them) without touching its points, and a leaf
+// that the box cuts tests each of its points.  The 64 boxes of a wave
+// (neighbours in the tree's leaf order) share one walk over the union of the
+// nodes they need (range_kernel).
 //
-// A query is run twice: a counting pass, then (after a prefix sum of the
-// counts) a pass that writes the input rows, in leaf order, from the query's
-// offset on.
+// Two passes: counting, then (after a prefix sum of the counts) writing the
+// input rows, in leaf order, from each box's offset.  pg_range_search keeps
+// each box's first rows during the counting pass and only walks again the
+// boxes that have more.
 #include "range.hpp"
 #include "knn.hpp"
 #include "scan.hpp"
