@@ -61,7 +61,7 @@ def lib():
         L.or_kd_export.restype = None
         L.or_kd_knn.argtypes = [vp, vp, vp, vp, i64, i32, vp, vp, vp]
         L.or_kd_knn.restype = i32
-        L.or_kd_build_spatial.argtypes = [vp, i64, i32, i32, i32, vp, vp, vp, vp]
+        L.or_kd_build_spatial.argtypes = [vp, i64, i32, i32, i32, i32, vp, vp, vp, vp, vp]
         L.or_kd_build_spatial.restype = i32
         L.or_range_brute.argtypes = [vp, vp, vp, i64, i32, i32, vp, i64, vp, vp, vp]
         L.or_range_brute.restype = i32
@@ -237,30 +237,34 @@ class KdTree:
         return counts, off, out, counters
 
 
-def spatial_tree(points, leaf=16):
+def spatial_tree(points, leaf=16, rule="cycle"):
     """Spatial-median kd-tree (Section 6.3: the node's space cut in half along
     a dimension), read as: root space = bounding box of the points; node
-    (l, j) cuts its cell along dimension l mod d at the cell's midpoint
-    (int: floor((lo + hi + 1) / 2), cells [lo, s-1] / [s, hi]; float: the
-    float nearest (lo + hi) / 2, cells [lo, s] / [s, hi]); coordinate < s
-    goes left, each side keeps the parent's order; depth L as the
-    object-median tree, so leaf sizes vary.  Returns (levels, splits float64
-    [2^L] with index 0 unused, rows int64 [n] in leaf order, leaf offsets
-    int64 [2^L + 1])."""
+    (l, j) cuts its cell at the cell's midpoint (int: floor((lo + hi + 1) /
+    2), cells [lo, s-1] / [s, hi]; float: the float nearest (lo + hi) / 2,
+    cells [lo, s] / [s, hi]) along dimension l mod d (rule "cycle") or along
+    the cell's widest side, lowest dimension on ties (rule "widest");
+    coordinate < s goes left, each side keeps the parent's order; depth L as
+    the object-median tree, so leaf sizes vary.  Returns (levels, splits
+    float64 [2^L] with index 0 unused, split dimensions int32 [2^L], rows
+    int64 [n] in leaf order, leaf offsets int64 [2^L + 1])."""
     points = np.ascontiguousarray(points)
     dt = _dtype_code(points)
     n, d = points.shape
+    r = {"cycle": 0, "widest": 1}[rule]
     lv = ctypes.c_int()
-    rc = lib().or_kd_build_spatial(_ptr(points), n, d, dt, leaf, ctypes.byref(lv), None, None, None)
+    rc = lib().or_kd_build_spatial(_ptr(points), n, d, dt, leaf, r, ctypes.byref(lv),
+                                   None, None, None, None)
     if rc != 0:
         raise ValueError("or_kd_build_spatial: bad arguments")
     L = lv.value
     splits = np.zeros(1 << L, dtype=np.float64)
+    dims = np.zeros(1 << L, dtype=np.int32)
     perm = np.empty(n, dtype=np.int64)
     loff = np.empty((1 << L) + 1, dtype=np.int64)
-    lib().or_kd_build_spatial(_ptr(points), n, d, dt, leaf, ctypes.byref(lv), _ptr(splits),
-                              _ptr(perm), _ptr(loff))
-    return L, splits, perm, loff
+    lib().or_kd_build_spatial(_ptr(points), n, d, dt, leaf, r, ctypes.byref(lv), _ptr(splits),
+                              _ptr(dims), _ptr(perm), _ptr(loff))
+    return L, splits, dims, perm, loff
 
 
 def tree_depth(n: int, leaf: int) -> int:

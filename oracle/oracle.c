@@ -527,7 +527,9 @@ int or_kd_range(const or_tree* T, const int64_t* ids, const uint8_t* alive,
 /* L = min{L : ceil(n/2^L) <= leaf}, so leaves hold varying numbers of      */
 /* points.  Midpoints: int cells [lo, hi] cut at floor((lo + hi + 1) / 2)    */
 /* into [lo, s-1] and [s, hi]; float cells [lo, hi] at the float nearest   */
-/* to (lo + hi) / 2 (sum in double) into [lo, s] and [s, hi].               */
+/* to (lo + hi) / 2 (sum in double) into [lo, s] and [s, hi].  Split        */
+/* dimension: l mod d (rule 0), or the cell's widest side hi - lo, the      */
+/* lowest such dimension on ties (rule 1).                                  */
 /* ------------------------------------------------------------------------ */
 static double sp_mid(double lo, double hi, int dt) {
     if (dt == OR_DT_INT) {
@@ -539,13 +541,19 @@ static double sp_mid(double lo, double hi, int dt) {
 }
 
 typedef struct {
-    const void* pts; int64_t n; int d, dt, L;
-    int64_t* perm; int64_t* tmp; double* split; int64_t* loff;
+    const void* pts; int64_t n; int d, dt, L, rule;
+    int64_t* perm; int64_t* tmp; double* split; int64_t* loff; int32_t* dim;
 } sp_ctx;
 
 static void sp_rec(sp_ctx* C, int l, int64_t j, int64_t lo, int64_t hi, double* clo, double* chi) {
     if (l == C->L) { C->loff[j] = lo; return; }
     int c = l % C->d;
+    if (C->rule == 1) {
+        c = 0;
+        for (int e = 1; e < C->d; e++)
+            if (chi[e] - clo[e] > chi[c] - clo[c]) c = e;
+    }
+    C->dim[((int64_t)1 << l) + j] = c;
     double s = sp_mid(clo[c], chi[c], C->dt);
     C->split[((int64_t)1 << l) + j] = s;
     /* stable partition of perm[lo, hi) by coordinate < s */
@@ -567,19 +575,22 @@ static void sp_rec(sp_ctx* C, int l, int64_t j, int64_t lo, int64_t hi, double* 
 }
 
 /* Builds the spatial-median tree.  Outputs: split_out [2^L] (node h at h,
- * index 0 unused), perm_out [n] rows in leaf order, loff_out [2^L + 1] leaf
- * offsets; *levels = L.  Arrays must hold 2^L(+1) entries: call with NULL
- * outputs first to get L. */
-int or_kd_build_spatial(const void* pts, int64_t n, int d, int dt, int leaf, int* levels,
-                        double* split_out, int64_t* perm_out, int64_t* loff_out) {
-    if (d < 1 || d > 8 || leaf < 1 || n < 0 || !levels) return 1;
+ * index 0 unused), dim_out [2^L] split dimension of node h, perm_out [n]
+ * rows in leaf order, loff_out [2^L + 1] leaf offsets; *levels = L.  Arrays
+ * must hold 2^L(+1) entries: call with NULL outputs first to get L. */
+int or_kd_build_spatial(const void* pts, int64_t n, int d, int dt, int leaf, int rule,
+                        int* levels, double* split_out, int32_t* dim_out, int64_t* perm_out,
+                        int64_t* loff_out) {
+    if (d < 1 || d > 8 || leaf < 1 || n < 0 || !levels || rule < 0 || rule > 1) return 1;
     int L = tree_depth(n, leaf);
     *levels = L;
-    if (!split_out || !perm_out || !loff_out) return 0;
-    sp_ctx C = {pts, n, d, dt, L, perm_out, (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1)),
-                split_out, loff_out};
+    if (!split_out || !dim_out || !perm_out || !loff_out) return 0;
+    sp_ctx C = {pts, n, d, dt, L, rule, perm_out,
+                (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1)), split_out, loff_out,
+                dim_out};
     for (int64_t i = 0; i < n; i++) perm_out[i] = i;
     split_out[0] = 0.0;
+    dim_out[0] = 0;
     double clo[8], chi[8];
     for (int c = 0; c < d; c++) { clo[c] = INFINITY; chi[c] = -INFINITY; }
     for (int64_t i = 0; i < n; i++)

@@ -37,7 +37,7 @@ def membership(perm, loff):
 
 def check_tree(pg, dev, pts, leaf):
     t = pg.kdtree_build(to_dev(pts, dev), leaf=leaf, split="spatial")
-    L, s, perm, loff = oracle.spatial_tree(pts, leaf=leaf)
+    L, s, _, perm, loff = oracle.spatial_tree(pts, leaf=leaf)
     assert t.levels == L
     gs, gperm = t.export()
     gloff = t.offsets()

@@ -102,12 +102,12 @@ def test_spatial_hand_worked_int_and_float():
     # 1-D int 0..9: root cell [0, 9] cut at floor(10/2) = 5; [0, 4] at
     # floor(5/2) = 2; [5, 9] at floor(15/2) = 7.  Depth 2 for leaf 3.
     pts = np.arange(10, dtype=np.int32).reshape(-1, 1)
-    L, s, perm, loff = oracle.spatial_tree(pts, leaf=3)
+    L, s, _, perm, loff = oracle.spatial_tree(pts, leaf=3)
     assert L == 2 and s[1:].tolist() == [5, 2, 7]
     assert loff.tolist() == [0, 2, 5, 7, 10] and perm.tolist() == list(range(10))
     # 1-D float {0, .25, .5, .75, 1}: [0, 1] at .5; [0, .5] at .25; [.5, 1] at .75
     f = np.array([1.0, 0.5, 0.0, 0.75, 0.25], dtype=np.float32).reshape(-1, 1)
-    L, s, perm, loff = oracle.spatial_tree(f, leaf=2)
+    L, s, _, perm, loff = oracle.spatial_tree(f, leaf=2)
     assert L == 2 and s[1:].tolist() == [0.5, 0.25, 0.75]
     # stable: rows 0 (1.0) and 3 (0.75) keep their input order in the last leaf
     assert loff.tolist() == [0, 1, 2, 3, 5] and perm.tolist() == [2, 4, 1, 0, 3]
@@ -121,7 +121,7 @@ def test_spatial_full_grid_is_morton_order():
     pts = np.stack([xs.ravel(), ys.ravel()], axis=1).astype(np.int32)
     rng = np.random.default_rng(0)
     pts = pts[rng.permutation(len(pts))]
-    L, s, perm, loff = oracle.spatial_tree(pts, leaf=1)
+    L, s, _, perm, loff = oracle.spatial_tree(pts, leaf=1)
     assert L == 2 * k and np.all(np.diff(loff) == 1)
 
     def morton(x, y):
@@ -136,7 +136,7 @@ def test_spatial_full_grid_is_morton_order():
 
 def test_spatial_identical_points_go_right():
     pts = np.full((37, 3), 5, dtype=np.int32)
-    L, s, perm, loff = oracle.spatial_tree(pts, leaf=4)
+    L, s, _, perm, loff = oracle.spatial_tree(pts, leaf=4)
     sizes = np.diff(loff)
     assert sizes[-1] == 37 and sizes[:-1].sum() == 0 and perm.tolist() == list(range(37))
 
@@ -150,7 +150,7 @@ def test_spatial_invariants(d, leaf, dtype):
         pts[::5] = pts[7]
     else:
         pts = (rng.standard_normal((n, d)) ** 3).astype(np.float32)
-    L, s, perm, loff = oracle.spatial_tree(pts, leaf=leaf)
+    L, s, _, perm, loff = oracle.spatial_tree(pts, leaf=leaf)
     assert L == oracle.tree_depth(n, leaf)
     assert sorted(perm.tolist()) == list(range(n))
     leaf_of = np.repeat(np.arange(1 << L), np.diff(loff))
@@ -167,3 +167,38 @@ def test_spatial_invariants(d, leaf, dtype):
         span = 1 << (L - l)
         lo, mid, hi = loff[j * span], loff[j * span + span // 2], loff[(j + 1) * span]
         assert np.all(P[lo:mid, c] < s[h]) and np.all(P[mid:hi, c] >= s[h])
+
+
+def test_spatial_widest_rule_hand_worked():
+    # cell 0..31 x 0..15: x is widest -> cut at 16; each half is 16 x 16, a
+    # tie -> x again (the lowest dimension): 8 and 24; then y (8 x 16) at 8
+    xs, ys = np.meshgrid(np.arange(32), np.arange(16), indexing="ij")
+    pts = np.stack([xs.ravel(), ys.ravel()], axis=1).astype(np.int32)
+    L, s, dims, perm, loff = oracle.spatial_tree(pts, leaf=64, rule="widest")
+    assert L == 3
+    assert dims[1:4].tolist() == [0, 0, 0] and s[1:4].tolist() == [16, 8, 24]
+    assert dims[4:8].tolist() == [1, 1, 1, 1] and s[4:8].tolist() == [8, 8, 8, 8]
+    assert np.all(np.diff(loff) == 64)
+    # the cyclic rule cuts y at the second level instead
+    L, s, dims, perm, loff = oracle.spatial_tree(pts, leaf=64, rule="cycle")
+    assert dims[1:4].tolist() == [0, 1, 1] and s[1:4].tolist() == [16, 8, 8]
+
+
+@pytest.mark.parametrize("dtype", [np.int32, np.float32])
+def test_spatial_widest_invariants(dtype):
+    rng = np.random.default_rng(9)
+    n, d, leaf = 4000, 3, 8
+    scale = np.array([1000.0, 30.0, 200.0])
+    pts = (rng.random((n, d)) * scale).astype(dtype)
+    L, s, dims, perm, loff = oracle.spatial_tree(pts, leaf=leaf, rule="widest")
+    assert dims[1] == 0  # the root's widest side
+    P = pts[perm].astype(np.float64)
+    for h in range(1, 1 << L):
+        l = h.bit_length() - 1
+        j = h - (1 << l)
+        c = dims[h]
+        span = 1 << (L - l)
+        lo, mid, hi = loff[j * span], loff[j * span + span // 2], loff[(j + 1) * span]
+        assert np.all(P[lo:mid, c] < s[h]) and np.all(P[mid:hi, c] >= s[h])
+    for j in range(1 << L):
+        assert np.all(np.diff(perm[loff[j]:loff[j + 1]]) > 0)
