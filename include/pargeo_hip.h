@@ -79,17 +79,23 @@ pg_status pg_kdtree_build(const void* points, int64_t n, int32_t d, int32_t leaf
 /* Builds a kd-tree by spatial-median splits (the alternative split rule
  * Section 6.3 measures: a node's space is cut in half along a dimension).
  * Readings: the root's space is the bounding box of the points; node
- * (l, j) cuts its cell along dimension l mod d at the cell's midpoint s
- * (int32: floor((lo + hi + 1) / 2), halves [lo, s-1] and [s, hi]; float32:
- * the float nearest (lo + hi) / 2, halves [lo, s] and [s, hi]); points with
- * coordinate < s go left.  The depth L and heap layout are those of
+ * (l, j) cuts its cell at the cell's midpoint s (int32: floor((lo + hi + 1)
+ * / 2), halves [lo, s-1] and [s, hi]; float32: the float nearest
+ * (lo + hi) / 2, halves [lo, s] and [s, hi]) along dimension l mod d
+ * (dim_rule 0) or along the cell's widest side, the lowest dimension on
+ * ties (dim_rule 1); points with coordinate < s go left.  The depth L and heap layout are those of
  * pg_kdtree_build, so leaves hold varying numbers of points (possibly more
  * than `leaf`, or none); pg_tree_offsets gives the leaf ranges.  The order
  * of points inside a leaf is unspecified.  Every query call accepts the
  * result (pg_knn, pg_knn_all, pg_knn_graph, pg_range_*).  Arguments and
  * errors as pg_kdtree_build. */
 pg_status pg_kdtree_build_spatial(const void* points, int64_t n, int32_t d, int32_t leaf,
-                                  int32_t dtype, void* stream, pg_tree** out);
+                                  int32_t dtype, int32_t dim_rule, void* stream, pg_tree** out);
+
+/* Split dimension of every internal heap node (host, [2^L] bytes, index 0
+ * unused): l mod d unless the tree was built with per-node dimensions.
+ * Synchronises for such trees. */
+pg_status pg_tree_split_dims(const pg_tree* t, uint8_t* dims_host, void* stream);
 
 /* Leaf offsets (host, [2^L + 1]): leaf j holds leaf-order positions
  * [loff[j], loff[j+1]) (the closed form floor(j n / 2^L) for trees from

@@ -41,7 +41,8 @@ SIGNATURES = {
     "pg_last_error": (ctypes.c_char_p, []),
     "pg_version": (ctypes.c_char_p, []),
     "pg_kdtree_build": (i32, [vp, i64, i32, i32, i32, vp, ctypes.POINTER(vp)]),
-    "pg_kdtree_build_spatial": (i32, [vp, i64, i32, i32, i32, vp, ctypes.POINTER(vp)]),
+    "pg_kdtree_build_spatial": (i32, [vp, i64, i32, i32, i32, i32, vp, ctypes.POINTER(vp)]),
+    "pg_tree_split_dims": (i32, [vp, vp, vp]),
     "pg_tree_offsets": (i32, [vp, vp, vp]),
     "pg_knn": (i32, [vp, vp, i64, i32, vp, vp, vp]),
     "pg_knn_all": (i32, [vp, i32, vp, vp, vp]),
@@ -270,6 +271,14 @@ class KdTree:
         check(lib().pg_tree_offsets(self._h, ctypes.c_void_p(loff.ctypes.data), stream_ptr(self.device)))
         return loff
 
+    def split_dims(self):
+        """Split dimension of every internal heap node (NumPy uint8 [2^L],
+        index 0 unused)."""
+        import numpy as np
+        dims = np.empty(1 << self.levels, dtype=np.uint8)
+        check(lib().pg_tree_split_dims(self._h, ctypes.c_void_p(dims.ctypes.data), stream_ptr(self.device)))
+        return dims
+
     def export(self):
         """(split values of heap nodes 1..2^L-1, input rows in leaf order) as
         NumPy arrays."""
@@ -282,21 +291,25 @@ class KdTree:
         return splits, perm
 
 
-def kdtree_build(points: torch.Tensor, leaf: int = 16, split: str = "object") -> KdTree:
+def kdtree_build(points: torch.Tensor, leaf: int = 16, split: str = "object",
+                 dim_rule: str = "cycle") -> KdTree:
     """Builds a kd-tree: ``split="object"`` (object median, every leaf at most
     ``leaf`` points) or ``"spatial"`` (cells cut at their midpoints, the same
-    depth, leaf sizes vary)."""
+    depth, leaf sizes vary; ``dim_rule`` "cycle" = level mod d, "widest" = the
+    cell's widest side)."""
     p = _points(points, "points")
     code = _dtype_code(p)
     h = ctypes.c_void_p()
+    args = (ctypes.c_void_p(p.data_ptr()), p.shape[0], p.shape[1], leaf, code)
     if split == "object":
-        fn = lib().pg_kdtree_build
+        if dim_rule != "cycle":
+            raise ValueError("object-median trees cycle through the dimensions")
+        check(lib().pg_kdtree_build(*args, stream_ptr(p.device), ctypes.byref(h)))
     elif split == "spatial":
-        fn = lib().pg_kdtree_build_spatial
+        rule = {"cycle": 0, "widest": 1}[dim_rule]
+        check(lib().pg_kdtree_build_spatial(*args, rule, stream_ptr(p.device), ctypes.byref(h)))
     else:
         raise ValueError("split must be 'object' or 'spatial'")
-    check(fn(ctypes.c_void_p(p.data_ptr()), p.shape[0], p.shape[1], leaf, code,
-             stream_ptr(p.device), ctypes.byref(h)))
     return KdTree(h, code, p.device)
 
 

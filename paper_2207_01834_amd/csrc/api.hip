@@ -56,6 +56,7 @@ static void tree_release(pg_tree* t) {
     dfree(t->nbox, t->stream);
     dfree(t->rec, t->stream);
     if (t->loff) dfree(t->loff, t->stream);
+    if (t->sdim) dfree(t->sdim, t->stream);
     delete t;
 }
 
@@ -89,16 +90,17 @@ pg_status pg_kdtree_build(const void* points, int64_t n, int32_t d, int32_t leaf
 }
 
 pg_status pg_kdtree_build_spatial(const void* points, int64_t n, int32_t d, int32_t leaf,
-                                  int32_t dtype, void* stream, pg_tree** out) {
+                                  int32_t dtype, int32_t dim_rule, void* stream, pg_tree** out) {
     if (!out) return fail(PG_ERR_INVALID, "pg_kdtree_build_spatial: out is NULL");
     if (d < 1 || d > 8) return fail(PG_ERR_INVALID, "pg_kdtree_build_spatial: d must be in [1, 8]");
     if (leaf < 1 || leaf > 64) return fail(PG_ERR_INVALID, "pg_kdtree_build_spatial: leaf must be in [1, 64]");
     if (n < 0 || n >= ((int64_t)1 << 31)) return fail(PG_ERR_INVALID, "pg_kdtree_build_spatial: n must be in [0, 2^31)");
     if (dtype != PG_INT32 && dtype != PG_FLOAT32) return fail(PG_ERR_INVALID, "pg_kdtree_build_spatial: bad dtype");
     if (n > 0 && !points) return fail(PG_ERR_INVALID, "pg_kdtree_build_spatial: points is NULL");
+    if (dim_rule != 0 && dim_rule != 1) return fail(PG_ERR_INVALID, "pg_kdtree_build_spatial: dim_rule must be 0 or 1");
     pg_tree* t = new (std::nothrow) pg_tree();
     if (!t) return fail(PG_ERR_NOMEM, "pg_kdtree_build_spatial: host allocation failed");
-    pg_status st = build_tree_spatial(points, n, d, leaf, dtype, (hipStream_t)stream, t);
+    pg_status st = build_tree_spatial(points, n, d, leaf, dtype, dim_rule, (hipStream_t)stream, t);
     if (st != PG_OK) {
         tree_release(t);
         return st;
@@ -118,6 +120,24 @@ pg_status pg_tree_offsets(const pg_tree* t, int64_t* loff_host, void* stream) {
         PG_HIP(hipStreamSynchronize(s));
     } else {
         for (int64_t j = 0; j <= leaves; j++) loff_host[j] = node_start(t->n, t->L, j);
+    }
+    return PG_OK;
+}
+
+pg_status pg_tree_split_dims(const pg_tree* t, uint8_t* dims_host, void* stream) {
+    if (!t) return fail(PG_ERR_INVALID, "pg_tree_split_dims: tree is NULL");
+    if (!dims_host) return fail(PG_ERR_INVALID, "pg_tree_split_dims: dims_host is NULL");
+    const int64_t nodes = (int64_t)1 << t->L;
+    if (t->sdim) {
+        hipStream_t s = (hipStream_t)stream;
+        PG_HIP(hipMemcpyAsync(dims_host, t->sdim, nodes, hipMemcpyDeviceToHost, s));
+        PG_HIP(hipStreamSynchronize(s));
+    } else {
+        dims_host[0] = 0;
+        for (int64_t h = 1; h < nodes; h++) {
+            int l = 63 - __builtin_clzll((unsigned long long)h);
+            dims_host[h] = (uint8_t)(l % t->d);
+        }
     }
     return PG_OK;
 }

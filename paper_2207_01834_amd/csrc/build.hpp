@@ -31,8 +31,9 @@ pg_status build_tree(const void* points, int64_t n, int d, int leaf, int dtype, 
                      pg_tree* T);
 
 // Allocates T's arrays and builds the spatial-median tree (explicit leaf
-// offsets in T->loff) from device rows [n][d].
-pg_status build_tree_spatial(const void* points, int64_t n, int d, int leaf, int dtype,
+// offsets in T->loff; rule 0: split dimension l mod d, rule 1: the cell's
+// widest side, stored per node in T->sdim) from device rows [n][d].
+pg_status build_tree_spatial(const void* points, int64_t n, int d, int leaf, int dtype, int rule,
                              hipStream_t s, pg_tree* T);
 
 }  // namespace pg

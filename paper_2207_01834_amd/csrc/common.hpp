@@ -115,6 +115,7 @@ struct TreeView {
     const int64_t* loff;    // [2^L + 1] leaf j holds positions [loff[j], loff[j+1]);
                             // null: the closed form floor(j n / 2^L) (trees grown
                             // in place keep their splits but not that form)
+    const uint8_t* sdim;    // [2^L] split dimension of internal node h; null: level mod d
 };
 
 inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
@@ -133,7 +134,8 @@ struct pg_tree {
     uint32_t* bbox = nullptr;
     uint32_t* rec = nullptr;
     int64_t* loff = nullptr;   // explicit leaf offsets [2^L + 1]; null: closed form
+    uint8_t* sdim = nullptr;   // split dimension per internal node; null: level mod d
     pg::TreeView view() const {
-        return pg::TreeView{n, d, L, pg::record_words(d), pts, pidx, split, bbox, rec, nbox, loff};
+        return pg::TreeView{n, d, L, pg::record_words(d), pts, pidx, split, bbox, rec, nbox, loff, sdim};
     }
 };

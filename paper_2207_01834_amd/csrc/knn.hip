@@ -34,6 +34,7 @@ query_leaf_kernel(TreeView tv, int fl, const uint32_t* __restrict__ queries, int
         uint32_t cur = 1;
         int dim = 0;
         for (int lvl = 0; lvl < levels; lvl++) {
+            if (tv.sdim) dim = tv.sdim[cur];
             const uint32_t qb = queries[row + dim];
             const uint32_t sb = lvl < tl ? top[cur] : tv.split[cur];
             bool right;

@@ -156,13 +156,21 @@ __device__ inline void kd_search(const TreeView& tv, const Ids& ids, const T (&q
         prev = 0;
         cur = 1;
     }
+    // split dimension of internal node h at level lvl (trees with offsets may
+    // carry one per node)
+    auto dim_of = [&](uint32_t h, int lvl) -> int {
+        if constexpr (LOFF) {
+            if (tv.sdim != nullptr) return tv.sdim[h];
+        }
+        return MD < 8 ? lvl % MD : lvl % d;
+    };
     bool more;
     do {
         while (__ballot(p0 == 0 && cur != 0) != 0) {
             if (cur != 0 && p1 == 0) {
                 const int lvl = 31 - __clz(cur);
                 const T s = M::load(tv.split[cur]);
-                const T qd = pick<MD>(q, MD < 8 ? lvl % MD : lvl % d);
+                const T qd = pick<MD>(q, dim_of(cur, lvl));
                 const uint32_t nearc = 2u * cur + (qd >= s ? 1u : 0u);
                 uint32_t next = nearc;
                 if (prev > cur) {
@@ -205,13 +213,14 @@ __device__ inline void kd_search(const TreeView& tv, const Ids& ids, const T (&q
             uint32_t c0 = p0, g0 = 0, g1 = 0;
             if (sub >= 1) {
                 const T s = M::load(tv.split[p0]);
-                const T qd = pick<MD>(q, MD < 8 ? W % MD : W % d);
+                const T qd = pick<MD>(q, dim_of(p0, W));
                 c0 = 2u * p0 + (qd >= s ? 1u : 0u);
             }
             if (sub == 2) {
-                const T qd = pick<MD>(q, MD < 8 ? (W + 1) % MD : (W + 1) % d);
-                g0 = qd >= M::load(tv.split[c0]) ? 1u : 0u;
-                g1 = qd >= M::load(tv.split[c0 ^ 1u]) ? 1u : 0u;
+                const T qd0 = pick<MD>(q, dim_of(c0, W + 1));
+                const T qd1 = pick<MD>(q, dim_of(c0 ^ 1u, W + 1));
+                g0 = qd0 >= M::load(tv.split[c0]) ? 1u : 0u;
+                g1 = qd1 >= M::load(tv.split[c0 ^ 1u]) ? 1u : 0u;
             }
             for (int t = 0; t < (1 << sub); t++) {
                 uint32_t lh = c0 ^ (uint32_t)t;

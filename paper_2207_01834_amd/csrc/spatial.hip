@@ -3,9 +3,10 @@
 // dimension instead of at the median point).
 //
 // Readings (the paper gives the rule only in words): the space of the root
-// is the bounding box of the points; node (l, j) cuts its cell along
-// dimension l mod d at the cell's midpoint s; its points with coordinate < s
-// go left, the others right.  Midpoints: an int32 cell [lo, hi] is cut at
+// is the bounding box of the points; node (l, j) cuts its cell at the cell's
+// midpoint s along dimension l mod d (rule 0) or along the cell's widest side,
+// the lowest dimension on ties (rule 1); its points with coordinate < s go
+// left, the others right.  Midpoints: an int32 cell [lo, hi] is cut at
 // floor((lo + hi + 1) / 2) into [lo, s - 1] and [s, hi]; a float32 cell at
 // the float nearest (lo + hi) / 2 (sum in double) into [lo, s] and [s, hi].
 // The tree keeps the object-median tree's depth L = min{L : ceil(n/2^L) <=
@@ -71,6 +72,21 @@ __device__ inline void root_cell(const uint32_t* box, int d, bool fl, double (&l
     }
 }
 
+// Split dimension of a cell at level l: l mod d, or its widest side.
+__device__ inline int cell_dim(const double (&lo)[8], const double (&hi)[8], int d, int l, int rule) {
+    if (rule == 0) return l % d;
+    int c = 0;
+    double best = hi[0] - lo[0];
+#pragma unroll
+    for (int cc = 1; cc < 8; cc++) {
+        if (cc < d && hi[cc] - lo[cc] > best) {
+            best = hi[cc] - lo[cc];
+            c = cc;
+        }
+    }
+    return c;
+}
+
 // Halves cell dimension c (runtime) toward `right`; returns the cut.
 __device__ inline double cut_cell(double (&lo)[8], double (&hi)[8], int c, bool right_of, bool fl,
                                   bool go_right) {
@@ -90,7 +106,7 @@ __device__ inline double cut_cell(double (&lo)[8], double (&hi)[8], int c, bool 
 
 // Leaf of every point (input order) and its rank among its leaf's points.
 __global__ void __launch_bounds__(kNT)
-spatial_leaf_kernel(const uint32_t* __restrict__ keys, int64_t n, int d, int L, int fl,
+spatial_leaf_kernel(const uint32_t* __restrict__ keys, int64_t n, int d, int L, int fl, int rule,
                     const uint32_t* __restrict__ box, uint32_t* __restrict__ leaf,
                     uint32_t* __restrict__ rank, uint32_t* __restrict__ cnt) {
     const int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x;
@@ -100,8 +116,8 @@ spatial_leaf_kernel(const uint32_t* __restrict__ keys, int64_t n, int d, int L, 
 #pragma unroll
     for (int c = 0; c < 8; c++) x[c] = c < d ? coord_value(key_to_coord(keys[(int64_t)c * n + i], fl != 0), fl != 0) : 0.0;
     uint32_t j = 0;
-    int c = 0;
     for (int l = 0; l < L; l++) {
+        const int c = cell_dim(lo, hi, d, l, rule);
         double xc = x[0];
 #pragma unroll
         for (int cc = 1; cc < 8; cc++) xc = cc == c ? x[cc] : xc;
@@ -112,33 +128,34 @@ spatial_leaf_kernel(const uint32_t* __restrict__ keys, int64_t n, int d, int L, 
         const bool right = xc >= s;
         cut_cell(lo, hi, c, true, fl != 0, right);
         j = 2u * j + (right ? 1u : 0u);
-        c = c + 1 == d ? 0 : c + 1;
     }
     leaf[i] = j;
     rank[i] = atomicAdd(&cnt[j], 1u);
 }
 
-// Split of internal node h: replay its path from the root, then cut.
+// Split (and dimension, when sdim is given) of internal node h: replay its
+// path from the root, then cut.
 __global__ void __launch_bounds__(kNT)
-spatial_split_kernel(int d, int L, int fl, const uint32_t* __restrict__ box,
-                     uint32_t* __restrict__ split) {
+spatial_split_kernel(int d, int L, int fl, int rule, const uint32_t* __restrict__ box,
+                     uint32_t* __restrict__ split, uint8_t* __restrict__ sdim) {
     const int64_t h = (int64_t)blockIdx.x * kNT + threadIdx.x;
     if (h >= ((int64_t)1 << L)) return;
     if (h == 0) {
         split[0] = 0u;
+        if (sdim) sdim[0] = 0;
         return;
     }
     const int l = 63 - __builtin_clzll((unsigned long long)h);
     double lo[8], hi[8];
     root_cell(box, d, fl != 0, lo, hi);
-    int c = 0;
     for (int t = 0; t < l; t++) {
         const bool right = ((h >> (l - 1 - t)) & 1) != 0;
-        cut_cell(lo, hi, c, true, fl != 0, right);
-        c = c + 1 == d ? 0 : c + 1;
+        cut_cell(lo, hi, cell_dim(lo, hi, d, t, rule), true, fl != 0, right);
     }
+    const int c = cell_dim(lo, hi, d, l, rule);
     const double s = cut_cell(lo, hi, c, false, fl != 0, false);
     split[h] = fl ? __float_as_uint((float)s) : (uint32_t)(int32_t)s;
+    if (sdim) sdim[h] = (uint8_t)c;
 }
 
 __global__ void spatial_offsets_kernel(const uint32_t* __restrict__ start, int64_t leaves, int64_t n,
@@ -173,7 +190,7 @@ spatial_scatter_kernel(const uint32_t* __restrict__ keys, const int32_t* __restr
 
 }  // namespace
 
-pg_status build_tree_spatial(const void* points, int64_t n, int d, int leaf, int dtype,
+pg_status build_tree_spatial(const void* points, int64_t n, int d, int leaf, int dtype, int rule,
                              hipStream_t s, pg_tree* T) {
     const bool fl = dtype == PG_FLOAT32;
     T->n = n;
@@ -193,7 +210,9 @@ pg_status build_tree_spatial(const void* points, int64_t n, int d, int leaf, int
     T->bbox = T->nbox + (size_t)leaves * 2 * d;
     PG_TRY(dalloc(&T->rec, ((size_t)nn + kTreePad) * rw, s));
     PG_TRY(dalloc(&T->loff, (size_t)leaves + 1, s));
+    if (rule == 1) PG_TRY(dalloc(&T->sdim, (size_t)leaves, s));
     if (n == 0) {
+        if (T->sdim) PG_HIP(hipMemsetAsync(T->sdim, 0, leaves, s));
         PG_HIP(hipMemsetAsync(T->loff, 0, sizeof(int64_t) * (leaves + 1), s));
         PG_HIP(hipMemsetAsync(T->split, 0, sizeof(uint32_t) * leaves, s));
         return offset_boxes(T, s);
@@ -216,7 +235,7 @@ pg_status build_tree_spatial(const void* points, int64_t n, int d, int leaf, int
     PG_TRY(start.alloc(sizeof(uint32_t) * leaves));
     PG_HIP(hipMemsetAsync(cnt.p, 0, sizeof(uint32_t) * leaves, s));
     hipLaunchKernelGGL(spatial_leaf_kernel, dim3(cdiv(n, kNT)), dim3(kNT), 0, s,
-                       keys.as<uint32_t>(), n, d, L, fl ? 1 : 0, box.as<uint32_t>(),
+                       keys.as<uint32_t>(), n, d, L, fl ? 1 : 0, rule, box.as<uint32_t>(),
                        lf.as<uint32_t>(), rk.as<uint32_t>(), cnt.as<uint32_t>());
     PG_LAUNCH_CHECK();
     PG_TRY(exclusive_scan_u32(cnt.as<uint32_t>(), start.as<uint32_t>(), leaves, nullptr, s));
@@ -229,7 +248,7 @@ pg_status build_tree_spatial(const void* points, int64_t n, int d, int leaf, int
                        T->pidx);
     PG_LAUNCH_CHECK();
     hipLaunchKernelGGL(spatial_split_kernel, dim3(cdiv(leaves, kNT)), dim3(kNT), 0, s, d, L,
-                       fl ? 1 : 0, box.as<uint32_t>(), T->split);
+                       fl ? 1 : 0, rule, box.as<uint32_t>(), T->split, T->sdim);
     PG_LAUNCH_CHECK();
     return offset_boxes(T, s);
 }

@@ -35,14 +35,15 @@ def membership(perm, loff):
     return np.sort(leaf * max(len(perm), 1) + perm.astype(np.int64))
 
 
-def check_tree(pg, dev, pts, leaf):
-    t = pg.kdtree_build(to_dev(pts, dev), leaf=leaf, split="spatial")
-    L, s, _, perm, loff = oracle.spatial_tree(pts, leaf=leaf)
+def check_tree(pg, dev, pts, leaf, rule="cycle"):
+    t = pg.kdtree_build(to_dev(pts, dev), leaf=leaf, split="spatial", dim_rule=rule)
+    L, s, dims, perm, loff = oracle.spatial_tree(pts, leaf=leaf, rule=rule)
     assert t.levels == L
     gs, gperm = t.export()
     gloff = t.offsets()
     assert np.array_equal(gloff, loff), "leaf offsets differ"
     assert np.array_equal(gs.astype(np.float64), s[1:]), "split values differ"
+    assert np.array_equal(t.split_dims()[1:].astype(np.int32), dims[1:]), "split dimensions differ"
     assert np.array_equal(membership(gperm, gloff), membership(perm, loff)), "leaf membership differs"
     return t
 
@@ -124,3 +125,35 @@ def test_spatial_full_size(pg, dev):
     rows = np.random.default_rng(4).choice(len(pts), 300, replace=False)
     oi, od = oracle.knn_brute(pts, pts[rows], 10, nthreads=16)
     assert_int_equal(gi[rows], gd[rows], oi, od)
+
+
+@pytest.mark.parametrize("n,d,leaf,dtype", [(20_000, 2, 16, np.int32), (9_000, 3, 8, np.float32),
+                                            (6_000, 5, 4, np.int32), (3_000, 3, 1, np.float32)])
+def test_spatial_widest_rule(pg, dev, n, d, leaf, dtype):
+    # stretched boxes, so the widest side differs from the level's dimension
+    rng = np.random.default_rng(n + d)
+    scale = np.array([1.0, 0.05, 0.4, 2.0, 0.01][:d])
+    if dtype == np.int32:
+        pts = (rng.random((n, d)) * scale * 100_000).astype(np.int32)
+    else:
+        pts = ((rng.standard_normal((n, d)) ** 3) * scale).astype(np.float32)
+    say(f"spatial widest n={n} d={d} leaf={leaf} {np.dtype(dtype).name}")
+    t = check_tree(pg, dev, pts, leaf, rule="widest")
+    assert len(set(t.split_dims()[1:].tolist())) > 1
+    check_knn(t, pts, None, 8, dev)
+    q = pts[rng.integers(0, n, 5_000)]
+    check_knn(t, pts, q, 5, dev)
+    gi, gd = host(*t.knn_graph(4))
+    oi, od = oracle.knn_graph_brute(pts, 4, nthreads=8)
+    if dtype == np.int32:
+        assert_int_equal(gi, gd, oi, od)
+    else:
+        assert_float_close(gi, gd, oi, od, pts, pts)
+    boxes = datagen.range_boxes(pts, float(np.ptp(pts, axis=0).max()) * 0.05 if dtype == np.float32
+                                else int(np.ptp(pts, axis=0).max() * 0.05), seed=3, m=2_000)
+    off, rows = t.range_search(to_dev(boxes, dev))
+    off, rows = host(off, rows)
+    oc, oo, oi = oracle.range_brute(pts, boxes)
+    assert np.array_equal(off, oo)
+    for i in range(0, 2_000, 11):
+        assert np.array_equal(np.sort(rows[off[i]:off[i + 1]].astype(np.int64)), oi[oo[i]:oo[i + 1]])
