@@ -357,6 +357,8 @@ def form_batch(torch, pg, datagen, dev, loop_clouds):
     # knn_self's), and the generic reverse-CSR backward for comparison
     bwd_ms = timed(torch, lambda: Bk.backward(x, idx, d2, g, out=grad))
     gen_ms = timed(torch, lambda: pg.knn_backward(x, x, idx, g, grad_q=grad, self_mode=True))
+    fast_ms = timed(torch, lambda: pg.knn_backward(x, x, idx, g, grad_q=grad, self_mode=True,
+                                                   deterministic=False))
     return {"workload": "4,096 unit-sphere clouds (+N(0,0.01^2)), sizes log-uniform [256,65536], "
                         f"{Ntot} points, per-cloud all-points k=16, float32",
             "tune": tune, "batched_ms": batch_ms, "clouds_per_s": 4096 / (batch_ms * 1e-3),
@@ -364,7 +366,7 @@ def form_batch(torch, pg, datagen, dev, loop_clouds):
             "per_cloud_loop_ms": loop_s * 1e3, "per_cloud_loop_sample_clouds": nc,
             "speedup_vs_per_cloud_loop": loop_s * 1e3 / batch_ms,
             "backward_ms": bwd_ms, "backward_pairs_per_s": Ntot * 16 / (bwd_ms * 1e-3),
-            "backward_generic_ms": gen_ms}
+            "backward_generic_ms": gen_ms, "backward_atomic_ms": fast_ms}
 
 
 # Oracle visit counts per box on the range workload (100,000 sampled boxes):

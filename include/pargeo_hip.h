@@ -396,6 +396,16 @@ pg_status pg_knn_backward(const float* queries, const float* points, int64_t m, 
                           int32_t d, int32_t k, const int32_t* idx, const float* grad_d2,
                           float* grad_q, float* grad_p, void* stream);
 
+/* The same gradients with float atomics for grad_p (each pair subtracts its
+ * term in whatever order the hardware takes them: not bit-reproducible, the
+ * sums differ by rounding only).  Arguments, aliasing and errors as
+ * pg_knn_backward; grad_q is the same deterministic per-query sum.  On the
+ * 4,096-cloud workload it is slower than both deterministic kernels (random
+ * float atomics bound it); it is kept as the plain reference form. */
+pg_status pg_knn_backward_atomic(const float* queries, const float* points, int64_t m, int64_t n,
+                               int32_t d, int32_t k, const int32_t* idx, const float* grad_d2,
+                               float* grad_q, float* grad_p, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -81,6 +81,7 @@ SIGNATURES = {
     "pg_batch_autotune": (i32, [vp, P64, i32, i32, i32, vp, vp]),
     "pg_batch_free": (None, [vp]),
     "pg_knn_backward": (i32, [vp, vp, i64, i64, i32, i32, vp, vp, vp, vp, vp]),
+    "pg_knn_backward_atomic": (i32, [vp, vp, i64, i64, i32, i32, vp, vp, vp, vp, vp]),
     "pg_batch_backward": (i32, [vp, vp, i32, vp, vp, vp, vp, vp]),
 }
 
@@ -462,9 +463,12 @@ def batch_autotune(points: torch.Tensor, offsets, k: int):
             "klist": t.klist}
 
 
-def knn_backward(queries, points, idx, grad_d2, grad_q=None, grad_p=None, self_mode=False):
+def knn_backward(queries, points, idx, grad_d2, grad_q=None, grad_p=None, self_mode=False,
+                 deterministic=True):
     """Gradients of sum g * D with fixed neighbours (see pg_knn_backward).
-    self_mode: queries is points, one gradient array receives both roles."""
+    self_mode: queries is points, one gradient array receives both roles.
+    deterministic=False: float atomics for the point gradients
+    (pg_knn_backward_atomic; equal up to rounding, not bit-reproducible)."""
     q = _points(queries, "queries")
     x = _points(points, "points")
     idx = idx.contiguous()
@@ -478,10 +482,11 @@ def knn_backward(queries, points, idx, grad_d2, grad_q=None, grad_p=None, self_m
     else:
         gq = torch.empty_like(q) if grad_q is None else grad_q
         gp = torch.empty_like(x) if grad_p is None else grad_p
-    check(lib().pg_knn_backward(ctypes.c_void_p(q.data_ptr()), ctypes.c_void_p(x.data_ptr()), m, n,
-                                d, k, ctypes.c_void_p(idx.data_ptr()), ctypes.c_void_p(g.data_ptr()),
-                                ctypes.c_void_p(gq.data_ptr()), ctypes.c_void_p(gp.data_ptr()),
-                                stream_ptr(q.device)))
+    fn = lib().pg_knn_backward if deterministic else lib().pg_knn_backward_atomic
+    check(fn(ctypes.c_void_p(q.data_ptr()), ctypes.c_void_p(x.data_ptr()), m, n,
+             d, k, ctypes.c_void_p(idx.data_ptr()), ctypes.c_void_p(g.data_ptr()),
+             ctypes.c_void_p(gq.data_ptr()), ctypes.c_void_p(gp.data_ptr()),
+             stream_ptr(q.device)))
     return gq, gp
 
 

@@ -238,6 +238,27 @@ __global__ void grad_q_kernel(const float* __restrict__ q, const float* __restri
     gq[t] = acc;
 }
 
+// Atomic form: every pair subtracts its term from grad_p[j] with a float
+// atomic (the order of the adds, hence the rounding, varies between runs).
+__global__ void grad_x_atomic_kernel(const float* __restrict__ q, const float* __restrict__ x,
+                                     int64_t P, int64_t n, int d, int k,
+                                     const int32_t* __restrict__ idx, const float* __restrict__ g,
+                                     float* __restrict__ gx) {
+    const int64_t p = (int64_t)blockIdx.x * kNT + threadIdx.x;
+    if (p >= P) return;
+    const int32_t j = idx[p];
+    if (j < 0 || j >= n) return;
+    const int64_t i = p / k;
+    const float w = 2.0f * g[p];
+    for (int c = 0; c < d; c++)
+        atomicAdd(&gx[(int64_t)j * d + c], -w * (q[i * d + c] - x[(int64_t)j * d + c]));
+}
+
+__global__ void zero_f32_kernel(float* __restrict__ a, int64_t count) {
+    const int64_t t = (int64_t)blockIdx.x * kNT + threadIdx.x;
+    if (t < count) a[t] = 0.0f;
+}
+
 __global__ void pair_count_kernel(const int32_t* __restrict__ idx, int64_t P, int64_t n,
                                   uint32_t* __restrict__ cnt) {
     const int64_t p = (int64_t)blockIdx.x * kNT + threadIdx.x;
@@ -910,6 +931,37 @@ pg_status pg_batch_backward(pg_batch* b, const float* points, int32_t k, const i
                        (const int64_t*)b->bstart_dev, C, pidx, d, wbuf.as<unsigned long long>(),
                        acc.as<unsigned long long>(), maxes.as<uint32_t>(), grad_points);
     PG_LAUNCH_CHECK();
+    return PG_OK;
+}
+
+pg_status pg_knn_backward_atomic(const float* queries, const float* points, int64_t m, int64_t n,
+                               int32_t d, int32_t k, const int32_t* idx, const float* grad_d2,
+                               float* grad_q, float* grad_p, void* stream) {
+    if (d < 1 || d > 8 || k < 1 || k > 64) return fail(PG_ERR_INVALID, "pg_knn_backward_atomic: bad d or k");
+    if (m < 0 || n < 0 || m * (int64_t)k >= ((int64_t)1 << 32) || n >= ((int64_t)1 << 31))
+        return fail(PG_ERR_INVALID, "pg_knn_backward_atomic: bad sizes");
+    if ((m > 0 && (!queries || !idx || !grad_d2 || !grad_q)) || (n > 0 && (!points || !grad_p)))
+        return fail(PG_ERR_INVALID, "pg_knn_backward_atomic: NULL pointer");
+    const bool alias = grad_q == grad_p;
+    if (alias && (queries != points || m != n))
+        return fail(PG_ERR_INVALID, "pg_knn_backward_atomic: grad_q may alias grad_p only when queries == points");
+    hipStream_t s = (hipStream_t)stream;
+    if (m > 0) {
+        hipLaunchKernelGGL(grad_q_kernel, dim3(cdiv(m * d, kNT)), dim3(kNT), 0, s, queries, points,
+                           m, n, d, k, idx, grad_d2, grad_q);
+        PG_LAUNCH_CHECK();
+    }
+    if (n == 0) return PG_OK;
+    if (!alias) {  // aliased: grad_q already overwrote every row
+        hipLaunchKernelGGL(zero_f32_kernel, dim3(cdiv(n * d, kNT)), dim3(kNT), 0, s, grad_p, n * d);
+        PG_LAUNCH_CHECK();
+    }
+    const int64_t P = m * k;
+    if (P > 0) {
+        hipLaunchKernelGGL(grad_x_atomic_kernel, dim3(cdiv(P, kNT)), dim3(kNT), 0, s, queries,
+                           points, P, n, d, k, idx, grad_d2, grad_p);
+        PG_LAUNCH_CHECK();
+    }
     return PG_OK;
 }
 

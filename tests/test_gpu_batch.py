@@ -253,3 +253,34 @@ def test_backward_query_form(pg, dev):
     for got, ref in ((host(q.grad)[0], gq_ref), (host(x.grad)[0], gx_ref)):
         scale = np.abs(ref).max()
         assert np.all(np.abs(got - ref) <= 1e-4 * np.abs(ref) + 1e-4 * scale)
+
+
+@pytest.mark.parametrize("self_mode", [False, True])
+def test_backward_float_atomics(pg, dev, self_mode):
+    # the float-atomic form against the FP64 closed form (same bar as the
+    # deterministic one) and against the deterministic kernel, with padding
+    import torch
+    g = np.random.default_rng(5 + self_mode)
+    X = g.random((4000, 3)).astype(np.float32)
+    Q = X if self_mode else g.random((700, 3)).astype(np.float32)
+    k = 8
+    m = len(Q)
+    idx = g.integers(0, len(X), (m, k)).astype(np.int32)
+    idx[::7, -1] = -1  # padding slots are skipped
+    W = g.standard_normal((m, k)).astype(np.float32)
+    xd = to_dev(X, dev)
+    qd = xd if self_mode else to_dev(Q, dev)  # one tensor in both roles
+    args = (qd, xd, to_dev(idx, dev), to_dev(W, dev))
+    gq_f, gp_f = pg.knn_backward(*args, self_mode=self_mode, deterministic=False)
+    gq_d, gp_d = pg.knn_backward(*args, self_mode=self_mode)
+    gq_f, gp_f, gq_d, gp_d = host(gq_f, gp_f, gq_d, gp_d)
+    gq_ref, gx_ref = grad_closed_form(Q, X, idx, W)
+    if self_mode:
+        refs = [(gq_f, gq_ref + gx_ref), (gq_d, gq_ref + gx_ref)]
+    else:
+        refs = [(gq_f, gq_ref), (gp_f, gx_ref), (gq_d, gq_ref), (gp_d, gx_ref)]
+    for got, ref in refs:
+        scale = np.abs(ref).max()
+        assert np.all(np.abs(got - ref) <= 1e-4 * np.abs(ref) + 1e-4 * scale)
+    if not self_mode:
+        assert np.array_equal(gq_f, gq_d)  # the per-query sums are the same kernel
