@@ -50,6 +50,23 @@ typedef enum { PG_INT32 = 0, PG_FLOAT32 = 1 } pg_dtype;
 typedef struct pg_tree pg_tree;
 typedef struct pg_bdl pg_bdl;
 
+/* Device memory.  By default the library allocates stream-ordered from the
+ * device's pool (hipMallocAsync / hipFreeAsync).  pg_set_allocator installs
+ * the caller's allocator instead (a framework's caching allocator, say):
+ * alloc(bytes, stream, ctx) returns device memory usable in stream order on
+ * `stream` (NULL on failure: the call returns PG_ERR_NOMEM), release(p,
+ * stream, ctx) takes back a block after the work queued on `stream` so far.
+ * NULL restores the default.  Returns PG_ERR_INVALID while the library
+ * holds any device block (free every handle first, so each block goes back
+ * to the allocator that made it) or when only one of the two functions is
+ * given.  Not thread-safe against concurrent library calls. */
+typedef struct {
+    void* (*alloc)(size_t bytes, void* stream, void* ctx);
+    void (*release)(void* p, void* stream, void* ctx);
+    void* ctx;
+} pg_allocator;
+pg_status pg_set_allocator(const pg_allocator* a);
+
 /* Text of the last non-OK status on this thread (never NULL). */
 const char* pg_last_error(void);
 /* Library version string (host). */

@@ -37,7 +37,15 @@ P64 = ctypes.POINTER(ctypes.c_int64)
 P32 = ctypes.POINTER(ctypes.c_int32)
 
 # name -> (restype, argtypes); the declarations of include/pargeo_hip.h
+class Allocator(ctypes.Structure):
+    _fields_ = [("alloc", ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                                           ctypes.c_void_p)),
+                ("release", ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)),
+                ("ctx", ctypes.c_void_p)]
+
+
 SIGNATURES = {
+    "pg_set_allocator": (i32, [ctypes.POINTER(Allocator)]),
     "pg_last_error": (ctypes.c_char_p, []),
     "pg_version": (ctypes.c_char_p, []),
     "pg_kdtree_build": (i32, [vp, i64, i32, i32, i32, vp, ctypes.POINTER(vp)]),
@@ -603,3 +611,30 @@ class B1Tree:
 
     def size(self) -> int:
         return lib().pg_b1_size(self._h)
+
+
+_torch_allocator = None
+
+
+def use_torch_allocator(enable: bool = True):
+    """Routes the library's device allocations through torch's caching
+    allocator (pg_set_allocator), or back to the library's own pool."""
+    global _torch_allocator
+    if not enable:
+        check(lib().pg_set_allocator(None))
+        _torch_allocator = None
+        return
+    A = Allocator._fields_
+
+    def _alloc(nbytes, stream, ctx):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), stream=int(stream or 0))
+        except Exception:
+            return None
+
+    def _release(p, stream, ctx):
+        torch.cuda.caching_allocator_delete(p)
+
+    a = Allocator(A[0][1](_alloc), A[1][1](_release), None)
+    check(lib().pg_set_allocator(ctypes.byref(a)))
+    _torch_allocator = a  # keep the callbacks alive

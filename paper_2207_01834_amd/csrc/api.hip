@@ -1,4 +1,5 @@
 // C ABI of libpargeo_hip.so: argument validation, handles, memory, errors.
+#include <atomic>
 #include <mutex>
 #include <new>
 #include <string>
@@ -32,7 +33,23 @@ pg_status fail(pg_status st, const std::string& msg) {
     return st;
 }
 
+namespace {
+// The caller's allocator (pg_set_allocator), and the number of device
+// blocks not yet released (either allocator's): the allocator may only be
+// replaced while none are held, so every block goes back to its maker.
+pg_allocator g_alloc = {nullptr, nullptr, nullptr};
+std::atomic<int64_t> g_outstanding{0};
+}  // namespace
+
 pg_status dmalloc(void** p, size_t bytes, hipStream_t s) {
+    if (g_alloc.alloc) {
+        *p = g_alloc.alloc(bytes ? bytes : 4, (void*)s, g_alloc.ctx);
+        if (!*p)
+            return fail(PG_ERR_NOMEM, std::string("allocator returned NULL for ") +
+                                          std::to_string(bytes) + " bytes");
+        g_outstanding++;
+        return PG_OK;
+    }
     std::call_once(g_pool_once, configure_pool);
     hipError_t e = hipMallocAsync(p, bytes ? bytes : 4, s);
     if (e != hipSuccess) {
@@ -41,11 +58,18 @@ pg_status dmalloc(void** p, size_t bytes, hipStream_t s) {
                     std::string("hipMallocAsync(") + std::to_string(bytes) + "): " +
                         hipGetErrorString(e));
     }
+    g_outstanding++;
     return PG_OK;
 }
 
 void dfree(void* p, hipStream_t s) {
-    if (p) (void)hipFreeAsync(p, s);
+    if (!p) return;
+    g_outstanding--;
+    if (g_alloc.release) {
+        g_alloc.release(p, (void*)s, g_alloc.ctx);
+        return;
+    }
+    (void)hipFreeAsync(p, s);
 }
 
 static void tree_release(pg_tree* t) {
@@ -69,6 +93,16 @@ extern "C" {
 const char* pg_last_error(void) { return g_last_error.c_str(); }
 
 const char* pg_version(void) { return "pargeo_hip 0.1 (gfx950)"; }
+
+pg_status pg_set_allocator(const pg_allocator* a) {
+    if (a && (!a->alloc || !a->release))
+        return fail(PG_ERR_INVALID, "pg_set_allocator: alloc and release must both be set");
+    if (g_outstanding.load() != 0)
+        return fail(PG_ERR_INVALID, "pg_set_allocator: " + std::to_string(g_outstanding.load()) +
+                                        " device blocks are still held (free every handle first)");
+    g_alloc = a ? *a : pg_allocator{nullptr, nullptr, nullptr};
+    return PG_OK;
+}
 
 pg_status pg_kdtree_build(const void* points, int64_t n, int32_t d, int32_t leaf, int32_t dtype,
                           void* stream, pg_tree** out) {

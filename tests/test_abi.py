@@ -117,3 +117,12 @@ def test_baseline_argument_errors(L):
     assert L.pg_b1_knn(h, fake, 1, 0, fake, fake, None) == 1 and "k must be" in _err(L)
     assert L.pg_b1_size(h) == 0
     L.pg_b1_free(h)
+
+
+def test_set_allocator_arguments(L):
+    from paper_2207_01834_amd import _binding
+    assert L.pg_set_allocator(None) == 0
+    half = _binding.Allocator()
+    half.alloc = _binding.Allocator._fields_[0][1](lambda n, s, c: None)
+    assert L.pg_set_allocator(ctypes.byref(half)) == 1 and "both" in _err(L)
+    assert L.pg_set_allocator(None) == 0

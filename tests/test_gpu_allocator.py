@@ -1,0 +1,47 @@
+"""pg_set_allocator through the C ABI: torch's caching allocator serves every
+device block of a build and a search (the device memory torch reports grows
+while the tree lives), the results equal those made with the library's own
+pool, and the allocator can be switched back once the tree is freed."""
+import gc
+
+import numpy as np
+import pytest
+
+from paper_2207_01834_amd import datagen
+from parity import say
+
+pytestmark = pytest.mark.gpu
+
+
+def test_torch_caching_allocator(dev):
+    import torch
+
+    import paper_2207_01834_amd._binding as pg
+    gc.collect()
+    pts = datagen.uniform_int(200_000, 3, seed=8)
+    x = torch.from_numpy(pts).to(dev)
+    t = pg.kdtree_build(x, leaf=16)
+    ref_i, ref_d = t.knn_all(10)
+    torch.cuda.synchronize()
+    ref_i, ref_d = ref_i.cpu(), ref_d.cpu()
+    del t
+    gc.collect()
+    say("switching to torch's caching allocator")
+    pg.use_torch_allocator(True)
+    try:
+        before = torch.cuda.memory_allocated(dev)
+        t = pg.kdtree_build(x, leaf=16)
+        torch.cuda.synchronize()
+        held = torch.cuda.memory_allocated(dev) - before
+        assert held > 200_000 * 3 * 4  # the tree's arrays came from torch
+        gi, gd = t.knn_all(10)
+        torch.cuda.synchronize()
+        assert torch.equal(gi.cpu(), ref_i) and torch.equal(gd.cpu(), ref_d)
+        with pytest.raises(pg.PargeoError):
+            pg.use_torch_allocator(False)  # the tree still holds blocks
+        del t, gi, gd
+        gc.collect()
+        torch.cuda.synchronize()
+    finally:
+        pg.use_torch_allocator(False)
+    assert torch.cuda.memory_allocated(dev) <= before + 16 * 1024 * 1024
