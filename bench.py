@@ -327,6 +327,101 @@ def form_baselines(torch, pg, datagen, dev, rounds):
     return out
 
 
+def wall_ms(torch, fn):
+    """Milliseconds of one fn() call between two device synchronisations
+    (the update calls synchronise inside, so events would miss host work)."""
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3, r
+
+
+def grow_tree(torch, pg, kind, d, chunks, dev):
+    """One tree of `kind` (bdl, b1, b2) grown from device batches in order;
+    B2 is built over the first batch (its splits come from it).  Returns the
+    tree and the milliseconds of each batch."""
+    G, ms = None, []
+    for c in chunks:
+        if G is None and kind == "b2":
+            t, G = wall_ms(torch, lambda: pg.B2Tree(c, leaf=LEAF))
+        else:
+            if G is None:
+                G = pg.BDLTree(d, torch.int32, leaf=LEAF, X=1 << 14, device=dev) if kind == "bdl" \
+                    else pg.B1Tree(d, torch.int32, leaf=LEAF, device=dev)
+            t, _ = wall_ms(torch, lambda: G.insert(c))
+        ms.append(t)
+    return G, ms
+
+
+def form_sec63(torch, pg, datagen, dev, n=N):
+    """The BDL-tree against its two baselines under the protocols of
+    Section 6.3 (Figure 3: the 7-D uniform 10M set -- construction in one
+    batch, 10 batches of 10% inserted into an empty tree, 10 batches of 10%
+    erased from the full tree, k-NN of every point for k = 5) and of the
+    appendix on incrementally built trees (each tree grown from 20 batches of
+    5% of the 2-D VisualVar-style and the 7-D uniform 10M sets, then k-NN of
+    every point for k = 2..11).  Throughputs are operations per second."""
+    import numpy as np
+    kinds = ("bdl", "b1", "b2")
+    out = {"n": n, "workload": "Section 6.3 protocols: 7-D uniform int32 10M (construction, 10x10% insert, "
+                       "10x10% erase, k-NN k=5 of all points); grown from 20x5% batches, k-NN of all "
+                       "points for k=2..11 on 2-D VisualVar-style and 7-D uniform 10M; leaf 16, X=2^14"}
+    x7 = torch.from_numpy(datagen.uniform_int(n, 7, seed=63)).to(dev)
+    tenth = list(torch.chunk(x7, 10))
+    order = torch.from_numpy(datagen.rng(64).permutation(n)).to(dev)
+    erase_batches = [x7.index_select(0, b) for b in torch.chunk(order, 10)]
+    fig3 = {}
+    for kind in kinds:
+        log(f"sec63 7d {kind}: construction + k-NN k=5")
+        G, ms = grow_tree(torch, pg, kind, 7, [x7], dev)
+        build = ms[0]
+        G.knn(x7[:4096], 5)
+        knn5 = timed(torch, lambda: G.knn(x7, 5), reps=1)
+        log(f"sec63 7d {kind}: 10 erases of 10%")
+        era = []
+        for E in erase_batches:
+            t, cnt = wall_ms(torch, lambda: G.erase(E))
+            era.append(t)
+        left = G.size()
+        del G
+        log(f"sec63 7d {kind}: 10 inserts of 10%")
+        G, ins = grow_tree(torch, pg, kind, 7, tenth, dev)
+        del G
+        torch.cuda.empty_cache()
+        fig3[kind] = {"construction_ms": build, "construction_pts_s": n / (build * 1e-3),
+                      "insert_ms_total": float(np.sum(ins)), "insert_pts_s": n / (np.sum(ins) * 1e-3),
+                      "erase_ms_total": float(np.sum(era)), "erase_pts_s": n / (np.sum(era) * 1e-3),
+                      "knn5_ms": knn5, "knn5_qps": n / (knn5 * 1e-3),
+                      "insert_ms_per_batch": [round(v, 2) for v in ins],
+                      "erase_ms_per_batch": [round(v, 2) for v in era], "live_after_erase": left}
+    out["fig3_7d_uniform"] = fig3
+    del tenth, erase_batches, order
+    vary = {}
+    for name, pts in (("2d_visualvar", None), ("7d_uniform", x7)):
+        if pts is None:
+            pts = torch.from_numpy(datagen.visual_var(n, 2, seed=65)).to(dev)
+        d = pts.shape[1]
+        chunks = list(torch.chunk(pts, 20))
+        res = {}
+        for kind in kinds:
+            log(f"sec63 {name} {kind}: grow from 20 batches of 5%, k-NN k=2..11")
+            G, ms = grow_tree(torch, pg, kind, d, chunks, dev)
+            qps = {}
+            for k in range(2, 12):
+                G.knn(pts[:4096], k)  # first launch of this k's kernels
+                qps[str(k)] = n / (timed(torch, lambda: G.knn(pts, k), reps=1) * 1e-3)
+            res[kind] = {"grow_ms_total": float(np.sum(ms)), "knn_qps": qps}
+            if kind == "b2":
+                res[kind]["levels"] = G.stats()[1]
+            del G
+            torch.cuda.empty_cache()
+        vary[name] = res
+        del chunks
+    out["vary_k_grown_20x5pct"] = vary
+    return out
+
+
 def form_batch(torch, pg, datagen, dev, loop_clouds):
     """4,096 sphere clouds (sizes log-uniform in [256, 65536]), per-cloud
     all-points k = 16 in one persistent launch, against the per-cloud static
@@ -433,8 +528,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms", default="all",
                     help="other forms to measure after the headline step: all, none, or a "
-                         "comma list of static_float,clustered,spatial,bdl,baselines,batch,range,graph")
+                         "comma list of static_float,clustered,spatial,bdl,baselines,batch,range,graph "
+                         "(sec63, the Section 6.3 protocols on 10M-point sets, runs only when named)")
     ap.add_argument("--bdl-rounds", type=int, default=10)
+    ap.add_argument("--sec63-n", type=int, default=N, help="set size of the sec63 form")
     ap.add_argument("--loop-clouds", type=int, default=512,
                     help="clouds timed for the per-cloud comparison (projected to 4,096)")
     ap.add_argument("--copy-probe-mib", type=int, default=1024,
@@ -565,6 +662,8 @@ def main():
             out[f] = form_baselines(torch, pg, datagen, dev, args.bdl_rounds)
         elif f == "graph":
             out[f] = form_graph(torch, pg, datagen, dev)
+        elif f == "sec63":
+            out[f] = form_sec63(torch, pg, datagen, dev, args.sec63_n)
         elif f == "range":
             out[f] = form_range(torch, pg, datagen, dev, not args.no_cpu_baseline)
         else:

@@ -15,6 +15,8 @@ Workload shapes (Section 6, "Data Sets"; Table 1):
     clustered generator (which is not available here);
   * many small clouds on the unit sphere with a thin noise shell, standing in
     for the OnSphere data set (surface thickness);
+  * a variable-density random-walk generator standing in for the paper's
+    VisualVar (V) data sets;
   * batch updates of 10% of the data set (Section 6.3 insertion/deletion
     experiments).
 """
@@ -70,6 +72,45 @@ def clustered(n: int, d: int, seed: int, n_clusters: int = 1000,
         return pts
     gq = rng(query_seed if query_seed is not None else seed + 31)
     return pts, draw(gq, n_queries)
+
+
+def visual_var(n: int, d: int, seed: int, restart_prob: float = 1e-4,
+               radius_exp=(-3.5, -1.5), step_frac: float = 0.05,
+               bits: int = COORD_BITS) -> np.ndarray:
+    """Variable-density clustered int32 points in [0, 2^bits)^d, standing in
+    for the paper's VisualVar data sets (Section 6, "Data Sets": a random
+    walk through a local region that jumps to a random location now and
+    then).  A walker starts at a uniform location with a local radius
+    r = 2^bits * 10^U(radius_exp); each point lies uniformly in the cube of
+    half side r around the walker, which then moves step_frac * r in a
+    uniformly random direction, or, with probability ``restart_prob``, jumps to a fresh
+    uniform location and draws a fresh radius (so clusters differ in density
+    by the spread of ``radius_exp``).  Coordinates wrap around the domain,
+    and the rows come out in a random order (a data set carries no order, so
+    a batch of consecutive rows samples every cluster)."""
+    g = rng(seed)
+    side = float(1 << bits)
+    jump = g.random(n) < restart_prob
+    if n:
+        jump[0] = True
+    seg = np.cumsum(jump) - 1
+    walks = int(seg[-1]) + 1 if n else 0
+    start = g.random((walks, d)) * side
+    radius = side * 10.0 ** g.uniform(radius_exp[0], radius_exp[1], size=walks)
+    r = radius[seg][:, None]
+    step = g.standard_normal((n, d))
+    nrm = np.sqrt(np.sum(step * step, axis=1, keepdims=True))
+    nrm[nrm == 0] = 1.0
+    step *= step_frac * r / nrm
+    # walker position before point i: its walk's start plus the steps taken
+    # since then (a running sum restarted at every jump)
+    run = np.cumsum(step, axis=0) - step
+    first = np.flatnonzero(jump)
+    pos = start[seg] + run - run[first][seg]
+    del run, step
+    pos += (2.0 * g.random((n, d)) - 1.0) * r
+    out = np.floor(np.mod(pos, side)).astype(np.int64).clip(0, (1 << bits) - 1).astype(np.int32)
+    return out[g.permutation(n)]
 
 
 def cloud_sizes(n_clouds: int, seed: int, lo: int = 256, hi: int = 65536) -> np.ndarray:

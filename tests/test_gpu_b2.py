@@ -157,3 +157,36 @@ def test_b2_full_size_sampled(pg, dev):
         rows = np.random.default_rng(r).choice(len(rd["queries"]), 300, replace=False)
         oi, od = oracle.knn_brute(pts, rd["queries"][rows], 10, ids=ids, nthreads=16)
         assert_int_equal(gi[rows], gd[rows], oi, od)
+
+
+@pytest.mark.parametrize("d,n,gen", [(2, 20_000, "visual_var"), (7, 8_000, "uniform_int")])
+def test_trees_grown_from_batches_vary_k(pg, dev, d, n, gen):
+    """The k-NN-vs-k setting of the paper's appendix on incrementally built
+    trees: BDL, B1 and B2 each grown from 20 batches of 5% of the set, then
+    every point queried for k = 2..11 (ids are insertion counters, so row r
+    of the set has id r)."""
+    import torch
+    pts = getattr(datagen, gen)(n, d, seed=40 + d)
+    chunks = np.array_split(pts, 20)
+    P = to_dev(pts, dev)
+    for kind in ("bdl", "b1", "b2"):
+        say(f"grown {kind} d={d} n={n} {gen}")
+        G = None
+        for c in chunks:
+            C = to_dev(c, dev)
+            if G is None and kind == "b2":
+                G = pg.B2Tree(C, leaf=16)
+                continue
+            if G is None:
+                cls = pg.BDLTree if kind == "bdl" else pg.B1Tree
+                G = cls(d, torch.int32, leaf=16, device=dev)
+            G.insert(C)
+        assert G.size() == n
+        if kind == "b2":
+            stored, levels = G.stats()
+            assert stored == n
+        for k in (2, 5, 11):
+            gi, gd = host(*G.knn(P, k))
+            oi, od = oracle.knn_brute(pts, pts, k, nthreads=8)
+            assert_int_equal(gi, gd, oi, od)
+        del G
