@@ -337,18 +337,18 @@ def wall_ms(torch, fn):
     return (time.perf_counter() - t0) * 1e3, r
 
 
-def grow_tree(torch, pg, kind, d, chunks, dev):
+def grow_tree(torch, pg, kind, d, chunks, dev, split="object"):
     """One tree of `kind` (bdl, b1, b2) grown from device batches in order;
     B2 is built over the first batch (its splits come from it).  Returns the
     tree and the milliseconds of each batch."""
     G, ms = None, []
     for c in chunks:
         if G is None and kind == "b2":
-            t, G = wall_ms(torch, lambda: pg.B2Tree(c, leaf=LEAF))
+            t, G = wall_ms(torch, lambda: pg.B2Tree(c, leaf=LEAF, split=split))
         else:
             if G is None:
-                G = pg.BDLTree(d, torch.int32, leaf=LEAF, X=1 << 14, device=dev) if kind == "bdl" \
-                    else pg.B1Tree(d, torch.int32, leaf=LEAF, device=dev)
+                G = pg.BDLTree(d, torch.int32, leaf=LEAF, X=1 << 14, device=dev, split=split) \
+                    if kind == "bdl" else pg.B1Tree(d, torch.int32, leaf=LEAF, device=dev, split=split)
             t, _ = wall_ms(torch, lambda: G.insert(c))
         ms.append(t)
     return G, ms
@@ -358,38 +358,39 @@ def form_sec63(torch, pg, datagen, dev, n=N):
     """The BDL-tree against its two baselines under the protocols of
     Section 6.3 (Figure 3: the 7-D uniform 10M set -- construction in one
     batch, 10 batches of 10% inserted into an empty tree, 10 batches of 10%
-    erased from the full tree, k-NN of every point for k = 5) and of the
+    erased from the full tree, k-NN of every point for k = 5 -- each with
+    object- and spatial-median splits) and of the
     appendix on incrementally built trees (each tree grown from 20 batches of
     5% of the 2-D VisualVar-style and the 7-D uniform 10M sets, then k-NN of
     every point for k = 2..11).  Throughputs are operations per second."""
     import numpy as np
     kinds = ("bdl", "b1", "b2")
     out = {"n": n, "workload": "Section 6.3 protocols: 7-D uniform int32 10M (construction, 10x10% insert, "
-                       "10x10% erase, k-NN k=5 of all points); grown from 20x5% batches, k-NN of all "
+                       "10x10% erase, k-NN k=5 of all points; object and spatial median); grown from 20x5% batches, k-NN of all "
                        "points for k=2..11 on 2-D VisualVar-style and 7-D uniform 10M; leaf 16, X=2^14"}
     x7 = torch.from_numpy(datagen.uniform_int(n, 7, seed=63)).to(dev)
     tenth = list(torch.chunk(x7, 10))
     order = torch.from_numpy(datagen.rng(64).permutation(n)).to(dev)
     erase_batches = [x7.index_select(0, b) for b in torch.chunk(order, 10)]
     fig3 = {}
-    for kind in kinds:
-        log(f"sec63 7d {kind}: construction + k-NN k=5")
-        G, ms = grow_tree(torch, pg, kind, 7, [x7], dev)
+    for split, kind in [(sp, kd) for sp in ("object", "spatial") for kd in kinds]:
+        log(f"sec63 7d {split} {kind}: construction + k-NN k=5")
+        G, ms = grow_tree(torch, pg, kind, 7, [x7], dev, split)
         build = ms[0]
         G.knn(x7[:4096], 5)
         knn5 = timed(torch, lambda: G.knn(x7, 5), reps=1)
-        log(f"sec63 7d {kind}: 10 erases of 10%")
+        log(f"sec63 7d {split} {kind}: 10 erases of 10%")
         era = []
         for E in erase_batches:
             t, cnt = wall_ms(torch, lambda: G.erase(E))
             era.append(t)
         left = G.size()
         del G
-        log(f"sec63 7d {kind}: 10 inserts of 10%")
-        G, ins = grow_tree(torch, pg, kind, 7, tenth, dev)
+        log(f"sec63 7d {split} {kind}: 10 inserts of 10%")
+        G, ins = grow_tree(torch, pg, kind, 7, tenth, dev, split)
         del G
         torch.cuda.empty_cache()
-        fig3[kind] = {"construction_ms": build, "construction_pts_s": n / (build * 1e-3),
+        fig3[f"{split}_{kind}"] = {"construction_ms": build, "construction_pts_s": n / (build * 1e-3),
                       "insert_ms_total": float(np.sum(ins)), "insert_pts_s": n / (np.sum(ins) * 1e-3),
                       "erase_ms_total": float(np.sum(era)), "erase_pts_s": n / (np.sum(era) * 1e-3),
                       "knn5_ms": knn5, "knn5_qps": n / (knn5 * 1e-3),

@@ -222,6 +222,12 @@ pg_status pg_range_search(const pg_tree* t, const void* boxes, int64_t m, int32_
  *   d : 1..8   dtype : PG_INT32 / PG_FLOAT32   leaf : 1..64
  *   buffer_X : X in [1, 2^31) */
 pg_status pg_bdl_create(int32_t d, int32_t dtype, int32_t leaf, int64_t buffer_X, pg_bdl** out);
+/* As pg_bdl_create, but every static tree and the buffer tree is built with
+ * spatial-median splits (Section 6.3 runs each tree both ways; cells halved
+ * as in pg_kdtree_build_spatial, split dimension l mod d).  Results are the
+ * same (same definition on the same live set); only the cost differs. */
+pg_status pg_bdl_create_spatial(int32_t d, int32_t dtype, int32_t leaf, int64_t buffer_X,
+                                pg_bdl** out);
 
 /* Batch insertion (Section 5 "Parallel Batch Insertion"; Algorithm 3).
  *   points   : [m][d] device, the tree's dtype; copied
@@ -269,6 +275,8 @@ typedef struct pg_b1 pg_b1;
 
 /* Creates an empty B1 tree (host only).  d 1..8, leaf 1..64. */
 pg_status pg_b1_create(int32_t d, int32_t dtype, int32_t leaf, pg_b1** out);
+/* As pg_b1_create, rebuilding with spatial-median splits (l mod d). */
+pg_status pg_b1_create_spatial(int32_t d, int32_t dtype, int32_t leaf, pg_b1** out);
 /* Inserts m device points and rebuilds.  first_id as in pg_bdl_insert.
  * Synchronises.  PG_ERR_UNSUPPORTED beyond 2^31 - 1 points. */
 pg_status pg_b1_insert(pg_b1* b, const void* points, int64_t m, void* stream, int64_t* first_id);
@@ -300,6 +308,10 @@ typedef struct pg_b2 pg_b2;
  * pg_kdtree_build.  Synchronises.  PG_ERR_RANGE on an out-of-range point. */
 pg_status pg_b2_create(const void* points, int64_t n, int32_t d, int32_t leaf, int32_t dtype,
                        void* stream, pg_b2** out);
+/* As pg_b2_create, with the fixed splits taken as spatial medians of the
+ * initial points' cells (l mod d); inserts follow the same rule. */
+pg_status pg_b2_create_spatial(const void* points, int64_t n, int32_t d, int32_t leaf,
+                               int32_t dtype, void* stream, pg_b2** out);
 /* Inserts m device points in place (new arrays of the grown size; leaf and
  * internal boxes recomputed).  first_id as in pg_bdl_insert.  Synchronises
  * (range check).  PG_ERR_UNSUPPORTED beyond 2^31 - 1 stored points. */

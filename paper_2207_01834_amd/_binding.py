@@ -62,6 +62,7 @@ SIGNATURES = {
     "pg_range_report": (i32, [vp, vp, i64, vp, vp, i64, vp]),
     "pg_range_search": (i32, [vp, vp, i64, vp, vp, vp, i64, P64, vp]),
     "pg_bdl_create": (i32, [i32, i32, i32, i64, ctypes.POINTER(vp)]),
+    "pg_bdl_create_spatial": (i32, [i32, i32, i32, i64, ctypes.POINTER(vp)]),
     "pg_bdl_insert": (i32, [vp, vp, i64, vp, P64]),
     "pg_bdl_erase": (i32, [vp, vp, i64, vp, P64]),
     "pg_bdl_knn": (i32, [vp, vp, i64, i32, vp, vp, vp]),
@@ -69,12 +70,14 @@ SIGNATURES = {
     "pg_bdl_stats": (i32, [vp, P64, P64, P64, i32]),
     "pg_bdl_free": (None, [vp]),
     "pg_b1_create": (i32, [i32, i32, i32, ctypes.POINTER(vp)]),
+    "pg_b1_create_spatial": (i32, [i32, i32, i32, ctypes.POINTER(vp)]),
     "pg_b1_insert": (i32, [vp, vp, i64, vp, P64]),
     "pg_b1_erase": (i32, [vp, vp, i64, vp, P64]),
     "pg_b1_knn": (i32, [vp, vp, i64, i32, vp, vp, vp]),
     "pg_b1_size": (i64, [vp]),
     "pg_b1_free": (None, [vp]),
     "pg_b2_create": (i32, [vp, i64, i32, i32, i32, vp, ctypes.POINTER(vp)]),
+    "pg_b2_create_spatial": (i32, [vp, i64, i32, i32, i32, vp, ctypes.POINTER(vp)]),
     "pg_b2_insert": (i32, [vp, vp, i64, vp, P64]),
     "pg_b2_erase": (i32, [vp, vp, i64, vp, P64]),
     "pg_b2_knn": (i32, [vp, vp, i64, i32, vp, vp, vp]),
@@ -322,18 +325,26 @@ def kdtree_build(points: torch.Tensor, leaf: int = 16, split: str = "object",
     return KdTree(h, code, p.device)
 
 
+def _dynamic_split(split: str) -> str:
+    if split not in ("object", "spatial"):
+        raise ValueError("split must be 'object' or 'spatial'")
+    return "_spatial" if split == "spatial" else ""
+
+
 class BDLTree:
     """Batch-dynamic kd-tree (Section 5): insert / erase batches, k-NN over the
-    live points.  Ids are a global insertion counter."""
+    live points.  Ids are a global insertion counter.  ``split`` picks object-
+    or spatial-median static trees (Section 6.3 runs both)."""
 
     def __init__(self, d: int, dtype=torch.int32, leaf: int = 16, X: int = 1 << 14,
-                 device="cuda"):
+                 device="cuda", split: str = "object"):
         self.d, self.leaf, self.X = d, leaf, X
         self.dtype = dtype
         self.code = PG_INT32 if dtype == torch.int32 else PG_FLOAT32
         self.device = torch.device(device)
         h = ctypes.c_void_p()
-        check(lib().pg_bdl_create(d, self.code, leaf, X, ctypes.byref(h)))
+        fn = getattr(lib(), "pg_bdl_create" + _dynamic_split(split))
+        check(fn(d, self.code, leaf, X, ctypes.byref(h)))
         self._h = h
 
     def __del__(self):
@@ -503,14 +514,15 @@ class B2Tree:
     points whose splits never change; inserts join the leaf they reach,
     erases leave tombstones.  Same interface as :class:`BDLTree`."""
 
-    def __init__(self, points: torch.Tensor, leaf: int = 16):
+    def __init__(self, points: torch.Tensor, leaf: int = 16, split: str = "object"):
         p = _points(points, "points")
         self.d, self.leaf = p.shape[1], leaf
         self.code = _dtype_code(p)
         self.device = p.device
         h = ctypes.c_void_p()
-        check(lib().pg_b2_create(ctypes.c_void_p(p.data_ptr()), p.shape[0], self.d, leaf, self.code,
-                                 stream_ptr(p.device), ctypes.byref(h)))
+        fn = getattr(lib(), "pg_b2_create" + _dynamic_split(split))
+        check(fn(ctypes.c_void_p(p.data_ptr()), p.shape[0], self.d, leaf, self.code,
+                 stream_ptr(p.device), ctypes.byref(h)))
         self._h = h
 
     def __del__(self):
@@ -566,12 +578,14 @@ class B1Tree:
     points, rebuilt from scratch after every batch.  Same interface as
     :class:`BDLTree`."""
 
-    def __init__(self, d: int, dtype=torch.int32, leaf: int = 16, device="cuda"):
+    def __init__(self, d: int, dtype=torch.int32, leaf: int = 16, device="cuda",
+                 split: str = "object"):
         self.d, self.leaf = d, leaf
         self.code = PG_INT32 if dtype == torch.int32 else PG_FLOAT32
         self.device = torch.device(device)
         h = ctypes.c_void_p()
-        check(lib().pg_b1_create(d, self.code, leaf, ctypes.byref(h)))
+        fn = getattr(lib(), "pg_b1_create" + _dynamic_split(split))
+        check(fn(d, self.code, leaf, ctypes.byref(h)))
         self._h = h
 
     def __del__(self):

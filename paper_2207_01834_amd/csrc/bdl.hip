@@ -213,6 +213,14 @@ pg_status erase_d(const Forest& f, const void* pts, const int32_t* o, int64_t m,
     }
 }
 
+// Trees with explicit leaf offsets (spatial-median splits, B2) take the
+// offset-reading form of the walk; closed-form object-median trees the other.
+template <typename T>
+pg_status erase_any(bool loff, const Forest& f, const void* pts, const int32_t* o, int64_t m, int d,
+                    unsigned long long* e, hipStream_t s) {
+    return loff ? erase_d<T, true>(f, pts, o, m, d, e, s) : erase_d<T, false>(f, pts, o, m, d, e, s);
+}
+
 template <typename T, int MD, int KT, bool EX, bool LOFF>
 pg_status launch_bdl_knn(const Forest& f, const void* q, const int32_t* o, int64_t m, int d, int k,
                          int64_t* oi, void* od, hipStream_t s) {
@@ -246,6 +254,13 @@ pg_status bdl_knn_d(const Forest& f, const void* q, const int32_t* o, int64_t m,
         case 5: return bdl_knn_k<T, 5, LOFF>(f, q, o, m, d, k, oi, od, s);
         default: return bdl_knn_k<T, 8, LOFF>(f, q, o, m, d, k, oi, od, s);
     }
+}
+
+template <typename T>
+pg_status bdl_knn_any(bool loff, const Forest& f, const void* q, const int32_t* o, int64_t m, int d,
+                      int k, int64_t* oi, void* od, hipStream_t s) {
+    return loff ? bdl_knn_d<T, true>(f, q, o, m, d, k, oi, od, s)
+                : bdl_knn_d<T, false>(f, q, o, m, d, k, oi, od, s);
 }
 
 // ---- B2 (Section 6.3's second baseline): one static tree whose splits stay
@@ -343,6 +358,7 @@ __global__ void closed_offsets_kernel(int64_t n, int L, int64_t* __restrict__ lo
 // ---------------------------------------------------------------------------
 struct Bdl {
     int d = 0, leaf = 0, dtype = 0;
+    int split = 0;  // 0: object median; 1: spatial median (split dimension l mod d)
     int64_t X = 0;
     BdlTree tree[kMaxTrees];
     BdlTree buf;
@@ -407,7 +423,8 @@ static pg_status copy_slice(const Bdl& B, const Staged& src, int64_t from, int64
 static pg_status build_bdl_tree(const Bdl& B, const Staged& S, hipStream_t s, BdlTree& out) {
     pg_tree* t = new (std::nothrow) pg_tree();
     if (!t) return fail(PG_ERR_NOMEM, "host allocation failed");
-    pg_status st = build_tree(S.rows, S.count, B.d, B.leaf, B.dtype, s, t);
+    pg_status st = B.split ? build_tree_spatial(S.rows, S.count, B.d, B.leaf, B.dtype, 0, s, t)
+                           : build_tree(S.rows, S.count, B.d, B.leaf, B.dtype, s, t);
     if (st != PG_OK) {
         pg_tree_free(t);
         return st;
@@ -660,7 +677,8 @@ using namespace pg;
 
 extern "C" {
 
-pg_status pg_bdl_create(int32_t d, int32_t dtype, int32_t leaf, int64_t buffer_X, pg_bdl** out) {
+static pg_status bdl_create(int32_t d, int32_t dtype, int32_t leaf, int64_t buffer_X, int split,
+                            pg_bdl** out) {
     if (!out) return fail(PG_ERR_INVALID, "pg_bdl_create: out is NULL");
     if (d < 1 || d > 8) return fail(PG_ERR_INVALID, "pg_bdl_create: d must be in [1, 8]");
     if (leaf < 1 || leaf > 64) return fail(PG_ERR_INVALID, "pg_bdl_create: leaf must be in [1, 64]");
@@ -673,8 +691,18 @@ pg_status pg_bdl_create(int32_t d, int32_t dtype, int32_t leaf, int64_t buffer_X
     h->b.dtype = dtype;
     h->b.leaf = leaf;
     h->b.X = buffer_X;
+    h->b.split = split;
     *out = h;
     return PG_OK;
+}
+
+pg_status pg_bdl_create(int32_t d, int32_t dtype, int32_t leaf, int64_t buffer_X, pg_bdl** out) {
+    return bdl_create(d, dtype, leaf, buffer_X, 0, out);
+}
+
+pg_status pg_bdl_create_spatial(int32_t d, int32_t dtype, int32_t leaf, int64_t buffer_X,
+                                pg_bdl** out) {
+    return bdl_create(d, dtype, leaf, buffer_X, 1, out);
 }
 
 pg_status pg_bdl_insert(pg_bdl* h, const void* points, int64_t m, void* stream, int64_t* first_id) {
@@ -729,8 +757,8 @@ pg_status pg_bdl_erase(pg_bdl* h, const void* points, int64_t m, void* stream, i
         PG_TRY(order_queries(f.s[0].tv, B.dtype == PG_FLOAT32, points, m, s, order));
         o = order.as<int32_t>();
     }
-    if (B.dtype == PG_FLOAT32) PG_TRY(erase_d<float>(f, points, o, m, B.d, e, s));
-    else PG_TRY(erase_d<int32_t>(f, points, o, m, B.d, e, s));
+    if (B.dtype == PG_FLOAT32) PG_TRY(erase_any<float>(B.split, f, points, o, m, B.d, e, s));
+    else PG_TRY(erase_any<int32_t>(B.split, f, points, o, m, B.d, e, s));
     unsigned long long host[kSlots];
     PG_HIP(hipMemcpyAsync(host, e, sizeof(host), hipMemcpyDeviceToHost, s));
     PG_HIP(hipStreamSynchronize(s));
@@ -786,8 +814,9 @@ pg_status pg_bdl_knn(const pg_bdl* h, const void* queries, int64_t m, int32_t k,
         PG_TRY(order_queries(f.s[0].tv, B.dtype == PG_FLOAT32, queries, m, s, order));
         o = order.as<int32_t>();
     }
-    if (B.dtype == PG_FLOAT32) return bdl_knn_d<float>(f, queries, o, m, B.d, k, out_id, out_dist, s);
-    return bdl_knn_d<int32_t>(f, queries, o, m, B.d, k, out_id, out_dist, s);
+    if (B.dtype == PG_FLOAT32)
+        return bdl_knn_any<float>(B.split, f, queries, o, m, B.d, k, out_id, out_dist, s);
+    return bdl_knn_any<int32_t>(B.split, f, queries, o, m, B.d, k, out_id, out_dist, s);
 }
 
 int64_t pg_bdl_size(const pg_bdl* h) {
@@ -815,7 +844,7 @@ void pg_bdl_free(pg_bdl* h) {
     delete h;
 }
 
-pg_status pg_b1_create(int32_t d, int32_t dtype, int32_t leaf, pg_b1** out) {
+static pg_status b1_create(int32_t d, int32_t dtype, int32_t leaf, int split, pg_b1** out) {
     if (!out) return fail(PG_ERR_INVALID, "pg_b1_create: out is NULL");
     if (d < 1 || d > 8) return fail(PG_ERR_INVALID, "pg_b1_create: d must be in [1, 8]");
     if (leaf < 1 || leaf > 64) return fail(PG_ERR_INVALID, "pg_b1_create: leaf must be in [1, 64]");
@@ -825,8 +854,17 @@ pg_status pg_b1_create(int32_t d, int32_t dtype, int32_t leaf, pg_b1** out) {
     h->b.shape.d = d;
     h->b.shape.dtype = dtype;
     h->b.shape.leaf = leaf;
+    h->b.shape.split = split;
     *out = h;
     return PG_OK;
+}
+
+pg_status pg_b1_create(int32_t d, int32_t dtype, int32_t leaf, pg_b1** out) {
+    return b1_create(d, dtype, leaf, 0, out);
+}
+
+pg_status pg_b1_create_spatial(int32_t d, int32_t dtype, int32_t leaf, pg_b1** out) {
+    return b1_create(d, dtype, leaf, 1, out);
 }
 
 pg_status pg_b1_insert(pg_b1* h, const void* points, int64_t m, void* stream, int64_t* first_id) {
@@ -875,8 +913,9 @@ pg_status pg_b1_erase(pg_b1* h, const void* points, int64_t m, void* stream, int
         o = order.as<int32_t>();
     }
     unsigned long long* e = cnt.as<unsigned long long>();
-    if (B.shape.dtype == PG_FLOAT32) PG_TRY(erase_d<float>(f, points, o, m, B.shape.d, e, s));
-    else PG_TRY(erase_d<int32_t>(f, points, o, m, B.shape.d, e, s));
+    const bool lo = B.shape.split != 0;
+    if (B.shape.dtype == PG_FLOAT32) PG_TRY(erase_any<float>(lo, f, points, o, m, B.shape.d, e, s));
+    else PG_TRY(erase_any<int32_t>(lo, f, points, o, m, B.shape.d, e, s));
     unsigned long long host = 0;
     PG_HIP(hipMemcpyAsync(&host, e, sizeof(host), hipMemcpyDeviceToHost, s));
     PG_HIP(hipStreamSynchronize(s));
@@ -906,8 +945,10 @@ pg_status pg_b1_knn(const pg_b1* h, const void* queries, int64_t m, int32_t k, i
         PG_TRY(order_queries(f.s[0].tv, B.shape.dtype == PG_FLOAT32, queries, m, s, order));
         o = order.as<int32_t>();
     }
-    if (B.shape.dtype == PG_FLOAT32) return bdl_knn_d<float>(f, queries, o, m, B.shape.d, k, out_id, out_dist, s);
-    return bdl_knn_d<int32_t>(f, queries, o, m, B.shape.d, k, out_id, out_dist, s);
+    const bool lo = B.shape.split != 0;
+    if (B.shape.dtype == PG_FLOAT32)
+        return bdl_knn_any<float>(lo, f, queries, o, m, B.shape.d, k, out_id, out_dist, s);
+    return bdl_knn_any<int32_t>(lo, f, queries, o, m, B.shape.d, k, out_id, out_dist, s);
 }
 
 int64_t pg_b1_size(const pg_b1* h) { return h ? (h->b.T.t ? h->b.T.live : 0) : -1; }
@@ -918,8 +959,8 @@ void pg_b1_free(pg_b1* h) {
     delete h;
 }
 
-pg_status pg_b2_create(const void* points, int64_t n, int32_t d, int32_t leaf, int32_t dtype,
-                       void* stream, pg_b2** out) {
+static pg_status b2_create(const void* points, int64_t n, int32_t d, int32_t leaf, int32_t dtype,
+                           int split, void* stream, pg_b2** out) {
     if (!out) return fail(PG_ERR_INVALID, "pg_b2_create: out is NULL");
     if (d < 1 || d > 8) return fail(PG_ERR_INVALID, "pg_b2_create: d must be in [1, 8]");
     if (leaf < 1 || leaf > 64) return fail(PG_ERR_INVALID, "pg_b2_create: leaf must be in [1, 64]");
@@ -937,6 +978,7 @@ pg_status pg_b2_create(const void* points, int64_t n, int32_t d, int32_t leaf, i
     shape.d = d;
     shape.leaf = leaf;
     shape.dtype = dtype;
+    shape.split = split;
     DevBuf ids(s);
     pg_status st = ids.alloc(sizeof(int64_t) * (n > 0 ? n : 1));
     if (st == PG_OK && n > 0) {
@@ -950,8 +992,10 @@ pg_status pg_b2_create(const void* points, int64_t n, int32_t d, int32_t leaf, i
     S.count = n;
     if (st == PG_OK) st = build_bdl_tree(shape, S, s, B.T);
     const int64_t leaves = B.T.t ? ((int64_t)1 << B.T.t->L) : 0;
-    if (st == PG_OK) st = dalloc(&B.T.t->loff, (size_t)leaves + 1, s);
-    if (st == PG_OK) {
+    // a spatial-median tree comes with its leaf offsets
+    const bool closed = st == PG_OK && B.T.t->loff == nullptr;
+    if (closed) st = dalloc(&B.T.t->loff, (size_t)leaves + 1, s);
+    if (closed && st == PG_OK) {
         hipLaunchKernelGGL(closed_offsets_kernel, dim3(cdiv(leaves + 1, kNT)), dim3(kNT), 0, s, n,
                            B.T.t->L, B.T.t->loff);
         if (hipGetLastError() != hipSuccess) st = fail(PG_ERR_DEVICE, "pg_b2_create: launch failed");
@@ -964,6 +1008,16 @@ pg_status pg_b2_create(const void* points, int64_t n, int32_t d, int32_t leaf, i
     B.next_id = n;
     *out = h;
     return PG_OK;
+}
+
+pg_status pg_b2_create(const void* points, int64_t n, int32_t d, int32_t leaf, int32_t dtype,
+                       void* stream, pg_b2** out) {
+    return b2_create(points, n, d, leaf, dtype, 0, stream, out);
+}
+
+pg_status pg_b2_create_spatial(const void* points, int64_t n, int32_t d, int32_t leaf, int32_t dtype,
+                               void* stream, pg_b2** out) {
+    return b2_create(points, n, d, leaf, dtype, 1, stream, out);
 }
 
 pg_status pg_b2_insert(pg_b2* h, const void* points, int64_t m, void* stream, int64_t* first_id) {

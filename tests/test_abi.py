@@ -117,6 +117,16 @@ def test_baseline_argument_errors(L):
     assert L.pg_b1_knn(h, fake, 1, 0, fake, fake, None) == 1 and "k must be" in _err(L)
     assert L.pg_b1_size(h) == 0
     L.pg_b1_free(h)
+    # spatial-median forms: the same checks, host-only handles
+    assert L.pg_b1_create_spatial(9, 0, 16, ctypes.byref(out)) == 1 and "d must be" in _err(L)
+    assert L.pg_bdl_create_spatial(3, 0, 16, 0, ctypes.byref(out)) == 1 and "buffer_X" in _err(L)
+    st = L.pg_b2_create_spatial(fake, 10, 3, 65, 0, None, ctypes.byref(out))
+    assert st == 1 and "leaf must be" in _err(L)
+    for make, free in ((lambda o: L.pg_b1_create_spatial(2, 1, 8, o), L.pg_b1_free),
+                       (lambda o: L.pg_bdl_create_spatial(2, 1, 8, 64, o), L.pg_bdl_free)):
+        h = ctypes.c_void_p()
+        assert make(ctypes.byref(h)) == 0 and h.value
+        free(h)
 
 
 def test_set_allocator_arguments(L):

@@ -45,7 +45,8 @@ def check_knn(G, M, q, k, dtype, dev):
         assert_float_close(gr, gd, orr, od, pts, q)
 
 
-def run(pg, dev, d, n0, steps, coord_hi, dtype, seed, k=7, leaf=8, batch=300, kind="b2"):
+def run(pg, dev, d, n0, steps, coord_hi, dtype, seed, k=7, leaf=8, batch=300, kind="b2",
+        split="object"):
     import torch
     g = np.random.default_rng(seed)
 
@@ -55,11 +56,12 @@ def run(pg, dev, d, n0, steps, coord_hi, dtype, seed, k=7, leaf=8, batch=300, ki
         return (np.floor(g.random((cnt, d)) * coord_hi) / coord_hi).astype(np.float32)
 
     init = draw(n0)
-    say(f"{kind} d={d} n0={n0} leaf={leaf} {np.dtype(dtype).name}")
+    say(f"{kind} d={d} n0={n0} leaf={leaf} {np.dtype(dtype).name} split={split}")
     if kind == "b2":
-        G = pg.B2Tree(to_dev(init, dev), leaf=leaf)
+        G = pg.B2Tree(to_dev(init, dev), leaf=leaf, split=split)
     else:
-        G = pg.B1Tree(d, torch.int32 if dtype == np.int32 else torch.float32, leaf=leaf, device=dev)
+        G = pg.B1Tree(d, torch.int32 if dtype == np.int32 else torch.float32, leaf=leaf, device=dev,
+                      split=split)
         assert G.insert(to_dev(init, dev)) == 0
     M = BDLModel(d, 1 << 20, dtype=dtype)
     M.insert(init)
@@ -112,6 +114,17 @@ def test_b1_sequences(pg, dev, d, n0, coord_hi, dtype, leaf):
         batch=200, kind="b1")
 
 
+@pytest.mark.parametrize("kind", ["b1", "b2"])
+@pytest.mark.parametrize("d,n0,coord_hi,dtype,leaf", [(3, 500, 10, np.int32, 8),
+                                                    (2, 3000, 1 << 20, np.int32, 16),
+                                                    (3, 1500, 64, np.float32, 8),
+                                                    (5, 40, 6, np.int32, 1), (2, 0, 100, np.int32, 4)])
+def test_spatial_sequences(pg, dev, kind, d, n0, coord_hi, dtype, leaf):
+    # spatial-median splits (B2: fixed at creation): same live set, same results
+    run(pg, dev, d=d, n0=n0, steps=12, coord_hi=coord_hi, dtype=dtype, seed=70 + d + n0, k=5,
+        leaf=leaf, batch=200, kind=kind, split="spatial")
+
+
 def test_b2_many_queries_ordered(pg, dev):
     # enough queries and erase points to take the leaf-ordered path
     init, rounds = datagen.bdl_rounds(100_000, 2, 10_000, 8_000, 3, seed=7)
@@ -159,8 +172,11 @@ def test_b2_full_size_sampled(pg, dev):
         assert_int_equal(gi[rows], gd[rows], oi, od)
 
 
-@pytest.mark.parametrize("d,n,gen", [(2, 20_000, "visual_var"), (7, 8_000, "uniform_int")])
-def test_trees_grown_from_batches_vary_k(pg, dev, d, n, gen):
+@pytest.mark.parametrize("d,n,gen,split", [(2, 20_000, "visual_var", "object"),
+                                           (7, 8_000, "uniform_int", "object"),
+                                           (2, 20_000, "visual_var", "spatial"),
+                                           (7, 8_000, "uniform_int", "spatial")])
+def test_trees_grown_from_batches_vary_k(pg, dev, d, n, gen, split):
     """The k-NN-vs-k setting of the paper's appendix on incrementally built
     trees: BDL, B1 and B2 each grown from 20 batches of 5% of the set, then
     every point queried for k = 2..11 (ids are insertion counters, so row r
@@ -170,16 +186,16 @@ def test_trees_grown_from_batches_vary_k(pg, dev, d, n, gen):
     chunks = np.array_split(pts, 20)
     P = to_dev(pts, dev)
     for kind in ("bdl", "b1", "b2"):
-        say(f"grown {kind} d={d} n={n} {gen}")
+        say(f"grown {kind} d={d} n={n} {gen} split={split}")
         G = None
         for c in chunks:
             C = to_dev(c, dev)
             if G is None and kind == "b2":
-                G = pg.B2Tree(C, leaf=16)
+                G = pg.B2Tree(C, leaf=16, split=split)
                 continue
             if G is None:
                 cls = pg.BDLTree if kind == "bdl" else pg.B1Tree
-                G = cls(d, torch.int32, leaf=16, device=dev)
+                G = cls(d, torch.int32, leaf=16, device=dev, split=split)
             G.insert(C)
         assert G.size() == n
         if kind == "b2":

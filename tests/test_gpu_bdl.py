@@ -70,10 +70,12 @@ def test_paper_insert_example(pg, dev):
         knn_check(pg, dev, G, M, g.integers(0, 50, size=(40, 2)).astype(np.int32), 5)
 
 
-def _run_sequence(pg, dev, d, X, steps, coord_hi, dtype, seed, k=7, leaf=8):
+def _run_sequence(pg, dev, d, X, steps, coord_hi, dtype, seed, k=7, leaf=8, split="object"):
     import torch
     g = np.random.default_rng(seed)
-    G = pg.BDLTree(d, torch.int32 if dtype == np.int32 else torch.float32, leaf=leaf, X=X, device=dev)
+    say(f"BDL sequence d={d} X={X} leaf={leaf} {np.dtype(dtype).name} split={split}")
+    G = pg.BDLTree(d, torch.int32 if dtype == np.int32 else torch.float32, leaf=leaf, X=X, device=dev,
+                   split=split)
     M = BDLModel(d, X, dtype=dtype)
 
     def draw(cnt):
@@ -128,12 +130,23 @@ def test_random_sequence_d5_leaf1(pg, dev):
     _run_sequence(pg, dev, d=5, X=4, steps=21, coord_hi=6, dtype=np.int32, seed=4, k=3, leaf=1)
 
 
-def test_cfg5_shaped_reduced(pg, dev):
+@pytest.mark.parametrize("d,X,coord_hi,dtype,leaf,k", [(3, 16, 10, np.int32, 8, 7),
+                                                     (2, 64, 1 << 20, np.int32, 16, 10),
+                                                     (3, 32, 64, np.float32, 8, 7),
+                                                     (5, 4, 6, np.int32, 1, 3)])
+def test_random_sequence_spatial(pg, dev, d, X, coord_hi, dtype, leaf, k):
+    # spatial-median static trees: same live set, so the same results
+    _run_sequence(pg, dev, d=d, X=X, steps=18, coord_hi=coord_hi, dtype=dtype, seed=50 + d,
+                  k=k, leaf=leaf, split="spatial")
+
+
+@pytest.mark.parametrize("split", ["object", "spatial"])
+def test_cfg5_shaped_reduced(pg, dev, split):
     """10% rounds as in the BDL experiments: 200k initial points, 3 rounds of
     20k inserts, 20k erases of live points, 20k fresh queries (k = 10)."""
     import torch
     init, rounds = datagen.bdl_rounds(200_000, 3, 20_000, 20_000, 3, seed=5)
-    G = pg.BDLTree(3, torch.int32, leaf=16, X=1024, device=dev)
+    G = pg.BDLTree(3, torch.int32, leaf=16, X=1024, device=dev, split=split)
     M = BDLModel(3, 1024)
     G.insert(to_dev(init, dev))
     M.insert(init)
