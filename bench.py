@@ -144,6 +144,23 @@ def cpu_baseline(pts, sample):
     _, _, cnt = t.knn(pts[rows], K)
     tq = time.perf_counter() - t0
     step_s = tb + tq * len(pts) / sample
+    # the same search, query-parallel: static chunks over every core this
+    # process may run on (the C call releases the interpreter lock)
+    from concurrent.futures import ThreadPoolExecutor
+    threads = min(len(os.sched_getaffinity(0)), 16)
+    psample = min(len(pts), sample * threads)
+    prow = np.random.default_rng(8).choice(len(pts), size=psample, replace=False)
+    chunks = np.array_split(pts[prow], threads)
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(threads) as ex:
+        list(ex.map(lambda c: t.knn(c, K), chunks))
+    tp = time.perf_counter() - t0
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return {
         "value": len(pts) / step_s, "unit": "queries/s", "cores": 1, "kind": "oracle",
         "sample": (f"serial C oracle: full object-median build of all {len(pts):,} points "
@@ -152,6 +169,11 @@ def cpu_baseline(pts, sample):
         "build_mpts_s": len(pts) / tb / 1e6, "knn_qps": sample / tq,
         "visits_per_query": {"internal": cnt[0] / sample, "leaves": cnt[1] / sample,
                              "points": cnt[2] / sample},
+        "query_parallel": {"threads": threads, "cpu": model, "queries": psample,
+                           "knn_qps": psample / tp,
+                           "step_qps": len(pts) / (tb + tp * len(pts) / psample),
+                           "note": "k-NN in static chunks on one thread per core; the build "
+                                   "stays serial"},
     }
 
 
