@@ -148,9 +148,15 @@ wide_hist_kernel(const uint32_t* __restrict__ keys, int64_t n, int l, int bpn,
     __syncthreads();
     const int hs = shift + width;
     const uint64_t pre = (uint64_t)ns[j].prefix >> hs;
-    for (int64_t e = e0 + threadIdx.x; e < e1; e += kNT) {
-        uint32_t k = keys[e];
-        if (((uint64_t)k >> hs) == pre) atomicAdd(&lh[(k >> shift) & (nb - 1)], 1u);
+    constexpr int PER = 8;  // loads issued together
+    for (int64_t b = e0 + threadIdx.x; b < e1; b += PER * kNT) {
+        uint32_t k[PER];
+#pragma unroll
+        for (int i = 0; i < PER; i++) k[i] = b + i * kNT < e1 ? keys[b + i * kNT] : 0u;
+#pragma unroll
+        for (int i = 0; i < PER; i++)
+            if (b + i * kNT < e1 && ((uint64_t)k[i] >> hs) == pre)
+                atomicAdd(&lh[(k[i] >> shift) & (nb - 1)], 1u);
     }
     __syncthreads();
     uint32_t* gh = ghist + j * nb;
@@ -210,9 +216,14 @@ wide_count_kernel(const uint32_t* __restrict__ keys, int64_t n, int l, int bpn,
     const int64_t e1 = min(e0 + kScat, hi);
     const uint32_t v = ns[j].prefix;
     uint64_t acc = 0;  // lt in the low 32 bits, eq in the high 32 bits
-    for (int64_t e = e0 + threadIdx.x; e < e1; e += kNT) {
-        uint32_t k = keys[e];
-        acc += (k < v) ? 1ull : ((k == v) ? (1ull << 32) : 0ull);
+    constexpr int PER = 4;  // loads issued together
+    for (int64_t b = e0 + threadIdx.x; b < e1; b += PER * kNT) {
+        uint32_t k[PER];
+#pragma unroll
+        for (int i = 0; i < PER; i++) k[i] = b + i * kNT < e1 ? keys[b + i * kNT] : 0u;
+#pragma unroll
+        for (int i = 0; i < PER; i++)
+            if (b + i * kNT < e1) acc += (k[i] < v) ? 1ull : ((k[i] == v) ? (1ull << 32) : 0ull);
     }
     acc = wave_sum(acc);
     if (lane_id() == 0) red[threadIdx.x / kWave] = acc;

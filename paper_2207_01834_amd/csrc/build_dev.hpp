@@ -27,18 +27,26 @@ __device__ inline void block_partition_range(const uint32_t* __restrict__ in,
                                              uint32_t teq, uint32_t base_lt, uint32_t base_eq,
                                              uint32_t* lds) {
     constexpr int NW = kBuildNT / kWave;
+    constexpr int PER = 4;  // 64-element groups per step: their loads are issued together
     const int w = threadIdx.x / kWave, lane = lane_id();
     const int64_t part = (c1 - c0 + NW - 1) / NW;
     const int64_t s0 = c0 + w * part < c1 ? c0 + w * part : c1;
     const int64_t s1 = s0 + part < c1 ? s0 + part : c1;
     const uint32_t* keys = in + (int64_t)c * n;
     uint32_t nlt = 0, neq = 0;
-    for (int64_t e0 = s0; e0 < s1; e0 += kWave) {
-        const int64_t e = e0 + lane;
-        const bool valid = e < s1;
-        const uint32_t k = valid ? keys[e] : 0u;
-        nlt += (uint32_t)__popcll(ballot(valid && k < v));
-        neq += (uint32_t)__popcll(ballot(valid && k == v));
+    for (int64_t b0 = s0; b0 < s1; b0 += PER * kWave) {
+        uint32_t k[PER];
+#pragma unroll
+        for (int i = 0; i < PER; i++) {
+            const int64_t e = b0 + i * kWave + lane;
+            k[i] = e < s1 ? keys[e] : 0u;
+        }
+#pragma unroll
+        for (int i = 0; i < PER; i++) {
+            const bool valid = b0 + i * kWave + lane < s1;
+            nlt += (uint32_t)__popcll(ballot(valid && k[i] < v));
+            neq += (uint32_t)__popcll(ballot(valid && k[i] == v));
+        }
     }
     if (lane == 0) {
         lds[w] = nlt;
@@ -51,29 +59,40 @@ __device__ inline void block_partition_range(const uint32_t* __restrict__ in,
         run_eq += lds[NW + i];
     }
     __syncthreads();
-    for (int64_t e0 = s0; e0 < s1; e0 += kWave) {
-        const int64_t e = e0 + lane;
-        const bool valid = e < s1;
-        const uint32_t k = valid ? keys[e] : 0u;
-        const bool lt = valid && k < v;
-        const bool eq = valid && k == v;
-        const uint64_t mlt = ballot(lt), meq = ballot(eq);
-        const uint32_t ltb = run_lt + lane_prefix(mlt);
-        const uint32_t eqb = run_eq + lane_prefix(meq);
-        if (valid) {
-            const uint32_t el = eqb < teq ? eqb : teq;
-            int64_t dest;
-            if (lt) dest = lo + ltb + el;
-            else if (eq && eqb < teq) dest = lo + ltb + eqb;
-            else dest = mid + (e - lo) - (int64_t)(ltb + el);
-            if (dest >= lo && dest < end_node) {  // always true for a consistent split
-                for (int cc = 0; cc < d; cc++)
-                    out[(int64_t)cc * n + dest] = cc == c ? k : in[(int64_t)cc * n + e];
-                out_idx[dest] = in_idx[e];
-            }
+    for (int64_t b0 = s0; b0 < s1; b0 += PER * kWave) {
+        uint32_t k[PER];
+        int32_t ix[PER];
+#pragma unroll
+        for (int i = 0; i < PER; i++) {
+            const int64_t e = b0 + i * kWave + lane;
+            k[i] = e < s1 ? keys[e] : 0u;
+            ix[i] = e < s1 ? in_idx[e] : 0;
         }
-        run_lt += (uint32_t)__popcll(mlt);
-        run_eq += (uint32_t)__popcll(meq);
+        // groups in element order, so the running counts stay in order
+#pragma unroll
+        for (int i = 0; i < PER; i++) {
+            const int64_t e = b0 + i * kWave + lane;
+            const bool valid = e < s1;
+            const bool lt = valid && k[i] < v;
+            const bool eq = valid && k[i] == v;
+            const uint64_t mlt = ballot(lt), meq = ballot(eq);
+            const uint32_t ltb = run_lt + lane_prefix(mlt);
+            const uint32_t eqb = run_eq + lane_prefix(meq);
+            if (valid) {
+                const uint32_t el = eqb < teq ? eqb : teq;
+                int64_t dest;
+                if (lt) dest = lo + ltb + el;
+                else if (eq && eqb < teq) dest = lo + ltb + eqb;
+                else dest = mid + (e - lo) - (int64_t)(ltb + el);
+                if (dest >= lo && dest < end_node) {  // always true for a consistent split
+                    for (int cc = 0; cc < d; cc++)
+                        out[(int64_t)cc * n + dest] = cc == c ? k[i] : in[(int64_t)cc * n + e];
+                    out_idx[dest] = ix[i];
+                }
+            }
+            run_lt += (uint32_t)__popcll(mlt);
+            run_eq += (uint32_t)__popcll(meq);
+        }
     }
 }
 
