@@ -444,9 +444,13 @@ pg_status build_from_keys(uint32_t* kA, int32_t* iA, uint32_t* kB, int32_t* iB, 
         std::swap(cur_i, oth_i);
     }
 
-    const size_t lds = subtree_lds_bytes(d, S);
+    // LDS for the largest subtree present (ceil(n / 2^ls) <= S points), so
+    // that more workgroups fit on a compute unit
+    const int64_t smax = (n + ((int64_t)1 << ls) - 1) >> ls;
+    const int Se = smax < 1 ? 1 : (int)smax;
+    const size_t lds = subtree_lds_bytes(d, Se);
     hipLaunchKernelGGL(subtree_kernel, dim3((unsigned)((int64_t)1 << ls)), dim3(kNT), lds, s,
-                       cur_k, cur_i, n, d, L, ls, S, ifl, T->pts, T->pidx, T->split, T->bbox,
+                       cur_k, cur_i, n, d, L, ls, Se, ifl, T->pts, T->pidx, T->split, T->bbox,
                        T->rec);
     PG_LAUNCH_CHECK();
     return internal_boxes(T, s);
