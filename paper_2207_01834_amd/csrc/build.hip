@@ -240,13 +240,24 @@ __global__ void __launch_bounds__(kNT)
 wide_scan_kernel(uint64_t* __restrict__ bcnt, int bpn) {
     __shared__ uint64_t lds[kNT / kWave + 1];
     uint64_t* b = bcnt + (int64_t)blockIdx.x * bpn;
+    constexpr int PER = 8;  // consecutive counts per thread
     uint64_t run = 0;
-    for (int t0 = 0; t0 < bpn; t0 += kNT) {
-        int t = t0 + threadIdx.x;
-        uint64_t v = t < bpn ? b[t] : 0ull;
+    for (int t0 = 0; t0 < bpn; t0 += PER * kNT) {
+        const int t = t0 + PER * threadIdx.x;
+        uint64_t v[PER];
+        uint64_t sum = 0;
+#pragma unroll
+        for (int i = 0; i < PER; i++) {
+            v[i] = t + i < bpn ? b[t + i] : 0ull;
+            sum += v[i];
+        }
         uint64_t tot;
-        uint64_t ex = block_excl_scan<kNT>(v, lds, &tot);
-        if (t < bpn) b[t] = run + ex;
+        uint64_t ex = run + block_excl_scan<kNT>(sum, lds, &tot);
+#pragma unroll
+        for (int i = 0; i < PER; i++) {
+            if (t + i < bpn) b[t + i] = ex;
+            ex += v[i];
+        }
         run += tot;
     }
 }

@@ -287,9 +287,15 @@ __device__ inline void block_node_split(const uint32_t* __restrict__ in,
         hist[threadIdx.x] = 0;
         __syncthreads();
         const uint64_t pre = (uint64_t)prefix >> hb;
-        for (int64_t e = lo + threadIdx.x; e < hi; e += kBuildNT) {
-            const uint32_t k = keys[e];
-            if (((uint64_t)k >> hb) == pre) atomicAdd(&hist[(k >> shift) & wmask], 1u);
+        constexpr int PER = 8;  // loads issued together
+        for (int64_t b = lo + threadIdx.x; b < hi; b += PER * kBuildNT) {
+            uint32_t k[PER];
+#pragma unroll
+            for (int i = 0; i < PER; i++) k[i] = b + i * kBuildNT < hi ? keys[b + i * kBuildNT] : 0u;
+#pragma unroll
+            for (int i = 0; i < PER; i++)
+                if (b + i * kBuildNT < hi && ((uint64_t)k[i] >> hb) == pre)
+                    atomicAdd(&hist[(k[i] >> shift) & wmask], 1u);
         }
         __syncthreads();
         const uint32_t cnt = hist[threadIdx.x];
