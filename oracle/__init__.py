@@ -237,7 +237,7 @@ class KdTree:
         return counts, off, out, counters
 
 
-def spatial_tree(points, leaf=16, rule="cycle"):
+def spatial_tree(points, leaf=16, rule="cycle", space="cell"):
     """Spatial-median kd-tree (Section 6.3: the node's space cut in half along
     a dimension), read as: root space = bounding box of the points; node
     (l, j) cuts its cell at the cell's midpoint (int: floor((lo + hi + 1) /
@@ -245,13 +245,16 @@ def spatial_tree(points, leaf=16, rule="cycle"):
     cells [lo, s] / [s, hi]) along dimension l mod d (rule "cycle") or along
     the cell's widest side, lowest dimension on ties (rule "widest");
     coordinate < s goes left, each side keeps the parent's order; depth L as
-    the object-median tree, so leaf sizes vary.  Returns (levels, splits
-    float64 [2^L] with index 0 unused, split dimensions int32 [2^L], rows
-    int64 [n] in leaf order, leaf offsets int64 [2^L + 1])."""
+    the object-median tree, so leaf sizes vary.  With space "points" the
+    space a node cuts is the bounding box of its own points (same midpoint
+    and side rules; a node without points takes split 0 and dimension
+    l mod d, or 0 under the widest rule).  Returns (levels, splits float64
+    [2^L] with index 0 unused, split dimensions int32 [2^L], rows int64 [n]
+    in leaf order, leaf offsets int64 [2^L + 1])."""
     points = np.ascontiguousarray(points)
     dt = _dtype_code(points)
     n, d = points.shape
-    r = {"cycle": 0, "widest": 1}[rule]
+    r = {"cycle": 0, "widest": 1}[rule] | {"cell": 0, "points": 2}[space]
     lv = ctypes.c_int()
     rc = lib().or_kd_build_spatial(_ptr(points), n, d, dt, leaf, r, ctypes.byref(lv),
                                    None, None, None, None)

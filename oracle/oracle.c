@@ -37,8 +37,9 @@
  *                     Table 1) written out: every point inside a closed box.
  *   or_kd_range    -- the same query on the tree (whole subtrees inside the
  *                     box are reported, subtrees outside it skipped).
- *   or_kd_build_spatial -- the tree by spatial-median splits (cell halving),
- *                     with the readings stated at its definition.
+ *   or_kd_build_spatial -- the tree by spatial-median splits (cell halving,
+ *                     or halving of each node's point box), with the
+ *                     readings stated at its definition.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -529,7 +530,10 @@ int or_kd_range(const or_tree* T, const int64_t* ids, const uint8_t* alive,
 /* into [lo, s-1] and [s, hi]; float cells [lo, hi] at the float nearest   */
 /* to (lo + hi) / 2 (sum in double) into [lo, s] and [s, hi].  Split        */
 /* dimension: l mod d (rule 0), or the cell's widest side hi - lo, the      */
-/* lowest such dimension on ties (rule 1).                                  */
+/* lowest such dimension on ties (rule bit 0).  With rule bit 1 the space a */
+/* node cuts is the bounding box of its own points instead of its cell (a   */
+/* tight box: the same midpoint and side rules applied to it); a node with  */
+/* no points takes split 0 and dimension l mod d (widest rule: 0).          */
 /* ------------------------------------------------------------------------ */
 static double sp_mid(double lo, double hi, int dt) {
     if (dt == OR_DT_INT) {
@@ -545,22 +549,41 @@ typedef struct {
     int64_t* perm; int64_t* tmp; double* split; int64_t* loff; int32_t* dim;
 } sp_ctx;
 
+static double sp_coord(const sp_ctx* C, int64_t row, int c) {
+    return C->dt == OR_DT_INT ? (double)((const int32_t*)C->pts)[row * C->d + c]
+                              : (double)((const float*)C->pts)[row * C->d + c];
+}
+
 static void sp_rec(sp_ctx* C, int l, int64_t j, int64_t lo, int64_t hi, double* clo, double* chi) {
     if (l == C->L) { C->loff[j] = lo; return; }
+    double blo[8], bhi[8];
+    const int box = (C->rule & 2) != 0;
+    if (box) {  /* the node's space: the bounding box of its points */
+        for (int e = 0; e < C->d; e++) { blo[e] = INFINITY; bhi[e] = -INFINITY; }
+        for (int64_t p = lo; p < hi; p++)
+            for (int e = 0; e < C->d; e++) {
+                double x = sp_coord(C, C->perm[p], e);
+                if (x < blo[e]) blo[e] = x;
+                if (x > bhi[e]) bhi[e] = x;
+            }
+        clo = blo;
+        chi = bhi;
+    }
+    const int empty = box && lo == hi;
     int c = l % C->d;
-    if (C->rule == 1) {
+    if (C->rule & 1) {
         c = 0;
-        for (int e = 1; e < C->d; e++)
-            if (chi[e] - clo[e] > chi[c] - clo[c]) c = e;
+        if (!empty)
+            for (int e = 1; e < C->d; e++)
+                if (chi[e] - clo[e] > chi[c] - clo[c]) c = e;
     }
     C->dim[((int64_t)1 << l) + j] = c;
-    double s = sp_mid(clo[c], chi[c], C->dt);
+    double s = empty ? 0.0 : sp_mid(clo[c], chi[c], C->dt);
     C->split[((int64_t)1 << l) + j] = s;
     /* stable partition of perm[lo, hi) by coordinate < s */
     int64_t nl = 0, w = lo;
     for (int64_t p = lo; p < hi; p++) {
-        double x = C->dt == OR_DT_INT ? (double)((const int32_t*)C->pts)[C->perm[p] * C->d + c]
-                                      : (double)((const float*)C->pts)[C->perm[p] * C->d + c];
+        double x = sp_coord(C, C->perm[p], c);
         if (x < s) C->perm[w++] = C->perm[p];
         else C->tmp[nl++] = C->perm[p];
     }
@@ -581,7 +604,7 @@ static void sp_rec(sp_ctx* C, int l, int64_t j, int64_t lo, int64_t hi, double* 
 int or_kd_build_spatial(const void* pts, int64_t n, int d, int dt, int leaf, int rule,
                         int* levels, double* split_out, int32_t* dim_out, int64_t* perm_out,
                         int64_t* loff_out) {
-    if (d < 1 || d > 8 || leaf < 1 || n < 0 || !levels || rule < 0 || rule > 1) return 1;
+    if (d < 1 || d > 8 || leaf < 1 || n < 0 || !levels || rule < 0 || rule > 3) return 1;
     int L = tree_depth(n, leaf);
     *levels = L;
     if (!split_out || !dim_out || !perm_out || !loff_out) return 0;

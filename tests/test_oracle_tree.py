@@ -202,3 +202,85 @@ def test_spatial_widest_invariants(dtype):
         assert np.all(P[lo:mid, c] < s[h]) and np.all(P[mid:hi, c] >= s[h])
     for j in range(1 << L):
         assert np.all(np.diff(perm[loff[j]:loff[j + 1]]) > 0)
+
+
+# --- spatial-median tree, each node cutting the bounding box of its points ---
+
+def test_spatial_point_box_hand_worked():
+    # 1-D int {100, 2, 0, 1}, leaf 1 (depth 2).  Point boxes: root [0, 100]
+    # cut at floor(101/2) = 50; left {2, 0, 1}: box [0, 2] cut at
+    # floor(3/2) = 1 -> {0} | {2, 1}; right {100}: box [100, 100] cut at
+    # 100 -> {} | {100}.
+    pts = np.array([[100], [2], [0], [1]], dtype=np.int32)
+    L, s, dims, perm, loff = oracle.spatial_tree(pts, leaf=1, space="points")
+    assert L == 2 and s[1:].tolist() == [50, 1, 100] and dims[1:].tolist() == [0, 0, 0]
+    assert loff.tolist() == [0, 1, 3, 3, 4] and perm.tolist() == [2, 1, 3, 0]
+    # cell halving on the same points: [0, 49] cut at 25, [50, 100] at 75
+    L, s, _, perm, loff = oracle.spatial_tree(pts, leaf=1, space="cell")
+    assert s[1:].tolist() == [50, 25, 75] and loff.tolist() == [0, 3, 3, 3, 4]
+    # float {0, .25, .5, 4}: [0, 4] at 2; [0, .5] at .25; [4, 4] at 4
+    f = np.array([[4.0], [0.5], [0.0], [0.25]], dtype=np.float32)
+    L, s, _, perm, loff = oracle.spatial_tree(f, leaf=1, space="points")
+    assert s[1:].tolist() == [2.0, 0.25, 4.0]
+    assert loff.tolist() == [0, 1, 3, 3, 4] and perm.tolist() == [2, 1, 3, 0]
+
+
+def test_spatial_point_box_empty_node():
+    # {0..6, 1000}, leaf 1 (depth 3): the root cuts [0, 1000] at 500; the
+    # right node {1000} cuts [1000, 1000] at 1000, so its left child (node 6,
+    # an internal node) is empty and takes split 0
+    pts = np.array([[v] for v in (0, 1, 2, 3, 4, 5, 6, 1000)], dtype=np.int32)
+    L, s, dims, perm, loff = oracle.spatial_tree(pts, leaf=1, space="points")
+    assert L == 3 and s[1] == 500 and s[3] == 1000 and s[6] == 0
+    assert np.diff(loff).tolist()[4:] == [0, 0, 0, 1]
+    # 2-D: an empty node takes dimension l mod d, or 0 under the widest rule
+    p2 = np.array([[0, 0], [1, 5], [2, 1], [3, 3], [4, 2], [5, 6], [6, 4], [1000, 9]], dtype=np.int32)
+    for rule in ("cycle", "widest"):
+        L, s, dims, perm, loff = oracle.spatial_tree(p2, leaf=1, rule=rule, space="points")
+        for h in range(1, 1 << L):
+            l = h.bit_length() - 1
+            span = 1 << (L - l)
+            j = h - (1 << l)
+            if loff[j * span] == loff[(j + 1) * span]:
+                assert s[h] == 0 and dims[h] == (l % 2 if rule == "cycle" else 0)
+
+
+@pytest.mark.parametrize("rule,dtype", [("cycle", np.int32), ("widest", np.int32),
+                                        ("cycle", np.float32), ("widest", np.float32)])
+def test_spatial_point_box_invariants(rule, dtype):
+    # a dense cluster beside a sparse background: every split lies inside its
+    # node's point box and separates it; the widest rule takes that box's
+    # widest side; once the cluster's node holds only cluster points, cutting
+    # point boxes spreads it over many leaves, while cell halving keeps it in
+    # one leaf (its cells stay far wider than the cluster)
+    rng = np.random.default_rng(31)
+    n, d, leaf = 4000, 3, 8
+    if dtype == np.int32:
+        bg = rng.integers(0, 1 << 19, (n // 4, d))
+        cl = 1_000_000 + rng.integers(0, 64, (n - n // 4, d))
+    else:
+        bg = 0.5 * rng.random((n // 4, d))
+        cl = 0.95 + 1e-4 * rng.random((n - n // 4, d))
+    pts = np.concatenate([bg, cl]).astype(dtype)[rng.permutation(n)]
+    L, s, dims, perm, loff = oracle.spatial_tree(pts, leaf=leaf, rule=rule, space="points")
+    assert sorted(perm.tolist()) == list(range(n))
+    P = pts[perm].astype(np.float64)
+    for h in range(1, 1 << L):
+        l = h.bit_length() - 1
+        j = h - (1 << l)
+        span = 1 << (L - l)
+        lo, mid, hi = loff[j * span], loff[j * span + span // 2], loff[(j + 1) * span]
+        if lo == hi:
+            continue
+        box_lo, box_hi = P[lo:hi].min(axis=0), P[lo:hi].max(axis=0)
+        c = dims[h]
+        if rule == "widest":
+            assert c == int(np.argmax(box_hi - box_lo))
+        else:
+            assert c == l % d
+        assert box_lo[c] <= s[h] <= box_hi[c]
+        assert np.all(P[lo:mid, c] < s[h]) and np.all(P[mid:hi, c] >= s[h])
+    for j in range(1 << L):
+        assert np.all(np.diff(perm[loff[j]:loff[j + 1]]) > 0)
+    cell = oracle.spatial_tree(pts, leaf=leaf, rule=rule, space="cell")[4]
+    assert 8 * np.diff(loff).max() < np.diff(cell).max()
