@@ -221,34 +221,43 @@ def form_graph(torch, pg, datagen, dev):
 
 
 def form_spatial(torch, pg, datagen, dev):
-    """Spatial-median splits (cells cut at their midpoints, the object-median
-    tree's depth) on the headline points and on the 5-D clustered set: build
-    and k-NN beside the object-median numbers of the other forms."""
+    """Spatial-median splits at the object-median tree's depth, each node
+    cutting its cell or the bounding box of its own points, on the headline
+    points and on the 5-D clustered set: build and k-NN beside the
+    object-median numbers of the other forms."""
     import numpy as np
     out = {}
     pts = datagen.uniform_int(N, D, seed=2)
     x = torch.from_numpy(pts).to(dev)
-    holder = {}
-    b_ms = timed(torch, lambda: holder.__setitem__("t", pg.kdtree_build(x, leaf=LEAF, split="spatial")))
-    t = holder["t"]
     idx = torch.empty((N, K), dtype=torch.int32, device=dev)
     dist = torch.empty((N, K), dtype=torch.int64, device=dev)
-    k_ms = timed(torch, lambda: t.knn_all(K, out=(idx, dist)))
-    sizes = np.diff(t.offsets())
-    out["uniform_3d"] = {"workload": "3-D n=10M int32 uniform, k=10, leaf 16, all points",
-                         "build_ms": b_ms, "knn_ms": k_ms, "max_leaf": int(sizes.max()),
-                         "empty_leaves": int((sizes == 0).sum())}
-    del t, holder["t"], idx, dist, x
+    holder = {}
+    for space, tag in (("cell", ""), ("points", "_point_box")):
+        b_ms = timed(torch, lambda: holder.__setitem__(
+            "t", pg.kdtree_build(x, leaf=LEAF, split="spatial", space=space)))
+        t = holder["t"]
+        k_ms = timed(torch, lambda: t.knn_all(K, out=(idx, dist)))
+        sizes = np.diff(t.offsets())
+        out["uniform_3d" + tag] = {"workload": f"3-D n=10M int32 uniform, k=10, leaf 16, all points, "
+                                               f"nodes cut their {space if space == 'cell' else 'point box'}",
+                                   "build_ms": b_ms, "knn_ms": k_ms, "max_leaf": int(sizes.max()),
+                                   "empty_leaves": int((sizes == 0).sum())}
+        del t, holder["t"]
+    del idx, dist, x
     f, q = datagen.clustered(N, 5, seed=3, n_queries=1_000_000, query_seed=33)
     xf = torch.from_numpy(f).to(dev)
     qd = torch.from_numpy(q).to(dev)
-    b_ms = timed(torch, lambda: holder.__setitem__("t", pg.kdtree_build(xf, leaf=LEAF, split="spatial")))
-    t = holder["t"]
-    k_ms = timed(torch, lambda: t.knn(qd, 5))
-    sizes = np.diff(t.offsets())
-    out["clustered_5d"] = {"workload": "5-D n=10M clustered float32, 1M queries, k=5, leaf 16",
-                           "build_ms": b_ms, "knn_ms": k_ms, "max_leaf": int(sizes.max()),
-                           "empty_leaves": int((sizes == 0).sum())}
+    for space, tag, reps in (("cell", "", 3), ("points", "_point_box", 3)):
+        b_ms = timed(torch, lambda: holder.__setitem__(
+            "t", pg.kdtree_build(xf, leaf=LEAF, split="spatial", space=space)))
+        t = holder["t"]
+        k_ms = timed(torch, lambda: t.knn(qd, 5), reps=reps)
+        sizes = np.diff(t.offsets())
+        out["clustered_5d" + tag] = {"workload": f"5-D n=10M clustered float32, 1M queries, k=5, leaf 16, "
+                                                 f"nodes cut their {space if space == 'cell' else 'point box'}",
+                                     "build_ms": b_ms, "knn_ms": k_ms, "max_leaf": int(sizes.max()),
+                                     "empty_leaves": int((sizes == 0).sum())}
+        del t, holder["t"]
     return out
 
 

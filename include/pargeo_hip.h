@@ -99,13 +99,18 @@ pg_status pg_kdtree_build(const void* points, int64_t n, int32_t d, int32_t leaf
  * (l, j) cuts its cell at the cell's midpoint s (int32: floor((lo + hi + 1)
  * / 2), halves [lo, s-1] and [s, hi]; float32: the float nearest
  * (lo + hi) / 2, halves [lo, s] and [s, hi]) along dimension l mod d
- * (dim_rule 0) or along the cell's widest side, the lowest dimension on
- * ties (dim_rule 1); points with coordinate < s go left.  The depth L and heap layout are those of
- * pg_kdtree_build, so leaves hold varying numbers of points (possibly more
- * than `leaf`, or none); pg_tree_offsets gives the leaf ranges.  The order
- * of points inside a leaf is unspecified.  Every query call accepts the
- * result (pg_knn, pg_knn_all, pg_knn_graph, pg_range_*).  Arguments and
- * errors as pg_kdtree_build. */
+ * (dim_rule bit 0 clear) or along the cell's widest side, the lowest
+ * dimension on ties (bit 0 set); points with coordinate < s go left.  With
+ * dim_rule bit 1 set, the space a node cuts is the bounding box of its own
+ * points instead of its cell (same midpoint and side rules; a node with no
+ * points takes split 0 and dimension l mod d, or 0 under the widest rule),
+ * which follows clusters that cell halving leaves in one leaf.  The depth L
+ * and heap layout are those of pg_kdtree_build, so leaves hold varying
+ * numbers of points (possibly more than `leaf`, or none); pg_tree_offsets
+ * gives the leaf ranges.  The order of points inside a leaf is unspecified.
+ * Every query call accepts the result (pg_knn, pg_knn_all, pg_knn_graph,
+ * pg_range_*).  Arguments and errors as pg_kdtree_build; dim_rule in
+ * [0, 3]. */
 pg_status pg_kdtree_build_spatial(const void* points, int64_t n, int32_t d, int32_t leaf,
                                   int32_t dtype, int32_t dim_rule, void* stream, pg_tree** out);
 

@@ -304,21 +304,24 @@ class KdTree:
 
 
 def kdtree_build(points: torch.Tensor, leaf: int = 16, split: str = "object",
-                 dim_rule: str = "cycle") -> KdTree:
+                 dim_rule: str = "cycle", space: str = "cell") -> KdTree:
     """Builds a kd-tree: ``split="object"`` (object median, every leaf at most
-    ``leaf`` points) or ``"spatial"`` (cells cut at their midpoints, the same
+    ``leaf`` points) or ``"spatial"`` (spaces cut at their midpoints, the same
     depth, leaf sizes vary; ``dim_rule`` "cycle" = level mod d, "widest" = the
-    cell's widest side)."""
+    space's widest side; ``space`` "cell" = the node's cell, "points" = the
+    bounding box of the node's points)."""
     p = _points(points, "points")
     code = _dtype_code(p)
     h = ctypes.c_void_p()
     args = (ctypes.c_void_p(p.data_ptr()), p.shape[0], p.shape[1], leaf, code)
+    if space not in ("cell", "points"):
+        raise ValueError("space must be 'cell' or 'points'")
     if split == "object":
-        if dim_rule != "cycle":
+        if dim_rule != "cycle" or space != "cell":
             raise ValueError("object-median trees cycle through the dimensions")
         check(lib().pg_kdtree_build(*args, stream_ptr(p.device), ctypes.byref(h)))
     elif split == "spatial":
-        rule = {"cycle": 0, "widest": 1}[dim_rule]
+        rule = {"cycle": 0, "widest": 1}[dim_rule] | (2 if space == "points" else 0)
         check(lib().pg_kdtree_build_spatial(*args, rule, stream_ptr(p.device), ctypes.byref(h)))
     else:
         raise ValueError("split must be 'object' or 'spatial'")

@@ -131,7 +131,8 @@ pg_status pg_kdtree_build_spatial(const void* points, int64_t n, int32_t d, int3
     if (n < 0 || n >= ((int64_t)1 << 31)) return fail(PG_ERR_INVALID, "pg_kdtree_build_spatial: n must be in [0, 2^31)");
     if (dtype != PG_INT32 && dtype != PG_FLOAT32) return fail(PG_ERR_INVALID, "pg_kdtree_build_spatial: bad dtype");
     if (n > 0 && !points) return fail(PG_ERR_INVALID, "pg_kdtree_build_spatial: points is NULL");
-    if (dim_rule != 0 && dim_rule != 1) return fail(PG_ERR_INVALID, "pg_kdtree_build_spatial: dim_rule must be 0 or 1");
+    if (dim_rule < 0 || dim_rule > 3)
+        return fail(PG_ERR_INVALID, "pg_kdtree_build_spatial: dim_rule must be in [0, 3]");
     pg_tree* t = new (std::nothrow) pg_tree();
     if (!t) return fail(PG_ERR_NOMEM, "pg_kdtree_build_spatial: host allocation failed");
     pg_status st = build_tree_spatial(points, n, d, leaf, dtype, dim_rule, (hipStream_t)stream, t);

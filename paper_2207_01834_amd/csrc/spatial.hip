@@ -13,10 +13,19 @@
 // leaf} and heap layout, so leaves hold varying numbers of points and their
 // ranges are explicit offsets.
 //
+// Point-box form (rule bit 1): a node cuts the bounding box of its own
+// points instead of its cell, with the same midpoint and side rules; a node
+// without points takes split 0 and dimension l mod d (0 under the widest
+// rule).
+//
 // GPU form: since every cut depends only on the cell, the leaf of a point
 // follows from its own coordinates (L comparisons against midpoints computed
 // on the fly), so the build is one pass for leaf keys, a counting sort by
-// leaf and a scatter, instead of one partition pass per level.  The order of
+// leaf and a scatter, instead of one partition pass per level.  A point box
+// depends on the node's members, so that form goes level by level, but moves
+// no points until the end: every point carries its node, each level reduces
+// the nodes' boxes (LDS-private while the level's boxes fit, then global
+// atomics), cuts them, and steps every point to its child.  The order of
 // points inside a leaf is the order the counting sort's atomics give (leaf
 // membership, splits and offsets are deterministic; results do not depend on
 // the order inside a leaf).
@@ -158,6 +167,136 @@ spatial_split_kernel(int d, int L, int fl, int rule, const uint32_t* __restrict_
     if (sdim) sdim[h] = (uint8_t)c;
 }
 
+// ---- point-box form ----
+
+__global__ void pbox_fill_kernel(uint32_t* __restrict__ bmin, uint32_t* __restrict__ bmax, int64_t cnt) {
+    const int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x;
+    if (i < cnt) {
+        bmin[i] = 0xffffffffu;
+        bmax[i] = 0u;
+    }
+}
+
+// Box (min / max key per dimension) of every node of the level, over the
+// points' current nodes nid.  lds: reduce into 2 * J * d LDS words first.
+__global__ void __launch_bounds__(kNT)
+pbox_reduce_kernel(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ nid, int64_t n,
+                   int d, int64_t J, int lds, uint32_t* __restrict__ bmin,
+                   uint32_t* __restrict__ bmax) {
+    extern __shared__ uint32_t sb[];
+    const int64_t Jd = J * d;
+    const int64_t stride = (int64_t)gridDim.x * kNT;
+    if (lds) {
+        for (int64_t t = threadIdx.x; t < Jd; t += kNT) {
+            sb[t] = 0xffffffffu;
+            sb[Jd + t] = 0u;
+        }
+        __syncthreads();
+        if (J == 1) {  // one node: registers first, one LDS atomic per thread and dimension
+            uint32_t mn[8], mx[8];
+#pragma unroll
+            for (int c = 0; c < 8; c++) {
+                mn[c] = 0xffffffffu;
+                mx[c] = 0u;
+            }
+            for (int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x; i < n; i += stride) {
+#pragma unroll
+                for (int c = 0; c < 8; c++) {
+                    if (c < d) {
+                        const uint32_t k = keys[(int64_t)c * n + i];
+                        mn[c] = k < mn[c] ? k : mn[c];
+                        mx[c] = k > mx[c] ? k : mx[c];
+                    }
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < 8; c++) {
+                if (c < d) {
+                    atomicMin(&sb[c], mn[c]);
+                    atomicMax(&sb[Jd + c], mx[c]);
+                }
+            }
+        } else {
+            for (int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x; i < n; i += stride) {
+                const int64_t j = nid[i];
+                for (int c = 0; c < d; c++) {
+                    const uint32_t k = keys[(int64_t)c * n + i];
+                    atomicMin(&sb[j * d + c], k);
+                    atomicMax(&sb[Jd + j * d + c], k);
+                }
+            }
+        }
+        __syncthreads();
+        for (int64_t t = threadIdx.x; t < Jd; t += kNT) {
+            if (sb[t] <= sb[Jd + t]) {  // the node has points in this workgroup's share
+                atomicMin(&bmin[t], sb[t]);
+                atomicMax(&bmax[t], sb[Jd + t]);
+            }
+        }
+        return;
+    }
+    for (int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x; i < n; i += stride) {
+        const int64_t j = nid[i];
+        for (int c = 0; c < d; c++) {
+            const uint32_t k = keys[(int64_t)c * n + i];
+            atomicMin(&bmin[j * d + c], k);
+            atomicMax(&bmax[j * d + c], k);
+        }
+    }
+}
+
+// Split of every node of level l from its point box: dimension (l mod d, or
+// the box's widest side, lowest on ties), cut at the box's midpoint.
+__global__ void __launch_bounds__(kNT)
+pbox_split_kernel(const uint32_t* __restrict__ bmin, const uint32_t* __restrict__ bmax, int64_t J,
+                  int l, int d, int fl, int widest, uint32_t* __restrict__ split_level,
+                  uint8_t* __restrict__ sdim_level, double* __restrict__ ns,
+                  uint8_t* __restrict__ nd) {
+    const int64_t j = (int64_t)blockIdx.x * kNT + threadIdx.x;
+    if (j >= J) return;
+    const bool empty = bmin[j * d] > bmax[j * d];
+    int c = widest ? 0 : l % d;
+    double s = 0.0;
+    if (!empty) {
+        double lo[8], hi[8];
+#pragma unroll
+        for (int cc = 0; cc < 8; cc++) {
+            lo[cc] = cc < d ? coord_value(key_to_coord(bmin[j * d + cc], fl != 0), fl != 0) : 0.0;
+            hi[cc] = cc < d ? coord_value(key_to_coord(bmax[j * d + cc], fl != 0), fl != 0) : 0.0;
+        }
+        c = cell_dim(lo, hi, d, l, widest);
+#pragma unroll
+        for (int cc = 0; cc < 8; cc++)
+            if (cc == c) s = cell_mid(lo[cc], hi[cc], fl != 0);
+    }
+    split_level[j] = fl ? __float_as_uint((float)s) : (uint32_t)(int32_t)s;
+    if (sdim_level) sdim_level[j] = (uint8_t)c;
+    ns[j] = s;
+    nd[j] = (uint8_t)c;
+}
+
+// Every point steps to the child of its node: right when its coordinate
+// along the node's dimension is at least the cut.
+__global__ void __launch_bounds__(kNT)
+pbox_step_kernel(const uint32_t* __restrict__ keys, uint32_t* __restrict__ nid, int64_t n, int fl,
+                 const double* __restrict__ ns, const uint8_t* __restrict__ nd) {
+    const int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t j = nid[i];
+    const int c = nd[j];
+    const double x = coord_value(key_to_coord(keys[(int64_t)c * n + i], fl != 0), fl != 0);
+    nid[i] = 2u * j + (x >= ns[j] ? 1u : 0u);
+}
+
+// Rank of every point among its leaf's points (the node after L steps).
+__global__ void __launch_bounds__(kNT)
+pbox_rank_kernel(const uint32_t* __restrict__ nid, int64_t n, uint32_t* __restrict__ rank,
+                 uint32_t* __restrict__ cnt) {
+    const int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x;
+    if (i >= n) return;
+    rank[i] = atomicAdd(&cnt[nid[i]], 1u);
+}
+
 __global__ void spatial_offsets_kernel(const uint32_t* __restrict__ start, int64_t leaves, int64_t n,
                                        int64_t* __restrict__ loff) {
     const int64_t j = (int64_t)blockIdx.x * kNT + threadIdx.x;
@@ -193,6 +332,8 @@ spatial_scatter_kernel(const uint32_t* __restrict__ keys, const int32_t* __restr
 pg_status build_tree_spatial(const void* points, int64_t n, int d, int leaf, int dtype, int rule,
                              hipStream_t s, pg_tree* T) {
     const bool fl = dtype == PG_FLOAT32;
+    const int widest = rule & 1;            // split dimension: the widest side
+    const bool point_box = (rule & 2) != 0;  // cut each node's point box
     T->n = n;
     T->d = d;
     T->leaf = leaf;
@@ -210,7 +351,7 @@ pg_status build_tree_spatial(const void* points, int64_t n, int d, int leaf, int
     T->bbox = T->nbox + (size_t)leaves * 2 * d;
     PG_TRY(dalloc(&T->rec, ((size_t)nn + kTreePad) * rw, s));
     PG_TRY(dalloc(&T->loff, (size_t)leaves + 1, s));
-    if (rule == 1) PG_TRY(dalloc(&T->sdim, (size_t)leaves, s));
+    if (widest) PG_TRY(dalloc(&T->sdim, (size_t)leaves, s));
     if (n == 0) {
         if (T->sdim) PG_HIP(hipMemsetAsync(T->sdim, 0, leaves, s));
         PG_HIP(hipMemsetAsync(T->loff, 0, sizeof(int64_t) * (leaves + 1), s));
@@ -222,22 +363,64 @@ pg_status build_tree_spatial(const void* points, int64_t n, int d, int leaf, int
     PG_TRY(idx.alloc(sizeof(int32_t) * (size_t)n));
     uint32_t vary[8] = {0}, keybase[8] = {0};
     PG_TRY(ingest_points(points, n, d, fl, keys.as<uint32_t>(), idx.as<int32_t>(), vary, keybase, s));
-    PG_TRY(box.alloc(sizeof(uint32_t) * 2 * d));
-    PG_HIP(hipMemsetAsync(box.p, 0xff, sizeof(uint32_t) * d, s));
-    PG_HIP(hipMemsetAsync(box.as<uint32_t>() + d, 0, sizeof(uint32_t) * d, s));
-    const unsigned grid = cdiv(n, kNT) < 1024u ? cdiv(n, kNT) : 1024u;
-    hipLaunchKernelGGL(key_box_kernel, dim3(grid), dim3(kNT), 0, s, keys.as<uint32_t>(), n, d,
-                       box.as<uint32_t>());
-    PG_LAUNCH_CHECK();
     PG_TRY(lf.alloc(sizeof(uint32_t) * n));
     PG_TRY(rk.alloc(sizeof(uint32_t) * n));
     PG_TRY(cnt.alloc(sizeof(uint32_t) * leaves));
     PG_TRY(start.alloc(sizeof(uint32_t) * leaves));
     PG_HIP(hipMemsetAsync(cnt.p, 0, sizeof(uint32_t) * leaves, s));
-    hipLaunchKernelGGL(spatial_leaf_kernel, dim3(cdiv(n, kNT)), dim3(kNT), 0, s,
-                       keys.as<uint32_t>(), n, d, L, fl ? 1 : 0, rule, box.as<uint32_t>(),
-                       lf.as<uint32_t>(), rk.as<uint32_t>(), cnt.as<uint32_t>());
-    PG_LAUNCH_CHECK();
+    if (!point_box) {
+        PG_TRY(box.alloc(sizeof(uint32_t) * 2 * d));
+        PG_HIP(hipMemsetAsync(box.p, 0xff, sizeof(uint32_t) * d, s));
+        PG_HIP(hipMemsetAsync(box.as<uint32_t>() + d, 0, sizeof(uint32_t) * d, s));
+        const unsigned grid = cdiv(n, kNT) < 1024u ? cdiv(n, kNT) : 1024u;
+        hipLaunchKernelGGL(key_box_kernel, dim3(grid), dim3(kNT), 0, s, keys.as<uint32_t>(), n, d,
+                           box.as<uint32_t>());
+        PG_LAUNCH_CHECK();
+        hipLaunchKernelGGL(spatial_leaf_kernel, dim3(cdiv(n, kNT)), dim3(kNT), 0, s,
+                           keys.as<uint32_t>(), n, d, L, fl ? 1 : 0, widest, box.as<uint32_t>(),
+                           lf.as<uint32_t>(), rk.as<uint32_t>(), cnt.as<uint32_t>());
+        PG_LAUNCH_CHECK();
+    } else {
+        // every point starts at the root; the level loop writes every split
+        // (and dimension) of nodes 1 .. 2^L - 1, node 0 is unused
+        uint32_t* nid = lf.as<uint32_t>();
+        PG_HIP(hipMemsetAsync(nid, 0, sizeof(uint32_t) * n, s));
+        PG_HIP(hipMemsetAsync(T->split, 0, sizeof(uint32_t) * leaves, s));
+        if (T->sdim) PG_HIP(hipMemsetAsync(T->sdim, 0, leaves, s));
+        const int64_t jmax = L > 0 ? leaves / 2 : 1;
+        DevBuf bmin(s), bmax(s), ns(s), nd(s);
+        PG_TRY(bmin.alloc(sizeof(uint32_t) * jmax * d));
+        PG_TRY(bmax.alloc(sizeof(uint32_t) * jmax * d));
+        PG_TRY(ns.alloc(sizeof(double) * jmax));
+        PG_TRY(nd.alloc(sizeof(uint8_t) * jmax));
+        constexpr int64_t kLdsBoxWords = 4096;  // J * d of a level reduced in LDS (32 KB)
+        for (int l = 0; l < L; l++) {
+            const int64_t J = (int64_t)1 << l;
+            const int64_t Jd = J * d;
+            hipLaunchKernelGGL(pbox_fill_kernel, dim3(cdiv(Jd, kNT)), dim3(kNT), 0, s,
+                               bmin.as<uint32_t>(), bmax.as<uint32_t>(), Jd);
+            PG_LAUNCH_CHECK();
+            const int lds = Jd <= kLdsBoxWords ? 1 : 0;
+            const unsigned cap = lds ? 512u : 8192u;
+            const unsigned grid = cdiv(n, kNT) < cap ? cdiv(n, kNT) : cap;
+            hipLaunchKernelGGL(pbox_reduce_kernel, dim3(grid), dim3(kNT),
+                               lds ? sizeof(uint32_t) * 2 * (size_t)Jd : 0, s, keys.as<uint32_t>(),
+                               nid, n, d, J, lds, bmin.as<uint32_t>(), bmax.as<uint32_t>());
+            PG_LAUNCH_CHECK();
+            hipLaunchKernelGGL(pbox_split_kernel, dim3(cdiv(J, kNT)), dim3(kNT), 0, s,
+                               bmin.as<uint32_t>(), bmax.as<uint32_t>(), J, l, d, fl ? 1 : 0, widest,
+                               T->split + J, T->sdim ? T->sdim + J : nullptr, ns.as<double>(),
+                               nd.as<uint8_t>());
+            PG_LAUNCH_CHECK();
+            hipLaunchKernelGGL(pbox_step_kernel, dim3(cdiv(n, kNT)), dim3(kNT), 0, s,
+                               keys.as<uint32_t>(), nid, n, fl ? 1 : 0, ns.as<double>(),
+                               nd.as<uint8_t>());
+            PG_LAUNCH_CHECK();
+        }
+        hipLaunchKernelGGL(pbox_rank_kernel, dim3(cdiv(n, kNT)), dim3(kNT), 0, s, nid, n,
+                           rk.as<uint32_t>(), cnt.as<uint32_t>());
+        PG_LAUNCH_CHECK();
+    }
     PG_TRY(exclusive_scan_u32(cnt.as<uint32_t>(), start.as<uint32_t>(), leaves, nullptr, s));
     hipLaunchKernelGGL(spatial_offsets_kernel, dim3(cdiv(leaves + 1, kNT)), dim3(kNT), 0, s,
                        start.as<uint32_t>(), leaves, n, T->loff);
@@ -247,9 +430,11 @@ pg_status build_tree_spatial(const void* points, int64_t n, int d, int leaf, int
                        lf.as<uint32_t>(), rk.as<uint32_t>(), start.as<uint32_t>(), T->pts, T->rec,
                        T->pidx);
     PG_LAUNCH_CHECK();
-    hipLaunchKernelGGL(spatial_split_kernel, dim3(cdiv(leaves, kNT)), dim3(kNT), 0, s, d, L,
-                       fl ? 1 : 0, rule, box.as<uint32_t>(), T->split, T->sdim);
-    PG_LAUNCH_CHECK();
+    if (!point_box) {
+        hipLaunchKernelGGL(spatial_split_kernel, dim3(cdiv(leaves, kNT)), dim3(kNT), 0, s, d, L,
+                           fl ? 1 : 0, widest, box.as<uint32_t>(), T->split, T->sdim);
+        PG_LAUNCH_CHECK();
+    }
     return offset_boxes(T, s);
 }
 

@@ -87,7 +87,7 @@ def test_range_graph_spatial_argument_errors(L):
     assert st == 1 and "d must be" in _err(L)
     st = L.pg_kdtree_build_spatial(None, 10, 3, 16, 0, 0, None, ctypes.byref(out))
     assert st == 1 and "points is NULL" in _err(L)
-    st = L.pg_kdtree_build_spatial(fake, 10, 3, 16, 0, 2, None, ctypes.byref(out))
+    st = L.pg_kdtree_build_spatial(fake, 10, 3, 16, 0, 4, None, ctypes.byref(out))
     assert st == 1 and "dim_rule" in _err(L)
     assert L.pg_tree_split_dims(None, fake, None) == 1
 

@@ -35,9 +35,9 @@ def membership(perm, loff):
     return np.sort(leaf * max(len(perm), 1) + perm.astype(np.int64))
 
 
-def check_tree(pg, dev, pts, leaf, rule="cycle"):
-    t = pg.kdtree_build(to_dev(pts, dev), leaf=leaf, split="spatial", dim_rule=rule)
-    L, s, dims, perm, loff = oracle.spatial_tree(pts, leaf=leaf, rule=rule)
+def check_tree(pg, dev, pts, leaf, rule="cycle", space="cell"):
+    t = pg.kdtree_build(to_dev(pts, dev), leaf=leaf, split="spatial", dim_rule=rule, space=space)
+    L, s, dims, perm, loff = oracle.spatial_tree(pts, leaf=leaf, rule=rule, space=space)
     assert t.levels == L
     gs, gperm = t.export()
     gloff = t.offsets()
@@ -157,3 +157,68 @@ def test_spatial_widest_rule(pg, dev, n, d, leaf, dtype):
     assert np.array_equal(off, oo)
     for i in range(0, 2_000, 11):
         assert np.array_equal(np.sort(rows[off[i]:off[i + 1]].astype(np.int64)), oi[oo[i]:oo[i + 1]])
+
+
+# --- nodes cutting the bounding box of their own points ----------------------
+
+@pytest.mark.parametrize("n,d,leaf,dtype,rule", [
+    (20_000, 2, 16, np.int32, "cycle"), (9_000, 3, 8, np.float32, "cycle"),
+    (5_000, 5, 16, np.int32, "widest"), (3_000, 1, 4, np.int32, "cycle"),
+    (2_000, 8, 2, np.float32, "widest"), (4_000, 3, 1, np.int32, "widest"),
+])
+def test_point_box_tree_queries(pg, dev, n, d, leaf, dtype, rule):
+    say(f"point-box n={n} d={d} leaf={leaf} {np.dtype(dtype).name} {rule}")
+    rng = np.random.default_rng(7 * n + d)
+    if dtype == np.int32:
+        pts = rng.integers(-3000, 3000, (n, d)).astype(np.int32)
+        pts[: n // 3] = 100_000 + rng.integers(0, 40, (n // 3, d))  # a far, dense cluster
+        pts[::7] = pts[3]  # duplicates
+    else:
+        pts = (rng.standard_normal((n, d)) ** 3).astype(np.float32)
+        pts[: n // 3] = (5.0 + 1e-3 * rng.random((n // 3, d))).astype(np.float32)
+    pts = pts[rng.permutation(n)]
+    t = check_tree(pg, dev, pts, leaf, rule=rule, space="points")
+    check_knn(t, pts, None, 9, dev)
+    q = pts[rng.integers(0, n, 5_000)]
+    check_knn(t, pts, q, 4, dev)
+    gi, gd = host(*t.knn_graph(5))
+    oi, od = oracle.knn_graph_brute(pts, 5, nthreads=8)
+    if dtype == np.int32:
+        assert_int_equal(gi, gd, oi, od)
+    else:
+        assert_float_close(gi, gd, oi, od, pts, pts)
+    half = 50 if dtype == np.int32 else 0.05
+    boxes = datagen.range_boxes(pts, half, seed=9, m=2_000)
+    off, rows = t.range_search(to_dev(boxes, dev))
+    off, rows = host(off, rows)
+    oc, oo, oi = oracle.range_brute(pts, boxes)
+    assert np.array_equal(off, oo)
+    for i in range(0, 2_000, 13):
+        assert np.array_equal(np.sort(rows[off[i]:off[i + 1]].astype(np.int64)), oi[oo[i]:oo[i + 1]])
+
+
+def test_point_box_small_empty_and_same(pg, dev):
+    for n in (0, 1, 2, 5, 33):
+        pts = (np.arange(2 * n, dtype=np.int32) ** 2).reshape(n, 2)
+        t = check_tree(pg, dev, pts, 1, space="points")
+        if n:
+            check_knn(t, pts, None, 3, dev)
+    same = np.full((500, 3), -7, dtype=np.int32)
+    t = check_tree(pg, dev, same, 4, rule="widest", space="points")
+    check_knn(t, same, None, 3, dev)
+
+
+def test_point_box_clustered_full_size(pg, dev):
+    """The 5-D clustered workload (10M float32 points, 1,000 clusters) with
+    point-box cuts: the whole tree against the oracle's, leaves far smaller
+    than with cell halving, sampled queries against the definition."""
+    pts, q = datagen.clustered(10_000_000, 5, seed=3, n_queries=1_000_000, query_seed=33)
+    say("point-box clustered 10M: build")
+    t = check_tree(pg, dev, pts, 16, space="points")
+    cell = pg.kdtree_build(to_dev(pts, dev), leaf=16, split="spatial")
+    assert 4 * np.diff(t.offsets()).max() < np.diff(cell.offsets()).max()
+    del cell
+    rows = np.random.default_rng(5).choice(len(q), 200, replace=False)
+    gi, gd = host(*t.knn(to_dev(q[rows], dev), 5))
+    oi, od = oracle.knn_brute(pts, q[rows], 5, nthreads=16)
+    assert_float_close(gi, gd, oi, od, pts, q[rows])
