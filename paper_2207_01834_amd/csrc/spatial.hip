@@ -169,6 +169,8 @@ spatial_split_kernel(int d, int L, int fl, int rule, const uint32_t* __restrict_
 
 // ---- point-box form ----
 
+constexpr int kBoxSlots = 512;  // node boxes cached per workgroup (a power of two)
+
 __global__ void pbox_fill_kernel(uint32_t* __restrict__ bmin, uint32_t* __restrict__ bmax, int64_t cnt) {
     const int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x;
     if (i < cnt) {
@@ -235,12 +237,48 @@ pbox_reduce_kernel(const uint32_t* __restrict__ keys, const uint32_t* __restrict
         }
         return;
     }
+    // Many nodes: a direct-mapped LDS cache of node boxes (tag = node).  A
+    // point whose node holds (or claims) its slot updates the slot; the
+    // others go to global memory.  Heavy nodes, which would serialise their
+    // global atomics, are the likeliest to hold a slot; each workgroup then
+    // flushes its slots once.
+    uint32_t* tag = sb;                   // [kBoxSlots]
+    uint32_t* cmin = sb + kBoxSlots;      // [kBoxSlots][d]
+    uint32_t* cmax = cmin + kBoxSlots * d;
+    for (int t = threadIdx.x; t < kBoxSlots; t += kNT) tag[t] = 0xffffffffu;
+    for (int t = threadIdx.x; t < kBoxSlots * d; t += kNT) {
+        cmin[t] = 0xffffffffu;
+        cmax[t] = 0u;
+    }
+    __syncthreads();
     for (int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x; i < n; i += stride) {
-        const int64_t j = nid[i];
-        for (int c = 0; c < d; c++) {
-            const uint32_t k = keys[(int64_t)c * n + i];
-            atomicMin(&bmin[j * d + c], k);
-            atomicMax(&bmax[j * d + c], k);
+        const uint32_t j = nid[i];
+        const int slot = (int)(j & (kBoxSlots - 1));
+        uint32_t held = tag[slot];
+        if (held == 0xffffffffu) {
+            const uint32_t prev = atomicCAS(&tag[slot], 0xffffffffu, j);
+            held = prev == 0xffffffffu ? j : prev;
+        }
+        if (held == j) {
+            for (int c = 0; c < d; c++) {
+                const uint32_t k = keys[(int64_t)c * n + i];
+                atomicMin(&cmin[slot * d + c], k);
+                atomicMax(&cmax[slot * d + c], k);
+            }
+        } else {
+            for (int c = 0; c < d; c++) {
+                const uint32_t k = keys[(int64_t)c * n + i];
+                atomicMin(&bmin[(int64_t)j * d + c], k);
+                atomicMax(&bmax[(int64_t)j * d + c], k);
+            }
+        }
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < kBoxSlots * d; t += kNT) {
+        const uint32_t j = tag[t / d];
+        if (j != 0xffffffffu && cmin[t] <= cmax[t]) {
+            atomicMin(&bmin[(int64_t)j * d + t % d], cmin[t]);
+            atomicMax(&bmax[(int64_t)j * d + t % d], cmax[t]);
         }
     }
 }
@@ -401,10 +439,12 @@ pg_status build_tree_spatial(const void* points, int64_t n, int d, int leaf, int
                                bmin.as<uint32_t>(), bmax.as<uint32_t>(), Jd);
             PG_LAUNCH_CHECK();
             const int lds = Jd <= kLdsBoxWords ? 1 : 0;
-            const unsigned cap = lds ? 512u : 8192u;
+            const unsigned cap = lds ? 512u : 1024u;
             const unsigned grid = cdiv(n, kNT) < cap ? cdiv(n, kNT) : cap;
-            hipLaunchKernelGGL(pbox_reduce_kernel, dim3(grid), dim3(kNT),
-                               lds ? sizeof(uint32_t) * 2 * (size_t)Jd : 0, s, keys.as<uint32_t>(),
+            const size_t lds_bytes = lds ? sizeof(uint32_t) * 2 * (size_t)Jd
+                                         : sizeof(uint32_t) * (size_t)kBoxSlots * (1 + 2 * d);
+            hipLaunchKernelGGL(pbox_reduce_kernel, dim3(grid), dim3(kNT), lds_bytes, s,
+                               keys.as<uint32_t>(),
                                nid, n, d, J, lds, bmin.as<uint32_t>(), bmax.as<uint32_t>());
             PG_LAUNCH_CHECK();
             hipLaunchKernelGGL(pbox_split_kernel, dim3(cdiv(J, kNT)), dim3(kNT), 0, s,
