@@ -454,6 +454,50 @@ def form_sec63(torch, pg, datagen, dev, n=N):
     return out
 
 
+def form_table1(torch, pg, datagen, dev, n=N):
+    """The kd-tree rows of Table 1 on their own shapes (10M uniform int32
+    points): build in 2-D and 5-D, all-points k-NN in 2-D (k = 10; the
+    paper does not state its k), range search in 2-D (a square of half side
+    512 around every point), the k-NN graph in 2-D (k = 10), and the
+    batch-dynamic tree in 5-D (construction over all points; ten 10%
+    batches inserted into an empty tree, then ten 10% batches erased, both
+    totals, as in Section 6.3)."""
+    import numpy as np
+    out = {"workload": f"Table 1 kd-tree rows: {n:,} uniform int32 points in [0,2^20)^d, leaf 16"}
+    holder = {}
+    x2 = torch.from_numpy(datagen.uniform_int(n, 2, seed=11)).to(dev)
+    x5 = torch.from_numpy(datagen.uniform_int(n, 5, seed=12)).to(dev)
+    out["build_2d_ms"] = timed(torch, lambda: holder.__setitem__("t", pg.kdtree_build(x2, leaf=LEAF)))
+    t2 = holder.pop("t")
+    out["build_5d_ms"] = timed(torch, lambda: holder.__setitem__("t", pg.kdtree_build(x5, leaf=LEAF)))
+    holder.pop("t")
+    idx = torch.empty((n, K), dtype=torch.int32, device=dev)
+    dist = torch.empty((n, K), dtype=torch.int64, device=dev)
+    out["knn_2d_ms"] = timed(torch, lambda: t2.knn_all(K, out=(idx, dist)))
+    out["knn_graph_2d_ms"] = timed(torch, lambda: t2.knn_graph(K, out=(idx, dist)))
+    del idx, dist
+    boxes = torch.from_numpy(datagen.range_boxes(x2.cpu().numpy(), 512)).to(dev)
+    t2.range_search(boxes)  # first launch of the range kernels
+    out["range_2d_ms"] = timed(torch, lambda: t2.range_search(boxes))
+    del t2, boxes
+    torch.cuda.empty_cache()
+    G, ms = grow_tree(torch, pg, "bdl", 5, [x5], dev)
+    out["bdl_construction_5d_ms"] = ms[0]
+    del G
+    tenth = list(torch.chunk(x5, 10))
+    G, ins = grow_tree(torch, pg, "bdl", 5, tenth, dev)
+    out["bdl_insert_5d_ms_total"] = float(np.sum(ins))
+    era = []
+    for E in tenth:
+        t, _ = wall_ms(torch, lambda: G.erase(E))
+        era.append(t)
+    out["bdl_delete_5d_ms_total"] = float(np.sum(era))
+    out["bdl_live_after_delete"] = G.size()
+    del G, tenth, x2, x5
+    torch.cuda.empty_cache()
+    return out
+
+
 def form_batch(torch, pg, datagen, dev, loop_clouds):
     """4,096 sphere clouds (sizes log-uniform in [256, 65536]), per-cloud
     all-points k = 16 in one persistent launch, against the per-cloud static
@@ -560,7 +604,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms", default="all",
                     help="other forms to measure after the headline step: all, none, or a "
-                         "comma list of static_float,clustered,spatial,bdl,baselines,batch,range,graph "
+                         "comma list of static_float,clustered,spatial,bdl,baselines,batch,range,graph,"
+                         "table1 "
                          "(sec63, the Section 6.3 protocols on 10M-point sets, runs only when named)")
     ap.add_argument("--bdl-rounds", type=int, default=10)
     ap.add_argument("--sec63-n", type=int, default=N, help="set size of the sec63 form")
@@ -674,7 +719,8 @@ def main():
     }
     del idx, dist, x
     torch.cuda.empty_cache()
-    forms = ["static_float", "clustered", "spatial", "bdl", "baselines", "batch", "range", "graph"] \
+    forms = ["static_float", "clustered", "spatial", "bdl", "baselines", "batch", "range", "graph",
+             "table1"] \
         if args.forms == "all" else \
         [f for f in args.forms.split(",") if f and f != "none"]
     out = {}
@@ -694,6 +740,8 @@ def main():
             out[f] = form_baselines(torch, pg, datagen, dev, args.bdl_rounds)
         elif f == "graph":
             out[f] = form_graph(torch, pg, datagen, dev)
+        elif f == "table1":
+            out[f] = form_table1(torch, pg, datagen, dev)
         elif f == "sec63":
             out[f] = form_sec63(torch, pg, datagen, dev, args.sec63_n)
         elif f == "range":
