@@ -45,3 +45,47 @@ def test_torch_caching_allocator(dev):
     finally:
         pg.use_torch_allocator(False)
     assert torch.cuda.memory_allocated(dev) <= before + 16 * 1024 * 1024
+
+
+def test_torch_allocator_bdl_sequence(dev):
+    """A BDL-tree insert / erase / k-NN sequence (many staging and per-tree
+    blocks, rebuilt trees freed along the way) gives the same results with
+    torch's caching allocator as with the library's pool, and returns every
+    block."""
+    import torch
+
+    import paper_2207_01834_amd._binding as pg
+    init, rounds = datagen.bdl_rounds(50_000, 3, 20_000, 3_000, 3, seed=17)
+
+    def run():
+        B = pg.BDLTree(3, torch.int32, leaf=8, X=256, device=dev)
+        B.insert(torch.from_numpy(init).to(dev))
+        pool, outs = init, []
+        for rd in rounds:
+            B.insert(torch.from_numpy(rd["insert"]).to(dev))
+            pool = np.concatenate([pool, rd["insert"]])
+            E = datagen.choose_erase(pool, 15_000, rd["erase_seed"])
+            outs.append(B.erase(torch.from_numpy(E).to(dev)))
+            i, dd = B.knn(torch.from_numpy(rd["queries"]).to(dev), 6)
+            torch.cuda.synchronize()
+            outs.append((i.cpu().numpy(), dd.cpu().numpy()))
+        outs.append(B.size())
+        del B
+        gc.collect()
+        torch.cuda.synchronize()
+        return outs
+
+    ref = run()
+    say("BDL sequence through torch's caching allocator")
+    pg.use_torch_allocator(True)
+    try:
+        before = torch.cuda.memory_allocated(dev)
+        got = run()
+        assert torch.cuda.memory_allocated(dev) == before  # every block came back
+    finally:
+        pg.use_torch_allocator(False)
+    for a, b in zip(ref, got):
+        if isinstance(a, tuple):
+            assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+        else:
+            assert a == b
