@@ -113,13 +113,61 @@ __device__ inline double cut_cell(double (&lo)[8], double (&hi)[8], int c, bool 
     return s;
 }
 
+// Ranks of the points of one workgroup (one point per thread) among their
+// leaves' points.  A leaf that holds one of kRankSlots LDS slots (tagged by
+// leaf) counts locally and takes one global atomic per workgroup; its points
+// get a local rank flagged by bit 31, finished by leaf_rank_fix_kernel from
+// the base stored in bbase[block][slot].  Other points take a global rank
+// directly.  A heavy leaf thus costs one global atomic per workgroup, not
+// one per point.  Must be called by every thread of the workgroup.
+constexpr int kRankSlots = 64;
+
+__device__ inline void rank_in_leaf(bool valid, uint32_t j, int64_t i, uint32_t* __restrict__ rank,
+                                    uint32_t* __restrict__ cnt, uint32_t* __restrict__ bbase) {
+    __shared__ uint32_t tag[kRankSlots], lcnt[kRankSlots];
+    if (threadIdx.x < kRankSlots) {
+        tag[threadIdx.x] = 0xffffffffu;
+        lcnt[threadIdx.x] = 0u;
+    }
+    __syncthreads();
+    if (valid) {
+        const int slot = (int)(j & (kRankSlots - 1));
+        uint32_t held = tag[slot];
+        if (held == 0xffffffffu) {
+            const uint32_t prev = atomicCAS(&tag[slot], 0xffffffffu, j);
+            held = prev == 0xffffffffu ? j : prev;
+        }
+        if (held == j) rank[i] = atomicAdd(&lcnt[slot], 1u) | 0x80000000u;
+        else rank[i] = atomicAdd(&cnt[j], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x < kRankSlots) {
+        const uint32_t t = tag[threadIdx.x];
+        bbase[(int64_t)blockIdx.x * kRankSlots + threadIdx.x] =
+            t != 0xffffffffu ? atomicAdd(&cnt[t], lcnt[threadIdx.x]) : 0u;
+    }
+}
+
+// Local ranks (bit 31) plus their workgroup's base for the leaf.
+__global__ void __launch_bounds__(kNT)
+leaf_rank_fix_kernel(const uint32_t* __restrict__ leaf, int64_t n, const uint32_t* __restrict__ bbase,
+                     uint32_t* __restrict__ rank) {
+    const int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t r = rank[i];
+    if (r & 0x80000000u)
+        rank[i] = bbase[(i / kNT) * kRankSlots + (leaf[i] & (kRankSlots - 1))] + (r & 0x7fffffffu);
+}
+
 // Leaf of every point (input order) and its rank among its leaf's points.
 __global__ void __launch_bounds__(kNT)
 spatial_leaf_kernel(const uint32_t* __restrict__ keys, int64_t n, int d, int L, int fl, int rule,
                     const uint32_t* __restrict__ box, uint32_t* __restrict__ leaf,
-                    uint32_t* __restrict__ rank, uint32_t* __restrict__ cnt) {
-    const int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x;
-    if (i >= n) return;
+                    uint32_t* __restrict__ rank, uint32_t* __restrict__ cnt,
+                    uint32_t* __restrict__ bbase) {
+    const int64_t i0 = (int64_t)blockIdx.x * kNT + threadIdx.x;
+    const bool valid = i0 < n;
+    const int64_t i = valid ? i0 : n - 1;  // an idle thread computes a real point's leaf
     double lo[8], hi[8], x[8];
     root_cell(box, d, fl != 0, lo, hi);
 #pragma unroll
@@ -138,8 +186,8 @@ spatial_leaf_kernel(const uint32_t* __restrict__ keys, int64_t n, int d, int L, 
         cut_cell(lo, hi, c, true, fl != 0, right);
         j = 2u * j + (right ? 1u : 0u);
     }
-    leaf[i] = j;
-    rank[i] = atomicAdd(&cnt[j], 1u);
+    if (valid) leaf[i] = j;
+    rank_in_leaf(valid, j, i, rank, cnt, bbase);
 }
 
 // Split (and dimension, when sdim is given) of internal node h: replay its
@@ -329,10 +377,10 @@ pbox_step_kernel(const uint32_t* __restrict__ keys, uint32_t* __restrict__ nid, 
 // Rank of every point among its leaf's points (the node after L steps).
 __global__ void __launch_bounds__(kNT)
 pbox_rank_kernel(const uint32_t* __restrict__ nid, int64_t n, uint32_t* __restrict__ rank,
-                 uint32_t* __restrict__ cnt) {
+                 uint32_t* __restrict__ cnt, uint32_t* __restrict__ bbase) {
     const int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x;
-    if (i >= n) return;
-    rank[i] = atomicAdd(&cnt[nid[i]], 1u);
+    const bool valid = i < n;
+    rank_in_leaf(valid, valid ? nid[i] : 0u, i, rank, cnt, bbase);
 }
 
 __global__ void spatial_offsets_kernel(const uint32_t* __restrict__ start, int64_t leaves, int64_t n,
@@ -396,7 +444,7 @@ pg_status build_tree_spatial(const void* points, int64_t n, int d, int leaf, int
         PG_HIP(hipMemsetAsync(T->split, 0, sizeof(uint32_t) * leaves, s));
         return offset_boxes(T, s);
     }
-    DevBuf keys(s), idx(s), box(s), lf(s), rk(s), cnt(s), start(s);
+    DevBuf keys(s), idx(s), box(s), lf(s), rk(s), cnt(s), start(s), bbase(s);
     PG_TRY(keys.alloc(sizeof(uint32_t) * (size_t)d * n));
     PG_TRY(idx.alloc(sizeof(int32_t) * (size_t)n));
     uint32_t vary[8] = {0}, keybase[8] = {0};
@@ -406,6 +454,7 @@ pg_status build_tree_spatial(const void* points, int64_t n, int d, int leaf, int
     PG_TRY(cnt.alloc(sizeof(uint32_t) * leaves));
     PG_TRY(start.alloc(sizeof(uint32_t) * leaves));
     PG_HIP(hipMemsetAsync(cnt.p, 0, sizeof(uint32_t) * leaves, s));
+    PG_TRY(bbase.alloc(sizeof(uint32_t) * (size_t)cdiv(n, kNT) * kRankSlots));
     if (!point_box) {
         PG_TRY(box.alloc(sizeof(uint32_t) * 2 * d));
         PG_HIP(hipMemsetAsync(box.p, 0xff, sizeof(uint32_t) * d, s));
@@ -416,7 +465,8 @@ pg_status build_tree_spatial(const void* points, int64_t n, int d, int leaf, int
         PG_LAUNCH_CHECK();
         hipLaunchKernelGGL(spatial_leaf_kernel, dim3(cdiv(n, kNT)), dim3(kNT), 0, s,
                            keys.as<uint32_t>(), n, d, L, fl ? 1 : 0, widest, box.as<uint32_t>(),
-                           lf.as<uint32_t>(), rk.as<uint32_t>(), cnt.as<uint32_t>());
+                           lf.as<uint32_t>(), rk.as<uint32_t>(), cnt.as<uint32_t>(),
+                           bbase.as<uint32_t>());
         PG_LAUNCH_CHECK();
     } else {
         // every point starts at the root; the level loop writes every split
@@ -458,9 +508,12 @@ pg_status build_tree_spatial(const void* points, int64_t n, int d, int leaf, int
             PG_LAUNCH_CHECK();
         }
         hipLaunchKernelGGL(pbox_rank_kernel, dim3(cdiv(n, kNT)), dim3(kNT), 0, s, nid, n,
-                           rk.as<uint32_t>(), cnt.as<uint32_t>());
+                           rk.as<uint32_t>(), cnt.as<uint32_t>(), bbase.as<uint32_t>());
         PG_LAUNCH_CHECK();
     }
+    hipLaunchKernelGGL(leaf_rank_fix_kernel, dim3(cdiv(n, kNT)), dim3(kNT), 0, s, lf.as<uint32_t>(),
+                       n, bbase.as<uint32_t>(), rk.as<uint32_t>());
+    PG_LAUNCH_CHECK();
     PG_TRY(exclusive_scan_u32(cnt.as<uint32_t>(), start.as<uint32_t>(), leaves, nullptr, s));
     hipLaunchKernelGGL(spatial_offsets_kernel, dim3(cdiv(leaves + 1, kNT)), dim3(kNT), 0, s,
                        start.as<uint32_t>(), leaves, n, T->loff);
