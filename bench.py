@@ -71,7 +71,7 @@ def measured_traffic(dtype):
     return rec.get("hbm_bytes_per_launch")
 
 
-def write_traffic(fetch_csv, write_csv, dtype, mib, command):
+def write_traffic(fetch_csv, write_csv, dtype, mib, command, out_path=None):
     """Turns two rocprofv3 --pmc counter CSVs (FETCH_SIZE, WRITE_SIZE; KiB per
     dispatch) of a bench run with the copy probe into the traffic summary the
     roofline line reads.  Each counter is scaled by what it reads for the
@@ -104,11 +104,12 @@ def write_traffic(fetch_csv, write_csv, dtype, mib, command):
         "source_hash": knn_source_hash(),
         "command": command,
     }
-    path = os.path.join(ROOT, "profiles", f"knn_all_{dtype}3d_10M_traffic.json")
+    path = out_path or os.path.join(ROOT, "profiles", f"knn_all_{dtype}3d_10M_traffic.json")
     with open(path, "w") as fh:
         json.dump(rec, fh, indent=1)
         fh.write("\n")
     print(json.dumps(rec))
+    return rec
 
 
 def copy_probe(torch, dev, mib):
