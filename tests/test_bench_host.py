@@ -63,3 +63,16 @@ def test_range_bytes_formula():
     tree = 8 * d + 8 * d * bench.R_NODES + 4 * (d + 1) * bench.R_PTS
     assert bench.range_bytes_per_query(d, 10.5, False) == pytest.approx(tree + 4)
     assert bench.range_bytes_per_query(d, 10.5, True) == pytest.approx(tree + 8 + 42)
+
+
+def test_range_constants_match_the_oracle():
+    """R_NODES and R_PTS are the oracle tree search's node boxes and points
+    tested per query on the 2-D range workload (10M uniform points, a square
+    of half side 512 around every point, leaf 16)."""
+    pts = datagen.uniform_int(bench.N, 2, seed=2)
+    t = oracle.KdTree(pts, leaf=bench.LEAF)
+    rows = np.random.default_rng(22).choice(len(pts), 20_000, replace=False)
+    boxes = datagen.range_boxes(pts[rows], 512)
+    *_, cnt = t.range(boxes)
+    assert cnt[0] / len(rows) == pytest.approx(bench.R_NODES, rel=0.01)
+    assert cnt[1] / len(rows) == pytest.approx(bench.R_PTS, rel=0.01)
