@@ -276,11 +276,14 @@ def form_clustered(torch, pg, datagen, dev):
             "build_mpts_s": N / (build_ms * 1e-3) / 1e6}
 
 
-def form_bdl(torch, pg, datagen, dev, rounds):
+def form_bdl(torch, pg, datagen, dev, rounds, with_oracle=False):
     """Batch-dynamic: 10M initial 3-D int points, then rounds of 1M inserts,
-    1M erases of live points, 1M fresh queries (k = 10), X = 2^14."""
+    1M erases of live points, 1M fresh queries (k = 10), X = 2^14.  With
+    the oracle: the serial C oracle's time for the last round's queries (a
+    tree over the live points, 10,000 sampled queries projected to 1M)."""
     import numpy as np
     init, rds = datagen.bdl_rounds(N, rounds, 1_000_000, 1_000_000, 3, seed=5)
+    warm_dynamic(torch, pg, datagen, 3, dev)
     B = pg.BDLTree(3, torch.int32, leaf=LEAF, X=1 << 14, device=dev)
     xi = torch.from_numpy(init).to(dev)
     torch.cuda.synchronize()
@@ -313,12 +316,26 @@ def form_bdl(torch, pg, datagen, dev, rounds):
         qd = torch.from_numpy(rd["queries"]).to(dev)
         knn.append(timed(torch, lambda: B.knn(qd, 10), reps=1))
     med = lambda a: float(np.median(a))
-    return {"workload": "BDL 3-D int, 10M initial, rounds of 1M insert / 1M erase / 1M kNN (k=10), X=2^14",
-            "rounds": rounds, "initial_insert_ms": build_ms,
-            "insert_ms": med(ins), "erase_ms": med(era), "knn_ms": med(knn),
-            "insert_mpts_s": 1.0 / med(ins) * 1e3, "erase_mpts_s": 1.0 / med(era) * 1e3,
-            "knn_qps": 1e6 / (med(knn) * 1e-3), "erased_per_round": erased_total / rounds,
-            "live_points": B.size()}
+    out = {"workload": "BDL 3-D int, 10M initial, rounds of 1M insert / 1M erase / 1M kNN (k=10), X=2^14",
+           "rounds": rounds, "initial_insert_ms": build_ms,
+           "insert_ms": med(ins), "erase_ms": med(era), "knn_ms": med(knn),
+           "insert_mpts_s": 1.0 / med(ins) * 1e3, "erase_mpts_s": 1.0 / med(era) * 1e3,
+           "knn_qps": 1e6 / (med(knn) * 1e-3), "erased_per_round": erased_total / rounds,
+           "live_points": B.size()}
+    if with_oracle and rds:
+        import oracle
+        q = rds[-1]["queries"][:10_000]
+        t0 = time.perf_counter()
+        T = oracle.KdTree(pool, leaf=LEAF)
+        tb = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        T.knn(q, 10)
+        tq = (time.perf_counter() - t0) * len(rds[-1]["queries"]) / len(q)
+        out["oracle_round"] = {"cores": 1, "build_live_s": tb, "knn_1M_s_projected": tq,
+                               "round_s": tb + tq,
+                               "sample": "serial C oracle: one tree over the last round's live points, "
+                                         "10,000 of its 1M queries, projected"}
+    return out
 
 
 def form_baselines(torch, pg, datagen, dev, rounds):
@@ -750,7 +767,7 @@ def main():
         elif f == "clustered":
             out[f] = form_clustered(torch, pg, datagen, dev)
         elif f == "bdl":
-            out[f] = form_bdl(torch, pg, datagen, dev, args.bdl_rounds)
+            out[f] = form_bdl(torch, pg, datagen, dev, args.bdl_rounds, not args.no_cpu_baseline)
         elif f == "batch":
             out[f] = form_batch(torch, pg, datagen, dev, args.loop_clouds)
         elif f == "spatial":
