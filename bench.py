@@ -534,6 +534,31 @@ def form_table1(torch, pg, datagen, dev, n=N):
     return out
 
 
+def form_small_2d(torch, pg, datagen, dev, with_oracle):
+    """The small correctness workload (10,000 uniform 2-D int32 points, all
+    queried, k = 10, leaf 16): GPU build and k-NN (launch-bound at this
+    size), and the oracle's brute force and kd-tree search on one core."""
+    n = 10_000
+    pts = datagen.uniform_int(n, 2, seed=1)
+    x = torch.from_numpy(pts).to(dev)
+    holder = {}
+    out = {"workload": "2-D n=10,000 int32 uniform, k=10, leaf 16, all points"}
+    out["build_ms"] = timed(torch, lambda: holder.__setitem__("t", pg.kdtree_build(x, leaf=LEAF)))
+    t = holder["t"]
+    out["knn_ms"] = timed(torch, lambda: t.knn_all(K))
+    if with_oracle:
+        import oracle
+        t0 = time.perf_counter()
+        oracle.knn_brute(pts, pts, K)
+        out["oracle_brute_s"] = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        T = oracle.KdTree(pts, leaf=LEAF)
+        T.knn(pts, K)
+        out["oracle_kdtree_s"] = time.perf_counter() - t0
+        out["oracle_cores"] = 1
+    return out
+
+
 def form_batch(torch, pg, datagen, dev, loop_clouds):
     """4,096 sphere clouds (sizes log-uniform in [256, 65536]), per-cloud
     all-points k = 16 in one persistent launch, against the per-cloud static
@@ -641,7 +666,7 @@ def main():
     ap.add_argument("--forms", default="all",
                     help="other forms to measure after the headline step: all, none, or a "
                          "comma list of static_float,clustered,spatial,bdl,baselines,batch,range,graph,"
-                         "table1 "
+                         "table1,small_2d "
                          "(sec63, the Section 6.3 protocols on 10M-point sets, runs only when named)")
     ap.add_argument("--bdl-rounds", type=int, default=10)
     ap.add_argument("--sec63-n", type=int, default=N, help="set size of the sec63 form")
@@ -756,7 +781,7 @@ def main():
     del idx, dist, x
     torch.cuda.empty_cache()
     forms = ["static_float", "clustered", "spatial", "bdl", "baselines", "batch", "range", "graph",
-             "table1"] \
+             "table1", "small_2d"] \
         if args.forms == "all" else \
         [f for f in args.forms.split(",") if f and f != "none"]
     out = {}
@@ -776,6 +801,8 @@ def main():
             out[f] = form_baselines(torch, pg, datagen, dev, args.bdl_rounds)
         elif f == "graph":
             out[f] = form_graph(torch, pg, datagen, dev)
+        elif f == "small_2d":
+            out[f] = form_small_2d(torch, pg, datagen, dev, not args.no_cpu_baseline)
         elif f == "table1":
             out[f] = form_table1(torch, pg, datagen, dev)
         elif f == "sec63":
