@@ -206,3 +206,33 @@ def test_trees_grown_from_batches_vary_k(pg, dev, d, n, gen, split):
             oi, od = oracle.knn_brute(pts, pts, k, nthreads=8)
             assert_int_equal(gi, gd, oi, od)
         del G
+
+
+def test_trees_grown_full_size_sampled(pg, dev):
+    """The k sweep's configuration at full size: BDL, B1 and B2 grown from 20
+    batches of 5% of the 10M 2-D VisualVar-style set; 200 sampled queries
+    against the definition for k = 2 and 11."""
+    import torch
+    n = 10_000_000
+    pts = datagen.visual_var(n, 2, seed=65)
+    P = to_dev(pts, dev)
+    chunks = list(torch.chunk(P, 20))
+    rows = np.random.default_rng(66).choice(n, 200, replace=False)
+    q = pts[rows]
+    refs = {k: oracle.knn_brute(pts, q, k, nthreads=16) for k in (2, 11)}
+    for kind in ("bdl", "b1", "b2"):
+        say(f"grown 10M {kind}")
+        G = None
+        for c in chunks:
+            if G is None and kind == "b2":
+                G = pg.B2Tree(c, leaf=16)
+                continue
+            if G is None:
+                cls = pg.BDLTree if kind == "bdl" else pg.B1Tree
+                G = cls(2, torch.int32, leaf=16, device=dev)
+            G.insert(c)
+        assert G.size() == n
+        for k, (oi, od) in refs.items():
+            gi, gd = host(*G.knn(to_dev(q, dev), k))
+            assert_int_equal(gi, gd, oi, od)
+        del G
