@@ -136,3 +136,20 @@ def test_set_allocator_arguments(L):
     half.alloc = _binding.Allocator._fields_[0][1](lambda n, s, c: None)
     assert L.pg_set_allocator(ctypes.byref(half)) == 1 and "both" in _err(L)
     assert L.pg_set_allocator(None) == 0
+
+
+def test_header_is_plain_c(tmp_path):
+    """The boundary header compiles as pedantic C99 (no C++ in the
+    signatures) and as C++17."""
+    import shutil
+    import subprocess
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    src = tmp_path / "h.c"
+    src.write_text('#include "pargeo_hip.h"\nint main(void) { return 0; }\n')
+    for cc, args in (("gcc", ["-std=c99", "-pedantic", "-Wall", "-Wextra", "-Werror"]),
+                     ("g++", ["-std=c++17", "-Wall", "-Werror", "-x", "c++"])):
+        if shutil.which(cc) is None:
+            pytest.skip(f"{cc} not available")
+        r = subprocess.run([cc, *args, "-I", inc, "-fsyntax-only", str(src)],
+                           capture_output=True, text=True)
+        assert r.returncode == 0, r.stderr
