@@ -13,8 +13,9 @@ Parts (each function cites the passage it follows):
                       (Algorithms 3 and 4), in Python;
   * ``grad``       -- the closed-form FP64 gradient of summed k-NN squared
                       distances and central finite differences, in NumPy;
-  * ``spatial_tree`` -- the kd-tree by spatial-median splits (C,
-                      ``or_kd_build_spatial``);
+  * ``spatial_tree`` -- the kd-tree by spatial-median splits, split until
+                      a node holds at most ``leaf`` points (C,
+                      ``or_sp_build``);
   * ``knn_graph_brute`` -- the k-NN graph (each point's k nearest other
                       points) from the k-NN definition;
   * ``range_brute`` / ``KdTree.range`` -- the orthogonal range query written
@@ -61,8 +62,16 @@ def lib():
         L.or_kd_export.restype = None
         L.or_kd_knn.argtypes = [vp, vp, vp, vp, i64, i32, vp, vp, vp]
         L.or_kd_knn.restype = i32
-        L.or_kd_build_spatial.argtypes = [vp, i64, i32, i32, i32, i32, vp, vp, vp, vp, vp]
-        L.or_kd_build_spatial.restype = i32
+        L.or_sp_build.argtypes = [vp, i64, i32, i32, i32, i32]
+        L.or_sp_build.restype = vp
+        L.or_sp_free.argtypes = [vp]
+        L.or_sp_free.restype = None
+        L.or_sp_nodes.argtypes = [vp]
+        L.or_sp_nodes.restype = i64
+        L.or_sp_depth.argtypes = [vp]
+        L.or_sp_depth.restype = i32
+        L.or_sp_export.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+        L.or_sp_export.restype = None
         L.or_range_brute.argtypes = [vp, vp, vp, i64, i32, i32, vp, i64, vp, vp, vp]
         L.or_range_brute.restype = i32
         L.or_kd_range.argtypes = [vp, vp, vp, vp, i64, vp, vp, vp, vp]
@@ -237,37 +246,62 @@ class KdTree:
         return counts, off, out, counters
 
 
+class SpatialTree:
+    """A kd-tree by spatial-median splits, as arrays (nodes numbered
+    breadth-first: the root is 0, a level's nodes in leaf order, the
+    children of an internal node consecutive):
+      split  float64 [N]  cut value (0 for leaves)
+      dim    int32   [N]  cut dimension (-1 for leaves)
+      child  int64   [N]  first child (-1 for leaves); the second is child+1
+      lo, hi int64   [N]  the node's leaf-order positions [lo, hi)
+      level  int32   [N]  depth of the node (root 0)
+      perm   int64   [n]  input rows in leaf order
+      depth  int          levels (1 + the deepest node's depth)"""
+
+    def __init__(self, **kw):
+        self.__dict__.update(kw)
+
+    @property
+    def leaves(self):
+        return np.nonzero(self.child < 0)[0]
+
+    def leaf_sizes(self):
+        lv = self.leaves
+        return self.hi[lv] - self.lo[lv]
+
+
 def spatial_tree(points, leaf=16, rule="cycle", space="cell"):
     """Spatial-median kd-tree (Section 6.3: the node's space cut in half along
-    a dimension), read as: root space = bounding box of the points; node
-    (l, j) cuts its cell at the cell's midpoint (int: floor((lo + hi + 1) /
-    2), cells [lo, s-1] / [s, hi]; float: the float nearest (lo + hi) / 2,
-    cells [lo, s] / [s, hi]) along dimension l mod d (rule "cycle") or along
-    the cell's widest side, lowest dimension on ties (rule "widest");
-    coordinate < s goes left, each side keeps the parent's order; depth L as
-    the object-median tree, so leaf sizes vary.  With space "points" the
-    space a node cuts is the bounding box of its own points (same midpoint
-    and side rules; a node without points takes split 0 and dimension
-    l mod d, or 0 under the widest rule).  Returns (levels, splits float64
-    [2^L] with index 0 unused, split dimensions int32 [2^L], rows int64 [n]
-    in leaf order, leaf offsets int64 [2^L + 1])."""
+    a dimension; Section 5: split until a node holds a small constant number
+    of points), read as: a node holding at most ``leaf`` points, or only
+    identical points, is a leaf; the root's space is the points' bounding
+    box; a node cuts its cell (space "cell") or the bounding box of its own
+    points (space "points") along dimension depth mod d (rule "cycle") or
+    the space's widest side, lowest dimension on ties (rule "widest"); the
+    cut of [lo, hi] is floor((lo + hi + 1) / 2) for int32, the float nearest
+    (lo + hi) / 2 for float32 (the next float above lo when that is lo
+    itself), lo when lo == hi; coordinate < cut goes left (cell [lo, cut-]),
+    the rest right (cell [cut, hi]), each side in the parent's order.
+    Returns a :class:`SpatialTree`."""
     points = np.ascontiguousarray(points)
     dt = _dtype_code(points)
     n, d = points.shape
     r = {"cycle": 0, "widest": 1}[rule] | {"cell": 0, "points": 2}[space]
-    lv = ctypes.c_int()
-    rc = lib().or_kd_build_spatial(_ptr(points), n, d, dt, leaf, r, ctypes.byref(lv),
-                                   None, None, None, None)
-    if rc != 0:
-        raise ValueError("or_kd_build_spatial: bad arguments")
-    L = lv.value
-    splits = np.zeros(1 << L, dtype=np.float64)
-    dims = np.zeros(1 << L, dtype=np.int32)
-    perm = np.empty(n, dtype=np.int64)
-    loff = np.empty((1 << L) + 1, dtype=np.int64)
-    lib().or_kd_build_spatial(_ptr(points), n, d, dt, leaf, r, ctypes.byref(lv), _ptr(splits),
-                              _ptr(dims), _ptr(perm), _ptr(loff))
-    return L, splits, dims, perm, loff
+    h = lib().or_sp_build(_ptr(points), n, d, dt, leaf, r)
+    if not h:
+        raise ValueError("or_sp_build: bad arguments")
+    try:
+        N = lib().or_sp_nodes(h)
+        out = dict(split=np.empty(N, np.float64), dim=np.empty(N, np.int32),
+                   child=np.empty(N, np.int64), lo=np.empty(N, np.int64),
+                   hi=np.empty(N, np.int64), level=np.empty(N, np.int32),
+                   perm=np.empty(n, np.int64))
+        lib().or_sp_export(h, *[_ptr(out[k]) for k in ("split", "dim", "child", "lo", "hi",
+                                                         "level", "perm")])
+        depth = lib().or_sp_depth(h)
+    finally:
+        lib().or_sp_free(h)
+    return SpatialTree(nodes=N, depth=depth, **out)
 
 
 def tree_depth(n: int, leaf: int) -> int:

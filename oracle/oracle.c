@@ -37,9 +37,10 @@
  *                     Table 1) written out: every point inside a closed box.
  *   or_kd_range    -- the same query on the tree (whole subtrees inside the
  *                     box are reported, subtrees outside it skipped).
- *   or_kd_build_spatial -- the tree by spatial-median splits (cell halving,
- *                     or halving of each node's point box), with the
- *                     readings stated at its definition.
+ *   or_sp_build    -- the tree by spatial-median splits (cell halving, or
+ *                     halving of each node's point box), split until a node
+ *                     holds at most `leaf` points, with the readings stated
+ *                     at its definition.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -520,113 +521,169 @@ int or_kd_range(const or_tree* T, const int64_t* ids, const uint8_t* alive,
 
 /* ------------------------------------------------------------------------ */
 /* O8: kd-tree by spatial-median splits (Section 6.3 compares them with the */
-/* object-median splits: a node's space is cut in half along a dimension).  */
-/* Readings: the space of the root is the bounding box of the points; node  */
-/* (l, j) cuts its cell along dimension l mod d at the cell's midpoint s;   */
-/* its points with coordinate < s go left, the others right, each side in   */
-/* the parent's order; the tree keeps the object-median tree's depth        */
-/* L = min{L : ceil(n/2^L) <= leaf}, so leaves hold varying numbers of      */
-/* points.  Midpoints: int cells [lo, hi] cut at floor((lo + hi + 1) / 2)    */
-/* into [lo, s-1] and [s, hi]; float cells [lo, hi] at the float nearest   */
-/* to (lo + hi) / 2 (sum in double) into [lo, s] and [s, hi].  Split        */
-/* dimension: l mod d (rule 0), or the cell's widest side hi - lo, the      */
-/* lowest such dimension on ties (rule bit 0).  With rule bit 1 the space a */
-/* node cuts is the bounding box of its own points instead of its cell (a   */
-/* tight box: the same midpoint and side rules applied to it); a node with  */
-/* no points takes split 0 and dimension l mod d (widest rule: 0).          */
+/* object-median splits: a node's space is cut in half along a dimension;   */
+/* Section 5 defines the kd-tree as splitting until a node holds a small    */
+/* constant number of points).  Readings:                                   */
+/*  - a node is a leaf when it holds at most `leaf` points, or when all of   */
+/*    its points are identical (no cut can separate them);                  */
+/*  - the space of the root is the bounding box of the points; a node cuts  */
+/*    its cell (rule bit 1 clear) or the bounding box of its own points     */
+/*    (rule bit 1 set);                                                     */
+/*  - the cut dimension is depth mod d (rule bit 0 clear) or the space's    */
+/*    widest side hi - lo, the lowest dimension on ties (bit 0 set);        */
+/*  - spaces are closed intervals [lo, hi] of representable coordinates,    */
+/*    and the cut s of [lo, hi] with lo < hi lies in (lo, hi]: int32        */
+/*    floor((lo + hi + 1) / 2); float32 the float nearest (lo + hi) / 2     */
+/*    (sum and halving in double), or the next float above lo when that     */
+/*    nearest float is lo itself.  When lo == hi, s = lo;                   */
+/*  - points with coordinate < s go left (to the cell [lo, s'] with s' the  */
+/*    value just below s), the others right (cell [s, hi]), each side in    */
+/*    the parent's order (a stable partition).                              */
+/* Both children of a cut always shrink the cut side, so every path ends.   */
+/* Nodes are numbered breadth-first: the root is 0, a level's nodes come in */
+/* leaf order, and an internal node's children are consecutive.            */
 /* ------------------------------------------------------------------------ */
-static double sp_mid(double lo, double hi, int dt) {
+typedef struct {
+    int64_t n; int d, dt, leaf, rule, depth;
+    const void* pts;
+    int64_t count, cap;  /* nodes */
+    double* split; int32_t* dim; int64_t* child; int64_t* lo; int64_t* hi; int32_t* level;
+    double* clo; double* chi;  /* cell of each node, [cap][d] */
+    int64_t* perm;             /* rows in leaf order */
+} or_sp_tree;
+
+static double sp_coord(const or_sp_tree* T, int64_t row, int c) {
+    return T->dt == OR_DT_INT ? (double)((const int32_t*)T->pts)[row * T->d + c]
+                              : (double)((const float*)T->pts)[row * T->d + c];
+}
+
+/* The cut of [lo, hi] (see the readings above). */
+static double sp_cut(double lo, double hi, int dt) {
+    if (!(lo < hi)) return lo;
     if (dt == OR_DT_INT) {
         int64_t t = (int64_t)lo + (int64_t)hi + 1;
-        int64_t s = t >= 0 ? t / 2 : -((-t + 1) / 2);
-        return (double)s;
+        return (double)(t >= 0 ? t / 2 : -((-t + 1) / 2));
     }
-    return (double)(float)(0.5 * (lo + hi));
+    float s = (float)(0.5 * (lo + hi));
+    if ((double)s <= lo) s = nextafterf((float)lo, INFINITY);
+    return (double)s;
 }
 
-typedef struct {
-    const void* pts; int64_t n; int d, dt, L, rule;
-    int64_t* perm; int64_t* tmp; double* split; int64_t* loff; int32_t* dim;
-} sp_ctx;
-
-static double sp_coord(const sp_ctx* C, int64_t row, int c) {
-    return C->dt == OR_DT_INT ? (double)((const int32_t*)C->pts)[row * C->d + c]
-                              : (double)((const float*)C->pts)[row * C->d + c];
+/* The largest coordinate below s. */
+static double sp_below(double s, int dt) {
+    return dt == OR_DT_INT ? s - 1.0 : (double)nextafterf((float)s, -INFINITY);
 }
 
-static void sp_rec(sp_ctx* C, int l, int64_t j, int64_t lo, int64_t hi, double* clo, double* chi) {
-    if (l == C->L) { C->loff[j] = lo; return; }
-    double blo[8], bhi[8];
-    const int box = (C->rule & 2) != 0;
-    if (box) {  /* the node's space: the bounding box of its points */
-        for (int e = 0; e < C->d; e++) { blo[e] = INFINITY; bhi[e] = -INFINITY; }
-        for (int64_t p = lo; p < hi; p++)
-            for (int e = 0; e < C->d; e++) {
-                double x = sp_coord(C, C->perm[p], e);
-                if (x < blo[e]) blo[e] = x;
-                if (x > bhi[e]) bhi[e] = x;
-            }
-        clo = blo;
-        chi = bhi;
-    }
-    const int empty = box && lo == hi;
-    int c = l % C->d;
-    if (C->rule & 1) {
-        c = 0;
-        if (!empty)
-            for (int e = 1; e < C->d; e++)
-                if (chi[e] - clo[e] > chi[c] - clo[c]) c = e;
-    }
-    C->dim[((int64_t)1 << l) + j] = c;
-    double s = empty ? 0.0 : sp_mid(clo[c], chi[c], C->dt);
-    C->split[((int64_t)1 << l) + j] = s;
-    /* stable partition of perm[lo, hi) by coordinate < s */
-    int64_t nl = 0, w = lo;
-    for (int64_t p = lo; p < hi; p++) {
-        double x = sp_coord(C, C->perm[p], c);
-        if (x < s) C->perm[w++] = C->perm[p];
-        else C->tmp[nl++] = C->perm[p];
-    }
-    for (int64_t t = 0; t < nl; t++) C->perm[w + t] = C->tmp[t];
-    double save_lo = clo[c], save_hi = chi[c];
-    chi[c] = C->dt == OR_DT_INT ? s - 1 : s;
-    sp_rec(C, l + 1, 2 * j, lo, w, clo, chi);
-    chi[c] = save_hi;
-    clo[c] = s;
-    sp_rec(C, l + 1, 2 * j + 1, w, hi, clo, chi);
-    clo[c] = save_lo;
+static int sp_grow(or_sp_tree* T, int64_t need) {
+    if (need <= T->cap) return 0;
+    int64_t cap = T->cap ? T->cap : 64;
+    while (cap < need) cap *= 2;
+    T->split = (double*)realloc(T->split, sizeof(double) * (size_t)cap);
+    T->dim = (int32_t*)realloc(T->dim, sizeof(int32_t) * (size_t)cap);
+    T->child = (int64_t*)realloc(T->child, sizeof(int64_t) * (size_t)cap);
+    T->lo = (int64_t*)realloc(T->lo, sizeof(int64_t) * (size_t)cap);
+    T->hi = (int64_t*)realloc(T->hi, sizeof(int64_t) * (size_t)cap);
+    T->level = (int32_t*)realloc(T->level, sizeof(int32_t) * (size_t)cap);
+    T->clo = (double*)realloc(T->clo, sizeof(double) * (size_t)(cap * T->d));
+    T->chi = (double*)realloc(T->chi, sizeof(double) * (size_t)(cap * T->d));
+    if (!T->split || !T->dim || !T->child || !T->lo || !T->hi || !T->level || !T->clo || !T->chi)
+        return 1;
+    T->cap = cap;
+    return 0;
 }
 
-/* Builds the spatial-median tree.  Outputs: split_out [2^L] (node h at h,
- * index 0 unused), dim_out [2^L] split dimension of node h, perm_out [n]
- * rows in leaf order, loff_out [2^L + 1] leaf offsets; *levels = L.  Arrays
- * must hold 2^L(+1) entries: call with NULL outputs first to get L. */
-int or_kd_build_spatial(const void* pts, int64_t n, int d, int dt, int leaf, int rule,
-                        int* levels, double* split_out, int32_t* dim_out, int64_t* perm_out,
-                        int64_t* loff_out) {
-    if (d < 1 || d > 8 || leaf < 1 || n < 0 || !levels || rule < 0 || rule > 3) return 1;
-    int L = tree_depth(n, leaf);
-    *levels = L;
-    if (!split_out || !dim_out || !perm_out || !loff_out) return 0;
-    sp_ctx C = {pts, n, d, dt, L, rule, perm_out,
-                (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1)), split_out, loff_out,
-                dim_out};
-    for (int64_t i = 0; i < n; i++) perm_out[i] = i;
-    split_out[0] = 0.0;
-    dim_out[0] = 0;
-    double clo[8], chi[8];
-    for (int c = 0; c < d; c++) { clo[c] = INFINITY; chi[c] = -INFINITY; }
+void or_sp_free(or_sp_tree* T) {
+    if (!T) return;
+    free(T->split); free(T->dim); free(T->child); free(T->lo); free(T->hi); free(T->level);
+    free(T->clo); free(T->chi); free(T->perm); free(T);
+}
+
+or_sp_tree* or_sp_build(const void* pts, int64_t n, int d, int dt, int leaf, int rule) {
+    if (d < 1 || d > 8 || leaf < 1 || n < 0 || rule < 0 || rule > 3) return NULL;
+    or_sp_tree* T = (or_sp_tree*)calloc(1, sizeof(or_sp_tree));
+    T->n = n; T->d = d; T->dt = dt; T->leaf = leaf; T->rule = rule; T->pts = pts;
+    T->perm = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    int64_t* tmp = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    if (!T->perm || !tmp || sp_grow(T, 1)) { free(tmp); or_sp_free(T); return NULL; }
+    for (int64_t i = 0; i < n; i++) T->perm[i] = i;
+    /* the root: every point, the points' bounding box as its cell */
+    T->count = 1;
+    T->lo[0] = 0; T->hi[0] = n; T->level[0] = 0;
+    for (int c = 0; c < d; c++) { T->clo[c] = INFINITY; T->chi[c] = -INFINITY; }
     for (int64_t i = 0; i < n; i++)
         for (int c = 0; c < d; c++) {
-            double x = dt == OR_DT_INT ? (double)((const int32_t*)pts)[i * d + c]
-                                       : (double)((const float*)pts)[i * d + c];
-            if (x < clo[c]) clo[c] = x;
-            if (x > chi[c]) chi[c] = x;
+            double x = sp_coord(T, i, c);
+            if (x < T->clo[c]) T->clo[c] = x;
+            if (x > T->chi[c]) T->chi[c] = x;
         }
-    if (n == 0)
-        for (int c = 0; c < d; c++) { clo[c] = 0; chi[c] = 0; }
-    sp_rec(&C, 0, 0, 0, n, clo, chi);
-    loff_out[(int64_t)1 << L] = n;
-    free(C.tmp);
-    return 0;
+    /* breadth-first: node u's children are appended when u is cut */
+    for (int64_t u = 0; u < T->count; u++) {
+        const int64_t lo = T->lo[u], hi = T->hi[u];
+        T->split[u] = 0.0; T->dim[u] = -1; T->child[u] = -1;
+        if (T->level[u] + 1 > T->depth) T->depth = T->level[u] + 1;
+        if (hi - lo <= leaf) continue;
+        double blo[8], bhi[8];
+        for (int c = 0; c < d; c++) { blo[c] = INFINITY; bhi[c] = -INFINITY; }
+        for (int64_t p = lo; p < hi; p++)
+            for (int c = 0; c < d; c++) {
+                double x = sp_coord(T, T->perm[p], c);
+                if (x < blo[c]) blo[c] = x;
+                if (x > bhi[c]) bhi[c] = x;
+            }
+        int same = 1;
+        for (int c = 0; c < d; c++) if (blo[c] != bhi[c]) same = 0;
+        if (same) continue;  /* identical points: a leaf */
+        const double* slo = (rule & 2) ? blo : T->clo + u * d;
+        const double* shi = (rule & 2) ? bhi : T->chi + u * d;
+        int c = T->level[u] % d;
+        if (rule & 1) {
+            c = 0;
+            for (int e = 1; e < d; e++)
+                if (shi[e] - slo[e] > shi[c] - slo[c]) c = e;
+        }
+        const double s = sp_cut(slo[c], shi[c], dt);
+        /* stable partition of perm[lo, hi) by coordinate < s */
+        int64_t w = lo, nr = 0;
+        for (int64_t p = lo; p < hi; p++) {
+            int64_t row = T->perm[p];
+            if (sp_coord(T, row, c) < s) T->perm[w++] = row;
+            else tmp[nr++] = row;
+        }
+        for (int64_t t = 0; t < nr; t++) T->perm[w + t] = tmp[t];
+        if (sp_grow(T, T->count + 2)) { free(tmp); or_sp_free(T); return NULL; }
+        const int64_t a = T->count, b = a + 1;
+        T->count += 2;
+        T->split[u] = s; T->dim[u] = c; T->child[u] = a;
+        T->lo[a] = lo; T->hi[a] = w; T->lo[b] = w; T->hi[b] = hi;
+        T->level[a] = T->level[b] = T->level[u] + 1;
+        for (int e = 0; e < d; e++) {
+            T->clo[a * d + e] = T->clo[b * d + e] = T->clo[u * d + e];
+            T->chi[a * d + e] = T->chi[b * d + e] = T->chi[u * d + e];
+        }
+        /* the children's cells: the cut side of the node's cell (in the
+         * point-box form the cells are carried along but unused) */
+        T->chi[a * d + c] = sp_below(s, dt);
+        T->clo[b * d + c] = s;
+    }
+    free(tmp);
+    return T;
+}
+
+int64_t or_sp_nodes(const or_sp_tree* T) { return T->count; }
+int or_sp_depth(const or_sp_tree* T) { return T->depth; }
+
+/* Copies the tree out: per node (count entries) split value (0 for
+ * leaves), split dimension (-1 for leaves), first child (-1 for leaves; the
+ * second child follows it), leaf-order range [lo, hi), depth; rows in leaf
+ * order (n entries).  Any output may be NULL. */
+void or_sp_export(const or_sp_tree* T, double* split, int32_t* dim, int64_t* child, int64_t* lo,
+                  int64_t* hi, int32_t* level, int64_t* perm) {
+    size_t c = (size_t)T->count;
+    if (split) memcpy(split, T->split, sizeof(double) * c);
+    if (dim) memcpy(dim, T->dim, sizeof(int32_t) * c);
+    if (child) memcpy(child, T->child, sizeof(int64_t) * c);
+    if (lo) memcpy(lo, T->lo, sizeof(int64_t) * c);
+    if (hi) memcpy(hi, T->hi, sizeof(int64_t) * c);
+    if (level) memcpy(level, T->level, sizeof(int32_t) * c);
+    if (perm && T->n > 0) memcpy(perm, T->perm, sizeof(int64_t) * (size_t)T->n);
 }

@@ -189,3 +189,62 @@ def test_knn_graph_many_duplicates_drop_last():
     gi, gd = oracle.knn_graph_brute(pts, 10)
     assert gi[11].tolist() == list(range(10)) and gd[11].tolist() == [0] * 10
     assert gi[0].tolist() == list(range(1, 11))
+
+
+# --- the search's visit counters, on trees small enough to walk by hand ------
+# (internal nodes entered, leaves whose points were offered, points offered).
+# Tree over the 1-D points 0..7 with leaf 2: the root splits at the value of
+# rank 4 (4), level 1 at ranks 2 and 6 (values 2 and 6), leaves {0,1} {2,3}
+# {4,5} {6,7}.
+
+def _line_tree():
+    pts = np.arange(8, dtype=np.int32).reshape(-1, 1)
+    t = oracle.KdTree(pts, leaf=2)
+    assert t.export()[0].tolist() == [4, 2, 6]
+    return t
+
+
+def test_visit_counters_hand_worked_1d():
+    t = _line_tree()
+    # q = 3, k = 3: root (internal 1) -> node [0,4) (internal 2) -> leaf
+    # {2,3} (2 points); fewer than k, so the sibling leaf {0,1} is added
+    # whole (2 more); back at the root the 3rd key is (4, id 1) and the far
+    # node [4,8) has box [4, 7], lower bound 1 <= 4: entered (internal 3),
+    # its near leaf {4,5} added (6 points); the 3rd key is now (1, id 4) and
+    # leaf {6,7} (lower bound 9) is pruned.
+    ids, dist, c = t.knn(np.array([[3]], np.int32), 3)
+    assert ids.tolist() == [[3, 2, 4]] and dist.tolist() == [[0, 1, 1]]
+    assert c.tolist() == [3, 3, 6]
+    # q = 4, k = 2: root -> [4,8) -> leaf {4,5}; the 2nd key (1, id 5) prunes
+    # {6,7} (lower bound 4); back at the root the box [0, 3] has lower bound
+    # 1, not above 1: entered (internal 3), leaf {2,3} offered; the 2nd key
+    # becomes (1, id 3) and {0,1} (lower bound 9) is pruned.
+    ids, dist, c = t.knn(np.array([[4]], np.int32), 2)
+    assert ids.tolist() == [[4, 3]] and dist.tolist() == [[0, 1]]
+    assert c.tolist() == [3, 2, 4]
+    # q = 3, k = 6: too few candidates after each near subtree, so every
+    # sibling subtree is added whole: 2 internal nodes, 4 leaves, 8 points
+    ids, dist, c = t.knn(np.array([[3]], np.int32), 6)
+    assert ids.tolist() == [[3, 2, 4, 1, 5, 0]] and c.tolist() == [2, 4, 8]
+    # counters sum over queries; q = 4, k = 3 mirrors q = 3 (root -> [4,8)
+    # -> {4,5}, sibling {6,7} added, [0,4) entered, {2,3} offered, {0,1}
+    # pruned): 3, 3, 6 each
+    _, _, c = t.knn(np.array([[3], [4]], np.int32), 3)
+    assert c.tolist() == [6, 6, 12]
+
+
+def test_visit_counters_hand_worked_contained_subtree():
+    # 2-D, leaf 1: rows (0,0) (0,100) (1,50) (1,51).  The root splits x at
+    # rank 2 (x = 1); the left node splits y at its rank-1 point (y = 100),
+    # the right node at y = 51.  Query (0, 100), k = 2: root -> left node ->
+    # leaf {(0,100)} (D 0); the sibling leaf {(0,0)} is added (D 10000);
+    # back at the root the right node's box x [1,1], y [50,51] lies within
+    # the 2nd distance (its farthest corner is at 1 + 50^2 = 2501 <= 10000),
+    # so it is added whole without entering it: 2 internal nodes, 4 leaves,
+    # 4 points.
+    pts = np.array([[0, 0], [0, 100], [1, 50], [1, 51]], dtype=np.int32)
+    t = oracle.KdTree(pts, leaf=1)
+    assert t.export()[0].tolist() == [1, 100, 51]
+    ids, dist, c = t.knn(np.array([[0, 100]], np.int32), 2)
+    assert ids.tolist() == [[1, 3]] and dist.tolist() == [[0, 2402]]
+    assert c.tolist() == [2, 4, 4]

@@ -96,33 +96,99 @@ def test_cfg1_depth_and_leaves():
     assert t.levels == 10
 
 
-# --- spatial-median tree (cell halving) -------------------------------------
+# --- spatial-median tree (split until a node holds at most `leaf` points) ---
 
-def test_spatial_hand_worked_int_and_float():
-    # 1-D int 0..9: root cell [0, 9] cut at floor(10/2) = 5; [0, 4] at
-    # floor(5/2) = 2; [5, 9] at floor(15/2) = 7.  Depth 2 for leaf 3.
-    pts = np.arange(10, dtype=np.int32).reshape(-1, 1)
-    L, s, _, perm, loff = oracle.spatial_tree(pts, leaf=3)
-    assert L == 2 and s[1:].tolist() == [5, 2, 7]
-    assert loff.tolist() == [0, 2, 5, 7, 10] and perm.tolist() == list(range(10))
-    # 1-D float {0, .25, .5, .75, 1}: [0, 1] at .5; [0, .5] at .25; [.5, 1] at .75
+def _sp(pts, leaf, rule="cycle", space="cell"):
+    return oracle.spatial_tree(np.asarray(pts), leaf=leaf, rule=rule, space=space)
+
+
+def _leaf_rows(t):
+    return [t.perm[t.lo[u]:t.hi[u]].tolist() for u in t.leaves]
+
+
+def test_spatial_hand_worked_1d_int():
+    # 0..9, leaf 3: root cell [0, 9] cut at floor(10/2) = 5; left {0..4} (5 > 3
+    # points) cell [0, 4] cut at floor(5/2) = 2; right {5..9} cell [5, 9] cut at
+    # floor(15/2) = 7; the four children hold 2, 3, 2, 3 points: leaves.
+    t = _sp(np.arange(10, dtype=np.int32).reshape(-1, 1), 3)
+    assert t.nodes == 7 and t.depth == 3
+    assert t.split[:3].tolist() == [5, 2, 7] and t.dim[:3].tolist() == [0, 0, 0]
+    assert t.child.tolist() == [1, 3, 5, -1, -1, -1, -1]
+    assert t.lo.tolist() == [0, 0, 5, 0, 2, 5, 7] and t.hi.tolist() == [10, 5, 10, 2, 5, 7, 10]
+    assert t.level.tolist() == [0, 1, 1, 2, 2, 2, 2]
+    assert t.perm.tolist() == list(range(10))
+
+
+def test_spatial_hand_worked_variable_depth_cell_and_box():
+    # {0, 1000..1004} in the input order below, leaf 2.  Cell halving: the
+    # root [0, 1004] cuts at 502: {0} | {1000..1004}; the right cell [502,
+    # 1004] then cuts at 753, 879, 942, 973, 989, 997 with an empty left child
+    # each time; [997, 1004] cuts at 1001: {1000} | {1001..1004}; [1001, 1004]
+    # cuts at 1003: {1001, 1002} | {1003, 1004}.
+    vals = [1003, 0, 1001, 1000, 1004, 1002]
+    pts = np.array(vals, dtype=np.int32).reshape(-1, 1)
+    t = _sp(pts, 2)
+    inner = t.child >= 0
+    assert t.split[inner].tolist() == [502, 753, 879, 942, 973, 989, 997, 1001, 1003]
+    assert t.depth == 10
+    assert [[vals[r] for r in rows] for rows in _leaf_rows(t)] == \
+        [[0]] + [[]] * 6 + [[1000], [1001, 1002], [1003, 1004]]
+    assert t.leaf_sizes().max() <= 2
+    # point boxes: the root box [0, 1004] cuts at 502; {1000..1004} has box
+    # [1000, 1004], cut at floor(2005/2) = 1002: {1001, 1000} | {1003, 1004,
+    # 1002} (input order kept); the latter, box [1002, 1004], cuts at 1003:
+    # {1002} | {1003, 1004}.
+    t = _sp(pts, 2, space="points")
+    assert t.split[t.child >= 0].tolist() == [502, 1002, 1003]
+    assert [[vals[r] for r in rows] for rows in _leaf_rows(t)] == \
+        [[0], [1001, 1000], [1002], [1003, 1004]]
+    assert t.depth == 4
+
+
+def test_spatial_hand_worked_float():
+    # {1, .5, 0, .75, .25}, leaf 2: cell [0, 1] cuts at .5: {0, .25} | {1, .5,
+    # .75}; the right cell [.5, 1] cuts at .75: {.5} | {1, .75}.  The left
+    # cell of a float cut ends at the float just below the cut.
     f = np.array([1.0, 0.5, 0.0, 0.75, 0.25], dtype=np.float32).reshape(-1, 1)
-    L, s, _, perm, loff = oracle.spatial_tree(f, leaf=2)
-    assert L == 2 and s[1:].tolist() == [0.5, 0.25, 0.75]
-    # stable: rows 0 (1.0) and 3 (0.75) keep their input order in the last leaf
-    assert loff.tolist() == [0, 1, 2, 3, 5] and perm.tolist() == [2, 4, 1, 0, 3]
+    t = _sp(f, 2)
+    assert t.split[t.child >= 0].tolist() == [0.5, 0.75]
+    assert _leaf_rows(t) == [[2, 4], [1], [0, 3]]
+    # two adjacent floats: the nearest float to their midpoint is the lower
+    # one (ties to even), so the cut moves up to the upper one
+    one = np.float32(1.0)
+    up = np.nextafter(one, np.float32(2.0))
+    g = np.array([up, one, up, one, one, up], dtype=np.float32).reshape(-1, 1)
+    t = _sp(g, 2)
+    assert t.nodes == 3 and t.split[0] == float(up)
+    assert _leaf_rows(t) == [[1, 3, 4], [0, 2, 5]]
+
+
+def test_spatial_identical_points_form_one_leaf():
+    # more identical points than `leaf`: no cut can separate them
+    t = _sp(np.full((37, 3), 5, dtype=np.int32), 4)
+    assert t.nodes == 1 and t.child[0] == -1 and t.hi[0] == 37
+    # beside one other point: the root cuts [5, 9] at 7 (dimension 0); the
+    # 37 identical points then form one leaf
+    pts = np.full((38, 3), 5, dtype=np.int32)
+    pts[17] = 9
+    for space in ("cell", "points"):
+        t = _sp(pts, 4, space=space)
+        assert t.nodes == 3 and t.split[0] == 7
+        assert _leaf_rows(t) == [[r for r in range(38) if r != 17], [17]]
 
 
 def test_spatial_full_grid_is_morton_order():
     # all of {0..15}^2 with one point per leaf: the cells are dyadic, so the
-    # leaf of (x, y) interleaves the bits of x and y (x first, high bits first)
+    # leaves, all at depth 8, come in the order that interleaves the bits of
+    # x and y (x first, high bits first)
     k = 4
     xs, ys = np.meshgrid(np.arange(1 << k), np.arange(1 << k), indexing="ij")
     pts = np.stack([xs.ravel(), ys.ravel()], axis=1).astype(np.int32)
     rng = np.random.default_rng(0)
     pts = pts[rng.permutation(len(pts))]
-    L, s, _, perm, loff = oracle.spatial_tree(pts, leaf=1)
-    assert L == 2 * k and np.all(np.diff(loff) == 1)
+    t = _sp(pts, 1)
+    assert t.depth == 2 * k + 1 and t.nodes == 2 * len(pts) - 1
+    assert np.all(t.level[t.leaves] == 2 * k) and np.all(t.leaf_sizes() == 1)
 
     def morton(x, y):
         m = 0
@@ -131,156 +197,98 @@ def test_spatial_full_grid_is_morton_order():
         return m
 
     want = np.argsort([morton(int(x), int(y)) for x, y in pts])
-    assert perm.tolist() == want.tolist()
+    assert t.perm.tolist() == want.tolist()
 
 
-def test_spatial_identical_points_go_right():
-    pts = np.full((37, 3), 5, dtype=np.int32)
-    L, s, _, perm, loff = oracle.spatial_tree(pts, leaf=4)
-    sizes = np.diff(loff)
-    assert sizes[-1] == 37 and sizes[:-1].sum() == 0 and perm.tolist() == list(range(37))
+def test_spatial_widest_rule_hand_worked():
+    # cell 0..31 x 0..15, leaf 64: x is widest -> cut at 16; each half is
+    # 16 x 16, a tie -> x again (the lowest dimension): 8 and 24; then y
+    # (8 x 16) at 8; 64 points per node: leaves
+    xs, ys = np.meshgrid(np.arange(32), np.arange(16), indexing="ij")
+    pts = np.stack([xs.ravel(), ys.ravel()], axis=1).astype(np.int32)
+    t = _sp(pts, 64, rule="widest")
+    assert t.nodes == 15
+    assert t.dim[:7].tolist() == [0, 0, 0, 1, 1, 1, 1]
+    assert t.split[:7].tolist() == [16, 8, 24, 8, 8, 8, 8]
+    assert np.all(t.leaf_sizes() == 64)
+    # the cyclic rule cuts y at the second level instead
+    t = _sp(pts, 64, rule="cycle")
+    assert t.dim[:3].tolist() == [0, 1, 1] and t.split[:3].tolist() == [16, 8, 8]
 
 
-@pytest.mark.parametrize("d,leaf,dtype", [(2, 4, np.int32), (3, 8, np.float32), (5, 2, np.int32)])
-def test_spatial_invariants(d, leaf, dtype):
+def _check_structure(t, pts, leaf, rule, space):
+    """Invariants of a spatial tree: ranges nest and partition, every cut
+    separates its node, lies in its space and takes the rule's dimension,
+    leaves hold at most `leaf` points unless identical, rows keep their
+    order inside each leaf (stable partitions)."""
+    n, d = pts.shape
+    P = pts[t.perm].astype(np.float64)
+    assert sorted(t.perm.tolist()) == list(range(n))
+    assert t.lo[0] == 0 and t.hi[0] == n
+    for u in range(t.nodes):
+        lo, hi = t.lo[u], t.hi[u]
+        if t.child[u] < 0:
+            box = P[lo:hi]
+            if hi - lo > leaf:
+                assert np.all(box == box[0]), f"leaf {u} of {hi - lo} non-identical points"
+            assert np.all(np.diff(t.perm[lo:hi]) > 0)
+            continue
+        a = t.child[u]
+        assert t.lo[a] == lo and t.hi[a] == t.lo[a + 1] and t.hi[a + 1] == hi
+        assert t.level[a] == t.level[a + 1] == t.level[u] + 1
+        c, s = t.dim[u], t.split[u]
+        assert np.all(P[lo:t.hi[a], c] < s) and np.all(P[t.lo[a + 1]:hi, c] >= s)
+        blo, bhi = P[lo:hi].min(axis=0), P[lo:hi].max(axis=0)
+        if space == "points":
+            assert blo[c] < s <= bhi[c] or blo[c] == bhi[c] == s
+            if rule == "widest":
+                assert c == int(np.argmax(bhi - blo))
+        if rule == "cycle":
+            assert c == t.level[u] % d
+    # breadth-first numbering: levels non-decreasing, leaf order within a level
+    assert np.all(np.diff(t.level) >= 0)
+    for lv in range(t.depth):
+        sel = np.nonzero(t.level == lv)[0]
+        assert np.all(np.diff(t.lo[sel]) >= 0)
+
+
+@pytest.mark.parametrize("d,leaf,dtype,rule,space", [
+    (2, 4, np.int32, "cycle", "cell"), (3, 8, np.float32, "cycle", "cell"),
+    (5, 2, np.int32, "widest", "cell"), (3, 8, np.float32, "widest", "points"),
+    (2, 1, np.int32, "cycle", "points"), (4, 16, np.float32, "cycle", "points")])
+def test_spatial_invariants(d, leaf, dtype, rule, space):
     rng = np.random.default_rng(d * 10 + leaf)
     n = 3000
     if dtype == np.int32:
         pts = rng.integers(-500, 500, (n, d)).astype(np.int32)
-        pts[::5] = pts[7]
+        pts[::5] = pts[7]          # heavy duplicates
     else:
         pts = (rng.standard_normal((n, d)) ** 3).astype(np.float32)
-    L, s, _, perm, loff = oracle.spatial_tree(pts, leaf=leaf)
-    assert L == oracle.tree_depth(n, leaf)
-    assert sorted(perm.tolist()) == list(range(n))
-    leaf_of = np.repeat(np.arange(1 << L), np.diff(loff))
-    # rows ascending inside every leaf (each side keeps the parent's order)
-    for j in range(1 << L):
-        rows = perm[loff[j]:loff[j + 1]]
-        assert np.all(np.diff(rows) > 0)
-    # every internal node separates: left coordinates < split <= right ones
-    P = pts[perm].astype(np.float64)
-    for h in range(1, 1 << L):
-        l = h.bit_length() - 1
-        j = h - (1 << l)
-        c = l % d
-        span = 1 << (L - l)
-        lo, mid, hi = loff[j * span], loff[j * span + span // 2], loff[(j + 1) * span]
-        assert np.all(P[lo:mid, c] < s[h]) and np.all(P[mid:hi, c] >= s[h])
+        pts[::7] = pts[3]
+    t = _sp(pts, leaf, rule, space)
+    _check_structure(t, pts, leaf, rule, space)
 
 
-def test_spatial_widest_rule_hand_worked():
-    # cell 0..31 x 0..15: x is widest -> cut at 16; each half is 16 x 16, a
-    # tie -> x again (the lowest dimension): 8 and 24; then y (8 x 16) at 8
-    xs, ys = np.meshgrid(np.arange(32), np.arange(16), indexing="ij")
-    pts = np.stack([xs.ravel(), ys.ravel()], axis=1).astype(np.int32)
-    L, s, dims, perm, loff = oracle.spatial_tree(pts, leaf=64, rule="widest")
-    assert L == 3
-    assert dims[1:4].tolist() == [0, 0, 0] and s[1:4].tolist() == [16, 8, 24]
-    assert dims[4:8].tolist() == [1, 1, 1, 1] and s[4:8].tolist() == [8, 8, 8, 8]
-    assert np.all(np.diff(loff) == 64)
-    # the cyclic rule cuts y at the second level instead
-    L, s, dims, perm, loff = oracle.spatial_tree(pts, leaf=64, rule="cycle")
-    assert dims[1:4].tolist() == [0, 1, 1] and s[1:4].tolist() == [16, 8, 8]
-
-
-@pytest.mark.parametrize("dtype", [np.int32, np.float32])
-def test_spatial_widest_invariants(dtype):
-    rng = np.random.default_rng(9)
-    n, d, leaf = 4000, 3, 8
-    scale = np.array([1000.0, 30.0, 200.0])
-    pts = (rng.random((n, d)) * scale).astype(dtype)
-    L, s, dims, perm, loff = oracle.spatial_tree(pts, leaf=leaf, rule="widest")
-    assert dims[1] == 0  # the root's widest side
-    P = pts[perm].astype(np.float64)
-    for h in range(1, 1 << L):
-        l = h.bit_length() - 1
-        j = h - (1 << l)
-        c = dims[h]
-        span = 1 << (L - l)
-        lo, mid, hi = loff[j * span], loff[j * span + span // 2], loff[(j + 1) * span]
-        assert np.all(P[lo:mid, c] < s[h]) and np.all(P[mid:hi, c] >= s[h])
-    for j in range(1 << L):
-        assert np.all(np.diff(perm[loff[j]:loff[j + 1]]) > 0)
-
-
-# --- spatial-median tree, each node cutting the bounding box of its points ---
-
-def test_spatial_point_box_hand_worked():
-    # 1-D int {100, 2, 0, 1}, leaf 1 (depth 2).  Point boxes: root [0, 100]
-    # cut at floor(101/2) = 50; left {2, 0, 1}: box [0, 2] cut at
-    # floor(3/2) = 1 -> {0} | {2, 1}; right {100}: box [100, 100] cut at
-    # 100 -> {} | {100}.
-    pts = np.array([[100], [2], [0], [1]], dtype=np.int32)
-    L, s, dims, perm, loff = oracle.spatial_tree(pts, leaf=1, space="points")
-    assert L == 2 and s[1:].tolist() == [50, 1, 100] and dims[1:].tolist() == [0, 0, 0]
-    assert loff.tolist() == [0, 1, 3, 3, 4] and perm.tolist() == [2, 1, 3, 0]
-    # cell halving on the same points: [0, 49] cut at 25, [50, 100] at 75
-    L, s, _, perm, loff = oracle.spatial_tree(pts, leaf=1, space="cell")
-    assert s[1:].tolist() == [50, 25, 75] and loff.tolist() == [0, 3, 3, 3, 4]
-    # float {0, .25, .5, 4}: [0, 4] at 2; [0, .5] at .25; [4, 4] at 4
-    f = np.array([[4.0], [0.5], [0.0], [0.25]], dtype=np.float32)
-    L, s, _, perm, loff = oracle.spatial_tree(f, leaf=1, space="points")
-    assert s[1:].tolist() == [2.0, 0.25, 4.0]
-    assert loff.tolist() == [0, 1, 3, 3, 4] and perm.tolist() == [2, 1, 3, 0]
-
-
-def test_spatial_point_box_empty_node():
-    # {0..6, 1000}, leaf 1 (depth 3): the root cuts [0, 1000] at 500; the
-    # right node {1000} cuts [1000, 1000] at 1000, so its left child (node 6,
-    # an internal node) is empty and takes split 0
-    pts = np.array([[v] for v in (0, 1, 2, 3, 4, 5, 6, 1000)], dtype=np.int32)
-    L, s, dims, perm, loff = oracle.spatial_tree(pts, leaf=1, space="points")
-    assert L == 3 and s[1] == 500 and s[3] == 1000 and s[6] == 0
-    assert np.diff(loff).tolist()[4:] == [0, 0, 0, 1]
-    # 2-D: an empty node takes dimension l mod d, or 0 under the widest rule
-    p2 = np.array([[0, 0], [1, 5], [2, 1], [3, 3], [4, 2], [5, 6], [6, 4], [1000, 9]], dtype=np.int32)
-    for rule in ("cycle", "widest"):
-        L, s, dims, perm, loff = oracle.spatial_tree(p2, leaf=1, rule=rule, space="points")
-        for h in range(1, 1 << L):
-            l = h.bit_length() - 1
-            span = 1 << (L - l)
-            j = h - (1 << l)
-            if loff[j * span] == loff[(j + 1) * span]:
-                assert s[h] == 0 and dims[h] == (l % 2 if rule == "cycle" else 0)
-
-
-@pytest.mark.parametrize("rule,dtype", [("cycle", np.int32), ("widest", np.int32),
-                                        ("cycle", np.float32), ("widest", np.float32)])
-def test_spatial_point_box_invariants(rule, dtype):
-    # a dense cluster beside a sparse background: every split lies inside its
-    # node's point box and separates it; the widest rule takes that box's
-    # widest side; once the cluster's node holds only cluster points, cutting
-    # point boxes spreads it over many leaves, while cell halving keeps it in
-    # one leaf (its cells stay far wider than the cluster)
+@pytest.mark.parametrize("space", ["cell", "points"])
+def test_spatial_dense_cluster_is_resolved(space):
+    # a dense cluster beside a sparse background: the cluster is cut until
+    # every leaf holds at most `leaf` points (the fixed-depth reading had left
+    # it in one leaf); cell halving reaches it deeper than point boxes do
     rng = np.random.default_rng(31)
     n, d, leaf = 4000, 3, 8
-    if dtype == np.int32:
-        bg = rng.integers(0, 1 << 19, (n // 4, d))
-        cl = 1_000_000 + rng.integers(0, 64, (n - n // 4, d))
-    else:
-        bg = 0.5 * rng.random((n // 4, d))
-        cl = 0.95 + 1e-4 * rng.random((n - n // 4, d))
-    pts = np.concatenate([bg, cl]).astype(dtype)[rng.permutation(n)]
-    L, s, dims, perm, loff = oracle.spatial_tree(pts, leaf=leaf, rule=rule, space="points")
-    assert sorted(perm.tolist()) == list(range(n))
-    P = pts[perm].astype(np.float64)
-    for h in range(1, 1 << L):
-        l = h.bit_length() - 1
-        j = h - (1 << l)
-        span = 1 << (L - l)
-        lo, mid, hi = loff[j * span], loff[j * span + span // 2], loff[(j + 1) * span]
-        if lo == hi:
-            continue
-        box_lo, box_hi = P[lo:hi].min(axis=0), P[lo:hi].max(axis=0)
-        c = dims[h]
-        if rule == "widest":
-            assert c == int(np.argmax(box_hi - box_lo))
-        else:
-            assert c == l % d
-        assert box_lo[c] <= s[h] <= box_hi[c]
-        assert np.all(P[lo:mid, c] < s[h]) and np.all(P[mid:hi, c] >= s[h])
-    for j in range(1 << L):
-        assert np.all(np.diff(perm[loff[j]:loff[j + 1]]) > 0)
-    cell = oracle.spatial_tree(pts, leaf=leaf, rule=rule, space="cell")[4]
-    assert 8 * np.diff(loff).max() < np.diff(cell).max()
+    bg = rng.integers(0, 1 << 19, (n // 4, d))
+    cl = 1_000_000 + rng.integers(0, 4096, (n - n // 4, d))
+    pts = np.concatenate([bg, cl]).astype(np.int32)[rng.permutation(n)]
+    t = _sp(pts, leaf, space=space)
+    _check_structure(t, pts, leaf, "cycle", space)
+    assert t.leaf_sizes().max() <= leaf
+    deep = _sp(pts, leaf, space="cell").depth
+    assert t.depth <= deep
+
+
+def test_spatial_small_and_empty():
+    for n in (0, 1, 2, 16, 17):
+        pts = np.arange(3 * n, dtype=np.int32).reshape(n, 3)
+        t = _sp(pts, 16)
+        assert t.hi[0] == n
+        assert t.nodes == (1 if n <= 16 else 3)
