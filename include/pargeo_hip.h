@@ -94,34 +94,56 @@ pg_status pg_kdtree_build(const void* points, int64_t n, int32_t d, int32_t leaf
                           int32_t dtype, void* stream, pg_tree** out);
 
 /* Builds a kd-tree by spatial-median splits (the alternative split rule
- * Section 6.3 measures: a node's space is cut in half along a dimension).
- * Readings: the root's space is the bounding box of the points; node
- * (l, j) cuts its cell at the cell's midpoint s (int32: floor((lo + hi + 1)
- * / 2), halves [lo, s-1] and [s, hi]; float32: the float nearest
- * (lo + hi) / 2, halves [lo, s] and [s, hi]) along dimension l mod d
- * (dim_rule bit 0 clear) or along the cell's widest side, the lowest
- * dimension on ties (bit 0 set); points with coordinate < s go left.  With
- * dim_rule bit 1 set, the space a node cuts is the bounding box of its own
- * points instead of its cell (same midpoint and side rules; a node with no
- * points takes split 0 and dimension l mod d, or 0 under the widest rule),
- * which follows clusters that cell halving leaves in one leaf.  The depth L
- * and heap layout are those of pg_kdtree_build, so leaves hold varying
- * numbers of points (possibly more than `leaf`, or none); pg_tree_offsets
- * gives the leaf ranges.  The order of points inside a leaf is unspecified.
- * Every query call accepts the result (pg_knn, pg_knn_all, pg_knn_graph,
- * pg_range_*).  Arguments and errors as pg_kdtree_build; dim_rule in
- * [0, 3]. */
+ * Section 6.3 measures: a node's space is cut in half along a dimension),
+ * split, as Section 5 defines a kd-tree, until a node holds a small constant
+ * number of points.  Readings: a node holding at most `leaf` points, or only
+ * identical points, is a leaf; the root's space is the bounding box of the
+ * points; a node cuts its cell (dim_rule bit 1 clear) or the bounding box of
+ * its own points (bit 1 set) along dimension depth mod d (bit 0 clear) or
+ * along the space's widest side, the lowest dimension on ties (bit 0 set);
+ * the cut s of space [lo, hi] (lo < hi) is floor((lo + hi + 1) / 2) for
+ * int32 and the float nearest (lo + hi) / 2 for float32 (the next float above
+ * lo when that is lo itself), s = lo when lo == hi; points with coordinate
+ * < s go to the first child (cell [lo, s-], s- the value just below s), the
+ * others to the second (cell [s, hi]), each side keeping the parent's order.
+ * The result is an explicit-node tree of any depth: nodes numbered
+ * breadth-first (root 0, the two children of a node consecutive), leaves
+ * holding at most `leaf` points apart from identical points, empty leaves
+ * where a cut leaves one side empty.  pg_tree_nodes and
+ * pg_tree_export_nodes describe it; pg_tree_offsets gives the leaf ranges in
+ * leaf order; every query call accepts it (pg_knn, pg_knn_all,
+ * pg_knn_graph, pg_range_*).  Arguments and errors as pg_kdtree_build;
+ * dim_rule in [0, 3]. */
 pg_status pg_kdtree_build_spatial(const void* points, int64_t n, int32_t d, int32_t leaf,
                                   int32_t dtype, int32_t dim_rule, void* stream, pg_tree** out);
 
 /* Split dimension of every internal heap node (host, [2^L] bytes, index 0
- * unused): l mod d unless the tree was built with per-node dimensions.
- * Synchronises for such trees. */
+ * unused): l mod d.  PG_ERR_UNSUPPORTED for explicit-node trees
+ * (pg_kdtree_build_spatial), which pg_tree_export_nodes describes. */
 pg_status pg_tree_split_dims(const pg_tree* t, uint8_t* dims_host, void* stream);
 
-/* Leaf offsets (host, [2^L + 1]): leaf j holds leaf-order positions
- * [loff[j], loff[j+1]) (the closed form floor(j n / 2^L) for trees from
- * pg_kdtree_build).  Synchronises for spatial-median trees. */
+/* Number of nodes and of leaves (host outputs; either may be NULL): 2^(L+1)
+ * - 1 and 2^L for trees from pg_kdtree_build, the node and leaf counts of
+ * explicit-node trees. */
+pg_status pg_tree_nodes(const pg_tree* t, int64_t* nodes, int64_t* leaves);
+
+/* Copies an explicit-node tree out, in its breadth-first numbering (host
+ * arrays of pg_tree_nodes' node count N; any may be NULL; synchronises):
+ *   split_host : [N] 32-bit cut values (int32 or float32 per dtype; 0 for leaves)
+ *   dim_host   : [N] cut dimension, -1 for leaves
+ *   child_host : [N] first child (the second is child + 1), -1 for leaves
+ *   lo_host, hi_host : [N] the node's leaf-order positions [lo, hi)
+ *   level_host : [N] depth (root 0)
+ *   perm_host  : [n] input rows in leaf order
+ * PG_ERR_UNSUPPORTED for trees from pg_kdtree_build (pg_tree_export). */
+pg_status pg_tree_export_nodes(const pg_tree* t, void* split_host, int32_t* dim_host,
+                               int64_t* child_host, int64_t* lo_host, int64_t* hi_host,
+                               int32_t* level_host, int32_t* perm_host, void* stream);
+
+/* Leaf offsets (host, [leaves + 1], leaves from pg_tree_nodes): leaf j holds
+ * leaf-order positions [loff[j], loff[j+1]) (the closed form
+ * floor(j n / 2^L) for trees from pg_kdtree_build).  Synchronises for
+ * spatial-median trees. */
 pg_status pg_tree_offsets(const pg_tree* t, int64_t* loff_host, void* stream);
 
 /* k-NN of m query points over the tree (Appendix C, "Data-Parallel k-NN":
@@ -149,11 +171,14 @@ pg_status pg_knn_all(const pg_tree* t, int32_t k, int32_t* out_idx, void* out_di
 pg_status pg_knn_graph(const pg_tree* t, int32_t k, int32_t* out_idx, void* out_dist,
                        void* stream);
 
-/* Tree facts (host outputs; any may be NULL). */
+/* Tree facts (host outputs; any may be NULL); levels: L for trees from
+ * pg_kdtree_build, the number of depths (deepest node's depth + 1) for
+ * explicit-node trees. */
 pg_status pg_tree_info(const pg_tree* t, int64_t* n, int32_t* d, int32_t* leaf,
                        int32_t* levels, int32_t* dtype);
 
-/* Copies the tree out for inspection (synchronises):
+/* Copies a tree from pg_kdtree_build out for inspection (synchronises;
+ * PG_ERR_UNSUPPORTED for explicit-node trees, see pg_tree_export_nodes):
  *   splits_host : (host) [2^L - 1] 32-bit split values of heap nodes 1..2^L-1
  *                 (node h has children 2h, 2h+1; node 2^l + j is node j of
  *                 level l), int32 or float32 per dtype
@@ -229,8 +254,9 @@ pg_status pg_range_search(const pg_tree* t, const void* boxes, int64_t m, int32_
 pg_status pg_bdl_create(int32_t d, int32_t dtype, int32_t leaf, int64_t buffer_X, pg_bdl** out);
 /* As pg_bdl_create, but every static tree and the buffer tree is built with
  * spatial-median splits (Section 6.3 runs each tree both ways; cells halved
- * as in pg_kdtree_build_spatial, split dimension l mod d).  Results are the
- * same (same definition on the same live set); only the cost differs. */
+ * as in pg_kdtree_build_spatial with dim_rule 0: split dimension depth mod
+ * d, down to at most `leaf` points per leaf).  Results are the same (same
+ * definition on the same live set); only the cost differs. */
 pg_status pg_bdl_create_spatial(int32_t d, int32_t dtype, int32_t leaf, int64_t buffer_X,
                                 pg_bdl** out);
 
@@ -280,7 +306,8 @@ typedef struct pg_b1 pg_b1;
 
 /* Creates an empty B1 tree (host only).  d 1..8, leaf 1..64. */
 pg_status pg_b1_create(int32_t d, int32_t dtype, int32_t leaf, pg_b1** out);
-/* As pg_b1_create, rebuilding with spatial-median splits (l mod d). */
+/* As pg_b1_create, rebuilding with spatial-median splits
+ * (pg_kdtree_build_spatial, dim_rule 0). */
 pg_status pg_b1_create_spatial(int32_t d, int32_t dtype, int32_t leaf, pg_b1** out);
 /* Inserts m device points and rebuilds.  first_id as in pg_bdl_insert.
  * Synchronises.  PG_ERR_UNSUPPORTED beyond 2^31 - 1 points. */
@@ -313,8 +340,10 @@ typedef struct pg_b2 pg_b2;
  * pg_kdtree_build.  Synchronises.  PG_ERR_RANGE on an out-of-range point. */
 pg_status pg_b2_create(const void* points, int64_t n, int32_t d, int32_t leaf, int32_t dtype,
                        void* stream, pg_b2** out);
-/* As pg_b2_create, with the fixed splits taken as spatial medians of the
- * initial points' cells (l mod d); inserts follow the same rule. */
+/* As pg_b2_create, with the fixed splits those of the spatial-median tree
+ * of the initial points (pg_kdtree_build_spatial, dim_rule 0); an inserted
+ * point descends by the same rule (coordinate < cut: first child), and may
+ * join an empty leaf. */
 pg_status pg_b2_create_spatial(const void* points, int64_t n, int32_t d, int32_t leaf,
                                int32_t dtype, void* stream, pg_b2** out);
 /* Inserts m device points in place (new arrays of the grown size; leaf and

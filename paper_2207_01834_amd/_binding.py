@@ -57,6 +57,8 @@ SIGNATURES = {
     "pg_knn_graph": (i32, [vp, i32, vp, vp, vp]),
     "pg_tree_info": (i32, [vp, P64, P32, P32, P32, P32]),
     "pg_tree_export": (i32, [vp, vp, vp, vp]),
+    "pg_tree_nodes": (i32, [vp, P64, P64]),
+    "pg_tree_export_nodes": (i32, [vp, vp, vp, vp, vp, vp, vp, vp, vp]),
     "pg_tree_free": (None, [vp]),
     "pg_range_count": (i32, [vp, vp, i64, vp, vp, P64, vp]),
     "pg_range_report": (i32, [vp, vp, i64, vp, vp, i64, vp]),
@@ -276,10 +278,33 @@ class KdTree:
             check(st)
         return off, out[:total.value]
 
-    def offsets(self):
-        """Leaf offsets (NumPy int64 [2^L + 1])."""
+    def counts(self):
+        """(nodes, leaves) of the tree."""
+        nodes, leaves = ctypes.c_int64(), ctypes.c_int64()
+        check(lib().pg_tree_nodes(self._h, ctypes.byref(nodes), ctypes.byref(leaves)))
+        return nodes.value, leaves.value
+
+    def nodes(self):
+        """An explicit-node tree (spatial-median splits) as NumPy arrays in
+        its breadth-first numbering: dict with split (coordinate dtype; 0 for
+        leaves), dim (int32, -1 for leaves), child (int64 first child, -1 for
+        leaves), lo / hi (int64 leaf-order range), level (int32) and perm
+        (int32 input rows in leaf order)."""
         import numpy as np
-        loff = np.empty((1 << self.levels) + 1, dtype=np.int64)
+        N, _ = self.counts()
+        out = dict(split=np.empty(N, dtype=np.int32 if self.dtype_code == PG_INT32 else np.float32),
+                   dim=np.empty(N, dtype=np.int32), child=np.empty(N, dtype=np.int64),
+                   lo=np.empty(N, dtype=np.int64), hi=np.empty(N, dtype=np.int64),
+                   level=np.empty(N, dtype=np.int32), perm=np.empty(self.n, dtype=np.int32))
+        check(lib().pg_tree_export_nodes(self._h, *[ctypes.c_void_p(out[k].ctypes.data) for k in
+                                                     ("split", "dim", "child", "lo", "hi", "level",
+                                                      "perm")], stream_ptr(self.device)))
+        return out
+
+    def offsets(self):
+        """Leaf offsets (NumPy int64 [leaves + 1])."""
+        import numpy as np
+        loff = np.empty(self.counts()[1] + 1, dtype=np.int64)
         check(lib().pg_tree_offsets(self._h, ctypes.c_void_p(loff.ctypes.data), stream_ptr(self.device)))
         return loff
 
@@ -306,10 +331,11 @@ class KdTree:
 def kdtree_build(points: torch.Tensor, leaf: int = 16, split: str = "object",
                  dim_rule: str = "cycle", space: str = "cell") -> KdTree:
     """Builds a kd-tree: ``split="object"`` (object median, every leaf at most
-    ``leaf`` points) or ``"spatial"`` (spaces cut at their midpoints, the same
-    depth, leaf sizes vary; ``dim_rule`` "cycle" = level mod d, "widest" = the
-    space's widest side; ``space`` "cell" = the node's cell, "points" = the
-    bounding box of the node's points)."""
+    ``leaf`` points) or ``"spatial"`` (spaces cut at their midpoints until a
+    node holds at most ``leaf`` points or only identical ones, any depth;
+    ``dim_rule`` "cycle" = depth mod d, "widest" = the space's widest side;
+    ``space`` "cell" = the node's cell, "points" = the bounding box of the
+    node's points)."""
     p = _points(points, "points")
     code = _dtype_code(p)
     h = ctypes.c_void_p()

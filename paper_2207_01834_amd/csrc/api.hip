@@ -2,6 +2,7 @@
 #include <atomic>
 #include <mutex>
 #include <new>
+#include <vector>
 #include <string>
 
 #include "build.hpp"
@@ -81,6 +82,9 @@ static void tree_release(pg_tree* t) {
     dfree(t->rec, t->stream);
     if (t->loff) dfree(t->loff, t->stream);
     if (t->sdim) dfree(t->sdim, t->stream);
+    if (t->xn) dfree(t->xn, t->stream);
+    if (t->xspan) dfree(t->xspan, t->stream);
+    if (t->lnode) dfree(t->lnode, t->stream);
     delete t;
 }
 
@@ -147,7 +151,7 @@ pg_status pg_kdtree_build_spatial(const void* points, int64_t n, int32_t d, int3
 pg_status pg_tree_offsets(const pg_tree* t, int64_t* loff_host, void* stream) {
     if (!t) return fail(PG_ERR_INVALID, "pg_tree_offsets: tree is NULL");
     if (!loff_host) return fail(PG_ERR_INVALID, "pg_tree_offsets: loff_host is NULL");
-    const int64_t leaves = (int64_t)1 << t->L;
+    const int64_t leaves = t->xn ? t->nleaves : (int64_t)1 << t->L;
     if (t->loff) {
         hipStream_t s = (hipStream_t)stream;
         PG_HIP(hipMemcpyAsync(loff_host, t->loff, sizeof(int64_t) * (leaves + 1),
@@ -162,6 +166,7 @@ pg_status pg_tree_offsets(const pg_tree* t, int64_t* loff_host, void* stream) {
 pg_status pg_tree_split_dims(const pg_tree* t, uint8_t* dims_host, void* stream) {
     if (!t) return fail(PG_ERR_INVALID, "pg_tree_split_dims: tree is NULL");
     if (!dims_host) return fail(PG_ERR_INVALID, "pg_tree_split_dims: dims_host is NULL");
+    if (t->xn) return fail(PG_ERR_UNSUPPORTED, "pg_tree_split_dims: explicit-node tree (use pg_tree_export_nodes)");
     const int64_t nodes = (int64_t)1 << t->L;
     if (t->sdim) {
         hipStream_t s = (hipStream_t)stream;
@@ -250,6 +255,7 @@ pg_status pg_tree_info(const pg_tree* t, int64_t* n, int32_t* d, int32_t* leaf, 
 
 pg_status pg_tree_export(const pg_tree* t, void* splits_host, int32_t* perm_host, void* stream) {
     if (!t) return fail(PG_ERR_INVALID, "pg_tree_export: tree is NULL");
+    if (t->xn) return fail(PG_ERR_UNSUPPORTED, "pg_tree_export: explicit-node tree (use pg_tree_export_nodes)");
     hipStream_t s = (hipStream_t)stream;
     const int64_t ni = ((int64_t)1 << t->L) - 1;
     if (splits_host && ni > 0)
@@ -258,6 +264,44 @@ pg_status pg_tree_export(const pg_tree* t, void* splits_host, int32_t* perm_host
     if (perm_host && t->n > 0)
         PG_HIP(hipMemcpyAsync(perm_host, t->pidx, sizeof(int32_t) * t->n, hipMemcpyDeviceToHost, s));
     PG_HIP(hipStreamSynchronize(s));
+    return PG_OK;
+}
+
+pg_status pg_tree_nodes(const pg_tree* t, int64_t* nodes, int64_t* leaves) {
+    if (!t) return fail(PG_ERR_INVALID, "pg_tree_nodes: tree is NULL");
+    const int64_t heap_leaves = (int64_t)1 << t->L;
+    if (nodes) *nodes = t->xn ? t->nnodes : 2 * heap_leaves - 1;
+    if (leaves) *leaves = t->xn ? t->nleaves : heap_leaves;
+    return PG_OK;
+}
+
+pg_status pg_tree_export_nodes(const pg_tree* t, void* split_host, int32_t* dim_host,
+                               int64_t* child_host, int64_t* lo_host, int64_t* hi_host,
+                               int32_t* level_host, int32_t* perm_host, void* stream) {
+    if (!t) return fail(PG_ERR_INVALID, "pg_tree_export_nodes: tree is NULL");
+    if (!t->xn) return fail(PG_ERR_UNSUPPORTED, "pg_tree_export_nodes: not an explicit-node tree (use pg_tree_export)");
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t N = t->nnodes, NL = t->nleaves;
+    std::vector<uint4> xn((size_t)N);
+    std::vector<uint2> sp((size_t)N);
+    std::vector<int64_t> loff((size_t)NL + 1);
+    PG_HIP(hipMemcpyAsync(xn.data(), t->xn, sizeof(uint4) * N, hipMemcpyDeviceToHost, s));
+    PG_HIP(hipMemcpyAsync(sp.data(), t->xspan, sizeof(uint2) * N, hipMemcpyDeviceToHost, s));
+    PG_HIP(hipMemcpyAsync(loff.data(), t->loff, sizeof(int64_t) * (NL + 1), hipMemcpyDeviceToHost, s));
+    if (perm_host && t->n > 0)
+        PG_HIP(hipMemcpyAsync(perm_host, t->pidx, sizeof(int32_t) * t->n, hipMemcpyDeviceToHost, s));
+    PG_HIP(hipStreamSynchronize(s));
+    for (int64_t u = 0; u < N; u++) {
+        const bool leaf = (xn[u].w & kXLeaf) != 0;
+        if (split_host) ((uint32_t*)split_host)[u] = leaf ? 0u : xn[u].x;
+        if (dim_host) dim_host[u] = leaf ? -1 : (int32_t)(xn[u].w & 15u);
+        if (child_host) child_host[u] = leaf ? -1 : (int64_t)xn[u].y;
+        if (lo_host) lo_host[u] = loff[sp[u].x];
+        if (hi_host) hi_host[u] = loff[sp[u].y];
+    }
+    if (level_host)
+        for (size_t l = 0; l + 1 < t->lvl.size(); l++)
+            for (int64_t u = t->lvl[l]; u < t->lvl[l + 1]; u++) level_host[u] = (int32_t)l;
     return PG_OK;
 }
 

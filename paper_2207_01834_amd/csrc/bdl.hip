@@ -25,7 +25,7 @@
 #include "build.hpp"
 #include "knn.hpp"
 #include "scan.hpp"
-#include "search.hpp"
+#include "xsearch.hpp"
 #include "wave.hpp"
 
 namespace pg {
@@ -99,8 +99,10 @@ __global__ void leaf_ids_kernel(const int32_t* __restrict__ pidx, const int64_t*
 
 // Erase: lane = erase point, blockIdx.y = tree slot.  Walks every node whose
 // cell can hold the exact coordinates (both children where the coordinate
-// equals the split) and clears live points with equal coordinates.
-template <typename T, int MD, bool LOFF>
+// equals the split) and clears live points with equal coordinates.  In an
+// explicit-node tree (spatial-median splits: coordinate < split left, the
+// rest right) that is the one path the point's descent takes.
+template <typename T, int MD, int TK>
 __global__ void __launch_bounds__(kNT)
 erase_kernel(Forest f, const uint32_t* __restrict__ pts, const int32_t* __restrict__ order,
              int64_t m, int d, unsigned long long* __restrict__ erased) {
@@ -117,57 +119,70 @@ erase_kernel(Forest f, const uint32_t* __restrict__ pts, const int32_t* __restri
     T q[MD];
 #pragma unroll
     for (int c = 0; c < MD; c++) q[c] = M::load(c < d ? pts[qi * d + c] : 0u);
-    const uint32_t first_leaf = 1u << tv.L;
-    uint32_t cur = 1, prev = 0;
-    int dim = 0;
     uint32_t hits = 0;
-    while (cur != 0) {
-        while (cur != 0 && cur < first_leaf) {
-            const T s = M::load(tv.split[cur]);
-            const T qd = pick<MD>(q, dim);
-            const uint32_t nearc = 2u * cur + (qd >= s ? 1u : 0u);
-            uint32_t next;
-            if (prev == (cur >> 1)) next = nearc;
-            else if (prev == nearc && qd == s) next = nearc ^ 1u;
-            else next = cur >> 1;
-            if (next > cur) dim = (dim + 1 == d) ? 0 : dim + 1;
-            else dim = (dim == 0) ? d - 1 : dim - 1;
-            prev = cur;
-            cur = next;
-        }
-        if (cur == 0) break;
-        const uint32_t leaf = cur - first_leaf;
-        const uint32_t* bb = tv.bbox + (size_t)leaf * 2 * d;
+    // clears the live points of leaf-order range [lo, hi) equal to q when
+    // the box bb holds q
+    auto scan = [&](const uint32_t* bb, int64_t lo, int64_t hi) {
         bool inside = true;
 #pragma unroll
         for (int c = 0; c < MD; c++)
             if (c < d) inside = inside && !(q[c] < M::load(bb[c])) && !(q[c] > M::load(bb[d + c]));
-        if (inside) {
-            const int64_t lo = LOFF ? tv.loff[leaf] : node_start(tv.n, tv.L, leaf);
-            const int64_t hi = LOFF ? tv.loff[leaf + 1] : node_start(tv.n, tv.L, leaf + 1);
-            for (int64_t i = lo; i < hi; i++) {
-                T p[MD];
-                uint32_t idw;
-                load_point<T, MD>(tv, i, d, p, idw);
-                bool eq = true;
+        if (!inside) return;
+        for (int64_t i = lo; i < hi; i++) {
+            T p[MD];
+            uint32_t idw;
+            load_point<T, MD>(tv, i, d, p, idw);
+            bool eq = true;
 #pragma unroll
-                for (int c = 0; c < MD; c++)
-                    if (c < d) eq = eq && (p[c] == q[c]);
-                if (eq) {
-                    const uint32_t bit = 1u << (i & 31);
-                    const uint32_t old = atomicAnd(&S.alive[i >> 5], ~bit);
-                    if (old & bit) hits++;
-                }
+            for (int c = 0; c < MD; c++)
+                if (c < d) eq = eq && (p[c] == q[c]);
+            if (eq) {
+                const uint32_t bit = 1u << (i & 31);
+                const uint32_t old = atomicAnd(&S.alive[i >> 5], ~bit);
+                if (old & bit) hits++;
             }
         }
-        prev = cur;
-        cur >>= 1;
-        dim = (dim == 0) ? d - 1 : dim - 1;
+    };
+    if constexpr (TK == kTreeX) {
+        uint32_t cur = 0;
+        uint4 r = tv.xn[0];
+        while (!(r.w & kXLeaf)) {
+            cur = r.y + (pick<MD>(q, (int)(r.w & 15u)) >= M::load(r.x) ? 1u : 0u);
+            r = tv.xn[cur];
+        }
+        if (!(r.w & kXEmpty)) scan(tv.nbox + (size_t)cur * 2 * d, tv.loff[r.x], tv.loff[r.x + 1]);
+    } else {
+        const uint32_t first_leaf = 1u << tv.L;
+        uint32_t cur = 1, prev = 0;
+        int dim = 0;
+        while (cur != 0) {
+            while (cur != 0 && cur < first_leaf) {
+                const T s = M::load(tv.split[cur]);
+                const T qd = pick<MD>(q, dim);
+                const uint32_t nearc = 2u * cur + (qd >= s ? 1u : 0u);
+                uint32_t next;
+                if (prev == (cur >> 1)) next = nearc;
+                else if (prev == nearc && qd == s) next = nearc ^ 1u;
+                else next = cur >> 1;
+                if (next > cur) dim = (dim + 1 == d) ? 0 : dim + 1;
+                else dim = (dim == 0) ? d - 1 : dim - 1;
+                prev = cur;
+                cur = next;
+            }
+            if (cur == 0) break;
+            const uint32_t leaf = cur - first_leaf;
+            scan(tv.bbox + (size_t)leaf * 2 * d,
+                 TK == kTreeLoff ? tv.loff[leaf] : node_start(tv.n, tv.L, leaf),
+                 TK == kTreeLoff ? tv.loff[leaf + 1] : node_start(tv.n, tv.L, leaf + 1));
+            prev = cur;
+            cur >>= 1;
+            dim = (dim == 0) ? d - 1 : dim - 1;
+        }
     }
     if (hits) atomicAdd(&erased[slot], (unsigned long long)hits);
 }
 
-template <typename T, int MD, int KT, bool EX, bool LOFF>
+template <typename T, int MD, int KT, bool EX, int TK>
 __global__ void __launch_bounds__(kNT)
 bdl_knn_kernel(Forest f, const uint32_t* __restrict__ queries, const int32_t* __restrict__ order,
                int64_t m, int d, int k, int64_t* __restrict__ out_id,
@@ -182,8 +197,8 @@ bdl_knn_kernel(Forest f, const uint32_t* __restrict__ queries, const int32_t* __
     KList<typename M::D, int64_t, KT, EX> kl;
     kl.init(M::inf(), INT64_MAX);
     for (int t = 0; t < f.count; t++)
-        kd_search<T, MD, decltype(kl), BdlIds, LOFF>(f.s[t].tv, BdlIds{f.s[t].ids, f.s[t].alive}, q,
-                                                     d, kl, k);
+        tree_search<T, MD, decltype(kl), BdlIds, TK>(f.s[t].tv, BdlIds{f.s[t].ids, f.s[t].alive}, q,
+                                                     d, kl, k, search_start<TK>(f.s[t].tv, false, 0));
 #pragma unroll
     for (int s = 0; s < KT; s++) {
         if (EX || s < k) {
@@ -193,74 +208,78 @@ bdl_knn_kernel(Forest f, const uint32_t* __restrict__ queries, const int32_t* __
     }
 }
 
-template <typename T, int MD, bool LOFF>
+template <typename T, int MD, int TK>
 pg_status launch_erase(const Forest& f, const void* pts, const int32_t* order, int64_t m, int d,
                        unsigned long long* erased, hipStream_t s) {
-    hipLaunchKernelGGL((erase_kernel<T, MD, LOFF>), dim3(cdiv(m, kNT), f.count), dim3(kNT), 0, s, f,
+    hipLaunchKernelGGL((erase_kernel<T, MD, TK>), dim3(cdiv(m, kNT), f.count), dim3(kNT), 0, s, f,
                        (const uint32_t*)pts, order, m, d, erased);
     PG_LAUNCH_CHECK();
     return PG_OK;
 }
 
-template <typename T, bool LOFF = false>
+template <typename T, int TK>
 pg_status erase_d(const Forest& f, const void* pts, const int32_t* o, int64_t m, int d,
                   unsigned long long* e, hipStream_t s) {
     switch (d) {
-        case 2: return launch_erase<T, 2, LOFF>(f, pts, o, m, d, e, s);
-        case 3: return launch_erase<T, 3, LOFF>(f, pts, o, m, d, e, s);
-        case 5: return launch_erase<T, 5, LOFF>(f, pts, o, m, d, e, s);
-        default: return launch_erase<T, 8, LOFF>(f, pts, o, m, d, e, s);
+        case 2: return launch_erase<T, 2, TK>(f, pts, o, m, d, e, s);
+        case 3: return launch_erase<T, 3, TK>(f, pts, o, m, d, e, s);
+        case 5: return launch_erase<T, 5, TK>(f, pts, o, m, d, e, s);
+        default: return launch_erase<T, 8, TK>(f, pts, o, m, d, e, s);
     }
 }
 
-// Trees with explicit leaf offsets (spatial-median splits, B2) take the
-// offset-reading form of the walk; closed-form object-median trees the other.
+// The walk for the forest's tree kind (every tree of a forest is of one
+// kind: explicit-node for spatial-median splits, heaps with leaf offsets for
+// grown B2 trees, closed-form heaps otherwise).
 template <typename T>
-pg_status erase_any(bool loff, const Forest& f, const void* pts, const int32_t* o, int64_t m, int d,
+pg_status erase_any(int tk, const Forest& f, const void* pts, const int32_t* o, int64_t m, int d,
                     unsigned long long* e, hipStream_t s) {
-    return loff ? erase_d<T, true>(f, pts, o, m, d, e, s) : erase_d<T, false>(f, pts, o, m, d, e, s);
+    if (tk == kTreeX) return erase_d<T, kTreeX>(f, pts, o, m, d, e, s);
+    if (tk == kTreeLoff) return erase_d<T, kTreeLoff>(f, pts, o, m, d, e, s);
+    return erase_d<T, kTreeHeap>(f, pts, o, m, d, e, s);
 }
 
-template <typename T, int MD, int KT, bool EX, bool LOFF>
+template <typename T, int MD, int KT, bool EX, int TK>
 pg_status launch_bdl_knn(const Forest& f, const void* q, const int32_t* o, int64_t m, int d, int k,
                          int64_t* oi, void* od, hipStream_t s) {
     using DT = typename Metric<T>::D;
-    hipLaunchKernelGGL((bdl_knn_kernel<T, MD, KT, EX, LOFF>), dim3(grid_for_xcd(cdiv(m, kNT))),
+    hipLaunchKernelGGL((bdl_knn_kernel<T, MD, KT, EX, TK>), dim3(grid_for_xcd(cdiv(m, kNT))),
                        dim3(kNT), 0, s, f, (const uint32_t*)q, o, m, d, k, oi, (DT*)od);
     PG_LAUNCH_CHECK();
     return PG_OK;
 }
 
-template <typename T, int MD, bool LOFF>
+template <typename T, int MD, int TK>
 pg_status bdl_knn_k(const Forest& f, const void* q, const int32_t* o, int64_t m, int d, int k,
                     int64_t* oi, void* od, hipStream_t s) {
-    if (k == 5) return launch_bdl_knn<T, MD, 5, true, LOFF>(f, q, o, m, d, k, oi, od, s);
-    if (k == 10) return launch_bdl_knn<T, MD, 10, true, LOFF>(f, q, o, m, d, k, oi, od, s);
-    if (k == 16) return launch_bdl_knn<T, MD, 16, true, LOFF>(f, q, o, m, d, k, oi, od, s);
-    if (k <= 2) return launch_bdl_knn<T, MD, 2, false, LOFF>(f, q, o, m, d, k, oi, od, s);
-    if (k <= 4) return launch_bdl_knn<T, MD, 4, false, LOFF>(f, q, o, m, d, k, oi, od, s);
-    if (k <= 8) return launch_bdl_knn<T, MD, 8, false, LOFF>(f, q, o, m, d, k, oi, od, s);
-    if (k <= 16) return launch_bdl_knn<T, MD, 16, false, LOFF>(f, q, o, m, d, k, oi, od, s);
-    if (k <= 32) return launch_bdl_knn<T, MD, 32, false, LOFF>(f, q, o, m, d, k, oi, od, s);
-    return launch_bdl_knn<T, MD, 64, false, LOFF>(f, q, o, m, d, k, oi, od, s);
+    if (k == 5) return launch_bdl_knn<T, MD, 5, true, TK>(f, q, o, m, d, k, oi, od, s);
+    if (k == 10) return launch_bdl_knn<T, MD, 10, true, TK>(f, q, o, m, d, k, oi, od, s);
+    if (k == 16) return launch_bdl_knn<T, MD, 16, true, TK>(f, q, o, m, d, k, oi, od, s);
+    if (k <= 2) return launch_bdl_knn<T, MD, 2, false, TK>(f, q, o, m, d, k, oi, od, s);
+    if (k <= 4) return launch_bdl_knn<T, MD, 4, false, TK>(f, q, o, m, d, k, oi, od, s);
+    if (k <= 8) return launch_bdl_knn<T, MD, 8, false, TK>(f, q, o, m, d, k, oi, od, s);
+    if (k <= 16) return launch_bdl_knn<T, MD, 16, false, TK>(f, q, o, m, d, k, oi, od, s);
+    if (k <= 32) return launch_bdl_knn<T, MD, 32, false, TK>(f, q, o, m, d, k, oi, od, s);
+    return launch_bdl_knn<T, MD, 64, false, TK>(f, q, o, m, d, k, oi, od, s);
 }
 
-template <typename T, bool LOFF = false>
+template <typename T, int TK>
 pg_status bdl_knn_d(const Forest& f, const void* q, const int32_t* o, int64_t m, int d, int k,
                     int64_t* oi, void* od, hipStream_t s) {
     switch (d) {
-        case 2: return bdl_knn_k<T, 2, LOFF>(f, q, o, m, d, k, oi, od, s);
-        case 3: return bdl_knn_k<T, 3, LOFF>(f, q, o, m, d, k, oi, od, s);
-        case 5: return bdl_knn_k<T, 5, LOFF>(f, q, o, m, d, k, oi, od, s);
-        default: return bdl_knn_k<T, 8, LOFF>(f, q, o, m, d, k, oi, od, s);
+        case 2: return bdl_knn_k<T, 2, TK>(f, q, o, m, d, k, oi, od, s);
+        case 3: return bdl_knn_k<T, 3, TK>(f, q, o, m, d, k, oi, od, s);
+        case 5: return bdl_knn_k<T, 5, TK>(f, q, o, m, d, k, oi, od, s);
+        default: return bdl_knn_k<T, 8, TK>(f, q, o, m, d, k, oi, od, s);
     }
 }
 
 template <typename T>
-pg_status bdl_knn_any(bool loff, const Forest& f, const void* q, const int32_t* o, int64_t m, int d,
+pg_status bdl_knn_any(int tk, const Forest& f, const void* q, const int32_t* o, int64_t m, int d,
                       int k, int64_t* oi, void* od, hipStream_t s) {
-    return loff ? bdl_knn_d<T, true>(f, q, o, m, d, k, oi, od, s)
-                : bdl_knn_d<T, false>(f, q, o, m, d, k, oi, od, s);
+    if (tk == kTreeX) return bdl_knn_d<T, kTreeX>(f, q, o, m, d, k, oi, od, s);
+    if (tk == kTreeLoff) return bdl_knn_d<T, kTreeLoff>(f, q, o, m, d, k, oi, od, s);
+    return bdl_knn_d<T, kTreeHeap>(f, q, o, m, d, k, oi, od, s);
 }
 
 // ---- B2 (Section 6.3's second baseline): one static tree whose splits stay
@@ -275,16 +294,21 @@ __global__ void b2_leaf_kernel(TreeView tv, int fl, const uint32_t* __restrict__
     const int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x;
     if (i >= m) return;
     const int d = tv.d;
-    const uint32_t first_leaf = 1u << tv.L;
-    uint32_t cur = 1;
-    int dim = 0;
-    while (cur < first_leaf) {
-        const uint32_t qb = pts[i * d + dim], sb = tv.split[cur];
-        const bool right = fl ? __uint_as_float(qb) >= __uint_as_float(sb) : (int32_t)qb >= (int32_t)sb;
-        cur = 2u * cur + (right ? 1u : 0u);
-        dim = dim + 1 == d ? 0 : dim + 1;
+    uint32_t j;
+    if (tv.xn) {
+        j = tv.xn[fl ? xdescend<float>(tv, pts + i * d) : xdescend<int32_t>(tv, pts + i * d)].x;
+    } else {
+        const uint32_t first_leaf = 1u << tv.L;
+        uint32_t cur = 1;
+        int dim = 0;
+        while (cur < first_leaf) {
+            const uint32_t qb = pts[i * d + dim], sb = tv.split[cur];
+            const bool right = fl ? __uint_as_float(qb) >= __uint_as_float(sb) : (int32_t)qb >= (int32_t)sb;
+            cur = 2u * cur + (right ? 1u : 0u);
+            dim = dim + 1 == d ? 0 : dim + 1;
+        }
+        j = cur - first_leaf;
     }
-    const uint32_t j = cur - first_leaf;
     leaf[i] = j;
     rank[i] = atomicAdd(&cnt[j], 1u);
 }
@@ -305,14 +329,8 @@ __global__ void b2_move_kernel(TreeView tv, const int64_t* __restrict__ ids,
                                uint32_t* __restrict__ alive2) {
     const int64_t p = (int64_t)blockIdx.x * kNT + threadIdx.x;
     if (p >= tv.n) return;
-    // leaf of p: the last j with loff[j] <= p (upper bound over 2^L + 1 offsets)
-    int64_t lo = 0, hi = ((int64_t)1 << tv.L);
-    while (hi - lo > 1) {
-        const int64_t mid = (lo + hi) >> 1;
-        if (tv.loff[mid] <= p) lo = mid;
-        else hi = mid;
-    }
-    const int64_t p2 = p + nstart[lo];
+    // leaf of p: the last j with loff[j] <= p
+    const int64_t p2 = p + nstart[leaf_at_n(tv.loff, tv.nleaves, p)];
     for (int c = 0; c < tv.d; c++) pts2[(int64_t)c * n2 + p2] = tv.pts[(int64_t)c * tv.n + p];
     for (int w = 0; w < tv.rw; w++) rec2[p2 * tv.rw + w] = tv.rec[p * tv.rw + w];
     pidx2[p2] = tv.pidx[p];
@@ -577,7 +595,7 @@ static pg_status b2_insert(B2& B, const void* points, int64_t m, hipStream_t s) 
     const int fl = B.dtype == PG_FLOAT32 ? 1 : 0;
     const int64_t n = t->n, n2 = n + m;
     if (n2 >= ((int64_t)1 << 31)) return fail(PG_ERR_UNSUPPORTED, "B2: more than 2^31 - 1 points");
-    const int64_t leaves = (int64_t)1 << t->L;
+    const int64_t leaves = t->view().nleaves;
     const int rw = record_words(d);
     const TreeView tv = t->view();
     DevBuf leaf(s), rank(s), cnt(s), nstart(s);
@@ -629,7 +647,7 @@ static pg_status b2_insert(B2& B, const void* points, int64_t m, hipStream_t s) 
     B.T.alive = alive2;
     B.T.live += m;
     t->loff = loff2;
-    return offset_boxes(t, s);
+    return t->xn ? xtree_boxes(t, s) : offset_boxes(t, s);
 }
 
 // B1 baseline handle: one static tree over the live points, rebuilt whole
@@ -757,8 +775,9 @@ pg_status pg_bdl_erase(pg_bdl* h, const void* points, int64_t m, void* stream, i
         PG_TRY(order_queries(f.s[0].tv, B.dtype == PG_FLOAT32, points, m, s, order));
         o = order.as<int32_t>();
     }
-    if (B.dtype == PG_FLOAT32) PG_TRY(erase_any<float>(B.split, f, points, o, m, B.d, e, s));
-    else PG_TRY(erase_any<int32_t>(B.split, f, points, o, m, B.d, e, s));
+    const int tk = B.split ? kTreeX : kTreeHeap;
+    if (B.dtype == PG_FLOAT32) PG_TRY(erase_any<float>(tk, f, points, o, m, B.d, e, s));
+    else PG_TRY(erase_any<int32_t>(tk, f, points, o, m, B.d, e, s));
     unsigned long long host[kSlots];
     PG_HIP(hipMemcpyAsync(host, e, sizeof(host), hipMemcpyDeviceToHost, s));
     PG_HIP(hipStreamSynchronize(s));
@@ -814,9 +833,10 @@ pg_status pg_bdl_knn(const pg_bdl* h, const void* queries, int64_t m, int32_t k,
         PG_TRY(order_queries(f.s[0].tv, B.dtype == PG_FLOAT32, queries, m, s, order));
         o = order.as<int32_t>();
     }
+    const int tk = B.split ? kTreeX : kTreeHeap;
     if (B.dtype == PG_FLOAT32)
-        return bdl_knn_any<float>(B.split, f, queries, o, m, B.d, k, out_id, out_dist, s);
-    return bdl_knn_any<int32_t>(B.split, f, queries, o, m, B.d, k, out_id, out_dist, s);
+        return bdl_knn_any<float>(tk, f, queries, o, m, B.d, k, out_id, out_dist, s);
+    return bdl_knn_any<int32_t>(tk, f, queries, o, m, B.d, k, out_id, out_dist, s);
 }
 
 int64_t pg_bdl_size(const pg_bdl* h) {
@@ -913,9 +933,9 @@ pg_status pg_b1_erase(pg_b1* h, const void* points, int64_t m, void* stream, int
         o = order.as<int32_t>();
     }
     unsigned long long* e = cnt.as<unsigned long long>();
-    const bool lo = B.shape.split != 0;
-    if (B.shape.dtype == PG_FLOAT32) PG_TRY(erase_any<float>(lo, f, points, o, m, B.shape.d, e, s));
-    else PG_TRY(erase_any<int32_t>(lo, f, points, o, m, B.shape.d, e, s));
+    const int tk = B.shape.split ? kTreeX : kTreeHeap;
+    if (B.shape.dtype == PG_FLOAT32) PG_TRY(erase_any<float>(tk, f, points, o, m, B.shape.d, e, s));
+    else PG_TRY(erase_any<int32_t>(tk, f, points, o, m, B.shape.d, e, s));
     unsigned long long host = 0;
     PG_HIP(hipMemcpyAsync(&host, e, sizeof(host), hipMemcpyDeviceToHost, s));
     PG_HIP(hipStreamSynchronize(s));
@@ -945,10 +965,10 @@ pg_status pg_b1_knn(const pg_b1* h, const void* queries, int64_t m, int32_t k, i
         PG_TRY(order_queries(f.s[0].tv, B.shape.dtype == PG_FLOAT32, queries, m, s, order));
         o = order.as<int32_t>();
     }
-    const bool lo = B.shape.split != 0;
+    const int tk = B.shape.split ? kTreeX : kTreeHeap;
     if (B.shape.dtype == PG_FLOAT32)
-        return bdl_knn_any<float>(lo, f, queries, o, m, B.shape.d, k, out_id, out_dist, s);
-    return bdl_knn_any<int32_t>(lo, f, queries, o, m, B.shape.d, k, out_id, out_dist, s);
+        return bdl_knn_any<float>(tk, f, queries, o, m, B.shape.d, k, out_id, out_dist, s);
+    return bdl_knn_any<int32_t>(tk, f, queries, o, m, B.shape.d, k, out_id, out_dist, s);
 }
 
 int64_t pg_b1_size(const pg_b1* h) { return h ? (h->b.T.t ? h->b.T.live : 0) : -1; }
@@ -993,7 +1013,7 @@ static pg_status b2_create(const void* points, int64_t n, int32_t d, int32_t lea
     if (st == PG_OK) st = build_bdl_tree(shape, S, s, B.T);
     const int64_t leaves = B.T.t ? ((int64_t)1 << B.T.t->L) : 0;
     // a spatial-median tree comes with its leaf offsets
-    const bool closed = st == PG_OK && B.T.t->loff == nullptr;
+    const bool closed = st == PG_OK && B.T.t->xn == nullptr && B.T.t->loff == nullptr;
     if (closed) st = dalloc(&B.T.t->loff, (size_t)leaves + 1, s);
     if (closed && st == PG_OK) {
         hipLaunchKernelGGL(closed_offsets_kernel, dim3(cdiv(leaves + 1, kNT)), dim3(kNT), 0, s, n,
@@ -1053,8 +1073,9 @@ pg_status pg_b2_erase(pg_b2* h, const void* points, int64_t m, void* stream, int
         o = order.as<int32_t>();
     }
     unsigned long long* e = cnt.as<unsigned long long>();
-    if (B.dtype == PG_FLOAT32) PG_TRY((erase_d<float, true>(f, points, o, m, B.d, e, s)));
-    else PG_TRY((erase_d<int32_t, true>(f, points, o, m, B.d, e, s)));
+    const int tk = B.T.t->xn ? kTreeX : kTreeLoff;
+    if (B.dtype == PG_FLOAT32) PG_TRY(erase_any<float>(tk, f, points, o, m, B.d, e, s));
+    else PG_TRY(erase_any<int32_t>(tk, f, points, o, m, B.d, e, s));
     unsigned long long host = 0;
     PG_HIP(hipMemcpyAsync(&host, e, sizeof(host), hipMemcpyDeviceToHost, s));
     PG_HIP(hipStreamSynchronize(s));
@@ -1080,8 +1101,9 @@ pg_status pg_b2_knn(const pg_b2* h, const void* queries, int64_t m, int32_t k, i
         PG_TRY(order_queries(f.s[0].tv, B.dtype == PG_FLOAT32, queries, m, s, order));
         o = order.as<int32_t>();
     }
-    if (B.dtype == PG_FLOAT32) return bdl_knn_d<float, true>(f, queries, o, m, B.d, k, out_id, out_dist, s);
-    return bdl_knn_d<int32_t, true>(f, queries, o, m, B.d, k, out_id, out_dist, s);
+    const int tk = B.T.t && B.T.t->xn ? kTreeX : kTreeLoff;
+    if (B.dtype == PG_FLOAT32) return bdl_knn_any<float>(tk, f, queries, o, m, B.d, k, out_id, out_dist, s);
+    return bdl_knn_any<int32_t>(tk, f, queries, o, m, B.d, k, out_id, out_dist, s);
 }
 
 int64_t pg_b2_size(const pg_b2* h) { return h ? h->b.T.live : -1; }

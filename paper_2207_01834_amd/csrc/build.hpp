@@ -30,10 +30,15 @@ pg_status offset_boxes(pg_tree* T, hipStream_t s);
 pg_status build_tree(const void* points, int64_t n, int d, int leaf, int dtype, hipStream_t s,
                      pg_tree* T);
 
-// Allocates T's arrays and builds the spatial-median tree (explicit leaf
-// offsets in T->loff; rule 0: split dimension l mod d, rule 1: the cell's
-// widest side, stored per node in T->sdim) from device rows [n][d].
+// Allocates T's arrays and builds the spatial-median tree as an
+// explicit-node tree (T->xn and friends) from device rows [n][d]; rule bit 0:
+// split dimension = the space's widest side instead of depth mod d; bit 1:
+// nodes cut the bounding box of their points instead of their cell.
 pg_status build_tree_spatial(const void* points, int64_t n, int d, int leaf, int dtype, int rule,
                              hipStream_t s, pg_tree* T);
+
+// Node boxes and empty flags of an explicit-node tree from its points and
+// leaf offsets (after points were added in place).
+pg_status xtree_boxes(pg_tree* T, hipStream_t s);
 
 }  // namespace pg

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <string>
+#include <vector>
 
 #include "pargeo_hip.h"
 
@@ -116,7 +117,23 @@ struct TreeView {
                             // null: the closed form floor(j n / 2^L) (trees grown
                             // in place keep their splits but not that form)
     const uint8_t* sdim;    // [2^L] split dimension of internal node h; null: level mod d
+    // Explicit-node trees (xn != null: spatial-median splits down to at most
+    // `leaf` points per node, any depth): nodes numbered breadth-first, root 0,
+    // the two children of a node consecutive.  split, bbox and sdim are then
+    // unused, nbox is [N][2d] by node, loff is [nleaves + 1] in leaf order.
+    const uint4* xn;        // [N] internal {split, first child, parent, meta};
+                            //     leaf {leaf index j, 0, parent, meta}
+    const uint2* xspan;     // [N] leaf-index span [jlo, jhi) of the node's subtree
+    const uint32_t* lnode;  // [nleaves] node of leaf j
+    int64_t nleaves;        // leaves (2^L for heap trees)
 };
+
+// Meta word of an explicit node: split dimension in bits 0..3, and flags.
+constexpr uint32_t kXLeaf = 1u << 8;      // the node is a leaf
+constexpr uint32_t kXEmpty = 1u << 9;     // a leaf without points
+constexpr uint32_t kXChildLeaf = 1u << 10;   // child s is a leaf: bit 10 + s
+constexpr uint32_t kXChildEmpty = 1u << 12;  // child s is an empty leaf: bit 12 + s
+constexpr uint32_t kXNone = 0xffffffffu;     // no node (the root's parent)
 
 inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
 
@@ -135,7 +152,15 @@ struct pg_tree {
     uint32_t* rec = nullptr;
     int64_t* loff = nullptr;   // explicit leaf offsets [2^L + 1]; null: closed form
     uint8_t* sdim = nullptr;   // split dimension per internal node; null: level mod d
+    // explicit-node trees (see TreeView): L is the number of levels
+    uint4* xn = nullptr;
+    uint2* xspan = nullptr;
+    uint32_t* lnode = nullptr;
+    int64_t nnodes = 0, nleaves = 0;
+    std::vector<int64_t> lvl;  // host: level l holds nodes [lvl[l], lvl[l+1])
+    int rule = 0;              // spatial rule bits the tree was built with
     pg::TreeView view() const {
-        return pg::TreeView{n, d, L, pg::record_words(d), pts, pidx, split, bbox, rec, nbox, loff, sdim};
+        return pg::TreeView{n, d, L, pg::record_words(d), pts, pidx, split, bbox, rec, nbox, loff, sdim,
+                            xn, xspan, lnode, xn ? nleaves : ((int64_t)1 << L)};
     }
 };

@@ -2,7 +2,7 @@
 // query checks, query ordering by leaf, and the dispatch to the per-type
 // kernels (knn_static.hpp, instantiated in knn_int.hip / knn_float.hip).
 #include "scan.hpp"
-#include "search.hpp"
+#include "xsearch.hpp"
 #include "wave.hpp"
 
 namespace pg {
@@ -50,6 +50,34 @@ query_leaf_kernel(TreeView tv, int fl, const uint32_t* __restrict__ queries, int
         }
         key[i] = cur - (1u << levels);
     }
+}
+
+// The same for explicit-node trees: the leaf index the descent reaches,
+// shifted right by `shift`.
+__global__ void __launch_bounds__(kNT)
+query_xleaf_kernel(TreeView tv, int fl, const uint32_t* __restrict__ queries, int64_t m, int shift,
+                   int box, uint32_t* __restrict__ key) {
+    const int d = tv.d;
+    const int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x;
+    if (i >= m) return;
+    const int64_t row = box ? i * 2 * d : i * d;
+    uint32_t cur = 0;
+    uint4 r = tv.xn[0];
+    while (!(r.w & kXLeaf)) {
+        const int dim = r.w & 15u;
+        const uint32_t qb = queries[row + dim], sb = r.x;
+        bool right;
+        if (box) {
+            const uint32_t hb = queries[row + d + dim];
+            right = fl ? 0.5f * __uint_as_float(qb) + 0.5f * __uint_as_float(hb) >= __uint_as_float(sb)
+                       : (int64_t)(int32_t)qb + (int32_t)hb >= 2 * (int64_t)(int32_t)sb;
+        } else {
+            right = fl ? __uint_as_float(qb) >= __uint_as_float(sb) : (int32_t)qb >= (int32_t)sb;
+        }
+        cur = r.y + (right ? 1u : 0u);
+        r = tv.xn[cur];
+    }
+    key[i] = r.x >> shift;
 }
 
 __global__ void bucket_count_kernel(const uint32_t* __restrict__ key, int64_t m,
@@ -101,8 +129,14 @@ pg_status order_queries(const TreeView& tv, bool fl, const void* queries, int64_
     // buckets: the leaves, coarsened to about one bucket per 4 queries
     int bits = 0;
     while (bits < 24 && ((int64_t)1 << (bits + 1)) * 4 <= m) bits++;
-    const int shift = tv.L > bits ? tv.L - bits : 0;
-    const int64_t nb = ((int64_t)1 << tv.L) >> shift;
+    int lbits = tv.L;  // leaves < 2^lbits
+    if (tv.xn) {
+        lbits = 0;
+        while (((int64_t)1 << lbits) < tv.nleaves) lbits++;
+    }
+    const int shift = lbits > bits ? lbits - bits : 0;
+    const int64_t nb = tv.xn ? ((tv.nleaves + ((int64_t)1 << shift) - 1) >> shift)
+                             : (((int64_t)1 << tv.L) >> shift);
     // one temporary: the queries' bucket keys, then the bucket counts (which
     // the scan turns, in place, into each bucket's next free slot)
     DevBuf work(s);
@@ -111,8 +145,12 @@ pg_status order_queries(const TreeView& tv, bool fl, const void* queries, int64_
     uint32_t* cnt = key + m;
     PG_TRY(order.alloc(sizeof(int32_t) * m));
     PG_HIP(hipMemsetAsync(cnt, 0, sizeof(uint32_t) * nb, s));
-    hipLaunchKernelGGL(query_leaf_kernel, dim3(cdiv(m, (int64_t)kNT * kLeafQpt)), dim3(kNT), 0, s,
-                       tv, fl ? 1 : 0, (const uint32_t*)queries, m, tv.L - shift, boxes ? 1 : 0, key);
+    if (tv.xn)
+        hipLaunchKernelGGL(query_xleaf_kernel, dim3(cdiv(m, kNT)), dim3(kNT), 0, s, tv, fl ? 1 : 0,
+                           (const uint32_t*)queries, m, shift, boxes ? 1 : 0, key);
+    else
+        hipLaunchKernelGGL(query_leaf_kernel, dim3(cdiv(m, (int64_t)kNT * kLeafQpt)), dim3(kNT), 0, s,
+                           tv, fl ? 1 : 0, (const uint32_t*)queries, m, tv.L - shift, boxes ? 1 : 0, key);
     PG_LAUNCH_CHECK();
     hipLaunchKernelGGL(bucket_count_kernel, dim3(cdiv(m, kNT)), dim3(kNT), 0, s, key, m, cnt);
     PG_LAUNCH_CHECK();

@@ -8,12 +8,15 @@ namespace pg {
 pg_status knn_static_float(const pg_tree* t, const void* queries, const int32_t* o, int64_t m, int k,
                  bool all, int32_t* out_idx, void* out_dist, hipStream_t s, bool no_self) {
     using namespace knn_detail;
-    if (t->loff) {
-        if (no_self) return dispatch_d<float, true, true>(t, nullptr, nullptr, m, k, true, out_idx, out_dist, s);
-        return dispatch_d<float, false, true>(t, queries, o, m, k, all, out_idx, out_dist, s);
+    const int tk = tree_kind(t);
+    if (no_self) {
+        if (tk == kTreeX) return dispatch_d<float, true, kTreeX>(t, nullptr, nullptr, m, k, true, out_idx, out_dist, s);
+        if (tk == kTreeLoff) return dispatch_d<float, true, kTreeLoff>(t, nullptr, nullptr, m, k, true, out_idx, out_dist, s);
+        return dispatch_d<float, true, kTreeHeap>(t, nullptr, nullptr, m, k, true, out_idx, out_dist, s);
     }
-    if (no_self) return dispatch_d<float, true, false>(t, nullptr, nullptr, m, k, true, out_idx, out_dist, s);
-    return dispatch_d<float, false, false>(t, queries, o, m, k, all, out_idx, out_dist, s);
+    if (tk == kTreeX) return dispatch_d<float, false, kTreeX>(t, queries, o, m, k, all, out_idx, out_dist, s);
+    if (tk == kTreeLoff) return dispatch_d<float, false, kTreeLoff>(t, queries, o, m, k, all, out_idx, out_dist, s);
+    return dispatch_d<float, false, kTreeHeap>(t, queries, o, m, k, all, out_idx, out_dist, s);
 }
 
 }  // namespace pg

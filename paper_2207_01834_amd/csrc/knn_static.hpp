@@ -6,7 +6,7 @@
 #pragma once
 
 #include "scan.hpp"
-#include "search.hpp"
+#include "xsearch.hpp"
 #include "wave.hpp"
 
 namespace pg {
@@ -29,8 +29,8 @@ __device__ inline void load_query(const TreeView& tv, const uint32_t* queries, i
 // reached the packed range's limit (int32 coordinates: 2^(64-B) - 1, or fewer
 // than k points) is appended to `redo` for knn_redo_kernel instead of written.
 // NS (all-points only): the query's own point is not a candidate (k-NN graph).
-// LOFF: the tree's leaf ranges are explicit offsets (spatial-median trees).
-template <typename T, int MD, int KT, bool EX, bool NS, bool LOFF>
+// TK: the tree kind (kTreeHeap, kTreeLoff, kTreeX).
+template <typename T, int MD, int KT, bool EX, bool NS, int TK>
 __global__ void __launch_bounds__(kNT)
 knn_static_kernel(TreeView tv, const uint32_t* __restrict__ queries,
                   const int32_t* __restrict__ order, int64_t m, int k, int all, int idbits,
@@ -47,10 +47,9 @@ knn_static_kernel(TreeView tv, const uint32_t* __restrict__ queries,
     using KL = PackedList<T, KT, EX>;
     KL kl;
     kl.init(idbits);
-    const uint32_t start =
-        all ? (1u << tv.L) + (LOFF ? leaf_at(tv.loff, tv.L, i) : leaf_of(tv.n, tv.L, i)) : 0u;
-    if constexpr (NS) kd_search<T, MD, KL, OtherIds, LOFF>(tv, OtherIds{i}, q, d, kl, k, start);
-    else kd_search<T, MD, KL, PlainIds, LOFF>(tv, PlainIds{}, q, d, kl, k, start);
+    const uint32_t start = search_start<TK>(tv, all != 0, i);
+    if constexpr (NS) tree_search<T, MD, KL, OtherIds, TK>(tv, OtherIds{i}, q, d, kl, k, start);
+    else tree_search<T, MD, KL, PlainIds, TK>(tv, PlainIds{}, q, d, kl, k, start);
     if (kl.needs_redo()) {
         redo[atomicAdd(nredo, 1u)] = (int32_t)i;
         return;
@@ -67,7 +66,7 @@ knn_static_kernel(TreeView tv, const uint32_t* __restrict__ queries,
 
 // The queries knn_static_kernel handed over, searched with exact
 // (distance, id) pairs.
-template <typename T, int MD, int KT, bool EX, bool NS, bool LOFF>
+template <typename T, int MD, int KT, bool EX, bool NS, int TK>
 __global__ void __launch_bounds__(kNT)
 knn_redo_kernel(TreeView tv, const uint32_t* __restrict__ queries, int k, int all,
                 const int32_t* __restrict__ redo, const uint32_t* __restrict__ nredo,
@@ -82,10 +81,9 @@ knn_redo_kernel(TreeView tv, const uint32_t* __restrict__ queries, int k, int al
         using KL = KList<typename M::D, int32_t, KT, EX>;
         KL kl;
         kl.init(M::inf(), INT32_MAX);
-        const uint32_t start =
-            all ? (1u << tv.L) + (LOFF ? leaf_at(tv.loff, tv.L, i) : leaf_of(tv.n, tv.L, i)) : 0u;
-        if constexpr (NS) kd_search<T, MD, KL, OtherIds, LOFF>(tv, OtherIds{i}, q, d, kl, k, start);
-        else kd_search<T, MD, KL, PlainIds, LOFF>(tv, PlainIds{}, q, d, kl, k, start);
+        const uint32_t start = search_start<TK>(tv, all != 0, i);
+        if constexpr (NS) tree_search<T, MD, KL, OtherIds, TK>(tv, OtherIds{i}, q, d, kl, k, start);
+        else tree_search<T, MD, KL, PlainIds, TK>(tv, PlainIds{}, q, d, kl, k, start);
         const int64_t row = all ? (int64_t)tv.pidx[i] : i;
 #pragma unroll
         for (int s = 0; s < KT; s++) {
@@ -99,7 +97,7 @@ knn_redo_kernel(TreeView tv, const uint32_t* __restrict__ queries, int k, int al
 
 constexpr unsigned kRedoBlocks = 512;
 
-template <typename T, int MD, int KT, bool EX, bool NS, bool LOFF>
+template <typename T, int MD, int KT, bool EX, bool NS, int TK>
 pg_status launch_static(const pg_tree* t, const void* queries, const int32_t* order, int64_t m,
                         int k, bool all, int32_t* out_idx, void* out_dist, hipStream_t s) {
     using DT = typename Metric<T>::D;
@@ -110,13 +108,13 @@ pg_status launch_static(const pg_tree* t, const void* queries, const int32_t* or
         PG_TRY(nredo.alloc(sizeof(uint32_t)));
         PG_HIP(hipMemsetAsync(nredo.p, 0, sizeof(uint32_t), s));
     }
-    hipLaunchKernelGGL((knn_static_kernel<T, MD, KT, EX, NS, LOFF>), dim3(grid_for_xcd(cdiv(m, kNT))),
+    hipLaunchKernelGGL((knn_static_kernel<T, MD, KT, EX, NS, TK>), dim3(grid_for_xcd(cdiv(m, kNT))),
                        dim3(kNT), 0, s, t->view(), (const uint32_t*)queries, order, m, k,
                        all ? 1 : 0, id_bits(t->n), out_idx, (DT*)out_dist, redo.as<int32_t>(),
                        nredo.as<uint32_t>());
     PG_LAUNCH_CHECK();
     if (!exact) {
-        hipLaunchKernelGGL((knn_redo_kernel<T, MD, KT, EX, NS, LOFF>), dim3(kRedoBlocks), dim3(kNT), 0, s,
+        hipLaunchKernelGGL((knn_redo_kernel<T, MD, KT, EX, NS, TK>), dim3(kRedoBlocks), dim3(kNT), 0, s,
                            t->view(), (const uint32_t*)queries, k, all ? 1 : 0,
                            redo.as<int32_t>(), nredo.as<uint32_t>(), out_idx, (DT*)out_dist);
         PG_LAUNCH_CHECK();
@@ -126,28 +124,28 @@ pg_status launch_static(const pg_tree* t, const void* queries, const int32_t* or
 
 // k-list capacities: exact lists for the common k = 5, 10, 16, otherwise the
 // next power of two with uniform guards.
-template <typename T, int MD, bool NS, bool LOFF>
+template <typename T, int MD, bool NS, int TK>
 pg_status dispatch_k(const pg_tree* t, const void* q, const int32_t* o, int64_t m, int k, bool all,
                      int32_t* oi, void* od, hipStream_t s) {
-    if (k == 5) return launch_static<T, MD, 5, true, NS, LOFF>(t, q, o, m, k, all, oi, od, s);
-    if (k == 10) return launch_static<T, MD, 10, true, NS, LOFF>(t, q, o, m, k, all, oi, od, s);
-    if (k == 16) return launch_static<T, MD, 16, true, NS, LOFF>(t, q, o, m, k, all, oi, od, s);
-    if (k <= 2) return launch_static<T, MD, 2, false, NS, LOFF>(t, q, o, m, k, all, oi, od, s);
-    if (k <= 4) return launch_static<T, MD, 4, false, NS, LOFF>(t, q, o, m, k, all, oi, od, s);
-    if (k <= 8) return launch_static<T, MD, 8, false, NS, LOFF>(t, q, o, m, k, all, oi, od, s);
-    if (k <= 16) return launch_static<T, MD, 16, false, NS, LOFF>(t, q, o, m, k, all, oi, od, s);
-    if (k <= 32) return launch_static<T, MD, 32, false, NS, LOFF>(t, q, o, m, k, all, oi, od, s);
-    return launch_static<T, MD, 64, false, NS, LOFF>(t, q, o, m, k, all, oi, od, s);
+    if (k == 5) return launch_static<T, MD, 5, true, NS, TK>(t, q, o, m, k, all, oi, od, s);
+    if (k == 10) return launch_static<T, MD, 10, true, NS, TK>(t, q, o, m, k, all, oi, od, s);
+    if (k == 16) return launch_static<T, MD, 16, true, NS, TK>(t, q, o, m, k, all, oi, od, s);
+    if (k <= 2) return launch_static<T, MD, 2, false, NS, TK>(t, q, o, m, k, all, oi, od, s);
+    if (k <= 4) return launch_static<T, MD, 4, false, NS, TK>(t, q, o, m, k, all, oi, od, s);
+    if (k <= 8) return launch_static<T, MD, 8, false, NS, TK>(t, q, o, m, k, all, oi, od, s);
+    if (k <= 16) return launch_static<T, MD, 16, false, NS, TK>(t, q, o, m, k, all, oi, od, s);
+    if (k <= 32) return launch_static<T, MD, 32, false, NS, TK>(t, q, o, m, k, all, oi, od, s);
+    return launch_static<T, MD, 64, false, NS, TK>(t, q, o, m, k, all, oi, od, s);
 }
 
-template <typename T, bool NS, bool LOFF>
+template <typename T, bool NS, int TK>
 pg_status dispatch_d(const pg_tree* t, const void* q, const int32_t* o, int64_t m, int k, bool all,
                      int32_t* oi, void* od, hipStream_t s) {
     switch (t->d) {
-        case 2: return dispatch_k<T, 2, NS, LOFF>(t, q, o, m, k, all, oi, od, s);
-        case 3: return dispatch_k<T, 3, NS, LOFF>(t, q, o, m, k, all, oi, od, s);
-        case 5: return dispatch_k<T, 5, NS, LOFF>(t, q, o, m, k, all, oi, od, s);
-        default: return dispatch_k<T, 8, NS, LOFF>(t, q, o, m, k, all, oi, od, s);
+        case 2: return dispatch_k<T, 2, NS, TK>(t, q, o, m, k, all, oi, od, s);
+        case 3: return dispatch_k<T, 3, NS, TK>(t, q, o, m, k, all, oi, od, s);
+        case 5: return dispatch_k<T, 5, NS, TK>(t, q, o, m, k, all, oi, od, s);
+        default: return dispatch_k<T, 8, NS, TK>(t, q, o, m, k, all, oi, od, s);
     }
 }
 

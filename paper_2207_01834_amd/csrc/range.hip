@@ -21,7 +21,7 @@
 #include "range.hpp"
 #include "knn.hpp"
 #include "scan.hpp"
-#include "search.hpp"
+#include "xsearch.hpp"
 #include "wave.hpp"
 
 namespace pg {
@@ -119,7 +119,7 @@ __device__ inline void box_masks(const T (&bl)[MD], const T (&bh)[MD], const T (
 //          i0-th go to out_idx[i0 * kStashRows ...], with i0 in where[i] (a
 //          later gather moves them; boxes with more rows are walked again by
 //          kReport).
-template <typename T, int MD, int MODE>
+template <typename T, int MD, int MODE, bool XT>
 __global__ void __launch_bounds__(kNT)
 range_kernel(TreeView tv, const uint32_t* __restrict__ boxes, const int32_t* __restrict__ order,
              int64_t m, int32_t* __restrict__ counts, const int64_t* __restrict__ offsets,
@@ -195,84 +195,146 @@ range_kernel(TreeView tv, const uint32_t* __restrict__ boxes, const int32_t* __r
     };
 
     const uint64_t live = __ballot(valid);
-    uint64_t act;  // lanes whose box cuts the node the walk enters
-    {
+    if constexpr (XT) {
+        // Explicit-node tree: the same walk, stack-free.  Entering node h
+        // (with act = the lanes whose box cuts it) tests its children in
+        // order; back from a child, the lanes cutting h are recomputed from
+        // h's box (node boxes nest, so they are the lanes active at h).
+        auto range_of = [&](uint32_t u, int64_t& s0, int64_t& s1) {
+            const uint2 sp = tv.xspan[u];
+            s0 = tv.loff[sp.x];
+            s1 = tv.loff[sp.y];
+        };
         T bl[MD], bh[MD];
-        load_node_box<T, MD>(tv, 1, d, bl, bh);
+        load_node_box<T, MD>(tv, 0, d, bl, bh);
         uint64_t miss, inside;
         box_masks<T, MD>(bl, bh, lo, hi, d, miss, inside);
         const uint64_t take = live & inside;
-        act = live & ~miss & ~inside;
+        uint64_t act = live & ~miss & ~inside;
         if (take != 0) take_range(0, tv.n, take);
-        if (tv.L == 0) {
+        uint4 r = tv.xn[0];
+        if (r.w & kXLeaf) {
             if (act != 0) scan_leaf(0, tv.n, act);
             act = 0;
         }
-    }
-    uint32_t h = 1;          // node entered (internal), level l
-    int l = 0;
-    uint32_t pending = 0;    // bit k: stk[k] holds the right child at level k+1
-    while (act != 0) {
-        T bl0[MD], bh0[MD], bl1[MD], bh1[MD];
-        load_node_box<T, MD>(tv, 2u * h, d, bl0, bh0);
-        load_node_box<T, MD>(tv, 2u * h + 1u, d, bl1, bh1);
-        uint64_t miss0, in0, miss1, in1;
-        box_masks<T, MD>(bl0, bh0, lo, hi, d, miss0, in0);
-        box_masks<T, MD>(bl1, bh1, lo, hi, d, miss1, in1);
-        const uint64_t take0 = act & in0, take1 = act & in1;
-        const uint64_t cut0 = act & ~miss0 & ~in0, cut1 = act & ~miss1 & ~in1;
-        // a lane's rows come out in leaf order: everything under the left
-        // child before anything under the right one
-        const int64_t j = 2 * ((int64_t)h - ((int64_t)1 << l));  // left child at level l+1
-        if (l + 1 == tv.L) {
-            if ((take0 | take1 | cut0 | cut1) != 0) {
-                const int64_t s0 = node_begin(tv, l + 1, j), s1 = node_begin(tv, l + 1, j + 1),
-                              s2 = node_begin(tv, l + 1, j + 2);
-                if (take0 != 0) take_range(s0, s1, take0);
-                if (cut0 != 0) scan_leaf(s0, s1, cut0);
-                if (take1 != 0) take_range(s1, s2, take1);
-                if (cut1 != 0) scan_leaf(s1, s2, cut1);
+        uint32_t h = 0, prev = kXNone;  // prev == parent: h was just entered
+        while (act != 0 || h != 0 || prev != kXNone) {
+            if (prev != r.z) {
+                // back from child prev: the lanes cutting h
+                load_node_box<T, MD>(tv, h, d, bl, bh);
+                box_masks<T, MD>(bl, bh, lo, hi, d, miss, inside);
+                act = live & ~miss & ~inside;
             }
-            act = 0;
-        } else {
-            if (take0 != 0)
-                take_range(node_begin(tv, l + 1, j), node_begin(tv, l + 1, j + 1), take0);
-            if (cut0 != 0) {
-                if ((cut1 | take1) != 0) {  // the right child waits (same value in every lane)
-                    stk[l][0] = cut1;
-                    stk[l][1] = take1;
-                    pending |= 1u << l;
+            uint32_t side = prev == r.z ? 0u : prev - r.y + 1u;
+            bool down = false;
+            for (; side < 2u; side++) {
+                const uint32_t c = r.y + side;
+                load_node_box<T, MD>(tv, c, d, bl, bh);
+                box_masks<T, MD>(bl, bh, lo, hi, d, miss, inside);
+                const uint64_t tk = act & inside, ct = act & ~miss & ~inside;
+                if ((tk | ct) == 0) continue;
+                int64_t s0, s1;
+                range_of(c, s0, s1);
+                if (tk != 0) take_range(s0, s1, tk);
+                if (ct != 0) {
+                    if (r.w & (kXChildLeaf << side)) {
+                        scan_leaf(s0, s1, ct);
+                    } else {
+                        prev = h;
+                        h = c;
+                        act = ct;
+                        r = tv.xn[h];
+                        down = true;
+                        break;
+                    }
                 }
-                h = 2u * h;
-                l++;
-                act = cut0;
-                continue;
             }
-            if (take1 != 0)
-                take_range(node_begin(tv, l + 1, j + 1), node_begin(tv, l + 1, j + 2), take1);
-            if (cut1 != 0) {
-                h = 2u * h + 1u;
-                l++;
-                act = cut1;
-                continue;
-            }
-            act = 0;
+            if (down) continue;
+            if (r.z == kXNone) break;  // back at the root, both children done
+            prev = h;
+            h = r.z;
+            r = tv.xn[h];
         }
-        // subtree done: the deepest waiting right child, its whole-range
-        // lanes first; entered when some lane's box cuts it
-        while (pending != 0) {
-            const int k = 31 - __builtin_clz(pending);
-            pending &= ~(1u << k);
-            h = 2u * (h >> (l - k)) + 1u;
-            l = k + 1;
-            const uint64_t ct = scalar_u64(stk[k][0]), tk = scalar_u64(stk[k][1]);
-            if (tk != 0) {
-                const int64_t jr = (int64_t)h - ((int64_t)1 << l);
-                take_range(node_begin(tv, l, jr), node_begin(tv, l, jr + 1), tk);
+    } else {
+        uint64_t act;  // lanes whose box cuts the node the walk enters
+        {
+            T bl[MD], bh[MD];
+            load_node_box<T, MD>(tv, 1, d, bl, bh);
+            uint64_t miss, inside;
+            box_masks<T, MD>(bl, bh, lo, hi, d, miss, inside);
+            const uint64_t take = live & inside;
+            act = live & ~miss & ~inside;
+            if (take != 0) take_range(0, tv.n, take);
+            if (tv.L == 0) {
+                if (act != 0) scan_leaf(0, tv.n, act);
+                act = 0;
             }
-            if (ct != 0) {
-                act = ct;
-                break;
+        }
+        uint32_t h = 1;          // node entered (internal), level l
+        int l = 0;
+        uint32_t pending = 0;    // bit k: stk[k] holds the right child at level k+1
+        while (act != 0) {
+            T bl0[MD], bh0[MD], bl1[MD], bh1[MD];
+            load_node_box<T, MD>(tv, 2u * h, d, bl0, bh0);
+            load_node_box<T, MD>(tv, 2u * h + 1u, d, bl1, bh1);
+            uint64_t miss0, in0, miss1, in1;
+            box_masks<T, MD>(bl0, bh0, lo, hi, d, miss0, in0);
+            box_masks<T, MD>(bl1, bh1, lo, hi, d, miss1, in1);
+            const uint64_t take0 = act & in0, take1 = act & in1;
+            const uint64_t cut0 = act & ~miss0 & ~in0, cut1 = act & ~miss1 & ~in1;
+            // a lane's rows come out in leaf order: everything under the left
+            // child before anything under the right one
+            const int64_t j = 2 * ((int64_t)h - ((int64_t)1 << l));  // left child at level l+1
+            if (l + 1 == tv.L) {
+                if ((take0 | take1 | cut0 | cut1) != 0) {
+                    const int64_t s0 = node_begin(tv, l + 1, j), s1 = node_begin(tv, l + 1, j + 1),
+                                  s2 = node_begin(tv, l + 1, j + 2);
+                    if (take0 != 0) take_range(s0, s1, take0);
+                    if (cut0 != 0) scan_leaf(s0, s1, cut0);
+                    if (take1 != 0) take_range(s1, s2, take1);
+                    if (cut1 != 0) scan_leaf(s1, s2, cut1);
+                }
+                act = 0;
+            } else {
+                if (take0 != 0)
+                    take_range(node_begin(tv, l + 1, j), node_begin(tv, l + 1, j + 1), take0);
+                if (cut0 != 0) {
+                    if ((cut1 | take1) != 0) {  // the right child waits (same value in every lane)
+                        stk[l][0] = cut1;
+                        stk[l][1] = take1;
+                        pending |= 1u << l;
+                    }
+                    h = 2u * h;
+                    l++;
+                    act = cut0;
+                    continue;
+                }
+                if (take1 != 0)
+                    take_range(node_begin(tv, l + 1, j + 1), node_begin(tv, l + 1, j + 2), take1);
+                if (cut1 != 0) {
+                    h = 2u * h + 1u;
+                    l++;
+                    act = cut1;
+                    continue;
+                }
+                act = 0;
+            }
+            // subtree done: the deepest waiting right child, its whole-range
+            // lanes first; entered when some lane's box cuts it
+            while (pending != 0) {
+                const int k = 31 - __builtin_clz(pending);
+                pending &= ~(1u << k);
+                h = 2u * (h >> (l - k)) + 1u;
+                l = k + 1;
+                const uint64_t ct = scalar_u64(stk[k][0]), tk = scalar_u64(stk[k][1]);
+                if (tk != 0) {
+                    const int64_t jr = (int64_t)h - ((int64_t)1 << l);
+                    take_range(node_begin(tv, l, jr), node_begin(tv, l, jr + 1), tk);
+                }
+                if (ct != 0) {
+                    act = ct;
+                    break;
+                }
             }
         }
     }
@@ -281,25 +343,36 @@ range_kernel(TreeView tv, const uint32_t* __restrict__ boxes, const int32_t* __r
     if (MODE == kReport && over) atomicOr(overflow, 1u);
 }
 
-template <typename T, int MD>
-pg_status launch_range(const pg_tree* t, const void* boxes, const int32_t* order, int64_t m,
-                       int mode, int32_t* counts, const int64_t* offsets, int32_t* out_idx,
-                       int64_t capacity, uint32_t* overflow, int32_t* where, hipStream_t s) {
+template <typename T, int MD, bool XT>
+pg_status launch_range_t(const pg_tree* t, const void* boxes, const int32_t* order, int64_t m,
+                         int mode, int32_t* counts, const int64_t* offsets, int32_t* out_idx,
+                         int64_t capacity, uint32_t* overflow, int32_t* where, hipStream_t s) {
     const dim3 grid(grid_for_xcd(cdiv(m, kNT)));
     if (mode == kReport)
-        hipLaunchKernelGGL((range_kernel<T, MD, kReport>), grid, dim3(kNT), 0, s, t->view(),
+        hipLaunchKernelGGL((range_kernel<T, MD, kReport, XT>), grid, dim3(kNT), 0, s, t->view(),
                            (const uint32_t*)boxes, order, m, nullptr, offsets, out_idx, capacity,
                            overflow, nullptr);
     else if (mode == kStash)
-        hipLaunchKernelGGL((range_kernel<T, MD, kStash>), grid, dim3(kNT), 0, s, t->view(),
+        hipLaunchKernelGGL((range_kernel<T, MD, kStash, XT>), grid, dim3(kNT), 0, s, t->view(),
                            (const uint32_t*)boxes, order, m, counts, nullptr, out_idx, 0, nullptr,
                            where);
     else
-        hipLaunchKernelGGL((range_kernel<T, MD, kCount>), grid, dim3(kNT), 0, s, t->view(),
+        hipLaunchKernelGGL((range_kernel<T, MD, kCount, XT>), grid, dim3(kNT), 0, s, t->view(),
                            (const uint32_t*)boxes, order, m, counts, nullptr, nullptr, 0,
                            nullptr, nullptr);
     PG_LAUNCH_CHECK();
     return PG_OK;
+}
+
+template <typename T, int MD>
+pg_status launch_range(const pg_tree* t, const void* boxes, const int32_t* order, int64_t m,
+                       int mode, int32_t* counts, const int64_t* offsets, int32_t* out_idx,
+                       int64_t capacity, uint32_t* overflow, int32_t* where, hipStream_t s) {
+    if (t->xn)
+        return launch_range_t<T, MD, true>(t, boxes, order, m, mode, counts, offsets, out_idx,
+                                           capacity, overflow, where, s);
+    return launch_range_t<T, MD, false>(t, boxes, order, m, mode, counts, offsets, out_idx, capacity,
+                                        overflow, where, s);
 }
 
 template <typename T>

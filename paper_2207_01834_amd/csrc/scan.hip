@@ -97,4 +97,9 @@ pg_status exclusive_scan_i32_i64(const int32_t* in, int64_t* out, int64_t n, int
     return exclusive_scan<int32_t, int64_t>(in, out, n, total, s);
 }
 
+pg_status exclusive_scan_u64(const uint64_t* in, uint64_t* out, int64_t n, uint64_t* total,
+                             hipStream_t s) {
+    return exclusive_scan<uint64_t, uint64_t>(in, out, n, total, s);
+}
+
 }  // namespace pg

@@ -11,5 +11,8 @@ pg_status exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint3
 // The same over int32 inputs with int64 sums (in and out do not alias).
 pg_status exclusive_scan_i32_i64(const int32_t* in, int64_t* out, int64_t n, int64_t* total,
                                  hipStream_t s);
+// The same over uint64 (in and out may alias).
+pg_status exclusive_scan_u64(const uint64_t* in, uint64_t* out, int64_t n, uint64_t* total,
+                             hipStream_t s);
 
 }  // namespace pg

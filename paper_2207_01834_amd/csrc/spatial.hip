@@ -1,34 +1,41 @@
 // Static kd-tree by spatial-median splits: the alternative to the object
 // median that Section 6.3 measures (a node's space is cut in half along a
-// dimension instead of at the median point).
+// dimension instead of at the median point), split, as Section 5 defines a
+// kd-tree, until a node holds a small constant number of points.
 //
-// Readings (the paper gives the rule only in words): the space of the root
-// is the bounding box of the points; node (l, j) cuts its cell at the cell's
-// midpoint s along dimension l mod d (rule 0) or along the cell's widest side,
-// the lowest dimension on ties (rule 1); its points with coordinate < s go
-// left, the others right.  Midpoints: an int32 cell [lo, hi] is cut at
-// floor((lo + hi + 1) / 2) into [lo, s - 1] and [s, hi]; a float32 cell at
-// the float nearest (lo + hi) / 2 (sum in double) into [lo, s] and [s, hi].
-// The tree keeps the object-median tree's depth L = min{L : ceil(n/2^L) <=
-// leaf} and heap layout, so leaves hold varying numbers of points and their
-// ranges are explicit offsets.
+// Readings (the paper gives the rule only in words):
+//  * a node holding at most `leaf` points, or only identical points (no cut
+//    separates them), is a leaf;
+//  * the root's space is the bounding box of the points; a node cuts its cell
+//    (rule bit 1 clear) or the bounding box of its own points (bit 1 set);
+//  * the cut dimension is depth mod d (rule bit 0 clear) or the space's
+//    widest side hi - lo, the lowest dimension on ties (bit 0 set);
+//  * spaces are closed intervals [lo, hi] of representable coordinates, and
+//    the cut s of [lo, hi] with lo < hi lies in (lo, hi]: int32
+//    floor((lo + hi + 1) / 2); float32 the float nearest (lo + hi) / 2 (sum
+//    and halving in double), or the next float above lo when that nearest
+//    float is lo itself; s = lo when lo == hi;
+//  * points with coordinate < s go to the first child (cell [lo, s-], s- the
+//    value just below s), the others to the second (cell [s, hi]), each side
+//    keeping the parent's order.
+// Nodes are numbered breadth-first: the root is 0, a level's nodes in leaf
+// order, the children of a node consecutive.
 //
-// Point-box form (rule bit 1): a node cuts the bounding box of its own
-// points instead of its cell, with the same midpoint and side rules; a node
-// without points takes split 0 and dimension l mod d (0 under the widest
-// rule).
-//
-// GPU form: since every cut depends only on the cell, the leaf of a point
-// follows from its own coordinates (L comparisons against midpoints computed
-// on the fly), so the build is one pass for leaf keys, a counting sort by
-// leaf and a scatter, instead of one partition pass per level.  A point box
-// depends on the node's members, so that form goes level by level, but moves
-// no points until the end: every point carries its node, each level reduces
-// the nodes' boxes (LDS-private while the level's boxes fit, then global
-// atomics), cuts them, and steps every point to its child.  The order of
-// points inside a leaf is the order the counting sort's atomics give (leaf
-// membership, splits and offsets are deterministic; results do not depend on
-// the order inside a leaf).
+// GPU form: level-synchronous over the nodes that still split.  The points
+// of every node are one contiguous segment of a key-plane buffer; each level
+// cuts the splitting nodes' segments into 256-point chunks (one wave each),
+// counts the points going left per chunk, scans the counts, and partitions
+// stably into the other buffer -- or, for a child that is already a leaf by
+// its count, straight into the tree's leaf-order arrays.  The same pass
+// reduces each child's bounding box (a wave-wide min/max, one atomic per
+// chunk, child and bound), which gives the next level its point boxes, its
+// identical-point test and the search its node boxes.  A child holding only
+// identical points but more than `leaf` of them is copied to the leaf-order
+// arrays by the next level's pass.  Points of finished nodes are never
+// touched again.  Afterwards, level by level, subtree leaf counts (bottom-up)
+// give every leaf its index in leaf order (top-down).
+#include <utility>
+
 #include "build.hpp"
 #include "scan.hpp"
 #include "wave.hpp"
@@ -38,24 +45,81 @@ namespace pg {
 namespace {
 
 constexpr int kNT = 256;
-
-// Midpoint of cell [lo, hi] (coordinate values as doubles) and the cells of
-// the two halves.
-__device__ inline double cell_mid(double lo, double hi, bool fl) {
-    if (!fl) {
-        const int64_t t = (int64_t)lo + (int64_t)hi + 1;
-        return (double)(t >= 0 ? t / 2 : -((-t + 1) / 2));
-    }
-    return (double)(float)(0.5 * (lo + hi));
-}
+constexpr int kCH = 256;                 // points per chunk: one wave, four per lane
+constexpr int kChunkGroups = kCH / kWave;
+constexpr uint32_t kCopy = 1u << 8;      // entry mode bit: copy the segment (identical points)
+constexpr uint64_t kFlagSplit = 1ull;
+constexpr uint64_t kFlagCopy = 1ull << 32;
 
 __device__ inline double coord_value(uint32_t bits, bool fl) {
     return fl ? (double)__uint_as_float(bits) : (double)(int32_t)bits;
 }
 
-// Root cell: min / max key per dimension (box[c], box[d + c]).
+// Coordinate bits of value v (representable as the coordinate type).
+__device__ inline uint32_t value_bits(double v, bool fl) {
+    return fl ? __float_as_uint((float)v) : (uint32_t)(int32_t)v;
+}
+
+// The next float above / below x (both zeros step to the smallest denormal).
+__device__ inline float next_up(float x) {
+    const uint32_t b = __float_as_uint(x);
+    if ((b & 0x7fffffffu) == 0) return __uint_as_float(1u);
+    return __uint_as_float((b & 0x80000000u) ? b - 1u : b + 1u);
+}
+__device__ inline float next_down(float x) {
+    const uint32_t b = __float_as_uint(x);
+    if ((b & 0x7fffffffu) == 0) return __uint_as_float(0x80000001u);
+    return __uint_as_float((b & 0x80000000u) ? b + 1u : b - 1u);
+}
+
+// The cut of [lo, hi].
+__device__ inline double space_cut(double lo, double hi, bool fl) {
+    if (!(lo < hi)) return lo;
+    if (!fl) {
+        const int64_t t = (int64_t)lo + (int64_t)hi + 1;
+        return (double)(t >= 0 ? t / 2 : -((-t + 1) / 2));
+    }
+    float s = (float)(0.5 * (lo + hi));
+    if ((double)s <= lo) s = next_up((float)lo);
+    return (double)s;
+}
+
+// The largest coordinate below s.
+__device__ inline double value_below(double s, bool fl) {
+    return fl ? (double)next_down((float)s) : s - 1.0;
+}
+
+// The cut dimension of space [lo, hi] at depth `depth`.
+__device__ inline int space_dim(const double* lo, const double* hi, int d, int depth, int widest) {
+    if (!widest) return depth % d;
+    int c = 0;
+    for (int e = 1; e < d; e++)
+        if (hi[e] - lo[e] > hi[c] - lo[c]) c = e;
+    return c;
+}
+
+// The list of nodes a level processes (SoA): splitting nodes first, then the
+// identical-point nodes whose segment is copied.
+struct Entries {
+    uint32_t* node;   // node id
+    uint32_t* par;    // its parent
+    uint32_t* lo;     // segment start (leaf-order position)
+    uint32_t* cnt;    // points
+    uint32_t* cut;    // key of the cut
+    uint32_t* dim;    // cut dimension | kCopy
+    double* cell;     // [A][2d] cell (cell form): lo[d], hi[d]
+};
+
+struct Nodes {
+    uint4* xn;        // records
+    uint32_t* key;    // [N][2d] box keys: min[d], max[d]
+    uint32_t* lo;     // segment start
+    uint32_t* cnt;    // points
+};
+
+// Box keys of the root.
 __global__ void __launch_bounds__(kNT)
-key_box_kernel(const uint32_t* __restrict__ keys, int64_t n, int d, uint32_t* __restrict__ box) {
+root_box_kernel(const uint32_t* __restrict__ keys, int64_t n, int d, uint32_t* __restrict__ box) {
     for (int c = 0; c < d; c++) {
         uint32_t mn = 0xffffffffu, mx = 0u;
         for (int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kNT) {
@@ -72,463 +136,727 @@ key_box_kernel(const uint32_t* __restrict__ keys, int64_t n, int d, uint32_t* __
     }
 }
 
-// Cell of the root from the key box, as coordinate values.
-__device__ inline void root_cell(const uint32_t* box, int d, bool fl, double (&lo)[8], double (&hi)[8]) {
-#pragma unroll
-    for (int c = 0; c < 8; c++) {
-        lo[c] = c < d ? coord_value(key_to_coord(box[c], fl), fl) : 0.0;
-        hi[c] = c < d ? coord_value(key_to_coord(box[d + c], fl), fl) : 0.0;
-    }
-}
-
-// Split dimension of a cell at level l: l mod d, or its widest side.
-__device__ inline int cell_dim(const double (&lo)[8], const double (&hi)[8], int d, int l, int rule) {
-    if (rule == 0) return l % d;
-    int c = 0;
-    double best = hi[0] - lo[0];
-#pragma unroll
-    for (int cc = 1; cc < 8; cc++) {
-        if (cc < d && hi[cc] - lo[cc] > best) {
-            best = hi[cc] - lo[cc];
-            c = cc;
-        }
-    }
-    return c;
-}
-
-// Halves cell dimension c (runtime) toward `right`; returns the cut.
-__device__ inline double cut_cell(double (&lo)[8], double (&hi)[8], int c, bool right_of, bool fl,
-                                  bool go_right) {
-    double s = 0.0;
-#pragma unroll
-    for (int cc = 0; cc < 8; cc++) {
-        if (cc == c) {
-            s = cell_mid(lo[cc], hi[cc], fl);
-            if (right_of) {
-                if (go_right) lo[cc] = s;
-                else hi[cc] = fl ? s : s - 1.0;
-            }
-        }
-    }
-    return s;
-}
-
-// Ranks of the points of one workgroup (one point per thread) among their
-// leaves' points.  A leaf that holds one of kRankSlots LDS slots (tagged by
-// leaf) counts locally and takes one global atomic per workgroup; its points
-// get a local rank flagged by bit 31, finished by leaf_rank_fix_kernel from
-// the base stored in bbase[block][slot].  Other points take a global rank
-// directly.  A heavy leaf thus costs one global atomic per workgroup, not
-// one per point.  Must be called by every thread of the workgroup.
-constexpr int kRankSlots = 64;
-
-__device__ inline void rank_in_leaf(bool valid, uint32_t j, int64_t i, uint32_t* __restrict__ rank,
-                                    uint32_t* __restrict__ cnt, uint32_t* __restrict__ bbase) {
-    __shared__ uint32_t tag[kRankSlots], lcnt[kRankSlots];
-    if (threadIdx.x < kRankSlots) {
-        tag[threadIdx.x] = 0xffffffffu;
-        lcnt[threadIdx.x] = 0u;
-    }
-    __syncthreads();
-    if (valid) {
-        const int slot = (int)(j & (kRankSlots - 1));
-        uint32_t held = tag[slot];
-        if (held == 0xffffffffu) {
-            const uint32_t prev = atomicCAS(&tag[slot], 0xffffffffu, j);
-            held = prev == 0xffffffffu ? j : prev;
-        }
-        if (held == j) rank[i] = atomicAdd(&lcnt[slot], 1u) | 0x80000000u;
-        else rank[i] = atomicAdd(&cnt[j], 1u);
-    }
-    __syncthreads();
-    if (threadIdx.x < kRankSlots) {
-        const uint32_t t = tag[threadIdx.x];
-        bbase[(int64_t)blockIdx.x * kRankSlots + threadIdx.x] =
-            t != 0xffffffffu ? atomicAdd(&cnt[t], lcnt[threadIdx.x]) : 0u;
-    }
-}
-
-// Local ranks (bit 31) plus their workgroup's base for the leaf.
-__global__ void __launch_bounds__(kNT)
-leaf_rank_fix_kernel(const uint32_t* __restrict__ leaf, int64_t n, const uint32_t* __restrict__ bbase,
-                     uint32_t* __restrict__ rank) {
+__global__ void fill_u32_kernel(uint32_t* __restrict__ p, int64_t count, uint32_t lo_val,
+                                uint32_t hi_val, int d) {
+    // boxes: words [2d) per node, min then max
     const int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x;
-    if (i >= n) return;
-    const uint32_t r = rank[i];
-    if (r & 0x80000000u)
-        rank[i] = bbase[(i / kNT) * kRankSlots + (leaf[i] & (kRankSlots - 1))] + (r & 0x7fffffffu);
+    if (i < count) p[i] = (i % (2 * d)) < d ? lo_val : hi_val;
 }
 
-// Leaf of every point (input order) and its rank among its leaf's points.
-__global__ void __launch_bounds__(kNT)
-spatial_leaf_kernel(const uint32_t* __restrict__ keys, int64_t n, int d, int L, int fl, int rule,
-                    const uint32_t* __restrict__ box, uint32_t* __restrict__ leaf,
-                    uint32_t* __restrict__ rank, uint32_t* __restrict__ cnt,
-                    uint32_t* __restrict__ bbase) {
-    const int64_t i0 = (int64_t)blockIdx.x * kNT + threadIdx.x;
-    const bool valid = i0 < n;
-    const int64_t i = valid ? i0 : n - 1;  // an idle thread computes a real point's leaf
-    double lo[8], hi[8], x[8];
-    root_cell(box, d, fl != 0, lo, hi);
-#pragma unroll
-    for (int c = 0; c < 8; c++) x[c] = c < d ? coord_value(key_to_coord(keys[(int64_t)c * n + i], fl != 0), fl != 0) : 0.0;
-    uint32_t j = 0;
-    for (int l = 0; l < L; l++) {
-        const int c = cell_dim(lo, hi, d, l, rule);
-        double xc = x[0];
-#pragma unroll
-        for (int cc = 1; cc < 8; cc++) xc = cc == c ? x[cc] : xc;
-        double s = 0.0;
-#pragma unroll
-        for (int cc = 0; cc < 8; cc++)
-            if (cc == c) s = cell_mid(lo[cc], hi[cc], fl != 0);
-        const bool right = xc >= s;
-        cut_cell(lo, hi, c, true, fl != 0, right);
-        j = 2u * j + (right ? 1u : 0u);
-    }
-    if (valid) leaf[i] = j;
-    rank_in_leaf(valid, j, i, rank, cnt, bbase);
+// Whether the box (keys) holds a single location.
+__device__ inline bool box_single(const uint32_t* b, int d) {
+    bool same = true;
+    for (int c = 0; c < d; c++) same = same && b[c] == b[d + c];
+    return same;
 }
 
-// Split (and dimension, when sdim is given) of internal node h: replay its
-// path from the root, then cut.
-__global__ void __launch_bounds__(kNT)
-spatial_split_kernel(int d, int L, int fl, int rule, const uint32_t* __restrict__ box,
-                     uint32_t* __restrict__ split, uint8_t* __restrict__ sdim) {
-    const int64_t h = (int64_t)blockIdx.x * kNT + threadIdx.x;
-    if (h >= ((int64_t)1 << L)) return;
-    if (h == 0) {
-        split[0] = 0u;
-        if (sdim) sdim[0] = 0;
+// Sets up the root: a leaf (copied when it holds points) or the first
+// splitting node.  tot = {splitting entries, copy entries}; cstart = {0, chunks}.
+__global__ void root_kernel(Nodes N, Entries E, int64_t n, int d, int leaf, int fl, int rule,
+                            uint32_t* __restrict__ cstart, uint32_t* __restrict__ tot) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const uint32_t* b = N.key;
+    const bool isleaf = n <= leaf || box_single(b, d);
+    N.lo[0] = 0;
+    N.cnt[0] = (uint32_t)n;
+    const uint32_t chunks = (uint32_t)((n + kCH - 1) / kCH);
+    cstart[0] = 0;
+    cstart[1] = chunks;
+    if (isleaf) {
+        N.xn[0] = make_uint4(0u, 0u, kXNone, kXLeaf | (n == 0 ? kXEmpty : 0u));
+        tot[0] = 0;
+        tot[1] = n > 0 ? 1u : 0u;
+        if (n > 0) {
+            E.node[0] = 0;
+            E.par[0] = kXNone;
+            E.lo[0] = 0;
+            E.cnt[0] = (uint32_t)n;
+            E.cut[0] = 0;
+            E.dim[0] = kCopy;
+        }
         return;
     }
-    const int l = 63 - __builtin_clzll((unsigned long long)h);
     double lo[8], hi[8];
-    root_cell(box, d, fl != 0, lo, hi);
-    for (int t = 0; t < l; t++) {
-        const bool right = ((h >> (l - 1 - t)) & 1) != 0;
-        cut_cell(lo, hi, cell_dim(lo, hi, d, t, rule), true, fl != 0, right);
-    }
-    const int c = cell_dim(lo, hi, d, l, rule);
-    const double s = cut_cell(lo, hi, c, false, fl != 0, false);
-    split[h] = fl ? __float_as_uint((float)s) : (uint32_t)(int32_t)s;
-    if (sdim) sdim[h] = (uint8_t)c;
-}
-
-// ---- point-box form ----
-
-constexpr int kBoxSlots = 512;  // node boxes cached per workgroup (a power of two)
-
-__global__ void pbox_fill_kernel(uint32_t* __restrict__ bmin, uint32_t* __restrict__ bmax, int64_t cnt) {
-    const int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x;
-    if (i < cnt) {
-        bmin[i] = 0xffffffffu;
-        bmax[i] = 0u;
-    }
-}
-
-// Box (min / max key per dimension) of every node of the level, over the
-// points' current nodes nid.  lds: reduce into 2 * J * d LDS words first.
-__global__ void __launch_bounds__(kNT)
-pbox_reduce_kernel(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ nid, int64_t n,
-                   int d, int64_t J, int lds, uint32_t* __restrict__ bmin,
-                   uint32_t* __restrict__ bmax) {
-    extern __shared__ uint32_t sb[];
-    const int64_t Jd = J * d;
-    const int64_t stride = (int64_t)gridDim.x * kNT;
-    if (lds) {
-        for (int64_t t = threadIdx.x; t < Jd; t += kNT) {
-            sb[t] = 0xffffffffu;
-            sb[Jd + t] = 0u;
+    for (int c = 0; c < d; c++) {
+        lo[c] = coord_value(key_to_coord(b[c], fl != 0), fl != 0);
+        hi[c] = coord_value(key_to_coord(b[d + c], fl != 0), fl != 0);
+        if (!(rule & 2)) {
+            E.cell[c] = lo[c];
+            E.cell[d + c] = hi[c];
         }
-        __syncthreads();
-        if (J == 1) {  // one node: registers first, one LDS atomic per thread and dimension
-            uint32_t mn[8], mx[8];
+    }
+    const int c = space_dim(lo, hi, d, 0, rule & 1);
+    const double s = space_cut(lo[c], hi[c], fl != 0);
+    E.node[0] = 0;
+    E.par[0] = kXNone;
+    E.lo[0] = 0;
+    E.cnt[0] = (uint32_t)n;
+    E.cut[0] = coord_to_key(value_bits(s, fl != 0), fl != 0);
+    E.dim[0] = (uint32_t)c;
+    tot[0] = 1;
+    tot[1] = 0;
+}
+
+// Entry of chunk c: the last a with cstart[a] <= c (every entry has a chunk).
+__device__ inline uint32_t chunk_entry(const uint32_t* cstart, uint32_t A, uint32_t c) {
+    uint32_t lo = 0, hi = A;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (cstart[mid] <= c) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Per chunk (one wave): its entry, and the number of its points going left.
+__global__ void __launch_bounds__(kNT)
+chunk_count_kernel(Entries E, const uint32_t* __restrict__ cstart, uint32_t A, uint32_t C,
+                   const uint32_t* __restrict__ keys, int64_t n, uint32_t* __restrict__ c2e,
+                   uint32_t* __restrict__ lcnt) {
+    const uint32_t c = blockIdx.x * (kNT / kWave) + threadIdx.x / kWave;
+    if (c == 0 && threadIdx.x == 0) lcnt[C] = 0;
+    if (c >= C) return;
+    const uint32_t a = chunk_entry(cstart, A, c);
+    const uint32_t dm = E.dim[a];
+    uint32_t left = 0;
+    if (!(dm & kCopy)) {
+        const uint32_t lo = E.lo[a], end = lo + E.cnt[a];
+        const uint32_t base = lo + (c - cstart[a]) * kCH;
+        const uint32_t cut = E.cut[a];
+        const uint32_t* plane = keys + (int64_t)(dm & 15u) * n;
+        uint32_t kv[kChunkGroups];
 #pragma unroll
-            for (int c = 0; c < 8; c++) {
-                mn[c] = 0xffffffffu;
-                mx[c] = 0u;
+        for (int g = 0; g < kChunkGroups; g++) {
+            const uint32_t p = base + g * kWave + lane_id();
+            kv[g] = p < end ? plane[p] : 0xffffffffu;
+        }
+#pragma unroll
+        for (int g = 0; g < kChunkGroups; g++) {
+            const uint32_t p = base + g * kWave + lane_id();
+            left += (uint32_t)__popcll(__ballot(p < end && kv[g] < cut));
+        }
+    }
+    if (lane_id() == 0) {
+        c2e[c] = a;
+        lcnt[c] = left;
+    }
+}
+
+// Writes point (keys kv, row r) to leaf-order position p of the tree.
+template <int MD>
+__device__ inline void put_final(const uint32_t (&kv)[MD], int32_t r, int64_t p, int d, int rw, bool fl,
+                                 int64_t n, uint32_t* __restrict__ pts, uint32_t* __restrict__ rec,
+                                 int32_t* __restrict__ pidx) {
+    uint32_t w[16];
+#pragma unroll
+    for (int e = 0; e < 16; e++) w[e] = 0u;
+#pragma unroll
+    for (int c = 0; c < MD; c++) {
+        if (c < d) {
+            const uint32_t v = key_to_coord(kv[c], fl);
+            pts[(int64_t)c * n + p] = v;
+            w[c] = v;
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < 16; e++)
+        if (e == d) w[e] = (uint32_t)r;
+    uint4* dst = reinterpret_cast<uint4*>(rec + p * rw);
+#pragma unroll
+    for (int q = 0; q < 4; q++)
+        if (q < rw / 4) dst[q] = make_uint4(w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]);
+    pidx[p] = r;
+}
+
+// Per chunk (one wave): stable partition of the chunk's points (left: key
+// of the cut dimension below the cut), into the other buffer or, for a child
+// that is a leaf by its count, the tree's arrays; reduces each child's box.
+// Copy entries write their points to the tree's arrays in place.
+template <int MD>
+__global__ void __launch_bounds__(kNT)
+chunk_scatter_kernel(Entries E, Nodes N, const uint32_t* __restrict__ cstart,
+                     const uint32_t* __restrict__ lpre, const uint32_t* __restrict__ c2e, uint32_t C,
+                     uint32_t nbase, int leaf, int d, int rw, int fl,
+                     const uint32_t* __restrict__ keys, const int32_t* __restrict__ idx,
+                     uint32_t* __restrict__ okeys, int32_t* __restrict__ oidx, int64_t n,
+                     uint32_t* __restrict__ pts, uint32_t* __restrict__ rec,
+                     int32_t* __restrict__ pidx) {
+    const uint32_t c = blockIdx.x * (kNT / kWave) + threadIdx.x / kWave;
+    if (c >= C) return;
+    const uint32_t a = c2e[c];
+    const uint32_t dm = E.dim[a];
+    const uint32_t lo = E.lo[a], cnt = E.cnt[a], end = lo + cnt;
+    const uint32_t off = (c - cstart[a]) * kCH;
+    const int lane = lane_id();
+    if (dm & kCopy) {
+        for (int g = 0; g < kChunkGroups; g++) {
+            const uint32_t p = lo + off + g * kWave + lane;
+            if (p < end) {
+                uint32_t kv[MD];
+#pragma unroll
+                for (int e = 0; e < MD; e++) kv[e] = e < d ? keys[(int64_t)e * n + p] : 0u;
+                put_final<MD>(kv, idx[p], p, d, rw, fl != 0, n, pts, rec, pidx);
             }
-            for (int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x; i < n; i += stride) {
+        }
+        return;
+    }
+    const int dim = (int)(dm & 15u);
+    const uint32_t cut = E.cut[a];
+    const uint32_t cs = cstart[a];
+    uint32_t lb = lpre[c] - lpre[cs];  // left points before this chunk in the node
+    const uint32_t nl = lpre[cstart[a + 1]] - lpre[cs];
+    uint32_t rb = off - lb;
+    const uint32_t nr = cnt - nl;
+    const bool lfin = nl <= (uint32_t)leaf, rfin = nr <= (uint32_t)leaf;
+    uint32_t bmin[2][MD], bmax[2][MD];
 #pragma unroll
-                for (int c = 0; c < 8; c++) {
-                    if (c < d) {
-                        const uint32_t k = keys[(int64_t)c * n + i];
-                        mn[c] = k < mn[c] ? k : mn[c];
-                        mx[c] = k > mx[c] ? k : mx[c];
+    for (int e = 0; e < MD; e++) {
+        bmin[0][e] = bmin[1][e] = 0xffffffffu;
+        bmax[0][e] = bmax[1][e] = 0u;
+    }
+    bool any0 = false, any1 = false;
+    for (int g = 0; g < kChunkGroups; g++) {
+        const uint32_t p = lo + off + g * kWave + lane;
+        const bool valid = p < end;
+        uint32_t kv[MD];
+        int32_t r = 0;
+#pragma unroll
+        for (int e = 0; e < MD; e++) kv[e] = (valid && e < d) ? keys[(int64_t)e * n + p] : 0u;
+        if (valid) r = idx[p];
+        uint32_t kc = kv[0];
+#pragma unroll
+        for (int e = 1; e < MD; e++) kc = e == dim ? kv[e] : kc;
+        const bool left = valid && kc < cut;
+        const uint64_t bl = __ballot(left), br = __ballot(valid && !left);
+        any0 = any0 || bl != 0;
+        any1 = any1 || br != 0;
+        if (valid) {
+            const uint32_t dst = left ? lo + lb + lane_prefix(bl) : lo + nl + rb + lane_prefix(br);
+            if (left ? lfin : rfin) {
+                put_final<MD>(kv, r, dst, d, rw, fl != 0, n, pts, rec, pidx);
+            } else {
+#pragma unroll
+                for (int e = 0; e < MD; e++)
+                    if (e < d) okeys[(int64_t)e * n + dst] = kv[e];
+                oidx[dst] = r;
+            }
+#pragma unroll
+            for (int e = 0; e < MD; e++) {
+                if (e < d) {
+                    const int sd = left ? 0 : 1;
+                    // select without dynamic register indexing
+                    if (sd == 0) {
+                        bmin[0][e] = kv[e] < bmin[0][e] ? kv[e] : bmin[0][e];
+                        bmax[0][e] = kv[e] > bmax[0][e] ? kv[e] : bmax[0][e];
+                    } else {
+                        bmin[1][e] = kv[e] < bmin[1][e] ? kv[e] : bmin[1][e];
+                        bmax[1][e] = kv[e] > bmax[1][e] ? kv[e] : bmax[1][e];
                     }
                 }
             }
+        }
+        lb += (uint32_t)__popcll(bl);
+        rb += (uint32_t)__popcll(br);
+    }
+    const uint32_t c0 = nbase + 2u * a;
 #pragma unroll
-            for (int c = 0; c < 8; c++) {
-                if (c < d) {
-                    atomicMin(&sb[c], mn[c]);
-                    atomicMax(&sb[Jd + c], mx[c]);
-                }
-            }
-        } else {
-            for (int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x; i < n; i += stride) {
-                const int64_t j = nid[i];
-                for (int c = 0; c < d; c++) {
-                    const uint32_t k = keys[(int64_t)c * n + i];
-                    atomicMin(&sb[j * d + c], k);
-                    atomicMax(&sb[Jd + j * d + c], k);
+    for (int sd = 0; sd < 2; sd++) {
+        if (sd == 0 ? !any0 : !any1) continue;
+        uint32_t* bk = N.key + (size_t)(c0 + sd) * 2 * d;
+#pragma unroll
+        for (int e = 0; e < MD; e++) {
+            if (e < d) {
+                const uint32_t mn = wave_min_u32(bmin[sd][e]);
+                const uint32_t mx = wave_max_u32(bmax[sd][e]);
+                if (lane == 0) {
+                    atomicMin(&bk[e], mn);
+                    atomicMax(&bk[d + e], mx);
                 }
             }
         }
-        __syncthreads();
-        for (int64_t t = threadIdx.x; t < Jd; t += kNT) {
-            if (sb[t] <= sb[Jd + t]) {  // the node has points in this workgroup's share
-                atomicMin(&bmin[t], sb[t]);
-                atomicMax(&bmax[t], sb[Jd + t]);
-            }
-        }
+    }
+}
+
+// Per splitting entry: the node's record, its children's records, counts and
+// segments, and the children's flags for the next level (split / copy / leaf).
+__global__ void __launch_bounds__(kNT)
+split_nodes_kernel(Entries E, Nodes N, const uint32_t* __restrict__ cstart,
+                   const uint32_t* __restrict__ lpre, uint32_t As, uint32_t nbase, int leaf, int d,
+                   int fl, uint64_t* __restrict__ flags, uint32_t* __restrict__ nch_next) {
+    const uint32_t a = blockIdx.x * kNT + threadIdx.x;
+    if (a >= As) return;
+    const uint32_t u = E.node[a];
+    const uint32_t lo = E.lo[a], cnt = E.cnt[a];
+    const uint32_t nl = lpre[cstart[a + 1]] - lpre[cstart[a]];
+    const uint32_t c0 = nbase + 2u * a;
+    uint32_t meta = E.dim[a] & 15u;
+    for (int s = 0; s < 2; s++) {
+        const uint32_t cc = c0 + s;
+        const uint32_t ccnt = s ? cnt - nl : nl;
+        const bool small = ccnt <= (uint32_t)leaf;
+        const bool same = !small && box_single(N.key + (size_t)cc * 2 * d, d);
+        const bool isleaf = small || same;
+        N.lo[cc] = s ? lo + nl : lo;
+        N.cnt[cc] = ccnt;
+        N.xn[cc] = make_uint4(0u, 0u, u, isleaf ? (kXLeaf | (ccnt == 0 ? kXEmpty : 0u)) : 0u);
+        if (isleaf) meta |= kXChildLeaf << s;
+        if (ccnt == 0) meta |= kXChildEmpty << s;
+        flags[2 * a + s] = small ? 0ull : (same ? kFlagCopy : kFlagSplit);
+        nch_next[2 * a + s] = 0u;
+    }
+    N.xn[u] = make_uint4(key_to_coord(E.cut[a], fl != 0), c0, E.par[a], meta);
+}
+
+// Per child slot t = 2a + s of the level's splitting entries: the next
+// level's entry of a child that splits (its space, cut dimension and cut;
+// the boxes of its future children reset) or is copied.
+__global__ void __launch_bounds__(kNT)
+emit_kernel(Entries E, Entries X, Nodes N, const uint64_t* __restrict__ flags,
+            const uint64_t* __restrict__ fpre, const uint64_t* __restrict__ ftot, uint32_t As,
+            uint32_t nbase, uint32_t nbase_next, int depth, int d, int fl, int rule,
+            uint32_t* __restrict__ nch_next) {
+    const uint32_t t = blockIdx.x * kNT + threadIdx.x;
+    if (t >= 2 * As) return;
+    const uint64_t f = flags[t];
+    if (f == 0) return;
+    const uint32_t a = t >> 1, s = t & 1u;
+    const uint32_t cc = nbase + t;
+    const uint32_t lo = N.lo[cc], cnt = N.cnt[cc];
+    const uint32_t chunks = (cnt + kCH - 1) / kCH;
+    if (f == kFlagCopy) {
+        const uint32_t e = (uint32_t)(*ftot) + (uint32_t)(fpre[t] >> 32);
+        X.node[e] = cc;
+        X.par[e] = E.node[a];
+        X.lo[e] = lo;
+        X.cnt[e] = cnt;
+        X.cut[e] = 0;
+        X.dim[e] = kCopy;
+        nch_next[e] = chunks;
         return;
     }
-    // Many nodes: a direct-mapped LDS cache of node boxes (tag = node).  A
-    // point whose node holds (or claims) its slot updates the slot; the
-    // others go to global memory.  Heavy nodes, which would serialise their
-    // global atomics, are the likeliest to hold a slot; each workgroup then
-    // flushes its slots once.
-    uint32_t* tag = sb;                   // [kBoxSlots]
-    uint32_t* cmin = sb + kBoxSlots;      // [kBoxSlots][d]
-    uint32_t* cmax = cmin + kBoxSlots * d;
-    for (int t = threadIdx.x; t < kBoxSlots; t += kNT) tag[t] = 0xffffffffu;
-    for (int t = threadIdx.x; t < kBoxSlots * d; t += kNT) {
-        cmin[t] = 0xffffffffu;
-        cmax[t] = 0u;
-    }
-    __syncthreads();
-    for (int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x; i < n; i += stride) {
-        const uint32_t j = nid[i];
-        const int slot = (int)(j & (kBoxSlots - 1));
-        uint32_t held = tag[slot];
-        if (held == 0xffffffffu) {
-            const uint32_t prev = atomicCAS(&tag[slot], 0xffffffffu, j);
-            held = prev == 0xffffffffu ? j : prev;
+    const uint32_t e = (uint32_t)fpre[t];
+    const bool fb = fl != 0;
+    double slo[8], shi[8];
+    if (rule & 2) {
+        const uint32_t* b = N.key + (size_t)cc * 2 * d;
+        for (int c = 0; c < d; c++) {
+            slo[c] = coord_value(key_to_coord(b[c], fb), fb);
+            shi[c] = coord_value(key_to_coord(b[d + c], fb), fb);
         }
-        if (held == j) {
-            for (int c = 0; c < d; c++) {
-                const uint32_t k = keys[(int64_t)c * n + i];
-                atomicMin(&cmin[slot * d + c], k);
-                atomicMax(&cmax[slot * d + c], k);
-            }
-        } else {
-            for (int c = 0; c < d; c++) {
-                const uint32_t k = keys[(int64_t)c * n + i];
-                atomicMin(&bmin[(int64_t)j * d + c], k);
-                atomicMax(&bmax[(int64_t)j * d + c], k);
-            }
+    } else {
+        // the child's cell: the parent's cell, cut
+        const double* pc = E.cell + (size_t)a * 2 * d;
+        for (int c = 0; c < d; c++) {
+            slo[c] = pc[c];
+            shi[c] = pc[d + c];
+        }
+        const int pd = (int)(E.dim[a] & 15u);
+        const double ps = coord_value(key_to_coord(E.cut[a], fb), fb);
+        if (s == 0) shi[pd] = value_below(ps, fb);
+        else slo[pd] = ps;
+        double* xc = X.cell + (size_t)e * 2 * d;
+        for (int c = 0; c < d; c++) {
+            xc[c] = slo[c];
+            xc[d + c] = shi[c];
         }
     }
-    __syncthreads();
-    for (int t = threadIdx.x; t < kBoxSlots * d; t += kNT) {
-        const uint32_t j = tag[t / d];
-        if (j != 0xffffffffu && cmin[t] <= cmax[t]) {
-            atomicMin(&bmin[(int64_t)j * d + t % d], cmin[t]);
-            atomicMax(&bmax[(int64_t)j * d + t % d], cmax[t]);
-        }
+    const int c = space_dim(slo, shi, d, depth, rule & 1);
+    const double cut = space_cut(slo[c], shi[c], fb);
+    X.node[e] = cc;
+    X.par[e] = E.node[a];
+    X.lo[e] = lo;
+    X.cnt[e] = cnt;
+    X.cut[e] = coord_to_key(value_bits(cut, fb), fb);
+    X.dim[e] = (uint32_t)c;
+    nch_next[e] = chunks;
+    uint32_t* bk = N.key + (size_t)(nbase_next + 2u * e) * 2 * d;
+    for (int w = 0; w < 2 * d; w++) {
+        bk[w] = (w % (2 * d)) < d ? 0xffffffffu : 0u;
+        bk[2 * d + w] = (w % (2 * d)) < d ? 0xffffffffu : 0u;
     }
 }
 
-// Split of every node of level l from its point box: dimension (l mod d, or
-// the box's widest side, lowest on ties), cut at the box's midpoint.
+// Leaves below each node of one level (bottom-up, deepest level first).
+__global__ void leaf_count_kernel(const uint4* __restrict__ xn, uint32_t first, uint32_t count,
+                                  uint32_t* __restrict__ nlv) {
+    const uint32_t i = blockIdx.x * kNT + threadIdx.x;
+    if (i >= count) return;
+    const uint32_t u = first + i;
+    const uint4 r = xn[u];
+    nlv[u] = (r.w & kXLeaf) ? 1u : nlv[r.y] + nlv[r.y + 1];
+}
+
+// Leaf-index spans of one level's nodes (top-down; jlo[u] is set by the
+// parent's level, the root's is 0): children's spans, and for a leaf its
+// index, offset and node.
+__global__ void leaf_index_kernel(uint4* __restrict__ xn, uint32_t first, uint32_t count,
+                                  const uint32_t* __restrict__ nlv, uint32_t* __restrict__ jlo,
+                                  const uint32_t* __restrict__ nlo, uint2* __restrict__ xspan,
+                                  int64_t* __restrict__ loff, uint32_t* __restrict__ lnode) {
+    const uint32_t i = blockIdx.x * kNT + threadIdx.x;
+    if (i >= count) return;
+    const uint32_t u = first + i;
+    const uint32_t j = u == 0 ? 0u : jlo[u];
+    const uint4 r = xn[u];
+    xspan[u] = make_uint2(j, j + nlv[u]);
+    if (r.w & kXLeaf) {
+        xn[u].x = j;
+        loff[j] = nlo[u];
+        lnode[j] = u;
+    } else {
+        jlo[r.y] = j;
+        jlo[r.y + 1] = j + nlv[r.y];
+    }
+}
+
+// Node boxes as coordinates (an empty node: min above max at the ends of the
+// coordinate range, which every box query misses).
+__global__ void node_box_kernel(const uint32_t* __restrict__ key, const uint32_t* __restrict__ cnt,
+                                int64_t N, int d, int fl, uint32_t* __restrict__ nbox) {
+    const int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x;
+    if (i >= N * 2 * d) return;
+    const int64_t u = i / (2 * d);
+    const int w = (int)(i % (2 * d));
+    uint32_t v;
+    if (cnt[u] == 0) {
+        const bool mn = w < d;
+        v = fl ? (mn ? 0x7f7fffffu : 0xff7fffffu) : (mn ? 0x7fffffffu : 0x80000000u);
+    } else {
+        v = key_to_coord(key[i], fl != 0);
+    }
+    nbox[i] = v;
+}
+
+__global__ void set_i64_kernel(int64_t* __restrict__ p, int64_t v) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+}
+
+// A device array that grows by copying (node arrays of unknown final size).
+template <typename T>
+struct Grow {
+    T* p = nullptr;
+    size_t cap = 0;
+    hipStream_t s = nullptr;
+    ~Grow() { if (p) dfree(p, s); }
+    pg_status reserve(size_t need, size_t used) {
+        if (need <= cap) return PG_OK;
+        size_t nc = cap ? cap : 1024;
+        while (nc < need) nc *= 2;
+        T* q = nullptr;
+        PG_TRY(dalloc(&q, nc, s));
+        if (used) PG_HIP(hipMemcpyAsync(q, p, sizeof(T) * used, hipMemcpyDeviceToDevice, s));
+        if (p) dfree(p, s);
+        p = q;
+        cap = nc;
+        return PG_OK;
+    }
+    T* release() { T* q = p; p = nullptr; cap = 0; return q; }
+};
+
+template <int MD>
+void launch_scatter(unsigned grid, hipStream_t s, const Entries& E, const Nodes& N,
+                    const uint32_t* cstart, const uint32_t* lpre, const uint32_t* c2e, uint32_t C,
+                    uint32_t nbase, int leaf, int d, int rw, int fl, const uint32_t* keys,
+                    const int32_t* idx, uint32_t* okeys, int32_t* oidx, int64_t n, pg_tree* T) {
+    hipLaunchKernelGGL((chunk_scatter_kernel<MD>), dim3(grid), dim3(kNT), 0, s, E, N, cstart, lpre,
+                       c2e, C, nbase, leaf, d, rw, fl, keys, idx, okeys, oidx, n, T->pts, T->rec,
+                       T->pidx);
+}
+
+// Leaf boxes (keys) of an explicit-node tree from its points: one lane per
+// leaf-order position, a segmented min/max over the lanes of each leaf, one
+// atomic per (leaf, dimension) and wave.
 __global__ void __launch_bounds__(kNT)
-pbox_split_kernel(const uint32_t* __restrict__ bmin, const uint32_t* __restrict__ bmax, int64_t J,
-                  int l, int d, int fl, int widest, uint32_t* __restrict__ split_level,
-                  uint8_t* __restrict__ sdim_level, double* __restrict__ ns,
-                  uint8_t* __restrict__ nd) {
-    const int64_t j = (int64_t)blockIdx.x * kNT + threadIdx.x;
-    if (j >= J) return;
-    const bool empty = bmin[j * d] > bmax[j * d];
-    int c = widest ? 0 : l % d;
-    double s = 0.0;
-    if (!empty) {
-        double lo[8], hi[8];
+xleaf_box_kernel(TreeView tv, int fl, uint32_t* __restrict__ lkey) {
+    const int64_t p = (int64_t)blockIdx.x * kNT + threadIdx.x;
+    const bool valid = p < tv.n;
+    if (__ballot(valid) == 0) return;
+    uint32_t j = 0xffffffffu;
+    if (valid) {
+        uint32_t lo = 0, hi = (uint32_t)tv.nleaves;  // loff[lo] <= p < loff[hi]
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (tv.loff[mid] <= p) lo = mid;
+            else hi = mid;
+        }
+        j = lo;
+    }
+    const int lane = lane_id();
+    const uint32_t jprev = __shfl_up(j, 1, kWave);
+    const bool head = valid && (lane == 0 || jprev != j);
+    const int d = tv.d;
+    for (int c = 0; c < d; c++) {
+        const uint32_t k = valid ? coord_to_key(tv.pts[(int64_t)c * tv.n + p], fl != 0) : 0u;
+        uint32_t mn = valid ? k : 0xffffffffu, mx = k;
 #pragma unroll
-        for (int cc = 0; cc < 8; cc++) {
-            lo[cc] = cc < d ? coord_value(key_to_coord(bmin[j * d + cc], fl != 0), fl != 0) : 0.0;
-            hi[cc] = cc < d ? coord_value(key_to_coord(bmax[j * d + cc], fl != 0), fl != 0) : 0.0;
+        for (int off = 1; off < kWave; off <<= 1) {
+            const uint32_t omn = __shfl_down(mn, off, kWave), omx = __shfl_down(mx, off, kWave);
+            const uint32_t oj = __shfl_down(j, off, kWave);
+            if (lane + off < kWave && oj == j) {
+                mn = omn < mn ? omn : mn;
+                mx = omx > mx ? omx : mx;
+            }
         }
-        c = cell_dim(lo, hi, d, l, widest);
-#pragma unroll
-        for (int cc = 0; cc < 8; cc++)
-            if (cc == c) s = cell_mid(lo[cc], hi[cc], fl != 0);
-    }
-    split_level[j] = fl ? __float_as_uint((float)s) : (uint32_t)(int32_t)s;
-    if (sdim_level) sdim_level[j] = (uint8_t)c;
-    ns[j] = s;
-    nd[j] = (uint8_t)c;
-}
-
-// Every point steps to the child of its node: right when its coordinate
-// along the node's dimension is at least the cut.
-__global__ void __launch_bounds__(kNT)
-pbox_step_kernel(const uint32_t* __restrict__ keys, uint32_t* __restrict__ nid, int64_t n, int fl,
-                 const double* __restrict__ ns, const uint8_t* __restrict__ nd) {
-    const int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x;
-    if (i >= n) return;
-    const uint32_t j = nid[i];
-    const int c = nd[j];
-    const double x = coord_value(key_to_coord(keys[(int64_t)c * n + i], fl != 0), fl != 0);
-    nid[i] = 2u * j + (x >= ns[j] ? 1u : 0u);
-}
-
-// Rank of every point among its leaf's points (the node after L steps).
-__global__ void __launch_bounds__(kNT)
-pbox_rank_kernel(const uint32_t* __restrict__ nid, int64_t n, uint32_t* __restrict__ rank,
-                 uint32_t* __restrict__ cnt, uint32_t* __restrict__ bbase) {
-    const int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x;
-    const bool valid = i < n;
-    rank_in_leaf(valid, valid ? nid[i] : 0u, i, rank, cnt, bbase);
-}
-
-__global__ void spatial_offsets_kernel(const uint32_t* __restrict__ start, int64_t leaves, int64_t n,
-                                       int64_t* __restrict__ loff) {
-    const int64_t j = (int64_t)blockIdx.x * kNT + threadIdx.x;
-    if (j < leaves) loff[j] = start[j];
-    else if (j == leaves) loff[j] = n;
-}
-
-// Point i to position start[leaf] + rank: coordinate planes, records, rows.
-__global__ void __launch_bounds__(kNT)
-spatial_scatter_kernel(const uint32_t* __restrict__ keys, const int32_t* __restrict__ idx, int64_t n,
-                       int d, int rw, int fl, const uint32_t* __restrict__ leaf,
-                       const uint32_t* __restrict__ rank, const uint32_t* __restrict__ start,
-                       uint32_t* __restrict__ pts, uint32_t* __restrict__ rec,
-                       int32_t* __restrict__ pidx) {
-    const int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x;
-    if (i >= n) return;
-    const int64_t p = (int64_t)start[leaf[i]] + rank[i];
-    for (int w = 0; w < rw; w++) {
-        uint32_t v = 0;
-        if (w < d) {
-            v = key_to_coord(keys[(int64_t)w * n + i], fl != 0);
-            pts[(int64_t)w * n + p] = v;
-        } else if (w == d) {
-            v = (uint32_t)idx[i];
+        if (head) {
+            atomicMin(&lkey[(int64_t)j * 2 * d + c], mn);
+            atomicMax(&lkey[(int64_t)j * 2 * d + d + c], mx);
         }
-        rec[p * rw + w] = v;
     }
-    pidx[p] = idx[i];
+}
+
+// One level of an explicit-node tree, bottom-up: a leaf's box from its
+// points and its empty flag from its range; an internal node's box as the
+// union of its children's, and its child flags from theirs.
+__global__ void xrefresh_kernel(uint4* __restrict__ xn, uint32_t first, uint32_t count, int d, int fl,
+                                const uint32_t* __restrict__ lkey, const int64_t* __restrict__ loff,
+                                uint32_t* __restrict__ nkey, uint32_t* __restrict__ ncnt,
+                                uint32_t* __restrict__ nbox) {
+    const uint32_t i = blockIdx.x * kNT + threadIdx.x;
+    if (i >= count) return;
+    const uint32_t u = first + i;
+    uint4 r = xn[u];
+    uint32_t* bk = nkey + (size_t)u * 2 * d;
+    if (r.w & kXLeaf) {
+        const uint32_t c = (uint32_t)(loff[r.x + 1] - loff[r.x]);
+        for (int w = 0; w < 2 * d; w++) bk[w] = lkey[(size_t)r.x * 2 * d + w];
+        ncnt[u] = c;
+        r.w = (r.w & ~kXEmpty) | (c == 0 ? kXEmpty : 0u);
+    } else {
+        const uint32_t* b0 = nkey + (size_t)r.y * 2 * d;
+        const uint32_t* b1 = b0 + 2 * d;
+        for (int c = 0; c < d; c++) {
+            bk[c] = b0[c] < b1[c] ? b0[c] : b1[c];
+            bk[d + c] = b0[d + c] > b1[d + c] ? b0[d + c] : b1[d + c];
+        }
+        const uint32_t c0 = ncnt[r.y], c1 = ncnt[r.y + 1];
+        ncnt[u] = c0 + c1;
+        r.w &= ~(3u * kXChildEmpty);
+        r.w |= (c0 == 0 ? kXChildEmpty : 0u) | (c1 == 0 ? kXChildEmpty << 1 : 0u);
+    }
+    xn[u] = r;
+    const uint32_t cu = ncnt[u];
+    for (int w = 0; w < 2 * d; w++) {
+        const bool mn = w < d;
+        nbox[(size_t)u * 2 * d + w] =
+            cu == 0 ? (fl ? (mn ? 0x7f7fffffu : 0xff7fffffu) : (mn ? 0x7fffffffu : 0x80000000u))
+                    : key_to_coord(bk[w], fl != 0);
+    }
 }
 
 }  // namespace
 
+pg_status xtree_boxes(pg_tree* T, hipStream_t s) {
+    const int d = T->d;
+    const int fl = T->dtype == PG_FLOAT32 ? 1 : 0;
+    const int64_t leaves = T->nleaves, nodes = T->nnodes;
+    DevBuf lk(s), nk(s), nc(s);
+    PG_TRY(lk.alloc(sizeof(uint32_t) * (size_t)leaves * 2 * d));
+    PG_TRY(nk.alloc(sizeof(uint32_t) * (size_t)nodes * 2 * d));
+    PG_TRY(nc.alloc(sizeof(uint32_t) * (size_t)nodes));
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(cdiv(leaves * 2 * d, kNT)), dim3(kNT), 0, s,
+                       lk.as<uint32_t>(), leaves * 2 * d, 0xffffffffu, 0u, d);
+    PG_LAUNCH_CHECK();
+    if (T->n > 0) {
+        hipLaunchKernelGGL(xleaf_box_kernel, dim3(cdiv(T->n, kNT)), dim3(kNT), 0, s, T->view(), fl,
+                           lk.as<uint32_t>());
+        PG_LAUNCH_CHECK();
+    }
+    for (int l = (int)T->lvl.size() - 2; l >= 0; l--) {
+        const uint32_t first = (uint32_t)T->lvl[l], count = (uint32_t)(T->lvl[l + 1] - T->lvl[l]);
+        hipLaunchKernelGGL(xrefresh_kernel, dim3(cdiv(count, kNT)), dim3(kNT), 0, s, T->xn, first,
+                           count, d, fl, lk.as<uint32_t>(), T->loff, nk.as<uint32_t>(),
+                           nc.as<uint32_t>(), T->nbox);
+        PG_LAUNCH_CHECK();
+    }
+    return PG_OK;
+}
+
 pg_status build_tree_spatial(const void* points, int64_t n, int d, int leaf, int dtype, int rule,
                              hipStream_t s, pg_tree* T) {
     const bool fl = dtype == PG_FLOAT32;
-    const int widest = rule & 1;            // split dimension: the widest side
-    const bool point_box = (rule & 2) != 0;  // cut each node's point box
+    const int ifl = fl ? 1 : 0;
     T->n = n;
     T->d = d;
     T->leaf = leaf;
     T->dtype = dtype;
     T->stream = s;
-    T->L = tree_levels(n, leaf);
-    const int L = T->L;
-    const int64_t leaves = (int64_t)1 << L;
+    T->rule = rule;
     const int64_t nn = n > 0 ? n : 1;
     const int rw = record_words(d);
     PG_TRY(dalloc(&T->pts, (size_t)d * nn, s));
     PG_TRY(dalloc(&T->pidx, (size_t)nn + kTreePad, s));
-    PG_TRY(dalloc(&T->split, (size_t)leaves, s));
-    PG_TRY(dalloc(&T->nbox, (size_t)leaves * 2 * 2 * d, s));
-    T->bbox = T->nbox + (size_t)leaves * 2 * d;
     PG_TRY(dalloc(&T->rec, ((size_t)nn + kTreePad) * rw, s));
-    PG_TRY(dalloc(&T->loff, (size_t)leaves + 1, s));
-    if (widest) PG_TRY(dalloc(&T->sdim, (size_t)leaves, s));
-    if (n == 0) {
-        if (T->sdim) PG_HIP(hipMemsetAsync(T->sdim, 0, leaves, s));
-        PG_HIP(hipMemsetAsync(T->loff, 0, sizeof(int64_t) * (leaves + 1), s));
-        PG_HIP(hipMemsetAsync(T->split, 0, sizeof(uint32_t) * leaves, s));
-        return offset_boxes(T, s);
-    }
-    DevBuf keys(s), idx(s), box(s), lf(s), rk(s), cnt(s), start(s), bbase(s);
-    PG_TRY(keys.alloc(sizeof(uint32_t) * (size_t)d * n));
-    PG_TRY(idx.alloc(sizeof(int32_t) * (size_t)n));
+
+    // key planes (ping-pong), node arrays, per-level entries
+    DevBuf ka(s), ia(s), kb(s), ib(s), aux(s);
+    PG_TRY(ka.alloc(sizeof(uint32_t) * (size_t)d * nn));
+    PG_TRY(ia.alloc(sizeof(int32_t) * (size_t)nn));
     uint32_t vary[8] = {0}, keybase[8] = {0};
-    PG_TRY(ingest_points(points, n, d, fl, keys.as<uint32_t>(), idx.as<int32_t>(), vary, keybase, s));
-    PG_TRY(lf.alloc(sizeof(uint32_t) * n));
-    PG_TRY(rk.alloc(sizeof(uint32_t) * n));
-    PG_TRY(cnt.alloc(sizeof(uint32_t) * leaves));
-    PG_TRY(start.alloc(sizeof(uint32_t) * leaves));
-    PG_HIP(hipMemsetAsync(cnt.p, 0, sizeof(uint32_t) * leaves, s));
-    PG_TRY(bbase.alloc(sizeof(uint32_t) * (size_t)cdiv(n, kNT) * kRankSlots));
-    if (!point_box) {
-        PG_TRY(box.alloc(sizeof(uint32_t) * 2 * d));
-        PG_HIP(hipMemsetAsync(box.p, 0xff, sizeof(uint32_t) * d, s));
-        PG_HIP(hipMemsetAsync(box.as<uint32_t>() + d, 0, sizeof(uint32_t) * d, s));
+    if (n > 0)
+        PG_TRY(ingest_points(points, n, d, fl, ka.as<uint32_t>(), ia.as<int32_t>(), vary, keybase, s));
+    PG_TRY(kb.alloc(sizeof(uint32_t) * (size_t)d * nn));
+    PG_TRY(ib.alloc(sizeof(int32_t) * (size_t)nn));
+
+    Grow<uint4> gxn;
+    Grow<uint32_t> gkey, glo, gcnt;
+    gxn.s = gkey.s = glo.s = gcnt.s = s;
+    const size_t guess = (size_t)(4 * (nn / leaf) + 64);
+    PG_TRY(gxn.reserve(guess, 0));
+    PG_TRY(gkey.reserve(guess * 2 * d, 0));
+    PG_TRY(glo.reserve(guess, 0));
+    PG_TRY(gcnt.reserve(guess, 0));
+
+    // entries: at most one per (leaf + 1) points, per level; two sets
+    const size_t amax = (size_t)(nn / (leaf + 1) + 2);
+    const size_t cmax = (size_t)(nn / kCH + amax + 2);  // chunks
+    DevBuf ebuf[2] = {DevBuf(s), DevBuf(s)};
+    Entries ent[2];
+    for (int b = 0; b < 2; b++) {
+        const size_t cellw = (rule & 2) ? 0 : amax * 2 * d;
+        PG_TRY(ebuf[b].alloc(sizeof(double) * cellw + sizeof(uint32_t) * amax * 6));
+        ent[b].cell = ebuf[b].as<double>();
+        uint32_t* w = reinterpret_cast<uint32_t*>(ent[b].cell + cellw);
+        ent[b].node = w;
+        ent[b].par = w + amax;
+        ent[b].lo = w + 2 * amax;
+        ent[b].cnt = w + 3 * amax;
+        ent[b].cut = w + 4 * amax;
+        ent[b].dim = w + 5 * amax;
+    }
+    // chunk starts x 2 (current / next; the next level's are first indexed
+    // by child slot, [2 amax + 1]), c2e [cmax], lcnt [cmax + 1], flags and
+    // their prefix [2 amax] u64, totals
+    DevBuf cbuf(s), fbuf(s);
+    PG_TRY(cbuf.alloc(sizeof(uint32_t) * (2 * (2 * amax + 1) + cmax + cmax + 1 + 8)));
+    uint32_t* cst[2] = {cbuf.as<uint32_t>(), cbuf.as<uint32_t>() + 2 * amax + 1};
+    uint32_t* c2e = cst[1] + 2 * amax + 1;
+    uint32_t* lcnt = c2e + cmax;
+    uint32_t* tot32 = lcnt + cmax + 1;  // [0] root splitting entries, [1] root copies
+    PG_TRY(fbuf.alloc(sizeof(uint64_t) * (4 * amax + 2)));
+    uint64_t* flags = fbuf.as<uint64_t>();
+    uint64_t* fpre = flags + 2 * amax;
+    uint64_t* ftot = fpre + 2 * amax;
+
+    Nodes N{gxn.p, gkey.p, glo.p, gcnt.p};
+    // root box
+    PG_HIP(hipMemsetAsync(gkey.p, 0xff, sizeof(uint32_t) * d, s));
+    PG_HIP(hipMemsetAsync(gkey.p + d, 0, sizeof(uint32_t) * d, s));
+    if (n > 0) {
         const unsigned grid = cdiv(n, kNT) < 1024u ? cdiv(n, kNT) : 1024u;
-        hipLaunchKernelGGL(key_box_kernel, dim3(grid), dim3(kNT), 0, s, keys.as<uint32_t>(), n, d,
-                           box.as<uint32_t>());
+        hipLaunchKernelGGL(root_box_kernel, dim3(grid), dim3(kNT), 0, s, ka.as<uint32_t>(), n, d,
+                           gkey.p);
         PG_LAUNCH_CHECK();
-        hipLaunchKernelGGL(spatial_leaf_kernel, dim3(cdiv(n, kNT)), dim3(kNT), 0, s,
-                           keys.as<uint32_t>(), n, d, L, fl ? 1 : 0, widest, box.as<uint32_t>(),
-                           lf.as<uint32_t>(), rk.as<uint32_t>(), cnt.as<uint32_t>(),
-                           bbase.as<uint32_t>());
+    }
+    hipLaunchKernelGGL(root_kernel, dim3(1), dim3(1), 0, s, N, ent[0], n, d, leaf, ifl, rule, cst[0],
+                       tot32);
+    PG_LAUNCH_CHECK();
+    // the root's children's boxes start empty
+    if (n > 0) {
+        hipLaunchKernelGGL(fill_u32_kernel, dim3(cdiv(4 * d, kNT)), dim3(kNT), 0, s, gkey.p + 2 * d,
+                           (int64_t)4 * d, 0xffffffffu, 0u, d);
         PG_LAUNCH_CHECK();
-    } else {
-        // every point starts at the root; the level loop writes every split
-        // (and dimension) of nodes 1 .. 2^L - 1, node 0 is unused
-        uint32_t* nid = lf.as<uint32_t>();
-        PG_HIP(hipMemsetAsync(nid, 0, sizeof(uint32_t) * n, s));
-        PG_HIP(hipMemsetAsync(T->split, 0, sizeof(uint32_t) * leaves, s));
-        if (T->sdim) PG_HIP(hipMemsetAsync(T->sdim, 0, leaves, s));
-        const int64_t jmax = L > 0 ? leaves / 2 : 1;
-        DevBuf bmin(s), bmax(s), ns(s), nd(s);
-        PG_TRY(bmin.alloc(sizeof(uint32_t) * jmax * d));
-        PG_TRY(bmax.alloc(sizeof(uint32_t) * jmax * d));
-        PG_TRY(ns.alloc(sizeof(double) * jmax));
-        PG_TRY(nd.alloc(sizeof(uint8_t) * jmax));
-        constexpr int64_t kLdsBoxWords = 4096;  // J * d of a level reduced in LDS (32 KB)
-        for (int l = 0; l < L; l++) {
-            const int64_t J = (int64_t)1 << l;
-            const int64_t Jd = J * d;
-            hipLaunchKernelGGL(pbox_fill_kernel, dim3(cdiv(Jd, kNT)), dim3(kNT), 0, s,
-                               bmin.as<uint32_t>(), bmax.as<uint32_t>(), Jd);
-            PG_LAUNCH_CHECK();
-            const int lds = Jd <= kLdsBoxWords ? 1 : 0;
-            const unsigned cap = lds ? 512u : 1024u;
-            const unsigned grid = cdiv(n, kNT) < cap ? cdiv(n, kNT) : cap;
-            const size_t lds_bytes = lds ? sizeof(uint32_t) * 2 * (size_t)Jd
-                                         : sizeof(uint32_t) * (size_t)kBoxSlots * (1 + 2 * d);
-            hipLaunchKernelGGL(pbox_reduce_kernel, dim3(grid), dim3(kNT), lds_bytes, s,
-                               keys.as<uint32_t>(),
-                               nid, n, d, J, lds, bmin.as<uint32_t>(), bmax.as<uint32_t>());
-            PG_LAUNCH_CHECK();
-            hipLaunchKernelGGL(pbox_split_kernel, dim3(cdiv(J, kNT)), dim3(kNT), 0, s,
-                               bmin.as<uint32_t>(), bmax.as<uint32_t>(), J, l, d, fl ? 1 : 0, widest,
-                               T->split + J, T->sdim ? T->sdim + J : nullptr, ns.as<double>(),
-                               nd.as<uint8_t>());
-            PG_LAUNCH_CHECK();
-            hipLaunchKernelGGL(pbox_step_kernel, dim3(cdiv(n, kNT)), dim3(kNT), 0, s,
-                               keys.as<uint32_t>(), nid, n, fl ? 1 : 0, ns.as<double>(),
-                               nd.as<uint8_t>());
-            PG_LAUNCH_CHECK();
+    }
+    uint32_t h[3] = {0, 0, 0};
+    PG_HIP(hipMemcpyAsync(h, tot32, sizeof(uint32_t) * 2, hipMemcpyDeviceToHost, s));
+    PG_HIP(hipMemcpyAsync(h + 2, cst[0] + 1, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    PG_HIP(hipStreamSynchronize(s));
+    uint32_t As = h[0], Ac = h[1], C = h[2];
+
+    uint32_t* kcur = ka.as<uint32_t>();
+    int32_t* icur = ia.as<int32_t>();
+    uint32_t* knext = kb.as<uint32_t>();
+    int32_t* inext = ib.as<int32_t>();
+    int64_t nodes = 1, leaves = As == 0 ? 1 : 0;
+    T->lvl.assign(1, 0);
+    T->lvl.push_back(1);
+    int depth = 0;  // depth of the current entries' nodes
+    int cur = 0;
+    while (As + Ac > 0) {
+        const uint32_t A = As + Ac;
+        // node arrays: this level's children and the next level's box resets
+        const size_t need = (size_t)nodes + 6 * (size_t)As + 2;
+        PG_TRY(gxn.reserve(need, nodes));
+        PG_TRY(gkey.reserve(need * 2 * d, (nodes + 2 * (size_t)As) * 2 * d));
+        PG_TRY(glo.reserve(need, nodes));
+        PG_TRY(gcnt.reserve(need, nodes));
+        N = Nodes{gxn.p, gkey.p, glo.p, gcnt.p};
+        const Entries& E = ent[cur];
+        const Entries& X = ent[cur ^ 1];
+        const unsigned cgrid = cdiv(C, kNT / kWave);
+        hipLaunchKernelGGL(chunk_count_kernel, dim3(cgrid), dim3(kNT), 0, s, E, cst[cur], A, C, kcur,
+                           n, c2e, lcnt);
+        PG_LAUNCH_CHECK();
+        PG_TRY(exclusive_scan_u32(lcnt, lcnt, (int64_t)C + 1, nullptr, s));
+        const uint32_t nbase = (uint32_t)nodes;
+        switch (d) {
+            case 1: launch_scatter<1>(cgrid, s, E, N, cst[cur], lcnt, c2e, C, nbase, leaf, d, rw, ifl, kcur, icur, knext, inext, n, T); break;
+            case 2: launch_scatter<2>(cgrid, s, E, N, cst[cur], lcnt, c2e, C, nbase, leaf, d, rw, ifl, kcur, icur, knext, inext, n, T); break;
+            case 3: launch_scatter<3>(cgrid, s, E, N, cst[cur], lcnt, c2e, C, nbase, leaf, d, rw, ifl, kcur, icur, knext, inext, n, T); break;
+            case 4: launch_scatter<4>(cgrid, s, E, N, cst[cur], lcnt, c2e, C, nbase, leaf, d, rw, ifl, kcur, icur, knext, inext, n, T); break;
+            case 5: launch_scatter<5>(cgrid, s, E, N, cst[cur], lcnt, c2e, C, nbase, leaf, d, rw, ifl, kcur, icur, knext, inext, n, T); break;
+            default: launch_scatter<8>(cgrid, s, E, N, cst[cur], lcnt, c2e, C, nbase, leaf, d, rw, ifl, kcur, icur, knext, inext, n, T); break;
         }
-        hipLaunchKernelGGL(pbox_rank_kernel, dim3(cdiv(n, kNT)), dim3(kNT), 0, s, nid, n,
-                           rk.as<uint32_t>(), cnt.as<uint32_t>(), bbase.as<uint32_t>());
+        PG_LAUNCH_CHECK();
+        if (As == 0) break;  // copies only: nothing below
+        hipLaunchKernelGGL(split_nodes_kernel, dim3(cdiv(As, kNT)), dim3(kNT), 0, s, E, N, cst[cur],
+                           lcnt, As, nbase, leaf, d, ifl, flags, cst[cur ^ 1]);
+        PG_LAUNCH_CHECK();
+        PG_TRY(exclusive_scan_u64(flags, fpre, 2 * (int64_t)As, ftot, s));
+        const uint32_t nbase_next = nbase + 2 * As;
+        hipLaunchKernelGGL(emit_kernel, dim3(cdiv(2 * (int64_t)As, kNT)), dim3(kNT), 0, s, E, X, N,
+                           flags, fpre, ftot, As, nbase, nbase_next, depth + 1, d, ifl, rule,
+                           cst[cur ^ 1]);
+        PG_LAUNCH_CHECK();
+        // chunk starts of the next level (entries past its count hold 0)
+        PG_TRY(exclusive_scan_u32(cst[cur ^ 1], cst[cur ^ 1], 2 * (int64_t)As, cst[cur ^ 1] + 2 * As, s));
+        uint64_t ft = 0;
+        PG_HIP(hipMemcpyAsync(&ft, ftot, sizeof(ft), hipMemcpyDeviceToHost, s));
+        PG_HIP(hipMemcpyAsync(&C, cst[cur ^ 1] + 2 * As, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        PG_HIP(hipStreamSynchronize(s));
+        const uint32_t As2 = (uint32_t)ft, Ac2 = (uint32_t)(ft >> 32);
+        nodes += 2 * (int64_t)As;
+        leaves += 2 * (int64_t)As - As2;
+        T->lvl.push_back(nodes);
+        depth++;
+        As = As2;
+        Ac = Ac2;
+        cur ^= 1;
+        std::swap(kcur, knext);
+        std::swap(icur, inext);
+    }
+    const int levels = (int)T->lvl.size() - 1;
+    T->L = levels;
+    T->nnodes = nodes;
+    T->nleaves = leaves;
+
+    // leaf order: subtree leaf counts bottom-up, then spans top-down
+    DevBuf lv(s);
+    PG_TRY(lv.alloc(sizeof(uint32_t) * 2 * (size_t)nodes));
+    uint32_t* nlv = lv.as<uint32_t>();
+    uint32_t* jlo = nlv + nodes;
+    for (int l = levels - 1; l >= 0; l--) {
+        const uint32_t first = (uint32_t)T->lvl[l], count = (uint32_t)(T->lvl[l + 1] - T->lvl[l]);
+        hipLaunchKernelGGL(leaf_count_kernel, dim3(cdiv(count, kNT)), dim3(kNT), 0, s, gxn.p, first,
+                           count, nlv);
         PG_LAUNCH_CHECK();
     }
-    hipLaunchKernelGGL(leaf_rank_fix_kernel, dim3(cdiv(n, kNT)), dim3(kNT), 0, s, lf.as<uint32_t>(),
-                       n, bbase.as<uint32_t>(), rk.as<uint32_t>());
-    PG_LAUNCH_CHECK();
-    PG_TRY(exclusive_scan_u32(cnt.as<uint32_t>(), start.as<uint32_t>(), leaves, nullptr, s));
-    hipLaunchKernelGGL(spatial_offsets_kernel, dim3(cdiv(leaves + 1, kNT)), dim3(kNT), 0, s,
-                       start.as<uint32_t>(), leaves, n, T->loff);
-    PG_LAUNCH_CHECK();
-    hipLaunchKernelGGL(spatial_scatter_kernel, dim3(cdiv(n, kNT)), dim3(kNT), 0, s,
-                       keys.as<uint32_t>(), idx.as<int32_t>(), n, d, rw, fl ? 1 : 0,
-                       lf.as<uint32_t>(), rk.as<uint32_t>(), start.as<uint32_t>(), T->pts, T->rec,
-                       T->pidx);
-    PG_LAUNCH_CHECK();
-    if (!point_box) {
-        hipLaunchKernelGGL(spatial_split_kernel, dim3(cdiv(leaves, kNT)), dim3(kNT), 0, s, d, L,
-                           fl ? 1 : 0, widest, box.as<uint32_t>(), T->split, T->sdim);
+    PG_TRY(dalloc(&T->xspan, (size_t)nodes, s));
+    PG_TRY(dalloc(&T->loff, (size_t)leaves + 1, s));
+    PG_TRY(dalloc(&T->lnode, (size_t)leaves, s));
+    for (int l = 0; l < levels; l++) {
+        const uint32_t first = (uint32_t)T->lvl[l], count = (uint32_t)(T->lvl[l + 1] - T->lvl[l]);
+        hipLaunchKernelGGL(leaf_index_kernel, dim3(cdiv(count, kNT)), dim3(kNT), 0, s, gxn.p, first,
+                           count, nlv, jlo, glo.p, T->xspan, T->loff, T->lnode);
         PG_LAUNCH_CHECK();
     }
-    return offset_boxes(T, s);
+    hipLaunchKernelGGL(set_i64_kernel, dim3(1), dim3(64), 0, s, T->loff + leaves, n);
+    PG_LAUNCH_CHECK();
+    PG_TRY(dalloc(&T->nbox, (size_t)nodes * 2 * d, s));
+    hipLaunchKernelGGL(node_box_kernel, dim3(cdiv(nodes * 2 * d, kNT)), dim3(kNT), 0, s, gkey.p,
+                       gcnt.p, nodes, d, ifl, T->nbox);
+    PG_LAUNCH_CHECK();
+    T->xn = gxn.release();
+    return PG_OK;
 }
 
 }  // namespace pg

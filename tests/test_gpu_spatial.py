@@ -1,7 +1,7 @@
 """GPU parity of the spatial-median kd-tree (pg_kdtree_build_spatial) against
-the oracle's: split values, leaf offsets and leaf membership identical; k-NN
-(queries, all points, graph) and range search on it exact against the
-definitions."""
+the oracle's: every node (cut value and dimension, children, leaf-order
+range, depth) and the leaf-order row permutation identical; k-NN (queries,
+all points, graph) and range search on it exact against the definitions."""
 import numpy as np
 import pytest
 
@@ -30,22 +30,29 @@ def host(*ts):
     return [t.cpu().numpy() for t in ts]
 
 
-def membership(perm, loff):
-    leaf = np.repeat(np.arange(len(loff) - 1, dtype=np.int64), np.diff(loff))
-    return np.sort(leaf * max(len(perm), 1) + perm.astype(np.int64))
-
-
 def check_tree(pg, dev, pts, leaf, rule="cycle", space="cell"):
     t = pg.kdtree_build(to_dev(pts, dev), leaf=leaf, split="spatial", dim_rule=rule, space=space)
-    L, s, dims, perm, loff = oracle.spatial_tree(pts, leaf=leaf, rule=rule, space=space)
-    assert t.levels == L
-    gs, gperm = t.export()
-    gloff = t.offsets()
-    assert np.array_equal(gloff, loff), "leaf offsets differ"
-    assert np.array_equal(gs.astype(np.float64), s[1:]), "split values differ"
-    assert np.array_equal(t.split_dims()[1:].astype(np.int32), dims[1:]), "split dimensions differ"
-    assert np.array_equal(membership(gperm, gloff), membership(perm, loff)), "leaf membership differs"
+    o = oracle.spatial_tree(pts, leaf=leaf, rule=rule, space=space)
+    g = t.nodes()
+    assert t.levels == o.depth, "depth differs"
+    assert len(g["dim"]) == o.nodes, "node count differs"
+    for key in ("dim", "child", "lo", "hi", "level"):
+        assert np.array_equal(g[key], getattr(o, key)), f"node {key} differs"
+    assert np.array_equal(g["split"].astype(np.float64), o.split), "cut values differ"
+    assert np.array_equal(g["perm"].astype(np.int64), o.perm), "leaf-order rows differ"
+    # leaf offsets: the leaves' ranges in leaf order
+    loff = t.offsets()
+    leaves = np.nonzero(g["child"] < 0)[0]
+    assert len(loff) == len(leaves) + 1 and loff[0] == 0 and loff[-1] == len(pts)
+    assert np.all(np.diff(loff) >= 0)
+    assert np.array_equal(np.sort(g["lo"][leaves]), loff[:-1])
     return t
+
+
+def leaf_sizes(t):
+    g = t.nodes()
+    lv = g["child"] < 0
+    return g["hi"][lv] - g["lo"][lv]
 
 
 def check_knn(t, pts, q, k, dev):
@@ -87,8 +94,7 @@ def test_spatial_tree_and_knn(pg, dev, n, d, leaf, dtype, span):
 def test_spatial_clustered_and_duplicates(pg, dev):
     f, q = datagen.clustered(30_000, 5, seed=3, n_queries=2_000, query_seed=33)
     t = check_tree(pg, dev, f, 16)
-    sizes = np.diff(t.offsets())
-    assert sizes.max() > 16  # spatial cuts leave dense leaves
+    assert leaf_sizes(t).max() <= 16  # split down to the leaf size
     check_knn(t, f, q, 5, dev)
     same = np.full((500, 2), 3, dtype=np.int32)
     t = check_tree(pg, dev, same, 4)
@@ -139,7 +145,8 @@ def test_spatial_widest_rule(pg, dev, n, d, leaf, dtype):
         pts = ((rng.standard_normal((n, d)) ** 3) * scale).astype(np.float32)
     say(f"spatial widest n={n} d={d} leaf={leaf} {np.dtype(dtype).name}")
     t = check_tree(pg, dev, pts, leaf, rule="widest")
-    assert len(set(t.split_dims()[1:].tolist())) > 1
+    dims = t.nodes()["dim"]
+    assert len(set(dims[dims >= 0].tolist())) > 1
     check_knn(t, pts, None, 8, dev)
     q = pts[rng.integers(0, n, 5_000)]
     check_knn(t, pts, q, 5, dev)
@@ -208,17 +215,16 @@ def test_point_box_small_empty_and_same(pg, dev):
     check_knn(t, same, None, 3, dev)
 
 
-def test_point_box_clustered_full_size(pg, dev):
-    """The 5-D clustered workload (10M float32 points, 1,000 clusters) with
-    point-box cuts: the whole tree against the oracle's, leaves far smaller
-    than with cell halving, sampled queries against the definition."""
+@pytest.mark.parametrize("space", ["points", "cell"])
+def test_clustered_full_size(pg, dev, space):
+    """The 5-D clustered workload (10M float32 points, 1,000 clusters, 1M
+    queries): the whole tree against the oracle's, every leaf at most 16
+    points, sampled queries against the definition."""
     pts, q = datagen.clustered(10_000_000, 5, seed=3, n_queries=1_000_000, query_seed=33)
-    say("point-box clustered 10M: build")
-    t = check_tree(pg, dev, pts, 16, space="points")
-    cell = pg.kdtree_build(to_dev(pts, dev), leaf=16, split="spatial")
-    assert 4 * np.diff(t.offsets()).max() < np.diff(cell.offsets()).max()
-    del cell
-    rows = np.random.default_rng(5).choice(len(q), 200, replace=False)
-    gi, gd = host(*t.knn(to_dev(q[rows], dev), 5))
+    say(f"clustered 10M, {space} boxes: build")
+    t = check_tree(pg, dev, pts, 16, space=space)
+    assert leaf_sizes(t).max() <= 16
+    rows = np.random.default_rng(5).choice(len(q), 300, replace=False)
+    gi, gd = host(*t.knn(to_dev(q, dev), 5))
     oi, od = oracle.knn_brute(pts, q[rows], 5, nthreads=16)
-    assert_float_close(gi, gd, oi, od, pts, q[rows])
+    assert_float_close(gi[rows], gd[rows], oi, od, pts, q[rows])
