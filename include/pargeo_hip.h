@@ -156,6 +156,17 @@ pg_status pg_tree_offsets(const pg_tree* t, int64_t* loff_host, void* stream);
 pg_status pg_knn(const pg_tree* t, const void* queries, int64_t m, int32_t k,
                  int32_t* out_idx, void* out_dist, void* stream);
 
+/* pg_knn for callers that cannot allocate device memory (code under stream
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * arguments, results and range check (it synchronises), with every temporary
+ * taken from a 64 MiB device array the library holds on each GPU it runs on
+ * until the process ends, instead of from the allocator.
+ *   m : 0 <= m <= 2^22 (4,194,304); larger m is PG_ERR_INVALID, nothing runs
+ * Calls share that array on a GPU: calls that overlap on one GPU (other
+ * streams, other threads) race and must be serialised by the caller. */
+pg_status pg_knn_noalloc(const pg_tree* t, const void* queries, int64_t m, int32_t k,
+                         int32_t* out_idx, void* out_dist, void* stream);
+
 /* All-points k-NN: the queries are the tree's own n points (each point is
  * its own first neighbour unless an identical point has a smaller row).
  * Output row i belongs to input row i.  Does not synchronise. */

@@ -53,6 +53,7 @@ SIGNATURES = {
     "pg_tree_split_dims": (i32, [vp, vp, vp]),
     "pg_tree_offsets": (i32, [vp, vp, vp]),
     "pg_knn": (i32, [vp, vp, i64, i32, vp, vp, vp]),
+    "pg_knn_noalloc": (i32, [vp, vp, i64, i32, vp, vp, vp]),
     "pg_knn_all": (i32, [vp, i32, vp, vp, vp]),
     "pg_knn_graph": (i32, [vp, i32, vp, vp, vp]),
     "pg_tree_info": (i32, [vp, P64, P32, P32, P32, P32]),
@@ -185,6 +186,24 @@ class KdTree:
         check(lib().pg_knn(self._h, ctypes.c_void_p(q.data_ptr()), m, k,
                            ctypes.c_void_p(idx.data_ptr()), ctypes.c_void_p(dist.data_ptr()),
                            stream_ptr(q.device)))
+        return idx, dist
+
+    def knn_noalloc(self, queries: torch.Tensor, k: int, out):
+        """As :meth:`knn`, through pg_knn_noalloc, into the caller's tensors
+        out = (idx int32 [m][k], dist [m][k]); the library allocates no
+        device memory (m <= 2^22)."""
+        q = _points(queries, "queries")
+        if _dtype_code(q) != self.dtype_code:
+            raise TypeError("queries must have the tree's dtype")
+        idx, dist = out
+        m = q.shape[0]
+        if (tuple(idx.shape) != (m, k) or tuple(dist.shape) != (m, k) or idx.dtype != torch.int32
+                or dist.dtype != _dist_dtype(self.dtype_code) or not idx.is_contiguous()
+                or not dist.is_contiguous()):
+            raise ValueError("out must be contiguous (int32 [m][k], distance dtype [m][k])")
+        check(lib().pg_knn_noalloc(self._h, ctypes.c_void_p(q.data_ptr()), m, k,
+                                   ctypes.c_void_p(idx.data_ptr()), ctypes.c_void_p(dist.data_ptr()),
+                                   stream_ptr(q.device)))
         return idx, dist
 
     def knn_all(self, k: int, out=None):

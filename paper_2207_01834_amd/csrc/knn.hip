@@ -108,25 +108,30 @@ __global__ void check_queries_kernel(const uint32_t* __restrict__ q, int64_t cou
 
 }  // namespace
 
-pg_status check_queries(const void* q, int64_t m, int d, bool fl, hipStream_t s) {
+pg_status check_queries_ws(const void* q, int64_t m, int d, bool fl, uint32_t* err, hipStream_t s) {
     if (m == 0) return PG_OK;
-    DevBuf err(s);
-    PG_TRY(err.alloc(sizeof(uint32_t)));
-    PG_HIP(hipMemsetAsync(err.p, 0, sizeof(uint32_t), s));
+    PG_TRY(fill_u32(err, 1, 0u, s));
     const int64_t count = m * d;
     hipLaunchKernelGGL(check_queries_kernel, dim3(cdiv(count, kNT)), dim3(kNT), 0, s,
-                       (const uint32_t*)q, count, fl ? 1 : 0, err.as<uint32_t>());
+                       (const uint32_t*)q, count, fl ? 1 : 0, err);
     PG_LAUNCH_CHECK();
     uint32_t h = 0;
-    PG_HIP(hipMemcpyAsync(&h, err.p, sizeof(h), hipMemcpyDeviceToHost, s));
+    PG_HIP(hipMemcpyAsync(&h, err, sizeof(h), hipMemcpyDeviceToHost, s));
     PG_HIP(hipStreamSynchronize(s));
     if (h) return fail(PG_ERR_RANGE, "query coordinate out of range (int32: [-2^29, 2^29); float32: finite, |x| <= 1e18)");
     return PG_OK;
 }
 
-pg_status order_queries(const TreeView& tv, bool fl, const void* queries, int64_t m,
-                        hipStream_t s, DevBuf& order, bool boxes) {
-    // buckets: the leaves, coarsened to about one bucket per 4 queries
+pg_status check_queries(const void* q, int64_t m, int d, bool fl, hipStream_t s) {
+    if (m == 0) return PG_OK;
+    DevBuf err(s);
+    PG_TRY(err.alloc(sizeof(uint32_t)));
+    return check_queries_ws(q, m, d, fl, err.as<uint32_t>(), s);
+}
+
+// Bucket shift and count of the query ordering: the leaves, coarsened to
+// about one bucket per 4 queries.
+static void bucket_plan(const TreeView& tv, int64_t m, int* shift_out, int64_t* nb_out) {
     int bits = 0;
     while (bits < 24 && ((int64_t)1 << (bits + 1)) * 4 <= m) bits++;
     int lbits = tv.L;  // leaves < 2^lbits
@@ -135,16 +140,41 @@ pg_status order_queries(const TreeView& tv, bool fl, const void* queries, int64_
         while (((int64_t)1 << lbits) < tv.nleaves) lbits++;
     }
     const int shift = lbits > bits ? lbits - bits : 0;
-    const int64_t nb = tv.xn ? ((tv.nleaves + ((int64_t)1 << shift) - 1) >> shift)
-                             : (((int64_t)1 << tv.L) >> shift);
-    // one temporary: the queries' bucket keys, then the bucket counts (which
-    // the scan turns, in place, into each bucket's next free slot)
+    *shift_out = shift;
+    *nb_out = tv.xn ? ((tv.nleaves + ((int64_t)1 << shift) - 1) >> shift)
+                    : (((int64_t)1 << tv.L) >> shift);
+}
+
+int64_t order_buckets(const TreeView& tv, int64_t m) {
+    int shift;
+    int64_t nb;
+    bucket_plan(tv, m, &shift, &nb);
+    return nb;
+}
+
+pg_status order_queries(const TreeView& tv, bool fl, const void* queries, int64_t m,
+                        hipStream_t s, DevBuf& order, bool boxes) {
+    // one temporary: the queries' bucket keys, then the bucket counts, then
+    // the scan's partial sums
+    const int64_t nb = order_buckets(tv, m);
     DevBuf work(s);
-    PG_TRY(work.alloc(sizeof(uint32_t) * (m + nb)));
-    uint32_t* key = work.as<uint32_t>();
-    uint32_t* cnt = key + m;
+    PG_TRY(work.alloc(sizeof(uint32_t) * (m + nb + scan_partials(nb))));
     PG_TRY(order.alloc(sizeof(int32_t) * m));
-    PG_HIP(hipMemsetAsync(cnt, 0, sizeof(uint32_t) * nb, s));
+    return order_queries_ws(tv, fl, queries, m, s, order.as<int32_t>(), work.as<uint32_t>(),
+                            work.as<uint32_t>() + m + nb, boxes);
+}
+
+pg_status order_queries_ws(const TreeView& tv, bool fl, const void* queries, int64_t m,
+                           hipStream_t s, int32_t* order, uint32_t* work, uint32_t* sums,
+                           bool boxes) {
+    int shift;
+    int64_t nb;
+    bucket_plan(tv, m, &shift, &nb);
+    // the queries' bucket keys, then the bucket counts (which the scan turns,
+    // in place, into each bucket's next free slot)
+    uint32_t* key = work;
+    uint32_t* cnt = key + m;
+    PG_TRY(fill_u32(cnt, nb, 0u, s));
     if (tv.xn)
         hipLaunchKernelGGL(query_xleaf_kernel, dim3(cdiv(m, kNT)), dim3(kNT), 0, s, tv, fl ? 1 : 0,
                            (const uint32_t*)queries, m, shift, boxes ? 1 : 0, key);
@@ -154,24 +184,30 @@ pg_status order_queries(const TreeView& tv, bool fl, const void* queries, int64_
     PG_LAUNCH_CHECK();
     hipLaunchKernelGGL(bucket_count_kernel, dim3(cdiv(m, kNT)), dim3(kNT), 0, s, key, m, cnt);
     PG_LAUNCH_CHECK();
-    PG_TRY(exclusive_scan_u32(cnt, cnt, nb, nullptr, s));
-    hipLaunchKernelGGL(bucket_fill_kernel, dim3(cdiv(m, kNT)), dim3(kNT), 0, s, key, m, cnt,
-                       order.as<int32_t>());
+    PG_TRY(exclusive_scan_u32_ws(cnt, cnt, nb, nullptr, sums, s));
+    hipLaunchKernelGGL(bucket_fill_kernel, dim3(cdiv(m, kNT)), dim3(kNT), 0, s, key, m, cnt, order);
     PG_LAUNCH_CHECK();
     return PG_OK;
 }
 
 pg_status knn_static(const pg_tree* t, const void* queries, int64_t m, int k, bool all,
-                     int32_t* out_idx, void* out_dist, hipStream_t s, bool no_self) {
+                     int32_t* out_idx, void* out_dist, hipStream_t s, bool no_self, const KnnWs* ws) {
     if (m == 0) return PG_OK;
     DevBuf order(s);
     const int32_t* o = nullptr;
     if (!all && m >= kOrderMin && t->n > 0) {
-        PG_TRY(order_queries(t->view(), t->dtype == PG_FLOAT32, queries, m, s, order));
-        o = order.as<int32_t>();
+        if (ws) {
+            PG_TRY(order_queries_ws(t->view(), t->dtype == PG_FLOAT32, queries, m, s, ws->order,
+                                    ws->work, ws->sums));
+            o = ws->order;
+        } else {
+            PG_TRY(order_queries(t->view(), t->dtype == PG_FLOAT32, queries, m, s, order));
+            o = order.as<int32_t>();
+        }
     }
-    if (t->dtype == PG_FLOAT32) return knn_static_float(t, queries, o, m, k, all, out_idx, out_dist, s, no_self);
-    return knn_static_int(t, queries, o, m, k, all, out_idx, out_dist, s, no_self);
+    if (t->dtype == PG_FLOAT32)
+        return knn_static_float(t, queries, o, m, k, all, out_idx, out_dist, s, no_self, ws);
+    return knn_static_int(t, queries, o, m, k, all, out_idx, out_dist, s, no_self, ws);
 }
 
 }  // namespace pg

@@ -226,26 +226,46 @@ inline int id_bits(int64_t n) {
 // Queries below this count are searched in the caller's order.
 constexpr int64_t kOrderMin = 4096;
 
+// Device workspace of one separate-query k-NN call, for callers that bring
+// their own memory (null members are allocated by the call).
+struct KnnWs {
+    int32_t* order;   // [m] query permutation
+    uint32_t* work;   // [m + buckets] bucket keys, then bucket counts
+    uint32_t* sums;   // [scan_partials(buckets)] partial sums of the bucket scan
+    int32_t* redo;    // [m] queries searched again with exact pairs (int32 trees)
+    uint32_t* nredo;  // [1] their count
+};
+
+// Buckets the query ordering uses for m queries over tree tv.
+int64_t order_buckets(const TreeView& tv, int64_t m);
+
 // A permutation of the m queries that follows the leaf order of tree tv (a
 // counting sort by the leaf each query's descent reaches); order receives
 // m int32 query indices.  With `boxes` the queries are boxes [m][2][d]
 // (lo, hi) and each descends by its centre.
 pg_status order_queries(const TreeView& tv, bool fl, const void* queries, int64_t m,
                         hipStream_t s, DevBuf& order, bool boxes = false);
+// The same into caller workspace (order [m], work [m + buckets], sums).
+pg_status order_queries_ws(const TreeView& tv, bool fl, const void* queries, int64_t m,
+                           hipStream_t s, int32_t* order, uint32_t* work, uint32_t* sums,
+                           bool boxes = false);
 // no_self (all-points only): each point's own row is not a candidate.
 pg_status knn_static(const pg_tree* t, const void* queries, int64_t m, int k, bool all_points,
-                     int32_t* out_idx, void* out_dist, hipStream_t s, bool no_self = false);
+                     int32_t* out_idx, void* out_dist, hipStream_t s, bool no_self = false,
+                     const KnnWs* ws = nullptr);
 
 // The static-tree k-NN launch for one coordinate type (order: the query
 // permutation or null; no_self: all-points without each point's own row).
 pg_status knn_static_int(const pg_tree* t, const void* queries, const int32_t* order, int64_t m,
                          int k, bool all, int32_t* out_idx, void* out_dist, hipStream_t s,
-                         bool no_self);
+                         bool no_self, const KnnWs* ws);
 pg_status knn_static_float(const pg_tree* t, const void* queries, const int32_t* order, int64_t m,
                            int k, bool all, int32_t* out_idx, void* out_dist, hipStream_t s,
-                           bool no_self);
+                           bool no_self, const KnnWs* ws);
 
 // Validates query coordinates (range / finite); synchronises.
 pg_status check_queries(const void* q, int64_t m, int d, bool fl, hipStream_t s);
+// The same with a caller-provided device flag word.
+pg_status check_queries_ws(const void* q, int64_t m, int d, bool fl, uint32_t* err, hipStream_t s);
 
 }  // namespace pg

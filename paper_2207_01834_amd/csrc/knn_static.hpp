@@ -99,24 +99,32 @@ constexpr unsigned kRedoBlocks = 512;
 
 template <typename T, int MD, int KT, bool EX, bool NS, int TK>
 pg_status launch_static(const pg_tree* t, const void* queries, const int32_t* order, int64_t m,
-                        int k, bool all, int32_t* out_idx, void* out_dist, hipStream_t s) {
+                        int k, bool all, int32_t* out_idx, void* out_dist, hipStream_t s,
+                        const KnnWs* ws) {
     using DT = typename Metric<T>::D;
     constexpr bool exact = PackedList<T, KT, EX>::kFloat;  // float keys: no redo pass
-    DevBuf redo(s), nredo(s);
+    DevBuf rbuf(s);
+    int32_t* redo = nullptr;
+    uint32_t* nredo = nullptr;
     if (!exact) {
-        PG_TRY(redo.alloc(sizeof(int32_t) * m));
-        PG_TRY(nredo.alloc(sizeof(uint32_t)));
-        PG_HIP(hipMemsetAsync(nredo.p, 0, sizeof(uint32_t), s));
+        if (ws) {
+            redo = ws->redo;
+            nredo = ws->nredo;
+        } else {
+            PG_TRY(rbuf.alloc(sizeof(int32_t) * (m + 1)));
+            nredo = rbuf.as<uint32_t>();
+            redo = rbuf.as<int32_t>() + 1;
+        }
+        PG_TRY(fill_u32(nredo, 1, 0u, s));
     }
     hipLaunchKernelGGL((knn_static_kernel<T, MD, KT, EX, NS, TK>), dim3(grid_for_xcd(cdiv(m, kNT))),
                        dim3(kNT), 0, s, t->view(), (const uint32_t*)queries, order, m, k,
-                       all ? 1 : 0, id_bits(t->n), out_idx, (DT*)out_dist, redo.as<int32_t>(),
-                       nredo.as<uint32_t>());
+                       all ? 1 : 0, id_bits(t->n), out_idx, (DT*)out_dist, redo, nredo);
     PG_LAUNCH_CHECK();
     if (!exact) {
         hipLaunchKernelGGL((knn_redo_kernel<T, MD, KT, EX, NS, TK>), dim3(kRedoBlocks), dim3(kNT), 0, s,
-                           t->view(), (const uint32_t*)queries, k, all ? 1 : 0,
-                           redo.as<int32_t>(), nredo.as<uint32_t>(), out_idx, (DT*)out_dist);
+                           t->view(), (const uint32_t*)queries, k, all ? 1 : 0, redo, nredo, out_idx,
+                           (DT*)out_dist);
         PG_LAUNCH_CHECK();
     }
     return PG_OK;
@@ -126,26 +134,26 @@ pg_status launch_static(const pg_tree* t, const void* queries, const int32_t* or
 // next power of two with uniform guards.
 template <typename T, int MD, bool NS, int TK>
 pg_status dispatch_k(const pg_tree* t, const void* q, const int32_t* o, int64_t m, int k, bool all,
-                     int32_t* oi, void* od, hipStream_t s) {
-    if (k == 5) return launch_static<T, MD, 5, true, NS, TK>(t, q, o, m, k, all, oi, od, s);
-    if (k == 10) return launch_static<T, MD, 10, true, NS, TK>(t, q, o, m, k, all, oi, od, s);
-    if (k == 16) return launch_static<T, MD, 16, true, NS, TK>(t, q, o, m, k, all, oi, od, s);
-    if (k <= 2) return launch_static<T, MD, 2, false, NS, TK>(t, q, o, m, k, all, oi, od, s);
-    if (k <= 4) return launch_static<T, MD, 4, false, NS, TK>(t, q, o, m, k, all, oi, od, s);
-    if (k <= 8) return launch_static<T, MD, 8, false, NS, TK>(t, q, o, m, k, all, oi, od, s);
-    if (k <= 16) return launch_static<T, MD, 16, false, NS, TK>(t, q, o, m, k, all, oi, od, s);
-    if (k <= 32) return launch_static<T, MD, 32, false, NS, TK>(t, q, o, m, k, all, oi, od, s);
-    return launch_static<T, MD, 64, false, NS, TK>(t, q, o, m, k, all, oi, od, s);
+                     int32_t* oi, void* od, hipStream_t s, const KnnWs* ws) {
+    if (k == 5) return launch_static<T, MD, 5, true, NS, TK>(t, q, o, m, k, all, oi, od, s, ws);
+    if (k == 10) return launch_static<T, MD, 10, true, NS, TK>(t, q, o, m, k, all, oi, od, s, ws);
+    if (k == 16) return launch_static<T, MD, 16, true, NS, TK>(t, q, o, m, k, all, oi, od, s, ws);
+    if (k <= 2) return launch_static<T, MD, 2, false, NS, TK>(t, q, o, m, k, all, oi, od, s, ws);
+    if (k <= 4) return launch_static<T, MD, 4, false, NS, TK>(t, q, o, m, k, all, oi, od, s, ws);
+    if (k <= 8) return launch_static<T, MD, 8, false, NS, TK>(t, q, o, m, k, all, oi, od, s, ws);
+    if (k <= 16) return launch_static<T, MD, 16, false, NS, TK>(t, q, o, m, k, all, oi, od, s, ws);
+    if (k <= 32) return launch_static<T, MD, 32, false, NS, TK>(t, q, o, m, k, all, oi, od, s, ws);
+    return launch_static<T, MD, 64, false, NS, TK>(t, q, o, m, k, all, oi, od, s, ws);
 }
 
 template <typename T, bool NS, int TK>
 pg_status dispatch_d(const pg_tree* t, const void* q, const int32_t* o, int64_t m, int k, bool all,
-                     int32_t* oi, void* od, hipStream_t s) {
+                     int32_t* oi, void* od, hipStream_t s, const KnnWs* ws) {
     switch (t->d) {
-        case 2: return dispatch_k<T, 2, NS, TK>(t, q, o, m, k, all, oi, od, s);
-        case 3: return dispatch_k<T, 3, NS, TK>(t, q, o, m, k, all, oi, od, s);
-        case 5: return dispatch_k<T, 5, NS, TK>(t, q, o, m, k, all, oi, od, s);
-        default: return dispatch_k<T, 8, NS, TK>(t, q, o, m, k, all, oi, od, s);
+        case 2: return dispatch_k<T, 2, NS, TK>(t, q, o, m, k, all, oi, od, s, ws);
+        case 3: return dispatch_k<T, 3, NS, TK>(t, q, o, m, k, all, oi, od, s, ws);
+        case 5: return dispatch_k<T, 5, NS, TK>(t, q, o, m, k, all, oi, od, s, ws);
+        default: return dispatch_k<T, 8, NS, TK>(t, q, o, m, k, all, oi, od, s, ws);
     }
 }
 

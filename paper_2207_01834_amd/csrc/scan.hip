@@ -67,25 +67,49 @@ tile_scan_kernel(const IT* __restrict__ in, int64_t n, const AT* __restrict__ su
     }
 }
 
+// sums: scan_partials(n) entries of workspace.
 template <typename IT, typename AT>
-pg_status exclusive_scan(const IT* in, AT* out, int64_t n, AT* total, hipStream_t s) {
+pg_status exclusive_scan_ws(const IT* in, AT* out, int64_t n, AT* total, AT* sums, hipStream_t s) {
     if (n <= 0) return PG_OK;
     const int64_t tiles = (n + kTile - 1) / kTile;
-    DevBuf sums(s);
-    PG_TRY(sums.alloc(sizeof(AT) * tiles));
-    hipLaunchKernelGGL((tile_sum_kernel<IT, AT>), dim3((unsigned)tiles), dim3(kNT), 0, s, in, n,
-                       sums.as<AT>());
+    hipLaunchKernelGGL((tile_sum_kernel<IT, AT>), dim3((unsigned)tiles), dim3(kNT), 0, s, in, n, sums);
     PG_LAUNCH_CHECK();
-    hipLaunchKernelGGL((scan_sums_kernel<AT>), dim3(1), dim3(kNT), 0, s, sums.as<AT>(), tiles,
-                       total);
+    hipLaunchKernelGGL((scan_sums_kernel<AT>), dim3(1), dim3(kNT), 0, s, sums, tiles, total);
     PG_LAUNCH_CHECK();
-    hipLaunchKernelGGL((tile_scan_kernel<IT, AT>), dim3((unsigned)tiles), dim3(kNT), 0, s, in, n,
-                       sums.as<AT>(), out);
+    hipLaunchKernelGGL((tile_scan_kernel<IT, AT>), dim3((unsigned)tiles), dim3(kNT), 0, s, in, n, sums,
+                       out);
     PG_LAUNCH_CHECK();
     return PG_OK;
 }
 
+template <typename IT, typename AT>
+pg_status exclusive_scan(const IT* in, AT* out, int64_t n, AT* total, hipStream_t s) {
+    if (n <= 0) return PG_OK;
+    DevBuf sums(s);
+    PG_TRY(sums.alloc(sizeof(AT) * scan_partials(n)));
+    return exclusive_scan_ws<IT, AT>(in, out, n, total, sums.as<AT>(), s);
+}
+
+__global__ void fill_kernel(uint32_t* __restrict__ p, int64_t n, uint32_t v) {
+    const int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
 }  // namespace
+
+int64_t scan_partials(int64_t n) { return n > 0 ? (n + kTile - 1) / kTile : 1; }
+
+pg_status exclusive_scan_u32_ws(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total,
+                                uint32_t* sums, hipStream_t s) {
+    return exclusive_scan_ws<uint32_t, uint32_t>(in, out, n, total, sums, s);
+}
+
+pg_status fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s) {
+    if (n <= 0) return PG_OK;
+    hipLaunchKernelGGL(fill_kernel, dim3(cdiv(n, kNT)), dim3(kNT), 0, s, p, n, v);
+    PG_LAUNCH_CHECK();
+    return PG_OK;
+}
 
 pg_status exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total,
                              hipStream_t s) {
