@@ -205,10 +205,13 @@ class KdTree:
         j = np.arange((1 << L) + 1, dtype=object)
         return np.array([(int(x) * self.n) >> L for x in j], dtype=np.int64)
 
-    def knn(self, queries, k, ids=None, alive=None):
+    def knn(self, queries, k, ids=None, alive=None, nthreads=1):
         """Appendix C single-query search for every query; returns
         (ids, dist, counters) with counters = [internal nodes visited,
-        leaves added, points whose distance was computed] summed."""
+        leaves added, points whose distance was computed] summed.  With
+        nthreads > 1 the queries are searched in that many static chunks on
+        as many threads (each search is the same serial search; the C call
+        releases the interpreter lock), which changes no result."""
         queries = np.ascontiguousarray(queries, dtype=self.points.dtype)
         m = queries.shape[0]
         if ids is not None:
@@ -216,12 +219,23 @@ class KdTree:
         if alive is not None:
             alive = np.ascontiguousarray(alive, dtype=np.uint8)
         out_id, out_d = _outputs(m, k, self.dt)
-        counters = np.zeros(3, dtype=np.int64)
-        rc = lib().or_kd_knn(self._h, _ptr(ids), _ptr(alive), _ptr(queries), m, k,
-                             _ptr(out_id), _ptr(out_d), _ptr(counters))
-        if rc != 0:
+        nthreads = max(1, min(int(nthreads), m))
+        bounds = [m * t // nthreads for t in range(nthreads + 1)]
+        counters = np.zeros((nthreads, 3), dtype=np.int64)
+
+        def run(t):
+            a, b = bounds[t], bounds[t + 1]
+            return lib().or_kd_knn(self._h, _ptr(ids), _ptr(alive), _ptr(queries[a:b]), b - a, k,
+                                   _ptr(out_id[a:b]), _ptr(out_d[a:b]), _ptr(counters[t]))
+        if nthreads == 1:
+            rcs = [run(0)]
+        else:
+            from concurrent.futures import ThreadPoolExecutor
+            with ThreadPoolExecutor(nthreads) as ex:
+                rcs = list(ex.map(run, range(nthreads)))
+        if any(rc != 0 for rc in rcs):
             raise ValueError("or_kd_knn: bad arguments")
-        return out_id, out_d, counters
+        return out_id, out_d, counters.sum(axis=0)
 
     def range(self, boxes, ids=None, alive=None):
         """Range search on the tree (boxes inside the query report whole,

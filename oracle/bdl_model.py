@@ -61,29 +61,61 @@ def insert_plan(F: int, b: int, m: int, X: int):
                 to_buffer=r if not overflow else buffer_after)
 
 
+def _canonical_bits(a):
+    """The 32-bit patterns of the coordinates of a, -0.0 first made +0.0, so
+    that two rows are equal coordinate by coordinate exactly when their
+    patterns are."""
+    a = np.ascontiguousarray(a)
+    if a.dtype.kind == "f":
+        a = np.where(a == 0, np.zeros((), a.dtype), a)
+    return np.ascontiguousarray(a).view(np.uint32).reshape(a.shape)
+
+
+def rows_in(a, b):
+    """Boolean mask over the rows of a: the row equals some row of b."""
+    A, B = _canonical_bits(a), _canonical_bits(b)
+    d = A.shape[1]
+    if len(A) == 0 or len(B) == 0:
+        return np.zeros(len(A), dtype=bool)
+    # candidates by the first two coordinates (one 64-bit key), then the
+    # whole rows of the candidates as byte strings
+    def pre(x):
+        k = x[:, 0].astype(np.uint64) << np.uint64(32)
+        return k | x[:, 1].astype(np.uint64) if d > 1 else k
+    cand = np.isin(pre(A), pre(B))
+    if d <= 2:
+        return cand
+    whole = lambda x: np.ascontiguousarray(x).view(np.dtype((np.void, 4 * d))).ravel()
+    out = np.zeros(len(A), dtype=bool)
+    ci = np.nonzero(cand)[0]
+    out[ci] = np.isin(whole(A[ci]), whole(B))
+    return out
+
+
 class BDLModel:
     """Point-set model of the BDL-tree.  Point ids are a global insertion
-    counter starting at 0."""
+    counter starting at 0.  Trees and the buffer are id arrays in staging
+    order."""
 
     def __init__(self, d: int, X: int, dtype=np.int32):
         self.d, self.X, self.dtype = d, X, np.dtype(dtype)
         self.coords = np.zeros((0, d), dtype=self.dtype)  # indexed by id
         self.alive = np.zeros(0, dtype=bool)
-        self.trees: dict[int, list] = {}                 # i -> ids in staging order
-        self.buffer: list = []
+        self.trees: dict[int, np.ndarray] = {}           # i -> ids in staging order
+        self.buffer = np.zeros(0, dtype=np.int64)
         self.next_id = 0
 
     # -- state ------------------------------------------------------------
     def F(self) -> int:
         f = 0
         for i, ids in self.trees.items():
-            if ids:
+            if len(ids):
                 f |= 1 << i
         return f
 
     def tree_live(self, i: int) -> int:
-        ids = self.trees.get(i, [])
-        return int(np.count_nonzero(self.alive[np.asarray(ids, dtype=np.int64)])) if ids else 0
+        ids = self.trees.get(i)
+        return int(np.count_nonzero(self.alive[ids])) if ids is not None and len(ids) else 0
 
     def stats(self, max_trees: int = 64):
         live = [self.tree_live(i) for i in range(max_trees)]
@@ -97,7 +129,8 @@ class BDLModel:
         return self.coords[ids], ids
 
     # -- Algorithm 3 --------------------------------------------------------
-    def _insert_ids(self, S: list):
+    def _insert_ids(self, S):
+        S = np.asarray(S, dtype=np.int64)
         X = self.X
         F = self.F()
         plan = insert_plan(F, len(self.buffer), len(S), X)
@@ -105,11 +138,11 @@ class BDLModel:
         if plan["overflow"]:
             take = X - len(self.buffer)
             n_fresh = (m // X) * X + take
-            bound = list(self.buffer) + list(S[:n_fresh])
-            self.buffer = list(S[n_fresh:])
+            bound = np.concatenate([self.buffer, S[:n_fresh]])
+            self.buffer = S[n_fresh:].copy()
         else:
-            bound = list(S[:m - r])
-            self.buffer = self.buffer + list(S[m - r:])
+            bound = S[:m - r]
+            self.buffer = np.concatenate([self.buffer, S[m - r:]])
         if plan["A"] == 0:
             return plan
         pos = 0
@@ -117,15 +150,16 @@ class BDLModel:
         for j in sorted(plan["quota"]):
             members = []
             for i in sorted(plan["assign"].get(j, [])):
-                members += [t for t in self.trees[i] if self.alive[t]]
+                ids = self.trees[i]
+                members.append(ids[self.alive[ids]])
             q = plan["quota"][j]
-            members += bound[pos:pos + q]
+            members.append(bound[pos:pos + q])
             pos += q
-            new_trees[j] = members
+            new_trees[j] = np.concatenate(members)
         assert pos == len(bound)
         for i in range(F.bit_length()):
             if (plan["destroyed"] >> i) & 1:
-                self.trees[i] = []
+                self.trees[i] = np.zeros(0, dtype=np.int64)
         for j, members in new_trees.items():
             self.trees[j] = members
         return plan
@@ -137,7 +171,7 @@ class BDLModel:
         self.coords = np.concatenate([self.coords, pts])
         self.alive = np.concatenate([self.alive, np.ones(m, dtype=bool)])
         self.next_id += m
-        self._insert_ids(list(range(first, first + m)))
+        self._insert_ids(np.arange(first, first + m, dtype=np.int64))
         return first
 
     # -- Algorithm 4 --------------------------------------------------------
@@ -145,21 +179,19 @@ class BDLModel:
         pts = np.ascontiguousarray(pts, dtype=self.dtype).reshape(-1, self.d)
         if len(pts) == 0:
             return 0
-        want = {tuple(p) for p in pts.tolist()}
         live_ids = np.nonzero(self.alive)[0]
-        hit = [t for t, c in zip(live_ids.tolist(), self.coords[live_ids].tolist())
-               if tuple(c) in want]
-        self.alive[np.asarray(hit, dtype=np.int64)] = False
-        self.buffer = [t for t in self.buffer if self.alive[t]]
+        hit = live_ids[rows_in(self.coords[live_ids], pts)]
+        self.alive[hit] = False
+        self.buffer = self.buffer[self.alive[self.buffer]]
         R = []
         for i in sorted(self.trees):
             ids = self.trees[i]
-            if not ids:
+            if not len(ids):
                 continue
-            live_i = [t for t in ids if self.alive[t]]
+            live_i = ids[self.alive[ids]]
             if 2 * len(live_i) < self.X * (1 << i):
-                R += live_i
-                self.trees[i] = []
+                R.append(live_i)
+                self.trees[i] = np.zeros(0, dtype=np.int64)
         if R:
-            self._insert_ids(R)
+            self._insert_ids(np.concatenate(R))
         return len(hit)

@@ -94,3 +94,52 @@ def _loss_sets(P, ids, g):
         diff = P[i] - P[ids[i]]
         tot += float(np.sum(g[i] * np.sum(diff * diff, axis=1)))
     return tot
+
+
+def fd_self_incremental(points, k, g, h=1e-6):
+    """fd_self with the same results, computed incrementally: perturbing
+    point a changes only row and column a of the FP64 distance matrix, so
+    only the neighbour lists that hold a, or that a's new distance now
+    enters, are sorted again, and the loss is summed from the updated matrix.
+    The lists of every other row, and every other distance, are those of the
+    unperturbed points."""
+    P = np.asarray(points, dtype=np.float64)
+    n, d = P.shape
+    g = np.asarray(g, dtype=np.float64)
+    diff = P[:, None, :] - P[None, :, :]
+    D = np.sum(diff * diff, axis=2)
+    base = _lists(D, k)
+    rows = np.arange(n)[:, None]
+    kth_d = D[np.arange(n), base[:, k - 1]]
+    kth_id = base[:, k - 1]
+    holds = np.zeros((n, n), dtype=bool)
+    holds[rows, base] = True  # holds[i, a]: a is in row i's list
+    grad = np.zeros_like(P)
+    stable = np.ones_like(P, dtype=bool)
+    for a in range(n):
+        for c in range(d):
+            vals = []
+            for s in (+1.0, -1.0):
+                Pp = P.copy()
+                Pp[a, c] += s * h
+                da = Pp[a] - Pp
+                ra = np.sum(da * da, axis=1)
+                Dp = D.copy()
+                Dp[a, :] = ra
+                Dp[:, a] = ra
+                hit = holds[:, a] | (ra < kth_d) | ((ra == kth_d) & (a < kth_id))
+                hit[a] = True
+                ids = base.copy()
+                ids[hit] = _lists(Dp[hit], k)
+                if not np.array_equal(ids, base):
+                    stable[a, c] = False
+                # row sums, then accumulated in row order (as _loss_sets)
+                vals.append(float(np.cumsum(np.sum(g * Dp[rows, ids], axis=1))[-1]))
+            grad[a, c] = (vals[0] - vals[1]) / (2.0 * h)
+    return grad, stable
+
+
+def _lists(Drows, k):
+    """The k smallest (distance, column) keys of each row, as columns."""
+    cols = np.broadcast_to(np.arange(Drows.shape[1]), Drows.shape)
+    return np.lexsort((cols, Drows), axis=1)[:, :k]

@@ -146,8 +146,8 @@ def test_b2_many_queries_ordered(pg, dev):
 
 def test_b2_full_size_sampled(pg, dev):
     """The batch-dynamic workload on B2: 10M initial points, 3 rounds of 1M
-    inserts, 1M erases of live points, 1M queries (k = 10); 300 sampled rows
-    per round against the definition over the live set."""
+    inserts, 1M erases of live points, 1M queries (k = 10); every query row
+    per round against the oracle's kd-tree search over the live set."""
     init, rounds = datagen.bdl_rounds(10_000_000, 3, 1_000_000, 1_000_000, 3, seed=5)
     say("B2 full size: build")
     G = pg.B2Tree(to_dev(init, dev), leaf=16)
@@ -167,9 +167,8 @@ def test_b2_full_size_sampled(pg, dev):
         pts, ids = pts[~hit], ids[~hit]
         assert G.size() == len(pts)
         gi, gd = host(*G.knn(to_dev(rd["queries"], dev), 10))
-        rows = np.random.default_rng(r).choice(len(rd["queries"]), 300, replace=False)
-        oi, od = oracle.knn_brute(pts, rd["queries"][rows], 10, ids=ids, nthreads=16)
-        assert_int_equal(gi[rows], gd[rows], oi, od)
+        oi, od, _ = oracle.KdTree(pts, leaf=16).knn(rd["queries"], 10, ids=ids, nthreads=16)
+        assert_int_equal(gi, gd, oi, od)
 
 
 @pytest.mark.parametrize("d,n,gen,split", [(2, 20_000, "visual_var", "object"),
@@ -210,16 +209,18 @@ def test_trees_grown_from_batches_vary_k(pg, dev, d, n, gen, split):
 
 def test_trees_grown_full_size_sampled(pg, dev):
     """The k sweep's configuration at full size: BDL, B1 and B2 grown from 20
-    batches of 5% of the 10M 2-D VisualVar-style set; 200 sampled queries
-    against the definition for k = 2 and 11."""
+    batches of 5% of the 10M 2-D VisualVar-style set; 1M of its points
+    queried for k = 2 and 11 against the oracle's kd-tree search."""
     import torch
     n = 10_000_000
     pts = datagen.visual_var(n, 2, seed=65)
     P = to_dev(pts, dev)
     chunks = list(torch.chunk(P, 20))
-    rows = np.random.default_rng(66).choice(n, 200, replace=False)
+    rows = np.random.default_rng(66).choice(n, 1_000_000, replace=False)
     q = pts[rows]
-    refs = {k: oracle.knn_brute(pts, q, k, nthreads=16) for k in (2, 11)}
+    ot = oracle.KdTree(pts, leaf=16)
+    refs = {k: ot.knn(q, k, nthreads=16)[:2] for k in (2, 11)}
+    del ot
     for kind in ("bdl", "b1", "b2"):
         say(f"grown 10M {kind}")
         G = None

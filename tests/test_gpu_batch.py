@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 import oracle
-from oracle.grad import fd_self, grad_closed_form
+from oracle.grad import fd_self_incremental, grad_closed_form
 from paper_2207_01834_amd import datagen
 from parity import assert_float_close, say
 
@@ -149,8 +149,10 @@ def test_batched_graph_capture_replays(pg, dev):
         _ = (x * 2).sum().item()  # eager work between replays
 
 
-def test_cfg4_full_size_sampled(pg, dev):
-    """4,096 clouds, sizes log-uniform in [256, 65536], k = 16, one launch."""
+def test_cfg4_full_size(pg, dev):
+    """4,096 clouds, sizes log-uniform in [256, 65536], k = 16, one launch:
+    every row of 66 whole clouds (the largest, the smallest and 64 drawn at
+    random) against the oracle's kd-tree search within the cloud."""
     sizes = datagen.cloud_sizes(4096, seed=4)
     pts, offs = datagen.sphere_clouds(sizes, seed=44)
     say(f"cfg4: {len(pts)} points")
@@ -158,16 +160,20 @@ def test_cfg4_full_size_sampled(pg, dev):
     B = pg.BatchKnn(offs, 3, device=dev)
     gi, gd = host(*B.knn_self(x, 16))
     assert not B.timed_out()
-    rows = np.random.default_rng(0).choice(len(pts), 300, replace=False)
-    oi, od = oracle_per_cloud(pts, offs, 16, rows=rows)
-    assert_float_close(gi[rows], gd[rows], oi, od, pts, pts[rows])
     assert (gi[:, 0] >= 0).all()
+    pick = np.random.default_rng(0).choice(len(sizes), 64, replace=False)
+    pick = np.unique(np.concatenate([pick, [np.argmax(sizes), np.argmin(sizes)]]))
+    for c in pick:
+        a, b = int(offs[c]), int(offs[c + 1])
+        cloud = pts[a:b]
+        oi, od, _ = oracle.KdTree(cloud, leaf=16).knn(cloud, 16, nthreads=16)
+        assert_float_close(gi[a:b] - a, gd[a:b], oi, od, cloud, cloud)
 
 
 def test_backward_fd_and_closed_form(pg, dev):
     """Autograd of sum g * kNN d2 on 64 clouds of 256 points (k = 16) against
-    FP64 central differences (away from ties) and the FP64 closed form with
-    the GPU's neighbour sets."""
+    FP64 central differences (away from ties) on all 64 clouds and the FP64
+    closed form with the GPU's neighbour sets."""
     import torch
 
     from paper_2207_01834_amd.diff import knn_sqdist
@@ -185,10 +191,11 @@ def test_backward_fd_and_closed_form(pg, dev):
     cf = gq + gx
     scale = np.abs(cf).max()
     assert np.all(np.abs(grad - cf) <= 1e-4 * np.abs(cf) + 1e-4 * scale)
-    # FP64 central differences on the first 2 clouds
-    for c in range(2):
+    # FP64 central differences on every cloud
+    for c in range(len(sizes)):
         a, b = int(offs[c]), int(offs[c + 1])
-        fd, stable = fd_self(pts[a:b].astype(np.float64), k, G[a:b].astype(np.float64), h=1e-6)
+        fd, stable = fd_self_incremental(pts[a:b].astype(np.float64), k, G[a:b].astype(np.float64),
+                                         h=1e-6)
         sub = grad[a:b]
         assert stable.mean() > 0.8
         err = np.abs(sub - fd)[stable]

@@ -167,39 +167,29 @@ def test_cfg5_shaped_reduced(pg, dev, split):
         assert_int_equal(gi, gd, oi, od)
 
 
-def test_cfg5_full_size_sampled(pg, dev):
+def test_cfg5_full_size(pg, dev):
     """The benchmarked batch-dynamic configuration: 10M initial points, 10
-    rounds of 1M inserts, 1M erases of live points, 1M queries (k = 10);
-    invariants on every round, 300 sampled query rows per round against the
-    definition over the live set."""
+    rounds of 1M inserts, 1M erases of live points, 1M queries (k = 10).
+    After every insert and every erase: F, buffer size, per-tree live counts
+    and erase counts equal the model's (Algorithms 3 and 4); every query row
+    byte-identical to the oracle's kd-tree search over the live set."""
     import torch
     init, rounds = datagen.bdl_rounds(10_000_000, 10, 1_000_000, 1_000_000, 3, seed=5)
     X = 1 << 14
     G = pg.BDLTree(3, torch.int32, leaf=16, X=X, device=dev)
+    M = BDLModel(3, X)
     say("cfg5: initial insert")
-    G.insert(to_dev(init, dev))
-    F, b, live = G.stats()
-    assert F == len(init) // X and b == len(init) % X
-    pts = init
-    ids = np.arange(len(init), dtype=np.int64)
-    nxt = len(init)
-    key = lambda a: a[:, 0].astype(np.int64) | (a[:, 1].astype(np.int64) << 20) | (a[:, 2].astype(np.int64) << 40)
+    assert G.insert(to_dev(init, dev)) == M.insert(init) == 0
+    same_state(G, M, "init")
     for r, rd in enumerate(rounds):
         say(f"cfg5 round {r}")
-        assert G.insert(to_dev(rd["insert"], dev)) == nxt
-        pts = np.concatenate([pts, rd["insert"]])
-        ids = np.concatenate([ids, np.arange(nxt, nxt + len(rd["insert"]), dtype=np.int64)])
-        nxt += len(rd["insert"])
+        assert G.insert(to_dev(rd["insert"], dev)) == M.insert(rd["insert"])
+        same_state(G, M, f"round {r} insert")
+        pts, _ = M.live()
         E = datagen.choose_erase(pts, 1_000_000, rd["erase_seed"])
-        hit = np.isin(key(pts), key(E))
-        assert G.erase(to_dev(E, dev)) == int(hit.sum())
-        pts, ids = pts[~hit], ids[~hit]
-        F, b, live = G.stats()
-        assert G.size() == len(pts) and 0 <= b < X
-        for i in range(40):
-            if (F >> i) & 1:
-                assert 2 * live[i] >= (X << i) and live[i] <= (X << i)
+        assert G.erase(to_dev(E, dev)) == M.erase(E)
+        same_state(G, M, f"round {r} erase")
         gi, gd = host(*G.knn(to_dev(rd["queries"], dev), 10))
-        rows = np.random.default_rng(r).choice(len(rd["queries"]), 300, replace=False)
-        oi, od = oracle.knn_brute(pts, rd["queries"][rows], 10, ids=ids, nthreads=16)
-        assert_int_equal(gi[rows], gd[rows], oi, od)
+        pts, ids = M.live()
+        oi, od, _ = oracle.KdTree(pts, leaf=16).knn(rd["queries"], 10, ids=ids, nthreads=16)
+        assert_int_equal(gi, gd, oi, od)

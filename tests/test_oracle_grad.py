@@ -32,3 +32,18 @@ def test_closed_form_matches_central_differences():
     assert stable.mean() > 0.9
     err = np.abs(cf - fd)[stable]
     assert err.max() <= 1e-8 * max(1.0, np.abs(cf).max())
+
+
+def test_incremental_differences_equal_the_plain_ones():
+    # the incremental form re-sorts only the lists a perturbation can change;
+    # its gradients and stability masks equal the plain full recomputation's,
+    # also with duplicate points and exact ties
+    from oracle.grad import fd_self_incremental
+    g = np.random.default_rng(3)
+    for P, k in ((g.random((60, 3)), 5), (np.round(g.random((50, 2)) * 4) / 4, 6),
+                 (g.standard_normal((30, 5)), 7)):
+        G = g.standard_normal((len(P), k))
+        a = fd_self(P, k, G, h=1e-6)
+        b = fd_self_incremental(P, k, G, h=1e-6)
+        assert np.array_equal(a[1], b[1])
+        assert np.array_equal(a[0], b[0])

@@ -248,3 +248,15 @@ def test_visit_counters_hand_worked_contained_subtree():
     ids, dist, c = t.knn(np.array([[0, 100]], np.int32), 2)
     assert ids.tolist() == [[1, 3]] and dist.tolist() == [[0, 2402]]
     assert c.tolist() == [2, 4, 4]
+
+
+def test_kd_knn_threaded_chunks_change_nothing():
+    # the query-parallel form runs the same serial search on static chunks
+    g = np.random.default_rng(31)
+    pts = g.integers(0, 300, size=(5000, 3)).astype(np.int32)
+    q = g.integers(0, 300, size=(777, 3)).astype(np.int32)
+    t = oracle.KdTree(pts, leaf=8)
+    a = t.knn(q, 9)
+    for th in (2, 5, 16):
+        b = t.knn(q, 9, nthreads=th)
+        assert all(np.array_equal(x, y) for x, y in zip(a, b))
