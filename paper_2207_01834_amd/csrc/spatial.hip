@@ -197,27 +197,56 @@ __global__ void root_kernel(Nodes N, Entries E, int64_t n, int d, int leaf, int 
     tot[1] = 0;
 }
 
-// Entry of chunk c: the last a with cstart[a] <= c (every entry has a chunk).
+// Entry of chunk c (the same in every lane): the last a with cstart[a] <= c
+// (every entry has a chunk).  A 64-way search: each step the lanes test 64
+// evenly spaced candidates, so a level of 10^6 entries takes four loads.
 __device__ inline uint32_t chunk_entry(const uint32_t* cstart, uint32_t A, uint32_t c) {
-    uint32_t lo = 0, hi = A;
+    uint32_t lo = 0, hi = A;  // cstart[lo] <= c < cstart[hi]
     while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (cstart[mid] <= c) lo = mid;
-        else hi = mid;
+        const uint32_t step = (hi - lo + kWave - 1) / kWave;
+        const uint32_t at = lo + (uint32_t)lane_id() * step;
+        const uint64_t le = __ballot(at < hi && cstart[at] <= c);  // a prefix of the lanes
+        const uint32_t last = 63u - (uint32_t)__clzll(le);
+        lo = lo + last * step;
+        hi = min(hi, lo + step);
     }
     return lo;
 }
 
+// Splitting entries of at least kRepChunks chunks reduce their children's
+// boxes into kReplicas copies each (replica = chunk mod kReplicas): with one
+// set of words per child, every chunk of a big node would update the same
+// few words, and those atomics serialise.
+constexpr uint32_t kRepChunks = 16;
+constexpr int kReplicas = 64;
+constexpr uint32_t kNoRep = 0xffffffffu;
+
 // Per chunk (one wave): its entry, and the number of its points going left.
+// The first chunk of a splitting entry with kRepChunks or more chunks takes
+// a replica block (rbase[a]; block b serves entry rentry[b]) and resets it.
 __global__ void __launch_bounds__(kNT)
 chunk_count_kernel(Entries E, const uint32_t* __restrict__ cstart, uint32_t A, uint32_t C,
                    const uint32_t* __restrict__ keys, int64_t n, uint32_t* __restrict__ c2e,
-                   uint32_t* __restrict__ lcnt) {
+                   uint32_t* __restrict__ lcnt, int d, uint32_t* __restrict__ rbase,
+                   uint32_t* __restrict__ rentry, uint32_t* __restrict__ rcount,
+                   uint32_t* __restrict__ rep) {
     const uint32_t c = blockIdx.x * (kNT / kWave) + threadIdx.x / kWave;
     if (c == 0 && threadIdx.x == 0) lcnt[C] = 0;
     if (c >= C) return;
     const uint32_t a = chunk_entry(cstart, A, c);
     const uint32_t dm = E.dim[a];
+    if (c == cstart[a]) {
+        uint32_t b = kNoRep;
+        if (!(dm & kCopy) && cstart[a + 1] - c >= kRepChunks) {
+            if (lane_id() == 0) b = atomicAdd(rcount, 1u);
+            b = __shfl(b, 0, kWave);
+            uint32_t* blk = rep + (size_t)b * 2 * kReplicas * 2 * d;
+            for (int w = lane_id(); w < 2 * kReplicas * 2 * d; w += kWave)
+                blk[w] = (w % (2 * d)) < d ? 0xffffffffu : 0u;
+            if (lane_id() == 0) rentry[b] = a;
+        }
+        if (lane_id() == 0) rbase[a] = b;
+    }
     uint32_t left = 0;
     if (!(dm & kCopy)) {
         const uint32_t lo = E.lo[a], end = lo + E.cnt[a];
@@ -276,7 +305,8 @@ template <int MD>
 __global__ void __launch_bounds__(kNT)
 chunk_scatter_kernel(Entries E, Nodes N, const uint32_t* __restrict__ cstart,
                      const uint32_t* __restrict__ lpre, const uint32_t* __restrict__ c2e, uint32_t C,
-                     uint32_t nbase, int leaf, int d, int rw, int fl,
+                     uint32_t nbase, const uint32_t* __restrict__ rbase, uint32_t* __restrict__ rep,
+                     int leaf, int d, int rw, int fl,
                      const uint32_t* __restrict__ keys, const int32_t* __restrict__ idx,
                      uint32_t* __restrict__ okeys, int32_t* __restrict__ oidx, int64_t n,
                      uint32_t* __restrict__ pts, uint32_t* __restrict__ rec,
@@ -358,11 +388,16 @@ chunk_scatter_kernel(Entries E, Nodes N, const uint32_t* __restrict__ cstart,
         lb += (uint32_t)__popcll(bl);
         rb += (uint32_t)__popcll(br);
     }
+    // the children's boxes, or (entries with a replica block) replica
+    // c mod kReplicas of them
     const uint32_t c0 = nbase + 2u * a;
+    const uint32_t rblk = rbase[a];
 #pragma unroll
     for (int sd = 0; sd < 2; sd++) {
         if (sd == 0 ? !any0 : !any1) continue;
-        uint32_t* bk = N.key + (size_t)(c0 + sd) * 2 * d;
+        uint32_t* bk = rblk != kNoRep
+                           ? rep + (((size_t)rblk * 2 + sd) * kReplicas + (c - cs) % kReplicas) * 2 * d
+                           : N.key + (size_t)(c0 + sd) * 2 * d;
 #pragma unroll
         for (int e = 0; e < MD; e++) {
             if (e < d) {
@@ -377,13 +412,37 @@ chunk_scatter_kernel(Entries E, Nodes N, const uint32_t* __restrict__ cstart,
     }
 }
 
+// Boxes of the children of the entries with a replica block: one wave per
+// (block, child), one replica per lane.
+__global__ void __launch_bounds__(kNT)
+merge_replicas_kernel(const uint32_t* __restrict__ rep, const uint32_t* __restrict__ rentry,
+                      const uint32_t* __restrict__ rcount, uint32_t nbase, int d,
+                      uint32_t* __restrict__ key) {
+    const uint32_t t = blockIdx.x * (kNT / kWave) + threadIdx.x / kWave;  // 2 block + child
+    if (t >= 2u * *rcount) return;
+    const int lane = lane_id();
+    const uint32_t a = rentry[t >> 1];
+    const uint32_t* r = rep + ((size_t)t * kReplicas + lane) * 2 * d;
+    uint32_t* k = key + (size_t)(nbase + 2u * a + (t & 1u)) * 2 * d;
+    for (int c = 0; c < d; c++) {
+        const uint32_t mn = wave_min_u32(r[c]);
+        const uint32_t mx = wave_max_u32(r[d + c]);
+        if (lane == 0) {
+            k[c] = mn;
+            k[d + c] = mx;
+        }
+    }
+}
+
 // Per splitting entry: the node's record, its children's records, counts and
 // segments, and the children's flags for the next level (split / copy / leaf).
 __global__ void __launch_bounds__(kNT)
 split_nodes_kernel(Entries E, Nodes N, const uint32_t* __restrict__ cstart,
                    const uint32_t* __restrict__ lpre, uint32_t As, uint32_t nbase, int leaf, int d,
-                   int fl, uint64_t* __restrict__ flags, uint32_t* __restrict__ nch_next) {
+                   int fl, uint64_t* __restrict__ flags, uint32_t* __restrict__ nch_next,
+                   uint32_t* __restrict__ rcount) {
     const uint32_t a = blockIdx.x * kNT + threadIdx.x;
+    if (a == 0) *rcount = 0;  // the replica blocks were merged: free for the next level
     if (a >= As) return;
     const uint32_t u = E.node[a];
     const uint32_t lo = E.lo[a], cnt = E.cnt[a];
@@ -556,11 +615,12 @@ struct Grow {
 template <int MD>
 void launch_scatter(unsigned grid, hipStream_t s, const Entries& E, const Nodes& N,
                     const uint32_t* cstart, const uint32_t* lpre, const uint32_t* c2e, uint32_t C,
-                    uint32_t nbase, int leaf, int d, int rw, int fl, const uint32_t* keys,
-                    const int32_t* idx, uint32_t* okeys, int32_t* oidx, int64_t n, pg_tree* T) {
+                    uint32_t nbase, const uint32_t* rbase, uint32_t* rep, int leaf, int d, int rw,
+                    int fl, const uint32_t* keys, const int32_t* idx, uint32_t* okeys, int32_t* oidx,
+                    int64_t n, pg_tree* T) {
     hipLaunchKernelGGL((chunk_scatter_kernel<MD>), dim3(grid), dim3(kNT), 0, s, E, N, cstart, lpre,
-                       c2e, C, nbase, leaf, d, rw, fl, keys, idx, okeys, oidx, n, T->pts, T->rec,
-                       T->pidx);
+                       c2e, C, nbase, rbase, rep, leaf, d, rw, fl, keys, idx, okeys, oidx, n, T->pts,
+                       T->rec, T->pidx);
 }
 
 // Leaf boxes (keys) of an explicit-node tree from its points: one lane per
@@ -726,7 +786,16 @@ pg_status build_tree_spatial(const void* points, int64_t n, int d, int leaf, int
     // chunk starts x 2 (current / next; the next level's are first indexed
     // by child slot, [2 amax + 1]), c2e [cmax], lcnt [cmax + 1], flags and
     // their prefix [2 amax] u64, totals
-    DevBuf cbuf(s), fbuf(s);
+    DevBuf cbuf(s), fbuf(s), rbuf(s), rmeta(s);
+    // replica blocks: one per entry of kRepChunks or more chunks, which holds
+    // more than kCH (kRepChunks - 1) points
+    const size_t rmax = (size_t)(nn / (kCH * (kRepChunks - 1)) + 2);
+    PG_TRY(rbuf.alloc(sizeof(uint32_t) * rmax * 2 * kReplicas * 2 * d));
+    PG_TRY(rmeta.alloc(sizeof(uint32_t) * (amax + rmax + 1)));
+    uint32_t* rbase = rmeta.as<uint32_t>();  // [amax] per entry
+    uint32_t* rentry = rbase + amax;         // [rmax] per block
+    uint32_t* rcount = rentry + rmax;        // blocks taken this level
+    PG_HIP(hipMemsetAsync(rcount, 0, sizeof(uint32_t), s));
     PG_TRY(cbuf.alloc(sizeof(uint32_t) * (2 * (2 * amax + 1) + cmax + cmax + 1 + 8)));
     uint32_t* cst[2] = {cbuf.as<uint32_t>(), cbuf.as<uint32_t>() + 2 * amax + 1};
     uint32_t* c2e = cst[1] + 2 * amax + 1;
@@ -784,22 +853,29 @@ pg_status build_tree_spatial(const void* points, int64_t n, int d, int leaf, int
         const Entries& X = ent[cur ^ 1];
         const unsigned cgrid = cdiv(C, kNT / kWave);
         hipLaunchKernelGGL(chunk_count_kernel, dim3(cgrid), dim3(kNT), 0, s, E, cst[cur], A, C, kcur,
-                           n, c2e, lcnt);
+                           n, c2e, lcnt, d, rbase, rentry, rcount, rbuf.as<uint32_t>());
         PG_LAUNCH_CHECK();
         PG_TRY(exclusive_scan_u32(lcnt, lcnt, (int64_t)C + 1, nullptr, s));
         const uint32_t nbase = (uint32_t)nodes;
+        uint32_t* rep = rbuf.as<uint32_t>();
         switch (d) {
-            case 1: launch_scatter<1>(cgrid, s, E, N, cst[cur], lcnt, c2e, C, nbase, leaf, d, rw, ifl, kcur, icur, knext, inext, n, T); break;
-            case 2: launch_scatter<2>(cgrid, s, E, N, cst[cur], lcnt, c2e, C, nbase, leaf, d, rw, ifl, kcur, icur, knext, inext, n, T); break;
-            case 3: launch_scatter<3>(cgrid, s, E, N, cst[cur], lcnt, c2e, C, nbase, leaf, d, rw, ifl, kcur, icur, knext, inext, n, T); break;
-            case 4: launch_scatter<4>(cgrid, s, E, N, cst[cur], lcnt, c2e, C, nbase, leaf, d, rw, ifl, kcur, icur, knext, inext, n, T); break;
-            case 5: launch_scatter<5>(cgrid, s, E, N, cst[cur], lcnt, c2e, C, nbase, leaf, d, rw, ifl, kcur, icur, knext, inext, n, T); break;
-            default: launch_scatter<8>(cgrid, s, E, N, cst[cur], lcnt, c2e, C, nbase, leaf, d, rw, ifl, kcur, icur, knext, inext, n, T); break;
+            case 1: launch_scatter<1>(cgrid, s, E, N, cst[cur], lcnt, c2e, C, nbase, rbase, rep, leaf, d, rw, ifl, kcur, icur, knext, inext, n, T); break;
+            case 2: launch_scatter<2>(cgrid, s, E, N, cst[cur], lcnt, c2e, C, nbase, rbase, rep, leaf, d, rw, ifl, kcur, icur, knext, inext, n, T); break;
+            case 3: launch_scatter<3>(cgrid, s, E, N, cst[cur], lcnt, c2e, C, nbase, rbase, rep, leaf, d, rw, ifl, kcur, icur, knext, inext, n, T); break;
+            case 4: launch_scatter<4>(cgrid, s, E, N, cst[cur], lcnt, c2e, C, nbase, rbase, rep, leaf, d, rw, ifl, kcur, icur, knext, inext, n, T); break;
+            case 5: launch_scatter<5>(cgrid, s, E, N, cst[cur], lcnt, c2e, C, nbase, rbase, rep, leaf, d, rw, ifl, kcur, icur, knext, inext, n, T); break;
+            default: launch_scatter<8>(cgrid, s, E, N, cst[cur], lcnt, c2e, C, nbase, rbase, rep, leaf, d, rw, ifl, kcur, icur, knext, inext, n, T); break;
         }
         PG_LAUNCH_CHECK();
         if (As == 0) break;  // copies only: nothing below
+        if (C >= kRepChunks) {
+            const int64_t slots = 2 * (int64_t)rmax;
+            hipLaunchKernelGGL(merge_replicas_kernel, dim3(cdiv(slots, kNT / kWave)), dim3(kNT), 0, s,
+                               rep, rentry, rcount, nbase, d, gkey.p);
+            PG_LAUNCH_CHECK();
+        }
         hipLaunchKernelGGL(split_nodes_kernel, dim3(cdiv(As, kNT)), dim3(kNT), 0, s, E, N, cst[cur],
-                           lcnt, As, nbase, leaf, d, ifl, flags, cst[cur ^ 1]);
+                           lcnt, As, nbase, leaf, d, ifl, flags, cst[cur ^ 1], rcount);
         PG_LAUNCH_CHECK();
         PG_TRY(exclusive_scan_u64(flags, fpre, 2 * (int64_t)As, ftot, s));
         const uint32_t nbase_next = nbase + 2 * As;
