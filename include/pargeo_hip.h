@@ -421,12 +421,34 @@ pg_status pg_batch_create(const int64_t* offsets_host, int32_t n_clouds, int32_t
 pg_status pg_batch_knn_self(pg_batch* b, const float* points, int32_t k, int32_t* out_idx,
                             float* out_d2, void* stream);
 
+/* k-NN of a separate query set per cloud (the static search of Appendix C
+ * within each cloud, from the root), in the same persistent launch:
+ * every cloud's tree is built from `points` as in pg_batch_knn_self and
+ * cloud c's queries search it.  A cloud may have points and no queries,
+ * queries and no points (their rows are padding), or neither.
+ *   points         : [N][d] float32, device (the clouds of pg_batch_create)
+ *   queries        : [M][d] float32, device (finite, |x| <= 1e18)
+ *   q_offsets_host : (host) [n_clouds+1], q_offsets[0] = 0, non-decreasing;
+ *                    cloud c's queries are rows [q_offsets[c], q_offsets[c+1]);
+ *                    M = q_offsets[n_clouds] < 2^31
+ *   out_idx        : [M][k] int32 global rows of the neighbours (-1 = none)
+ *   out_d2         : [M][k] float32 squared distances
+ * The handle keeps the last query layout: a call with the same q_offsets
+ * uploads nothing, allocates nothing and does not synchronise (it may be
+ * captured in a HIP graph); a call with new q_offsets uploads them and
+ * synchronises once.  Calls sharing one workspace must not overlap. */
+pg_status pg_batch_knn(pg_batch* b, const float* points, const float* queries,
+                       const int64_t* q_offsets_host, int32_t k, int32_t* out_idx, float* out_d2,
+                       void* stream);
+
 /* Range check of float32 points (synchronises); PG_ERR_RANGE if any is
  * non-finite or |x| > 1e18. */
 pg_status pg_batch_check(const float* points, int64_t n, int32_t d, void* stream);
 
-/* Reads the workspace's wait-timeout flag of the last launch (synchronises). */
-pg_status pg_batch_status(const pg_batch* b, void* stream, int32_t* timed_out);
+/* Reads the workspace's flag word (synchronises): bit 0, a wait of the last
+ * launch timed out; bit 1, a pg_batch_backward since then met a cloud whose
+ * largest term bound (2 max|g| sqrt(max D)) is not a finite float. */
+pg_status pg_batch_status(const pg_batch* b, void* stream, int32_t* flags);
 
 /* Times every tuning candidate (leaf 8/16/32 x 2/4 workgroups per CU x 1/4
  * queries per lane x k-list in registers/LDS: 24 launches) on these points
@@ -445,11 +467,14 @@ void pg_batch_free(pg_batch* b);
  *   grad_points[j] = sum_r 2 g[j,r] (x_j - x_{idx[j,r]})
  *                  - sum_{(i,r): idx[i,r] = j} 2 g[i,r] (x_i - x_j)
  * Queries are taken in each cloud's leaf order, so most neighbour terms are
- * summed in LDS; all sums are int64 fixed point scaled from the largest term
- * (about 38 bits per term), hence independent of the order of the adds:
- * deterministic.  Not in the paper (the gradient of its k-NN distances).
+ * summed in LDS; all sums are int64 fixed point scaled from the cloud's
+ * largest term (about 38 bits per term), hence independent of the order of
+ * the adds: deterministic.  Not in the paper (the gradient of its k-NN
+ * distances).
  *   idx, d2  : [N][k] device, the forward's outputs (global rows, float32 D)
- *   grad_d2  : [N][k] device float32, finite
+ *   grad_d2  : [N][k] device float32; a cloud whose term bound is not a
+ *              finite float (NaN or infinite entries, or terms beyond 3e38)
+ *              receives NaN gradients and sets bit 1 of pg_batch_status
  *   grad_points : [N][d] device float32, written (not accumulated)
  * Allocates scratch (stream-ordered pool); does not synchronise. */
 pg_status pg_batch_backward(pg_batch* b, const float* points, int32_t k, const int32_t* idx,

@@ -90,6 +90,7 @@ SIGNATURES = {
     "pg_batch_workspace": (i32, [P64, i32, i32, vp, ctypes.POINTER(ctypes.c_size_t)]),
     "pg_batch_create": (i32, [P64, i32, i32, vp, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]),
     "pg_batch_knn_self": (i32, [vp, vp, i32, vp, vp, vp]),
+    "pg_batch_knn": (i32, [vp, vp, vp, P64, i32, vp, vp, vp]),
     "pg_batch_check": (i32, [vp, i64, i32, vp]),
     "pg_batch_status": (i32, [vp, vp, P32]),
     "pg_batch_autotune": (i32, [vp, P64, i32, i32, i32, vp, vp]),
@@ -492,6 +493,29 @@ class BatchKnn:
         self.generation += 1
         return idx, d2
 
+    def knn(self, points: torch.Tensor, queries: torch.Tensor, q_offsets, k: int, out=None):
+        """k-NN of a separate query set per cloud (cloud c's queries are rows
+        [q_offsets[c], q_offsets[c+1]) of ``queries``) in one persistent
+        launch: (idx int32 [M][k] global point rows, d2 float32 [M][k])."""
+        p = _points(points, "points")
+        q = _points(queries, "queries")
+        if p.dtype != torch.float32 or p.shape != (self.N, self.d):
+            raise TypeError("points must be float32 [N][d] matching the offsets")
+        qo, qptr = _offsets_array(q_offsets)
+        if len(qo) != self.C + 1 or q.dtype != torch.float32 or q.shape != (int(qo[-1]), self.d):
+            raise TypeError("queries must be float32 [M][d] with q_offsets of C + 1 entries")
+        M = q.shape[0]
+        if out is None:
+            idx = torch.empty((M, k), dtype=torch.int32, device=p.device)
+            d2 = torch.empty((M, k), dtype=torch.float32, device=p.device)
+        else:
+            idx, d2 = out
+        check(lib().pg_batch_knn(self._h, ctypes.c_void_p(p.data_ptr()), ctypes.c_void_p(q.data_ptr()),
+                                 qptr, k, ctypes.c_void_p(idx.data_ptr()),
+                                 ctypes.c_void_p(d2.data_ptr()), stream_ptr(p.device)))
+        self.generation += 1
+        return idx, d2
+
     def backward(self, points: torch.Tensor, idx: torch.Tensor, d2: torch.Tensor,
                  grad_d2: torch.Tensor, out=None):
         """Gradient of sum grad_d2 * d2 w.r.t. the points for the last
@@ -508,10 +532,19 @@ class BatchKnn:
                                       stream_ptr(p.device)))
         return gp
 
-    def timed_out(self) -> bool:
+    def flags(self) -> int:
         flag = ctypes.c_int32()
         check(lib().pg_batch_status(self._h, stream_ptr(self.device), ctypes.byref(flag)))
-        return bool(flag.value)
+        return flag.value
+
+    def timed_out(self) -> bool:
+        """A wait of the last launch timed out."""
+        return bool(self.flags() & 1)
+
+    def backward_nonfinite(self) -> bool:
+        """A backward met a cloud whose term bound is not a finite float (its
+        gradients are NaN)."""
+        return bool(self.flags() & 2)
 
 
 def batch_check(points: torch.Tensor):

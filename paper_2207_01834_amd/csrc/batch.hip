@@ -72,6 +72,10 @@ struct BatchParams {
     int64_t total_items;
     int32_t C, d, k, S;
     int32_t lq;  // queries each lane searches per query item
+    // separate query sets (null queries: every point queries its own cloud)
+    const uint32_t* queries;  // [M][d] float32 bits
+    const int64_t* qoff;      // [C+1] cloud c's queries are rows [qoff[c], qoff[c+1])
+    const int64_t* qitems;    // [C+1] first query item of order[t]
 };
 
 __global__ void batch_reset_kernel(uint32_t* queue, uint32_t* ready, int C) {
@@ -132,18 +136,20 @@ __device__ inline void build_cloud(const BatchParams& P, int c, uint32_t* sm) {
 }
 
 // One query item: the cloud's points [blk * kQB * lq, ...), lane t taking
-// points t, t + kQB, ... (lq of them).  LDSL: the k-list lives in LDS (sm).
+// points t, t + kQB, ... (lq of them); with separate query sets, the cloud's
+// queries in the same way.  LDSL: the k-list lives in LDS (sm).
 template <int MD, int KT, bool EX, bool LDSL>
 __device__ inline void query_item(const BatchParams& P, int64_t q, int* s_ok, uint32_t* sm) {
-    // item -> position t in the size order (binary search over qstart)
-    int lo = 0, hi = P.C;  // qstart[lo] <= q < qstart[hi]
+    // item -> position t in the size order (binary search over the item starts)
+    const int64_t* qs = P.queries ? P.qitems : P.qstart;
+    int lo = 0, hi = P.C;  // qs[lo] <= q < qs[hi]
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
-        if (P.qstart[mid] <= q) lo = mid;
+        if (qs[mid] <= q) lo = mid;
         else hi = mid;
     }
     const int c = P.order[lo];
-    const int64_t blk = q - P.qstart[lo];
+    const int64_t blk = q - qs[lo];
     if (threadIdx.x == 0) {
         uint32_t spins = 0;
         int ok = 1;
@@ -167,14 +173,25 @@ __device__ inline void query_item(const BatchParams& P, int64_t q, int* s_ok, ui
     const TreeView tv{D.n, d, D.L, record_words(d), P.pts + D.pts, P.pidx + D.row,
                       P.split + D.split, P.bbox + D.bbox, P.rec + D.row * record_words(d)};
     using M = Metric<float>;
+    const bool sep = P.queries != nullptr;
+    const int64_t mq = sep ? P.qoff[c + 1] - P.qoff[c] : D.n;
     for (int r = 0; r < P.lq; r++) {
         const int64_t i = (blk * P.lq + r) * kQB + threadIdx.x;
-        if (i >= D.n) break;
+        if (i >= mq) break;
         float q_[MD];
+        uint32_t start;
+        int64_t row;
+        if (sep) {
+            row = P.qoff[c] + i;
 #pragma unroll
-        for (int cc = 0; cc < MD; cc++) q_[cc] = cc < d ? M::load(tv.pts[(int64_t)cc * D.n + i]) : 0.0f;
-        const uint32_t start = (1u << D.L) + leaf_of(D.n, D.L, i);
-        const int64_t row = D.row + tv.pidx[i];
+            for (int cc = 0; cc < MD; cc++) q_[cc] = cc < d ? M::load(P.queries[row * d + cc]) : 0.0f;
+            start = 0;  // from the root
+        } else {
+#pragma unroll
+            for (int cc = 0; cc < MD; cc++) q_[cc] = cc < d ? M::load(tv.pts[(int64_t)cc * D.n + i]) : 0.0f;
+            start = (1u << D.L) + leaf_of(D.n, D.L, i);
+            row = D.row + tv.pidx[i];
+        }
         if constexpr (LDSL) {
             LdsList<KT, EX> kl;
             kl.init(reinterpret_cast<uint64_t*>(sm) + threadIdx.x, kNT);
@@ -359,13 +376,22 @@ __global__ void bwd_inv_kernel(const CloudDesc* __restrict__ desc, const int64_t
     }
 }
 
-// maxes[0] = max |g|, maxes[1] = max D over the pairs with a neighbour (the
-// padding of a cloud smaller than k has D = +inf); as float bits:
-// non-negative floats order like their bits.
-__global__ void bwd_scale_kernel(const float* __restrict__ g, const float* __restrict__ d2,
-                                 int64_t P, uint32_t* __restrict__ maxes) {
+// Per cloud: maxes[2c] = max |g|, maxes[2c+1] = max D over the cloud's pairs
+// with a neighbour (the padding of a cloud smaller than k has D = +inf); as
+// float bits: non-negative floats order like their bits, and a NaN |g|
+// orders above every finite value.  One workgroup per backward item (its
+// rows' pairs are contiguous).
+__global__ void __launch_bounds__(kNT)
+bwd_scale_kernel(const CloudDesc* __restrict__ desc, const int64_t* __restrict__ start, int C, int k,
+                 const float* __restrict__ g, const float* __restrict__ d2,
+                 uint32_t* __restrict__ maxes) {
+    __shared__ uint32_t red[2][kNT / kWave];
+    const int c = cloud_of_item(start, C, blockIdx.x);
+    const CloudDesc D = desc[c];
+    const int64_t p0 = ((int64_t)blockIdx.x - start[c]) * kBwdItem;
+    const int64_t r1 = D.row + (p0 + kBwdItem < D.n ? p0 + kBwdItem : (int64_t)D.n);
     uint32_t mg = 0, md = 0;
-    for (int64_t p = (int64_t)blockIdx.x * kNT + threadIdx.x; p < P; p += (int64_t)gridDim.x * kNT) {
+    for (int64_t p = (D.row + p0) * k + threadIdx.x; p < r1 * k; p += kNT) {
         const float dp = d2[p];
         if (!(dp < __builtin_huge_valf())) continue;
         const uint32_t a = __float_as_uint(fabsf(g[p])), b = __float_as_uint(dp);
@@ -375,15 +401,29 @@ __global__ void bwd_scale_kernel(const float* __restrict__ g, const float* __res
     mg = wave_max_u32(mg);
     md = wave_max_u32(md);
     if (lane_id() == 0) {
-        atomicMax(&maxes[0], mg);
-        atomicMax(&maxes[1], md);
+        red[0][threadIdx.x / kWave] = mg;
+        red[1][threadIdx.x / kWave] = md;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kNT / kWave; w++) {
+            mg = red[0][w] > mg ? red[0][w] : mg;
+            md = red[1][w] > md ? red[1][w] : md;
+        }
+        mg = red[0][0] > mg ? red[0][0] : mg;
+        md = red[1][0] > md ? red[1][0] : md;
+        atomicMax(&maxes[2 * c], mg);
+        atomicMax(&maxes[2 * c + 1], md);
     }
 }
 
-// Power-of-two scale of the terms (see above); 1 when every term is 0.
-__device__ inline float bwd_scale(const uint32_t* maxes) {
-    const float t = 2.0f * __uint_as_float(maxes[0]) * sqrtf(__uint_as_float(maxes[1]));
-    if (!(t > 0.0f) || !(t <= 3.0e38f)) return 1.0f;
+// Power-of-two scale of cloud c's terms (see above); 1 when every term is 0;
+// 0 when the bound is not a finite float (NaN or infinite gradients, or
+// terms beyond 3e38): that cloud's neighbour sums are then NaN.
+__device__ inline float bwd_scale(const uint32_t* maxes, int c) {
+    const float t = 2.0f * __uint_as_float(maxes[2 * c]) * sqrtf(__uint_as_float(maxes[2 * c + 1]));
+    if (!(t <= 3.0e38f)) return 0.0f;
+    if (!(t > 0.0f)) return 1.0f;
     int e = 0;
     (void)frexpf(t, &e);  // t < 2^e
     return ldexpf(1.0f, 30 - e);
@@ -413,7 +453,7 @@ bwd_main_kernel(const CloudDesc* __restrict__ desc, const int64_t* __restrict__ 
     for (int e = threadIdx.x; e < kBwdWin * d; e += kNT) win[e] = 0ull;
     if (threadIdx.x == 0) nspill = 0;
     __syncthreads();
-    const float scale = bwd_scale(maxes);
+    const float scale = bwd_scale(maxes, c);  // 0: the terms are not rounded (the sums become NaN)
     for (int e = threadIdx.x; e < kBwdItem; e += kNT) {
         const int64_t pos = p0 + e;
         if (pos >= D.n) break;
@@ -458,6 +498,11 @@ bwd_main_kernel(const CloudDesc* __restrict__ desc, const int64_t* __restrict__ 
             for (int u = 0; u < 4; u++) {
                 if (jj[u] < 0) continue;
                 const float gr = gg[u];
+                if (scale == 0.0f) {  // the cloud's neighbour sums are NaN (bwd_finish_kernel)
+#pragma unroll
+                    for (int cc = 0; cc < MD; cc++) gq[cc] += 2.0f * gr * (xi[cc] - xj[u][cc]);
+                    continue;
+                }
                 const bool in_win = w[u] >= 0 && w[u] < kBwdWin;
                 int32_t t[MD];
 #pragma unroll
@@ -518,18 +563,20 @@ bwd_main_kernel(const CloudDesc* __restrict__ desc, const int64_t* __restrict__ 
 // the neighbouring item of the same cloud whose window also covers it, if any
 // (the previous item's below p0 + kBwdMargin, the next item's from
 // p0 + kBwdItem - kBwdMargin on), and its row accumulator; gout += that sum /
-// scale.
+// scale (NaN, and bit 1 of *flags, for a cloud whose scale is 0).
 __global__ void __launch_bounds__(kNT)
 bwd_finish_kernel(const CloudDesc* __restrict__ desc, const int64_t* __restrict__ start, int C,
                   const int32_t* __restrict__ pidx, int d,
                   const unsigned long long* __restrict__ wbuf,
                   const unsigned long long* __restrict__ acc, const uint32_t* __restrict__ maxes,
-                  float* __restrict__ gout) {
+                  uint32_t* __restrict__ flags, float* __restrict__ gout) {
     const int c = cloud_of_item(start, C, blockIdx.x);
     const CloudDesc D = desc[c];
     const int64_t b = blockIdx.x, b0 = start[c], b1 = start[c + 1];
     const int64_t p0 = (b - b0) * kBwdItem;
-    const float inv_scale = 1.0f / bwd_scale(maxes);
+    const float scale = bwd_scale(maxes, c);
+    const float inv_scale = scale > 0.0f ? 1.0f / scale : __builtin_nanf("");
+    if (scale == 0.0f && threadIdx.x == 0) atomicOr(flags, 2u);
     const unsigned long long* own = wbuf + b * kBwdWin * d;
     for (int e = threadIdx.x; e < kBwdItem * d; e += kNT) {
         const int64_t pos = p0 + e / d;
@@ -558,7 +605,11 @@ struct BatchPlan {
     // workspace carve-up
     size_t bytes = 0;
     size_t o_queue = 0, o_ready = 0, o_order = 0, o_qstart = 0, o_desc = 0, o_pts = 0,
-           o_keys = 0, o_pidx = 0, o_pidx2 = 0, o_split = 0, o_bbox = 0, o_rec = 0;
+           o_keys = 0, o_pidx = 0, o_pidx2 = 0, o_split = 0, o_bbox = 0, o_rec = 0,
+           o_qoff = 0, o_qitems = 0;
+    // the query offsets last uploaded for pg_batch_knn, and their item count
+    std::vector<int64_t> qoff;
+    int64_t q_items = 0;
     std::vector<int32_t> order;
     std::vector<int64_t> qstart;
     std::vector<int64_t> bstart;  // first backward work item of cloud c (cloud order)
@@ -632,6 +683,8 @@ static pg_status make_plan(const int64_t* offs, int C, int d, int leaf, int bpc,
     P.o_split = o; o = align256(o + 4 * (size_t)(split > 0 ? split : 1));
     P.o_bbox = o; o = align256(o + 4 * (size_t)(bbox > 0 ? bbox : 1));
     P.o_rec = o; o = align256(o + 4 * (size_t)record_words(d) * (size_t)(P.N > 0 ? P.N : 1));
+    P.o_qoff = o; o = align256(o + 8 * (size_t)(C + 1));
+    P.o_qitems = o; o = align256(o + 8 * (size_t)(C + 1));
     P.bytes = o;
     return PG_OK;
 }
@@ -757,12 +810,9 @@ pg_status pg_batch_create(const int64_t* offsets_host, int32_t n_clouds, int32_t
     return PG_OK;
 }
 
-pg_status pg_batch_knn_self(pg_batch* b, const float* points, int32_t k, int32_t* out_idx,
-                            float* out_d2, void* stream) {
-    if (!b) return fail(PG_ERR_INVALID, "pg_batch_knn_self: handle is NULL");
-    if (k < 1 || k > 64) return fail(PG_ERR_INVALID, "pg_batch_knn_self: k must be in [1, 64]");
+static BatchParams batch_params(pg_batch* b, const float* points, int32_t k, int32_t* out_idx,
+                                float* out_d2) {
     const BatchPlan& PL = b->plan;
-    if (PL.N > 0 && (!points || !out_idx || !out_d2)) return fail(PG_ERR_INVALID, "pg_batch_knn_self: NULL pointer");
     BatchParams P;
     P.points = (const uint32_t*)points;
     P.out_idx = out_idx;
@@ -785,8 +835,14 @@ pg_status pg_batch_knn_self(pg_batch* b, const float* points, int32_t k, int32_t
     P.k = k;
     P.S = PL.S;
     P.lq = PL.lq;
-    hipStream_t s = (hipStream_t)stream;
-    switch (PL.d) {
+    P.queries = nullptr;
+    P.qoff = nullptr;
+    P.qitems = nullptr;
+    return P;
+}
+
+static pg_status batch_launch(pg_batch* b, const BatchParams& P, hipStream_t s) {
+    switch (b->plan.d) {
         case 2: return batch_k<2>(b, P, s);
         case 3: return batch_k<3>(b, P, s);
         case 5: return batch_k<5>(b, P, s);
@@ -794,13 +850,69 @@ pg_status pg_batch_knn_self(pg_batch* b, const float* points, int32_t k, int32_t
     }
 }
 
-pg_status pg_batch_status(const pg_batch* b, void* stream, int32_t* timed_out) {
+pg_status pg_batch_knn_self(pg_batch* b, const float* points, int32_t k, int32_t* out_idx,
+                            float* out_d2, void* stream) {
+    if (!b) return fail(PG_ERR_INVALID, "pg_batch_knn_self: handle is NULL");
+    if (k < 1 || k > 64) return fail(PG_ERR_INVALID, "pg_batch_knn_self: k must be in [1, 64]");
+    const BatchPlan& PL = b->plan;
+    if (PL.N > 0 && (!points || !out_idx || !out_d2)) return fail(PG_ERR_INVALID, "pg_batch_knn_self: NULL pointer");
+    return batch_launch(b, batch_params(b, points, k, out_idx, out_d2), (hipStream_t)stream);
+}
+
+pg_status pg_batch_knn(pg_batch* b, const float* points, const float* queries,
+                       const int64_t* q_offsets_host, int32_t k, int32_t* out_idx, float* out_d2,
+                       void* stream) {
+    if (!b) return fail(PG_ERR_INVALID, "pg_batch_knn: handle is NULL");
+    if (k < 1 || k > 64) return fail(PG_ERR_INVALID, "pg_batch_knn: k must be in [1, 64]");
+    if (!q_offsets_host) return fail(PG_ERR_INVALID, "pg_batch_knn: q_offsets_host is NULL");
+    BatchPlan& PL = b->plan;
+    const int C = PL.C;
+    const int64_t M = q_offsets_host[C];
+    if (PL.N > 0 && !points) return fail(PG_ERR_INVALID, "pg_batch_knn: points is NULL");
+    if (M > 0 && (!queries || !out_idx || !out_d2)) return fail(PG_ERR_INVALID, "pg_batch_knn: NULL pointer");
+    hipStream_t s = (hipStream_t)stream;
+    const bool same = (int)PL.qoff.size() == C + 1 &&
+                      std::equal(PL.qoff.begin(), PL.qoff.end(), q_offsets_host);
+    if (!same) {
+        // a new query layout: checked, its items planned in the clouds' size
+        // order, uploaded (synchronises)
+        if (q_offsets_host[0] != 0) return fail(PG_ERR_INVALID, "pg_batch_knn: q_offsets[0] must be 0");
+        for (int c = 0; c < C; c++)
+            if (q_offsets_host[c + 1] < q_offsets_host[c])
+                return fail(PG_ERR_INVALID, "pg_batch_knn: q_offsets must be non-decreasing");
+        if (M >= ((int64_t)1 << 31)) return fail(PG_ERR_INVALID, "pg_batch_knn: total queries must be < 2^31");
+        std::vector<int64_t> items(C + 1);
+        int64_t q = 0;
+        const int64_t per = (int64_t)kQB * PL.lq;
+        for (int t = 0; t < C; t++) {
+            items[t] = q;
+            const int c = PL.order[t];
+            q += (q_offsets_host[c + 1] - q_offsets_host[c] + per - 1) / per;
+        }
+        items[C] = q;
+        PG_HIP(hipMemcpyAsync(b->ws + PL.o_qoff, q_offsets_host, sizeof(int64_t) * (C + 1),
+                              hipMemcpyHostToDevice, s));
+        PG_HIP(hipMemcpyAsync(b->ws + PL.o_qitems, items.data(), sizeof(int64_t) * (C + 1),
+                              hipMemcpyHostToDevice, s));
+        PG_HIP(hipStreamSynchronize(s));
+        PL.qoff.assign(q_offsets_host, q_offsets_host + C + 1);
+        PL.q_items = q;
+    }
+    BatchParams P = batch_params(b, points, k, out_idx, out_d2);
+    P.queries = (const uint32_t*)queries;
+    P.qoff = (const int64_t*)(b->ws + PL.o_qoff);
+    P.qitems = (const int64_t*)(b->ws + PL.o_qitems);
+    P.total_items = C + PL.q_items;
+    return batch_launch(b, P, s);
+}
+
+pg_status pg_batch_status(const pg_batch* b, void* stream, int32_t* flags) {
     if (!b) return fail(PG_ERR_INVALID, "pg_batch_status: handle is NULL");
     uint32_t h[2] = {0, 0};
     hipStream_t s = (hipStream_t)stream;
     PG_HIP(hipMemcpyAsync(h, b->ws + b->plan.o_queue, sizeof(h), hipMemcpyDeviceToHost, s));
     PG_HIP(hipStreamSynchronize(s));
-    if (timed_out) *timed_out = (h[1] & 1u) ? 1 : 0;
+    if (flags) *flags = (int32_t)(h[1] & 3u);
     return PG_OK;
 }
 
@@ -907,16 +1019,15 @@ pg_status pg_batch_backward(pg_batch* b, const float* points, int32_t k, const i
     DevBuf inv(s), acc(s), maxes(s), wbuf(s);
     PG_TRY(inv.alloc(sizeof(int32_t) * (size_t)N));
     PG_TRY(acc.alloc(sizeof(unsigned long long) * (size_t)N * d));
-    PG_TRY(maxes.alloc(sizeof(uint32_t) * 2));
+    PG_TRY(maxes.alloc(sizeof(uint32_t) * 2 * (size_t)C));
     PG_TRY(wbuf.alloc(sizeof(unsigned long long) * (size_t)items * kBwdWin * d));
     PG_HIP(hipMemsetAsync(acc.p, 0, sizeof(unsigned long long) * (size_t)N * d, s));
-    PG_HIP(hipMemsetAsync(maxes.p, 0, sizeof(uint32_t) * 2, s));
+    PG_HIP(hipMemsetAsync(maxes.p, 0, sizeof(uint32_t) * 2 * (size_t)C, s));
     hipLaunchKernelGGL(bwd_inv_kernel, dim3((unsigned)items), dim3(kNT), 0, s, desc,
                        (const int64_t*)b->bstart_dev, C, pidx, inv.as<int32_t>());
     PG_LAUNCH_CHECK();
-    const int64_t P = N * k;
-    hipLaunchKernelGGL(bwd_scale_kernel, dim3(cdiv(P, kNT) < 4096u ? cdiv(P, kNT) : 4096u), dim3(kNT),
-                       0, s, grad_d2, d2, P, maxes.as<uint32_t>());
+    hipLaunchKernelGGL(bwd_scale_kernel, dim3((unsigned)items), dim3(kNT), 0, s, desc,
+                       (const int64_t*)b->bstart_dev, C, k, grad_d2, d2, maxes.as<uint32_t>());
     PG_LAUNCH_CHECK();
     const size_t lds = sizeof(unsigned long long) * (size_t)kBwdWin * d;
     auto main_kernel = d == 2 ? bwd_main_kernel<2>
@@ -929,7 +1040,8 @@ pg_status pg_batch_backward(pg_batch* b, const float* points, int32_t k, const i
     PG_LAUNCH_CHECK();
     hipLaunchKernelGGL(bwd_finish_kernel, dim3((unsigned)items), dim3(kNT), 0, s, desc,
                        (const int64_t*)b->bstart_dev, C, pidx, d, wbuf.as<unsigned long long>(),
-                       acc.as<unsigned long long>(), maxes.as<uint32_t>(), grad_points);
+                       acc.as<unsigned long long>(), maxes.as<uint32_t>(),
+                       (uint32_t*)(b->ws + PL.o_queue) + 1, grad_points);
     PG_LAUNCH_CHECK();
     return PG_OK;
 }

@@ -36,6 +36,23 @@ class _SelfKnn(torch.autograd.Function):
         return gx, None, None
 
 
+class _BatchQueryKnn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, q, x, k, batch, q_offsets):
+        idx, d2 = batch.knn(x.detach(), q.detach(), q_offsets, k)
+        ctx.save_for_backward(q, x, idx)
+        ctx.mark_non_differentiable(idx)
+        return d2, idx
+
+    @staticmethod
+    def backward(ctx, g_d2, g_idx):
+        q, x, idx = ctx.saved_tensors
+        if g_d2 is None:
+            return None, None, None, None, None
+        gq, gx = B.knn_backward(q.detach(), x.detach(), idx, g_d2)
+        return gq, gx, None, None, None
+
+
 class _QueryKnn(torch.autograd.Function):
     @staticmethod
     def forward(ctx, q, x, k, leaf):
@@ -55,15 +72,25 @@ class _QueryKnn(torch.autograd.Function):
 
 
 def knn_sqdist(x: torch.Tensor, k: int, offsets=None, queries: torch.Tensor | None = None,
-               batch: "B.BatchKnn | None" = None, leaf: int = 16):
+               batch: "B.BatchKnn | None" = None, leaf: int = 16, q_offsets=None):
     """k nearest squared distances and neighbour rows.
 
     * ``queries is None``: every point of ``x`` queries its own cloud
       (``offsets`` delimit the clouds; None = one cloud).  Returns
       (d2 [N][k], idx [N][k] global rows); gradients flow to ``x`` through
       both roles (query and neighbour).
-    * otherwise: k-NN of ``queries`` over ``x``; gradients flow to both.
+    * ``queries`` with ``q_offsets``: cloud c's queries (rows
+      [q_offsets[c], q_offsets[c+1]) of ``queries``) search cloud c of ``x``
+      (``offsets``), all clouds in one persistent launch; idx are global
+      rows of ``x``; gradients flow to both.
+    * ``queries`` alone: k-NN of ``queries`` over all of ``x``.
     """
+    if queries is not None and q_offsets is not None:
+        if batch is None:
+            if offsets is None:
+                offsets = [0, x.shape[0]]
+            batch = B.BatchKnn(offsets, x.shape[1], device=x.device)
+        return _BatchQueryKnn.apply(queries, x, k, batch, q_offsets)
     if queries is not None:
         return _QueryKnn.apply(queries, x, k, leaf)
     if batch is None:

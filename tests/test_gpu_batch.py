@@ -291,3 +291,155 @@ def test_backward_float_atomics(pg, dev, self_mode):
         assert np.all(np.abs(got - ref) <= 1e-4 * np.abs(ref) + 1e-4 * scale)
     if not self_mode:
         assert np.array_equal(gq_f, gq_d)  # the per-query sums are the same kernel
+
+
+# --- separate query sets per cloud (pg_batch_knn) ---------------------------
+
+def query_sets(seed, offs, d=3):
+    """Queries per cloud: uneven counts, clouds without queries, query-only
+    clouds (no points), queries near the cloud's points and far from them."""
+    g = np.random.default_rng(seed)
+    C = len(offs) - 1
+    counts = np.floor(np.exp(g.uniform(0, np.log(2000), size=C))).astype(np.int64)
+    counts[6:9] = 0          # clouds with points but no queries
+    counts[0] = 37           # the empty cloud is queried (padding rows)
+    qo = np.zeros(C + 1, np.int64)
+    qo[1:] = np.cumsum(counts)
+    q = (g.standard_normal((int(qo[-1]), d)) * 1.2).astype(np.float32)
+    return q, qo
+
+
+def oracle_query_sets(pts, offs, q, qo, k):
+    oi = np.full((len(q), k), -1, np.int64)
+    od = np.full((len(q), k), np.inf, np.float64)
+    for c in range(len(offs) - 1):
+        a, b = int(offs[c]), int(offs[c + 1])
+        qa, qb = int(qo[c]), int(qo[c + 1])
+        if qb == qa or b == a:
+            continue
+        ids, dist = oracle.knn_brute(pts[a:b], q[qa:qb], k, nthreads=8)
+        oi[qa:qb] = np.where(ids >= 0, ids + a, -1)
+        od[qa:qb] = dist
+    return oi, od
+
+
+@pytest.mark.parametrize("d,k", [(3, 10), (3, 16), (2, 1), (5, 7), (8, 33)])
+def test_batched_query_sets(pg, dev, d, k):
+    say(f"query sets d={d} k={k}")
+    if d == 3:
+        pts, offs = small_clouds(21 + k, C=120)
+    else:
+        g = np.random.default_rng(22 + d)
+        sizes = g.integers(0, 2500, size=50)
+        sizes[0] = 0
+        offs = np.zeros(51, np.int64)
+        offs[1:] = np.cumsum(sizes)
+        pts = g.standard_normal((int(offs[-1]), d)).astype(np.float32)
+    q, qo = query_sets(30 + d + k, offs, d)
+    B = pg.BatchKnn(offs, d, device=dev)
+    gi, gd = host(*B.knn(to_dev(pts, dev), to_dev(q, dev), qo, k))
+    assert not B.timed_out()
+    oi, od = oracle_query_sets(pts, offs, q, qo, k)
+    assert_float_close(gi, gd, oi, od, pts, q)
+    # the self form on the same handle is unchanged, and the query form again
+    si, sd = host(*B.knn_self(to_dev(pts, dev), k))
+    oi2, od2 = oracle_per_cloud(pts, offs, k)
+    assert_float_close(si, sd, oi2, od2, pts, pts)
+    gi2, gd2 = host(*B.knn(to_dev(pts, dev), to_dev(q, dev), qo, k))
+    assert np.array_equal(gi2, gi) and np.array_equal(gd2, gd)
+
+
+def test_batched_query_sets_graph_replays_and_new_layout(pg, dev):
+    import torch
+    pts, offs = small_clouds(41, C=90)
+    q, qo = query_sets(42, offs)
+    k = 8
+    x, qd = to_dev(pts, dev), to_dev(q, dev)
+    B = pg.BatchKnn(offs, 3, device=dev)
+    eager = host(*B.knn(x, qd, qo, k))  # uploads the query layout
+    idx = torch.empty((len(q), k), dtype=torch.int32, device=dev)
+    d2 = torch.empty((len(q), k), dtype=torch.float32, device=dev)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        B.knn(x, qd, qo, k, out=(idx, d2))
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        B.knn(x, qd, qo, k, out=(idx, d2))
+    for rep in range(3):
+        idx.fill_(-7)
+        d2.fill_(-1.0)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        got = host(idx, d2)
+        assert np.array_equal(got[0], eager[0]) and np.array_equal(got[1], eager[1]), rep
+        _ = (x * 2).sum().item()
+    # a different layout of the same queries (uploaded again)
+    qo2 = qo.copy()
+    qo2[1:-1] = np.minimum(qo[1:-1] + 5, qo[-1])
+    qo2 = np.maximum.accumulate(qo2)
+    gi, gd = host(*B.knn(x, qd, qo2, k))
+    oi, od = oracle_query_sets(pts, offs, q, qo2, k)
+    assert_float_close(gi, gd, oi, od, pts, q)
+
+
+def test_batched_query_sets_gradient(pg, dev):
+    """knn_sqdist with per-cloud query sets: gradients to queries and points
+    against the FP64 closed form with the GPU's neighbour sets."""
+    import torch
+
+    from paper_2207_01834_amd.diff import knn_sqdist
+    pts, offs = small_clouds(51, C=40, hi=1500)
+    q, qo = query_sets(52, offs)
+    k = 6
+    x = to_dev(pts, dev).requires_grad_(True)
+    qq = to_dev(q, dev).requires_grad_(True)
+    d2, idx = knn_sqdist(x, k, offsets=offs, queries=qq, q_offsets=qo)
+    W = np.random.default_rng(53).standard_normal((len(q), k)).astype(np.float32)
+    real = host(idx)[0] >= 0
+    # padding slots (query-only clouds) hold +inf: left out of the loss
+    live = torch.where(to_dev(real, dev), d2, torch.zeros_like(d2))
+    (live * to_dev(W * real, dev)).sum().backward()
+    gq_ref, gx_ref = grad_closed_form(q, pts, host(idx)[0].astype(np.int64), W * real)
+    for got, ref in ((host(qq.grad)[0], gq_ref), (host(x.grad)[0], gx_ref)):
+        scale = np.abs(ref).max()
+        assert np.all(np.abs(got - ref) <= 1e-4 * np.abs(ref) + 1e-4 * scale)
+
+
+def test_batched_backward_mixed_scales_and_nonfinite(pg, dev):
+    """Clouds of very different sizes in one batch (unit sphere, and scaled by
+    1e3 and 1e-3): each cloud's gradients to a purely relative bar away from
+    zero (the fixed-point scale is per cloud); a cloud whose gradient input
+    holds a NaN gets NaN gradients and raises the status bit, the others are
+    unaffected."""
+    sizes = np.array([3000, 2500, 2000, 1500], dtype=np.int64)
+    pts, offs = datagen.sphere_clouds(sizes, 61)
+    pts = pts.astype(np.float64)
+    pts[offs[1]:offs[2]] *= 1e3
+    pts[offs[2]:offs[3]] *= 1e-3
+    pts = pts.astype(np.float32)
+    k = 10
+    G = np.random.default_rng(62).standard_normal((len(pts), k)).astype(np.float32)
+    B = pg.BatchKnn(offs, 3, device=dev)
+    x = to_dev(pts, dev)
+    idx, d2 = B.knn_self(x, k)
+    grad = host(B.backward(x, idx, d2, to_dev(G, dev)))[0].astype(np.float64)
+    assert not B.backward_nonfinite()
+    idx_h = host(idx)[0].astype(np.int64)
+    gq, gx = grad_closed_form(pts, pts, idx_h, G)
+    cf = gq + gx
+    for c in range(len(sizes)):
+        a, b = int(offs[c]), int(offs[c + 1])
+        ref, got = cf[a:b], grad[a:b]
+        big = np.abs(ref) >= 1e-3 * np.abs(ref).max()
+        rel = np.abs(got - ref)[big] / np.abs(ref)[big]
+        assert rel.max() <= 1e-4, (c, rel.max())
+    Gn = G.copy()
+    Gn[offs[3] + 5, 2] = np.nan
+    grad = host(B.backward(x, idx, d2, to_dev(Gn, dev)))[0]
+    assert B.backward_nonfinite()
+    assert np.isnan(grad[offs[3]:offs[4]]).all()
+    assert np.isfinite(grad[:offs[3]]).all()
