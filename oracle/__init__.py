@@ -13,6 +13,8 @@ Parts (each function cites the passage it follows):
                       (Algorithms 3 and 4), in Python;
   * ``grad``       -- the closed-form FP64 gradient of summed k-NN squared
                       distances and central finite differences, in NumPy;
+  * ``KdTree.wspd`` -- the well-separated pair decomposition from the
+                      kd-tree (C, ``or_wspd``);
   * ``spatial_tree`` -- the kd-tree by spatial-median splits, split until
                       a node holds at most ``leaf`` points (C,
                       ``or_sp_build``);
@@ -72,6 +74,8 @@ def lib():
         L.or_sp_depth.restype = i32
         L.or_sp_export.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
         L.or_sp_export.restype = None
+        L.or_wspd.argtypes = [vp, ctypes.c_double, vp, i64]
+        L.or_wspd.restype = i64
         L.or_range_brute.argtypes = [vp, vp, vp, i64, i32, i32, vp, i64, vp, vp, vp]
         L.or_range_brute.restype = i32
         L.or_kd_range.argtypes = [vp, vp, vp, vp, i64, vp, vp, vp, vp]
@@ -236,6 +240,24 @@ class KdTree:
         if any(rc != 0 for rc in rcs):
             raise ValueError("or_kd_knn: bad arguments")
         return out_id, out_d, counters.sum(axis=0)
+
+    def wspd(self, s=2.0):
+        """The well-separated pair decomposition generated from this tree
+        (leaf size 1): int64 [P][2] heap node pairs (a from the first
+        child's side of the internal node that started the pairing), in the
+        order the recursion emits them."""
+        cnt = lib().or_wspd(self._h, float(s), None, 0)
+        if cnt < 0:
+            raise ValueError("or_wspd: s must be positive and finite, and the leaf size 1")
+        out = np.empty((cnt, 2), dtype=np.int64)
+        lib().or_wspd(self._h, float(s), _ptr(out), cnt)
+        return out
+
+    def node_range(self, h):
+        """Leaf-order positions [lo, hi) of heap node h."""
+        l = int(h).bit_length() - 1
+        j = int(h) - (1 << l)
+        return (j * self.n) >> l, ((j + 1) * self.n) >> l
 
     def range(self, boxes, ids=None, alive=None):
         """Range search on the tree (boxes inside the query report whole,

@@ -8,7 +8,10 @@ SO = os.path.join(HERE, "liboracle.so")
 
 def build(verbose: bool = False) -> str:
     src = os.path.join(HERE, "oracle.c")
-    cmd = ["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-Wall", "-Wno-unused-function",
+    # no contraction of a * b + c into one rounding: the WSPD test's squares
+    # and sums are separate IEEE operations
+    cmd = ["gcc", "-O2", "-std=gnu11", "-ffp-contract=off", "-fPIC", "-shared", "-Wall",
+           "-Wno-unused-function",
            "-o", SO + ".tmp", src, "-lpthread", "-lm"]
     if verbose:
         print(" ".join(cmd))

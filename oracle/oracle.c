@@ -41,6 +41,10 @@
  *                     halving of each node's point box), split until a node
  *                     holds at most `leaf` points, with the readings stated
  *                     at its definition.
+ *   or_wspd        -- the well-separated pair decomposition generated from the
+ *                     kd-tree (Section 2, second module), by the recursive
+ *                     pairing of Callahan and Kosaraju, with the readings
+ *                     stated at its definition.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -686,4 +690,95 @@ void or_sp_export(const or_sp_tree* T, double* split, int32_t* dim, int64_t* chi
     if (hi) memcpy(hi, T->hi, sizeof(int64_t) * c);
     if (level) memcpy(level, T->level, sizeof(int32_t) * c);
     if (perm && T->n > 0) memcpy(perm, T->perm, sizeof(int64_t) * (size_t)T->n);
+}
+
+/* ------------------------------------------------------------------------ */
+/* O9: well-separated pair decomposition (WSPD) from the kd-tree (Section 2, */
+/* second module, after Callahan and Kosaraju).  Readings:                  */
+/*  - the tree is the object-median tree with leaf size 1, so every leaf     */
+/*    holds at most one point and the pairs cover every pair of distinct   */
+/*    points exactly once;                                                  */
+/*  - a node's ball is centred at the centre of its bounding box, with the  */
+/*    half diagonal as radius; nodes a and b are well separated for s when  */
+/*    the distance of the centres is at least (s + 2) r, r the larger of    */
+/*    the two radii (balls of radius r around each set, at least s r        */
+/*    apart), tested on squares: |c_a - c_b|^2 >= (s + 2)^2 r^2, every      */
+/*    quantity in double: half side (hi - lo) * 0.5, centre (lo + hi) * 0.5,*/
+/*    sums over dimensions 0..d-1 in order;                                 */
+/*  - a pair that is not separated is refined by splitting the node with    */
+/*    the larger radius (the first on ties; never a leaf), and pairs with  */
+/*    an empty node are dropped;                                            */
+/*  - every internal node pairs its two children, then both children are  */
+/*    processed the same way.                                               */
+/* Output: pairs (a, b) of heap node indices, a from the first child's side.*/
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    const or_tree* T; double s2; int64_t cnt, cap; int64_t* out;
+} wspd_ctx;
+
+static int64_t node_points(const or_tree* T, int64_t h) {
+    int l = 63 - __builtin_clzll((unsigned long long)h);
+    int64_t j = h - ((int64_t)1 << l);
+    return node_lo(T->n, l, j + 1) - node_lo(T->n, l, j);
+}
+
+static double half_diag2(const or_tree* T, int64_t h) {
+    double r2 = 0.0;
+    for (int c = 0; c < T->d; c++) {
+        double t = (T->bmax[h * T->d + c] - T->bmin[h * T->d + c]) * 0.5;
+        r2 += t * t;
+    }
+    return r2;
+}
+
+static double centre_gap2(const or_tree* T, int64_t a, int64_t b) {
+    double g2 = 0.0;
+    for (int c = 0; c < T->d; c++) {
+        double ca = (T->bmin[a * T->d + c] + T->bmax[a * T->d + c]) * 0.5;
+        double cb = (T->bmin[b * T->d + c] + T->bmax[b * T->d + c]) * 0.5;
+        double t = ca - cb;
+        g2 += t * t;
+    }
+    return g2;
+}
+
+static void wspd_pair(wspd_ctx* C, int64_t a, int64_t b) {
+    const or_tree* T = C->T;
+    if (node_points(T, a) == 0 || node_points(T, b) == 0) return;
+    double ra = half_diag2(T, a), rb = half_diag2(T, b);
+    double r2 = ra > rb ? ra : rb;
+    if (centre_gap2(T, a, b) >= C->s2 * r2) {
+        if (C->out && C->cnt < C->cap) {
+            C->out[2 * C->cnt] = a;
+            C->out[2 * C->cnt + 1] = b;
+        }
+        C->cnt++;
+        return;
+    }
+    int64_t first_leaf = (int64_t)1 << T->L;
+    int split_a = (ra >= rb && a < first_leaf) || b >= first_leaf;
+    if (split_a) {
+        wspd_pair(C, 2 * a, b);
+        wspd_pair(C, 2 * a + 1, b);
+    } else {
+        wspd_pair(C, a, 2 * b);
+        wspd_pair(C, a, 2 * b + 1);
+    }
+}
+
+static void wspd_node(wspd_ctx* C, int64_t h) {
+    if (h >= ((int64_t)1 << C->T->L)) return;
+    wspd_pair(C, 2 * h, 2 * h + 1);
+    wspd_node(C, 2 * h);
+    wspd_node(C, 2 * h + 1);
+}
+
+/* Returns the number of pairs (writing at most cap of them to out[cap][2]);
+ * -1 for bad arguments (s not positive and finite, or leaf size above 1). */
+int64_t or_wspd(const or_tree* T, double s, int64_t* out, int64_t cap) {
+    if (!(s > 0.0) || !(s < INFINITY)) return -1;
+    if ((T->n + ((int64_t)1 << T->L) - 1) >> T->L > 1) return -1;
+    wspd_ctx C = {T, (s + 2.0) * (s + 2.0), 0, cap, out};
+    if (T->L > 0) wspd_node(&C, 1);
+    return C.cnt;
 }
