@@ -198,6 +198,33 @@ pg_status pg_tree_info(const pg_tree* t, int64_t* n, int32_t* d, int32_t* leaf,
 pg_status pg_tree_export(const pg_tree* t, void* splits_host, int32_t* perm_host,
                          void* stream);
 
+/* Well-separated pair decomposition of the tree's points (Section 2's
+ * second module generates it from the kd-tree; the recursive pairing of
+ * Callahan and Kosaraju).  Readings: a node's ball is centred at its
+ * bounding box's centre with the half diagonal as radius; nodes a, b are
+ * well separated for s when |c_a - c_b|^2 >= (s + 2)^2 r^2, r the larger
+ * radius (in double: half side (hi - lo) * 0.5, centre (lo + hi) * 0.5,
+ * sums over dimensions in order, no fused multiply-adds); every internal
+ * node starts with the pair of its children; an unseparated pair splits the
+ * node of larger radius (the first on ties, never a leaf); pairs with an
+ * empty node are dropped.  With leaf size 1 every pair of distinct points
+ * lies in exactly one pair.
+ *   t          : a tree from pg_kdtree_build with leaf 1 (PG_ERR_UNSUPPORTED
+ *                otherwise)
+ *   s          : separation, positive and finite
+ *   out_pairs  : [capacity][2] uint32, device, 8-byte aligned: heap node
+ *                indices (a, b), a on the first child's side of the node
+ *                that started the pairing; node 2^l + j holds leaf-order
+ *                positions [floor(j n/2^l), floor((j+1) n/2^l)) (rows via
+ *                pg_tree_export's perm); pairs come round by round of the
+ *                refinement, in a fixed order
+ *   count_host : (host) receives the number of pairs
+ * When there are more than `capacity` pairs the first `capacity` are
+ * written, *count_host is set and PG_ERR_INVALID returned (capacity 0 only
+ * counts).  Synchronises once per refinement round. */
+pg_status pg_wspd(const pg_tree* t, double s, uint32_t* out_pairs, int64_t capacity,
+                  int64_t* count_host, void* stream);
+
 /* Releases the tree (stream-ordered on the stream it was built on). */
 void pg_tree_free(pg_tree* t);
 

@@ -59,6 +59,7 @@ SIGNATURES = {
     "pg_tree_info": (i32, [vp, P64, P32, P32, P32, P32]),
     "pg_tree_export": (i32, [vp, vp, vp, vp]),
     "pg_tree_nodes": (i32, [vp, P64, P64]),
+    "pg_wspd": (i32, [vp, ctypes.c_double, vp, i64, P64, vp]),
     "pg_tree_export_nodes": (i32, [vp, vp, vp, vp, vp, vp, vp, vp, vp]),
     "pg_tree_free": (None, [vp]),
     "pg_range_count": (i32, [vp, vp, i64, vp, vp, P64, vp]),
@@ -297,6 +298,24 @@ class KdTree:
         else:
             check(st)
         return off, out[:total.value]
+
+    def wspd(self, s: float = 2.0, capacity: int = None):
+        """Well-separated pair decomposition (tree built with leaf 1): int32
+        [P][2] heap node pairs on the device.  One call when the pairs fit
+        ``capacity`` (default: a guess from the point count), else a second
+        with the exact size."""
+        if capacity is None:
+            capacity = 24 * self.n + 1024
+        out = torch.empty((max(capacity, 1), 2), dtype=torch.int32, device=self.device)
+        cnt = ctypes.c_int64()
+        st = lib().pg_wspd(self._h, float(s), ctypes.c_void_p(out.data_ptr()), capacity,
+                           ctypes.byref(cnt), stream_ptr(self.device))
+        if st != 0 and cnt.value > capacity:
+            out = torch.empty((max(cnt.value, 1), 2), dtype=torch.int32, device=self.device)
+            st = lib().pg_wspd(self._h, float(s), ctypes.c_void_p(out.data_ptr()), cnt.value,
+                               ctypes.byref(cnt), stream_ptr(self.device))
+        check(st)
+        return out[:cnt.value]
 
     def counts(self):
         """(nodes, leaves) of the tree."""

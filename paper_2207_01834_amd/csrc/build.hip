@@ -469,11 +469,11 @@ pg_status build_from_keys(uint32_t* kA, int32_t* iA, uint32_t* kB, int32_t* iB, 
 
 namespace {
 // Leaf boxes of a tree with explicit leaf offsets, from its points, as
-// order-preserving keys first (min starts at all ones, max at zero, so an
-// empty leaf keeps the inverted box), then converted to coordinates.
-__global__ void box_keys_init_kernel(uint32_t* __restrict__ box, int64_t leaves, int d) {
+// order-preserving keys first (starting from the empty box, which an empty
+// leaf keeps), then converted to coordinates.
+__global__ void box_keys_init_kernel(uint32_t* __restrict__ box, int64_t leaves, int d, int fl) {
     const int64_t e = (int64_t)blockIdx.x * kNT + threadIdx.x;
-    if (e < leaves * 2 * d) box[e] = (e % (2 * d)) < d ? 0xffffffffu : 0u;
+    if (e < leaves * 2 * d) box[e] = (e % (2 * d)) < d ? empty_min_key(fl != 0) : empty_max_key(fl != 0);
 }
 
 // One lane per leaf-order position.  Positions of a wave are consecutive,
@@ -528,7 +528,7 @@ pg_status offset_boxes(pg_tree* T, hipStream_t s) {
     const int64_t count = leaves * 2 * T->d;
     const int fl = T->dtype == PG_FLOAT32 ? 1 : 0;
     hipLaunchKernelGGL(box_keys_init_kernel, dim3(cdiv(count, kNT)), dim3(kNT), 0, s, T->bbox,
-                       leaves, T->d);
+                       leaves, T->d, fl);
     PG_LAUNCH_CHECK();
     if (T->n > 0) {
         hipLaunchKernelGGL(offset_leaf_box_kernel, dim3(cdiv(T->n, kNT)), dim3(kNT), 0, s,

@@ -392,7 +392,10 @@ __device__ inline void block_subtree(const uint32_t* in, const int32_t* in_idx, 
             mn = k < mn ? k : mn;
             mx = k > mx ? k : mx;
         }
-        if (llo == lhi) mn = mx = 0x80000000u;  // empty leaf (leaf size 1 only)
+        if (llo == lhi) {  // empty leaf (leaf size 1 only)
+            mn = empty_min_key(fl);
+            mx = empty_max_key(fl);
+        }
         bbox[jj * 2 * d + c] = key_to_coord(mn, fl);
         bbox[jj * 2 * d + d + c] = key_to_coord(mx, fl);
     }

@@ -81,6 +81,13 @@ __host__ __device__ inline uint32_t key_to_coord(uint32_t key, bool fl) {
     return (key & 0x80000000u) ? (key & 0x7fffffffu) : ~key;
 }
 
+// Keys of an empty box's min and max: at or above / at or below every valid
+// coordinate (int32: [-2^29, 2^29); float32: |x| <= 1e18), so min / max
+// unions ignore the box, and its coordinates (int32 2^29 - 1 and -2^29,
+// float32 +-FLT_MAX) keep the box-distance arithmetic in range.
+__host__ __device__ inline uint32_t empty_min_key(bool fl) { return fl ? 0xff7fffffu : 0x9fffffffu; }
+__host__ __device__ inline uint32_t empty_max_key(bool fl) { return fl ? 0x00800000u : 0x60000000u; }
+
 // Leaf-order position where node j of level l starts: floor(j n / 2^l).
 // Exact in 64 bits: n < 2^31 and j <= 2^32 (levels <= 31).
 __host__ __device__ inline int64_t node_start(int64_t n, int l, int64_t j) {

@@ -568,22 +568,16 @@ __global__ void leaf_index_kernel(uint4* __restrict__ xn, uint32_t first, uint32
     }
 }
 
-// Node boxes as coordinates (an empty node: min above max at the ends of the
-// coordinate range, which every box query misses).
+// Node boxes as coordinates (an empty node: the empty box, which every box
+// query misses).
 __global__ void node_box_kernel(const uint32_t* __restrict__ key, const uint32_t* __restrict__ cnt,
                                 int64_t N, int d, int fl, uint32_t* __restrict__ nbox) {
     const int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x;
     if (i >= N * 2 * d) return;
     const int64_t u = i / (2 * d);
     const int w = (int)(i % (2 * d));
-    uint32_t v;
-    if (cnt[u] == 0) {
-        const bool mn = w < d;
-        v = fl ? (mn ? 0x7f7fffffu : 0xff7fffffu) : (mn ? 0x7fffffffu : 0x80000000u);
-    } else {
-        v = key_to_coord(key[i], fl != 0);
-    }
-    nbox[i] = v;
+    const uint32_t k = cnt[u] == 0 ? (w < d ? empty_min_key(fl != 0) : empty_max_key(fl != 0)) : key[i];
+    nbox[i] = key_to_coord(k, fl != 0);
 }
 
 __global__ void set_i64_kernel(int64_t* __restrict__ p, int64_t v) {
@@ -696,10 +690,8 @@ __global__ void xrefresh_kernel(uint4* __restrict__ xn, uint32_t first, uint32_t
     xn[u] = r;
     const uint32_t cu = ncnt[u];
     for (int w = 0; w < 2 * d; w++) {
-        const bool mn = w < d;
-        nbox[(size_t)u * 2 * d + w] =
-            cu == 0 ? (fl ? (mn ? 0x7f7fffffu : 0xff7fffffu) : (mn ? 0x7fffffffu : 0x80000000u))
-                    : key_to_coord(bk[w], fl != 0);
+        const uint32_t k = cu == 0 ? (w < d ? empty_min_key(fl != 0) : empty_max_key(fl != 0)) : bk[w];
+        nbox[(size_t)u * 2 * d + w] = key_to_coord(k, fl != 0);
     }
 }
 
