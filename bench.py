@@ -45,6 +45,49 @@ def bytes_per_query(dist_bytes):
     return 4 * D + K * (4 + dist_bytes) + 4 * N_INT + 4 * (D + 1) * N_PTS
 
 
+# Oracle visit counts (internal nodes, points) per query of the other
+# benchmarked searches (``python -m oracle.visit_counts --workloads``):
+# 5-D clustered queries (k = 5), fresh uniform 3-D queries of the
+# batch-dynamic rounds over 10M points (k = 10), all-points searches within
+# the sphere clouds (k = 16, size-weighted over every 16th cloud in size
+# order: 256 clouds, 3.07M points).
+VISITS = {
+    "clustered_5d_queries": (115.277, 332.081),
+    "uniform_3d_fresh_queries": (41.89, 96.63),
+    "sphere_clouds_all_points": (21.653, 83.576),
+}
+
+
+def knn_bytes(d, k, id_bytes, dist_bytes, n_int, n_pts):
+    """Algorithmic bytes of one k-NN query: the query, its output row, the
+    split values of the visited internal nodes and the records of the
+    scanned points (the oracle's visits)."""
+    return 4 * d + k * (id_bytes + dist_bytes) + 4 * n_int + 4 * (d + 1) * n_pts
+
+
+def build_bytes(n, d, L):
+    """Algorithmic bytes of the object-median build the paper describes as
+    O(n) per level: ingest (rows read, key planes and rows written) plus, per
+    level, one key read and one record read and write."""
+    return n * (4 * d + 4 * (d + 1)) + L * n * (4 + 8 * (d + 1))
+
+
+def tree_levels(n, leaf=16):
+    L = 0
+    while -(-n // (1 << L)) > leaf:
+        L += 1
+    return L
+
+
+def roof(nbytes, ms, kernel, model):
+    """Roofline object of one timed call: algorithmic bytes over its time
+    against the HBM peak."""
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "kernel": kernel, "achieved": gbs, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS, "algorithmic_bytes": nbytes,
+            "model": model}
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -205,7 +248,11 @@ def form_static_float(torch, pg, datagen, dev):
     knn_ms = timed(torch, lambda: holder["t"].knn_all(K, out=(idx, dist)))
     return {"workload": "3-D n=10M float32 uniform, k=10, leaf 16, all points",
             "build_ms": build_ms, "knn_ms": knn_ms, "knn_qps": N / (knn_ms * 1e-3),
-            "build_mpts_s": N / (build_ms * 1e-3) / 1e6}
+            "build_mpts_s": N / (build_ms * 1e-3) / 1e6,
+            "roofline": roof(bytes_per_query(4) * N, knn_ms, "knn_static_kernel (all-points)",
+                             "headline visit counts, float32 distances"),
+            "build_roofline": roof(build_bytes(N, D, tree_levels(N)), build_ms, "build (all kernels)",
+                                   "n(8d+4) + L n (8d+12)")}
 
 
 def form_graph(torch, pg, datagen, dev):
@@ -218,11 +265,13 @@ def form_graph(torch, pg, datagen, dev):
     dist = torch.empty((N, K), dtype=torch.int64, device=dev)
     graph_ms = timed(torch, lambda: t.knn_graph(K, out=(idx, dist)))
     return {"workload": "k-NN graph, 3-D n=10M int32 uniform, k=10 other points per point, leaf 16",
-            "graph_ms": graph_ms, "edges_per_s": N * K / (graph_ms * 1e-3)}
+            "graph_ms": graph_ms, "edges_per_s": N * K / (graph_ms * 1e-3),
+            "roofline": roof(bytes_per_query(8) * N, graph_ms, "knn_static_kernel (all-points, own "
+                             "point excluded)", "headline visit counts")}
 
 
 def form_spatial(torch, pg, datagen, dev):
-    """Spatial-median splits at the object-median tree's depth, each node
+    """Spatial-median splits down to at most 16 points per leaf, each node
     cutting its cell or the bounding box of its own points, on the headline
     points and on the 5-D clustered set: build and k-NN beside the
     object-median numbers of the other forms."""
@@ -239,10 +288,16 @@ def form_spatial(torch, pg, datagen, dev):
         t = holder["t"]
         k_ms = timed(torch, lambda: t.knn_all(K, out=(idx, dist)))
         sizes = np.diff(t.offsets())
+        nodes, leaves = t.counts()
         out["uniform_3d" + tag] = {"workload": f"3-D n=10M int32 uniform, k=10, leaf 16, all points, "
                                                f"nodes cut their {space if space == 'cell' else 'point box'}",
                                    "build_ms": b_ms, "knn_ms": k_ms, "max_leaf": int(sizes.max()),
-                                   "empty_leaves": int((sizes == 0).sum())}
+                                   "empty_leaves": int((sizes == 0).sum()), "nodes": nodes,
+                                   "levels": t.levels,
+                                   "roofline": roof(bytes_per_query(8) * N, k_ms,
+                                                    "knn_static_kernel (explicit-node walk)",
+                                                    "the object-median search's visit counts (the "
+                                                    "algorithm's bytes, not this tree's)")}
         del t, holder["t"]
     del idx, dist, x
     f, q = datagen.clustered(N, 5, seed=3, n_queries=1_000_000, query_seed=33)
@@ -254,10 +309,16 @@ def form_spatial(torch, pg, datagen, dev):
         t = holder["t"]
         k_ms = timed(torch, lambda: t.knn(qd, 5), reps=reps)
         sizes = np.diff(t.offsets())
+        nodes, leaves = t.counts()
+        vi, vp = VISITS["clustered_5d_queries"]
         out["clustered_5d" + tag] = {"workload": f"5-D n=10M clustered float32, 1M queries, k=5, leaf 16, "
                                                  f"nodes cut their {space if space == 'cell' else 'point box'}",
                                      "build_ms": b_ms, "knn_ms": k_ms, "max_leaf": int(sizes.max()),
-                                     "empty_leaves": int((sizes == 0).sum())}
+                                     "empty_leaves": int((sizes == 0).sum()), "nodes": nodes,
+                                     "levels": t.levels,
+                                     "roofline": roof(knn_bytes(5, 5, 4, 4, vi, vp) * len(q), k_ms,
+                                                      "knn_static_kernel (explicit-node walk)",
+                                                      "the object-median search's visit counts")}
         del t, holder["t"]
     return out
 
@@ -271,9 +332,45 @@ def form_clustered(torch, pg, datagen, dev):
     holder = {}
     build_ms = timed(torch, lambda: holder.__setitem__("t", pg.kdtree_build(x, leaf=LEAF)))
     knn_ms = timed(torch, lambda: holder["t"].knn(qd, 5))
+    vi, vp = VISITS["clustered_5d_queries"]
     return {"workload": "5-D n=10M clustered float32, 1M queries, k=5, leaf 16",
             "build_ms": build_ms, "knn_ms": knn_ms, "knn_qps": len(q) / (knn_ms * 1e-3),
-            "build_mpts_s": N / (build_ms * 1e-3) / 1e6}
+            "build_mpts_s": N / (build_ms * 1e-3) / 1e6,
+            "roofline": roof(knn_bytes(5, 5, 4, 4, vi, vp) * len(q), knn_ms,
+                             "knn_static_kernel (queries ordered by leaf)",
+                             f"oracle visits {vi} internal nodes, {vp} points per query"),
+            "build_roofline": roof(build_bytes(N, 5, tree_levels(N)), build_ms, "build (all kernels)",
+                                   "n(8d+4) + L n (8d+12)")}
+
+
+def bdl_insert_bytes(before, after, m, d=3, X=1 << 14):
+    """Algorithmic bytes of one BDL insert from the forest before and after
+    it (F, buffer size, live points per tree): the batch read, the live
+    points of destroyed trees gathered (read 4(d+1), written 4d + 8), and
+    every new tree and the new buffer built (build_bytes)."""
+    F0, b0, live0 = before
+    F1, b1, live1 = after
+    nb = m * 4 * d
+    for i in range(len(live1)):
+        if (F1 >> i) & 1 and not (F0 >> i) & 1:
+            nb += build_bytes(live1[i], d, tree_levels(live1[i]))
+        if (F0 >> i) & 1 and not (F1 >> i) & 1:
+            nb += live0[i] * (4 * (d + 1) + 4 * d + 8)
+    if b1 != b0 or F1 != F0:
+        nb += build_bytes(b1, d, tree_levels(b1))
+    return nb
+
+
+def bdl_erase_bytes(state, m, d=3):
+    """Algorithmic bytes of one erase batch of m points: each point read,
+    and in every tree of the forest one descent (a split value per level)
+    and one leaf scanned (its records)."""
+    F, b, live = state
+    per = 4 * d
+    for n_t in [live[i] for i in range(len(live)) if (F >> i) & 1] + ([b] if b else []):
+        L = tree_levels(n_t)
+        per += 4 * L + 4 * (d + 1) * n_t / (1 << L)
+    return m * per
 
 
 def form_bdl(torch, pg, datagen, dev, rounds, with_oracle=False):
@@ -293,14 +390,19 @@ def form_bdl(torch, pg, datagen, dev, rounds, with_oracle=False):
     build_ms = (time.perf_counter() - t0) * 1e3
     pool = init
     ins, era, knn = [], [], []
+    ins_b, era_b = [], []
     erased_total = 0
     for r, rd in enumerate(rds):
         xr = torch.from_numpy(rd["insert"]).to(dev)
+        before = B.stats(40)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         B.insert(xr)
         torch.cuda.synchronize()
         ins.append((time.perf_counter() - t0) * 1e3)
+        after = B.stats(40)
+        ins_b.append(bdl_insert_bytes(before, after, len(rd["insert"])))
+        era_b.append(bdl_erase_bytes(after, 1_000_000))
         pool = np.concatenate([pool, rd["insert"]])
         g = np.random.default_rng(rd["erase_seed"])
         pick = g.choice(len(pool), size=1_000_000, replace=False)
@@ -316,12 +418,27 @@ def form_bdl(torch, pg, datagen, dev, rounds, with_oracle=False):
         qd = torch.from_numpy(rd["queries"]).to(dev)
         knn.append(timed(torch, lambda: B.knn(qd, 10), reps=1))
     med = lambda a: float(np.median(a))
+    vi, vp = VISITS["uniform_3d_fresh_queries"]
+    # per-round algorithmic bytes over per-round time, median over rounds
+    ins_gbs = [b / (t * 1e-3) / 1e9 for b, t in zip(ins_b, ins)]
+    era_gbs = [b / (t * 1e-3) / 1e9 for b, t in zip(era_b, era)]
+    knn_bytes_1m = knn_bytes(3, 10, 8, 8, vi, vp) * 1e6
     out = {"workload": "BDL 3-D int, 10M initial, rounds of 1M insert / 1M erase / 1M kNN (k=10), X=2^14",
            "rounds": rounds, "initial_insert_ms": build_ms,
            "insert_ms": med(ins), "erase_ms": med(era), "knn_ms": med(knn),
            "insert_mpts_s": 1.0 / med(ins) * 1e3, "erase_mpts_s": 1.0 / med(era) * 1e3,
            "knn_qps": 1e6 / (med(knn) * 1e-3), "erased_per_round": erased_total / rounds,
-           "live_points": B.size()}
+           "live_points": B.size(),
+           "roofline": roof(knn_bytes_1m, med(knn), "bdl_knn_kernel (all trees, one k-list)",
+                            f"one tree over the live set: {vi} internal nodes, {vp} points per "
+                            "query (a forest visits more)"),
+           "insert_roofline": roof(med(ins_b), med(ins), "insert (gather + builds)",
+                                   "batch read + destroyed trees gathered + new trees and buffer "
+                                   "built (build_bytes); wall time incl. host planning"),
+           "erase_roofline": roof(med(era_b), med(era), "erase_kernel (one walk per point and tree)",
+                                  "per point: its coordinates + per tree one descent and one leaf"),
+           "insert_gbs_per_round": [round(v, 1) for v in ins_gbs],
+           "erase_gbs_per_round": [round(v, 1) for v in era_gbs]}
     if with_oracle and rds:
         import oracle
         q = rds[-1]["queries"][:10_000]
@@ -369,8 +486,32 @@ def form_baselines(torch, pg, datagen, dev, rounds):
             era.append(timed(torch, lambda: G.erase(E), reps=1))
             Q = torch.from_numpy(rd["queries"]).to(dev)
             knn.append(timed(torch, lambda: G.knn(Q, 10), reps=1))
+        # byte models at the rounds' typical sizes: n live points before a
+        # round's insert, m per batch
+        n0, m, d = len(init), 1_000_000, 3
+        L = tree_levels(n0 + m)
+        leaf_pts = (n0 + m) / (1 << L)
+        gather = (4 * (d + 1) + 4 * d + 8)
+        if name == "b1":
+            ins_b = m * 4 * d + n0 * gather + build_bytes(n0 + m, d, L)
+            era_b = m * (4 * d + 4 * L + 4 * (d + 1) * leaf_pts) + n0 * gather + build_bytes(n0, d,
+                                                                                              tree_levels(n0))
+            imodel = "batch read + live points gathered + one build of all live points"
+            emodel = "one descent and leaf per point + gather + rebuild of the live points"
+        else:
+            Lb = tree_levels(n0)  # B2's splits come from the initial points
+            ins_b = m * (4 * d + 4 * Lb) + (n0 + m) * (8 * (d + 1) + 16)
+            era_b = m * (4 * d + 4 * Lb + 4 * (d + 1) * (n0 + m) / (1 << Lb))
+            imodel = "new points read and descended + every point moved to the grown arrays"
+            emodel = "one descent and leaf per point"
+        vi, vp = VISITS["uniform_3d_fresh_queries"]
         out[name] = {"insert_ms": float(np.median(ins)), "erase_ms": float(np.median(era)),
-                     "knn_ms": float(np.median(knn)), "knn_ms_last": knn[-1]}
+                     "knn_ms": float(np.median(knn)), "knn_ms_last": knn[-1],
+                     "roofline": roof(knn_bytes(3, 10, 8, 8, vi, vp) * 1e6, float(np.median(knn)),
+                                      "bdl_knn_kernel (one tree)",
+                                      "the oracle search's visits on one tree over the live set"),
+                     "insert_roofline": roof(ins_b, float(np.median(ins)), "insert", imodel),
+                     "erase_roofline": roof(era_b, float(np.median(era)), "erase", emodel)}
         del G
         torch.cuda.empty_cache()
     return out
@@ -534,6 +675,26 @@ def form_table1(torch, pg, datagen, dev, n=N):
     return out
 
 
+def form_wspd(torch, pg, datagen, dev):
+    """The WSPD row of Table 1: 10M uniform 2-D int32 points (seed 11), the
+    object-median tree with leaf size 1, separation s = 2: the build and the
+    decomposition (pairs of heap nodes)."""
+    pts = datagen.uniform_int(N, 2, seed=11)
+    x = torch.from_numpy(pts).to(dev)
+    holder = {}
+    build_ms = timed(torch, lambda: holder.__setitem__("t", pg.kdtree_build(x, leaf=1)))
+    t = holder["t"]
+    pairs = t.wspd(2.0)
+    P = pairs.shape[0]
+    buf = torch.empty((P, 2), dtype=torch.int32, device=dev)
+    wspd_ms = timed(torch, lambda: t.wspd(2.0, out=buf))
+    return {"workload": "WSPD, 2-D n=10M int32 uniform, leaf 1, s=2", "build_ms": build_ms,
+            "wspd_ms": wspd_ms, "pairs": P, "pairs_per_point": P / N,
+            "pairs_per_s": P / (wspd_ms * 1e-3),
+            "roofline": roof(P * (8 + 2 * 2 * 2 * 4), wspd_ms, "wspd rounds (test + scatter + scans)",
+                             "per output pair: its 8 bytes and the two node boxes tested")}
+
+
 def form_small_2d(torch, pg, datagen, dev, with_oracle):
     """The small correctness workload (10,000 uniform 2-D int32 points, all
     queried, k = 10, leaf 16): GPU build and k-NN (launch-bound at this
@@ -591,8 +752,18 @@ def form_batch(torch, pg, datagen, dev, loop_clouds):
     gen_ms = timed(torch, lambda: pg.knn_backward(x, x, idx, g, grad_q=grad, self_mode=True))
     fast_ms = timed(torch, lambda: pg.knn_backward(x, x, idx, g, grad_q=grad, self_mode=True,
                                                    deterministic=False))
+    vi, vp = VISITS["sphere_clouds_all_points"]
+    fwd_b = sum(build_bytes(int(n), 3, tree_levels(int(n))) for n in sizes) + \
+        Ntot * knn_bytes(3, 16, 4, 4, vi, vp)
+    bwd_b = Ntot * 16 * 8 + Ntot * 12 * 2  # idx + g per pair; points read, gradient written
     return {"workload": "4,096 unit-sphere clouds (+N(0,0.01^2)), sizes log-uniform [256,65536], "
                         f"{Ntot} points, per-cloud all-points k=16, float32",
+            "roofline": roof(fwd_b, batch_ms, "batch_kernel (builds + searches, one launch)",
+                             f"per-cloud builds (build_bytes) + searches ({vi} internal nodes, "
+                             f"{vp} points per query, oracle on 256 clouds)"),
+            "backward_roofline": roof(bwd_b, bwd_ms, "bwd_* (leaf-order batched backward)",
+                                      "8 B per (query, neighbour) pair (index, gradient) + the "
+                                      "points read and the gradient written"),
             "tune": tune, "batched_ms": batch_ms, "clouds_per_s": 4096 / (batch_ms * 1e-3),
             "points_per_s": Ntot / (batch_ms * 1e-3),
             "per_cloud_loop_ms": loop_s * 1e3, "per_cloud_loop_sample_clouds": nc,
@@ -645,6 +816,10 @@ def form_range(torch, pg, datagen, dev, with_oracle):
         gbs = range_bytes_per_query(2, res, rep) * N / (ms * 1e-3) / 1e9
         out[f"{name}_algorithmic_gbs"] = gbs
         out[f"{name}_roofline_frac"] = gbs / HBM_PEAK_GBS
+    out["roofline"] = roof((range_bytes_per_query(2, res, False) + range_bytes_per_query(2, res, True))
+                           * N, search_ms, "range_kernel (counting and reporting walks)",
+                           f"per box: the box, {R_NODES} node boxes and {R_PTS} points tested "
+                           "(oracle), count, offset and rows; both passes")
     if with_oracle:
         import oracle
         sample = 100_000
@@ -666,7 +841,7 @@ def main():
     ap.add_argument("--forms", default="all",
                     help="other forms to measure after the headline step: all, none, or a "
                          "comma list of static_float,clustered,spatial,bdl,baselines,batch,range,graph,"
-                         "table1,small_2d "
+                         "wspd,table1,small_2d "
                          "(sec63, the Section 6.3 protocols on 10M-point sets, runs only when named)")
     ap.add_argument("--bdl-rounds", type=int, default=10)
     ap.add_argument("--sec63-n", type=int, default=N, help="set size of the sec63 form")
@@ -777,11 +952,14 @@ def main():
             "algorithmic_bytes_per_launch": launch_bytes,
             "algorithmic_bytes_per_query": bytes_per_query(dbytes),
         },
+        "build_roofline": roof(build_bytes(N, D, tree_levels(N)), build_ms, "build (all kernels)",
+                               "n(8d+4) + L n (8d+12): ingest, then per level one key read and "
+                               "one record read and write"),
     }
     del idx, dist, x
     torch.cuda.empty_cache()
     forms = ["static_float", "clustered", "spatial", "bdl", "baselines", "batch", "range", "graph",
-             "table1", "small_2d"] \
+             "wspd", "table1", "small_2d"] \
         if args.forms == "all" else \
         [f for f in args.forms.split(",") if f and f != "none"]
     out = {}
@@ -809,6 +987,8 @@ def main():
             out[f] = form_sec63(torch, pg, datagen, dev, args.sec63_n)
         elif f == "range":
             out[f] = form_range(torch, pg, datagen, dev, not args.no_cpu_baseline)
+        elif f == "wspd":
+            out[f] = form_wspd(torch, pg, datagen, dev)
         else:
             raise SystemExit(f"unknown form {f}")
         torch.cuda.empty_cache()

@@ -299,14 +299,17 @@ class KdTree:
             check(st)
         return off, out[:total.value]
 
-    def wspd(self, s: float = 2.0, capacity: int = None):
+    def wspd(self, s: float = 2.0, capacity: int = None, out=None):
         """Well-separated pair decomposition (tree built with leaf 1): int32
         [P][2] heap node pairs on the device.  One call when the pairs fit
-        ``capacity`` (default: a guess from the point count), else a second
-        with the exact size."""
+        ``capacity`` (default: ``out``'s rows, else a guess from the point
+        count), else a second with the exact size."""
+        if out is not None:
+            capacity = out.shape[0] if capacity is None else capacity
         if capacity is None:
             capacity = 24 * self.n + 1024
-        out = torch.empty((max(capacity, 1), 2), dtype=torch.int32, device=self.device)
+        if out is None or out.shape[0] < capacity:
+            out = torch.empty((max(capacity, 1), 2), dtype=torch.int32, device=self.device)
         cnt = ctypes.c_int64()
         st = lib().pg_wspd(self._h, float(s), ctypes.c_void_p(out.data_ptr()), capacity,
                            ctypes.byref(cnt), stream_ptr(self.device))

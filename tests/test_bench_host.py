@@ -76,3 +76,52 @@ def test_range_constants_match_the_oracle():
     *_, cnt = t.range(boxes)
     assert cnt[0] / len(rows) == pytest.approx(bench.R_NODES, rel=0.01)
     assert cnt[1] / len(rows) == pytest.approx(bench.R_PTS, rel=0.01)
+
+
+def test_build_bytes_model():
+    # ingest n(4d + 4(d+1)) + L levels of n(4 + 8(d+1)): 748 B per point at
+    # d = 3, L = 20 (the headline tree)
+    assert bench.tree_levels(10_000_000) == 20
+    assert bench.build_bytes(10_000_000, 3, 20) == 748 * 10_000_000
+    assert bench.tree_levels(16) == 0 and bench.tree_levels(17) == 1
+
+
+def test_other_visit_constants_match_the_oracle():
+    """The visit counts behind the other k-NN rooflines, from fresh samples:
+    5-D clustered queries, fresh uniform queries over 10M points, and the
+    sphere clouds (other clouds than the constants were drawn from)."""
+    f, q = datagen.clustered(bench.N, 5, seed=3, n_queries=1_000_000, query_seed=33)
+    rows = np.random.default_rng(22).choice(len(q), 20_000, replace=False)
+    _, _, c = oracle.KdTree(f, leaf=16).knn(q[rows], 5, nthreads=8)
+    vi, vp = bench.VISITS["clustered_5d_queries"]
+    assert c[0] / len(rows) == pytest.approx(vi, rel=0.03)
+    assert c[2] / len(rows) == pytest.approx(vp, rel=0.03)
+    del f, q
+    init, rounds = datagen.bdl_rounds(bench.N, 1, 1_000_000, 1_000_000, 3, seed=5)
+    rows = np.random.default_rng(23).choice(1_000_000, 20_000, replace=False)
+    _, _, c = oracle.KdTree(init, leaf=16).knn(rounds[0]["queries"][rows], 10, nthreads=8)
+    vi, vp = bench.VISITS["uniform_3d_fresh_queries"]
+    assert c[0] / len(rows) == pytest.approx(vi, rel=0.01)
+    assert c[2] / len(rows) == pytest.approx(vp, rel=0.01)
+    from oracle.visit_counts import cloud_counts
+    cc = cloud_counts(16, 16, stride=16, offset=8)  # the interleaved other stratum
+    vi, vp = bench.VISITS["sphere_clouds_all_points"]
+    assert cc["n_int"] == pytest.approx(vi, rel=0.02)
+    assert cc["n_pts"] == pytest.approx(vp, rel=0.02)
+
+
+def test_bdl_byte_models():
+    # one new tree of 16384 * 2^6 points and a rebuilt buffer of 576, one
+    # destroyed tree of 16384 * 2^5 live points
+    X = 1 << 14
+    before = (1 << 5, 100, [0] * 5 + [X << 5] + [0] * 34)
+    after = (1 << 6, 576, [0] * 6 + [X << 6] + [0] * 33)
+    m = 1_000_000
+    want = (m * 12 + bench.build_bytes(X << 6, 3, bench.tree_levels(X << 6))
+            + (X << 5) * (16 + 12 + 8) + bench.build_bytes(576, 3, bench.tree_levels(576)))
+    assert bench.bdl_insert_bytes(before, after, m) == want
+    # erase: per point 12 + per tree (4 L + 16 n / 2^L)
+    n = X << 6
+    L = bench.tree_levels(n)
+    assert bench.bdl_erase_bytes(after, 10) == pytest.approx(
+        10 * (12 + 4 * L + 16 * n / (1 << L) + 4 * bench.tree_levels(576) + 16 * 576 / (1 << bench.tree_levels(576))))
