@@ -286,6 +286,10 @@ pg_status pg_range_search(const pg_tree* t, const void* boxes, int64_t m, int32_
  * ascending order; a tree is rebuilt when fewer than X 2^i / 2 of its points
  * are live (the buffer is exempt).
  *
+ * A handle (BDL, B1 and B2 alike) keeps device scratch for its erase and
+ * k-NN calls from one call to the next, grown as needed and released with
+ * the handle: calls on one handle, k-NN included, must not overlap.
+ *
  * Creates an empty BDL-tree (host only; no device work).
  *   d : 1..8   dtype : PG_INT32 / PG_FLOAT32   leaf : 1..64
  *   buffer_X : X in [1, 2^31) */
@@ -316,7 +320,9 @@ pg_status pg_bdl_erase(pg_bdl* b, const void* points, int64_t m, void* stream,
 
 /* Data-parallel k-NN over the live points of all trees (Section 5
  * "Data-Parallel k-NN": one k-NN buffer per query carried across the
- * trees).
+ * trees, largest tree first).  While every id is below 2^31 the buffer
+ * holds packed (distance, id) keys; int32 queries whose k-th key reaches
+ * the packed range's limit are searched again with exact pairs.
  *   out_id   : [m][k] int64 ids (-1 = none)
  *   out_dist : [m][k] int64 / float32 squared distances
  * Synchronises (query range check). */
@@ -331,7 +337,8 @@ int64_t pg_bdl_size(const pg_bdl* b);
 pg_status pg_bdl_stats(const pg_bdl* b, int64_t* tree_mask, int64_t* buffer_count,
                        int64_t* live_counts, int32_t max_trees);
 
-/* Releases every tree (stream-ordered on the streams they were built on). */
+/* Releases every tree and the handle's scratch (stream-ordered on the
+ * streams they were made on). */
 void pg_bdl_free(pg_bdl* b);
 
 /* ---------------------------------------------------------------------- */
@@ -359,7 +366,7 @@ pg_status pg_b1_knn(const pg_b1* b, const void* queries, int64_t m, int32_t k, i
                     void* out_dist, void* stream);
 /* Live points (host; -1 for a NULL handle). */
 int64_t pg_b1_size(const pg_b1* b);
-/* Releases the tree. */
+/* Releases the tree and the handle's scratch. */
 void pg_b1_free(pg_b1* b);
 
 /* ---------------------------------------------------------------------- */
@@ -400,7 +407,7 @@ int64_t pg_b2_size(const pg_b2* b);
 /* Stored points including tombstones, and the tree's depth (host outputs,
  * either may be NULL). */
 pg_status pg_b2_stats(const pg_b2* b, int64_t* stored, int32_t* levels);
-/* Releases the tree. */
+/* Releases the tree and the handle's scratch. */
 void pg_b2_free(pg_b2* b);
 
 /* ---------------------------------------------------------------------- */

@@ -25,13 +25,11 @@
 #include "build.hpp"
 #include "knn.hpp"
 #include "scan.hpp"
+#include "forest.hpp"
 #include "xsearch.hpp"
 #include "wave.hpp"
 
 namespace pg {
-
-constexpr int kMaxTrees = 31;        // static trees 0..30
-constexpr int kSlots = kMaxTrees + 1;  // + the buffer tree
 
 struct BdlTree {
     pg_tree* t = nullptr;
@@ -41,27 +39,9 @@ struct BdlTree {
     int64_t n() const { return t ? t->n : 0; }
 };
 
-struct ForestSlot {
-    TreeView tv;
-    const int64_t* ids;
-    uint32_t* alive;
-};
-
-struct Forest {
-    ForestSlot s[kSlots];
-    int count;
-};
-
 namespace {
 
 constexpr int kNT = 256;
-
-struct BdlIds {
-    const int64_t* ids;
-    const uint32_t* alive;
-    __device__ inline int64_t id(int64_t i, uint32_t) const { return ids[i]; }
-    __device__ inline bool live(int64_t i) const { return (alive[i >> 5] >> (i & 31)) & 1u; }
-};
 
 // flags[pidx[i]] = liveness of leaf-order point i (staging order).
 __global__ void stage_flags_kernel(const int32_t* __restrict__ pidx, const uint32_t* __restrict__ alive,
@@ -91,10 +71,17 @@ __global__ void iota64_kernel(int64_t* __restrict__ out, int64_t count, int64_t 
     if (i < count) out[i] = first + i;
 }
 
+// Ids of the leaf-order points, also into the records' row words (low 32
+// bits).
 __global__ void leaf_ids_kernel(const int32_t* __restrict__ pidx, const int64_t* __restrict__ staged,
-                                int64_t n, int64_t* __restrict__ ids) {
+                                int64_t n, int64_t* __restrict__ ids, uint32_t* __restrict__ rec, int rw,
+                                int d) {
     const int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x;
-    if (i < n) ids[i] = staged[pidx[i]];
+    if (i < n) {
+        const int64_t v = staged[pidx[i]];
+        ids[i] = v;
+        rec[i * rw + d] = (uint32_t)v;
+    }
 }
 
 // Erase: lane = erase point, blockIdx.y = tree slot.  Walks every node whose
@@ -182,32 +169,6 @@ erase_kernel(Forest f, const uint32_t* __restrict__ pts, const int32_t* __restri
     if (hits) atomicAdd(&erased[slot], (unsigned long long)hits);
 }
 
-template <typename T, int MD, int KT, bool EX, int TK>
-__global__ void __launch_bounds__(kNT)
-bdl_knn_kernel(Forest f, const uint32_t* __restrict__ queries, const int32_t* __restrict__ order,
-               int64_t m, int d, int k, int64_t* __restrict__ out_id,
-               typename Metric<T>::D* __restrict__ out_dist) {
-    using M = Metric<T>;
-    const int64_t i0 = xcd_block() * kNT + threadIdx.x;
-    if (i0 >= m) return;
-    const int64_t qi = order ? (int64_t)order[i0] : i0;  // leaf order of the largest tree
-    T q[MD];
-#pragma unroll
-    for (int c = 0; c < MD; c++) q[c] = M::load(c < d ? queries[qi * d + c] : 0u);
-    KList<typename M::D, int64_t, KT, EX> kl;
-    kl.init(M::inf(), INT64_MAX);
-    for (int t = 0; t < f.count; t++)
-        tree_search<T, MD, decltype(kl), BdlIds, TK>(f.s[t].tv, BdlIds{f.s[t].ids, f.s[t].alive}, q,
-                                                     d, kl, k, search_start<TK>(f.s[t].tv, false, 0));
-#pragma unroll
-    for (int s = 0; s < KT; s++) {
-        if (EX || s < k) {
-            out_id[qi * k + s] = kl.id[s] == INT64_MAX ? -1 : kl.id[s];
-            out_dist[qi * k + s] = kl.d[s];
-        }
-    }
-}
-
 template <typename T, int MD, int TK>
 pg_status launch_erase(const Forest& f, const void* pts, const int32_t* order, int64_t m, int d,
                        unsigned long long* erased, hipStream_t s) {
@@ -237,49 +198,6 @@ pg_status erase_any(int tk, const Forest& f, const void* pts, const int32_t* o, 
     if (tk == kTreeX) return erase_d<T, kTreeX>(f, pts, o, m, d, e, s);
     if (tk == kTreeLoff) return erase_d<T, kTreeLoff>(f, pts, o, m, d, e, s);
     return erase_d<T, kTreeHeap>(f, pts, o, m, d, e, s);
-}
-
-template <typename T, int MD, int KT, bool EX, int TK>
-pg_status launch_bdl_knn(const Forest& f, const void* q, const int32_t* o, int64_t m, int d, int k,
-                         int64_t* oi, void* od, hipStream_t s) {
-    using DT = typename Metric<T>::D;
-    hipLaunchKernelGGL((bdl_knn_kernel<T, MD, KT, EX, TK>), dim3(grid_for_xcd(cdiv(m, kNT))),
-                       dim3(kNT), 0, s, f, (const uint32_t*)q, o, m, d, k, oi, (DT*)od);
-    PG_LAUNCH_CHECK();
-    return PG_OK;
-}
-
-template <typename T, int MD, int TK>
-pg_status bdl_knn_k(const Forest& f, const void* q, const int32_t* o, int64_t m, int d, int k,
-                    int64_t* oi, void* od, hipStream_t s) {
-    if (k == 5) return launch_bdl_knn<T, MD, 5, true, TK>(f, q, o, m, d, k, oi, od, s);
-    if (k == 10) return launch_bdl_knn<T, MD, 10, true, TK>(f, q, o, m, d, k, oi, od, s);
-    if (k == 16) return launch_bdl_knn<T, MD, 16, true, TK>(f, q, o, m, d, k, oi, od, s);
-    if (k <= 2) return launch_bdl_knn<T, MD, 2, false, TK>(f, q, o, m, d, k, oi, od, s);
-    if (k <= 4) return launch_bdl_knn<T, MD, 4, false, TK>(f, q, o, m, d, k, oi, od, s);
-    if (k <= 8) return launch_bdl_knn<T, MD, 8, false, TK>(f, q, o, m, d, k, oi, od, s);
-    if (k <= 16) return launch_bdl_knn<T, MD, 16, false, TK>(f, q, o, m, d, k, oi, od, s);
-    if (k <= 32) return launch_bdl_knn<T, MD, 32, false, TK>(f, q, o, m, d, k, oi, od, s);
-    return launch_bdl_knn<T, MD, 64, false, TK>(f, q, o, m, d, k, oi, od, s);
-}
-
-template <typename T, int TK>
-pg_status bdl_knn_d(const Forest& f, const void* q, const int32_t* o, int64_t m, int d, int k,
-                    int64_t* oi, void* od, hipStream_t s) {
-    switch (d) {
-        case 2: return bdl_knn_k<T, 2, TK>(f, q, o, m, d, k, oi, od, s);
-        case 3: return bdl_knn_k<T, 3, TK>(f, q, o, m, d, k, oi, od, s);
-        case 5: return bdl_knn_k<T, 5, TK>(f, q, o, m, d, k, oi, od, s);
-        default: return bdl_knn_k<T, 8, TK>(f, q, o, m, d, k, oi, od, s);
-    }
-}
-
-template <typename T>
-pg_status bdl_knn_any(int tk, const Forest& f, const void* q, const int32_t* o, int64_t m, int d,
-                      int k, int64_t* oi, void* od, hipStream_t s) {
-    if (tk == kTreeX) return bdl_knn_d<T, kTreeX>(f, q, o, m, d, k, oi, od, s);
-    if (tk == kTreeLoff) return bdl_knn_d<T, kTreeLoff>(f, q, o, m, d, k, oi, od, s);
-    return bdl_knn_d<T, kTreeHeap>(f, q, o, m, d, k, oi, od, s);
 }
 
 // ---- B2 (Section 6.3's second baseline): one static tree whose splits stay
@@ -455,7 +373,7 @@ static pg_status build_bdl_tree(const Bdl& B, const Staged& S, hipStream_t s, Bd
     PG_TRY(dalloc(&out.alive, words > 0 ? words : 1, s));
     if (n > 0) {
         hipLaunchKernelGGL(leaf_ids_kernel, dim3(cdiv(n, kNT)), dim3(kNT), 0, s, t->pidx, S.ids, n,
-                           out.ids);
+                           out.ids, t->rec, t->view().rw, B.d);
         PG_LAUNCH_CHECK();
         PG_HIP(hipMemsetAsync(out.alive, 0xff, sizeof(uint32_t) * words, s));
     }
@@ -568,8 +486,8 @@ static Forest make_forest(const Bdl& B) {
     Forest f{};
     f.count = 0;
     for (int i = kMaxTrees - 1; i >= 0; i--)  // largest first
-        if (B.tree[i].t) f.s[f.count++] = ForestSlot{B.tree[i].t->view(), B.tree[i].ids, B.tree[i].alive};
-    if (B.buf.t) f.s[f.count++] = ForestSlot{B.buf.t->view(), B.buf.ids, B.buf.alive};
+        if (B.tree[i].t) f.s[f.count++] = ForestSlot{B.tree[i].t->view(), B.tree[i].ids, B.tree[i].alive, 1};
+    if (B.buf.t) f.s[f.count++] = ForestSlot{B.buf.t->view(), B.buf.ids, B.buf.alive, 1};
     return f;
 }
 
@@ -584,7 +502,7 @@ struct B2 {
 static Forest b2_forest(const B2& B) {
     Forest f{};
     f.count = 0;
-    if (B.T.t) f.s[f.count++] = ForestSlot{B.T.t->view(), B.T.ids, B.T.alive};
+    if (B.T.t) f.s[f.count++] = ForestSlot{B.T.t->view(), B.T.ids, B.T.alive, 0};  // records move
     return f;
 }
 
@@ -677,18 +595,85 @@ static pg_status b1_rebuild(B1& B, const Staged& extra, hipStream_t s) {
     return PG_OK;
 }
 
+// Device memory a handle keeps between calls (grown, never shrunk) for the
+// temporaries of its erase and k-NN calls: after a rebuild has freed and
+// allocated large blocks, a fresh allocation can hold the host for
+// milliseconds.  Calls on one handle must not overlap.
+struct Workspace {
+    void* p = nullptr;
+    size_t cap = 0;
+    hipStream_t s = nullptr;
+    pg_status ensure(size_t bytes, hipStream_t st) {
+        if (bytes <= cap) return PG_OK;
+        release();
+        const size_t want = bytes + bytes / 4;
+        PG_TRY(dmalloc(&p, want, st));
+        cap = want;
+        s = st;
+        return PG_OK;
+    }
+    void release() {
+        if (p) dfree(p, s);
+        p = nullptr;
+        cap = 0;
+    }
+};
+
+// Temporaries of one erase or k-NN call, carved from a Workspace.
+struct CallWs {
+    uint32_t* err = nullptr;              // range-check flag
+    uint32_t* nredo = nullptr;            // redo count of the packed k-NN
+    unsigned long long* cnt = nullptr;    // [kSlots] erase counts per tree
+    int32_t* order = nullptr;             // [m] point order (null: unordered)
+    QueryKeys keys;                       // where the ordering's descents ended
+    int32_t* redo = nullptr;              // [m] redo list of the packed k-NN
+};
+
+inline size_t up256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Checks the m points' range and, when tv is given and m >= kOrderMin,
+// orders them by tv's leaves; the erase counts start at zero.
+static pg_status begin_call(Workspace& w, const TreeView* tv, const void* pts, int64_t m, int d,
+                            bool fl, hipStream_t s, CallWs& c) {
+    const bool ordered = tv && tv->n > 0 && m >= kOrderMin;
+    const int64_t nb = ordered ? order_buckets(*tv, m) : 0;
+    const size_t head = 512;  // err, nredo | cnt at 256
+    const size_t o_order = head, o_work = o_order + (ordered ? up256(sizeof(int32_t) * m) : 0);
+    const size_t o_sums = o_work + (ordered ? up256(sizeof(uint32_t) * (m + nb)) : 0);
+    const size_t o_redo = o_sums + (ordered ? up256(sizeof(uint32_t) * scan_partials(nb)) : 0);
+    PG_TRY(w.ensure(o_redo + up256(sizeof(int32_t) * m), s));
+    uint8_t* b = static_cast<uint8_t*>(w.p);
+    c.err = reinterpret_cast<uint32_t*>(b);
+    c.nredo = reinterpret_cast<uint32_t*>(b + 4);
+    c.cnt = reinterpret_cast<unsigned long long*>(b + 256);
+    c.redo = reinterpret_cast<int32_t*>(b + o_redo);
+    static_assert(sizeof(unsigned long long) * kSlots <= 256, "erase counts exceed their slot");
+    PG_TRY(check_queries_ws(pts, m, d, fl, c.err, s));
+    PG_TRY(fill_u32(reinterpret_cast<uint32_t*>(c.cnt), 2 * kSlots, 0u, s));
+    c.order = nullptr;
+    if (ordered) {
+        c.order = reinterpret_cast<int32_t*>(b + o_order);
+        PG_TRY(order_queries_ws(*tv, fl, pts, m, s, c.order, reinterpret_cast<uint32_t*>(b + o_work),
+                                reinterpret_cast<uint32_t*>(b + o_sums), false, &c.keys));
+    }
+    return PG_OK;
+}
+
 }  // namespace pg
 
 struct pg_bdl {
     pg::Bdl b;
+    mutable pg::Workspace ws;
 };
 
 struct pg_b1 {
     pg::B1 b;
+    mutable pg::Workspace ws;
 };
 
 struct pg_b2 {
     pg::B2 b;
+    mutable pg::Workspace ws;
 };
 
 using namespace pg;
@@ -754,8 +739,9 @@ pg_status pg_bdl_erase(pg_bdl* h, const void* points, int64_t m, void* stream, i
     hipStream_t s = (hipStream_t)stream;
     if (n_erased) *n_erased = 0;
     if (m == 0) return PG_OK;
-    PG_TRY(check_queries(points, m, B.d, B.dtype == PG_FLOAT32, s));
     Forest f = make_forest(B);
+    CallWs c;
+    PG_TRY(begin_call(h->ws, f.count > 0 ? &f.s[0].tv : nullptr, points, m, B.d, B.dtype == PG_FLOAT32, s, c));
     if (f.count == 0) return PG_OK;
     // slot -> tree index (-1: buffer), same order as make_forest
     int slot_tree[kSlots];
@@ -765,16 +751,8 @@ pg_status pg_bdl_erase(pg_bdl* h, const void* points, int64_t m, void* stream, i
             if (B.tree[i].t) slot_tree[c++] = i;
         if (B.buf.t) slot_tree[c++] = -1;
     }
-    DevBuf cnt(s);
-    PG_TRY(cnt.alloc(sizeof(unsigned long long) * kSlots));
-    PG_HIP(hipMemsetAsync(cnt.p, 0, sizeof(unsigned long long) * kSlots, s));
-    unsigned long long* e = cnt.as<unsigned long long>();
-    DevBuf order(s);
-    const int32_t* o = nullptr;
-    if (m >= kOrderMin) {
-        PG_TRY(order_queries(f.s[0].tv, B.dtype == PG_FLOAT32, points, m, s, order));
-        o = order.as<int32_t>();
-    }
+    unsigned long long* e = c.cnt;
+    const int32_t* o = c.order;
     const int tk = B.split ? kTreeX : kTreeHeap;
     if (B.dtype == PG_FLOAT32) PG_TRY(erase_any<float>(tk, f, points, o, m, B.d, e, s));
     else PG_TRY(erase_any<int32_t>(tk, f, points, o, m, B.d, e, s));
@@ -825,18 +803,15 @@ pg_status pg_bdl_knn(const pg_bdl* h, const void* queries, int64_t m, int32_t k,
     if (m == 0) return PG_OK;
     const Bdl& B = h->b;
     hipStream_t s = (hipStream_t)stream;
-    PG_TRY(check_queries(queries, m, B.d, B.dtype == PG_FLOAT32, s));
     Forest f = make_forest(B);
-    DevBuf order(s);
-    const int32_t* o = nullptr;
-    if (f.count > 0 && m >= kOrderMin) {
-        PG_TRY(order_queries(f.s[0].tv, B.dtype == PG_FLOAT32, queries, m, s, order));
-        o = order.as<int32_t>();
-    }
+    CallWs c;
+    PG_TRY(begin_call(h->ws, f.count > 0 ? &f.s[0].tv : nullptr, queries, m, B.d, B.dtype == PG_FLOAT32, s, c));
     const int tk = B.split ? kTreeX : kTreeHeap;
     if (B.dtype == PG_FLOAT32)
-        return bdl_knn_any<float>(tk, f, queries, o, m, B.d, k, out_id, out_dist, s);
-    return bdl_knn_any<int32_t>(tk, f, queries, o, m, B.d, k, out_id, out_dist, s);
+        return forest_knn_float(tk, f, queries, c.order, c.keys, m, B.d, k, B.next_id, c.redo, c.nredo, out_id,
+                                out_dist, s);
+    return forest_knn_int(tk, f, queries, c.order, c.keys, m, B.d, k, B.next_id, c.redo, c.nredo, out_id, out_dist,
+                          s);
 }
 
 int64_t pg_bdl_size(const pg_bdl* h) {
@@ -861,6 +836,7 @@ void pg_bdl_free(pg_bdl* h) {
     if (!h) return;
     for (int i = 0; i < kMaxTrees; i++) free_tree(h->b.tree[i]);
     free_tree(h->b.buf);
+    h->ws.release();
     delete h;
 }
 
@@ -920,19 +896,13 @@ pg_status pg_b1_erase(pg_b1* h, const void* points, int64_t m, void* stream, int
     hipStream_t s = (hipStream_t)stream;
     if (n_erased) *n_erased = 0;
     if (m == 0 || !B.T.t || B.T.t->n == 0) return PG_OK;
-    PG_TRY(check_queries(points, m, B.shape.d, B.shape.dtype == PG_FLOAT32, s));
     Forest f{};
     f.count = 1;
-    f.s[0] = ForestSlot{B.T.t->view(), B.T.ids, B.T.alive};
-    DevBuf cnt(s), order(s);
-    PG_TRY(cnt.alloc(sizeof(unsigned long long)));
-    PG_HIP(hipMemsetAsync(cnt.p, 0, sizeof(unsigned long long), s));
-    const int32_t* o = nullptr;
-    if (m >= kOrderMin) {
-        PG_TRY(order_queries(f.s[0].tv, B.shape.dtype == PG_FLOAT32, points, m, s, order));
-        o = order.as<int32_t>();
-    }
-    unsigned long long* e = cnt.as<unsigned long long>();
+    f.s[0] = ForestSlot{B.T.t->view(), B.T.ids, B.T.alive, 1};
+    CallWs c;
+    PG_TRY(begin_call(h->ws, &f.s[0].tv, points, m, B.shape.d, B.shape.dtype == PG_FLOAT32, s, c));
+    const int32_t* o = c.order;
+    unsigned long long* e = c.cnt;
     const int tk = B.shape.split ? kTreeX : kTreeHeap;
     if (B.shape.dtype == PG_FLOAT32) PG_TRY(erase_any<float>(tk, f, points, o, m, B.shape.d, e, s));
     else PG_TRY(erase_any<int32_t>(tk, f, points, o, m, B.shape.d, e, s));
@@ -955,20 +925,18 @@ pg_status pg_b1_knn(const pg_b1* h, const void* queries, int64_t m, int32_t k, i
     if (m == 0) return PG_OK;
     const B1& B = h->b;
     hipStream_t s = (hipStream_t)stream;
-    PG_TRY(check_queries(queries, m, B.shape.d, B.shape.dtype == PG_FLOAT32, s));
     Forest f{};
     f.count = 0;
-    if (B.T.t) f.s[f.count++] = ForestSlot{B.T.t->view(), B.T.ids, B.T.alive};
-    DevBuf order(s);
-    const int32_t* o = nullptr;
-    if (f.count > 0 && m >= kOrderMin) {
-        PG_TRY(order_queries(f.s[0].tv, B.shape.dtype == PG_FLOAT32, queries, m, s, order));
-        o = order.as<int32_t>();
-    }
+    if (B.T.t) f.s[f.count++] = ForestSlot{B.T.t->view(), B.T.ids, B.T.alive, 1};
+    CallWs c;
+    PG_TRY(begin_call(h->ws, f.count > 0 ? &f.s[0].tv : nullptr, queries, m, B.shape.d,
+                      B.shape.dtype == PG_FLOAT32, s, c));
     const int tk = B.shape.split ? kTreeX : kTreeHeap;
     if (B.shape.dtype == PG_FLOAT32)
-        return bdl_knn_any<float>(tk, f, queries, o, m, B.shape.d, k, out_id, out_dist, s);
-    return bdl_knn_any<int32_t>(tk, f, queries, o, m, B.shape.d, k, out_id, out_dist, s);
+        return forest_knn_float(tk, f, queries, c.order, c.keys, m, B.shape.d, k, B.next_id, c.redo, c.nredo, out_id,
+                                out_dist, s);
+    return forest_knn_int(tk, f, queries, c.order, c.keys, m, B.shape.d, k, B.next_id, c.redo, c.nredo, out_id,
+                          out_dist, s);
 }
 
 int64_t pg_b1_size(const pg_b1* h) { return h ? (h->b.T.t ? h->b.T.live : 0) : -1; }
@@ -976,6 +944,7 @@ int64_t pg_b1_size(const pg_b1* h) { return h ? (h->b.T.t ? h->b.T.live : 0) : -
 void pg_b1_free(pg_b1* h) {
     if (!h) return;
     free_tree(h->b.T);
+    h->ws.release();
     delete h;
 }
 
@@ -1062,17 +1031,11 @@ pg_status pg_b2_erase(pg_b2* h, const void* points, int64_t m, void* stream, int
     hipStream_t s = (hipStream_t)stream;
     if (n_erased) *n_erased = 0;
     if (m == 0 || !B.T.t || B.T.t->n == 0) return PG_OK;
-    PG_TRY(check_queries(points, m, B.d, B.dtype == PG_FLOAT32, s));
     Forest f = b2_forest(B);
-    DevBuf cnt(s), order(s);
-    PG_TRY(cnt.alloc(sizeof(unsigned long long)));
-    PG_HIP(hipMemsetAsync(cnt.p, 0, sizeof(unsigned long long), s));
-    const int32_t* o = nullptr;
-    if (m >= kOrderMin) {
-        PG_TRY(order_queries(f.s[0].tv, B.dtype == PG_FLOAT32, points, m, s, order));
-        o = order.as<int32_t>();
-    }
-    unsigned long long* e = cnt.as<unsigned long long>();
+    CallWs c;
+    PG_TRY(begin_call(h->ws, &f.s[0].tv, points, m, B.d, B.dtype == PG_FLOAT32, s, c));
+    const int32_t* o = c.order;
+    unsigned long long* e = c.cnt;
     const int tk = B.T.t->xn ? kTreeX : kTreeLoff;
     if (B.dtype == PG_FLOAT32) PG_TRY(erase_any<float>(tk, f, points, o, m, B.d, e, s));
     else PG_TRY(erase_any<int32_t>(tk, f, points, o, m, B.d, e, s));
@@ -1093,17 +1056,15 @@ pg_status pg_b2_knn(const pg_b2* h, const void* queries, int64_t m, int32_t k, i
     if (m == 0) return PG_OK;
     const B2& B = h->b;
     hipStream_t s = (hipStream_t)stream;
-    PG_TRY(check_queries(queries, m, B.d, B.dtype == PG_FLOAT32, s));
     Forest f = b2_forest(B);
-    DevBuf order(s);
-    const int32_t* o = nullptr;
-    if (f.count > 0 && m >= kOrderMin) {
-        PG_TRY(order_queries(f.s[0].tv, B.dtype == PG_FLOAT32, queries, m, s, order));
-        o = order.as<int32_t>();
-    }
+    CallWs c;
+    PG_TRY(begin_call(h->ws, f.count > 0 ? &f.s[0].tv : nullptr, queries, m, B.d, B.dtype == PG_FLOAT32, s, c));
     const int tk = B.T.t && B.T.t->xn ? kTreeX : kTreeLoff;
-    if (B.dtype == PG_FLOAT32) return bdl_knn_any<float>(tk, f, queries, o, m, B.d, k, out_id, out_dist, s);
-    return bdl_knn_any<int32_t>(tk, f, queries, o, m, B.d, k, out_id, out_dist, s);
+    if (B.dtype == PG_FLOAT32)
+        return forest_knn_float(tk, f, queries, c.order, c.keys, m, B.d, k, B.next_id, c.redo, c.nredo, out_id,
+                                out_dist, s);
+    return forest_knn_int(tk, f, queries, c.order, c.keys, m, B.d, k, B.next_id, c.redo, c.nredo, out_id, out_dist,
+                          s);
 }
 
 int64_t pg_b2_size(const pg_b2* h) { return h ? h->b.T.live : -1; }
@@ -1118,6 +1079,7 @@ pg_status pg_b2_stats(const pg_b2* h, int64_t* stored, int32_t* levels) {
 void pg_b2_free(pg_b2* h) {
     if (!h) return;
     free_tree(h->b.T);
+    h->ws.release();
     delete h;
 }
 

@@ -52,11 +52,10 @@ query_leaf_kernel(TreeView tv, int fl, const uint32_t* __restrict__ queries, int
     }
 }
 
-// The same for explicit-node trees: the leaf index the descent reaches,
-// shifted right by `shift`.
+// The same for explicit-node trees: the leaf index the descent reaches.
 __global__ void __launch_bounds__(kNT)
-query_xleaf_kernel(TreeView tv, int fl, const uint32_t* __restrict__ queries, int64_t m, int shift,
-                   int box, uint32_t* __restrict__ key) {
+query_xleaf_kernel(TreeView tv, int fl, const uint32_t* __restrict__ queries, int64_t m, int box,
+                   uint32_t* __restrict__ key) {
     const int d = tv.d;
     const int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x;
     if (i >= m) return;
@@ -77,21 +76,22 @@ query_xleaf_kernel(TreeView tv, int fl, const uint32_t* __restrict__ queries, in
         cur = r.y + (right ? 1u : 0u);
         r = tv.xn[cur];
     }
-    key[i] = r.x >> shift;
+    key[i] = r.x;
 }
 
-__global__ void bucket_count_kernel(const uint32_t* __restrict__ key, int64_t m,
+// Bucket of a query: its key shifted right by `shift`.
+__global__ void bucket_count_kernel(const uint32_t* __restrict__ key, int64_t m, int shift,
                                     uint32_t* __restrict__ cnt) {
     const int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x;
-    if (i < m) atomicAdd(&cnt[key[i]], 1u);
+    if (i < m) atomicAdd(&cnt[key[i] >> shift], 1u);
 }
 
 // start[b] is the next free slot of bucket b (its exclusive prefix sum
 // first); each query takes one.
-__global__ void bucket_fill_kernel(const uint32_t* __restrict__ key, int64_t m,
+__global__ void bucket_fill_kernel(const uint32_t* __restrict__ key, int64_t m, int shift,
                                    uint32_t* __restrict__ start, int32_t* __restrict__ order) {
     const int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x;
-    if (i < m) order[atomicAdd(&start[key[i]], 1u)] = (int32_t)i;
+    if (i < m) order[atomicAdd(&start[key[i] >> shift], 1u)] = (int32_t)i;
 }
 
 __global__ void check_queries_kernel(const uint32_t* __restrict__ q, int64_t count, int fl,
@@ -153,40 +153,45 @@ int64_t order_buckets(const TreeView& tv, int64_t m) {
 }
 
 pg_status order_queries(const TreeView& tv, bool fl, const void* queries, int64_t m,
-                        hipStream_t s, DevBuf& order, bool boxes) {
-    // one temporary: the queries' bucket keys, then the bucket counts, then
-    // the scan's partial sums
+                        hipStream_t s, DevBuf& order, bool boxes, QueryKeys* keys) {
+    // one allocation: the order, the queries' keys, the bucket counts, the
+    // scan's partial sums
     const int64_t nb = order_buckets(tv, m);
-    DevBuf work(s);
-    PG_TRY(work.alloc(sizeof(uint32_t) * (m + nb + scan_partials(nb))));
-    PG_TRY(order.alloc(sizeof(int32_t) * m));
-    return order_queries_ws(tv, fl, queries, m, s, order.as<int32_t>(), work.as<uint32_t>(),
-                            work.as<uint32_t>() + m + nb, boxes);
+    PG_TRY(order.alloc(sizeof(uint32_t) * (m + m + nb + scan_partials(nb))));
+    uint32_t* work = order.as<uint32_t>() + m;
+    return order_queries_ws(tv, fl, queries, m, s, order.as<int32_t>(), work, work + m + nb, boxes, keys);
 }
 
 pg_status order_queries_ws(const TreeView& tv, bool fl, const void* queries, int64_t m,
                            hipStream_t s, int32_t* order, uint32_t* work, uint32_t* sums,
-                           bool boxes) {
+                           bool boxes, QueryKeys* keys) {
     int shift;
     int64_t nb;
     bucket_plan(tv, m, &shift, &nb);
+    // heap trees: keys are the nodes of level L - shift (the buckets);
+    // explicit-node trees: leaf indices, shifted into buckets
     // the queries' bucket keys, then the bucket counts (which the scan turns,
     // in place, into each bucket's next free slot)
     uint32_t* key = work;
     uint32_t* cnt = key + m;
     PG_TRY(fill_u32(cnt, nb, 0u, s));
+    const int kshift = tv.xn ? shift : 0;
     if (tv.xn)
         hipLaunchKernelGGL(query_xleaf_kernel, dim3(cdiv(m, kNT)), dim3(kNT), 0, s, tv, fl ? 1 : 0,
-                           (const uint32_t*)queries, m, shift, boxes ? 1 : 0, key);
+                           (const uint32_t*)queries, m, boxes ? 1 : 0, key);
     else
         hipLaunchKernelGGL(query_leaf_kernel, dim3(cdiv(m, (int64_t)kNT * kLeafQpt)), dim3(kNT), 0, s,
                            tv, fl ? 1 : 0, (const uint32_t*)queries, m, tv.L - shift, boxes ? 1 : 0, key);
     PG_LAUNCH_CHECK();
-    hipLaunchKernelGGL(bucket_count_kernel, dim3(cdiv(m, kNT)), dim3(kNT), 0, s, key, m, cnt);
+    hipLaunchKernelGGL(bucket_count_kernel, dim3(cdiv(m, kNT)), dim3(kNT), 0, s, key, m, kshift, cnt);
     PG_LAUNCH_CHECK();
     PG_TRY(exclusive_scan_u32_ws(cnt, cnt, nb, nullptr, sums, s));
-    hipLaunchKernelGGL(bucket_fill_kernel, dim3(cdiv(m, kNT)), dim3(kNT), 0, s, key, m, cnt, order);
+    hipLaunchKernelGGL(bucket_fill_kernel, dim3(cdiv(m, kNT)), dim3(kNT), 0, s, key, m, kshift, cnt, order);
     PG_LAUNCH_CHECK();
+    if (keys) {
+        keys->key = key;
+        keys->lev = tv.xn ? -1 : tv.L - shift;
+    }
     return PG_OK;
 }
 
@@ -195,19 +200,20 @@ pg_status knn_static(const pg_tree* t, const void* queries, int64_t m, int k, bo
     if (m == 0) return PG_OK;
     DevBuf order(s);
     const int32_t* o = nullptr;
+    QueryKeys qk;
     if (!all && m >= kOrderMin && t->n > 0) {
         if (ws) {
             PG_TRY(order_queries_ws(t->view(), t->dtype == PG_FLOAT32, queries, m, s, ws->order,
-                                    ws->work, ws->sums));
+                                    ws->work, ws->sums, false, &qk));
             o = ws->order;
         } else {
-            PG_TRY(order_queries(t->view(), t->dtype == PG_FLOAT32, queries, m, s, order));
+            PG_TRY(order_queries(t->view(), t->dtype == PG_FLOAT32, queries, m, s, order, false, &qk));
             o = order.as<int32_t>();
         }
     }
     if (t->dtype == PG_FLOAT32)
-        return knn_static_float(t, queries, o, m, k, all, out_idx, out_dist, s, no_self, ws);
-    return knn_static_int(t, queries, o, m, k, all, out_idx, out_dist, s, no_self, ws);
+        return knn_static_float(t, queries, o, qk, m, k, all, out_idx, out_dist, s, no_self, ws);
+    return knn_static_int(t, queries, o, qk, m, k, all, out_idx, out_dist, s, no_self, ws);
 }
 
 }  // namespace pg

@@ -236,31 +236,43 @@ struct KnnWs {
     uint32_t* nredo;  // [1] their count
 };
 
+// Where each separate query's descent in the tree that ordered the queries
+// ended: key[i] is the level-`lev` node of a heap tree as an offset from
+// 2^lev, or (lev < 0) the leaf index of an explicit-node tree.  key == null:
+// not recorded.
+struct QueryKeys {
+    const uint32_t* key = nullptr;
+    int lev = 0;
+};
+
 // Buckets the query ordering uses for m queries over tree tv.
 int64_t order_buckets(const TreeView& tv, int64_t m);
 
 // A permutation of the m queries that follows the leaf order of tree tv (a
 // counting sort by the leaf each query's descent reaches); order receives
 // m int32 query indices.  With `boxes` the queries are boxes [m][2][d]
-// (lo, hi) and each descends by its centre.
+// (lo, hi) and each descends by its centre.  keys (may be null): where each
+// descent ended, valid while `order` is.
 pg_status order_queries(const TreeView& tv, bool fl, const void* queries, int64_t m,
-                        hipStream_t s, DevBuf& order, bool boxes = false);
-// The same into caller workspace (order [m], work [m + buckets], sums).
+                        hipStream_t s, DevBuf& order, bool boxes = false, QueryKeys* keys = nullptr);
+// The same into caller workspace (order [m], work [m + buckets], sums); the
+// keys live in the first m words of work.
 pg_status order_queries_ws(const TreeView& tv, bool fl, const void* queries, int64_t m,
                            hipStream_t s, int32_t* order, uint32_t* work, uint32_t* sums,
-                           bool boxes = false);
+                           bool boxes = false, QueryKeys* keys = nullptr);
 // no_self (all-points only): each point's own row is not a candidate.
 pg_status knn_static(const pg_tree* t, const void* queries, int64_t m, int k, bool all_points,
                      int32_t* out_idx, void* out_dist, hipStream_t s, bool no_self = false,
                      const KnnWs* ws = nullptr);
 
 // The static-tree k-NN launch for one coordinate type (order: the query
-// permutation or null; no_self: all-points without each point's own row).
-pg_status knn_static_int(const pg_tree* t, const void* queries, const int32_t* order, int64_t m,
-                         int k, bool all, int32_t* out_idx, void* out_dist, hipStream_t s,
+// permutation or null; qk: where the ordering's descents ended, or none;
+// no_self: all-points without each point's own row).
+pg_status knn_static_int(const pg_tree* t, const void* queries, const int32_t* order, QueryKeys qk,
+                         int64_t m, int k, bool all, int32_t* out_idx, void* out_dist, hipStream_t s,
                          bool no_self, const KnnWs* ws);
-pg_status knn_static_float(const pg_tree* t, const void* queries, const int32_t* order, int64_t m,
-                           int k, bool all, int32_t* out_idx, void* out_dist, hipStream_t s,
+pg_status knn_static_float(const pg_tree* t, const void* queries, const int32_t* order, QueryKeys qk,
+                           int64_t m, int k, bool all, int32_t* out_idx, void* out_dist, hipStream_t s,
                            bool no_self, const KnnWs* ws);
 
 // Validates query coordinates (range / finite); synchronises.

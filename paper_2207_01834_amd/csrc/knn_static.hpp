@@ -33,7 +33,7 @@ __device__ inline void load_query(const TreeView& tv, const uint32_t* queries, i
 template <typename T, int MD, int KT, bool EX, bool NS, int TK>
 __global__ void __launch_bounds__(kNT)
 knn_static_kernel(TreeView tv, const uint32_t* __restrict__ queries,
-                  const int32_t* __restrict__ order, int64_t m, int k, int all, int idbits,
+                  const int32_t* __restrict__ order, QueryKeys qk, int64_t m, int k, int all, int idbits,
                   int32_t* __restrict__ out_idx, typename Metric<T>::D* __restrict__ out_dist,
                   int32_t* __restrict__ redo, uint32_t* __restrict__ nredo) {
     const int d = MD < 8 ? MD : tv.d;
@@ -49,7 +49,8 @@ knn_static_kernel(TreeView tv, const uint32_t* __restrict__ queries,
     kl.init(idbits);
     const uint32_t start = search_start<TK>(tv, all != 0, i);
     if constexpr (NS) tree_search<T, MD, KL, OtherIds, TK>(tv, OtherIds{i}, q, d, kl, k, start);
-    else tree_search<T, MD, KL, PlainIds, TK>(tv, PlainIds{}, q, d, kl, k, start);
+    else tree_search<T, MD, KL, PlainIds, TK>(tv, PlainIds{}, q, d, kl, k, start,
+                                              all ? root_from<TK>() : search_from<TK>(tv, qk, i));
     if (kl.needs_redo()) {
         redo[atomicAdd(nredo, 1u)] = (int32_t)i;
         return;
@@ -98,7 +99,7 @@ knn_redo_kernel(TreeView tv, const uint32_t* __restrict__ queries, int k, int al
 constexpr unsigned kRedoBlocks = 512;
 
 template <typename T, int MD, int KT, bool EX, bool NS, int TK>
-pg_status launch_static(const pg_tree* t, const void* queries, const int32_t* order, int64_t m,
+pg_status launch_static(const pg_tree* t, const void* queries, const int32_t* order, QueryKeys qk, int64_t m,
                         int k, bool all, int32_t* out_idx, void* out_dist, hipStream_t s,
                         const KnnWs* ws) {
     using DT = typename Metric<T>::D;
@@ -118,7 +119,7 @@ pg_status launch_static(const pg_tree* t, const void* queries, const int32_t* or
         PG_TRY(fill_u32(nredo, 1, 0u, s));
     }
     hipLaunchKernelGGL((knn_static_kernel<T, MD, KT, EX, NS, TK>), dim3(grid_for_xcd(cdiv(m, kNT))),
-                       dim3(kNT), 0, s, t->view(), (const uint32_t*)queries, order, m, k,
+                       dim3(kNT), 0, s, t->view(), (const uint32_t*)queries, order, qk, m, k,
                        all ? 1 : 0, id_bits(t->n), out_idx, (DT*)out_dist, redo, nredo);
     PG_LAUNCH_CHECK();
     if (!exact) {
@@ -133,27 +134,27 @@ pg_status launch_static(const pg_tree* t, const void* queries, const int32_t* or
 // k-list capacities: exact lists for the common k = 5, 10, 16, otherwise the
 // next power of two with uniform guards.
 template <typename T, int MD, bool NS, int TK>
-pg_status dispatch_k(const pg_tree* t, const void* q, const int32_t* o, int64_t m, int k, bool all,
+pg_status dispatch_k(const pg_tree* t, const void* q, const int32_t* o, QueryKeys qk, int64_t m, int k, bool all,
                      int32_t* oi, void* od, hipStream_t s, const KnnWs* ws) {
-    if (k == 5) return launch_static<T, MD, 5, true, NS, TK>(t, q, o, m, k, all, oi, od, s, ws);
-    if (k == 10) return launch_static<T, MD, 10, true, NS, TK>(t, q, o, m, k, all, oi, od, s, ws);
-    if (k == 16) return launch_static<T, MD, 16, true, NS, TK>(t, q, o, m, k, all, oi, od, s, ws);
-    if (k <= 2) return launch_static<T, MD, 2, false, NS, TK>(t, q, o, m, k, all, oi, od, s, ws);
-    if (k <= 4) return launch_static<T, MD, 4, false, NS, TK>(t, q, o, m, k, all, oi, od, s, ws);
-    if (k <= 8) return launch_static<T, MD, 8, false, NS, TK>(t, q, o, m, k, all, oi, od, s, ws);
-    if (k <= 16) return launch_static<T, MD, 16, false, NS, TK>(t, q, o, m, k, all, oi, od, s, ws);
-    if (k <= 32) return launch_static<T, MD, 32, false, NS, TK>(t, q, o, m, k, all, oi, od, s, ws);
-    return launch_static<T, MD, 64, false, NS, TK>(t, q, o, m, k, all, oi, od, s, ws);
+    if (k == 5) return launch_static<T, MD, 5, true, NS, TK>(t, q, o, qk, m, k, all, oi, od, s, ws);
+    if (k == 10) return launch_static<T, MD, 10, true, NS, TK>(t, q, o, qk, m, k, all, oi, od, s, ws);
+    if (k == 16) return launch_static<T, MD, 16, true, NS, TK>(t, q, o, qk, m, k, all, oi, od, s, ws);
+    if (k <= 2) return launch_static<T, MD, 2, false, NS, TK>(t, q, o, qk, m, k, all, oi, od, s, ws);
+    if (k <= 4) return launch_static<T, MD, 4, false, NS, TK>(t, q, o, qk, m, k, all, oi, od, s, ws);
+    if (k <= 8) return launch_static<T, MD, 8, false, NS, TK>(t, q, o, qk, m, k, all, oi, od, s, ws);
+    if (k <= 16) return launch_static<T, MD, 16, false, NS, TK>(t, q, o, qk, m, k, all, oi, od, s, ws);
+    if (k <= 32) return launch_static<T, MD, 32, false, NS, TK>(t, q, o, qk, m, k, all, oi, od, s, ws);
+    return launch_static<T, MD, 64, false, NS, TK>(t, q, o, qk, m, k, all, oi, od, s, ws);
 }
 
 template <typename T, bool NS, int TK>
-pg_status dispatch_d(const pg_tree* t, const void* q, const int32_t* o, int64_t m, int k, bool all,
+pg_status dispatch_d(const pg_tree* t, const void* q, const int32_t* o, QueryKeys qk, int64_t m, int k, bool all,
                      int32_t* oi, void* od, hipStream_t s, const KnnWs* ws) {
     switch (t->d) {
-        case 2: return dispatch_k<T, 2, NS, TK>(t, q, o, m, k, all, oi, od, s, ws);
-        case 3: return dispatch_k<T, 3, NS, TK>(t, q, o, m, k, all, oi, od, s, ws);
-        case 5: return dispatch_k<T, 5, NS, TK>(t, q, o, m, k, all, oi, od, s, ws);
-        default: return dispatch_k<T, 8, NS, TK>(t, q, o, m, k, all, oi, od, s, ws);
+        case 2: return dispatch_k<T, 2, NS, TK>(t, q, o, qk, m, k, all, oi, od, s, ws);
+        case 3: return dispatch_k<T, 3, NS, TK>(t, q, o, qk, m, k, all, oi, od, s, ws);
+        case 5: return dispatch_k<T, 5, NS, TK>(t, q, o, qk, m, k, all, oi, od, s, ws);
+        default: return dispatch_k<T, 8, NS, TK>(t, q, o, qk, m, k, all, oi, od, s, ws);
     }
 }
 

@@ -71,8 +71,11 @@ __device__ inline void load_point(const TreeView& tv, int64_t i, int d, T (&p)[M
     }
 }
 
-// Points of leaf-order position i: id and liveness.
+// Points of leaf-order position i: id and liveness.  kLazy: the id and the
+// liveness cost loads of their own, so a point is measured first and they
+// are read only for a point within the current k-th distance.
 struct PlainIds {
+    static constexpr bool kLazy = false;
     __device__ inline int32_t id(int64_t, uint32_t idw) const { return (int32_t)idw; }
     __device__ inline bool live(int64_t) const { return true; }
 };
@@ -80,6 +83,7 @@ struct PlainIds {
 // Every point but the one at leaf-order position `self` (the query's own
 // point, for the k-NN graph).
 struct OtherIds {
+    static constexpr bool kLazy = false;
     int64_t self;
     __device__ inline int32_t id(int64_t, uint32_t idw) const { return (int32_t)idw; }
     __device__ inline bool live(int64_t i) const { return i != self; }
@@ -90,7 +94,13 @@ template <typename T, int MD, typename List, typename Ids>
 __device__ inline void visit_point(const Ids& ids, const T (&q)[MD], int d, List& kl, int k,
                                    uint32_t i, const T (&p)[MD], uint32_t idw) {
     using M = Metric<T>;
-    if (ids.live(i)) {
+    if constexpr (Ids::kLazy) {
+        typename M::D dd = 0;
+#pragma unroll
+        for (int c = 0; c < MD; c++)
+            if (MD < 8 || c < d) dd = M::acc(dd, q[c], p[c]);
+        if (!(dd > kl.kd) && ids.live(i)) kl.offer(dd, ids.id(i, idw), k);
+    } else if (ids.live(i)) {
         typename M::D dd = 0;
 #pragma unroll
         for (int c = 0; c < MD; c++)
@@ -115,8 +125,12 @@ __device__ inline uint32_t leaf_at(const int64_t* loff, int L, int64_t i) {
     return lo;
 }
 
-// k-NN walk of one query.  start: 0 = from the root; otherwise the heap index
-// of the leaf holding the query (all-points mode).
+// k-NN walk of one query.  start: 0 = a separate query; otherwise the heap
+// index of the leaf holding the query (all-points mode).  from (separate
+// queries): a node of the query's own descent -- the root, or the node where
+// the query ordering's descent stopped -- where the walk begins, as if
+// entered from its parent: the nodes above it were entered on the query's
+// side, so the climb treats them as any other.
 //
 // The walk (cur, entered from prev: its parent when prev < cur) hands leaves
 // to a scan phase.  A lane holds up to two reached-but-unscanned leaves: all
@@ -128,7 +142,7 @@ __device__ inline uint32_t leaf_at(const int64_t* loff, int L, int64_t i) {
 // LOFF: leaf ranges come from tv.loff (trees grown in place).
 template <typename T, int MD, typename List, typename Ids, bool LOFF = false>
 __device__ inline void kd_search(const TreeView& tv, const Ids& ids, const T (&q)[MD], int d,
-                                 List& kl, int k, uint32_t start = 0) {
+                                 List& kl, int k, uint32_t start = 0, uint32_t from = 1) {
     using M = Metric<T>;
     using DT = typename M::D;
     const int64_t n = tv.n;
@@ -152,9 +166,18 @@ __device__ inline void kd_search(const TreeView& tv, const Ids& ids, const T (&q
         prev = wstart;
         cur = wstart >> 1;
     } else {
-        p0 = 0;
-        prev = 0;
-        cur = 1;
+        // at or below the walk leaves: the walk leaf above `from` is the
+        // first leaf pending, and the walk stands at its parent
+        const int lv = 31 - __clz(from);
+        if (lv >= W) {
+            p0 = from >> (lv - W);
+            prev = p0;
+            cur = p0 >> 1;
+        } else {
+            p0 = 0;
+            prev = from >> 1;
+            cur = from;
+        }
     }
     // split dimension of internal node h at level lvl (trees with offsets may
     // carry one per node)

@@ -62,16 +62,18 @@ __device__ inline typename Metric<T>::D xnode_gap(const TreeView& tv, uint32_t u
     return lb;
 }
 
-// k-NN walk of one query over an explicit-node tree.  start: kXNone = from
-// the root; otherwise the leaf node holding the query (all-points mode: the
-// walk scans it first and then climbs its path, where the child it came from
-// counts as the one entered first).
+// k-NN walk of one query over an explicit-node tree.  start: kXNone = a
+// separate query; otherwise the leaf node holding the query (all-points mode:
+// the walk scans it first and then climbs its path, where the child it came
+// from counts as the one entered first).  from (separate queries): a node of
+// the query's own descent (0: the root) where the walk begins, as if entered
+// from its parent.
 //
 // As in kd_search a lane holds up to two reached-but-unscanned leaves, and
 // all lanes walk while some lane has none.
 template <typename T, int MD, typename List, typename Ids>
 __device__ inline void kdx_search(const TreeView& tv, const Ids& ids, const T (&q)[MD], int d,
-                                  List& kl, int k, uint32_t start = kXNone) {
+                                  List& kl, int k, uint32_t start = kXNone, uint32_t from = 0) {
     using M = Metric<T>;
     if (tv.n == 0) return;
     uint32_t cur, prev, pathc = kXNone, pathp = kXNone, p0 = kXNone, p1 = kXNone;
@@ -81,13 +83,17 @@ __device__ inline void kdx_search(const TreeView& tv, const Ids& ids, const T (&
         pathp = start;
         cur = tv.xn[start].z;
         pathc = cur;
-    } else if (tv.xn[0].w & kXLeaf) {
-        p0 = 0;
-        prev = 0;
-        cur = kXNone;
     } else {
-        cur = 0;
-        prev = kXNone;
+        const uint4 r = tv.xn[from];
+        if (r.w & kXLeaf) {
+            // the leaf pending (an empty one skipped), the walk at its parent
+            p0 = (r.w & kXEmpty) ? kXNone : from;
+            prev = from;
+            cur = r.z;
+        } else {
+            cur = from;
+            prev = r.z;
+        }
     }
     bool more;
     do {
@@ -181,12 +187,25 @@ __device__ inline uint32_t search_start(const TreeView& tv, bool all, int64_t i)
     else return all ? (1u << tv.L) + leaf_of(tv.n, tv.L, i) : 0u;
 }
 
-// The k-NN walk for tree kind TK (start from search_start).
+// Where the walk of separate query i begins: the node its recorded descent
+// reached (qk from the ordering by this same tree), else the root.
+template <int TK>
+__device__ inline uint32_t search_from(const TreeView& tv, const QueryKeys& qk, int64_t i) {
+    if constexpr (TK == kTreeX) return (qk.key && qk.lev < 0) ? tv.lnode[qk.key[i]] : 0u;
+    else return qk.key ? qk.key[i] + (1u << qk.lev) : 1u;
+}
+
+// The root as the start of a separate query's walk.
+template <int TK>
+__device__ inline uint32_t root_from() { return TK == kTreeX ? 0u : 1u; }
+
+// The k-NN walk for tree kind TK (start from search_start; from, for a
+// separate query, from search_from or root_from).
 template <typename T, int MD, typename List, typename Ids, int TK>
 __device__ inline void tree_search(const TreeView& tv, const Ids& ids, const T (&q)[MD], int d,
-                                   List& kl, int k, uint32_t start) {
-    if constexpr (TK == kTreeX) kdx_search<T, MD, List, Ids>(tv, ids, q, d, kl, k, start);
-    else kd_search<T, MD, List, Ids, TK == kTreeLoff>(tv, ids, q, d, kl, k, start);
+                                   List& kl, int k, uint32_t start, uint32_t from = root_from<TK>()) {
+    if constexpr (TK == kTreeX) kdx_search<T, MD, List, Ids>(tv, ids, q, d, kl, k, start, from);
+    else kd_search<T, MD, List, Ids, TK == kTreeLoff>(tv, ids, q, d, kl, k, start, from);
 }
 
 }  // namespace pg
