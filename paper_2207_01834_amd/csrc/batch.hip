@@ -364,15 +364,34 @@ __device__ inline int cloud_of_item(const int64_t* __restrict__ start, int C, in
     return lo;
 }
 
-// inv[row] = leaf position of the row within its cloud.
+// Work items are dealt to the XCDs in contiguous eighths (xcd_block), so the
+// items of a cloud run on one XCD and its points stay in that XCD's L2.
+__device__ inline int64_t bwd_item() { return xcd_block(); }
+
+// inv[row] = global leaf position of the row (its cloud's first row plus its
+// position in the cloud's leaf order).  With rrec (d <= 3): rrec[row] = {the
+// row's coordinates, its global leaf position}, so that the main pass
+// gathers a neighbour's coordinates and window slot with one 16-byte load.
 __global__ void bwd_inv_kernel(const CloudDesc* __restrict__ desc, const int64_t* __restrict__ start,
-                               int C, const int32_t* __restrict__ pidx, int32_t* __restrict__ inv) {
-    const int c = cloud_of_item(start, C, blockIdx.x);
+                               int C, int64_t items, const int32_t* __restrict__ pidx,
+                               const float* __restrict__ x, int d, int32_t* __restrict__ inv,
+                               uint4* __restrict__ rrec) {
+    const int64_t it = bwd_item();
+    if (it >= items) return;
+    const int c = cloud_of_item(start, C, it);
     const CloudDesc D = desc[c];
-    const int64_t p0 = ((int64_t)blockIdx.x - start[c]) * kBwdItem;
+    const int64_t p0 = (it - start[c]) * kBwdItem;
     for (int e = threadIdx.x; e < kBwdItem; e += kNT) {
         const int64_t pos = p0 + e;
-        if (pos < D.n) inv[D.row + pidx[D.row + pos]] = (int32_t)pos;
+        if (pos >= D.n) break;
+        const int64_t row = D.row + pidx[D.row + pos];
+        if (rrec) {
+            uint32_t w[3] = {0u, 0u, 0u};
+            for (int cc = 0; cc < d; cc++) w[cc] = __float_as_uint(x[row * d + cc]);
+            rrec[row] = make_uint4(w[0], w[1], w[2], (uint32_t)(D.row + pos));
+        } else {
+            inv[row] = (int32_t)(D.row + pos);
+        }
     }
 }
 
@@ -382,13 +401,15 @@ __global__ void bwd_inv_kernel(const CloudDesc* __restrict__ desc, const int64_t
 // orders above every finite value.  One workgroup per backward item (its
 // rows' pairs are contiguous).
 __global__ void __launch_bounds__(kNT)
-bwd_scale_kernel(const CloudDesc* __restrict__ desc, const int64_t* __restrict__ start, int C, int k,
-                 const float* __restrict__ g, const float* __restrict__ d2,
+bwd_scale_kernel(const CloudDesc* __restrict__ desc, const int64_t* __restrict__ start, int C,
+                 int64_t items, int k, const float* __restrict__ g, const float* __restrict__ d2,
                  uint32_t* __restrict__ maxes) {
     __shared__ uint32_t red[2][kNT / kWave];
-    const int c = cloud_of_item(start, C, blockIdx.x);
+    const int64_t it = bwd_item();
+    if (it >= items) return;
+    const int c = cloud_of_item(start, C, it);
     const CloudDesc D = desc[c];
-    const int64_t p0 = ((int64_t)blockIdx.x - start[c]) * kBwdItem;
+    const int64_t p0 = (it - start[c]) * kBwdItem;
     const int64_t r1 = D.row + (p0 + kBwdItem < D.n ? p0 + kBwdItem : (int64_t)D.n);
     uint32_t mg = 0, md = 0;
     for (int64_t p = (D.row + p0) * k + threadIdx.x; p < r1 * k; p += kNT) {
@@ -431,24 +452,28 @@ __device__ inline float bwd_scale(const uint32_t* maxes, int c) {
 
 // One work item: kBwdItem leaf positions of one cloud.  Lane queries i (in
 // leaf order) accumulate their own gradient in registers (fixed order) and
-// write it to gout; the neighbour terms go to the LDS window, or the pair to
-// the spill list; the window is then stored to the item's slot of wbuf and the
-// spilled pairs' terms are added to acc.
+// write it to gl at their global leaf position; the neighbour terms go to the
+// LDS window, or the pair to the spill list; the window is then stored to the
+// item's slot of wbuf and the spilled pairs' terms are added to acc (indexed
+// by global leaf position).
 template <int MD>
 __global__ void __launch_bounds__(kNT)
 bwd_main_kernel(const CloudDesc* __restrict__ desc, const int64_t* __restrict__ start, int C,
-                const int32_t* __restrict__ pidx, const int32_t* __restrict__ inv,
-                const float* __restrict__ x, int d_, int k, const int32_t* __restrict__ idx,
+                int64_t items, const int32_t* __restrict__ pidx, const int32_t* __restrict__ inv,
+                const uint4* __restrict__ rrec, const float* __restrict__ x, int d_, int k,
+                const int32_t* __restrict__ idx,
                 const float* __restrict__ g, const uint32_t* __restrict__ maxes,
                 unsigned long long* __restrict__ acc, unsigned long long* __restrict__ wbuf,
-                float* __restrict__ gout) {
+                float* __restrict__ gl) {
     extern __shared__ __align__(16) unsigned long long win[];  // [kBwdWin][d]
     __shared__ uint32_t spill[kBwdSpill];
     __shared__ uint32_t nspill;
     const int d = MD < 8 ? MD : d_;
-    const int c = cloud_of_item(start, C, blockIdx.x);
+    const int64_t it = bwd_item();
+    if (it >= items) return;
+    const int c = cloud_of_item(start, C, it);
     const CloudDesc D = desc[c];
-    const int64_t p0 = ((int64_t)blockIdx.x - start[c]) * kBwdItem;
+    const int64_t p0 = (it - start[c]) * kBwdItem;
     const int64_t org = p0 - kBwdMargin;  // position of window entry 0
     for (int e = threadIdx.x; e < kBwdWin * d; e += kNT) win[e] = 0ull;
     if (threadIdx.x == 0) nspill = 0;
@@ -483,16 +508,27 @@ bwd_main_kernel(const CloudDesc* __restrict__ desc, const int64_t* __restrict__ 
                 }
             }
             float xj[4][MD];
-            int64_t w[4];
+            int64_t w[4], pg[4];
 #pragma unroll
             for (int u = 0; u < 4; u++) {
                 const int32_t j = jj[u] >= 0 ? jj[u] : (int32_t)i;  // a safe row for the loads
+                int64_t pj;
+                if constexpr (MD <= 3) {
+                    const uint4 r = rrec[j];
+                    const uint32_t rw[3] = {r.x, r.y, r.z};
 #pragma unroll
-                for (int cc = 0; cc < MD; cc++)
-                    xj[u][cc] = (MD < 8 || cc < d) ? x[(int64_t)j * d + cc] : 0.0f;
+                    for (int cc = 0; cc < MD; cc++) xj[u][cc] = __uint_as_float(rw[cc]);
+                    pj = (int64_t)r.w;
+                } else {
+#pragma unroll
+                    for (int cc = 0; cc < MD; cc++)
+                        xj[u][cc] = (MD < 8 || cc < d) ? x[(int64_t)j * d + cc] : 0.0f;
+                    pj = (uint32_t)inv[j];
+                }
                 // a neighbour of the same cloud inside the window sums in LDS
                 const bool same = jj[u] >= 0 && j >= D.row && j < D.row + D.n;
-                w[u] = same ? (int64_t)inv[j] - org : -1;
+                w[u] = same ? pj - D.row - org : -1;
+                pg[u] = pj;
             }
 #pragma unroll
             for (int u = 0; u < 4; u++) {
@@ -524,28 +560,28 @@ bwd_main_kernel(const CloudDesc* __restrict__ desc, const int64_t* __restrict__ 
 #pragma unroll
                         for (int cc = 0; cc < MD; cc++)
                             if (MD < 8 || cc < d)
-                                atomicAdd(&acc[(int64_t)jj[u] * d + cc], (unsigned long long)(long long)t[cc]);
+                                atomicAdd(&acc[pg[u] * d + cc], (unsigned long long)(long long)t[cc]);
                     }
                 }
             }
         }
 #pragma unroll
         for (int cc = 0; cc < MD; cc++)
-            if (MD < 8 || cc < d) gout[i * d + cc] = gq[cc];
+            if (MD < 8 || cc < d) gl[(D.row + pos) * d + cc] = gq[cc];
     }
     __syncthreads();
-    unsigned long long* slot = wbuf + (int64_t)blockIdx.x * kBwdWin * d;
+    unsigned long long* slot = wbuf + it * kBwdWin * d;
     for (int e = threadIdx.x; e < kBwdWin * d; e += kNT) slot[e] = win[e];
     __syncthreads();
     // spilled pairs: terms into the (now free) window space, then the atomics
     const int ns = nspill < (uint32_t)kBwdSpill ? (int)nspill : kBwdSpill;
-    int32_t* rec = reinterpret_cast<int32_t*>(win);  // [ns][d + 1]: row j, terms
+    int32_t* rec = reinterpret_cast<int32_t*>(win);  // [ns][d + 1]: j's global leaf position, terms
     for (int e = threadIdx.x; e < ns; e += kNT) {
         const uint32_t pp = spill[e];
         const int64_t i = pp / (uint32_t)k;
         const int32_t j = idx[pp];
         const float gr = g[pp];
-        rec[e * (d + 1)] = j;
+        rec[e * (d + 1)] = (int32_t)(MD <= 3 ? rrec[j].w : (uint32_t)inv[j]);
         for (int cc = 0; cc < d; cc++) {
             const float diff = x[i * d + cc] - x[(int64_t)j * d + cc];
             rec[e * (d + 1) + 1 + cc] = (int32_t)rintf(-2.0f * gr * diff * scale);
@@ -554,25 +590,28 @@ bwd_main_kernel(const CloudDesc* __restrict__ desc, const int64_t* __restrict__ 
     __syncthreads();
     for (int e = threadIdx.x; e < ns * d; e += kNT) {
         const int q = e / d, cc = e - q * d;
-        const int64_t j = rec[q * (d + 1)];
-        atomicAdd(&acc[j * d + cc], (unsigned long long)(long long)rec[q * (d + 1) + 1 + cc]);
+        const int64_t pj = (uint32_t)rec[q * (d + 1)];
+        atomicAdd(&acc[pj * d + cc], (unsigned long long)(long long)rec[q * (d + 1) + 1 + cc]);
     }
 }
 
 // Per item: each of its positions takes its own window entry, the entry of
 // the neighbouring item of the same cloud whose window also covers it, if any
 // (the previous item's below p0 + kBwdMargin, the next item's from
-// p0 + kBwdItem - kBwdMargin on), and its row accumulator; gout += that sum /
-// scale (NaN, and bit 1 of *flags, for a cloud whose scale is 0).
+// p0 + kBwdItem - kBwdMargin on), and its accumulator (all in leaf order);
+// gout[row] = its own gradient (gl, leaf order) + that sum / scale (NaN, and
+// bit 1 of *flags, for a cloud whose scale is 0): one store per row.
 __global__ void __launch_bounds__(kNT)
 bwd_finish_kernel(const CloudDesc* __restrict__ desc, const int64_t* __restrict__ start, int C,
-                  const int32_t* __restrict__ pidx, int d,
+                  int64_t items, const int32_t* __restrict__ pidx, int d,
                   const unsigned long long* __restrict__ wbuf,
                   const unsigned long long* __restrict__ acc, const uint32_t* __restrict__ maxes,
-                  uint32_t* __restrict__ flags, float* __restrict__ gout) {
-    const int c = cloud_of_item(start, C, blockIdx.x);
+                  const float* __restrict__ gl, uint32_t* __restrict__ flags, float* __restrict__ gout) {
+    const int64_t b = bwd_item();
+    if (b >= items) return;
+    const int c = cloud_of_item(start, C, b);
     const CloudDesc D = desc[c];
-    const int64_t b = blockIdx.x, b0 = start[c], b1 = start[c + 1];
+    const int64_t b0 = start[c], b1 = start[c + 1];
     const int64_t p0 = (b - b0) * kBwdItem;
     const float scale = bwd_scale(maxes, c);
     const float inv_scale = scale > 0.0f ? 1.0f / scale : __builtin_nanf("");
@@ -589,8 +628,9 @@ bwd_finish_kernel(const CloudDesc* __restrict__ desc, const int64_t* __restrict_
         } else if (pos >= p0 + kBwdItem - kBwdMargin) {
             if (b + 1 < b1) v += (long long)wbuf[(b + 1) * kBwdWin * d + (pos - (p0 + kBwdItem - kBwdMargin)) * d + cc];
         }
-        v += (long long)acc[row * d + cc];
-        gout[row * d + cc] += (float)((double)v * (double)inv_scale);
+        const int64_t gp = (D.row + pos) * d + cc;
+        v += (long long)acc[gp];
+        gout[row * d + cc] = gl[gp] + (float)((double)v * (double)inv_scale);
     }
 }
 
@@ -1016,31 +1056,34 @@ pg_status pg_batch_backward(pg_batch* b, const float* points, int32_t k, const i
     const int64_t items = PL.bstart[C];
     const CloudDesc* desc = (const CloudDesc*)(b->ws + PL.o_desc);
     const int32_t* pidx = (const int32_t*)(b->ws + PL.o_pidx);
-    DevBuf inv(s), acc(s), maxes(s), wbuf(s);
-    PG_TRY(inv.alloc(sizeof(int32_t) * (size_t)N));
+    DevBuf inv(s), acc(s), maxes(s), wbuf(s), gl(s);
+    const bool recs = d <= 3;  // row records {x, leaf position} instead of inv
+    PG_TRY(inv.alloc(recs ? sizeof(uint4) * (size_t)N : sizeof(int32_t) * (size_t)N));
     PG_TRY(acc.alloc(sizeof(unsigned long long) * (size_t)N * d));
     PG_TRY(maxes.alloc(sizeof(uint32_t) * 2 * (size_t)C));
+    PG_TRY(gl.alloc(sizeof(float) * (size_t)N * d));
     PG_TRY(wbuf.alloc(sizeof(unsigned long long) * (size_t)items * kBwdWin * d));
     PG_HIP(hipMemsetAsync(acc.p, 0, sizeof(unsigned long long) * (size_t)N * d, s));
     PG_HIP(hipMemsetAsync(maxes.p, 0, sizeof(uint32_t) * 2 * (size_t)C, s));
-    hipLaunchKernelGGL(bwd_inv_kernel, dim3((unsigned)items), dim3(kNT), 0, s, desc,
-                       (const int64_t*)b->bstart_dev, C, pidx, inv.as<int32_t>());
+    const unsigned grid = grid_for_xcd(items);
+    hipLaunchKernelGGL(bwd_inv_kernel, dim3(grid), dim3(kNT), 0, s, desc, (const int64_t*)b->bstart_dev,
+                       C, items, pidx, points, d, inv.as<int32_t>(), recs ? inv.as<uint4>() : nullptr);
     PG_LAUNCH_CHECK();
-    hipLaunchKernelGGL(bwd_scale_kernel, dim3((unsigned)items), dim3(kNT), 0, s, desc,
-                       (const int64_t*)b->bstart_dev, C, k, grad_d2, d2, maxes.as<uint32_t>());
+    hipLaunchKernelGGL(bwd_scale_kernel, dim3(grid), dim3(kNT), 0, s, desc, (const int64_t*)b->bstart_dev,
+                       C, items, k, grad_d2, d2, maxes.as<uint32_t>());
     PG_LAUNCH_CHECK();
     const size_t lds = sizeof(unsigned long long) * (size_t)kBwdWin * d;
     auto main_kernel = d == 2 ? bwd_main_kernel<2>
                      : d == 3 ? bwd_main_kernel<3>
                      : d == 5 ? bwd_main_kernel<5> : bwd_main_kernel<8>;
-    hipLaunchKernelGGL(main_kernel, dim3((unsigned)items), dim3(kNT), lds, s, desc,
-                       (const int64_t*)b->bstart_dev, C, pidx, inv.as<int32_t>(), points, d, k, idx,
+    hipLaunchKernelGGL(main_kernel, dim3(grid), dim3(kNT), lds, s, desc, (const int64_t*)b->bstart_dev, C,
+                       items, pidx, inv.as<int32_t>(), recs ? inv.as<uint4>() : nullptr, points, d, k, idx,
                        grad_d2, maxes.as<uint32_t>(), acc.as<unsigned long long>(),
-                       wbuf.as<unsigned long long>(), grad_points);
+                       wbuf.as<unsigned long long>(), gl.as<float>());
     PG_LAUNCH_CHECK();
-    hipLaunchKernelGGL(bwd_finish_kernel, dim3((unsigned)items), dim3(kNT), 0, s, desc,
-                       (const int64_t*)b->bstart_dev, C, pidx, d, wbuf.as<unsigned long long>(),
-                       acc.as<unsigned long long>(), maxes.as<uint32_t>(),
+    hipLaunchKernelGGL(bwd_finish_kernel, dim3(grid), dim3(kNT), 0, s, desc,
+                       (const int64_t*)b->bstart_dev, C, items, pidx, d, wbuf.as<unsigned long long>(),
+                       acc.as<unsigned long long>(), maxes.as<uint32_t>(), gl.as<float>(),
                        (uint32_t*)(b->ws + PL.o_queue) + 1, grad_points);
     PG_LAUNCH_CHECK();
     return PG_OK;

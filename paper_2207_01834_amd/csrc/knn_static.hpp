@@ -5,6 +5,9 @@
 // walk nearly the same nodes; the result row is the point's input row.
 #pragma once
 
+#include <cstdlib>
+#include <string>
+
 #include "scan.hpp"
 #include "xsearch.hpp"
 #include "wave.hpp"
@@ -98,6 +101,30 @@ knn_redo_kernel(TreeView tv, const uint32_t* __restrict__ queries, int k, int al
 
 constexpr unsigned kRedoBlocks = 512;
 
+}  // namespace knn_detail
+}  // namespace pg
+
+#include "knn_wave.hpp"
+
+namespace pg {
+namespace knn_detail {
+
+// Whether a heap tree with node boxes takes the wave-per-block walk
+// (knn_wave.hpp) instead of the per-lane walk.  The per-lane walk is the
+// default: measured on 3-D n = 10M all-points k = 10, the wave walk issues
+// about twice the vector instructions per wave (each lane measures every
+// point of the union of the wave's leaves, about ten times the points of its
+// own search) and runs about five times longer.  PG_KNN_WAVE selects it, read
+// at every launch: "all" (all-points searches), "sep" (separate queries),
+// "both"; anything else, or unset, keeps the per-lane walk.
+inline bool use_wave_kernel(bool all) {
+    const char* e = std::getenv("PG_KNN_WAVE");
+    if (!e) return false;
+    const std::string v(e);
+    const int mode = v == "all" ? 1 : v == "sep" ? 2 : v == "both" ? 3 : 0;
+    return all ? (mode & 1) != 0 : (mode & 2) != 0;
+}
+
 template <typename T, int MD, int KT, bool EX, bool NS, int TK>
 pg_status launch_static(const pg_tree* t, const void* queries, const int32_t* order, QueryKeys qk, int64_t m,
                         int k, bool all, int32_t* out_idx, void* out_dist, hipStream_t s,
@@ -118,9 +145,21 @@ pg_status launch_static(const pg_tree* t, const void* queries, const int32_t* or
         }
         PG_TRY(fill_u32(nredo, 1, 0u, s));
     }
-    hipLaunchKernelGGL((knn_static_kernel<T, MD, KT, EX, NS, TK>), dim3(grid_for_xcd(cdiv(m, kNT))),
-                       dim3(kNT), 0, s, t->view(), (const uint32_t*)queries, order, qk, m, k,
-                       all ? 1 : 0, id_bits(t->n), out_idx, (DT*)out_dist, redo, nredo);
+    const TreeView tv = t->view();
+    bool wave = false;
+    if constexpr (TK == kTreeHeap && MD <= 7) {
+        if (tv.nbox != nullptr && t->leaf <= kWave && use_wave_kernel(all)) {
+            wave = true;
+            hipLaunchKernelGGL((knn_wave_kernel<T, MD, KT, EX, NS>), dim3(grid_for_xcd(cdiv(m, kNT))),
+                               dim3(kNT), 0, s, tv, (const uint32_t*)queries, order, m, k, all ? 1 : 0,
+                               id_bits(t->n), out_idx, (DT*)out_dist, redo, nredo, tv.split, tv.nbox,
+                               tv.rec);
+        }
+    }
+    if (!wave)
+        hipLaunchKernelGGL((knn_static_kernel<T, MD, KT, EX, NS, TK>), dim3(grid_for_xcd(cdiv(m, kNT))),
+                           dim3(kNT), 0, s, tv, (const uint32_t*)queries, order, qk, m, k,
+                           all ? 1 : 0, id_bits(t->n), out_idx, (DT*)out_dist, redo, nredo);
     PG_LAUNCH_CHECK();
     if (!exact) {
         hipLaunchKernelGGL((knn_redo_kernel<T, MD, KT, EX, NS, TK>), dim3(kRedoBlocks), dim3(kNT), 0, s,

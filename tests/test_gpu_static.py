@@ -280,3 +280,25 @@ def test_knn_graph_full_size_sampled(pg, dev):
     rows = np.random.default_rng(12).choice(len(pts), 300, replace=False)
     oi, od = graph_oracle_rows(pts, rows, 10)
     assert_int_equal(gi[rows], gd[rows], oi, od)
+
+
+@pytest.mark.parametrize("case", range(0, 36, 3))
+def test_wave_walk_small_random(pg, dev, case, monkeypatch):
+    # the wave-per-block walk (selected per launch by PG_KNN_WAVE) must
+    # return the lists of the per-lane walk: all-points, separate queries
+    # and queries equal to the points, over the mixed small cases
+    monkeypatch.setenv("PG_KNN_WAVE", "both")
+    for c in (case, case + 1, case + 2):
+        test_small_random(pg, dev, c)
+
+
+def test_wave_walk_ties_redo_graph(pg, dev, monkeypatch):
+    monkeypatch.setenv("PG_KNN_WAVE", "both")
+    test_ties_identical_grid_planes(pg, dev)
+    test_wide_distances_exact_redo(pg, dev)
+    say("wave walk: knn graph")
+    pts = np.random.default_rng(4).integers(0, 8, (3_000, 3)).astype(np.int32)
+    t = pg.kdtree_build(to_dev(pts, dev), leaf=16)
+    gi, gd = host(*t.knn_graph(10))
+    oi, od = oracle.knn_graph_brute(pts, 10, nthreads=8)
+    assert_int_equal(gi, gd, oi, od)
