@@ -94,8 +94,8 @@ def log(*a):
 
 def knn_source_hash():
     h = hashlib.sha256()
-    for f in ("knn.hip", "knn_static.hpp", "knn_int.hip", "search.hpp", "knn.hpp", "common.hpp",
-              "wave.hpp"):
+    for f in ("knn.hip", "knn_static.hpp", "knn_wave.hpp", "knn_int.hip", "search.hpp", "xsearch.hpp",
+              "knn.hpp", "common.hpp", "wave.hpp"):
         with open(os.path.join(ROOT, "paper_2207_01834_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
