@@ -347,6 +347,13 @@ static void add_subtree(knn_ctx* C, int l, int64_t j) {
 static void box_bounds(const knn_ctx* C, int64_t h, or_key* lo_key, or_key* hi_key) {
     const or_tree* T = C->T; int d = T->d;
     int64_t loi = 0, hii = 0; double lof = 0.0, hif = 0.0;
+    if (T->bmin[h * d] > T->bmax[h * d]) {
+        /* a node without points (its box is [+inf, -inf]): beyond every
+         * distance, so it is never entered or added */
+        lo_key->di = INT64_MAX; lo_key->df = INFINITY; lo_key->id = INT64_MAX;
+        hi_key->di = INT64_MAX; hi_key->df = INFINITY; hi_key->id = INT64_MAX;
+        return;
+    }
     for (int c = 0; c < d; c++) {
         double q = qcoord(C, c), a = T->bmin[h * d + c], b = T->bmax[h * d + c];
         if (T->dt == OR_DT_INT) {
