@@ -486,8 +486,12 @@ pg_status pg_batch_status(const pg_batch* b, void* stream, int32_t* flags);
 
 /* Times every tuning candidate (leaf 8/16/32 x 2/4 workgroups per CU x 1/4
  * queries per lane x k-list in registers/LDS: 24 launches) on these points
- * and returns the fastest; results are cached per
- * (clouds, size bucket, d, k) for the life of the process.  Synchronises. */
+ * and returns the fastest.  Results are cached per (device, cloud-count
+ * bucket, point-count bucket, d, k) -- buckets are powers of two -- for the
+ * life of the process, and, when the environment variable PG_TUNE_CACHE
+ * names a file, across processes: a key found there is returned without
+ * timing, a new choice is appended (one text line per key; unreadable lines
+ * are ignored).  Synchronises when it times. */
 pg_status pg_batch_autotune(const float* points, const int64_t* offsets_host, int32_t n_clouds,
                             int32_t d, int32_t k, void* stream, pg_tune* best);
 

@@ -23,10 +23,14 @@
 // fastest per workload key; every choice returns identical results (the k-NN
 // result depends neither on the tree nor on where the list lives).
 #include <algorithm>
+#include <cstdlib>
+#include <fstream>
 #include <map>
 #include <mutex>
 #include <new>
 #include <numeric>
+#include <sstream>
+#include <string>
 #include <tuple>
 #include <vector>
 
@@ -774,7 +778,63 @@ pg_status batch_k(pg_batch* b, const BatchParams& P, hipStream_t s) {
 }
 
 std::mutex g_tune_mu;
-std::map<std::tuple<int, int64_t, int, int>, pg_tune> g_tune_cache;
+std::map<std::tuple<std::string, int64_t, int64_t, int, int>, pg_tune> g_tune_cache;
+
+// The tuner's cache key: the device (its name and ISA), the cloud count and
+// the point count each rounded up to a power of two, d and k.
+using TuneKey = std::tuple<std::string, int64_t, int64_t, int, int>;
+
+inline int64_t pow2_at_least(int64_t v) {
+    int64_t b = 1;
+    while (b < v) b <<= 1;
+    return b;
+}
+
+std::string device_tag() {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+    std::string tag = std::string(prop.gcnArchName) + "/" + prop.name;
+    for (char& ch : tag)
+        if (ch == ' ' || ch == '\t' || ch == '\n') ch = '_';
+    return tag;
+}
+
+// PG_TUNE_CACHE names a text file that keeps the tuner's choices across
+// processes: one line per key, "device clouds points d k leaf blocks_per_cu
+// lane_queries klist" (the counts as their power-of-two buckets).  Lines
+// that do not parse, or whose choice is out of range, are ignored; a new
+// choice is appended.
+bool tune_file_lookup(const char* path, const TuneKey& key, pg_tune* out) {
+    std::ifstream in(path);
+    if (!in) return false;
+    std::string line;
+    bool found = false;
+    while (std::getline(in, line)) {
+        std::istringstream ls(line);
+        std::string dev;
+        int64_t c = 0, n = 0;
+        int d = 0, k = 0;
+        pg_tune t{};
+        if (!(ls >> dev >> c >> n >> d >> k >> t.leaf >> t.blocks_per_cu >> t.lane_queries >> t.klist)) continue;
+        if (t.leaf < 1 || t.leaf > 64 || t.blocks_per_cu < 1 || t.blocks_per_cu > 16 || t.lane_queries < 1 ||
+            t.lane_queries > 8 || (t.klist != PG_KLIST_VGPR && t.klist != PG_KLIST_LDS))
+            continue;
+        if (TuneKey(dev, c, n, d, k) == key) {
+            *out = t;  // the last matching line wins
+            found = true;
+        }
+    }
+    return found;
+}
+
+void tune_file_append(const char* path, const TuneKey& key, const pg_tune& t) {
+    std::ofstream o(path, std::ios::app);
+    if (!o) return;
+    o << std::get<0>(key) << ' ' << std::get<1>(key) << ' ' << std::get<2>(key) << ' ' << std::get<3>(key) << ' '
+      << std::get<4>(key) << ' ' << t.leaf << ' ' << t.blocks_per_cu << ' ' << t.lane_queries << ' ' << t.klist
+      << '\n';
+}
 
 }  // namespace
 }  // namespace pg
@@ -969,14 +1029,19 @@ pg_status pg_batch_autotune(const float* points, const int64_t* offsets_host, in
     if (n_clouds < 1 || d < 1 || d > 8 || k < 1 || k > 64)
         return fail(PG_ERR_INVALID, "pg_batch_autotune: bad sizes");
     const int64_t N = offsets_host[n_clouds];
-    int64_t bucket = 1;
-    while (bucket < N) bucket <<= 1;
-    const auto key = std::make_tuple(n_clouds, bucket, d * 100 + k, 0);
+    const TuneKey key(device_tag(), pow2_at_least(n_clouds), pow2_at_least(N), d, k);
+    const char* cache_path = std::getenv("PG_TUNE_CACHE");
     {
         std::lock_guard<std::mutex> g(g_tune_mu);
         auto it = g_tune_cache.find(key);
         if (it != g_tune_cache.end()) {
             *best = it->second;
+            return PG_OK;
+        }
+        pg_tune t{};
+        if (cache_path && *cache_path && tune_file_lookup(cache_path, key, &t)) {
+            g_tune_cache[key] = t;
+            *best = t;
             return PG_OK;
         }
     }
@@ -1023,6 +1088,7 @@ pg_status pg_batch_autotune(const float* points, const int64_t* offsets_host, in
     {
         std::lock_guard<std::mutex> g(g_tune_mu);
         g_tune_cache[key] = win;
+        if (cache_path && *cache_path) tune_file_append(cache_path, key, win);
     }
     *best = win;
     return PG_OK;

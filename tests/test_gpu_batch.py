@@ -443,3 +443,47 @@ def test_batched_backward_mixed_scales_and_nonfinite(pg, dev):
     assert B.backward_nonfinite()
     assert np.isnan(grad[offs[3]:offs[4]]).all()
     assert np.isfinite(grad[:offs[3]]).all()
+
+
+_TUNE_CHILD = r"""
+import json, sys
+sys.path.insert(0, sys.argv[1])
+import numpy as np, torch
+from paper_2207_01834_amd import _binding as pg, datagen
+sizes = np.array([300, 0, 1500, 40, 900], dtype=np.int64)
+pts, offs = datagen.sphere_clouds(sizes, 5)
+x = torch.from_numpy(pts).to("cuda:0")
+print(json.dumps(pg.batch_autotune(x, offs, 8)))
+"""
+
+
+def test_autotune_cache_file(pg, dev, tmp_path):
+    # PG_TUNE_CACHE keeps the tuner's choice across processes: the first
+    # process times and appends a line; a second one returns the file's
+    # choice (here edited to another valid setting) without timing
+    import json
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    cache = tmp_path / "tune.txt"
+    env = dict(os.environ, PG_TUNE_CACHE=str(cache))
+
+    def child():
+        say("autotune child process")
+        r = subprocess.run([sys.executable, "-c", _TUNE_CHILD, root], env=env, capture_output=True,
+                           text=True, timeout=300)
+        assert r.returncode == 0, r.stderr[-2000:]
+        return json.loads(r.stdout.strip().splitlines()[-1])
+
+    first = child()
+    lines = cache.read_text().splitlines()
+    assert len(lines) == 1
+    f = lines[0].split()
+    assert len(f) == 9 and [int(v) for v in f[5:]] == [first["leaf"], first["blocks_per_cu"],
+                                                        first["lane_queries"], first["klist"]]
+    other = [8 if first["leaf"] != 8 else 32, 2, 4, pg.KLIST_LDS]
+    cache.write_text("not a line\n" + " ".join(f[:5] + [str(v) for v in other]) + "\n")
+    second = child()
+    assert [second["leaf"], second["blocks_per_cu"], second["lane_queries"], second["klist"]] == other
+    assert len(cache.read_text().splitlines()) == 2  # found: nothing appended
