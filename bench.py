@@ -630,6 +630,37 @@ def form_sec63(torch, pg, datagen, dev, n=N):
     return out
 
 
+def form_ksweep(torch, pg, datagen, dev, n=2_000_000):
+    """The appendix's k sweep on incrementally built trees, at a size that
+    fits the default run: the 2-D VisualVar-style set (n = 2M, seed 65)
+    grown into each dynamic tree from 20 batches of 5%, then k-NN of all
+    points for k = 2, 5, 11."""
+    import numpy as np
+    warm_dynamic(torch, pg, datagen, 2, dev)
+    pts = torch.from_numpy(datagen.visual_var(n, 2, seed=65)).to(dev)
+    chunks = list(torch.chunk(pts, 20))
+    out = {"workload": f"2-D VisualVar-style n={n} int32, grown from 20 x 5% batches, all-points k-NN"}
+    ks = (2, 5, 11)
+    for kind in ("bdl", "b1", "b2"):
+        G, ms = grow_tree(torch, pg, kind, 2, chunks, dev)
+        res = {"grow_ms_total": float(np.sum(ms))}
+        for k in ks:
+            G.knn(pts, k)  # first launch of this k's kernels, and the handle's scratch at full size
+            t = timed(torch, lambda: G.knn(pts, k), reps=1)
+            res[f"k{k}_ms"] = t
+            res[f"k{k}_qps"] = n / (t * 1e-3)
+        # a lower bound of the bytes: each query read, its k (id, distance) written
+        res["roofline"] = roof(n * (8 + 11 * 16), res["k11_ms"], "bdl_knn_kernel (k = 11)",
+                               "lower bound: query coordinates read + k int64 ids and int64 distances written "
+                               "(visits unmodelled on this set)")
+        if kind == "b2":
+            res["levels"] = G.stats()[1]
+        out[kind] = res
+        del G
+        torch.cuda.empty_cache()
+    return out
+
+
 def form_table1(torch, pg, datagen, dev, n=N):
     """The kd-tree rows of Table 1 on their own shapes (10M uniform int32
     points): build in 2-D and 5-D, all-points k-NN in 2-D (k = 10; the
@@ -840,8 +871,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms", default="all",
                     help="other forms to measure after the headline step: all, none, or a "
-                         "comma list of static_float,clustered,spatial,bdl,baselines,batch,range,graph,"
-                         "wspd,table1,small_2d "
+                         "comma list of static_float,clustered,spatial,bdl,baselines,ksweep,batch,range,"
+                         "graph,wspd,table1,small_2d "
                          "(sec63, the Section 6.3 protocols on 10M-point sets, runs only when named)")
     ap.add_argument("--bdl-rounds", type=int, default=10)
     ap.add_argument("--sec63-n", type=int, default=N, help="set size of the sec63 form")
@@ -958,7 +989,7 @@ def main():
     }
     del idx, dist, x
     torch.cuda.empty_cache()
-    forms = ["static_float", "clustered", "spatial", "bdl", "baselines", "batch", "range", "graph",
+    forms = ["static_float", "clustered", "spatial", "bdl", "baselines", "ksweep", "batch", "range", "graph",
              "wspd", "table1", "small_2d"] \
         if args.forms == "all" else \
         [f for f in args.forms.split(",") if f and f != "none"]
@@ -989,6 +1020,8 @@ def main():
             out[f] = form_range(torch, pg, datagen, dev, not args.no_cpu_baseline)
         elif f == "wspd":
             out[f] = form_wspd(torch, pg, datagen, dev)
+        elif f == "ksweep":
+            out[f] = form_ksweep(torch, pg, datagen, dev)
         else:
             raise SystemExit(f"unknown form {f}")
         torch.cuda.empty_cache()
