@@ -126,4 +126,9 @@ pg_status exclusive_scan_u64(const uint64_t* in, uint64_t* out, int64_t n, uint6
     return exclusive_scan<uint64_t, uint64_t>(in, out, n, total, s);
 }
 
+pg_status exclusive_scan_u64_ws(const uint64_t* in, uint64_t* out, int64_t n, uint64_t* total,
+                                uint64_t* sums, hipStream_t s) {
+    return exclusive_scan_ws<uint64_t, uint64_t>(in, out, n, total, sums, s);
+}
+
 }  // namespace pg

@@ -21,5 +21,8 @@ pg_status fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);
 // The same over uint64 (in and out may alias).
 pg_status exclusive_scan_u64(const uint64_t* in, uint64_t* out, int64_t n, uint64_t* total,
                              hipStream_t s);
+// exclusive_scan_u64 with caller-provided workspace sums[scan_partials(n)].
+pg_status exclusive_scan_u64_ws(const uint64_t* in, uint64_t* out, int64_t n, uint64_t* total,
+                                uint64_t* sums, hipStream_t s);
 
 }  // namespace pg
