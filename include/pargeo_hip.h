@@ -51,8 +51,16 @@ typedef struct pg_tree pg_tree;
 typedef struct pg_bdl pg_bdl;
 
 /* Device memory.  By default the library allocates stream-ordered from the
- * device's pool (hipMallocAsync / hipFreeAsync).  pg_set_allocator installs
- * the caller's allocator instead (a framework's caching allocator, say):
+ * device's pool (hipMallocAsync / hipFreeAsync) and keeps the blocks of
+ * 1 MiB or more that it frees, per stream and size class (sizes rounded up
+ * by at most a quarter), for its next allocation of that class on that
+ * stream; up to PG_CACHE_LIMIT_MIB (environment, default 8192) MiB stay
+ * cached.  pg_release_cached returns them to the device (after a device
+ * synchronisation), as an allocation failure does first; call it before
+ * destroying a stream the library has run on, so that no block stays
+ * filed under a stream handle the runtime may hand out again.
+ * pg_set_allocator installs the caller's allocator instead (a framework's
+ * caching allocator, say):
  * alloc(bytes, stream, ctx) returns device memory usable in stream order on
  * `stream` (NULL on failure: the call returns PG_ERR_NOMEM), release(p,
  * stream, ctx) takes back a block after the work queued on `stream` so far.
@@ -66,6 +74,9 @@ typedef struct {
     void* ctx;
 } pg_allocator;
 pg_status pg_set_allocator(const pg_allocator* a);
+/* Returns the default path's cached blocks to the device (synchronises the
+ * device).  Not thread-safe against concurrent library calls. */
+pg_status pg_release_cached(void);
 
 /* Text of the last non-OK status on this thread (never NULL). */
 const char* pg_last_error(void);

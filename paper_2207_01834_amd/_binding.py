@@ -46,6 +46,7 @@ class Allocator(ctypes.Structure):
 
 SIGNATURES = {
     "pg_set_allocator": (i32, [ctypes.POINTER(Allocator)]),
+    "pg_release_cached": (i32, []),
     "pg_last_error": (ctypes.c_char_p, []),
     "pg_version": (ctypes.c_char_p, []),
     "pg_kdtree_build": (i32, [vp, i64, i32, i32, i32, vp, ctypes.POINTER(vp)]),
@@ -731,6 +732,12 @@ class B1Tree:
 
 
 _torch_allocator = None
+
+
+def release_cached():
+    """Returns the device blocks the library's default allocator keeps for
+    reuse to the device (pg_release_cached; synchronises the device)."""
+    check(lib().pg_release_cached())
 
 
 def use_torch_allocator(enable: bool = True):

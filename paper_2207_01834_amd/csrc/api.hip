@@ -1,9 +1,13 @@
 // C ABI of libpargeo_hip.so: argument validation, handles, memory, errors.
 #include <atomic>
+#include <cstdlib>
+#include <map>
 #include <mutex>
 #include <new>
-#include <vector>
 #include <string>
+#include <unordered_map>
+#include <utility>
+#include <vector>
 
 #include "build.hpp"
 #include "knn.hpp"
@@ -42,6 +46,56 @@ pg_allocator g_alloc = {nullptr, nullptr, nullptr};
 std::atomic<int64_t> g_outstanding{0};
 }  // namespace
 
+namespace {
+// Blocks of at least kCacheMin bytes that the library frees are kept, per
+// stream and size class, for the next allocation of that class on that
+// stream: stream order makes such a reuse safe without an event, and
+// hipMallocAsync / hipFreeAsync of large blocks were measured holding the
+// host for 0.05-3 ms each (a B1 rebuild makes a dozen of each).  Classes
+// round a size up to a quarter of its power of two (at most 25% slack).
+// Cached bytes above the limit (PG_CACHE_LIMIT_MIB, default 8 GiB), or all
+// of them on an allocation failure, pg_release_cached or a change of
+// allocator, go back to the device after a device synchronisation.
+constexpr size_t kCacheMin = (size_t)1 << 20;
+std::mutex g_cache_mu;
+std::unordered_map<void*, size_t> g_block_class;  // every large block of the default path
+std::map<std::pair<hipStream_t, size_t>, std::vector<void*>> g_cache;
+size_t g_cached_bytes = 0;
+
+size_t cache_limit() {
+    static const size_t lim = [] {
+        const char* e = std::getenv("PG_CACHE_LIMIT_MIB");
+        return e ? (size_t)std::strtoull(e, nullptr, 10) << 20 : (size_t)8 << 30;
+    }();
+    return lim;
+}
+
+size_t size_class(size_t b) {
+    if (b < kCacheMin) return b;
+    const int e = 63 - __builtin_clzll((unsigned long long)b);
+    const size_t step = (size_t)1 << (e - 2);
+    return (b + step - 1) / step * step;
+}
+
+// Returns cached blocks to the device until at most `keep` bytes stay
+// cached.  Caller holds g_cache_mu.
+void trim_locked(size_t keep) {
+    if (g_cached_bytes <= keep) return;
+    (void)hipDeviceSynchronize();  // the blocks' last uses, on any stream, are done
+    for (auto it = g_cache.begin(); it != g_cache.end() && g_cached_bytes > keep;) {
+        auto& v = it->second;
+        while (!v.empty() && g_cached_bytes > keep) {
+            void* q = v.back();
+            v.pop_back();
+            g_cached_bytes -= it->first.second;
+            g_block_class.erase(q);
+            (void)hipFreeAsync(q, nullptr);
+        }
+        it = v.empty() ? g_cache.erase(it) : std::next(it);
+    }
+}
+}  // namespace
+
 pg_status dmalloc(void** p, size_t bytes, hipStream_t s) {
     if (g_alloc.alloc) {
         *p = g_alloc.alloc(bytes ? bytes : 4, (void*)s, g_alloc.ctx);
@@ -52,12 +106,34 @@ pg_status dmalloc(void** p, size_t bytes, hipStream_t s) {
         return PG_OK;
     }
     std::call_once(g_pool_once, configure_pool);
-    hipError_t e = hipMallocAsync(p, bytes ? bytes : 4, s);
+    const size_t want = size_class(bytes ? bytes : 4);
+    if (want >= kCacheMin) {
+        std::lock_guard<std::mutex> lock(g_cache_mu);
+        auto it = g_cache.find({s, want});
+        if (it != g_cache.end() && !it->second.empty()) {
+            *p = it->second.back();
+            it->second.pop_back();
+            g_cached_bytes -= want;
+            g_outstanding++;
+            return PG_OK;
+        }
+    }
+    hipError_t e = hipMallocAsync(p, want, s);
+    if (e == hipErrorOutOfMemory && want >= kCacheMin) {
+        std::lock_guard<std::mutex> lock(g_cache_mu);
+        trim_locked(0);
+        (void)hipGetLastError();
+        e = hipMallocAsync(p, want, s);
+    }
     if (e != hipSuccess) {
         *p = nullptr;
         return fail(e == hipErrorOutOfMemory ? PG_ERR_NOMEM : PG_ERR_DEVICE,
                     std::string("hipMallocAsync(") + std::to_string(bytes) + "): " +
                         hipGetErrorString(e));
+    }
+    if (want >= kCacheMin) {
+        std::lock_guard<std::mutex> lock(g_cache_mu);
+        g_block_class[*p] = want;
     }
     g_outstanding++;
     return PG_OK;
@@ -70,7 +146,22 @@ void dfree(void* p, hipStream_t s) {
         g_alloc.release(p, (void*)s, g_alloc.ctx);
         return;
     }
+    {
+        std::lock_guard<std::mutex> lock(g_cache_mu);
+        auto it = g_block_class.find(p);
+        if (it != g_block_class.end()) {
+            g_cache[{s, it->second}].push_back(p);
+            g_cached_bytes += it->second;
+            if (g_cached_bytes > cache_limit()) trim_locked(cache_limit() / 2);
+            return;
+        }
+    }
     (void)hipFreeAsync(p, s);
+}
+
+void release_cached() {
+    std::lock_guard<std::mutex> lock(g_cache_mu);
+    trim_locked(0);
 }
 
 static void tree_release(pg_tree* t) {
@@ -104,7 +195,13 @@ pg_status pg_set_allocator(const pg_allocator* a) {
     if (g_outstanding.load() != 0)
         return fail(PG_ERR_INVALID, "pg_set_allocator: " + std::to_string(g_outstanding.load()) +
                                         " device blocks are still held (free every handle first)");
+    release_cached();
     g_alloc = a ? *a : pg_allocator{nullptr, nullptr, nullptr};
+    return PG_OK;
+}
+
+pg_status pg_release_cached(void) {
+    release_cached();
     return PG_OK;
 }
 

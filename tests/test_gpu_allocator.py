@@ -1,7 +1,10 @@
 """pg_set_allocator through the C ABI: torch's caching allocator serves every
 device block of a build and a search (the device memory torch reports grows
 while the tree lives), the results equal those made with the library's own
-pool, and the allocator can be switched back once the tree is freed."""
+pool, and the allocator can be switched back once the tree is freed.  The
+default allocator's block cache: results do not depend on its limit (a child
+process with a 4 MiB limit trims at nearly every free) or on
+pg_release_cached between calls."""
 import gc
 
 import numpy as np
@@ -89,3 +92,55 @@ def test_torch_allocator_bdl_sequence(dev):
             assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
         else:
             assert a == b
+
+
+_CACHE_CHILD = r"""
+import sys
+sys.path.insert(0, sys.argv[1])
+import numpy as np, torch
+from paper_2207_01834_amd import _binding as pg, datagen
+init, rounds = datagen.bdl_rounds(60_000, 3, 30_000, 5_000, 3, seed=23)
+B = pg.BDLTree(3, torch.int32, leaf=8, X=512, device="cuda:0")
+B.insert(torch.from_numpy(init).to("cuda:0"))
+pool, h = init, []
+for j, rd in enumerate(rounds):
+    B.insert(torch.from_numpy(rd["insert"]).to("cuda:0"))
+    pool = np.concatenate([pool, rd["insert"]])
+    E = datagen.choose_erase(pool, 20_000, rd["erase_seed"])
+    h.append(B.erase(torch.from_numpy(E).to("cuda:0")))
+    if j == 1 and sys.argv[2] == "release":
+        pg.release_cached()
+    i, d = B.knn(torch.from_numpy(rd["queries"]).to("cuda:0"), 7)
+    torch.cuda.synchronize()
+    h.append(int(np.bitwise_xor.reduce(i.cpu().numpy().ravel() * 1000003 + d.cpu().numpy().ravel())))
+h.append(B.size())
+del B
+pg.release_cached()
+print(" ".join(str(v) for v in h))
+"""
+
+
+def test_block_cache_limits(dev):
+    # the same BDL sequence with the default cache, with a 4 MiB limit (a
+    # trim, with its device synchronisation, at nearly every large free) and
+    # with an explicit release mid-sequence gives the same erase counts,
+    # k-NN results and sizes
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+    def child(limit, mode):
+        env = dict(os.environ)
+        env.pop("PG_CACHE_LIMIT_MIB", None)
+        if limit is not None:
+            env["PG_CACHE_LIMIT_MIB"] = str(limit)
+        say(f"block-cache child: limit {limit} MiB, {mode}")
+        r = subprocess.run([sys.executable, "-c", _CACHE_CHILD, root, mode], env=env,
+                           capture_output=True, text=True, timeout=300)
+        assert r.returncode == 0, r.stderr[-2000:]
+        return r.stdout.strip().splitlines()[-1]
+
+    a = child(None, "keep")
+    assert child(4, "keep") == a
+    assert child(None, "release") == a
