@@ -53,7 +53,9 @@ bdl_knn_kernel(Forest f, const uint32_t* __restrict__ queries, const int32_t* __
         for (int t = 0; t < f.count; t++)
             tree_search<T, MD, decltype(kl), BdlIds, TK>(
                 f.s[t].tv, BdlIds{f.s[t].ids, f.s[t].alive, f.s[t].idrec}, q, d, kl, k,
-                search_start<TK>(f.s[t].tv, false, 0), t == 0 ? search_from<TK>(f.s[0].tv, qk, qi) : root_from<TK>());
+                search_start<TK>(f.s[t].tv, false, 0),
+                descend_from<T, MD, TK>(f.s[t].tv, q, d,
+                                        t == 0 ? search_from<TK>(f.s[0].tv, qk, qi) : root_from<TK>()));
         if (kl.needs_redo()) {
             redo[atomicAdd(nredo, 1u)] = (int32_t)qi;
             return;
@@ -71,7 +73,9 @@ bdl_knn_kernel(Forest f, const uint32_t* __restrict__ queries, const int32_t* __
         for (int t = 0; t < f.count; t++)
             tree_search<T, MD, decltype(kl), BdlIds, TK>(
                 f.s[t].tv, BdlIds{f.s[t].ids, f.s[t].alive, 0}, q, d, kl, k,
-                search_start<TK>(f.s[t].tv, false, 0), t == 0 ? search_from<TK>(f.s[0].tv, qk, qi) : root_from<TK>());
+                search_start<TK>(f.s[t].tv, false, 0),
+                descend_from<T, MD, TK>(f.s[t].tv, q, d,
+                                        t == 0 ? search_from<TK>(f.s[0].tv, qk, qi) : root_from<TK>()));
 #pragma unroll
         for (int s = 0; s < KT; s++) {
             if (EX || s < k) {

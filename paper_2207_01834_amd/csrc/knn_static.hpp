@@ -53,7 +53,8 @@ knn_static_kernel(TreeView tv, const uint32_t* __restrict__ queries,
     const uint32_t start = search_start<TK>(tv, all != 0, i);
     if constexpr (NS) tree_search<T, MD, KL, OtherIds, TK>(tv, OtherIds{i}, q, d, kl, k, start);
     else tree_search<T, MD, KL, PlainIds, TK>(tv, PlainIds{}, q, d, kl, k, start,
-                                              all ? root_from<TK>() : search_from<TK>(tv, qk, i));
+                                              all ? root_from<TK>()
+                                                  : descend_from<T, MD, TK>(tv, q, d, search_from<TK>(tv, qk, i)));
     if (kl.needs_redo()) {
         redo[atomicAdd(nredo, 1u)] = (int32_t)i;
         return;

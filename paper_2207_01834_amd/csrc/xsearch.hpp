@@ -199,6 +199,44 @@ __device__ inline uint32_t search_from(const TreeView& tv, const QueryKeys& qk, 
 template <int TK>
 __device__ inline uint32_t root_from() { return TK == kTreeX ? 0u : 1u; }
 
+// Continues separate query q's descent from node `from` (the root, or where
+// an earlier descent stopped) down to its walk leaf (heap trees: the level
+// two above the leaves) or its leaf node (explicit trees), taking the
+// query's side of every split as the walk does.  The walk may then begin
+// there: its state is the one a walk from `from` would reach on the way
+// down, and the descent, a plain loop of (for heap trees) uniform length,
+// costs far fewer instructions than the same levels taken as walk steps.
+template <typename T, int MD, int TK>
+__device__ inline uint32_t descend_from(const TreeView& tv, const T (&q)[MD], int d, uint32_t from) {
+    using M = Metric<T>;
+    if (tv.n == 0) return from;
+    if constexpr (TK == kTreeX) {
+        uint32_t cur = from;
+        uint4 r = tv.xn[cur];
+        while (!(r.w & kXLeaf)) {
+            cur = r.y + (pick<MD>(q, (int)(r.w & 15u)) >= M::load(r.x) ? 1u : 0u);
+            r = tv.xn[cur];
+        }
+        return cur;
+    } else {
+        const int L = tv.L;
+        const int W = L - (L < 2 ? L : 2);
+        const int D = MD < 8 ? MD : d;
+        int lv = 31 - __clz(from);
+        uint32_t h = from;
+        int dim = lv % D;
+        for (; lv < W; lv++) {
+            int dm = dim;
+            if constexpr (TK == kTreeLoff) {
+                if (tv.sdim != nullptr) dm = tv.sdim[h];
+            }
+            h = 2u * h + (pick<MD>(q, dm) >= M::load(tv.split[h]) ? 1u : 0u);
+            dim = dim + 1 == D ? 0 : dim + 1;
+        }
+        return h;
+    }
+}
+
 // The k-NN walk for tree kind TK (start from search_start; from, for a
 // separate query, from search_from or root_from).
 template <typename T, int MD, typename List, typename Ids, int TK>
