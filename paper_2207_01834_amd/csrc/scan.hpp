@@ -25,4 +25,15 @@ pg_status exclusive_scan_u64(const uint64_t* in, uint64_t* out, int64_t n, uint6
 pg_status exclusive_scan_u64_ws(const uint64_t* in, uint64_t* out, int64_t n, uint64_t* total,
                                 uint64_t* sums, hipStream_t s);
 
+// Scans whose count is read on the device when they run: n = mul * *cnt +
+// add <= n_max (grids and the workspace sums[scan_partials(n_max)] are
+// sized for n_max).  The total goes to *total (may be NULL) and, with
+// at_end, to out[n].  in and out may alias.
+pg_status exclusive_scan_u32_dev(const uint32_t* in, uint32_t* out, const uint32_t* cnt, uint32_t mul,
+                                 uint32_t add, int64_t n_max, uint32_t* total, bool at_end,
+                                 uint32_t* sums, hipStream_t s);
+pg_status exclusive_scan_u64_dev(const uint64_t* in, uint64_t* out, const uint32_t* cnt, uint32_t mul,
+                                 uint32_t add, int64_t n_max, uint64_t* total, bool at_end,
+                                 uint64_t* sums, hipStream_t s);
+
 }  // namespace pg

@@ -34,7 +34,9 @@
 // arrays by the next level's pass.  Points of finished nodes are never
 // touched again.  Afterwards, level by level, subtree leaf counts (bottom-up)
 // give every leaf its index in leaf order (top-down).
+#include <algorithm>
 #include <utility>
+#include <vector>
 
 #include "build.hpp"
 #include "scan.hpp"
@@ -108,6 +110,13 @@ struct Entries {
     uint32_t* cut;    // key of the cut
     uint32_t* dim;    // cut dimension | kCopy
     double* cell;     // [A][2d] cell (cell form): lo[d], hi[d]
+};
+
+// The counts of one level, kept in device memory so that levels are queued
+// without the host reading them: splitting entries, copy entries, chunks,
+// and the id of the level's first child node.
+struct Level {
+    uint32_t As, Ac, C, nbase;
 };
 
 struct Nodes {
@@ -197,6 +206,30 @@ __global__ void root_kernel(Nodes N, Entries E, int64_t n, int d, int leaf, int 
     tot[1] = 0;
 }
 
+// The first level's counts from the root's set-up.
+__global__ void level_init_kernel(Level* __restrict__ L, const uint32_t* __restrict__ tot,
+                                  const uint32_t* __restrict__ cstart) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) L[0] = Level{tot[0], tot[1], cstart[1], 1u};
+}
+
+// The next level's counts: the split and copy entries the scan of the
+// children's flags counted, their chunks, and the node id after this
+// level's children.  A level without splitting entries ends the build.
+__global__ void level_advance_kernel(Level* __restrict__ L, const uint64_t* __restrict__ ftot,
+                                     const uint32_t* __restrict__ cst_next) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const Level c = L[0];
+    Level x{0u, 0u, 0u, c.nbase};
+    if (c.As > 0) {
+        const uint64_t f = *ftot;
+        x.As = (uint32_t)f;
+        x.Ac = (uint32_t)(f >> 32);
+        x.C = cst_next[2u * c.As];
+        x.nbase = c.nbase + 2u * c.As;
+    }
+    L[1] = x;
+}
+
 // Entry of chunk c (the same in every lane): the last a with cstart[a] <= c
 // (every entry has a chunk).  A 64-way search: each step the lanes test 64
 // evenly spaced candidates, so a level of 10^6 entries takes four loads.
@@ -221,18 +254,12 @@ constexpr uint32_t kRepChunks = 16;
 constexpr int kReplicas = 64;
 constexpr uint32_t kNoRep = 0xffffffffu;
 
-// Per chunk (one wave): its entry, and the number of its points going left.
-// The first chunk of a splitting entry with kRepChunks or more chunks takes
-// a replica block (rbase[a]; block b serves entry rentry[b]) and resets it.
-__global__ void __launch_bounds__(kNT)
-chunk_count_kernel(Entries E, const uint32_t* __restrict__ cstart, uint32_t A, uint32_t C,
-                   const uint32_t* __restrict__ keys, int64_t n, uint32_t* __restrict__ c2e,
-                   uint32_t* __restrict__ lcnt, int d, uint32_t* __restrict__ rbase,
-                   uint32_t* __restrict__ rentry, uint32_t* __restrict__ rcount,
-                   uint32_t* __restrict__ rep) {
-    const uint32_t c = blockIdx.x * (kNT / kWave) + threadIdx.x / kWave;
-    if (c == 0 && threadIdx.x == 0) lcnt[C] = 0;
-    if (c >= C) return;
+// One chunk of chunk_count_kernel.
+__device__ inline void chunk_count_one(const Entries& E, const uint32_t* __restrict__ cstart, uint32_t A,
+                                       uint32_t c, const uint32_t* __restrict__ keys, int64_t n,
+                                       uint32_t* __restrict__ c2e, uint32_t* __restrict__ lcnt, int d,
+                                       uint32_t* __restrict__ rbase, uint32_t* __restrict__ rentry,
+                                       uint32_t* __restrict__ rcount, uint32_t* __restrict__ rep) {
     const uint32_t a = chunk_entry(cstart, A, c);
     const uint32_t dm = E.dim[a];
     if (c == cstart[a]) {
@@ -271,6 +298,22 @@ chunk_count_kernel(Entries E, const uint32_t* __restrict__ cstart, uint32_t A, u
     }
 }
 
+// Per chunk (one wave, grid-stride): its entry, and the number of its
+// points going left.  The first chunk of a splitting entry with kRepChunks
+// or more chunks takes a replica block (rbase[a]; block b serves entry
+// rentry[b]) and resets it.
+__global__ void __launch_bounds__(kNT)
+chunk_count_kernel(Entries E, const uint32_t* __restrict__ cstart, const Level* __restrict__ L,
+                   const uint32_t* __restrict__ keys, int64_t n, uint32_t* __restrict__ c2e,
+                   uint32_t* __restrict__ lcnt, int d, uint32_t* __restrict__ rbase,
+                   uint32_t* __restrict__ rentry, uint32_t* __restrict__ rcount,
+                   uint32_t* __restrict__ rep) {
+    const uint32_t A = L->As + L->Ac, C = L->C;
+    if (blockIdx.x == 0 && threadIdx.x == 0) lcnt[C] = 0;
+    for (uint32_t c = blockIdx.x * (kNT / kWave) + threadIdx.x / kWave; c < C;
+         c += gridDim.x * (kNT / kWave))
+        chunk_count_one(E, cstart, A, c, keys, n, c2e, lcnt, d, rbase, rentry, rcount, rep);
+}
 // Writes point (keys kv, row r) to leaf-order position p of the tree.
 template <int MD>
 __device__ inline void put_final(const uint32_t (&kv)[MD], int32_t r, int64_t p, int d, int rw, bool fl,
@@ -302,17 +345,14 @@ __device__ inline void put_final(const uint32_t (&kv)[MD], int32_t r, int64_t p,
 // that is a leaf by its count, the tree's arrays; reduces each child's box.
 // Copy entries write their points to the tree's arrays in place.
 template <int MD>
-__global__ void __launch_bounds__(kNT)
-chunk_scatter_kernel(Entries E, Nodes N, const uint32_t* __restrict__ cstart,
-                     const uint32_t* __restrict__ lpre, const uint32_t* __restrict__ c2e, uint32_t C,
-                     uint32_t nbase, const uint32_t* __restrict__ rbase, uint32_t* __restrict__ rep,
-                     int leaf, int d, int rw, int fl,
-                     const uint32_t* __restrict__ keys, const int32_t* __restrict__ idx,
-                     uint32_t* __restrict__ okeys, int32_t* __restrict__ oidx, int64_t n,
-                     uint32_t* __restrict__ pts, uint32_t* __restrict__ rec,
-                     int32_t* __restrict__ pidx) {
-    const uint32_t c = blockIdx.x * (kNT / kWave) + threadIdx.x / kWave;
-    if (c >= C) return;
+__device__ inline void chunk_scatter_one(const Entries& E, const Nodes& N, const uint32_t* __restrict__ cstart,
+                                         const uint32_t* __restrict__ lpre, const uint32_t* __restrict__ c2e,
+                                         uint32_t c, uint32_t nbase, const uint32_t* __restrict__ rbase,
+                                         uint32_t* __restrict__ rep, int leaf, int d, int rw, int fl,
+                                         const uint32_t* __restrict__ keys, const int32_t* __restrict__ idx,
+                                         uint32_t* __restrict__ okeys, int32_t* __restrict__ oidx, int64_t n,
+                                         uint32_t* __restrict__ pts, uint32_t* __restrict__ rec,
+                                         int32_t* __restrict__ pidx) {
     const uint32_t a = c2e[c];
     const uint32_t dm = E.dim[a];
     const uint32_t lo = E.lo[a], cnt = E.cnt[a], end = lo + cnt;
@@ -412,38 +452,52 @@ chunk_scatter_kernel(Entries E, Nodes N, const uint32_t* __restrict__ cstart,
     }
 }
 
+template <int MD>
+__global__ void __launch_bounds__(kNT)
+chunk_scatter_kernel(Entries E, Nodes N, const uint32_t* __restrict__ cstart,
+                     const uint32_t* __restrict__ lpre, const uint32_t* __restrict__ c2e,
+                     const Level* __restrict__ L, const uint32_t* __restrict__ rbase,
+                     uint32_t* __restrict__ rep, int leaf, int d, int rw, int fl,
+                     const uint32_t* __restrict__ keys, const int32_t* __restrict__ idx,
+                     uint32_t* __restrict__ okeys, int32_t* __restrict__ oidx, int64_t n,
+                     uint32_t* __restrict__ pts, uint32_t* __restrict__ rec,
+                     int32_t* __restrict__ pidx) {
+    const uint32_t C = L->C, nbase = L->nbase;
+    for (uint32_t c = blockIdx.x * (kNT / kWave) + threadIdx.x / kWave; c < C;
+         c += gridDim.x * (kNT / kWave))
+        chunk_scatter_one<MD>(E, N, cstart, lpre, c2e, c, nbase, rbase, rep, leaf, d, rw, fl, keys, idx,
+                              okeys, oidx, n, pts, rec, pidx);
+}
+
 // Boxes of the children of the entries with a replica block: one wave per
-// (block, child), one replica per lane.
+// (block, child), one replica per lane (grid-stride).
 __global__ void __launch_bounds__(kNT)
 merge_replicas_kernel(const uint32_t* __restrict__ rep, const uint32_t* __restrict__ rentry,
-                      const uint32_t* __restrict__ rcount, uint32_t nbase, int d,
+                      const uint32_t* __restrict__ rcount, const Level* __restrict__ L, int d,
                       uint32_t* __restrict__ key) {
-    const uint32_t t = blockIdx.x * (kNT / kWave) + threadIdx.x / kWave;  // 2 block + child
-    if (t >= 2u * *rcount) return;
+    const uint32_t nbase = L->nbase, slots = 2u * *rcount;
     const int lane = lane_id();
-    const uint32_t a = rentry[t >> 1];
-    const uint32_t* r = rep + ((size_t)t * kReplicas + lane) * 2 * d;
-    uint32_t* k = key + (size_t)(nbase + 2u * a + (t & 1u)) * 2 * d;
-    for (int c = 0; c < d; c++) {
-        const uint32_t mn = wave_min_u32(r[c]);
-        const uint32_t mx = wave_max_u32(r[d + c]);
-        if (lane == 0) {
-            k[c] = mn;
-            k[d + c] = mx;
+    for (uint32_t t = blockIdx.x * (kNT / kWave) + threadIdx.x / kWave; t < slots;
+         t += gridDim.x * (kNT / kWave)) {  // 2 block + child
+        const uint32_t a = rentry[t >> 1];
+        const uint32_t* r = rep + ((size_t)t * kReplicas + lane) * 2 * d;
+        uint32_t* k = key + (size_t)(nbase + 2u * a + (t & 1u)) * 2 * d;
+        for (int c = 0; c < d; c++) {
+            const uint32_t mn = wave_min_u32(r[c]);
+            const uint32_t mx = wave_max_u32(r[d + c]);
+            if (lane == 0) {
+                k[c] = mn;
+                k[d + c] = mx;
+            }
         }
     }
 }
 
-// Per splitting entry: the node's record, its children's records, counts and
-// segments, and the children's flags for the next level (split / copy / leaf).
-__global__ void __launch_bounds__(kNT)
-split_nodes_kernel(Entries E, Nodes N, const uint32_t* __restrict__ cstart,
-                   const uint32_t* __restrict__ lpre, uint32_t As, uint32_t nbase, int leaf, int d,
-                   int fl, uint64_t* __restrict__ flags, uint32_t* __restrict__ nch_next,
-                   uint32_t* __restrict__ rcount) {
-    const uint32_t a = blockIdx.x * kNT + threadIdx.x;
-    if (a == 0) *rcount = 0;  // the replica blocks were merged: free for the next level
-    if (a >= As) return;
+// One entry of split_nodes_kernel.
+__device__ inline void split_node_one(const Entries& E, const Nodes& N, const uint32_t* __restrict__ cstart,
+                                      const uint32_t* __restrict__ lpre, uint32_t a, uint32_t nbase,
+                                      int leaf, int d, int fl, uint64_t* __restrict__ flags,
+                                      uint32_t* __restrict__ nch_next) {
     const uint32_t u = E.node[a];
     const uint32_t lo = E.lo[a], cnt = E.cnt[a];
     const uint32_t nl = lpre[cstart[a + 1]] - lpre[cstart[a]];
@@ -466,16 +520,28 @@ split_nodes_kernel(Entries E, Nodes N, const uint32_t* __restrict__ cstart,
     N.xn[u] = make_uint4(key_to_coord(E.cut[a], fl != 0), c0, E.par[a], meta);
 }
 
+// Per splitting entry (grid-stride): the node's record, its children's
+// records, counts and segments, and the children's flags for the next level
+// (split / copy / leaf).
+__global__ void __launch_bounds__(kNT)
+split_nodes_kernel(Entries E, Nodes N, const uint32_t* __restrict__ cstart,
+                   const uint32_t* __restrict__ lpre, const Level* __restrict__ L, int leaf, int d,
+                   int fl, uint64_t* __restrict__ flags, uint32_t* __restrict__ nch_next,
+                   uint32_t* __restrict__ rcount) {
+    const uint32_t As = L->As, nbase = L->nbase;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *rcount = 0;  // the replica blocks were merged
+    for (uint32_t a = blockIdx.x * kNT + threadIdx.x; a < As; a += gridDim.x * kNT)
+        split_node_one(E, N, cstart, lpre, a, nbase, leaf, d, fl, flags, nch_next);
+}
+
 // Per child slot t = 2a + s of the level's splitting entries: the next
 // level's entry of a child that splits (its space, cut dimension and cut;
 // the boxes of its future children reset) or is copied.
-__global__ void __launch_bounds__(kNT)
-emit_kernel(Entries E, Entries X, Nodes N, const uint64_t* __restrict__ flags,
-            const uint64_t* __restrict__ fpre, const uint64_t* __restrict__ ftot, uint32_t As,
-            uint32_t nbase, uint32_t nbase_next, int depth, int d, int fl, int rule,
-            uint32_t* __restrict__ nch_next) {
-    const uint32_t t = blockIdx.x * kNT + threadIdx.x;
-    if (t >= 2 * As) return;
+__device__ inline void emit_one(const Entries& E, const Entries& X, const Nodes& N,
+                                const uint64_t* __restrict__ flags, const uint64_t* __restrict__ fpre,
+                                const uint64_t* __restrict__ ftot, uint32_t t, uint32_t nbase,
+                                uint32_t nbase_next, int depth, int d, int fl, int rule,
+                                uint32_t* __restrict__ nch_next) {
     const uint64_t f = flags[t];
     if (f == 0) return;
     const uint32_t a = t >> 1, s = t & 1u;
@@ -533,6 +599,18 @@ emit_kernel(Entries E, Entries X, Nodes N, const uint64_t* __restrict__ flags,
         bk[w] = (w % (2 * d)) < d ? 0xffffffffu : 0u;
         bk[2 * d + w] = (w % (2 * d)) < d ? 0xffffffffu : 0u;
     }
+}
+
+// emit_one over the level's child slots (grid-stride).
+__global__ void __launch_bounds__(kNT)
+emit_kernel(Entries E, Entries X, Nodes N, const uint64_t* __restrict__ flags,
+            const uint64_t* __restrict__ fpre, const uint64_t* __restrict__ ftot,
+            const Level* __restrict__ L, int depth, int d, int fl, int rule,
+            uint32_t* __restrict__ nch_next) {
+    const uint32_t As = L->As, nbase = L->nbase;
+    const uint32_t nbase_next = nbase + 2u * As;
+    for (uint32_t t = blockIdx.x * kNT + threadIdx.x; t < 2u * As; t += gridDim.x * kNT)
+        emit_one(E, X, N, flags, fpre, ftot, t, nbase, nbase_next, depth, d, fl, rule, nch_next);
 }
 
 // Leaves below each node of one level (bottom-up, deepest level first).
@@ -608,13 +686,13 @@ struct Grow {
 
 template <int MD>
 void launch_scatter(unsigned grid, hipStream_t s, const Entries& E, const Nodes& N,
-                    const uint32_t* cstart, const uint32_t* lpre, const uint32_t* c2e, uint32_t C,
-                    uint32_t nbase, const uint32_t* rbase, uint32_t* rep, int leaf, int d, int rw,
-                    int fl, const uint32_t* keys, const int32_t* idx, uint32_t* okeys, int32_t* oidx,
-                    int64_t n, pg_tree* T) {
+                    const uint32_t* cstart, const uint32_t* lpre, const uint32_t* c2e, const Level* L,
+                    const uint32_t* rbase, uint32_t* rep, int leaf, int d, int rw, int fl,
+                    const uint32_t* keys, const int32_t* idx, uint32_t* okeys, int32_t* oidx, int64_t n,
+                    pg_tree* T) {
     hipLaunchKernelGGL((chunk_scatter_kernel<MD>), dim3(grid), dim3(kNT), 0, s, E, N, cstart, lpre,
-                       c2e, C, nbase, rbase, rep, leaf, d, rw, fl, keys, idx, okeys, oidx, n, T->pts,
-                       T->rec, T->pidx);
+                       c2e, L, rbase, rep, leaf, d, rw, fl, keys, idx, okeys, oidx, n, T->pts, T->rec,
+                       T->pidx);
 }
 
 // Leaf boxes (keys) of an explicit-node tree from its points: one lane per
@@ -817,80 +895,136 @@ pg_status build_tree_spatial(const void* points, int64_t n, int d, int leaf, int
                            (int64_t)4 * d, 0xffffffffu, 0u, d);
         PG_LAUNCH_CHECK();
     }
-    uint32_t h[3] = {0, 0, 0};
-    PG_HIP(hipMemcpyAsync(h, tot32, sizeof(uint32_t) * 2, hipMemcpyDeviceToHost, s));
-    PG_HIP(hipMemcpyAsync(h + 2, cst[0] + 1, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-    PG_HIP(hipStreamSynchronize(s));
-    uint32_t As = h[0], Ac = h[1], C = h[2];
+    // Levels are queued in batches without the host reading their counts:
+    // each level's kernels read them from L[j] and the last one writes
+    // L[j + 1]; grids are sized for bounds on them (a level has at most
+    // twice the splitting entries of the one above), and the node arrays
+    // are reserved for the batch's worst case.  The host reads the counts
+    // back once per batch.
+    constexpr int kBatch = 16;
+    DevBuf lbuf(s), sbuf(s);
+    PG_TRY(lbuf.alloc(sizeof(Level) * (kBatch + 1)));
+    Level* Ld = lbuf.as<Level>();
+    const int64_t smax = std::max<int64_t>((int64_t)cmax + 1, 2 * (int64_t)amax);
+    PG_TRY(sbuf.alloc(sizeof(uint64_t) * (size_t)scan_partials(smax)));
+    uint32_t* sums32 = sbuf.as<uint32_t>();
+    uint64_t* sums64 = sbuf.as<uint64_t>();
+    hipLaunchKernelGGL(level_init_kernel, dim3(1), dim3(64), 0, s, Ld, tot32, cst[0]);
+    PG_LAUNCH_CHECK();
+    auto grid_cap = [](uint64_t blocks, uint64_t cap) {
+        return (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(blocks, cap));
+    };
+    const unsigned mgrid = grid_cap(cdiv((int64_t)(2 * rmax), kNT / kWave), 512);
 
     uint32_t* kcur = ka.as<uint32_t>();
     int32_t* icur = ia.as<int32_t>();
     uint32_t* knext = kb.as<uint32_t>();
     int32_t* inext = ib.as<int32_t>();
-    int64_t nodes = 1, leaves = As == 0 ? 1 : 0;
+    int64_t nodes = 1, leaves = 0;
     T->lvl.assign(1, 0);
     T->lvl.push_back(1);
     int depth = 0;  // depth of the current entries' nodes
     int cur = 0;
-    while (As + Ac > 0) {
-        const uint32_t A = As + Ac;
-        // node arrays: this level's children and the next level's box resets
-        const size_t need = (size_t)nodes + 6 * (size_t)As + 2;
-        PG_TRY(gxn.reserve(need, nodes));
-        PG_TRY(gkey.reserve(need * 2 * d, (nodes + 2 * (size_t)As) * 2 * d));
-        PG_TRY(glo.reserve(need, nodes));
-        PG_TRY(gcnt.reserve(need, nodes));
+    // bounds on the batch's first level: its splitting entries, all entries
+    uint64_t a0 = n > 0 ? 1 : 0, e0 = n > 0 ? 1 : 0;
+    bool first = true, done = false;
+    std::vector<Level> hl(kBatch + 1);
+    while (!done) {
+        // level j of a batch adds its 2 As_j children and resets the boxes
+        // of up to 4 As_j children of the next level
+        auto need_upto = [&](int B) {
+            size_t nd = (size_t)nodes, a = (size_t)a0, need = 0;
+            for (int j = 0; j < B; j++) {
+                need = std::max(need, nd + 6 * a + 2);
+                nd += 2 * a;
+                a = std::min(2 * a, amax);
+            }
+            return need;
+        };
+        const size_t need1 = need_upto(1);
+        PG_TRY(gxn.reserve(need1, nodes));
+        PG_TRY(gkey.reserve(need1 * 2 * d, (nodes + 2 * (size_t)a0) * 2 * d));
+        PG_TRY(glo.reserve(need1, nodes));
+        PG_TRY(gcnt.reserve(need1, nodes));
+        const size_t cap = std::min(std::min(gxn.cap, gkey.cap / (2 * (size_t)d)), std::min(glo.cap, gcnt.cap));
+        int B = 1;
+        while (B < kBatch && need_upto(B + 1) <= cap) B++;
         N = Nodes{gxn.p, gkey.p, glo.p, gcnt.p};
-        const Entries& E = ent[cur];
-        const Entries& X = ent[cur ^ 1];
-        const unsigned cgrid = cdiv(C, kNT / kWave);
-        hipLaunchKernelGGL(chunk_count_kernel, dim3(cgrid), dim3(kNT), 0, s, E, cst[cur], A, C, kcur,
-                           n, c2e, lcnt, d, rbase, rentry, rcount, rbuf.as<uint32_t>());
-        PG_LAUNCH_CHECK();
-        PG_TRY(exclusive_scan_u32(lcnt, lcnt, (int64_t)C + 1, nullptr, s));
-        const uint32_t nbase = (uint32_t)nodes;
-        uint32_t* rep = rbuf.as<uint32_t>();
-        switch (d) {
-            case 1: launch_scatter<1>(cgrid, s, E, N, cst[cur], lcnt, c2e, C, nbase, rbase, rep, leaf, d, rw, ifl, kcur, icur, knext, inext, n, T); break;
-            case 2: launch_scatter<2>(cgrid, s, E, N, cst[cur], lcnt, c2e, C, nbase, rbase, rep, leaf, d, rw, ifl, kcur, icur, knext, inext, n, T); break;
-            case 3: launch_scatter<3>(cgrid, s, E, N, cst[cur], lcnt, c2e, C, nbase, rbase, rep, leaf, d, rw, ifl, kcur, icur, knext, inext, n, T); break;
-            case 4: launch_scatter<4>(cgrid, s, E, N, cst[cur], lcnt, c2e, C, nbase, rbase, rep, leaf, d, rw, ifl, kcur, icur, knext, inext, n, T); break;
-            case 5: launch_scatter<5>(cgrid, s, E, N, cst[cur], lcnt, c2e, C, nbase, rbase, rep, leaf, d, rw, ifl, kcur, icur, knext, inext, n, T); break;
-            default: launch_scatter<8>(cgrid, s, E, N, cst[cur], lcnt, c2e, C, nbase, rbase, rep, leaf, d, rw, ifl, kcur, icur, knext, inext, n, T); break;
-        }
-        PG_LAUNCH_CHECK();
-        if (As == 0) break;  // copies only: nothing below
-        if (C >= kRepChunks) {
-            const int64_t slots = 2 * (int64_t)rmax;
-            hipLaunchKernelGGL(merge_replicas_kernel, dim3(cdiv(slots, kNT / kWave)), dim3(kNT), 0, s,
-                               rep, rentry, rcount, nbase, d, gkey.p);
+        uint64_t a = a0, e = e0;
+        int c = cur;
+        uint32_t *kc = kcur, *kn = knext;
+        int32_t *ic = icur, *in = inext;
+        for (int j = 0; j < B; j++) {
+            const Level* Lj = Ld + j;
+            const Entries& E = ent[c];
+            const Entries& X = ent[c ^ 1];
+            const uint64_t cb = std::min<uint64_t>(cmax, (uint64_t)(nn / kCH) + e + 1);
+            const unsigned cgrid = grid_cap(cdiv((int64_t)cb, kNT / kWave), 4096);
+            hipLaunchKernelGGL(chunk_count_kernel, dim3(cgrid), dim3(kNT), 0, s, E, cst[c], Lj, kc, n, c2e,
+                               lcnt, d, rbase, rentry, rcount, rbuf.as<uint32_t>());
             PG_LAUNCH_CHECK();
+            PG_TRY(exclusive_scan_u32_dev(lcnt, lcnt, &Lj->C, 1, 1, (int64_t)cb + 1, nullptr, false, sums32, s));
+            uint32_t* rep = rbuf.as<uint32_t>();
+            switch (d) {
+                case 1: launch_scatter<1>(cgrid, s, E, N, cst[c], lcnt, c2e, Lj, rbase, rep, leaf, d, rw, ifl, kc, ic, kn, in, n, T); break;
+                case 2: launch_scatter<2>(cgrid, s, E, N, cst[c], lcnt, c2e, Lj, rbase, rep, leaf, d, rw, ifl, kc, ic, kn, in, n, T); break;
+                case 3: launch_scatter<3>(cgrid, s, E, N, cst[c], lcnt, c2e, Lj, rbase, rep, leaf, d, rw, ifl, kc, ic, kn, in, n, T); break;
+                case 4: launch_scatter<4>(cgrid, s, E, N, cst[c], lcnt, c2e, Lj, rbase, rep, leaf, d, rw, ifl, kc, ic, kn, in, n, T); break;
+                case 5: launch_scatter<5>(cgrid, s, E, N, cst[c], lcnt, c2e, Lj, rbase, rep, leaf, d, rw, ifl, kc, ic, kn, in, n, T); break;
+                default: launch_scatter<8>(cgrid, s, E, N, cst[c], lcnt, c2e, Lj, rbase, rep, leaf, d, rw, ifl, kc, ic, kn, in, n, T); break;
+            }
+            PG_LAUNCH_CHECK();
+            hipLaunchKernelGGL(merge_replicas_kernel, dim3(mgrid), dim3(kNT), 0, s, rep, rentry, rcount, Lj, d,
+                               gkey.p);
+            PG_LAUNCH_CHECK();
+            const unsigned agrid = grid_cap(cdiv((int64_t)a, kNT), 2048);
+            const unsigned a2grid = grid_cap(cdiv(2 * (int64_t)a, kNT), 2048);
+            hipLaunchKernelGGL(split_nodes_kernel, dim3(agrid), dim3(kNT), 0, s, E, N, cst[c], lcnt, Lj, leaf,
+                               d, ifl, flags, cst[c ^ 1], rcount);
+            PG_LAUNCH_CHECK();
+            PG_TRY(exclusive_scan_u64_dev(flags, fpre, &Lj->As, 2, 0, 2 * (int64_t)a, ftot, false, sums64, s));
+            hipLaunchKernelGGL(emit_kernel, dim3(a2grid), dim3(kNT), 0, s, E, X, N, flags, fpre, ftot, Lj,
+                               depth + j + 1, d, ifl, rule, cst[c ^ 1]);
+            PG_LAUNCH_CHECK();
+            // chunk starts of the next level (entries past its count hold 0)
+            PG_TRY(exclusive_scan_u32_dev(cst[c ^ 1], cst[c ^ 1], &Lj->As, 2, 0, 2 * (int64_t)a, nullptr, true,
+                                          sums32, s));
+            hipLaunchKernelGGL(level_advance_kernel, dim3(1), dim3(64), 0, s, Ld + j, ftot, cst[c ^ 1]);
+            PG_LAUNCH_CHECK();
+            e = std::min<uint64_t>(2 * a, amax);
+            a = e;
+            c ^= 1;
+            std::swap(kc, kn);
+            std::swap(ic, in);
         }
-        hipLaunchKernelGGL(split_nodes_kernel, dim3(cdiv(As, kNT)), dim3(kNT), 0, s, E, N, cst[cur],
-                           lcnt, As, nbase, leaf, d, ifl, flags, cst[cur ^ 1], rcount);
-        PG_LAUNCH_CHECK();
-        PG_TRY(exclusive_scan_u64(flags, fpre, 2 * (int64_t)As, ftot, s));
-        const uint32_t nbase_next = nbase + 2 * As;
-        hipLaunchKernelGGL(emit_kernel, dim3(cdiv(2 * (int64_t)As, kNT)), dim3(kNT), 0, s, E, X, N,
-                           flags, fpre, ftot, As, nbase, nbase_next, depth + 1, d, ifl, rule,
-                           cst[cur ^ 1]);
-        PG_LAUNCH_CHECK();
-        // chunk starts of the next level (entries past its count hold 0)
-        PG_TRY(exclusive_scan_u32(cst[cur ^ 1], cst[cur ^ 1], 2 * (int64_t)As, cst[cur ^ 1] + 2 * As, s));
-        uint64_t ft = 0;
-        PG_HIP(hipMemcpyAsync(&ft, ftot, sizeof(ft), hipMemcpyDeviceToHost, s));
-        PG_HIP(hipMemcpyAsync(&C, cst[cur ^ 1] + 2 * As, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        PG_HIP(hipMemcpyAsync(hl.data(), Ld, sizeof(Level) * (B + 1), hipMemcpyDeviceToHost, s));
         PG_HIP(hipStreamSynchronize(s));
-        const uint32_t As2 = (uint32_t)ft, Ac2 = (uint32_t)(ft >> 32);
-        nodes += 2 * (int64_t)As;
-        leaves += 2 * (int64_t)As - As2;
-        T->lvl.push_back(nodes);
-        depth++;
-        As = As2;
-        Ac = Ac2;
-        cur ^= 1;
-        std::swap(kcur, knext);
-        std::swap(icur, inext);
+        if (first) {
+            leaves = hl[0].As == 0 ? 1 : 0;
+            first = false;
+        }
+        if (depth > (1 << 16))
+            return fail(PG_ERR_DEVICE, "spatial-median build: no end after 65536 levels");
+        for (int j = 0; j < B && !done; j++) {
+            const Level& L0 = hl[j];
+            if (L0.As == 0) {
+                done = true;  // nothing splits (a copy-only level did its copies)
+                break;
+            }
+            nodes += 2 * (int64_t)L0.As;
+            leaves += 2 * (int64_t)L0.As - hl[j + 1].As;
+            T->lvl.push_back(nodes);
+            depth++;
+            cur ^= 1;
+            std::swap(kcur, knext);
+            std::swap(icur, inext);
+        }
+        if (!done) {
+            a0 = hl[B].As;
+            e0 = (uint64_t)hl[B].As + hl[B].Ac;
+            if (e0 == 0) done = true;
+            else PG_HIP(hipMemcpyAsync(Ld, Ld + B, sizeof(Level), hipMemcpyDeviceToDevice, s));
+        }
     }
     const int levels = (int)T->lvl.size() - 1;
     T->L = levels;
