@@ -68,7 +68,9 @@ __device__ inline void block_partition_range(const uint32_t* __restrict__ in,
             k[i] = e < s1 ? keys[e] : 0u;
             ix[i] = e < s1 ? in_idx[e] : 0;
         }
-        // groups in element order, so the running counts stay in order
+        // destinations, groups in element order so the running counts stay
+        // in order
+        int64_t dst[PER];
 #pragma unroll
         for (int i = 0; i < PER; i++) {
             const int64_t e = b0 + i * kWave + lane;
@@ -78,20 +80,50 @@ __device__ inline void block_partition_range(const uint32_t* __restrict__ in,
             const uint64_t mlt = ballot(lt), meq = ballot(eq);
             const uint32_t ltb = run_lt + lane_prefix(mlt);
             const uint32_t eqb = run_eq + lane_prefix(meq);
-            if (valid) {
-                const uint32_t el = eqb < teq ? eqb : teq;
-                int64_t dest;
-                if (lt) dest = lo + ltb + el;
-                else if (eq && eqb < teq) dest = lo + ltb + eqb;
-                else dest = mid + (e - lo) - (int64_t)(ltb + el);
-                if (dest >= lo && dest < end_node) {  // always true for a consistent split
-                    for (int cc = 0; cc < d; cc++)
-                        out[(int64_t)cc * n + dest] = cc == c ? k[i] : in[(int64_t)cc * n + e];
-                    out_idx[dest] = ix[i];
-                }
-            }
+            const uint32_t el = eqb < teq ? eqb : teq;
+            int64_t dest;
+            if (lt) dest = lo + ltb + el;
+            else if (eq && eqb < teq) dest = lo + ltb + eqb;
+            else dest = mid + (e - lo) - (int64_t)(ltb + el);
+            // always inside the node for a consistent split
+            dst[i] = valid && dest >= lo && dest < end_node ? dest : -1;
             run_lt += (uint32_t)__popcll(mlt);
             run_eq += (uint32_t)__popcll(meq);
+        }
+        // then plane by plane, the group's loads issued before its stores;
+        // a step whose elements are all in the range stores without
+        // per-lane branches, so the stores are not held up one by one
+        if (b0 + PER * kWave <= s1) {
+#pragma unroll
+            for (int i = 0; i < PER; i++) {
+                const int64_t e = b0 + i * kWave + lane;
+                dst[i] = dst[i] >= 0 ? dst[i] : e;  // (an inconsistent split keeps the element)
+            }
+            for (int cc = 0; cc < d; cc++) {
+                uint32_t val[PER];
+#pragma unroll
+                for (int i = 0; i < PER; i++)
+                    val[i] = cc == c ? k[i] : in[(int64_t)cc * n + b0 + i * kWave + lane];
+#pragma unroll
+                for (int i = 0; i < PER; i++) out[(int64_t)cc * n + dst[i]] = val[i];
+            }
+#pragma unroll
+            for (int i = 0; i < PER; i++) out_idx[dst[i]] = ix[i];
+        } else {
+            for (int cc = 0; cc < d; cc++) {
+                uint32_t val[PER];
+#pragma unroll
+                for (int i = 0; i < PER; i++) {
+                    const int64_t e = b0 + i * kWave + lane;
+                    val[i] = cc == c ? k[i] : (dst[i] >= 0 ? in[(int64_t)cc * n + e] : 0u);
+                }
+#pragma unroll
+                for (int i = 0; i < PER; i++)
+                    if (dst[i] >= 0) out[(int64_t)cc * n + dst[i]] = val[i];
+            }
+#pragma unroll
+            for (int i = 0; i < PER; i++)
+                if (dst[i] >= 0) out_idx[dst[i]] = ix[i];
         }
     }
 }
