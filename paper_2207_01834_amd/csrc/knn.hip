@@ -21,7 +21,7 @@ constexpr int kLeafQpt = 4;
 
 __global__ void __launch_bounds__(kNT)
 query_leaf_kernel(TreeView tv, int fl, const uint32_t* __restrict__ queries, int64_t m,
-                  int levels, int box, uint32_t* __restrict__ key) {
+                  int levels, int box, uint32_t* __restrict__ key, uint32_t* __restrict__ cnt) {
     __shared__ uint32_t top[1 << kTopLevels];
     const int tl = levels < kTopLevels ? levels : kTopLevels;
     for (int e = threadIdx.x; e < (1 << tl); e += kNT) top[e] = e ? tv.split[e] : 0u;
@@ -49,13 +49,14 @@ query_leaf_kernel(TreeView tv, int fl, const uint32_t* __restrict__ queries, int
             dim = dim + 1 == d ? 0 : dim + 1;
         }
         key[i] = cur - (1u << levels);
+        atomicAdd(&cnt[cur - (1u << levels)], 1u);  // the bucket's count
     }
 }
 
 // The same for explicit-node trees: the leaf index the descent reaches.
 __global__ void __launch_bounds__(kNT)
 query_xleaf_kernel(TreeView tv, int fl, const uint32_t* __restrict__ queries, int64_t m, int box,
-                   uint32_t* __restrict__ key) {
+                   int shift, uint32_t* __restrict__ key, uint32_t* __restrict__ cnt) {
     const int d = tv.d;
     const int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x;
     if (i >= m) return;
@@ -77,17 +78,12 @@ query_xleaf_kernel(TreeView tv, int fl, const uint32_t* __restrict__ queries, in
         r = tv.xn[cur];
     }
     key[i] = r.x;
+    atomicAdd(&cnt[r.x >> shift], 1u);  // the bucket's count
 }
 
-// Bucket of a query: its key shifted right by `shift`.
-__global__ void bucket_count_kernel(const uint32_t* __restrict__ key, int64_t m, int shift,
-                                    uint32_t* __restrict__ cnt) {
-    const int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x;
-    if (i < m) atomicAdd(&cnt[key[i] >> shift], 1u);
-}
-
-// start[b] is the next free slot of bucket b (its exclusive prefix sum
-// first); each query takes one.
+// Bucket of a query: its key shifted right by `shift`.  start[b] is the
+// next free slot of bucket b (the exclusive prefix sum of the counts the
+// descent kernels took); each query takes one.
 __global__ void bucket_fill_kernel(const uint32_t* __restrict__ key, int64_t m, int shift,
                                    uint32_t* __restrict__ start, int32_t* __restrict__ order) {
     const int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x;
@@ -176,14 +172,13 @@ pg_status order_queries_ws(const TreeView& tv, bool fl, const void* queries, int
     uint32_t* cnt = key + m;
     PG_TRY(fill_u32(cnt, nb, 0u, s));
     const int kshift = tv.xn ? shift : 0;
+    // (the descent kernels also count each bucket's queries)
     if (tv.xn)
         hipLaunchKernelGGL(query_xleaf_kernel, dim3(cdiv(m, kNT)), dim3(kNT), 0, s, tv, fl ? 1 : 0,
-                           (const uint32_t*)queries, m, boxes ? 1 : 0, key);
+                           (const uint32_t*)queries, m, boxes ? 1 : 0, kshift, key, cnt);
     else
         hipLaunchKernelGGL(query_leaf_kernel, dim3(cdiv(m, (int64_t)kNT * kLeafQpt)), dim3(kNT), 0, s,
-                           tv, fl ? 1 : 0, (const uint32_t*)queries, m, tv.L - shift, boxes ? 1 : 0, key);
-    PG_LAUNCH_CHECK();
-    hipLaunchKernelGGL(bucket_count_kernel, dim3(cdiv(m, kNT)), dim3(kNT), 0, s, key, m, kshift, cnt);
+                           tv, fl ? 1 : 0, (const uint32_t*)queries, m, tv.L - shift, boxes ? 1 : 0, key, cnt);
     PG_LAUNCH_CHECK();
     PG_TRY(exclusive_scan_u32_ws(cnt, cnt, nb, nullptr, sums, s));
     hipLaunchKernelGGL(bucket_fill_kernel, dim3(cdiv(m, kNT)), dim3(kNT), 0, s, key, m, kshift, cnt, order);
