@@ -2,7 +2,9 @@
 // templates instantiated by forest_knn_int.hip and forest_knn_float.hip.
 //
 // One lane per query walks the trees largest first with one k-list, so the
-// k-th distance found in the large trees prunes the small ones.  While
+// k-th distance found in the large trees prunes the small ones: a smaller
+// tree's descent already notes which of its path's split planes are out of
+// reach, and the walk skips those ancestors on its way back.  While
 // every id is below 2^31 the list holds packed (distance, id) keys, and the
 // trees whose records carry the ids in their row words need no id load.
 // Tombstoned points are skipped by their liveness bit, read only for points
@@ -50,12 +52,14 @@ bdl_knn_kernel(Forest f, const uint32_t* __restrict__ queries, const int32_t* __
     if constexpr (PK) {
         PackedList<T, KT, EX> kl;
         kl.init(idbits);
-        for (int t = 0; t < f.count; t++)
+        if (f.count > 0)
             tree_search<T, MD, decltype(kl), BdlIds, TK>(
-                f.s[t].tv, BdlIds{f.s[t].ids, f.s[t].alive, f.s[t].idrec}, q, d, kl, k,
-                search_start<TK>(f.s[t].tv, false, 0),
-                descend_from<T, MD, TK>(f.s[t].tv, q, d,
-                                        t == 0 ? search_from<TK>(f.s[0].tv, qk, qi) : root_from<TK>()));
+                f.s[0].tv, BdlIds{f.s[0].ids, f.s[0].alive, f.s[0].idrec}, q, d, kl, k,
+                search_start<TK>(f.s[0].tv, false, 0),
+                descend_from<T, MD, TK>(f.s[0].tv, q, d, search_from<TK>(f.s[0].tv, qk, qi)));
+        for (int t = 1; t < f.count; t++)
+            tree_search_next<T, MD, decltype(kl), BdlIds, TK>(
+                f.s[t].tv, BdlIds{f.s[t].ids, f.s[t].alive, f.s[t].idrec}, q, d, kl, k);
         if (kl.needs_redo()) {
             redo[atomicAdd(nredo, 1u)] = (int32_t)qi;
             return;
@@ -70,12 +74,14 @@ bdl_knn_kernel(Forest f, const uint32_t* __restrict__ queries, const int32_t* __
     } else {
         KList<typename M::D, int64_t, KT, EX> kl;
         kl.init(M::inf(), INT64_MAX);
-        for (int t = 0; t < f.count; t++)
+        if (f.count > 0)
             tree_search<T, MD, decltype(kl), BdlIds, TK>(
-                f.s[t].tv, BdlIds{f.s[t].ids, f.s[t].alive, 0}, q, d, kl, k,
-                search_start<TK>(f.s[t].tv, false, 0),
-                descend_from<T, MD, TK>(f.s[t].tv, q, d,
-                                        t == 0 ? search_from<TK>(f.s[0].tv, qk, qi) : root_from<TK>()));
+                f.s[0].tv, BdlIds{f.s[0].ids, f.s[0].alive, 0}, q, d, kl, k,
+                search_start<TK>(f.s[0].tv, false, 0),
+                descend_from<T, MD, TK>(f.s[0].tv, q, d, search_from<TK>(f.s[0].tv, qk, qi)));
+        for (int t = 1; t < f.count; t++)
+            tree_search_next<T, MD, decltype(kl), BdlIds, TK>(f.s[t].tv, BdlIds{f.s[t].ids, f.s[t].alive, 0},
+                                                             q, d, kl, k);
 #pragma unroll
         for (int s = 0; s < KT; s++) {
             if (EX || s < k) {

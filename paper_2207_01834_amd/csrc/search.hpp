@@ -140,9 +140,17 @@ __device__ inline uint32_t leaf_at(const int64_t* loff, int L, int64_t i) {
 // Stepping into a leaf only records it; the walk then stands at the leaf's
 // parent as if back from it.
 // LOFF: leaf ranges come from tv.loff (trees grown in place).
-template <typename T, int MD, typename List, typename Ids, bool LOFF = false>
+// DUE (separate queries whose `from` is their walk leaf): bit l of `due` is
+// clear when the split plane of the descent path's node at level l was
+// beyond the k-th distance when the descent passed it.  That node can never
+// send the walk into its other child (the distance only shrinks), so a walk
+// leaving a path node upward goes straight to the deepest path ancestor
+// whose bit is set, as if back from its child on the path, and ends when
+// there is none: the same nodes are entered in the same order.
+template <typename T, int MD, typename List, typename Ids, bool LOFF = false, bool DUE = false>
 __device__ inline void kd_search(const TreeView& tv, const Ids& ids, const T (&q)[MD], int d,
-                                 List& kl, int k, uint32_t start = 0, uint32_t from = 1) {
+                                 List& kl, int k, uint32_t start = 0, uint32_t from = 1,
+                                 uint32_t due = ~0u) {
     using M = Metric<T>;
     using DT = typename M::D;
     const int64_t n = tv.n;
@@ -156,6 +164,12 @@ __device__ inline void kd_search(const TreeView& tv, const Ids& ids, const T (&q
     const uint32_t first_wleaf = 1u << W;
     const uint32_t first_leaf = 1u << L;
     const uint32_t wstart = start >> sub;
+    // the descent path's walk leaf (DUE), 0 when `from` lies above it
+    uint32_t pleaf = 0;
+    if constexpr (DUE) {
+        const int lf = 31 - __clz(from);
+        pleaf = (start == 0 && W > 0 && lf >= W) ? from >> (lf - W) : 0u;
+    }
     uint32_t cur, prev, p0, p1 = 0;
     if (W == 0) {
         p0 = 1;
@@ -196,6 +210,7 @@ __device__ inline void kd_search(const TreeView& tv, const Ids& ids, const T (&q
                 const T qd = pick<MD>(q, dim_of(cur, lvl));
                 const uint32_t nearc = 2u * cur + (qd >= s ? 1u : 0u);
                 uint32_t next = nearc;
+                uint32_t jprev = cur;  // prev after the step when it moves up
                 if (prev > cur) {
                     // back from child prev: the other child is due when prev
                     // was entered first -- the start leaf's side on its path,
@@ -218,13 +233,27 @@ __device__ inline void kd_search(const TreeView& tv, const Ids& ids, const T (&q
                         }
                         if (reach) next = other;
                     }
+                    if constexpr (DUE) {
+                        // leaving a path node upward: to the deepest path
+                        // ancestor still due, or done
+                        if (next == (cur >> 1) && pleaf != 0 && (pleaf >> (W - lvl)) == cur) {
+                            const uint32_t m = due & ((1u << lvl) - 1u);
+                            if (m == 0) {
+                                next = 0;
+                            } else {
+                                const int la = 31 - __clz(m);
+                                next = pleaf >> (W - la);
+                                jprev = pleaf >> (W - la - 1);
+                            }
+                        }
+                    }
                 }
                 if (next >= first_wleaf) {
                     if (p0 == 0) p0 = next;
                     else p1 = next;
                     prev = next;
                 } else {
-                    prev = cur;
+                    prev = jprev;
                     cur = next;
                 }
             }

@@ -237,6 +237,35 @@ __device__ inline uint32_t descend_from(const TreeView& tv, const T (&q)[MD], in
     }
 }
 
+// descend_from from the root of a heap tree that also returns `due`: bit l
+// set when the split plane of the path's node at level l is within kd of q
+// (see kd_search).
+template <typename T, int MD, int TK>
+__device__ inline uint32_t descend_due(const TreeView& tv, const T (&q)[MD], int d,
+                                       typename Metric<T>::D kd, uint32_t& due) {
+    using M = Metric<T>;
+    due = ~0u;
+    if (tv.n == 0) return 1u;
+    const int L = tv.L;
+    const int W = L - (L < 2 ? L : 2);
+    const int D = MD < 8 ? MD : d;
+    uint32_t h = 1, bits = 0;
+    int dim = 0;
+    for (int lv = 0; lv < W; lv++) {
+        int dm = dim;
+        if constexpr (TK == kTreeLoff) {
+            if (tv.sdim != nullptr) dm = tv.sdim[h];
+        }
+        const T qd = pick<MD>(q, dm);
+        const T s = M::load(tv.split[h]);
+        if (!(M::sq(qd, s) > kd)) bits |= 1u << lv;
+        h = 2u * h + (qd >= s ? 1u : 0u);
+        dim = dim + 1 == D ? 0 : dim + 1;
+    }
+    due = bits;
+    return h;
+}
+
 // The k-NN walk for tree kind TK (start from search_start; from, for a
 // separate query, from search_from or root_from).
 template <typename T, int MD, typename List, typename Ids, int TK>
@@ -244,6 +273,21 @@ __device__ inline void tree_search(const TreeView& tv, const Ids& ids, const T (
                                    List& kl, int k, uint32_t start, uint32_t from = root_from<TK>()) {
     if constexpr (TK == kTreeX) kdx_search<T, MD, List, Ids>(tv, ids, q, d, kl, k, start, from);
     else kd_search<T, MD, List, Ids, TK == kTreeLoff>(tv, ids, q, d, kl, k, start, from);
+}
+
+// A separate query's walk of a tree other than the first of a forest: the
+// descent with the current k-th distance, then the walk that skips the
+// ancestors out of reach (heap trees; explicit trees walk from their root).
+template <typename T, int MD, typename List, typename Ids, int TK>
+__device__ inline void tree_search_next(const TreeView& tv, const Ids& ids, const T (&q)[MD], int d,
+                                        List& kl, int k) {
+    if constexpr (TK == kTreeX) {
+        kdx_search<T, MD, List, Ids>(tv, ids, q, d, kl, k, kXNone, descend_from<T, MD, TK>(tv, q, d, 0u));
+    } else {
+        uint32_t due;
+        const uint32_t from = descend_due<T, MD, TK>(tv, q, d, kl.kd, due);
+        kd_search<T, MD, List, Ids, TK == kTreeLoff, true>(tv, ids, q, d, kl, k, 0u, from, due);
+    }
 }
 
 }  // namespace pg
