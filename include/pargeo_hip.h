@@ -42,7 +42,7 @@ typedef enum {
     PG_ERR_RANGE = 2,       /* coordinate out of range / non-finite          */
     PG_ERR_NOMEM = 3,       /* device allocation failed                      */
     PG_ERR_DEVICE = 4,      /* a HIP call or kernel launch failed            */
-    PG_ERR_UNSUPPORTED = 5  /* valid request this build does not serve       */
+    PG_ERR_UNSUPPORTED = 5  /* valid request the library does not serve     */
 } pg_status;
 
 typedef enum { PG_INT32 = 0, PG_FLOAT32 = 1 } pg_dtype;
