@@ -133,9 +133,11 @@ __global__ void wide_init_kernel(NodeSel* ns, int64_t J, int64_t n, int l, uint3
     if (write_split) split_level[j] = key_to_coord(prefix0, fl);
 }
 
+// first: the level's first digit pass, where every node's selected prefix
+// is still prefix0 (the selection state is not read).
 __global__ void __launch_bounds__(kNT)
 wide_hist_kernel(const uint32_t* __restrict__ keys, int64_t n, int l, int bpn,
-                 const NodeSel* __restrict__ ns, int shift, int width,
+                 const NodeSel* __restrict__ ns, int shift, int width, int first, uint32_t prefix0,
                  uint32_t* __restrict__ ghist) {
     extern __shared__ uint32_t lh[];
     const int64_t j = blockIdx.x / bpn;
@@ -147,7 +149,7 @@ wide_hist_kernel(const uint32_t* __restrict__ keys, int64_t n, int l, int bpn,
     for (int b = threadIdx.x; b < nb; b += kNT) lh[b] = 0;
     __syncthreads();
     const int hs = shift + width;
-    const uint64_t pre = (uint64_t)ns[j].prefix >> hs;
+    const uint64_t pre = (uint64_t)(first ? prefix0 : ns[j].prefix) >> hs;
     constexpr int PER = 8;  // loads issued together
     for (int64_t b = e0 + threadIdx.x; b < e1; b += PER * kNT) {
         uint32_t k[PER];
@@ -166,9 +168,12 @@ wide_hist_kernel(const uint32_t* __restrict__ keys, int64_t n, int l, int bpn,
     }
 }
 
+// first: the selection starts from (prefix0, the node's split rank), as
+// wide_init_kernel would have set it.
 __global__ void __launch_bounds__(kNT)
 wide_select_kernel(uint32_t* __restrict__ ghist, NodeSel* __restrict__ ns, int shift, int width,
-                   int last, uint32_t* __restrict__ split_level, int fl) {
+                   int last, int first, uint32_t prefix0, int64_t n, int l,
+                   uint32_t* __restrict__ split_level, int fl) {
     __shared__ uint32_t lds[kNT / kWave + 1];
     const int64_t j = blockIdx.x;
     const int nb = 1 << width;
@@ -182,7 +187,15 @@ wide_select_kernel(uint32_t* __restrict__ ghist, NodeSel* __restrict__ ns, int s
         loc[i] = (i < per && b < nb) ? gh[b] : 0u;
         sum += loc[i];
     }
-    const uint32_t prefix = ns[j].prefix, r = ns[j].rank;
+    uint32_t prefix, r;
+    if (first) {
+        int64_t lo, hi, mid;
+        prefix = prefix0;
+        r = (uint32_t)split_rank_pos(n, l, j, &lo, &hi, &mid);
+    } else {
+        prefix = ns[j].prefix;
+        r = ns[j].rank;
+    }
     uint32_t tot;
     uint32_t excl = block_excl_scan<kNT>(sum, lds, &tot);
     if (sum > 0 && excl <= r && r < excl + sum) {
@@ -421,20 +434,24 @@ pg_status build_from_keys(uint32_t* kA, int32_t* iA, uint32_t* kB, int32_t* iB, 
             const int spn = (int)cdiv(smax, kScat);
             const unsigned nsblk = (unsigned)(J * spn);
             NodeSel* ns = nsel.as<NodeSel>();
-            hipLaunchKernelGGL(wide_init_kernel, dim3(cdiv(J, kNT)), dim3(kNT), 0, s, ns, J, n, l,
-                               prefix0, sb == 0 ? 1 : 0, split_level, ifl);
-            PG_LAUNCH_CHECK();
+            if (sb == 0) {
+                // every key of the dimension is equal: no digit pass
+                hipLaunchKernelGGL(wide_init_kernel, dim3(cdiv(J, kNT)), dim3(kNT), 0, s, ns, J, n, l,
+                                   prefix0, 1, split_level, ifl);
+                PG_LAUNCH_CHECK();
+            }
             for (int hb = sb; hb > 0; hb -= kWideDigit) {
                 const int shift = hb > kWideDigit ? hb - kWideDigit : 0;
                 const int width = hb - shift;
+                const int first = hb == sb ? 1 : 0;
                 const uint32_t* keys = cur_k + (int64_t)c * n;
                 hipLaunchKernelGGL(wide_hist_kernel, dim3(nblk), dim3(kNT),
                                    sizeof(uint32_t) << width, s, keys, n, l, bpn, ns, shift,
-                                   width, ghist.as<uint32_t>());
+                                   width, first, prefix0, ghist.as<uint32_t>());
                 PG_LAUNCH_CHECK();
                 hipLaunchKernelGGL(wide_select_kernel, dim3((unsigned)J), dim3(kNT), 0, s,
-                                   ghist.as<uint32_t>(), ns, shift, width, shift == 0 ? 1 : 0,
-                                   split_level, ifl);
+                                   ghist.as<uint32_t>(), ns, shift, width, shift == 0 ? 1 : 0, first,
+                                   prefix0, n, l, split_level, ifl);
                 PG_LAUNCH_CHECK();
             }
             hipLaunchKernelGGL(wide_count_kernel, dim3(nsblk), dim3(kNT), 0, s,
