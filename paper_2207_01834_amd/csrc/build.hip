@@ -11,10 +11,10 @@
 // How (MI355X): coordinates become order-preserving 32-bit keys stored as SoA
 // planes.  Every partition is stable, so each node segment stays in input-row
 // order and "ties by input row" becomes "ties by position in the segment".
-//   * wide levels (< 1024 nodes): radix select over 11-bit digits with
+//   * wide levels (< 1024 nodes of > 4096 points): radix select over 11-bit digits with
 //     multi-workgroup LDS histograms merged by global atomics, then a stable
 //     scatter whose per-workgroup offsets come from a per-node scan;
-//   * middle levels (>= 1024 nodes, node > S points): one workgroup per node
+//   * middle levels (the other nodes of > S points): one workgroup per node
 //     does an 8-bit radix select and the stable partition itself;
 //   * bottom levels (node <= S = 1024 points): one workgroup per subtree loads
 //     it into LDS, and each wave selects (8-bit digit histograms, or direct
@@ -37,7 +37,8 @@ constexpr int kNT = kBuildNT;       // threads per workgroup
 constexpr int kChunk = 8192;        // elements per histogram workgroup in the wide levels
 constexpr int kScat = 1024;         // elements per count/scatter workgroup in the wide levels
 constexpr int kWideDigit = 11;      // radix digit width in the wide levels
-constexpr int kWideNodes = 1024;    // levels with fewer nodes use the wide path
+constexpr int kWideNodes = 1024;    // levels with fewer nodes use the wide path...
+constexpr int64_t kWideMinPts = 4096;  // ...while their nodes hold more points than this
 constexpr int kBoxLevels = 8;       // tree levels of internal boxes per launch
 
 struct NodeSel {
@@ -405,7 +406,11 @@ pg_status build_from_keys(uint32_t* kA, int32_t* iA, uint32_t* kB, int32_t* iB, 
 
     DevBuf nsel(s), ghist(s), bcnt(s);
     int wide_levels = 0;
-    while (wide_levels < ls && ((int64_t)1 << wide_levels) < kWideNodes) wide_levels++;
+    // a wide level costs seven launches, a node level one: smaller builds
+    // (launch-bound) move to node levels once nodes hold few points
+    while (wide_levels < ls && ((int64_t)1 << wide_levels) < kWideNodes &&
+           (n >> wide_levels) > kWideMinPts)
+        wide_levels++;
     if (wide_levels > 0) {
         const int64_t Jmax = (int64_t)1 << (wide_levels - 1);
         int64_t blocks_max = 1;
