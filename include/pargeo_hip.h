@@ -58,7 +58,9 @@ typedef struct pg_bdl pg_bdl;
  * cached.  pg_release_cached returns them to the device (after a device
  * synchronisation), as an allocation failure does first; call it before
  * destroying a stream the library has run on, so that no block stays
- * filed under a stream handle the runtime may hand out again.
+ * filed under a stream handle the runtime may hand out again, and before
+ * making another device current (the release synchronises and frees on the
+ * current device).
  * pg_set_allocator installs the caller's allocator instead (a framework's
  * caching allocator, say):
  * alloc(bytes, stream, ctx) returns device memory usable in stream order on
