@@ -219,32 +219,51 @@ wide_select_kernel(uint32_t* __restrict__ ghist, NodeSel* __restrict__ ns, int s
     }
 }
 
+// Per scatter workgroup: the counts (lt | eq << 32) of its keys against the
+// pivot, per wave over the part block_partition_range gives that wave
+// (wcnt: waves x blocks), and per workgroup (bcnt, which the scan turns into
+// offsets): the scatter then skips its own counting pass.
 __global__ void __launch_bounds__(kNT)
 wide_count_kernel(const uint32_t* __restrict__ keys, int64_t n, int l, int bpn,
-                  const NodeSel* __restrict__ ns, uint64_t* __restrict__ bcnt) {
-    __shared__ uint64_t red[kNT / kWave];
+                  const NodeSel* __restrict__ ns, uint64_t* __restrict__ bcnt,
+                  uint64_t* __restrict__ wcnt) {
+    constexpr int NW = kNT / kWave;
+    __shared__ uint64_t red[NW];
     const int64_t j = blockIdx.x / bpn;
     const int t = blockIdx.x % bpn;
     const int64_t lo = node_start(n, l, j), hi = node_start(n, l, j + 1);
     const int64_t e0 = lo + (int64_t)t * kScat;
     const int64_t e1 = min(e0 + kScat, hi);
     const uint32_t v = ns[j].prefix;
-    uint64_t acc = 0;  // lt in the low 32 bits, eq in the high 32 bits
-    constexpr int PER = 4;  // loads issued together
-    for (int64_t b = e0 + threadIdx.x; b < e1; b += PER * kNT) {
+    const int w = threadIdx.x / kWave, lane = lane_id();
+    const int64_t part = (e1 - e0 + NW - 1) / NW;
+    const int64_t s0 = e0 + w * part < e1 ? e0 + w * part : e1;
+    const int64_t s1 = s0 + part < e1 ? s0 + part : e1;
+    uint32_t nlt = 0, neq = 0;
+    constexpr int PER = 4;  // 64-element groups per step: their loads are issued together
+    for (int64_t b0 = s0; b0 < s1; b0 += PER * kWave) {
         uint32_t k[PER];
 #pragma unroll
-        for (int i = 0; i < PER; i++) k[i] = b + i * kNT < e1 ? keys[b + i * kNT] : 0u;
+        for (int i = 0; i < PER; i++) {
+            const int64_t e = b0 + i * kWave + lane;
+            k[i] = e < s1 ? keys[e] : 0u;
+        }
 #pragma unroll
-        for (int i = 0; i < PER; i++)
-            if (b + i * kNT < e1) acc += (k[i] < v) ? 1ull : ((k[i] == v) ? (1ull << 32) : 0ull);
+        for (int i = 0; i < PER; i++) {
+            const bool valid = b0 + i * kWave + lane < s1;
+            nlt += (uint32_t)__popcll(__ballot(valid && k[i] < v));
+            neq += (uint32_t)__popcll(__ballot(valid && k[i] == v));
+        }
     }
-    acc = wave_sum(acc);
-    if (lane_id() == 0) red[threadIdx.x / kWave] = acc;
+    const uint64_t acc = (uint64_t)nlt | ((uint64_t)neq << 32);
+    if (lane == 0) {
+        red[w] = acc;
+        wcnt[(int64_t)blockIdx.x * NW + w] = acc;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
         uint64_t s = 0;
-        for (int w = 0; w < kNT / kWave; w++) s += red[w];
+        for (int i = 0; i < NW; i++) s += red[i];
         bcnt[blockIdx.x] = s;
     }
 }
@@ -280,7 +299,7 @@ __global__ void __launch_bounds__(kNT)
 wide_scatter_kernel(const uint32_t* __restrict__ in, const int32_t* __restrict__ in_idx,
                     uint32_t* __restrict__ out, int32_t* __restrict__ out_idx, int d, int c,
                     int64_t n, int l, int bpn, const NodeSel* __restrict__ ns,
-                    const uint64_t* __restrict__ boff) {
+                    const uint64_t* __restrict__ boff, const uint64_t* __restrict__ wcnt) {
     __shared__ uint32_t lds[2 * (kNT / kWave)];
     const int64_t j = blockIdx.x / bpn;
     const int t = blockIdx.x % bpn;
@@ -291,7 +310,8 @@ wide_scatter_kernel(const uint32_t* __restrict__ in, const int32_t* __restrict__
     const uint32_t v = ns[j].prefix, teq = ns[j].rank;
     block_partition_range(in, in_idx, out, out_idx, d, c, n, e0, e1, lo, mid, hi, v, teq,
                           (uint32_t)(boff[blockIdx.x] & 0xffffffffull),
-                          (uint32_t)(boff[blockIdx.x] >> 32), lds);
+                          (uint32_t)(boff[blockIdx.x] >> 32), lds,
+                          wcnt + (int64_t)blockIdx.x * (kNT / kWave));
 }
 
 // ---------------------------------------------------------------------------
@@ -411,9 +431,9 @@ pg_status build_from_keys(uint32_t* kA, int32_t* iA, uint32_t* kB, int32_t* iB, 
     while (wide_levels < ls && ((int64_t)1 << wide_levels) < kWideNodes &&
            (n >> wide_levels) > kWideMinPts)
         wide_levels++;
+    int64_t blocks_max = 1;  // scatter workgroups of the widest level
     if (wide_levels > 0) {
         const int64_t Jmax = (int64_t)1 << (wide_levels - 1);
-        int64_t blocks_max = 1;
         for (int l = 0; l < wide_levels; l++) {
             const int64_t J = (int64_t)1 << l;
             const int64_t b = J * (int64_t)cdiv((n + J - 1) / J, kScat);
@@ -421,7 +441,7 @@ pg_status build_from_keys(uint32_t* kA, int32_t* iA, uint32_t* kB, int32_t* iB, 
         }
         PG_TRY(nsel.alloc(sizeof(NodeSel) * Jmax));
         PG_TRY(ghist.alloc(sizeof(uint32_t) * Jmax * (1 << kWideDigit)));
-        PG_TRY(bcnt.alloc(sizeof(uint64_t) * blocks_max));
+        PG_TRY(bcnt.alloc(sizeof(uint64_t) * blocks_max * (1 + kNT / kWave)));
         PG_HIP(hipMemsetAsync(ghist.p, 0, sizeof(uint32_t) * Jmax * (1 << kWideDigit), s));
     }
 
@@ -459,14 +479,15 @@ pg_status build_from_keys(uint32_t* kA, int32_t* iA, uint32_t* kB, int32_t* iB, 
                                    prefix0, n, l, split_level, ifl);
                 PG_LAUNCH_CHECK();
             }
+            uint64_t* wcnt = bcnt.as<uint64_t>() + blocks_max;
             hipLaunchKernelGGL(wide_count_kernel, dim3(nsblk), dim3(kNT), 0, s,
-                               cur_k + (int64_t)c * n, n, l, spn, ns, bcnt.as<uint64_t>());
+                               cur_k + (int64_t)c * n, n, l, spn, ns, bcnt.as<uint64_t>(), wcnt);
             PG_LAUNCH_CHECK();
             hipLaunchKernelGGL(wide_scan_kernel, dim3((unsigned)J), dim3(kNT), 0, s,
                                bcnt.as<uint64_t>(), spn);
             PG_LAUNCH_CHECK();
             hipLaunchKernelGGL(wide_scatter_kernel, dim3(nsblk), dim3(kNT), 0, s, cur_k, cur_i,
-                               oth_k, oth_i, d, c, n, l, spn, ns, bcnt.as<uint64_t>());
+                               oth_k, oth_i, d, c, n, l, spn, ns, bcnt.as<uint64_t>(), wcnt);
             PG_LAUNCH_CHECK();
         } else {
             hipLaunchKernelGGL(node_kernel, dim3((unsigned)J), dim3(kNT), 0, s, cur_k, cur_i,

@@ -17,7 +17,9 @@ constexpr int kBuildNT = 256;  // threads of every build workgroup
 // keys < v / == v before c0.  The workgroup's waves each take one contiguous
 // part of the chunk: they count it with ballots, exchange their totals
 // through LDS (lds: >= 2 * waves words), then scatter their part in order,
-// positions from ballot prefix counts.  Contains barriers.
+// positions from ballot prefix counts.  Contains barriers.  wcnt (may be
+// NULL): the waves' counts (lt | eq << 32), already taken over the same
+// parts, so the counting pass is skipped.
 __device__ inline void block_partition_range(const uint32_t* __restrict__ in,
                                              const int32_t* __restrict__ in_idx,
                                              uint32_t* __restrict__ out,
@@ -25,7 +27,7 @@ __device__ inline void block_partition_range(const uint32_t* __restrict__ in,
                                              int64_t n, int64_t c0, int64_t c1, int64_t lo,
                                              int64_t mid, int64_t end_node, uint32_t v,
                                              uint32_t teq, uint32_t base_lt, uint32_t base_eq,
-                                             uint32_t* lds) {
+                                             uint32_t* lds, const uint64_t* __restrict__ wcnt = nullptr) {
     constexpr int NW = kBuildNT / kWave;
     constexpr int PER = 4;  // 64-element groups per step: their loads are issued together
     const int w = threadIdx.x / kWave, lane = lane_id();
@@ -33,32 +35,39 @@ __device__ inline void block_partition_range(const uint32_t* __restrict__ in,
     const int64_t s0 = c0 + w * part < c1 ? c0 + w * part : c1;
     const int64_t s1 = s0 + part < c1 ? s0 + part : c1;
     const uint32_t* keys = in + (int64_t)c * n;
-    uint32_t nlt = 0, neq = 0;
-    for (int64_t b0 = s0; b0 < s1; b0 += PER * kWave) {
-        uint32_t k[PER];
-#pragma unroll
-        for (int i = 0; i < PER; i++) {
-            const int64_t e = b0 + i * kWave + lane;
-            k[i] = e < s1 ? keys[e] : 0u;
-        }
-#pragma unroll
-        for (int i = 0; i < PER; i++) {
-            const bool valid = b0 + i * kWave + lane < s1;
-            nlt += (uint32_t)__popcll(ballot(valid && k[i] < v));
-            neq += (uint32_t)__popcll(ballot(valid && k[i] == v));
-        }
-    }
-    if (lane == 0) {
-        lds[w] = nlt;
-        lds[NW + w] = neq;
-    }
-    __syncthreads();
     uint32_t run_lt = base_lt, run_eq = base_eq;
-    for (int i = 0; i < w; i++) {
-        run_lt += lds[i];
-        run_eq += lds[NW + i];
+    if (wcnt) {
+        for (int i = 0; i < w; i++) {
+            run_lt += (uint32_t)wcnt[i];
+            run_eq += (uint32_t)(wcnt[i] >> 32);
+        }
+    } else {
+        uint32_t nlt = 0, neq = 0;
+        for (int64_t b0 = s0; b0 < s1; b0 += PER * kWave) {
+            uint32_t k[PER];
+#pragma unroll
+            for (int i = 0; i < PER; i++) {
+                const int64_t e = b0 + i * kWave + lane;
+                k[i] = e < s1 ? keys[e] : 0u;
+            }
+#pragma unroll
+            for (int i = 0; i < PER; i++) {
+                const bool valid = b0 + i * kWave + lane < s1;
+                nlt += (uint32_t)__popcll(ballot(valid && k[i] < v));
+                neq += (uint32_t)__popcll(ballot(valid && k[i] == v));
+            }
+        }
+        if (lane == 0) {
+            lds[w] = nlt;
+            lds[NW + w] = neq;
+        }
+        __syncthreads();
+        for (int i = 0; i < w; i++) {
+            run_lt += lds[i];
+            run_eq += lds[NW + i];
+        }
+        __syncthreads();
     }
-    __syncthreads();
     for (int64_t b0 = s0; b0 < s1; b0 += PER * kWave) {
         uint32_t k[PER];
         int32_t ix[PER];
